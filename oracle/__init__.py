@@ -1,0 +1,207 @@
+"""Plain FP64 CPU oracle for the five-equation finite-volume RHS and SSP-RK3 step.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the benchmark's
+CPU-baseline leg are the only callers.  The product path never imports this.
+
+The arithmetic lives in ``orc.c`` (built to ``liborc.so`` with
+``-O2 -fno-fast-math -ffp-contract=off -fopenmp``); this module only marshals
+numpy arrays.  ``exact_riemann`` holds the exact two-material Riemann solution
+used to pin the oracle's discretisation.
+
+Paper: arXiv 2409.10729, Sec. II-A (model, stiffened-gas EOS) and Sec. II-B
+(eq. discretization and the cell-integrated form below it; HLLC after Toro,
+WENO5 after Shu).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "orc.c")
+_LIB = os.path.join(_HERE, "liborc.so")
+
+NV = 7
+
+
+class OrcGrid(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("dx", ctypes.c_double * 3),
+        ("bc", (ctypes.c_int32 * 2) * 3),
+        ("gamma", ctypes.c_double * 2),
+        ("pinf", ctypes.c_double * 2),
+        ("eps", ctypes.c_double),
+        ("cfl", ctypes.c_double),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile liborc.so with gcc (plain C, no contraction, OpenMP)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.run(
+            ["gcc", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-fPIC",
+             "-shared", "-std=c11", "-Wall", "-o", tmp, _SRC, "-lm"],
+            check=True,
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB)
+        dp = ctypes.POINTER(ctypes.c_double)
+        gp = ctypes.POINTER(OrcGrid)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        L.orc_weno5.argtypes = [dp, ctypes.c_double, dp, dp]
+        L.orc_weno5_betas.argtypes = [dp, dp]
+        L.orc_hllc.argtypes = [gp, dp, dp, ctypes.c_int, dp, dp]
+        L.orc_sound_speed.argtypes = [gp, dp]
+        L.orc_sound_speed.restype = ctypes.c_double
+        L.orc_cons_to_prim_cell.argtypes = [gp, dp, dp]
+        L.orc_prim_to_cons_cell.argtypes = [gp, dp, dp]
+        L.orc_prim_to_cons.argtypes = [gp, dp, dp]
+        L.orc_cons_to_prim.argtypes = [gp, dp, dp]
+        L.orc_rhs.argtypes = [gp, dp, dp]
+        L.orc_rhs_at.argtypes = [gp, dp, ctypes.c_int64, i64p, dp]
+        L.orc_cfl_dt.argtypes = [gp, dp]
+        L.orc_cfl_dt.restype = ctypes.c_double
+        L.orc_rk3_combine.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, dp, ctypes.c_double, dp]
+        L.orc_rk3_step.argtypes = [gp, dp, ctypes.c_double]
+        L.orc_rk3_step.restype = ctypes.c_double
+        L.orc_run.argtypes = [gp, dp, ctypes.c_int, dp, dp]
+        L.orc_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def make_grid(spec: dict) -> OrcGrid:
+    """Grid from a problem description dict (keys n, dx, bc, gamma, pinf, eps, cfl)."""
+    g = OrcGrid()
+    for d in range(3):
+        g.n[d] = int(spec["n"][d])
+        g.dx[d] = float(spec["dx"][d])
+        g.bc[d][0] = int(spec["bc"][d][0])
+        g.bc[d][1] = int(spec["bc"][d][1])
+    g.gamma[0], g.gamma[1] = map(float, spec["gamma"])
+    g.pinf[0], g.pinf[1] = map(float, spec["pinf"])
+    g.eps = float(spec.get("eps", 1e-6))
+    g.cfl = float(spec.get("cfl", 0.4))
+    return g
+
+
+def _shape(g: OrcGrid):
+    return (NV, g.n[2], g.n[1], g.n[0])
+
+
+def prim_to_cons(g: OrcGrid, w: np.ndarray) -> np.ndarray:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    q = np.empty_like(w)
+    lib().orc_prim_to_cons(ctypes.byref(g), _dp(w), _dp(q))
+    return q
+
+
+def cons_to_prim(g: OrcGrid, q: np.ndarray) -> np.ndarray:
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    w = np.empty_like(q)
+    lib().orc_cons_to_prim(ctypes.byref(g), _dp(q), _dp(w))
+    return w
+
+
+def rhs(g: OrcGrid, q: np.ndarray) -> np.ndarray:
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    out = np.empty_like(q)
+    lib().orc_rhs(ctypes.byref(g), _dp(q), _dp(out))
+    return out
+
+
+def rhs_at(g: OrcGrid, q: np.ndarray, cells: np.ndarray) -> np.ndarray:
+    """RHS at linear cell indices ``cells``; returns [ncell, 7]."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    out = np.empty((cells.size, NV), dtype=np.float64)
+    lib().orc_rhs_at(ctypes.byref(g), _dp(q), cells.size,
+                     cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out))
+    return out
+
+
+def cfl_dt(g: OrcGrid, q: np.ndarray) -> float:
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    return lib().orc_cfl_dt(ctypes.byref(g), _dp(q))
+
+
+def rk3_combine(stage: int, qn: np.ndarray, qs: np.ndarray, L: np.ndarray, dt: float) -> np.ndarray:
+    qn = np.ascontiguousarray(qn, dtype=np.float64)
+    qs = np.ascontiguousarray(qs, dtype=np.float64)
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    out = np.empty_like(qs)
+    lib().orc_rk3_combine(int(stage), qs.size, _dp(qn), _dp(qs), _dp(L), float(dt), _dp(out))
+    return out
+
+
+def rk3_step(g: OrcGrid, q: np.ndarray, dt: float = 0.0):
+    """One SSP-RK3 step; returns (new q, dt used).  dt <= 0 selects the CFL dt."""
+    q = np.array(q, dtype=np.float64, order="C", copy=True)
+    used = lib().orc_rk3_step(ctypes.byref(g), _dp(q), float(dt))
+    return q, used
+
+
+def run(g: OrcGrid, q: np.ndarray, nsteps: int, dts=None):
+    """nsteps steps; returns (q, dts used).  ``dts`` replays a prescribed sequence."""
+    q = np.array(q, dtype=np.float64, order="C", copy=True)
+    out = np.empty(max(nsteps, 1), dtype=np.float64)
+    if dts is not None:
+        dts = np.ascontiguousarray(dts, dtype=np.float64)
+        assert dts.size >= nsteps
+    lib().orc_run(ctypes.byref(g), _dp(q), int(nsteps), _dp(dts) if dts is not None else None, _dp(out))
+    return q, out[:nsteps]
+
+
+def weno5(v, eps=1e-6):
+    """(left edge, right edge) of the middle cell of a 5-value stencil."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    l = ctypes.c_double()
+    r = ctypes.c_double()
+    lib().orc_weno5(_dp(v), float(eps), ctypes.byref(l), ctypes.byref(r))
+    return l.value, r.value
+
+
+def weno5_betas(v):
+    """The three smoothness indicators of the middle cell of a 5-value stencil."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    b = np.empty(3, dtype=np.float64)
+    lib().orc_weno5_betas(_dp(v), _dp(b))
+    return b
+
+
+def hllc(g: OrcGrid, wl, wr, d: int):
+    wl = np.ascontiguousarray(wl, dtype=np.float64)
+    wr = np.ascontiguousarray(wr, dtype=np.float64)
+    F = np.empty(NV, dtype=np.float64)
+    uf = ctypes.c_double()
+    lib().orc_hllc(ctypes.byref(g), _dp(wl), _dp(wr), int(d), _dp(F), ctypes.byref(uf))
+    return F, uf.value
+
+
+def sound_speed(g: OrcGrid, w) -> float:
+    w = np.ascontiguousarray(w, dtype=np.float64)
+    return lib().orc_sound_speed(ctypes.byref(g), _dp(w))
+
+
+def max_threads() -> int:
+    return lib().orc_max_threads()

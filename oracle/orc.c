@@ -1,0 +1,468 @@
+/*
+ * Plain FP64 CPU oracle for the finite-volume right-hand side of the
+ * two-component five-equation (Allaire) diffuse-interface model and its
+ * SSP-RK3 time step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark may load this library.  It shares no
+ * code, header, table or helper with the GPU library; both sides only read
+ * the same seeded input arrays.
+ *
+ * What it follows (paper: "OpenACC offloading of the MFC compressible
+ * multiphase flow solver on AMD and NVIDIA GPUs", arXiv 2409.10729):
+ *   - model:      Sec. II-A, the two-component Allaire system (the
+ *                 unnumbered align block), read as partial-density
+ *                 continuity, mixture momentum and energy, and alpha_1
+ *                 advection;
+ *   - EOS:        Sec. II-A, stiffened gas with mixture gamma, pi_inf
+ *                 (mixture rules linear in alpha_1 for 1/(gamma-1) and
+ *                 gamma*pi_inf/(gamma-1), after Allaire et al. 2002);
+ *   - scheme:     Sec. II-B, eq. (discretization) and the cell-integrated
+ *                 form below it (eq. rhs): flux differences per direction
+ *                 minus h(q) div(u), with HLLC fluxes (Toro 2009) from
+ *                 WENO5 face states (Shu 2006, Jiang-Shu weights);
+ *   - h(q):       only the alpha_1 equation carries a source, +alpha_1
+ *                 div(u), with div(u) built from the HLLC face velocity
+ *                 (Johnsen & Colonius 2006, the approach the cited
+ *                 Coralic-Colonius scheme uses);
+ *   - time:       SSP-RK3 in Shu-Osher form, CFL time step from the sum
+ *                 over directions of (|u_d| + c) / dx_d.
+ *
+ * Conserved variables, in this order, stored structure-of-arrays as
+ * q[v][k][j][i] (x fastest):
+ *   0: alpha1*rho1  1: alpha2*rho2  2: rho*u  3: rho*v  4: rho*w
+ *   5: rho*E        6: alpha1
+ * Primitive variables (same order): alpha1*rho1, alpha2*rho2, u, v, w, p,
+ * alpha1.
+ *
+ * Ghost cells are materialised in a padded copy (3 layers per active
+ * direction) filled by periodic wrap or zero-gradient copy.  Built with
+ * -O2 -fno-fast-math -ffp-contract=off; OpenMP over pencils only, so the
+ * result does not depend on the thread count.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define NV 7
+#define NG 3
+
+typedef struct {
+    int32_t n[3];      /* interior cells per direction; 1 = inactive */
+    double dx[3];      /* uniform spacing per direction */
+    int32_t bc[3][2];  /* 0 = periodic, 1 = transmissive (zero gradient) */
+    double gamma[2];   /* fluid 1, fluid 2 */
+    double pinf[2];
+    double eps;        /* WENO epsilon */
+    double cfl;
+} orc_grid;
+
+/* ---------- equation of state (Sec. II-A) ---------- */
+
+static double fluid_Gamma(const orc_grid* g, int f) { return 1.0 / (g->gamma[f] - 1.0); }
+static double fluid_Pi(const orc_grid* g, int f)
+{
+    return g->gamma[f] * g->pinf[f] / (g->gamma[f] - 1.0);
+}
+/* mixture 1/(gamma-1) */
+static double mix_Gamma(const orc_grid* g, double a1)
+{
+    return a1 * fluid_Gamma(g, 0) + (1.0 - a1) * fluid_Gamma(g, 1);
+}
+/* mixture gamma*pi_inf/(gamma-1) */
+static double mix_Pi(const orc_grid* g, double a1)
+{
+    return a1 * fluid_Pi(g, 0) + (1.0 - a1) * fluid_Pi(g, 1);
+}
+
+static void cons_to_prim(const orc_grid* g, const double* q, double* w)
+{
+    double rho = q[0] + q[1];
+    double u = q[2] / rho, v = q[3] / rho, ww = q[4] / rho;
+    double ke = 0.5 * rho * (u * u + v * v + ww * ww);
+    double G = mix_Gamma(g, q[6]), P = mix_Pi(g, q[6]);
+    w[0] = q[0];
+    w[1] = q[1];
+    w[2] = u;
+    w[3] = v;
+    w[4] = ww;
+    w[5] = (q[5] - ke - P) / G;
+    w[6] = q[6];
+}
+
+static void prim_to_cons(const orc_grid* g, const double* w, double* q)
+{
+    double rho = w[0] + w[1];
+    double ke = 0.5 * rho * (w[2] * w[2] + w[3] * w[3] + w[4] * w[4]);
+    q[0] = w[0];
+    q[1] = w[1];
+    q[2] = rho * w[2];
+    q[3] = rho * w[3];
+    q[4] = rho * w[4];
+    q[5] = mix_Gamma(g, w[6]) * w[5] + mix_Pi(g, w[6]) + ke;
+    q[6] = w[6];
+}
+
+/* c^2 = ((Gamma+1) p + Pi) / (Gamma rho); for one pure fluid this is
+   gamma (p + pi_inf) / rho. */
+static double sound_speed(const orc_grid* g, const double* w)
+{
+    double rho = w[0] + w[1];
+    double G = mix_Gamma(g, w[6]), P = mix_Pi(g, w[6]);
+    return sqrt(((G + 1.0) * w[5] + P) / (G * rho));
+}
+
+/* ---------- WENO5 (Jiang-Shu weights) ----------
+   Cell c with stencil values v[0..4] = w_{c-2..c+2}.  The three
+   smoothness indicators belong to the cell and serve both of its edges.
+   right = value at c+1/2 (linear weights 1/10, 6/10, 3/10 on the stencils
+   {c-2..c}, {c-1..c+1}, {c..c+2}); left = value at c-1/2 (weights 3/10,
+   6/10, 1/10 on the same stencils).  The indicators are those of Jiang &
+   Shu: for each stencil, h times the cell integral of the squared first
+   derivative plus h^3 times that of the squared second derivative of the
+   stencil's quadratic. */
+static void weno5_betas(const double* v, double* b)
+{
+    b[0] = 13.0 / 12.0 * (v[0] - 2.0 * v[1] + v[2]) * (v[0] - 2.0 * v[1] + v[2]) +
+           0.25 * (v[0] - 4.0 * v[1] + 3.0 * v[2]) * (v[0] - 4.0 * v[1] + 3.0 * v[2]);
+    b[1] = 13.0 / 12.0 * (v[1] - 2.0 * v[2] + v[3]) * (v[1] - 2.0 * v[2] + v[3]) +
+           0.25 * (v[1] - v[3]) * (v[1] - v[3]);
+    b[2] = 13.0 / 12.0 * (v[2] - 2.0 * v[3] + v[4]) * (v[2] - 2.0 * v[3] + v[4]) +
+           0.25 * (3.0 * v[2] - 4.0 * v[3] + v[4]) * (3.0 * v[2] - 4.0 * v[3] + v[4]);
+}
+
+static void weno5(const double* v, double eps, double* left, double* right)
+{
+    double b[3];
+    weno5_betas(v, b);
+    double b0 = b[0], b1 = b[1], b2 = b[2];
+
+    /* right edge c+1/2 */
+    double r0 = (2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2]) / 6.0;
+    double r1 = (-v[1] + 5.0 * v[2] + 2.0 * v[3]) / 6.0;
+    double r2 = (2.0 * v[2] + 5.0 * v[3] - v[4]) / 6.0;
+    double a0 = 0.1 / ((eps + b0) * (eps + b0));
+    double a1 = 0.6 / ((eps + b1) * (eps + b1));
+    double a2 = 0.3 / ((eps + b2) * (eps + b2));
+    double s = a0 + a1 + a2;
+    *right = (a0 / s) * r0 + (a1 / s) * r1 + (a2 / s) * r2;
+
+    /* left edge c-1/2 */
+    double l0 = (-v[0] + 5.0 * v[1] + 2.0 * v[2]) / 6.0;
+    double l1 = (2.0 * v[1] + 5.0 * v[2] - v[3]) / 6.0;
+    double l2 = (11.0 * v[2] - 7.0 * v[3] + 2.0 * v[4]) / 6.0;
+    a0 = 0.3 / ((eps + b0) * (eps + b0));
+    a1 = 0.6 / ((eps + b1) * (eps + b1));
+    a2 = 0.1 / ((eps + b2) * (eps + b2));
+    s = a0 + a1 + a2;
+    *left = (a0 / s) * l0 + (a1 / s) * l1 + (a2 / s) * l2;
+}
+
+/* ---------- HLLC (Toro 2009, Davis wave speeds) ----------
+   Face with normal along direction d; wl, wr primitive states.  Returns
+   the 7 flux components and the face velocity used for div(u). */
+static void hllc(const orc_grid* g, const double* wl, const double* wr, int d, double* F,
+                 double* uf)
+{
+    double rl = wl[0] + wl[1], rr = wr[0] + wr[1];
+    double pl = wl[5], pr = wr[5];
+    double unl = wl[2 + d], unr = wr[2 + d];
+    double El = mix_Gamma(g, wl[6]) * pl + mix_Pi(g, wl[6]) +
+                0.5 * rl * (wl[2] * wl[2] + wl[3] * wl[3] + wl[4] * wl[4]);
+    double Er = mix_Gamma(g, wr[6]) * pr + mix_Pi(g, wr[6]) +
+                0.5 * rr * (wr[2] * wr[2] + wr[3] * wr[3] + wr[4] * wr[4]);
+    double cl = sound_speed(g, wl), cr = sound_speed(g, wr);
+
+    double SL = fmin(unl - cl, unr - cr);
+    double SR = fmax(unl + cl, unr + cr);
+    double Ss = (pr - pl + rl * unl * (SL - unl) - rr * unr * (SR - unr)) /
+                (rl * (SL - unl) - rr * (SR - unr));
+
+    /* pick the side of the contact (ties go left) */
+    const double* w;
+    double rho, p, un, E, S, s;
+    if (Ss >= 0.0) {
+        w = wl; rho = rl; p = pl; un = unl; E = El; S = SL; s = fmin(0.0, SL);
+    } else {
+        w = wr; rho = rr; p = pr; un = unr; E = Er; S = SR; s = fmax(0.0, SR);
+    }
+
+    double U[NV], Fk[NV], Us[NV];
+    U[0] = w[0];
+    U[1] = w[1];
+    U[2] = rho * w[2];
+    U[3] = rho * w[3];
+    U[4] = rho * w[4];
+    U[5] = E;
+    U[6] = w[6];
+
+    for (int v = 0; v < NV; ++v) Fk[v] = U[v] * un;
+    Fk[2 + d] = Fk[2 + d] + p;
+    Fk[5] = (E + p) * un;
+
+    double xi = (S - un) / (S - Ss);
+    Us[0] = xi * w[0];
+    Us[1] = xi * w[1];
+    Us[2] = xi * (rho * w[2]);
+    Us[3] = xi * (rho * w[3]);
+    Us[4] = xi * (rho * w[4]);
+    Us[2 + d] = xi * (rho * Ss);
+    Us[5] = xi * (E + (Ss - un) * (rho * Ss + p / (S - un)));
+    Us[6] = xi * w[6];
+
+    for (int v = 0; v < NV; ++v) F[v] = Fk[v] + s * (Us[v] - U[v]);
+    *uf = un + s * (xi - 1.0);
+}
+
+/* ---------- boundary index map ---------- */
+static int64_t map_index(const orc_grid* g, int d, int64_t i)
+{
+    int64_t n = g->n[d];
+    if (i >= 0 && i < n) return i;
+    if (i < 0) {
+        if (g->bc[d][0] == 0) return ((i % n) + n) % n;
+        return 0;
+    }
+    if (g->bc[d][1] == 0) return i % n;
+    return n - 1;
+}
+
+static int active(const orc_grid* g, int d) { return g->n[d] > 1; }
+
+/* ---------- exported helpers for unit tests ---------- */
+void orc_weno5(const double* v, double eps, double* left, double* right)
+{
+    weno5(v, eps, left, right);
+}
+void orc_weno5_betas(const double* v, double* b) { weno5_betas(v, b); }
+void orc_hllc(const orc_grid* g, const double* wl, const double* wr, int d, double* F, double* uf)
+{
+    hllc(g, wl, wr, d, F, uf);
+}
+double orc_sound_speed(const orc_grid* g, const double* w) { return sound_speed(g, w); }
+void orc_cons_to_prim_cell(const orc_grid* g, const double* q, double* w) { cons_to_prim(g, q, w); }
+void orc_prim_to_cons_cell(const orc_grid* g, const double* w, double* q) { prim_to_cons(g, w, q); }
+
+int orc_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+static int64_t ncells(const orc_grid* g) { return (int64_t)g->n[0] * g->n[1] * g->n[2]; }
+
+/* Whole-array conversions, layout [7][nz][ny][nx]. */
+void orc_prim_to_cons(const orc_grid* g, const double* w, double* q)
+{
+    int64_t N = ncells(g);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+        double wc[NV], qc[NV];
+        for (int v = 0; v < NV; ++v) wc[v] = w[v * N + c];
+        prim_to_cons(g, wc, qc);
+        for (int v = 0; v < NV; ++v) q[v * N + c] = qc[v];
+    }
+}
+
+void orc_cons_to_prim(const orc_grid* g, const double* q, double* w)
+{
+    int64_t N = ncells(g);
+#pragma omp parallel for schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+        double wc[NV], qc[NV];
+        for (int v = 0; v < NV; ++v) qc[v] = q[v * N + c];
+        cons_to_prim(g, qc, wc);
+        for (int v = 0; v < NV; ++v) w[v * N + c] = wc[v];
+    }
+}
+
+/* ---------- right-hand side on the whole grid ---------- */
+void orc_rhs(const orc_grid* g, const double* q, double* rhs)
+{
+    int gh[3], P[3];
+    for (int d = 0; d < 3; ++d) {
+        gh[d] = active(g, d) ? NG : 0;
+        P[d] = g->n[d] + 2 * gh[d];
+    }
+    const int64_t N = ncells(g);
+    const int64_t NP = (int64_t)P[0] * P[1] * P[2];
+    double* wp = (double*)malloc(sizeof(double) * NV * NP);
+
+    /* padded primitive array: ghosts filled by the BC map, then converted */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int k = 0; k < P[2]; ++k)
+        for (int j = 0; j < P[1]; ++j) {
+            int64_t sk = map_index(g, 2, k - gh[2]);
+            int64_t sj = map_index(g, 1, j - gh[1]);
+            for (int i = 0; i < P[0]; ++i) {
+                int64_t si = map_index(g, 0, i - gh[0]);
+                int64_t src = (sk * g->n[1] + sj) * g->n[0] + si;
+                int64_t dst = ((int64_t)k * P[1] + j) * P[0] + i;
+                double qc[NV], wc[NV];
+                for (int v = 0; v < NV; ++v) qc[v] = q[v * N + src];
+                cons_to_prim(g, qc, wc);
+                for (int v = 0; v < NV; ++v) wp[v * NP + dst] = wc[v];
+            }
+        }
+
+    for (int64_t x = 0; x < NV * N; ++x) rhs[x] = 0.0;
+
+    /* one sweep per active direction, in the order x, y, z */
+    for (int d = 0; d < 3; ++d) {
+        if (!active(g, d)) continue;
+        int a = (d == 0) ? 1 : 0;          /* first transverse direction */
+        int b = (d == 2) ? 1 : 2;          /* second transverse direction */
+        int64_t stride_p[3] = {1, P[0], (int64_t)P[0] * P[1]};
+        int64_t stride_n[3] = {1, g->n[0], (int64_t)g->n[0] * g->n[1]};
+        int n = g->n[d];
+#pragma omp parallel for collapse(2) schedule(static)
+        for (int ib = 0; ib < g->n[b]; ++ib)
+            for (int ia = 0; ia < g->n[a]; ++ia) {
+                /* edges of cells -1..n, faces 0..n (face f sits between f-1 and f) */
+                double* lft = (double*)malloc(sizeof(double) * NV * (n + 2));
+                double* rgt = (double*)malloc(sizeof(double) * NV * (n + 2));
+                double* F = (double*)malloc(sizeof(double) * NV * (n + 1));
+                double* uf = (double*)malloc(sizeof(double) * (n + 1));
+                int64_t base_p = (ia + gh[a]) * stride_p[a] + (ib + gh[b]) * stride_p[b];
+                int64_t base_n = ia * stride_n[a] + ib * stride_n[b];
+                for (int c = -1; c <= n; ++c) {
+                    for (int v = 0; v < NV; ++v) {
+                        double st[5];
+                        for (int o = -2; o <= 2; ++o)
+                            st[o + 2] = wp[v * NP + base_p + (int64_t)(c + gh[d] + o) * stride_p[d]];
+                        weno5(st, g->eps, &lft[(c + 1) * NV + v], &rgt[(c + 1) * NV + v]);
+                    }
+                }
+                for (int f = 0; f <= n; ++f)
+                    hllc(g, &rgt[f * NV], &lft[(f + 1) * NV], d, &F[f * NV], &uf[f]);
+                for (int i = 0; i < n; ++i) {
+                    int64_t cell = base_n + (int64_t)i * stride_n[d];
+                    double a1 = wp[6 * NP + base_p + (int64_t)(i + gh[d]) * stride_p[d]];
+                    for (int v = 0; v < NV; ++v)
+                        rhs[v * N + cell] += (F[i * NV + v] - F[(i + 1) * NV + v]) / g->dx[d];
+                    rhs[6 * N + cell] += a1 * ((uf[i + 1] - uf[i]) / g->dx[d]);
+                }
+                free(lft);
+                free(rgt);
+                free(F);
+                free(uf);
+            }
+    }
+    free(wp);
+}
+
+/* ---------- right-hand side at selected cells, one by one ----------
+   cells: linear indices (k*ny + j)*nx + i; out: [ncell][7].  Uses the same
+   per-cell formulas with the BC map applied to each stencil index, and the
+   same accumulation order, so it equals orc_rhs at those cells. */
+void orc_rhs_at(const orc_grid* g, const double* q, int64_t ncell, const int64_t* cells, double* out)
+{
+    const int64_t N = ncells(g);
+    int64_t stride_n[3] = {1, g->n[0], (int64_t)g->n[0] * g->n[1]};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t c = 0; c < ncell; ++c) {
+        int64_t lin = cells[c];
+        int64_t pos[3] = {lin % g->n[0], (lin / g->n[0]) % g->n[1], lin / ((int64_t)g->n[0] * g->n[1])};
+        double r[NV] = {0, 0, 0, 0, 0, 0, 0};
+        for (int d = 0; d < 3; ++d) {
+            if (!active(g, d)) continue;
+            double w7[7][NV];
+            for (int o = -3; o <= 3; ++o) {
+                int64_t p2[3] = {pos[0], pos[1], pos[2]};
+                p2[d] = map_index(g, d, pos[d] + o);
+                int64_t src = p2[0] * stride_n[0] + p2[1] * stride_n[1] + p2[2] * stride_n[2];
+                double qc[NV];
+                for (int v = 0; v < NV; ++v) qc[v] = q[v * N + src];
+                cons_to_prim(g, qc, w7[o + 3]);
+            }
+            double lft[3][NV], rgt[3][NV];
+            for (int cc = 0; cc < 3; ++cc)
+                for (int v = 0; v < NV; ++v) {
+                    double st[5];
+                    for (int o = 0; o < 5; ++o) st[o] = w7[cc + o][v];
+                    weno5(st, g->eps, &lft[cc][v], &rgt[cc][v]);
+                }
+            double Fm[NV], Fp[NV], um, up;
+            hllc(g, rgt[0], lft[1], d, Fm, &um);
+            hllc(g, rgt[1], lft[2], d, Fp, &up);
+            for (int v = 0; v < NV; ++v) r[v] += (Fm[v] - Fp[v]) / g->dx[d];
+            r[6] += w7[3][6] * ((up - um) / g->dx[d]);
+        }
+        for (int v = 0; v < NV; ++v) out[c * NV + v] = r[v];
+    }
+}
+
+/* ---------- CFL time step ---------- */
+double orc_cfl_dt(const orc_grid* g, const double* q)
+{
+    const int64_t N = ncells(g);
+    double smax = 0.0;
+#pragma omp parallel for reduction(max : smax) schedule(static)
+    for (int64_t c = 0; c < N; ++c) {
+        double qc[NV], wc[NV];
+        for (int v = 0; v < NV; ++v) qc[v] = q[v * N + c];
+        cons_to_prim(g, qc, wc);
+        double cs = sound_speed(g, wc);
+        double s = 0.0;
+        for (int d = 0; d < 3; ++d)
+            if (active(g, d)) s = s + (fabs(wc[2 + d]) + cs) / g->dx[d];
+        if (s > smax) smax = s;
+    }
+    return g->cfl / smax;
+}
+
+/* ---------- SSP-RK3 (Shu-Osher) ----------
+   stage 1: out = qs + dt*L
+   stage 2: out = 3/4 qn + 1/4 (qs + dt*L)
+   stage 3: out = 1/3 qn + 2/3 (qs + dt*L) */
+void orc_rk3_combine(int stage, int64_t n, const double* qn, const double* qs, const double* L,
+                     double dt, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t x = 0; x < n; ++x) {
+        if (stage == 1)
+            out[x] = qs[x] + dt * L[x];
+        else if (stage == 2)
+            out[x] = 0.75 * qn[x] + 0.25 * (qs[x] + dt * L[x]);
+        else
+            out[x] = (1.0 / 3.0) * qn[x] + (2.0 / 3.0) * (qs[x] + dt * L[x]);
+    }
+}
+
+/* One SSP-RK3 step in place.  dt <= 0 selects the CFL time step of q.
+   Returns the time step used. */
+double orc_rk3_step(const orc_grid* g, double* q, double dt)
+{
+    const int64_t M = NV * ncells(g);
+    if (!(dt > 0.0)) dt = orc_cfl_dt(g, q);
+    double* L = (double*)malloc(sizeof(double) * M);
+    double* q1 = (double*)malloc(sizeof(double) * M);
+    double* q2 = (double*)malloc(sizeof(double) * M);
+    orc_rhs(g, q, L);
+    orc_rk3_combine(1, M, q, q, L, dt, q1);
+    orc_rhs(g, q1, L);
+    orc_rk3_combine(2, M, q, q1, L, dt, q2);
+    orc_rhs(g, q2, L);
+    orc_rk3_combine(3, M, q, q2, L, dt, q);
+    free(L);
+    free(q1);
+    free(q2);
+    return dt;
+}
+
+/* nsteps steps in place.  dts_in (may be NULL) prescribes each step's dt;
+   dts_out (may be NULL) receives the dt used at each step. */
+void orc_run(const orc_grid* g, double* q, int nsteps, const double* dts_in, double* dts_out)
+{
+    for (int s = 0; s < nsteps; ++s) {
+        double dt = orc_rk3_step(g, q, dts_in ? dts_in[s] : 0.0);
+        if (dts_out) dts_out[s] = dt;
+    }
+}

@@ -1,0 +1,256 @@
+"""Seeded synthetic problems shaped like the paper's two-phase workloads.
+
+This module only draws initial conditions in PRIMITIVE variables
+(alpha1*rho1, alpha2*rho2, u, v, w, p, alpha1), stored [7][nz][ny][nx] in
+float64, plus the grid description.  It holds none of the solver's
+arithmetic (no equation of state, no reconstruction, no fluxes): both the
+GPU library and the CPU oracle convert these fields to conserved variables
+with their own code.
+
+Fluid 1 is water-like (gamma 4.4, pi_inf 6e8), fluid 2 air-like (gamma 1.4,
+pi_inf 0).  Domain [0,1]^d, uniform spacing 1/n, cell centres (i + 1/2)/n.
+Random numbers come from numpy's PCG64 ``default_rng(seed)``.
+
+Workloads (the paper's demonstrations, Sec. V, are 2B-cell shock-droplet and
+shock-bubble-cloud runs; these are single-GPU blocks of the same physics):
+  shock_tube      1D water|air tube, 1000 cells, transmissive
+  advected_bubble 3D periodic air bubble in water, uniform velocity
+  shock_droplet   3D Mach-2 air shock on a water droplet with 1% density noise
+  bubble_cloud    3D Mach-1.5 water shock on several air bubbles
+  droplet_cloud   3D Mach-2 air shock on many log-uniform droplets
+  random_smooth   small random valid states for RHS parity
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+PERIODIC, TRANSMISSIVE = 0, 1
+WATER = (4.4, 6.0e8)
+AIR = (1.4, 0.0)
+ALPHA_EPS = 1.0e-6
+
+
+def spec(n, bc, cfl=0.4, eps=1e-6):
+    n = tuple(int(v) for v in n)
+    return {
+        "n": n,
+        "dx": tuple(1.0 / v for v in n),
+        "lo": (0.0, 0.0, 0.0),
+        "bc": tuple(tuple(int(b) for b in pair) for pair in bc),
+        "gamma": (WATER[0], AIR[0]),
+        "pinf": (WATER[1], AIR[1]),
+        "eps": float(eps),
+        "cfl": float(cfl),
+    }
+
+
+def _centres(n):
+    nx, ny, nz = n
+    x = (np.arange(nx) + 0.5) / nx
+    y = (np.arange(ny) + 0.5) / ny
+    z = (np.arange(nz) + 0.5) / nz
+    return np.meshgrid(z, y, x, indexing="ij")  # Z, Y, X each [nz, ny, nx]
+
+
+def _pack(a1, rho1, rho2, u, v, w, p):
+    a1 = np.asarray(a1, dtype=np.float64)
+    shape = a1.shape
+    out = np.empty((7,) + shape, dtype=np.float64)
+    out[0] = a1 * rho1
+    out[1] = (1.0 - a1) * rho2
+    out[2] = u
+    out[3] = v
+    out[4] = w
+    out[5] = p
+    out[6] = a1
+    return out
+
+
+def _smooth_indicator(dist, radius, width):
+    """1 inside the sphere, 0 outside, tanh transition of the given width."""
+    return 0.5 * (1.0 - np.tanh((dist - radius) / width))
+
+
+def shock_tube(n=1000, x0=0.5, p_left=1.0e9, p_right=1.0e5, rho_w=1000.0, rho_a=50.0):
+    """Water (left, alpha1 = 1-1e-6) against air (right, alpha1 = 1e-6), both at rest."""
+    s = spec((n, 1, 1), ((TRANSMISSIVE, TRANSMISSIVE), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)))
+    x = (np.arange(n) + 0.5) / n
+    left = x < x0
+    a1 = np.where(left, 1.0 - ALPHA_EPS, ALPHA_EPS)
+    p = np.where(left, p_left, p_right)
+    w = _pack(a1, rho_w, rho_a, 0.0, 0.0, 0.0, p)
+    return {"name": "shock_tube", "spec": s, "w": w.reshape(7, 1, 1, n)}
+
+
+def advected_bubble(n=128, seed=0, velocity=(1.0, 0.5, 0.25), p0=1.0e5):
+    """Air bubble (radius U(0.1,0.2), centre U(0,1)^3) in water; periodic;
+    interface alpha1 = e + (1-2e) * 0.5 (1 + tanh((r-R)/(1.5 dx)))."""
+    n3 = (n, n, n) if np.isscalar(n) else tuple(n)
+    rng = np.random.default_rng(seed)
+    R = rng.uniform(0.1, 0.2)
+    c = rng.uniform(0.0, 1.0, size=3)
+    s = spec(n3, ((PERIODIC, PERIODIC),) * 3)
+    Z, Y, X = _centres(n3)
+    d = [X - c[0], Y - c[1], Z - c[2]]
+    d = [a - np.round(a) for a in d]  # minimum image on the unit torus
+    r = np.sqrt(d[0] ** 2 + d[1] ** 2 + d[2] ** 2)
+    width = 1.5 / max(n3)
+    a1 = ALPHA_EPS + (1.0 - 2.0 * ALPHA_EPS) * 0.5 * (1.0 + np.tanh((r - R) / width))
+    w = _pack(a1, 1000.0, 1.2, velocity[0], velocity[1], velocity[2], p0)
+    return {"name": "advected_bubble", "spec": s, "w": w, "meta": {"R": R, "centre": c.tolist()}}
+
+
+def _ideal_gas_shock(M, rho1, p1, gamma):
+    """Post-shock (rho, p, u) behind a shock of Mach M into gas at rest
+    (normal-shock relations)."""
+    c1 = math.sqrt(gamma * p1 / rho1)
+    p2 = p1 * (1.0 + 2.0 * gamma / (gamma + 1.0) * (M * M - 1.0))
+    rho2 = rho1 * (gamma + 1.0) * M * M / ((gamma - 1.0) * M * M + 2.0)
+    u2 = M * c1 * (1.0 - rho1 / rho2)
+    return rho2, p2, u2
+
+
+def _stiff_shock(M, rho1, p1, gamma, pinf):
+    """Same relations written in p + pi_inf (stiffened gas)."""
+    c1 = math.sqrt(gamma * (p1 + pinf) / rho1)
+    pb2 = (p1 + pinf) * (1.0 + 2.0 * gamma / (gamma + 1.0) * (M * M - 1.0))
+    rho2 = rho1 * (gamma + 1.0) * M * M / ((gamma - 1.0) * M * M + 2.0)
+    u2 = M * c1 * (1.0 - rho1 / rho2)
+    return rho2, pb2 - pinf, u2
+
+
+def _noise(rng, shape, amp=0.01):
+    return 1.0 + amp * np.clip(rng.standard_normal(shape), -3.0, 3.0)
+
+
+def shock_droplet(n=256, seed=0, mach=2.0, radius=0.15, noise=0.01):
+    """Mach-2 air shock (ideal-gas normal-shock state) 4 cells upstream of a
+    water droplet (radius 0.15, centre (0.5,0.5,0.5) + U(-0.05,0.05)^3);
+    x transmissive, y/z periodic; 1% Gaussian multiplicative density noise
+    (clipped at 3 sigma) on both partial densities."""
+    n3 = (n, n, n) if np.isscalar(n) else tuple(n)
+    rng = np.random.default_rng(seed)
+    c = 0.5 + rng.uniform(-0.05, 0.05, size=3)
+    s = spec(n3, ((TRANSMISSIVE, TRANSMISSIVE), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)))
+    Z, Y, X = _centres(n3)
+    h = 1.0 / n3[0]
+    r = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)
+    water = _smooth_indicator(r, radius, 1.5 * h)
+    a1 = ALPHA_EPS + (1.0 - 2.0 * ALPHA_EPS) * water
+    rho_a1, p_a1 = 1.2, 1.0e5
+    rho_a2, p_a2, u_a2 = _ideal_gas_shock(mach, rho_a1, p_a1, AIR[0])
+    xs = c[0] - radius - 4.0 * h
+    post = X < xs
+    rho_air = np.where(post, rho_a2, rho_a1)
+    p = np.where(post, p_a2, p_a1)
+    u = np.where(post, u_a2, 0.0)
+    w = _pack(a1, 1000.0, rho_air, u, 0.0, 0.0, p)
+    f = _noise(rng, a1.shape, noise)
+    w[0] *= f
+    w[1] *= f
+    return {"name": "shock_droplet", "spec": s, "w": w,
+            "meta": {"centre": c.tolist(), "radius": radius, "shock_x": xs}}
+
+
+def _place_spheres(rng, count, rmin, rmax, gap, log_uniform, xmin=0.15, tries=20000):
+    centres, radii = [], []
+    for _ in range(tries):
+        if len(radii) == count:
+            break
+        r = math.exp(rng.uniform(math.log(rmin), math.log(rmax))) if log_uniform else rng.uniform(rmin, rmax)
+        c = np.array([rng.uniform(xmin + r, 1.0 - r - gap), rng.uniform(r, 1.0 - r), rng.uniform(r, 1.0 - r)])
+        if all(np.linalg.norm(c - c2) >= r + r2 + gap for c2, r2 in zip(centres, radii)):
+            centres.append(c)
+            radii.append(r)
+    return centres, radii
+
+
+def bubble_cloud(n=192, seed=0, mach=1.5):
+    """Water at rest (rho 1000, p 1e5) with U{4..16} non-overlapping air
+    bubbles of radius U(0.05,0.15) (gap >= 4 cells); Mach-1.5 water shock
+    (stiffened-gas normal-shock state) 4 cells upstream of the first bubble."""
+    n3 = (n, n, n) if np.isscalar(n) else tuple(n)
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n3[0]
+    nb = int(rng.integers(4, 17))
+    centres, radii = _place_spheres(rng, nb, 0.05, 0.15, 4.0 * h, False)
+    s = spec(n3, ((TRANSMISSIVE, TRANSMISSIVE), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)))
+    Z, Y, X = _centres(n3)
+    air = np.zeros(X.shape)
+    for c, R in zip(centres, radii):
+        r = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)
+        air = np.maximum(air, _smooth_indicator(r, R, 1.5 * h))
+    a1 = ALPHA_EPS + (1.0 - 2.0 * ALPHA_EPS) * (1.0 - air)
+    rho2, p2, u2 = _stiff_shock(mach, 1000.0, 1.0e5, WATER[0], WATER[1])
+    xs = min(c[0] - R for c, R in zip(centres, radii)) - 4.0 * h
+    post = X < xs
+    rho_w = np.where(post, rho2, 1000.0)
+    p = np.where(post, p2, 1.0e5)
+    u = np.where(post, u2, 0.0)
+    w = _pack(a1, rho_w, 1.2, u, 0.0, 0.0, p)
+    return {"name": "bubble_cloud", "spec": s, "w": w,
+            "meta": {"bubbles": len(radii), "shock_x": xs}}
+
+
+def droplet_cloud(n=384, seed=0, count=32, mach=2.0, noise=0.01):
+    """Shock-droplet physics with ``count`` non-overlapping water droplets of
+    log-uniform radius in [0.02, 0.1]."""
+    n3 = (n, n, n) if np.isscalar(n) else tuple(n)
+    rng = np.random.default_rng(seed)
+    h = 1.0 / n3[0]
+    centres, radii = _place_spheres(rng, count, 0.02, 0.1, 4.0 * h, True, xmin=0.2)
+    s = spec(n3, ((TRANSMISSIVE, TRANSMISSIVE), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)))
+    Z, Y, X = _centres(n3)
+    water = np.zeros(X.shape)
+    for c, R in zip(centres, radii):
+        r = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)
+        water = np.maximum(water, _smooth_indicator(r, R, 1.5 * h))
+    a1 = ALPHA_EPS + (1.0 - 2.0 * ALPHA_EPS) * water
+    rho_a2, p_a2, u_a2 = _ideal_gas_shock(mach, 1.2, 1.0e5, AIR[0])
+    xs = min(c[0] - R for c, R in zip(centres, radii)) - 4.0 * h
+    post = X < xs
+    rho_air = np.where(post, rho_a2, 1.2)
+    p = np.where(post, p_a2, 1.0e5)
+    u = np.where(post, u_a2, 0.0)
+    w = _pack(a1, 1000.0, rho_air, u, 0.0, 0.0, p)
+    f = _noise(rng, a1.shape, noise)
+    w[0] *= f
+    w[1] *= f
+    return {"name": "droplet_cloud", "spec": s, "w": w,
+            "meta": {"droplets": len(radii), "shock_x": xs}}
+
+
+def random_smooth(n=(24, 20, 16), seed=0, bc=None, jumps=True):
+    """Random valid state: smooth Fourier-mode fields plus (optionally) a
+    material interface and a pressure jump, for RHS parity on small grids.
+    bc defaults to periodic in every direction."""
+    n3 = tuple(int(v) for v in n)
+    rng = np.random.default_rng(seed)
+    if bc is None:
+        bc = ((PERIODIC, PERIODIC),) * 3
+    s = spec(n3, bc)
+    Z, Y, X = _centres(n3)
+
+    def field(amp):
+        f = np.zeros(X.shape)
+        for _ in range(3):
+            k = rng.integers(1, 3, size=3)
+            ph = rng.uniform(0, 2 * math.pi, size=3)
+            f += rng.uniform(-1, 1) * np.sin(2 * math.pi * k[0] * X + ph[0]) * \
+                np.sin(2 * math.pi * k[1] * Y + ph[1]) * np.sin(2 * math.pi * k[2] * Z + ph[2])
+        return amp * f / 3.0
+
+    a1 = 0.5 + field(0.45)
+    p = 1.0e5 * (1.0 + field(0.5))
+    rho1 = 1000.0 * (1.0 + field(0.05))
+    rho2 = 1.2 * (1.0 + field(0.3))
+    u, v, w_ = field(50.0), field(50.0), field(50.0)
+    if jumps:
+        cx = rng.uniform(0.3, 0.7)
+        inside = X < cx
+        a1 = np.where(inside, 1.0 - ALPHA_EPS, a1)
+        p = np.where(Y < rng.uniform(0.3, 0.7), p * 20.0, p)
+    w = _pack(a1, rho1, rho2, u, v, w_, p)
+    return {"name": "random_smooth", "spec": s, "w": w}
