@@ -1,0 +1,109 @@
+"""ctypes binding of the mfx C ABI (include/mfx.h).
+
+Argument marshalling only: every step of the solver runs in the HIP library
+``libmfx.so`` built in-tree next to this file.  Importing this module fails
+loudly if the library is missing; there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmfx.so")
+
+MFX_OK, MFX_EINVAL, MFX_EHIP, MFX_ENOMEM, MFX_ESTATE = 0, -1, -2, -3, -4
+MFX_BC_PERIODIC, MFX_BC_TRANSMISSIVE = 0, 1
+MFX_FP64, MFX_FP32_MIXED = 0, 1
+MFX_WENO5_JS, MFX_WENO5_LEARNED = 0, 1
+
+EXPORTED = (
+    "mfx_workspace_bytes", "mfx_init_grid", "mfx_set_state", "mfx_set_primitive", "mfx_get_state",
+    "mfx_rhs", "mfx_rk3_step", "mfx_set_mlp", "mfx_stats", "mfx_profile", "mfx_profile_read",
+    "mfx_destroy", "mfx_last_error",
+)
+PROF_KINDS = 30
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int32 * 3),
+        ("lo", ctypes.c_double * 3),
+        ("dx", ctypes.c_double * 3),
+        ("bc", (ctypes.c_int32 * 2) * 3),
+        ("gamma", ctypes.c_double * 2),
+        ("pi_inf", ctypes.c_double * 2),
+        ("cfl", ctypes.c_double),
+        ("weno_eps", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("weights", ctypes.c_int32),
+    ]
+
+
+class MfxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"mfx error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libmfx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                              "or python -m paper_2409_10729_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        dp = ctypes.POINTER(GridDesc)
+        L.mfx_workspace_bytes.argtypes = [dp]
+        L.mfx_workspace_bytes.restype = ctypes.c_size_t
+        L.mfx_init_grid.argtypes = [dp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)]
+        L.mfx_init_grid.restype = ctypes.c_int
+        for name in ("mfx_set_state", "mfx_set_primitive", "mfx_get_state", "mfx_rhs"):
+            f = getattr(L, name)
+            f.argtypes = [vp, vp]
+            f.restype = ctypes.c_int
+        L.mfx_rk3_step.argtypes = [vp, ctypes.c_double, ctypes.POINTER(ctypes.c_double)]
+        L.mfx_rk3_step.restype = ctypes.c_int
+        L.mfx_set_mlp.argtypes = [vp, vp, ctypes.c_int32]
+        L.mfx_set_mlp.restype = ctypes.c_int
+        L.mfx_stats.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64),
+                                ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint32)]
+        L.mfx_stats.restype = ctypes.c_int
+        L.mfx_profile.argtypes = [vp, ctypes.c_int]
+        L.mfx_profile.restype = ctypes.c_int
+        L.mfx_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        L.mfx_profile_read.restype = ctypes.c_int
+        L.mfx_destroy.argtypes = [vp]
+        L.mfx_destroy.restype = None
+        L.mfx_last_error.argtypes = [vp]
+        L.mfx_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def make_desc(spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS) -> GridDesc:
+    d = GridDesc()
+    for k in range(3):
+        d.n[k] = int(spec["n"][k])
+        d.lo[k] = float(spec.get("lo", (0.0, 0.0, 0.0))[k])
+        d.dx[k] = float(spec["dx"][k])
+        d.bc[k][0] = int(spec["bc"][k][0])
+        d.bc[k][1] = int(spec["bc"][k][1])
+    d.gamma[0], d.gamma[1] = map(float, spec["gamma"])
+    d.pi_inf[0], d.pi_inf[1] = map(float, spec["pinf"])
+    d.cfl = float(spec.get("cfl", 0.4))
+    d.weno_eps = float(spec.get("eps", 1e-6))
+    d.precision = int(precision)
+    d.weights = int(weights)
+    return d
+
+
+def check(rc: int, ctx=None):
+    if rc != MFX_OK:
+        msg = lib().mfx_last_error(ctx)
+        raise MfxError(rc, msg.decode() if msg else "")

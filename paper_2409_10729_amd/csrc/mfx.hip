@@ -1,0 +1,651 @@
+// mfx C ABI: context, workspace layout, launch sequencing of the per-direction
+// sweeps for the right-hand side and the SSP-RK3 step, and the small kernels
+// around them (primitive -> conserved, CFL reduction, state validation).
+//
+// Paper: arXiv 2409.10729, Sec. II-B (eq. discretization / eq. rhs).  The
+// interface is declared in include/mfx.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/mfx.h"
+#include "sweep.h"
+
+using namespace mfx;
+
+namespace {
+
+constexpr int SWEEP_BLOCK = 256;
+constexpr int UTIL_BLOCK = 256;
+constexpr int CFL_BLOCKS = 1024;  // grid of the standalone CFL reduction
+constexpr size_t ALIGN = 256;
+
+thread_local std::string g_init_error;
+
+size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    size_t q, q1, q2, r, scal, partial, total;
+    long long n_partial;
+};
+
+// Geometry of one sweep launch for direction d.
+struct SweepGeom {
+    dim3 grid;
+    int seg;
+};
+
+SweepGeom sweep_geom(const int n[3], int d, int seg_override)
+{
+    int seg = seg_override > 0 ? seg_override : 64;
+    SweepGeom g;
+    if (d == 0) {
+        // blocks of XROWS rows (y,z flattened), segments along x
+        const long long rows = (long long)n[1] * n[2];
+        while (seg > 16 && rows * ((n[0] + seg - 1) / seg) < 256LL * 64 * 16) seg /= 2;
+        seg = std::min(seg, n[0]);
+        g.grid = dim3((unsigned)((rows + XROWS - 1) / XROWS), 1, (n[0] + seg - 1) / seg);
+    } else {
+        const int sa = (d == 2) ? 1 : 2;
+        const long long pencils = (long long)n[0] * n[sa];
+        // keep enough waves in flight: shrink segments while the pencil count is small
+        while (seg > 16 && pencils * ((n[d] + seg - 1) / seg) < 256LL * 64 * 16) seg /= 2;
+        seg = std::min(seg, n[d]);
+        g.grid = dim3((n[0] + SWEEP_BLOCK - 1) / SWEEP_BLOCK, n[sa], (n[d] + seg - 1) / seg);
+    }
+    g.seg = seg;
+    return g;
+}
+
+Layout make_layout(const mfx_grid_desc* d, int seg_override)
+{
+    Layout L{};
+    const long long N = (long long)d->n[0] * d->n[1] * d->n[2];
+    const size_t state = align_up(sizeof(double) * 7 * (size_t)N);
+    long long np = CFL_BLOCKS;
+    for (int k = 0; k < 3; ++k) {
+        if (d->n[k] <= 1) continue;
+        SweepGeom g = sweep_geom(d->n, k, seg_override);
+        np = std::max(np, (long long)g.grid.x * g.grid.y * g.grid.z);
+    }
+    if (d->n[0] == 1 && d->n[1] == 1 && d->n[2] == 1) {
+        SweepGeom g = sweep_geom(d->n, 0, seg_override);
+        np = std::max(np, (long long)g.grid.x * g.grid.y * g.grid.z);
+    }
+    size_t off = 0;
+    L.q = off;
+    off += state;
+    L.q1 = off;
+    off += state;
+    L.q2 = off;
+    off += state;
+    L.r = off;
+    off += state;
+    L.scal = off;
+    off += align_up(64);
+    L.partial = off;
+    off += align_up(sizeof(double) * (size_t)np);
+    L.total = off;
+    L.n_partial = np;
+    return L;
+}
+
+bool validate(const mfx_grid_desc* d, std::string& why)
+{
+    if (!d) {
+        why = "descriptor is NULL";
+        return false;
+    }
+    long long N = 1;
+    for (int k = 0; k < 3; ++k) {
+        if (d->n[k] < 1 || d->n[k] > 65535) {
+            why = "n[" + std::to_string(k) + "] must lie in [1, 65535]";
+            return false;
+        }
+        N *= d->n[k];
+        if (!(d->dx[k] > 0.0) || !std::isfinite(d->dx[k])) {
+            why = "dx[" + std::to_string(k) + "] must be finite and > 0";
+            return false;
+        }
+        for (int s = 0; s < 2; ++s)
+            if (d->bc[k][s] != MFX_BC_PERIODIC && d->bc[k][s] != MFX_BC_TRANSMISSIVE) {
+                why = "bc[" + std::to_string(k) + "] holds an unknown boundary type";
+                return false;
+            }
+        if ((d->bc[k][0] == MFX_BC_PERIODIC) != (d->bc[k][1] == MFX_BC_PERIODIC)) {
+            why = "periodic boundaries must be paired (bc[" + std::to_string(k) + "])";
+            return false;
+        }
+    }
+    if (N > (1LL << 31)) {
+        why = "grid too large for one context (more than 2^31 cells)";
+        return false;
+    }
+    for (int f = 0; f < 2; ++f) {
+        if (!(d->gamma[f] > 1.0) || !std::isfinite(d->gamma[f])) {
+            why = "gamma must be finite and > 1";
+            return false;
+        }
+        if (!(d->pi_inf[f] >= 0.0) || !std::isfinite(d->pi_inf[f])) {
+            why = "pi_inf must be finite and >= 0";
+            return false;
+        }
+    }
+    if (!(d->cfl > 0.0 && d->cfl <= 1.0)) {
+        why = "cfl must lie in (0, 1]";
+        return false;
+    }
+    if (!(d->weno_eps > 0.0) || !std::isfinite(d->weno_eps)) {
+        why = "weno_eps must be finite and > 0";
+        return false;
+    }
+    if (d->precision != MFX_FP64 && d->precision != MFX_FP32_MIXED) {
+        why = "unknown precision";
+        return false;
+    }
+    if (d->weights != MFX_WENO5_JS && d->weights != MFX_WENO5_LEARNED) {
+        why = "unknown weights mode";
+        return false;
+    }
+    return true;
+}
+
+// ---------------------------------------------------------------- kernels
+
+__global__ void __launch_bounds__(UTIL_BLOCK) prim_to_cons_kernel(Grid g, const double* __restrict__ w,
+                                                                  double* __restrict__ q)
+{
+    const long long N = g.N;
+    for (long long c = blockIdx.x * (long long)UTIL_BLOCK + threadIdx.x; c < N;
+         c += (long long)gridDim.x * UTIL_BLOCK) {
+        const double a1 = w[6 * N + c];
+        const double rho = w[0 * N + c] + w[1 * N + c];
+        const double u = w[2 * N + c], v = w[3 * N + c], ww = w[4 * N + c];
+        const double ke = 0.5 * rho * (u * u + v * v + ww * ww);
+        const double G = a1 * g.G1 + (1.0 - a1) * g.G2;
+        const double P = a1 * g.P1 + (1.0 - a1) * g.P2;
+        q[0 * N + c] = w[0 * N + c];
+        q[1 * N + c] = w[1 * N + c];
+        q[2 * N + c] = rho * u;
+        q[3 * N + c] = rho * v;
+        q[4 * N + c] = rho * ww;
+        q[5 * N + c] = G * w[5 * N + c] + P + ke;
+        q[6 * N + c] = a1;
+    }
+}
+
+// CFL partial maxima over the state q, with the validity checks.
+__global__ void __launch_bounds__(UTIL_BLOCK) cfl_partial_kernel(Grid g, const double* __restrict__ q,
+                                                                 double* __restrict__ partial,
+                                                                 unsigned* __restrict__ status)
+{
+    const long long N = g.N;
+    double smax = 0.0;
+    unsigned bad = 0;
+    for (long long c = blockIdx.x * (long long)UTIL_BLOCK + threadIdx.x; c < N;
+         c += (long long)gridDim.x * UTIL_BLOCK) {
+        double qc[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qc[v] = q[v * N + c];
+        smax = fmax(smax, cfl_speed(g, qc, bad));
+    }
+    if (bad) atomicOr(status, bad);
+    block_max_to<UTIL_BLOCK>(smax, partial + blockIdx.x);
+}
+
+// Scalars kept on the device: [0] dt of the current state, [1] time,
+// [2] step count (as double), [3] spare.
+__global__ void __launch_bounds__(UTIL_BLOCK) cfl_finalize_kernel(const double* __restrict__ partial, long long np,
+                                                                  double cfl, double* scal, int advance,
+                                                                  double dt_arg)
+{
+    double m = 0.0;
+    for (long long i = threadIdx.x; i < np; i += UTIL_BLOCK) m = fmax(m, partial[i]);
+    __shared__ double red[UTIL_BLOCK / 64];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double mm = red[0];
+        for (int i = 1; i < UTIL_BLOCK / 64; ++i) mm = fmax(mm, red[i]);
+        if (advance) {
+            const double used = dt_arg > 0.0 ? dt_arg : scal[0];
+            scal[1] = scal[1] + used;
+            scal[2] = scal[2] + 1.0;
+        }
+        scal[0] = cfl / mm;
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- context
+
+struct mfx_ctx {
+    mfx_grid_desc desc;
+    Grid g;
+    hipStream_t stream;
+    int device;
+    char* ws;
+    size_t ws_bytes;
+    Layout L;
+    double *q, *q1, *q2, *r, *scal, *partial;
+    unsigned* status;
+    int dirs[3];
+    int ndirs;
+    int seg_override;
+    int min_waves;  // 1: no register spills; 2: two waves per SIMD (MFX_SWEEP_MINW)
+    bool has_state;
+    std::string err;
+    // kernel timing (mfx_profile): events around each sweep launch
+    bool profiling;
+    struct Pending {
+        int kind;
+        hipEvent_t a, b;
+    };
+    std::vector<Pending> pending;
+    std::vector<hipEvent_t> pool;
+    double prof_ms[MFX_PROF_KINDS];
+    int64_t prof_n[MFX_PROF_KINDS];
+};
+
+namespace {
+
+int fail(mfx_ctx* c, int code, const std::string& msg)
+{
+    if (c)
+        c->err = msg;
+    else
+        g_init_error = msg;
+    return code;
+}
+
+#define HIP_TRY(ctx, call)                                                                       \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return fail((ctx), MFX_EHIP, std::string(#call ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+int launch_check(mfx_ctx* c, const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, MFX_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+    return MFX_OK;
+}
+
+int set_device(mfx_ctx* c)
+{
+    int cur = -1;
+    HIP_TRY(c, hipGetDevice(&cur));
+    if (cur != c->device) HIP_TRY(c, hipSetDevice(c->device));
+    return MFX_OK;
+}
+
+// Launch the sweep for direction d.
+hipEvent_t take_event(mfx_ctx* c)
+{
+    if (!c->pool.empty()) {
+        hipEvent_t e = c->pool.back();
+        c->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* out, int first, int mode,
+                 const double* dt_dev, double dt_arg)
+{
+    SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override);
+    if ((long long)sg.grid.x * sg.grid.y * sg.grid.z > c->L.n_partial)
+        return fail(c, MFX_EINVAL, "internal: partial buffer smaller than sweep grid");
+    mfx_ctx::Pending pend{(d * 2 + (first ? 1 : 0)) * 5 + mode, nullptr, nullptr};
+    if (c->profiling) {
+        pend.a = take_event(c);
+        pend.b = take_event(c);
+        if (!pend.a || !pend.b) return fail(c, MFX_EHIP, "hipEventCreate failed");
+        HIP_TRY(c, hipEventRecord(pend.a, c->stream));
+    }
+    const bool two = c->min_waves == 2;
+    switch (d) {
+    case 0:
+        if (two)
+            sweep_x_fp64<2><<<sg.grid, XROWS, 0, c->stream>>>(c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev,
+                                                              dt_arg, c->partial, c->status);
+        else
+            sweep_x_fp64<1><<<sg.grid, XROWS, 0, c->stream>>>(c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev,
+                                                              dt_arg, c->partial, c->status);
+        break;
+    case 1:
+        if (two)
+            sweep_yz_fp64<1, SWEEP_BLOCK, 2><<<sg.grid, SWEEP_BLOCK, 0, c->stream>>>(
+                c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev, dt_arg, c->partial, c->status);
+        else
+            sweep_yz_fp64<1, SWEEP_BLOCK, 1><<<sg.grid, SWEEP_BLOCK, 0, c->stream>>>(
+                c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev, dt_arg, c->partial, c->status);
+        break;
+    default:
+        if (two)
+            sweep_yz_fp64<2, SWEEP_BLOCK, 2><<<sg.grid, SWEEP_BLOCK, 0, c->stream>>>(
+                c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev, dt_arg, c->partial, c->status);
+        else
+            sweep_yz_fp64<2, SWEEP_BLOCK, 1><<<sg.grid, SWEEP_BLOCK, 0, c->stream>>>(
+                c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev, dt_arg, c->partial, c->status);
+        break;
+    }
+    int rc = launch_check(c, "sweep kernel");
+    if (rc) return rc;
+    if (c->profiling) {
+        HIP_TRY(c, hipEventRecord(pend.b, c->stream));
+        c->pending.push_back(pend);
+    }
+    return MFX_OK;
+}
+
+// All direction passes of one right-hand-side evaluation; the last active
+// direction applies `last_mode` with output `out`.
+int run_passes(mfx_ctx* c, const double* qs, const double* qn, double* out, int last_mode, const double* dt_dev,
+               double dt_arg, long long* last_blocks)
+{
+    for (int i = 0; i < c->ndirs; ++i) {
+        const int d = c->dirs[i];
+        const bool last = (i == c->ndirs - 1);
+        int rc = launch_sweep(c, d, qs, qn, last ? out : nullptr, i == 0, last ? last_mode : OUT_ACCUM, dt_dev,
+                              dt_arg);
+        if (rc != MFX_OK) return rc;
+        if (last && last_blocks) {
+            SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override);
+            *last_blocks = (long long)sg.grid.x * sg.grid.y * sg.grid.z;
+        }
+    }
+    return MFX_OK;
+}
+
+int standalone_cfl(mfx_ctx* c)
+{
+    cfl_partial_kernel<<<CFL_BLOCKS, UTIL_BLOCK, 0, c->stream>>>(c->g, c->q, c->partial, c->status);
+    int rc = launch_check(c, "cfl_partial_kernel");
+    if (rc != MFX_OK) return rc;
+    cfl_finalize_kernel<<<1, UTIL_BLOCK, 0, c->stream>>>(c->partial, CFL_BLOCKS, c->g.cfl, c->scal, 0, 0.0);
+    return launch_check(c, "cfl_finalize_kernel");
+}
+
+int read_status(mfx_ctx* c, unsigned* st)
+{
+    HIP_TRY(c, hipMemcpyAsync(st, c->status, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    return MFX_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- C ABI
+
+extern "C" {
+
+size_t mfx_workspace_bytes(const mfx_grid_desc* desc)
+{
+    std::string why;
+    if (!validate(desc, why)) return 0;
+    return make_layout(desc, 0).total;
+}
+
+int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void* hip_stream, mfx_ctx** out)
+{
+    if (!out) return fail(nullptr, MFX_EINVAL, "out is NULL");
+    *out = nullptr;
+    std::string why;
+    if (!validate(desc, why)) return fail(nullptr, MFX_EINVAL, why);
+    if (desc->weights == MFX_WENO5_LEARNED || desc->precision == MFX_FP32_MIXED)
+        return fail(nullptr, MFX_EINVAL, "this build supports precision MFX_FP64 with MFX_WENO5_JS only");
+    if (!ws_dev) return fail(nullptr, MFX_EINVAL, "workspace pointer is NULL");
+    if (reinterpret_cast<uintptr_t>(ws_dev) % ALIGN != 0)
+        return fail(nullptr, MFX_EINVAL, "workspace must be 256-byte aligned");
+
+    int seg_override = 0;
+    if (const char* s = std::getenv("MFX_SWEEP_SEG")) seg_override = std::atoi(s);
+    Layout L = make_layout(desc, seg_override);
+    if (ws_bytes < L.total)
+        return fail(nullptr, MFX_ENOMEM, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
+                                             std::to_string(L.total));
+
+    mfx_ctx* c = new (std::nothrow) mfx_ctx();
+    if (!c) return fail(nullptr, MFX_ENOMEM, "host allocation of the context failed");
+    c->desc = *desc;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->seg_override = seg_override;
+    c->min_waves = 2;
+    if (const char* s = std::getenv("MFX_SWEEP_MINW")) c->min_waves = std::atoi(s) == 1 ? 1 : 2;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return fail(nullptr, MFX_EHIP, "hipGetDevice failed");
+    }
+    c->ws = static_cast<char*>(ws_dev);
+    c->ws_bytes = ws_bytes;
+    c->L = L;
+    c->q = reinterpret_cast<double*>(c->ws + L.q);
+    c->q1 = reinterpret_cast<double*>(c->ws + L.q1);
+    c->q2 = reinterpret_cast<double*>(c->ws + L.q2);
+    c->r = reinterpret_cast<double*>(c->ws + L.r);
+    c->scal = reinterpret_cast<double*>(c->ws + L.scal);
+    c->status = reinterpret_cast<unsigned*>(c->ws + L.scal + 4 * sizeof(double));
+    c->partial = reinterpret_cast<double*>(c->ws + L.partial);
+
+    Grid& g = c->g;
+    g.N = (long long)desc->n[0] * desc->n[1] * desc->n[2];
+    g.stride[0] = 1;
+    g.stride[1] = desc->n[0];
+    g.stride[2] = (long long)desc->n[0] * desc->n[1];
+    c->ndirs = 0;
+    for (int k = 0; k < 3; ++k) {
+        g.n[k] = desc->n[k];
+        g.dx[k] = desc->dx[k];
+        g.inv_dx[k] = 1.0 / desc->dx[k];
+        g.bc[k][0] = desc->bc[k][0];
+        g.bc[k][1] = desc->bc[k][1];
+        g.active[k] = desc->n[k] > 1;
+        if (g.active[k]) c->dirs[c->ndirs++] = k;
+    }
+    if (c->ndirs == 0) c->dirs[c->ndirs++] = 0;  // a single cell still sweeps x (all faces from ghosts)
+    g.G1 = 1.0 / (desc->gamma[0] - 1.0);
+    g.G2 = 1.0 / (desc->gamma[1] - 1.0);
+    g.P1 = desc->gamma[0] * desc->pi_inf[0] / (desc->gamma[0] - 1.0);
+    g.P2 = desc->gamma[1] * desc->pi_inf[1] / (desc->gamma[1] - 1.0);
+    g.eps = desc->weno_eps;
+    g.cfl = desc->cfl;
+
+    if (hipMemsetAsync(c->ws + L.scal, 0, 64, c->stream) != hipSuccess) {
+        delete c;
+        return fail(nullptr, MFX_EHIP, "hipMemsetAsync of the scalar block failed");
+    }
+    c->has_state = false;
+    c->profiling = false;
+    for (int k = 0; k < MFX_PROF_KINDS; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    *out = c;
+    return MFX_OK;
+}
+
+int mfx_set_state(mfx_ctx* c, const double* q_dev)
+{
+    if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
+    if (!q_dev) return fail(c, MFX_EINVAL, "q_dev is NULL");
+    int rc = set_device(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipMemcpyAsync(c->q, q_dev, sizeof(double) * 7 * (size_t)c->g.N, hipMemcpyDeviceToDevice,
+                              c->stream));
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->L.scal, 0, 64, c->stream));
+    c->has_state = true;
+    return standalone_cfl(c);
+}
+
+int mfx_set_primitive(mfx_ctx* c, const double* w_dev)
+{
+    if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
+    if (!w_dev) return fail(c, MFX_EINVAL, "w_dev is NULL");
+    int rc = set_device(c);
+    if (rc) return rc;
+    const long long blocks = std::min<long long>((c->g.N + UTIL_BLOCK - 1) / UTIL_BLOCK, 65536);
+    prim_to_cons_kernel<<<(unsigned)blocks, UTIL_BLOCK, 0, c->stream>>>(c->g, w_dev, c->q);
+    rc = launch_check(c, "prim_to_cons_kernel");
+    if (rc) return rc;
+    HIP_TRY(c, hipMemsetAsync(c->ws + c->L.scal, 0, 64, c->stream));
+    c->has_state = true;
+    return standalone_cfl(c);
+}
+
+int mfx_get_state(mfx_ctx* c, double* q_dev_out)
+{
+    if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
+    if (!q_dev_out) return fail(c, MFX_EINVAL, "q_dev_out is NULL");
+    if (!c->has_state) return fail(c, MFX_EINVAL, "no state set");
+    int rc = set_device(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipMemcpyAsync(q_dev_out, c->q, sizeof(double) * 7 * (size_t)c->g.N, hipMemcpyDeviceToDevice,
+                              c->stream));
+    unsigned st = 0;
+    rc = read_status(c, &st);
+    if (rc) return rc;
+    if (st) return fail(c, MFX_ESTATE, "non-physical state flagged (status " + std::to_string(st) + ")");
+    return MFX_OK;
+}
+
+int mfx_rhs(mfx_ctx* c, double* rhs_out)
+{
+    if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
+    if (!rhs_out) return fail(c, MFX_EINVAL, "rhs_dev_out is NULL");
+    if (!c->has_state) return fail(c, MFX_EINVAL, "no state set");
+    const char* o = reinterpret_cast<const char*>(rhs_out);
+    if (o < c->ws + c->ws_bytes && o + sizeof(double) * 7 * c->g.N > c->ws)
+        return fail(c, MFX_EINVAL, "rhs_dev_out overlaps the workspace");
+    int rc = set_device(c);
+    if (rc) return rc;
+    return run_passes(c, c->q, c->q, rhs_out, OUT_RHS, nullptr, 0.0, nullptr);
+}
+
+int mfx_rk3_step(mfx_ctx* c, double dt, double* dt_used_host)
+{
+    if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
+    if (!c->has_state) return fail(c, MFX_EINVAL, "no state set");
+    if (!std::isfinite(dt)) return fail(c, MFX_EINVAL, "dt is not finite");
+    if (!(dt > 0.0) && !(c->g.active[0] || c->g.active[1] || c->g.active[2]))
+        return fail(c, MFX_EINVAL, "no active direction: the CFL time step is undefined, pass dt > 0");
+    int rc = set_device(c);
+    if (rc) return rc;
+    const double* dt_dev = dt > 0.0 ? nullptr : c->scal;
+    const double dt_arg = dt > 0.0 ? dt : 0.0;
+    double dt_seen = 0.0;
+    if (dt_used_host && !(dt > 0.0)) {
+        HIP_TRY(c, hipMemcpyAsync(&dt_seen, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    long long nb = 0;
+    rc = run_passes(c, c->q, c->q, c->q1, OUT_STAGE1, dt_dev, dt_arg, nullptr);
+    if (rc) return rc;
+    rc = run_passes(c, c->q1, c->q, c->q2, OUT_STAGE2, dt_dev, dt_arg, nullptr);
+    if (rc) return rc;
+    rc = run_passes(c, c->q2, c->q, c->q, OUT_STAGE3, dt_dev, dt_arg, &nb);
+    if (rc) return rc;
+    cfl_finalize_kernel<<<1, UTIL_BLOCK, 0, c->stream>>>(c->partial, nb, c->g.cfl, c->scal, 1, dt_arg);
+    rc = launch_check(c, "cfl_finalize_kernel");
+    if (rc) return rc;
+    if (dt_used_host) {
+        unsigned st = 0;
+        rc = read_status(c, &st);
+        if (rc) return rc;
+        *dt_used_host = dt > 0.0 ? dt : dt_seen;
+        if (st) return fail(c, MFX_ESTATE, "non-physical state flagged (status " + std::to_string(st) + ")");
+    }
+    return MFX_OK;
+}
+
+int mfx_set_mlp(mfx_ctx* c, const float* params_dev, int32_t n_params)
+{
+    if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
+    (void)params_dev;
+    (void)n_params;
+    return fail(c, MFX_EINVAL, "learned weights are not available in this build");
+}
+
+int mfx_stats(mfx_ctx* c, double* t, int64_t* step, int64_t* fallback_faces, uint32_t* status)
+{
+    if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
+    int rc = set_device(c);
+    if (rc) return rc;
+    double sc[4];
+    unsigned st = 0;
+    HIP_TRY(c, hipMemcpyAsync(sc, c->scal, sizeof(sc), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&st, c->status, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (t) *t = sc[1];
+    if (step) *step = (int64_t)sc[2];
+    if (fallback_faces) *fallback_faces = 0;
+    if (status) *status = st;
+    if (st) return fail(c, MFX_ESTATE, "non-physical state flagged (status " + std::to_string(st) + ")");
+    return MFX_OK;
+}
+
+int mfx_profile(mfx_ctx* c, int enable)
+{
+    if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
+    int rc = set_device(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto& p : c->pending) {
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pending.clear();
+    for (int k = 0; k < MFX_PROF_KINDS; ++k) {
+        c->prof_ms[k] = 0.0;
+        c->prof_n[k] = 0;
+    }
+    c->profiling = enable != 0;
+    return MFX_OK;
+}
+
+int mfx_profile_read(mfx_ctx* c, double* ms, int64_t* counts)
+{
+    if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
+    int rc = set_device(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    for (auto& p : c->pending) {
+        float e = 0.f;
+        HIP_TRY(c, hipEventElapsedTime(&e, p.a, p.b));
+        c->prof_ms[p.kind] += e;
+        c->prof_n[p.kind] += 1;
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    c->pending.clear();
+    for (int k = 0; k < MFX_PROF_KINDS; ++k) {
+        if (ms) ms[k] = c->prof_ms[k];
+        if (counts) counts[k] = c->prof_n[k];
+    }
+    return MFX_OK;
+}
+
+void mfx_destroy(mfx_ctx* c)
+{
+    if (!c) return;
+    for (auto& p : c->pending) {
+        c->pool.push_back(p.a);
+        c->pool.push_back(p.b);
+    }
+    for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+    delete c;
+}
+
+const char* mfx_last_error(const mfx_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+}  // extern "C"

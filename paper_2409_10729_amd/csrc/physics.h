@@ -1,0 +1,181 @@
+// Device-side physics of the five-equation model: mixture stiffened-gas EOS,
+// WENO5 face reconstruction and the HLLC flux.  Templated on the arithmetic
+// type T (double for the FP64 path, float for the mixed-precision bulk).
+//
+// Paper: arXiv 2409.10729, Sec. II-A (model; EOS rho E = Gamma p + Pi with
+// mixture Gamma = 1/(gamma-1), Pi = gamma pi_inf/(gamma-1)) and Sec. II-B
+// (HLLC after Toro from WENO5 states after Shu).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace mfx {
+
+constexpr int NV = 7;  // alpha1 rho1, alpha2 rho2, rho u, rho v, rho w, rho E, alpha1
+
+// Per-fluid constants of the mixture rules, linear in alpha1:
+//   Gamma(a) = a G1 + (1 - a) G2,  Pi(a) = a P1 + (1 - a) P2
+// with G_i = 1/(gamma_i - 1) and P_i = gamma_i pi_i / (gamma_i - 1).
+template <typename T>
+struct Mix {
+    T G1, G2, P1, P2;
+    __device__ __forceinline__ T Gamma(T a) const { return a * G1 + (T(1) - a) * G2; }
+    __device__ __forceinline__ T Pi(T a) const { return a * P1 + (T(1) - a) * P2; }
+};
+
+// Conserved -> primitive for one cell, always in float64 and without
+// contraction, in the operation order of the plain definition
+//   u = (rho u)/rho, p = (rho E - rho |u|^2 / 2 - Pi) / Gamma.
+// In water at 1e5 Pa the subtraction cancels about four digits
+// (Pi ~ 7.8e8), so the pressure carries ~1e-7 Pa of rounding noise that
+// every later stage inherits; fixing the order makes that noise the same
+// as in any other implementation of the definition.
+__device__ __forceinline__ void cons_to_prim(const Mix<double>& mix, const double q[NV], double w[NV])
+{
+#pragma clang fp contract(off)
+    const double rho = q[0] + q[1];
+    const double u = q[2] / rho, v = q[3] / rho, ww = q[4] / rho;
+    const double ke = 0.5 * rho * (u * u + v * v + ww * ww);
+    const double a1 = q[6];
+    const double G = a1 * mix.G1 + (1.0 - a1) * mix.G2;
+    const double P = a1 * mix.P1 + (1.0 - a1) * mix.P2;
+    w[0] = q[0];
+    w[1] = q[1];
+    w[2] = u;
+    w[3] = v;
+    w[4] = ww;
+    w[5] = (q[5] - ke - P) / G;
+    w[6] = a1;
+}
+
+// WENO5 with Jiang-Shu weights for cell c from w_{c-2..c+2} = a..e: both
+// edge values from one set of smoothness indicators.  right is the value at
+// c+1/2 (linear weights 1/10, 6/10, 3/10 on the stencils {c-2..c},
+// {c-1..c+1}, {c..c+2}), left the value at c-1/2 (weights 3/10, 6/10, 1/10).
+//
+// The weights alpha_k = d_k / (eps + beta_k)^2 are scaled by the product of
+// the three (eps + beta)^2 so each edge needs one division:
+//   value = sum_k d_k t_k p_k / sum_k d_k t_k,  t_0 = s1 s2, t_1 = s0 s2, t_2 = s0 s1.
+// In float64 the products stay far from overflow for physical data
+// (beta <= 1e20 gives t <= 1e80).
+template <typename T>
+__device__ __forceinline__ void weno5_js(T a, T b, T c, T d, T e, T eps, T& left, T& right)
+{
+    const T k13 = T(13.0 / 12.0);
+    const T q0 = a - T(2) * b + c, h0 = a - T(4) * b + T(3) * c;
+    const T q1 = b - T(2) * c + d, h1 = b - d;
+    const T q2 = c - T(2) * d + e, h2 = T(3) * c - T(4) * d + e;
+    T s0 = eps + (k13 * q0 * q0 + T(0.25) * h0 * h0);
+    T s1 = eps + (k13 * q1 * q1 + T(0.25) * h1 * h1);
+    T s2 = eps + (k13 * q2 * q2 + T(0.25) * h2 * h2);
+    s0 *= s0;
+    s1 *= s1;
+    s2 *= s2;
+    const T t0 = s1 * s2, t1 = s0 * s2, t2 = s0 * s1;
+
+    // six times the candidate values
+    const T r0 = T(2) * a - T(7) * b + T(11) * c;
+    const T r1 = -b + T(5) * c + T(2) * d;
+    const T r2 = T(2) * c + T(5) * d - e;
+    const T l0 = -a + T(5) * b + T(2) * c;
+    const T l1 = T(2) * b + T(5) * c - d;
+    const T l2 = T(11) * c - T(7) * d + T(2) * e;
+
+    const T wr0 = T(0.1) * t0, wr1 = T(0.6) * t1, wr2 = T(0.3) * t2;
+    const T wl0 = T(0.3) * t0, wl1 = T(0.6) * t1, wl2 = T(0.1) * t2;
+    right = (wr0 * r0 + wr1 * r1 + wr2 * r2) / (T(6) * (wr0 + wr1 + wr2));
+    left = (wl0 * l0 + wl1 * l1 + wl2 * l2) / (T(6) * (wl0 + wl1 + wl2));
+}
+
+// Same weights in the overflow-free ratio form for float32, where the
+// product form overflows for pressure jumps of 1e9:
+//   alpha_k ~ d_k ((eps + beta_min) / (eps + beta_k))^2.
+__device__ __forceinline__ void weno5_js_ratio(float a, float b, float c, float d, float e, float eps,
+                                               float& left, float& right)
+{
+    const float k13 = 13.0f / 12.0f;
+    const float q0 = a - 2.f * b + c, h0 = a - 4.f * b + 3.f * c;
+    const float q1 = b - 2.f * c + d, h1 = b - d;
+    const float q2 = c - 2.f * d + e, h2 = 3.f * c - 4.f * d + e;
+    const float s0 = eps + (k13 * q0 * q0 + 0.25f * h0 * h0);
+    const float s1 = eps + (k13 * q1 * q1 + 0.25f * h1 * h1);
+    const float s2 = eps + (k13 * q2 * q2 + 0.25f * h2 * h2);
+    const float smin = fminf(s0, fminf(s1, s2));
+    float x0 = smin / s0, x1 = smin / s1, x2 = smin / s2;
+    x0 *= x0;
+    x1 *= x1;
+    x2 *= x2;
+    const float r0 = 2.f * a - 7.f * b + 11.f * c;
+    const float r1 = -b + 5.f * c + 2.f * d;
+    const float r2 = 2.f * c + 5.f * d - e;
+    const float l0 = -a + 5.f * b + 2.f * c;
+    const float l1 = 2.f * b + 5.f * c - d;
+    const float l2 = 11.f * c - 7.f * d + 2.f * e;
+    const float wr0 = 0.1f * x0, wr1 = 0.6f * x1, wr2 = 0.3f * x2;
+    const float wl0 = 0.3f * x0, wl1 = 0.6f * x1, wl2 = 0.1f * x2;
+    right = (wr0 * r0 + wr1 * r1 + wr2 * r2) / (6.f * (wr0 + wr1 + wr2));
+    left = (wl0 * l0 + wl1 * l1 + wl2 * l2) / (6.f * (wl0 + wl1 + wl2));
+}
+
+// HLLC flux across a face normal to direction DIR (Toro 2009, Sec. 10.4),
+// Davis wave-speed estimates, extended to the five-equation model: each
+// partial density and alpha1 are scaled by xi = (S_K - u_K)/(S_K - S*) in
+// the star state.  Also returns the face velocity u_f used for div(u) in
+// the alpha1 source; the side of the contact is chosen by S* >= 0 (ties go
+// left), and only that side's star state is formed.
+template <int DIR, typename T>
+__device__ __forceinline__ void hllc(const Mix<T>& mix, const T wl[NV], const T wr[NV], T F[NV], T& uf)
+{
+    const T rl = wl[0] + wl[1], rr = wr[0] + wr[1];
+    const T pl = wl[5], pr = wr[5];
+    const T unl = wl[2 + DIR], unr = wr[2 + DIR];
+    const T Gl = mix.Gamma(wl[6]), Gr = mix.Gamma(wr[6]);
+    const T Pl = mix.Pi(wl[6]), Pr = mix.Pi(wr[6]);
+    const T El = Gl * pl + Pl + T(0.5) * rl * (wl[2] * wl[2] + wl[3] * wl[3] + wl[4] * wl[4]);
+    const T Er = Gr * pr + Pr + T(0.5) * rr * (wr[2] * wr[2] + wr[3] * wr[3] + wr[4] * wr[4]);
+    const T cl = sqrt(((Gl + T(1)) * pl + Pl) / (Gl * rl));
+    const T cr = sqrt(((Gr + T(1)) * pr + Pr) / (Gr * rr));
+
+    const T SL = fmin(unl - cl, unr - cr);
+    const T SR = fmax(unl + cl, unr + cr);
+    const T ml = rl * (SL - unl), mr = rr * (SR - unr);
+    const T Ss = (pr - pl + ml * unl - mr * unr) / (ml - mr);
+
+    const bool left = Ss >= T(0);
+    T w[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = left ? wl[v] : wr[v];
+    const T rho = left ? rl : rr;
+    const T p = left ? pl : pr;
+    const T un = left ? unl : unr;
+    const T E = left ? El : Er;
+    const T S = left ? SL : SR;
+    const T s = left ? fmin(T(0), SL) : fmax(T(0), SR);
+
+    const T xi = (S - un) / (S - Ss);
+    const T Eratio = p / (S - un);
+
+    T U[NV], Us[NV];
+    U[0] = w[0];
+    U[1] = w[1];
+    U[2] = rho * w[2];
+    U[3] = rho * w[3];
+    U[4] = rho * w[4];
+    U[5] = E;
+    U[6] = w[6];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Us[v] = xi * U[v];
+    Us[2 + DIR] = xi * (rho * Ss);
+    Us[5] = xi * (E + (Ss - un) * (rho * Ss + Eratio));
+
+    T Fk[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fk[v] = U[v] * un;
+    Fk[2 + DIR] += p;
+    Fk[5] = (E + p) * un;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = Fk[v] + s * (Us[v] - U[v]);
+    uf = un + s * (xi - T(1));
+}
+
+}  // namespace mfx

@@ -1,0 +1,150 @@
+"""Helpers shared by the GPU parity tests: run the HIP path through the C ABI,
+run the oracle, and compare per field with the relative max norm
+    relLinf_k = max_i |x_i - y_i| / max_i |y_i|.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+
+TOL = 1e-12  # FP64 path against the FP64 oracle, per conserved field
+
+
+MOMENTUM = (2, 3, 4)
+
+
+def _shared_momentum(scale: np.ndarray) -> np.ndarray:
+    """The three momentum components share one scale, so the error norm does
+    not depend on how the axes are oriented (a problem with v = w = 0 has
+    max|rho v| = 0, which cannot serve as a scale)."""
+    scale = scale.copy()
+    scale[list(MOMENTUM)] = scale[list(MOMENTUM)].max()
+    return scale
+
+
+def rel_linf(x: np.ndarray, y: np.ndarray) -> np.ndarray:
+    """State error per field: max|x - y| / max|y|, momentum sharing one scale."""
+    x = x.reshape(7, -1)
+    y = y.reshape(7, -1)
+    den = _shared_momentum(np.abs(y).max(axis=1))
+    den = np.where(den > 0, den, 1.0)
+    return np.abs(x - y).max(axis=1) / den
+
+
+def flux_scale(q: np.ndarray, spec) -> np.ndarray:
+    """Size of the terms a right-hand side is a difference of: per field,
+    max over cells of sum over active d of |F_k,d(q)| / dx_d, with the
+    model's physical flux F (partial densities and alpha1 times u_d;
+    momentum rho u u_d + p delta; energy (rho E + p) u_d)."""
+    g = oracle.make_grid(spec)
+    w = oracle.cons_to_prim(g, q).reshape(7, -1)
+    qq = q.reshape(7, -1)
+    p = w[5]
+    tot = np.zeros_like(qq)
+    for d in range(3):
+        if spec["n"][d] <= 1:
+            continue
+        ud = w[2 + d]
+        F = np.abs(qq * ud)
+        F[2 + d] = np.abs(qq[2 + d] * ud + p)
+        F[5] = np.abs((qq[5] + p) * ud)
+        tot += F / spec["dx"][d]
+    return _shared_momentum(tot.max(axis=1))
+
+
+def rhs_rel_linf(x: np.ndarray, y: np.ndarray, q: np.ndarray, spec) -> np.ndarray:
+    """Right-hand-side error per field, scaled by the size of the flux terms it
+    is a difference of (flux_scale).  Where L_k vanishes in exact arithmetic
+    (uniform alpha1, or uniform pressure for the transverse momentum) both
+    sides hold rounding noise of those terms, so max|L_k| is no scale."""
+    x = x.reshape(7, -1)
+    y = y.reshape(7, -1)
+    den = np.maximum(np.abs(y).max(axis=1), flux_scale(q, spec))
+    den = np.where(den > 0, den, 1.0)  # no active direction: L == 0 exactly
+    return np.abs(x - y).max(axis=1) / den
+
+
+def gpu_solver(spec, q0=None, w0=None, **kw):
+    import torch
+
+    from paper_2409_10729_amd import Solver
+
+    s = Solver(spec, **kw)
+    if w0 is not None:
+        s.set_primitive(torch.from_numpy(np.ascontiguousarray(w0)).cuda())
+    else:
+        s.set_state(torch.from_numpy(np.ascontiguousarray(q0)).cuda())
+    return s
+
+
+def cross_cells(spec, cells: np.ndarray, reach: int = 3) -> np.ndarray:
+    """All cells within `reach` along one active axis of any cell in `cells`
+    (boundary index map applied), as sorted unique linear indices."""
+    n = spec["n"]
+    i = cells % n[0]
+    j = (cells // n[0]) % n[1]
+    k = cells // (n[0] * n[1])
+    out = [cells]
+    pos = [i, j, k]
+    for d in range(3):
+        if n[d] <= 1:
+            continue
+        for o in range(-reach, reach + 1):
+            if o == 0:
+                continue
+            p = pos[d] + o
+            lo, hi = spec["bc"][d]
+            if lo == 0:
+                p = np.mod(p, n[d])
+            else:
+                p = np.clip(p, 0, n[d] - 1)
+            q = list(pos)
+            q[d] = p
+            out.append((q[2] * n[1] + q[1]) * n[0] + q[0])
+    return np.unique(np.concatenate(out))
+
+
+def oracle_step_at(spec, q0: np.ndarray, cells: np.ndarray, dt: float) -> np.ndarray:
+    """One SSP-RK3 step of the oracle evaluated only at `cells` (returns [7, ncell]).
+    Each stage's state is formed on the cells the next stage's stencils reach."""
+    g = oracle.make_grid(spec)
+    Nc = q0[0].size
+    qf = q0.reshape(7, Nc)
+    S2 = cross_cells(spec, cells)
+    S1 = cross_cells(spec, S2)
+    L0 = oracle.rhs_at(g, q0, S1).T
+    q1s = oracle.rk3_combine(1, qf[:, S1], qf[:, S1], L0, dt)
+    Q1 = np.zeros_like(qf)
+    Q1[:, S1] = q1s
+    L1 = oracle.rhs_at(g, Q1.reshape(q0.shape), S2).T
+    q2s = oracle.rk3_combine(2, qf[:, S2], Q1[:, S2], L1, dt)
+    Q2 = np.zeros_like(qf)
+    Q2[:, S2] = q2s
+    del Q1
+    L2 = oracle.rhs_at(g, Q2.reshape(q0.shape), cells).T
+    return oracle.rk3_combine(3, qf[:, cells], Q2[:, cells], L2, dt)
+
+
+def sample_cells(spec, count: int, seed: int, q0: np.ndarray | None = None) -> np.ndarray:
+    """Random cells plus every corner/edge-adjacent boundary cell class and,
+    if a state is given, the cells with the largest alpha1 and pressure-like
+    gradients (interfaces and shocks)."""
+    rng = np.random.default_rng(seed)
+    n = spec["n"]
+    N = n[0] * n[1] * n[2]
+    cells = [rng.integers(0, N, size=count)]
+    for d in range(3):
+        for edge in (0, 1, 2, n[d] - 3, n[d] - 2, n[d] - 1):
+            if 0 <= edge < n[d]:
+                pos = [rng.integers(0, n[0], 16), rng.integers(0, n[1], 16), rng.integers(0, n[2], 16)]
+                pos[d] = np.full(16, edge)
+                cells.append((pos[2] * n[1] + pos[1]) * n[0] + pos[0])
+    if q0 is not None:
+        for v in (5, 6):
+            f = q0[v].reshape(n[2], n[1], n[0])
+            g = np.abs(np.diff(f, axis=2))
+            top = np.argsort(g.ravel())[-count // 4:]
+            kk, jj, ii = np.unravel_index(top, g.shape)
+            cells.append((kk * n[1] + jj) * n[0] + ii)
+    return np.unique(np.concatenate(cells)).astype(np.int64)

@@ -1,0 +1,104 @@
+"""Host-side checks of the C ABI (no GPU needed): the library builds/loads,
+exports every symbol include/mfx.h declares, sizes workspaces, and rejects
+bad descriptors before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2409_10729_amd import _native
+from paper_2409_10729_amd import workloads as wl
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mfx.h")).read()
+    return sorted(set(re.findall(r"\b(mfx_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_and_binding_agree():
+    assert _declared() == sorted(_native.EXPORTED)
+
+
+def test_library_exports_every_declared_symbol():
+    L = _native.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def _desc(**over):
+    spec = wl.spec((32, 16, 8), ((1, 1), (0, 0), (0, 0)))
+    d = _native.make_desc(spec)
+    for k, v in over.items():
+        setattr(d, k, v)
+    return d
+
+
+def test_workspace_bytes_scales_with_grid():
+    L = _native.lib()
+    d = _desc()
+    b = L.mfx_workspace_bytes(ctypes.byref(d))
+    N = 32 * 16 * 8
+    assert b >= 4 * 7 * 8 * N  # q, two stage buffers, RHS
+    d2 = _native.make_desc(wl.spec((64, 16, 8), ((1, 1), (0, 0), (0, 0))))
+    assert L.mfx_workspace_bytes(ctypes.byref(d2)) > b
+
+
+@pytest.mark.parametrize("field,value", [
+    ("cfl", 0.0), ("cfl", 1.5), ("weno_eps", 0.0), ("precision", 7), ("weights", 9),
+])
+def test_bad_scalars_rejected(field, value):
+    L = _native.lib()
+    d = _desc(**{field: value})
+    assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0
+    ctx = ctypes.c_void_p()
+    rc = L.mfx_init_grid(ctypes.byref(d), ctypes.c_void_p(256), 1 << 30, None, ctypes.byref(ctx))
+    assert rc == _native.MFX_EINVAL
+    assert ctx.value is None
+    assert L.mfx_last_error(None)
+
+
+def test_bad_arrays_rejected():
+    L = _native.lib()
+    for mutate in (lambda d: d.n.__setitem__(1, 0), lambda d: d.dx.__setitem__(0, -1.0),
+                   lambda d: d.bc[0].__setitem__(0, 5), lambda d: d.gamma.__setitem__(1, 1.0),
+                   lambda d: d.pi_inf.__setitem__(0, -1.0)):
+        d = _desc()
+        mutate(d)
+        assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0
+        ctx = ctypes.c_void_p()
+        assert L.mfx_init_grid(ctypes.byref(d), ctypes.c_void_p(256), 1 << 30, None,
+                               ctypes.byref(ctx)) == _native.MFX_EINVAL
+
+
+def test_unpaired_periodic_rejected():
+    L = _native.lib()
+    d = _desc()
+    d.bc[1][0] = 0
+    d.bc[1][1] = 1
+    ctx = ctypes.c_void_p()
+    assert L.mfx_init_grid(ctypes.byref(d), ctypes.c_void_p(256), 1 << 30, None,
+                           ctypes.byref(ctx)) == _native.MFX_EINVAL
+    assert b"paired" in L.mfx_last_error(None)
+
+
+def test_small_or_misaligned_workspace_rejected():
+    L = _native.lib()
+    d = _desc()
+    need = L.mfx_workspace_bytes(ctypes.byref(d))
+    ctx = ctypes.c_void_p()
+    assert L.mfx_init_grid(ctypes.byref(d), ctypes.c_void_p(4096), need - 1, None,
+                           ctypes.byref(ctx)) == _native.MFX_ENOMEM
+    assert L.mfx_init_grid(ctypes.byref(d), ctypes.c_void_p(4096 + 8), need, None,
+                           ctypes.byref(ctx)) == _native.MFX_EINVAL
+    assert L.mfx_init_grid(ctypes.byref(d), None, need, None, ctypes.byref(ctx)) == _native.MFX_EINVAL
+
+
+def test_null_context_calls_rejected():
+    L = _native.lib()
+    assert L.mfx_set_state(None, None) == _native.MFX_EINVAL
+    assert L.mfx_rhs(None, None) == _native.MFX_EINVAL
+    assert L.mfx_rk3_step(None, 0.0, None) == _native.MFX_EINVAL
+    assert L.mfx_stats(None, None, None, None, None) == _native.MFX_EINVAL

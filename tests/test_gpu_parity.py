@@ -1,0 +1,185 @@
+"""FP64 HIP path against the FP64 oracle, through the C ABI.
+
+Bar: per conserved field, relative L-infinity (max |x - y| / max |y|) at
+most 1e-12; right-hand sides are scaled by the size of the flux terms they
+are differences of (see parity_util.rhs_rel_linf).  Small grids are compared element by element over whole runs
+(sizes spanning several sweep segments and 256-lane blocks, with ragged
+tails); the full 256^3 workload is compared on sampled cells the oracle
+computes one by one.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_10729_amd import workloads as wl
+from parity_util import TOL, gpu_solver, oracle_step_at, rel_linf, rhs_rel_linf, sample_cells
+
+pytestmark = pytest.mark.gpu
+
+
+def _q0(P):
+    g = oracle.make_grid(P["spec"])
+    return g, oracle.prim_to_cons(g, P["w"])
+
+
+def _report(name, err):
+    print(f"{name}: relLinf per field = " + " ".join(f"{e:.2e}" for e in err), flush=True)
+
+
+def test_set_primitive_matches_oracle_conversion():
+    P = wl.random_smooth(n=(24, 20, 16), seed=0)
+    g, q0 = _q0(P)
+    s = gpu_solver(P["spec"], w0=P["w"])
+    q = s.get_state().cpu().numpy()
+    err = rel_linf(q, q0)
+    _report("prim->cons", err)
+    assert np.all(err <= 1e-15)
+
+
+@pytest.mark.parametrize("n,bc,seed", [
+    ((37, 29, 23), ((1, 1), (0, 0), (1, 1)), 0),
+    ((300, 5, 4), ((0, 0), (1, 1), (0, 0)), 1),
+    ((7, 260, 9), ((1, 1), (1, 1), (0, 0)), 2),
+    ((6, 5, 70), ((0, 0), (0, 0), (1, 1)), 3),
+    ((64, 48, 1), ((1, 1), (0, 0), (0, 0)), 4),
+    ((1, 40, 33), ((0, 0), (1, 1), (0, 0)), 5),
+    ((257, 1, 1), ((1, 1), (0, 0), (0, 0)), 6),
+    ((2, 3, 2), ((0, 0), (0, 0), (1, 1)), 7),
+    ((1, 1, 1), ((0, 0), (0, 0), (0, 0)), 8),
+])
+def test_rhs_matches_oracle(n, bc, seed):
+    P = wl.random_smooth(n=n, seed=seed, bc=bc)
+    g, q0 = _q0(P)
+    s = gpu_solver(P["spec"], q0=q0)
+    r = s.rhs().cpu().numpy()
+    r_ref = oracle.rhs(g, q0)
+    err = rhs_rel_linf(r, r_ref, q0, P["spec"])
+    _report(f"rhs {n}", err)
+    assert np.all(err <= TOL), err
+
+
+def test_cfl_dt_matches_oracle():
+    P = wl.shock_droplet(n=(40, 32, 24), seed=2)
+    g, q0 = _q0(P)
+    s = gpu_solver(P["spec"], q0=q0)
+    dt = s.rk3_step(sync=True)
+    dt_ref = oracle.cfl_dt(g, q0)
+    print(f"dt gpu {dt!r} oracle {dt_ref!r}", flush=True)
+    assert dt == pytest.approx(dt_ref, rel=1e-15)
+
+
+def test_shock_tube_300_steps():
+    P = wl.shock_tube()
+    g, q0 = _q0(P)
+    s = gpu_solver(P["spec"], q0=q0)
+    dts = [s.rk3_step(sync=True) for _ in range(300)]
+    q = s.get_state().cpu().numpy()
+    q_ref, dts_ref = oracle.run(g, q0, 300)
+    err = rel_linf(q, q_ref)
+    _report("shock tube 300 steps", err)
+    assert np.all(err <= TOL), err
+    assert np.abs(np.array(dts) / dts_ref - 1).max() <= 1e-12
+    st = s.stats()
+    assert st["step"] == 300 and st["status"] == 0
+    assert st["t"] == pytest.approx(dts_ref.sum(), rel=1e-12)
+
+
+@pytest.mark.parametrize("maker,n,steps", [
+    (wl.advected_bubble, 40, 10),
+    (wl.shock_droplet, (48, 40, 36), 6),
+    (wl.bubble_cloud, (56, 32, 32), 4),
+])
+def test_3d_runs_match_oracle(maker, n, steps):
+    P = maker(n=n, seed=1)
+    g, q0 = _q0(P)
+    s = gpu_solver(P["spec"], q0=q0)
+    for _ in range(steps):
+        s.rk3_step()
+    q = s.get_state().cpu().numpy()
+    q_ref, _ = oracle.run(g, q0, steps)
+    err = rel_linf(q, q_ref)
+    _report(f"{P['name']} {n} x{steps}", err)
+    assert np.all(err <= TOL), err
+
+
+def test_explicit_dt_replay():
+    P = wl.shock_droplet(n=(32, 24, 20), seed=3)
+    g, q0 = _q0(P)
+    s = gpu_solver(P["spec"], q0=q0)
+    dts = np.array([2e-7, 1.5e-7, 3e-7])
+    for dt in dts:
+        assert s.rk3_step(dt, sync=True) == dt
+    q_ref, _ = oracle.run(g, q0, 3, dts=dts)
+    err = rel_linf(s.get_state().cpu().numpy(), q_ref)
+    assert np.all(err <= TOL), err
+
+
+def test_full_size_rhs_sampled():
+    """256^3 shock-droplet workload: the GPU right-hand side on sampled cells
+    (random, boundary layers, strongest interface and pressure gradients)."""
+    P = wl.shock_droplet(n=256, seed=0)
+    g, q0 = _q0(P)
+    s = gpu_solver(P["spec"], q0=q0)
+    r = s.rhs().cpu().numpy().reshape(7, -1)
+    cells = sample_cells(P["spec"], 4000, seed=0, q0=q0)
+    ref = oracle.rhs_at(g, q0, cells).T
+    err = rhs_rel_linf(r[:, cells], ref, q0, P["spec"])
+    _report(f"rhs 256^3 on {cells.size} cells", err)
+    assert np.all(err <= TOL), err
+
+
+def test_full_size_step_sampled():
+    """One CFL SSP-RK3 step of the 256^3 workload, in the launch configuration
+    the benchmark times; the oracle forms each stage only where the next
+    stage's stencils reach the sampled cells."""
+    P = wl.shock_droplet(n=256, seed=0)
+    g, q0 = _q0(P)
+    s = gpu_solver(P["spec"], q0=q0)
+    dt = s.rk3_step(sync=True)
+    assert dt == pytest.approx(oracle.cfl_dt(g, q0), rel=1e-15)
+    q = s.get_state().cpu().numpy().reshape(7, -1)
+    cells = sample_cells(P["spec"], 300, seed=1, q0=q0)
+    ref = oracle_step_at(P["spec"], q0, cells, dt)
+    err = rel_linf(q[:, cells], ref)
+    _report(f"step 256^3 on {cells.size} cells", err)
+    assert np.all(err <= TOL), err
+
+
+def test_segment_length_does_not_change_results(monkeypatch):
+    P = wl.shock_droplet(n=(40, 36, 44), seed=4)
+    g, q0 = _q0(P)
+    outs = []
+    for seg in ("16", "32", "64", "4096"):
+        monkeypatch.setenv("MFX_SWEEP_SEG", seg)
+        s = gpu_solver(P["spec"], q0=q0)
+        s.rk3_step()
+        s.rk3_step()
+        outs.append(s.get_state().cpu().numpy())
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_occupancy_variant_does_not_change_results(monkeypatch):
+    P = wl.shock_droplet(n=(72, 40, 36), seed=6)
+    g, q0 = _q0(P)
+    outs = []
+    for minw in ("1", "2"):
+        monkeypatch.setenv("MFX_SWEEP_MINW", minw)
+        s = gpu_solver(P["spec"], q0=q0)
+        s.rk3_step()
+        outs.append(s.get_state().cpu().numpy())
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_repeat_runs_bitwise_equal():
+    P = wl.advected_bubble(n=48, seed=5)
+    g, q0 = _q0(P)
+    res = []
+    for _ in range(2):
+        s = gpu_solver(P["spec"], q0=q0)
+        for _ in range(5):
+            s.rk3_step()
+        res.append(s.get_state().cpu().numpy())
+    assert np.array_equal(res[0], res[1])
