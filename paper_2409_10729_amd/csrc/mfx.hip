@@ -241,7 +241,6 @@ struct mfx_ctx {
     int dirs[3];
     int ndirs;
     int seg_override;
-    int min_waves;  // 1: no register spills; 2: two waves per SIMD (MFX_SWEEP_MINW)
     bool has_state;
     std::string err;
     // kernel timing (mfx_profile): events around each sweep launch
@@ -301,6 +300,46 @@ hipEvent_t take_event(mfx_ctx* c)
     return e;
 }
 
+template <int DIR, bool FIRST, int MODE>
+void launch_one(const SweepGeom& sg, hipStream_t st, const Grid& g, const double* qs, const double* qn, double* r,
+                double* out, const double* dt_dev, double dt_arg, double* partial, unsigned* status)
+{
+    if constexpr (DIR == 0)
+        sweep_x_fp64<FIRST, MODE><<<sg.grid, XROWS, 0, st>>>(g, qs, qn, r, out, sg.seg, dt_dev, dt_arg, partial,
+                                                            status);
+    else
+        sweep_yz_fp64<DIR, FIRST, MODE><<<sg.grid, SWEEP_BLOCK, 0, st>>>(g, qs, qn, r, out, sg.seg, dt_dev, dt_arg,
+                                                                        partial, status);
+}
+
+template <int DIR, bool FIRST>
+void launch_mode(int mode, const SweepGeom& sg, hipStream_t st, const Grid& g, const double* qs, const double* qn,
+                 double* r, double* out, const double* dt_dev, double dt_arg, double* partial, unsigned* status)
+{
+    switch (mode) {
+    case OUT_ACCUM: launch_one<DIR, FIRST, OUT_ACCUM>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status); break;
+    case OUT_RHS: launch_one<DIR, FIRST, OUT_RHS>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status); break;
+    case OUT_STAGE1: launch_one<DIR, FIRST, OUT_STAGE1>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status); break;
+    case OUT_STAGE2: launch_one<DIR, FIRST, OUT_STAGE2>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status); break;
+    default: launch_one<DIR, FIRST, OUT_STAGE3>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status); break;
+    }
+}
+
+// The x sweep, when active, is always the first direction of a pass.
+void launch_dispatch(int d, bool first, int mode, const SweepGeom& sg, hipStream_t st, const Grid& g,
+                     const double* qs, const double* qn, double* r, double* out, const double* dt_dev, double dt_arg,
+                     double* partial, unsigned* status)
+{
+    if (d == 0)
+        launch_mode<0, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status);
+    else if (d == 1)
+        first ? launch_mode<1, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status)
+              : launch_mode<1, false>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status);
+    else
+        first ? launch_mode<2, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status)
+              : launch_mode<2, false>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status);
+}
+
 int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* out, int first, int mode,
                  const double* dt_dev, double dt_arg)
 {
@@ -314,33 +353,8 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
         if (!pend.a || !pend.b) return fail(c, MFX_EHIP, "hipEventCreate failed");
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
-    const bool two = c->min_waves == 2;
-    switch (d) {
-    case 0:
-        if (two)
-            sweep_x_fp64<2><<<sg.grid, XROWS, 0, c->stream>>>(c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev,
-                                                              dt_arg, c->partial, c->status);
-        else
-            sweep_x_fp64<1><<<sg.grid, XROWS, 0, c->stream>>>(c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev,
-                                                              dt_arg, c->partial, c->status);
-        break;
-    case 1:
-        if (two)
-            sweep_yz_fp64<1, SWEEP_BLOCK, 2><<<sg.grid, SWEEP_BLOCK, 0, c->stream>>>(
-                c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev, dt_arg, c->partial, c->status);
-        else
-            sweep_yz_fp64<1, SWEEP_BLOCK, 1><<<sg.grid, SWEEP_BLOCK, 0, c->stream>>>(
-                c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev, dt_arg, c->partial, c->status);
-        break;
-    default:
-        if (two)
-            sweep_yz_fp64<2, SWEEP_BLOCK, 2><<<sg.grid, SWEEP_BLOCK, 0, c->stream>>>(
-                c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev, dt_arg, c->partial, c->status);
-        else
-            sweep_yz_fp64<2, SWEEP_BLOCK, 1><<<sg.grid, SWEEP_BLOCK, 0, c->stream>>>(
-                c->g, qs, qn, c->r, out, first, mode, sg.seg, dt_dev, dt_arg, c->partial, c->status);
-        break;
-    }
+    launch_dispatch(d, first != 0, mode, sg, c->stream, c->g, qs, qn, c->r, out, dt_dev, dt_arg, c->partial,
+                    c->status);
     int rc = launch_check(c, "sweep kernel");
     if (rc) return rc;
     if (c->profiling) {
@@ -422,8 +436,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     c->desc = *desc;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->seg_override = seg_override;
-    c->min_waves = 2;
-    if (const char* s = std::getenv("MFX_SWEEP_MINW")) c->min_waves = std::atoi(s) == 1 ? 1 : 2;
+
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return fail(nullptr, MFX_EHIP, "hipGetDevice failed");

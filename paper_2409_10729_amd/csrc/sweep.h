@@ -105,27 +105,73 @@ __device__ __forceinline__ double rk3_combine(int mode, double qn, double qs, do
     return (1.0 / 3.0) * qn + (2.0 / 3.0) * a;
 }
 
-// Everything a marching thread needs besides its cell source.
-struct MarchArgs {
+// What a pass does with a cell's contribution of this direction: fd[v] =
+// (F_{c-1/2} - F_{c+1/2}) / dx and the alpha1 source term src, added to the
+// running sum as (R + fd) + src for alpha1 and R + fd otherwise.  FIRST
+// (no running sum yet) and MODE (what is written) are compile-time so each
+// kernel carries only its own path.
+struct OutArgs {
     const double* qs;  // stage state (for the stage update)
     const double* qn;  // step's initial state (aliases out in stage 3)
     double* racc;      // partial RHS buffer
     double* out;       // caller RHS or new state
-    long long base;    // offset of the pencil's cell 0
-    long long sd;      // stride along the sweep
-    int c0, c1;        // segment [c0, c1)
-    int first, mode;
-    bool valid;        // this lane owns a real pencil (else compute, never store)
     double dt;
 };
 
-// The marching loop.  Src::load(pos, q) returns the conserved state of cell
-// `pos` along the sweep (boundary map applied); it is called for positions
-// c0-3, c0-2, ..., c1+2 in that order, the same sequence on every lane.
-template <int DIR, class Src>
-__device__ __forceinline__ double march(const Grid& g, Src& src, const MarchArgs& a, unsigned& bad)
+// Output of one cell at linear offset `cell`; returns the CFL speed of the
+// new state in stage 3 (else 0).
+template <bool FIRST, int MODE>
+__device__ __forceinline__ double emit_cell(const Grid& g, const OutArgs& o, long long cell, const double fd[NV],
+                                            double src, unsigned& bad)
 {
     const long long N = g.N;
+    double r[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r[v] = FIRST ? fd[v] : o.racc[v * N + cell] + fd[v];
+    r[6] += src;
+    if constexpr (MODE == OUT_ACCUM) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) o.racc[v * N + cell] = r[v];
+        return 0.0;
+    } else if constexpr (MODE == OUT_RHS) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) o.out[v * N + cell] = r[v];
+        return 0.0;
+    } else {
+        double qo[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const double qnv = MODE == OUT_STAGE1 ? 0.0 : o.qn[v * N + cell];
+            qo[v] = rk3_combine(MODE, qnv, o.qs[v * N + cell], o.dt, r[v]);
+        }
+#pragma unroll
+        for (int v = 0; v < NV; ++v) o.out[v * N + cell] = qo[v];
+        return MODE == OUT_STAGE3 ? cfl_speed(g, qo, bad) : 0.0;
+    }
+}
+
+// Sink of the y and z sweeps: each lane writes its own cell (lanes are
+// consecutive x, so every access is a contiguous row).
+template <bool FIRST, int MODE>
+struct GlobalSink {
+    OutArgs o;
+    long long base, sd;
+    bool valid;
+    double smax;
+    unsigned bad;
+    __device__ __forceinline__ void put(const Grid& g, int c, const double fd[NV], double src)
+    {
+        if (valid) smax = fmax(smax, emit_cell<FIRST, MODE>(g, o, base + (long long)c * sd, fd, src, bad));
+    }
+};
+
+// The marching loop over the segment [c0, c1).  Src::load(pos, q) returns
+// the conserved state of cell `pos` along the sweep (boundary map applied);
+// it is called for positions c0-3, c0-2, ..., c1+2 in that order, and
+// Sink::put for cells c0..c1-1 in order, the same sequence on every lane.
+template <int DIR, class Src, class Sink>
+__device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, int c0, int c1)
+{
     const double idx = g.inv_dx[DIR];
     const double eps = g.eps;
     const Mix<double> mix{g.G1, g.G2, g.P1, g.P2};
@@ -135,58 +181,32 @@ __device__ __forceinline__ double march(const Grid& g, Src& src, const MarchArgs
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         double qc[NV];
-        src.load(a.c0 - 3 + k, qc);
+        src.load(c0 - 3 + k, qc);
         cons_to_prim(mix, qc, W[k]);
     }
 
     double rprev[NV], Fprev[NV], ufprev = 0.0;
 #pragma unroll
     for (int v = 0; v < NV; ++v) rprev[v] = Fprev[v] = 0.0;
-    double smax = 0.0;
 
-    for (int c = a.c0 - 1; c <= a.c1; ++c) {
+    for (int c = c0 - 1; c <= c1; ++c) {
         // next cell entering the window (c+3), fetched early
         double qnext[NV];
-        if (c < a.c1) src.load(c + 3, qnext);
+        if (c < c1) src.load(c + 3, qnext);
 
         double lft[NV], rgt[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) weno5_js<double>(W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, lft[v], rgt[v]);
 
-        if (c >= a.c0) {
+        if (c >= c0) {
             double F[NV], uf;
             hllc<DIR, double>(mix, rprev, lft, F, uf);
-            if (c > a.c0) {
+            if (c > c0) {
                 // cell c-1: faces c-3/2 (Fprev) and c-1/2 (F)
-                const long long cell = a.base + (long long)(c - 1) * a.sd;
-                double r[NV];
-                if (a.first) {
+                double fd[NV];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) r[v] = (Fprev[v] - F[v]) * idx;
-                } else {
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) r[v] = a.racc[v * N + cell] + (Fprev[v] - F[v]) * idx;
-                }
-                r[6] += W[1][6] * ((uf - ufprev) * idx);
-                if (a.valid) {
-                    if (a.mode == OUT_ACCUM) {
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) a.racc[v * N + cell] = r[v];
-                    } else if (a.mode == OUT_RHS) {
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) a.out[v * N + cell] = r[v];
-                    } else {
-                        double qo[NV];
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) {
-                            const double qnv = a.mode == OUT_STAGE1 ? 0.0 : a.qn[v * N + cell];
-                            qo[v] = rk3_combine(a.mode, qnv, a.qs[v * N + cell], a.dt, r[v]);
-                        }
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) a.out[v * N + cell] = qo[v];
-                        if (a.mode == OUT_STAGE3) smax = fmax(smax, cfl_speed(g, qo, bad));
-                    }
-                }
+                for (int v = 0; v < NV; ++v) fd[v] = (Fprev[v] - F[v]) * idx;
+                sink.put(g, c - 1, fd, W[1][6] * ((uf - ufprev) * idx));
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fprev[v] = F[v];
@@ -195,7 +215,7 @@ __device__ __forceinline__ double march(const Grid& g, Src& src, const MarchArgs
 #pragma unroll
         for (int v = 0; v < NV; ++v) rprev[v] = rgt[v];
 
-        if (c < a.c1) {
+        if (c < c1) {
 #pragma unroll
             for (int k = 0; k < 4; ++k)
 #pragma unroll
@@ -203,7 +223,6 @@ __device__ __forceinline__ double march(const Grid& g, Src& src, const MarchArgs
             cons_to_prim(mix, qnext, W[4]);
         }
     }
-    return smax;
 }
 
 // Cell source for the y and z sweeps: straight from global memory; the
@@ -226,14 +245,13 @@ struct GlobalSrc {
 // qn and out alias in the third stage (the new state overwrites q in place;
 // each cell's q is read only by the thread that then writes it), so neither
 // is declared __restrict__.
-template <int DIR, int BLOCK, int MINW>
-__global__ void __launch_bounds__(BLOCK, MINW) sweep_yz_fp64(Grid g, const double* __restrict__ qs,
-                                                             const double* qn, double* __restrict__ racc,
-                                                             double* out, int first, int mode, int seg,
-                                                             const double* __restrict__ dt_dev, double dt_arg,
-                                                             double* __restrict__ partial,
-                                                             unsigned* __restrict__ status)
+template <int DIR, bool FIRST, int MODE>
+__global__ void __launch_bounds__(256, 2) sweep_yz_fp64(Grid g, const double* __restrict__ qs, const double* qn,
+                                                        double* __restrict__ racc, double* out, int seg,
+                                                        const double* __restrict__ dt_dev, double dt_arg,
+                                                        double* __restrict__ partial, unsigned* __restrict__ status)
 {
+    constexpr int BLOCK = 256;
     static_assert(DIR == 1 || DIR == 2, "y or z sweep");
     constexpr int SA = (DIR == 2) ? 1 : 2;  // slow transverse axis
     const int n = g.n[DIR];
@@ -242,36 +260,29 @@ __global__ void __launch_bounds__(BLOCK, MINW) sweep_yz_fp64(Grid g, const doubl
     const bool valid = i_raw < nx;
     const int i = valid ? i_raw : nx - 1;
 
-    MarchArgs a;
-    a.qs = qs;
-    a.qn = qn;
-    a.racc = racc;
-    a.out = out;
-    a.base = (long long)i + (long long)blockIdx.y * g.stride[SA];
-    a.sd = g.stride[DIR];
-    a.c0 = blockIdx.z * seg;
-    a.c1 = min(a.c0 + seg, n);
-    a.first = first;
-    a.mode = mode;
-    a.valid = valid;
-    a.dt = dt_dev ? *dt_dev : dt_arg;
+    const long long base = (long long)i + (long long)blockIdx.y * g.stride[SA];
+    const int c0 = blockIdx.z * seg;
+    const int c1 = min(c0 + seg, n);
+    GlobalSrc src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
+    GlobalSink<FIRST, MODE> sink{OutArgs{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid,
+                                 0.0, 0u};
+    march<DIR>(g, src, sink, c0, c1);
 
-    GlobalSrc src{qs, a.base, a.sd, g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
-    unsigned bad = 0;
-    const double smax = march<DIR>(g, src, a, bad);
-
-    if (mode == OUT_STAGE3) {
-        if (bad) atomicOr(status, bad);
+    if constexpr (MODE == OUT_STAGE3) {
+        if (sink.bad) atomicOr(status, sink.bad);
         const long long bid = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        block_max_to<BLOCK>(smax, partial + bid);
+        block_max_to<BLOCK>(sink.smax, partial + bid);
     }
 }
 
-// Cell source for the x sweep.  The 64 lanes of the (one-wave) block own 64
-// consecutive rows and march along x together; every XCHUNK positions the
-// block stages the next XCHUNK cells of all 64 rows through LDS with
-// row-contiguous reads (XCHUNK consecutive doubles per row and variable),
-// then each lane reads its own row from LDS.
+// x sweep.  The 64 lanes of the (one-wave) block own 64 consecutive rows
+// (row = k * ny + j, x-contiguous in memory) and march along x together.
+// Inputs: every XCHUNK positions the block stages the next XCHUNK cells of
+// all 64 rows through LDS with row-contiguous reads, then each lane reads
+// its own row.  Outputs: each lane parks its cell's contribution in LDS and
+// every XCHUNK cells the block writes them out row-contiguously (including
+// the partial-RHS read and the stage update), so no global access is
+// strided across lanes.
 constexpr int XROWS = 64;
 constexpr int XCHUNK = 4;
 
@@ -289,10 +300,9 @@ struct LdsSrc {
         const int slot = (pos - pstart) % XCHUNK;
         if (slot == 0) {
             __syncthreads();  // every lane has consumed the previous chunk
-            const int lane = threadIdx.x;
-#pragma unroll
+#pragma unroll 1
             for (int it = 0; it < XCHUNK; ++it) {
-                const int item = lane + it * XROWS;
+                const int item = threadIdx.x + it * XROWS;
                 const int r = item / XCHUNK, cx = item % XCHUNK;
                 const long long row = min(row0 + r, nrows - 1);
                 const long long off = row * nx + map_cell(pos + cx, nx, bclo, bchi);
@@ -306,46 +316,64 @@ struct LdsSrc {
     }
 };
 
-// Launch geometry of the x sweep: blockIdx.x = group of 64 rows (row =
-// k * ny + j, x-contiguous in memory), blockIdx.z = segment along x.
-template <int MINW>
-__global__ void __launch_bounds__(XROWS, MINW) sweep_x_fp64(Grid g, const double* __restrict__ qs,
-                                                            const double* qn, double* __restrict__ racc,
-                                                            double* out, int first, int mode, int seg,
-                                                            const double* __restrict__ dt_dev, double dt_arg,
-                                                            double* __restrict__ partial,
-                                                            unsigned* __restrict__ status)
+template <bool FIRST, int MODE>
+struct LdsSink {
+    double (*buf)[NV + 1][XROWS];  // [XCHUNK][fd 0..6, src][XROWS]
+    OutArgs o;
+    long long row0, nrows;
+    int nx, c0, c1;
+    double smax;
+    unsigned bad;
+
+    __device__ __forceinline__ void put(const Grid& g, int c, const double fd[NV], double src)
+    {
+        const int slot = (c - c0) % XCHUNK;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) buf[slot][v][threadIdx.x] = fd[v];
+        buf[slot][NV][threadIdx.x] = src;
+        if (slot == XCHUNK - 1 || c == c1 - 1) {
+            const int p0 = c - slot, cnt = slot + 1;
+            __syncthreads();
+#pragma unroll 1
+            for (int it = 0; it < XCHUNK; ++it) {
+                const int item = threadIdx.x + it * XROWS;
+                const int r = item / XCHUNK, cx = item % XCHUNK;
+                if (cx < cnt && row0 + r < nrows) {
+                    double f[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) f[v] = buf[cx][v][r];
+                    const long long cell = (row0 + r) * nx + p0 + cx;
+                    smax = fmax(smax, emit_cell<FIRST, MODE>(g, o, cell, f, buf[cx][NV][r], bad));
+                }
+            }
+            __syncthreads();  // the buffer is refilled next
+        }
+    }
+};
+
+template <bool FIRST, int MODE>
+__global__ void __launch_bounds__(XROWS, 2) sweep_x_fp64(Grid g, const double* __restrict__ qs, const double* qn,
+                                                         double* __restrict__ racc, double* out, int seg,
+                                                         const double* __restrict__ dt_dev, double dt_arg,
+                                                         double* __restrict__ partial, unsigned* __restrict__ status)
 {
-    __shared__ double buf[XCHUNK][NV][XROWS];
+    __shared__ double ibuf[XCHUNK][NV][XROWS];
+    __shared__ double obuf[XCHUNK][NV + 1][XROWS];
     const int nx = g.n[0];
     const long long nrows = (long long)g.n[1] * g.n[2];
     const long long row0 = (long long)blockIdx.x * XROWS;
-    const long long row_raw = row0 + threadIdx.x;
-    const bool valid = row_raw < nrows;
-    const long long row = valid ? row_raw : nrows - 1;
+    const int c0 = blockIdx.z * seg;
+    const int c1 = min(c0 + seg, nx);
 
-    MarchArgs a;
-    a.qs = qs;
-    a.qn = qn;
-    a.racc = racc;
-    a.out = out;
-    a.base = row * nx;
-    a.sd = 1;
-    a.c0 = blockIdx.z * seg;
-    a.c1 = min(a.c0 + seg, nx);
-    a.first = first;
-    a.mode = mode;
-    a.valid = valid;
-    a.dt = dt_dev ? *dt_dev : dt_arg;
+    LdsSrc src{ibuf, qs, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
+    LdsSink<FIRST, MODE> sink{obuf, OutArgs{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx, c0, c1,
+                              0.0, 0u};
+    march<0>(g, src, sink, c0, c1);
 
-    LdsSrc src{buf, qs, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], a.c0 - 3};
-    unsigned bad = 0;
-    const double smax = march<0>(g, src, a, bad);
-
-    if (mode == OUT_STAGE3) {
-        if (bad) atomicOr(status, bad);
+    if constexpr (MODE == OUT_STAGE3) {
+        if (sink.bad) atomicOr(status, sink.bad);
         const long long bid = (long long)blockIdx.z * gridDim.x + blockIdx.x;
-        block_max_to<XROWS>(smax, partial + bid);
+        block_max_to<XROWS>(sink.smax, partial + bid);
     }
 }
 

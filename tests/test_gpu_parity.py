@@ -161,18 +161,6 @@ def test_segment_length_does_not_change_results(monkeypatch):
         assert np.array_equal(o, outs[0])
 
 
-def test_occupancy_variant_does_not_change_results(monkeypatch):
-    P = wl.shock_droplet(n=(72, 40, 36), seed=6)
-    g, q0 = _q0(P)
-    outs = []
-    for minw in ("1", "2"):
-        monkeypatch.setenv("MFX_SWEEP_MINW", minw)
-        s = gpu_solver(P["spec"], q0=q0)
-        s.rk3_step()
-        outs.append(s.get_state().cpu().numpy())
-    assert np.array_equal(outs[0], outs[1])
-
-
 def test_repeat_runs_bitwise_equal():
     P = wl.advected_bubble(n=48, seed=5)
     g, q0 = _q0(P)
