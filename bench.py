@@ -112,6 +112,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain device-to-device copy of 7 * n^3 float64 (known bytes), five times, "
+                         "to scale rocprofv3 FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -127,6 +130,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        a = torch.ones(7 * args.n ** 3, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(5):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "launches": 5}), flush=True)
+        return
     print(f"[bench] generating shock_droplet n={args.n} seed={args.seed}", file=sys.stderr, flush=True)
     P = wl.shock_droplet(n=args.n, seed=args.seed)
     N = args.n ** 3
