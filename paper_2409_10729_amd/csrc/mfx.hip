@@ -16,6 +16,7 @@
 
 #include "../../include/mfx.h"
 #include "sweep.h"
+#include "xrow.h"
 
 using namespace mfx;
 
@@ -30,27 +31,67 @@ thread_local std::string g_init_error;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
+// Launch-shape overrides for tuning and tests (results do not depend on
+// them): MFX_SWEEP_SEG = segment length of the marching sweeps,
+// MFX_XSWEEP = "march" to force the marching x sweep.
+struct Overrides {
+    int seg;
+    int xmode;
+};
+
+Overrides read_overrides()
+{
+    Overrides o{0, 0};
+    if (const char* s = std::getenv("MFX_SWEEP_SEG")) o.seg = std::atoi(s);
+    if (const char* s = std::getenv("MFX_XSWEEP")) o.xmode = std::strcmp(s, "march") == 0 ? 1 : 0;
+    return o;
+}
+
 struct Layout {
-    size_t q, q1, q2, r, scal, partial, total;
+    size_t q, q1, q2, r, scal, partial, bface, total;
     long long n_partial;
 };
 
 // Geometry of one sweep launch for direction d.
 struct SweepGeom {
     dim3 grid;
-    int seg;
+    int block;
+    int seg;          // segment length (marching sweeps) or rows per block (x row sweep)
+    size_t lds;       // dynamic LDS bytes
+    bool xrows;       // x sweep by whole rows
 };
 
-SweepGeom sweep_geom(const int n[3], int d, int seg_override)
+// The x sweep takes whole rows when a row fits the row kernel (nx <=
+// XROW_MAX and its LDS fits a workgroup), else it marches along x.
+bool use_xrows(const int n[3], int mode_override)
+{
+    if (mode_override == 1) return false;
+    return n[0] <= XROW_MAX && xrow_lds_bytes(n[0]) <= 64 * 1024;
+}
+
+SweepGeom sweep_geom(const int n[3], int d, int seg_override, int xmode_override)
 {
     int seg = seg_override > 0 ? seg_override : 64;
     SweepGeom g;
-    if (d == 0) {
+    g.lds = 0;
+    g.xrows = false;
+    if (d == 0 && use_xrows(n, xmode_override)) {
+        const long long rows = (long long)n[1] * n[2];
+        // about 2048 blocks, at least one row each
+        const long long rpb = std::max<long long>(1, rows / 2048);
+        g.grid = dim3((unsigned)((rows + rpb - 1) / rpb), 1, 1);
+        g.block = 64 * ((n[0] + 63) / 64);
+        g.seg = (int)rpb;
+        g.lds = xrow_lds_bytes(n[0]);
+        g.xrows = true;
+    } else if (d == 0) {
         // blocks of XROWS rows (y,z flattened), segments along x
         const long long rows = (long long)n[1] * n[2];
         while (seg > 16 && rows * ((n[0] + seg - 1) / seg) < 256LL * 64 * 16) seg /= 2;
         seg = std::min(seg, n[0]);
         g.grid = dim3((unsigned)((rows + XROWS - 1) / XROWS), 1, (n[0] + seg - 1) / seg);
+        g.block = XROWS;
+        g.seg = seg;
     } else {
         const int sa = (d == 2) ? 1 : 2;
         const long long pencils = (long long)n[0] * n[sa];
@@ -58,26 +99,24 @@ SweepGeom sweep_geom(const int n[3], int d, int seg_override)
         while (seg > 16 && pencils * ((n[d] + seg - 1) / seg) < 256LL * 64 * 16) seg /= 2;
         seg = std::min(seg, n[d]);
         g.grid = dim3((n[0] + SWEEP_BLOCK - 1) / SWEEP_BLOCK, n[sa], (n[d] + seg - 1) / seg);
+        g.block = SWEEP_BLOCK;
+        g.seg = seg;
     }
-    g.seg = seg;
     return g;
 }
 
-Layout make_layout(const mfx_grid_desc* d, int seg_override)
+Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
 {
     Layout L{};
     const long long N = (long long)d->n[0] * d->n[1] * d->n[2];
     const size_t state = align_up(sizeof(double) * 7 * (size_t)N);
     long long np = CFL_BLOCKS;
     for (int k = 0; k < 3; ++k) {
-        if (d->n[k] <= 1) continue;
-        SweepGeom g = sweep_geom(d->n, k, seg_override);
+        if (d->n[k] <= 1 && !(k == 0 && d->n[1] == 1 && d->n[2] == 1)) continue;
+        SweepGeom g = sweep_geom(d->n, k, seg_override, xmode_override);
         np = std::max(np, (long long)g.grid.x * g.grid.y * g.grid.z);
     }
-    if (d->n[0] == 1 && d->n[1] == 1 && d->n[2] == 1) {
-        SweepGeom g = sweep_geom(d->n, 0, seg_override);
-        np = std::max(np, (long long)g.grid.x * g.grid.y * g.grid.z);
-    }
+    const long long nrows = (long long)d->n[1] * d->n[2];
     size_t off = 0;
     L.q = off;
     off += state;
@@ -91,6 +130,8 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override)
     off += align_up(64);
     L.partial = off;
     off += align_up(sizeof(double) * (size_t)np);
+    L.bface = off;
+    off += align_up(sizeof(double) * BFACE * 2 * (size_t)nrows);
     L.total = off;
     L.n_partial = np;
     return L;
@@ -236,11 +277,12 @@ struct mfx_ctx {
     char* ws;
     size_t ws_bytes;
     Layout L;
-    double *q, *q1, *q2, *r, *scal, *partial;
+    double *q, *q1, *q2, *r, *scal, *partial, *bface;
     unsigned* status;
     int dirs[3];
     int ndirs;
     int seg_override;
+    int xmode_override;  // MFX_XSWEEP: 0 automatic, 1 marching x sweep
     bool has_state;
     std::string err;
     // kernel timing (mfx_profile): events around each sweep launch
@@ -300,50 +342,61 @@ hipEvent_t take_event(mfx_ctx* c)
     return e;
 }
 
+// The x row sweep reads the boundary faces that boundary_faces_x leaves in
+// `bface` (launched just before it on the same stream).
 template <int DIR, bool FIRST, int MODE>
 void launch_one(const SweepGeom& sg, hipStream_t st, const Grid& g, const double* qs, const double* qn, double* r,
-                double* out, const double* dt_dev, double dt_arg, double* partial, unsigned* status)
+                double* out, const double* dt_dev, double dt_arg, double* partial, unsigned* status,
+                double* bface)
 {
-    if constexpr (DIR == 0)
-        sweep_x_fp64<FIRST, MODE><<<sg.grid, XROWS, 0, st>>>(g, qs, qn, r, out, sg.seg, dt_dev, dt_arg, partial,
-                                                            status);
-    else
+    if constexpr (DIR == 0) {
+        if (sg.xrows) {
+            const long long faces = 2LL * g.n[1] * g.n[2];
+            boundary_faces_x<<<(unsigned)((faces + 255) / 256), 256, 0, st>>>(g, qs, bface);
+            sweep_x_rows<FIRST, MODE><<<sg.grid, sg.block, sg.lds, st>>>(g, qs, qn, r, out, sg.seg, bface, dt_dev,
+                                                                        dt_arg, partial, status);
+        } else {
+            sweep_x_fp64<FIRST, MODE><<<sg.grid, XROWS, 0, st>>>(g, qs, qn, r, out, sg.seg, dt_dev, dt_arg, partial,
+                                                                status);
+        }
+    } else
         sweep_yz_fp64<DIR, FIRST, MODE><<<sg.grid, SWEEP_BLOCK, 0, st>>>(g, qs, qn, r, out, sg.seg, dt_dev, dt_arg,
                                                                         partial, status);
 }
 
 template <int DIR, bool FIRST>
 void launch_mode(int mode, const SweepGeom& sg, hipStream_t st, const Grid& g, const double* qs, const double* qn,
-                 double* r, double* out, const double* dt_dev, double dt_arg, double* partial, unsigned* status)
+                 double* r, double* out, const double* dt_dev, double dt_arg, double* partial, unsigned* status,
+                 double* bface)
 {
     switch (mode) {
-    case OUT_ACCUM: launch_one<DIR, FIRST, OUT_ACCUM>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status); break;
-    case OUT_RHS: launch_one<DIR, FIRST, OUT_RHS>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status); break;
-    case OUT_STAGE1: launch_one<DIR, FIRST, OUT_STAGE1>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status); break;
-    case OUT_STAGE2: launch_one<DIR, FIRST, OUT_STAGE2>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status); break;
-    default: launch_one<DIR, FIRST, OUT_STAGE3>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status); break;
+    case OUT_ACCUM: launch_one<DIR, FIRST, OUT_ACCUM>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface); break;
+    case OUT_RHS: launch_one<DIR, FIRST, OUT_RHS>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface); break;
+    case OUT_STAGE1: launch_one<DIR, FIRST, OUT_STAGE1>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface); break;
+    case OUT_STAGE2: launch_one<DIR, FIRST, OUT_STAGE2>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface); break;
+    default: launch_one<DIR, FIRST, OUT_STAGE3>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface); break;
     }
 }
 
 // The x sweep, when active, is always the first direction of a pass.
 void launch_dispatch(int d, bool first, int mode, const SweepGeom& sg, hipStream_t st, const Grid& g,
                      const double* qs, const double* qn, double* r, double* out, const double* dt_dev, double dt_arg,
-                     double* partial, unsigned* status)
+                     double* partial, unsigned* status, double* bface)
 {
     if (d == 0)
-        launch_mode<0, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status);
+        launch_mode<0, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface);
     else if (d == 1)
-        first ? launch_mode<1, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status)
-              : launch_mode<1, false>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status);
+        first ? launch_mode<1, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface)
+              : launch_mode<1, false>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface);
     else
-        first ? launch_mode<2, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status)
-              : launch_mode<2, false>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status);
+        first ? launch_mode<2, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface)
+              : launch_mode<2, false>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface);
 }
 
 int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* out, int first, int mode,
                  const double* dt_dev, double dt_arg)
 {
-    SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override);
+    SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override);
     if ((long long)sg.grid.x * sg.grid.y * sg.grid.z > c->L.n_partial)
         return fail(c, MFX_EINVAL, "internal: partial buffer smaller than sweep grid");
     mfx_ctx::Pending pend{(d * 2 + (first ? 1 : 0)) * 5 + mode, nullptr, nullptr};
@@ -354,7 +407,7 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
     launch_dispatch(d, first != 0, mode, sg, c->stream, c->g, qs, qn, c->r, out, dt_dev, dt_arg, c->partial,
-                    c->status);
+                    c->status, c->bface);
     int rc = launch_check(c, "sweep kernel");
     if (rc) return rc;
     if (c->profiling) {
@@ -376,7 +429,7 @@ int run_passes(mfx_ctx* c, const double* qs, const double* qn, double* out, int 
                               dt_arg);
         if (rc != MFX_OK) return rc;
         if (last && last_blocks) {
-            SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override);
+            SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override);
             *last_blocks = (long long)sg.grid.x * sg.grid.y * sg.grid.z;
         }
     }
@@ -409,7 +462,8 @@ size_t mfx_workspace_bytes(const mfx_grid_desc* desc)
 {
     std::string why;
     if (!validate(desc, why)) return 0;
-    return make_layout(desc, 0).total;
+    const Overrides o = read_overrides();
+    return make_layout(desc, o.seg, o.xmode).total;
 }
 
 int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void* hip_stream, mfx_ctx** out)
@@ -424,9 +478,8 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     if (reinterpret_cast<uintptr_t>(ws_dev) % ALIGN != 0)
         return fail(nullptr, MFX_EINVAL, "workspace must be 256-byte aligned");
 
-    int seg_override = 0;
-    if (const char* s = std::getenv("MFX_SWEEP_SEG")) seg_override = std::atoi(s);
-    Layout L = make_layout(desc, seg_override);
+    const Overrides ov = read_overrides();
+    Layout L = make_layout(desc, ov.seg, ov.xmode);
     if (ws_bytes < L.total)
         return fail(nullptr, MFX_ENOMEM, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
                                              std::to_string(L.total));
@@ -435,7 +488,8 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     if (!c) return fail(nullptr, MFX_ENOMEM, "host allocation of the context failed");
     c->desc = *desc;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
-    c->seg_override = seg_override;
+    c->seg_override = ov.seg;
+    c->xmode_override = ov.xmode;
 
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -451,6 +505,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     c->scal = reinterpret_cast<double*>(c->ws + L.scal);
     c->status = reinterpret_cast<unsigned*>(c->ws + L.scal + 4 * sizeof(double));
     c->partial = reinterpret_cast<double*>(c->ws + L.partial);
+    c->bface = reinterpret_cast<double*>(c->ws + L.bface);
 
     Grid& g = c->g;
     g.N = (long long)desc->n[0] * desc->n[1] * desc->n[2];

@@ -92,6 +92,22 @@ __device__ __forceinline__ void block_max_to(double v, double* slot)
     }
 }
 
+// Block-wide maximum for any block of whole waves (up to 16).
+__device__ __forceinline__ void block_max_dyn(double v, double* slot)
+{
+    __shared__ double red[16];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = red[0];
+        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, red[i]);
+        *slot = m;
+    }
+}
+
 // SSP-RK3 stage combination of one cell, in the operation order of the
 // plain definition and without contraction: rho E feeds the pressure
 // inversion, which turns one unit in the last place of rho E into ~1e-7 Pa

@@ -161,6 +161,29 @@ def test_segment_length_does_not_change_results(monkeypatch):
         assert np.array_equal(o, outs[0])
 
 
+@pytest.mark.parametrize("n,bc", [((72, 40, 36), ((1, 1), (0, 0), (0, 0))),
+                                  ((130, 6, 5), ((0, 0), (1, 1), (0, 0))),
+                                  ((3, 40, 4), ((1, 1), (0, 0), (1, 1)))])
+def test_x_sweep_variants_agree(monkeypatch, n, bc):
+    """The whole-row x sweep and the marching x sweep compute the same faces
+    with the same formulas (the compiler may fuse multiply-adds differently
+    in the two kernels, so agreement is to rounding, not bitwise)."""
+    P = wl.random_smooth(n=n, seed=8, bc=bc)
+    g, q0 = _q0(P)
+    outs = []
+    for mode in ("rows", "march"):
+        monkeypatch.setenv("MFX_XSWEEP", mode)
+        s = gpu_solver(P["spec"], q0=q0)
+        r = s.rhs().cpu().numpy()
+        s.rk3_step()
+        outs.append((r, s.get_state().cpu().numpy()))
+    e_rhs = rhs_rel_linf(outs[0][0], outs[1][0], q0, P["spec"])
+    e_q = rel_linf(outs[0][1], outs[1][1])
+    _report(f"x-sweep variants rhs {n}", e_rhs)
+    _report(f"x-sweep variants step {n}", e_q)
+    assert np.all(e_rhs <= 1e-13) and np.all(e_q <= 1e-13)
+
+
 def test_repeat_runs_bitwise_equal():
     P = wl.advected_bubble(n=48, seed=5)
     g, q0 = _q0(P)
