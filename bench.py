@@ -25,18 +25,19 @@ sys.path.insert(0, ROOT)
 METRIC = "grind time (ns/cell/RK-stage) + %HBM peak; FP32/learned vs FP64 at fixed L1"
 HBM_PEAK_GBS = 8000.0
 STATE_BYTES = 56  # 7 float64 per cell
-KERNEL_NAMES = {0: "sweep_fp64<0>", 1: "sweep_fp64<1>", 2: "sweep_fp64<2>"}
+KERNEL_NAMES = {0: "sweep_x", 1: "sweep_y", 2: "sweep_z"}
 
 
-def sweep_bytes_per_cell(first: int, mode: int) -> int:
+def sweep_bytes_per_cell(first: int, mode: int, rhs_bytes: int = STATE_BYTES) -> int:
     """Algorithmic HBM bytes per cell of one sweep launch: read the stage state
     (stencil and, for the stage update, the same cells again: counted once),
     read the partial RHS unless first, write the partial RHS / caller RHS /
-    new state, and read the step's initial state in stages 2 and 3."""
+    new state, and read the step's initial state in stages 2 and 3.
+    rhs_bytes is the partial-RHS size per cell (56 in FP64, 28 in FP32)."""
     b = STATE_BYTES  # stage state
     if not first:
-        b += STATE_BYTES  # partial RHS in
-    b += STATE_BYTES  # output
+        b += rhs_bytes  # partial RHS in
+    b += rhs_bytes if mode == 0 else STATE_BYTES  # output
     if mode in (3, 4):
         b += STATE_BYTES  # q^n for the RK combination
     return b
@@ -112,6 +113,9 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--compare-steps", type=int, default=200,
+                    help="steps of the FP64 run whose time steps the FP32 form replays for its L1 error "
+                         "(negative: skip the FP32 form)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device-to-device copy of 7 * n^3 float64 (known bytes), five times, "
                          "to scale rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -125,7 +129,7 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2409_10729_amd import Solver
+    from paper_2409_10729_amd import MFX_FP32_MIXED, MFX_FP64, Solver
     from paper_2409_10729_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -142,70 +146,121 @@ def main():
     P = wl.shock_droplet(n=args.n, seed=args.seed)
     N = args.n ** 3
     w_dev = torch.from_numpy(P["w"]).cuda()
-    s = Solver(P["spec"])
-    s.set_primitive(w_dev)
-    del w_dev
-    stream = s.stream
 
-    print(f"[bench] warmup {args.warmup} steps", file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        s.rk3_step()
-    torch.cuda.synchronize()
+    def new_solver(precision):
+        s = Solver(P["spec"], precision=precision)
+        s.set_primitive(w_dev)
+        return s
 
-    s.profile(True)
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    ev0.record(stream)
-    for _ in range(args.steps):
-        s.rk3_step()
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_total = ev0.elapsed_time(ev1)
-    prof = s.profile_read()
-    s.profile(False)
-    st = s.stats()
-    if st["status"] != 0:
-        raise RuntimeError(f"solver flagged a non-physical state: {st}")
+    def time_form(precision, dt):
+        """Warm-up, then `steps` timed steps with HIP events on the solver's
+        stream; per-kernel event times from the library.  dt <= 0 uses the
+        device CFL step (FP64 headline run)."""
+        s = new_solver(precision)
+        for _ in range(args.warmup):
+            s.rk3_step(dt)
+        torch.cuda.synchronize()
+        s.profile(True)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        ev0.record(s.stream)
+        for _ in range(args.steps):
+            s.rk3_step(dt)
+        ev1.record(s.stream)
+        torch.cuda.synchronize()
+        ms_total = ev0.elapsed_time(ev1)
+        prof = s.profile_read()
+        s.profile(False)
+        st = s.stats()
+        if st["status"] != 0:
+            raise RuntimeError(f"solver flagged a non-physical state: {st}")
+        s.destroy()
+        return ms_total, prof
+
+    def kernel_table(prof, ms_total, rhs_bytes):
+        per_dir = {}
+        for (d, first, mode), (ms, cnt) in prof.items():
+            b = sweep_bytes_per_cell(first, mode, rhs_bytes) * N
+            e = per_dir.setdefault(d, {"ms": 0.0, "launches": 0, "bytes": 0})
+            e["ms"] += ms
+            e["launches"] += cnt
+            e["bytes"] += b * cnt
+        kernels = {}
+        for d, e in sorted(per_dir.items()):
+            mean_ms = e["ms"] / e["launches"]
+            bpl = e["bytes"] / e["launches"]
+            kernels[KERNEL_NAMES[d]] = {
+                "mean_us": round(mean_ms * 1e3, 2),
+                "launches": e["launches"],
+                "share": round(e["ms"] / ms_total, 4),
+                "alg_bytes_per_launch": bpl,
+                "achieved_GBs": round(bpl / (mean_ms * 1e-3) / 1e9, 1),
+            }
+        step_bytes = sum(e["bytes"] for e in per_dir.values()) / args.steps
+        return kernels, step_bytes
+
+    # ---- FP64 headline run
+    print(f"[bench] fp64: warmup {args.warmup}, {args.steps} timed steps", file=sys.stderr, flush=True)
+    ms_total, prof = time_form(MFX_FP64, 0.0)
     ms_step = ms_total / args.steps
     grind = ms_step * 1e6 / (N * 3)
-    print(f"[bench] {args.steps} steps: {ms_step:.3f} ms/step, {grind:.4f} ns/cell/stage", file=sys.stderr,
-          flush=True)
-
-    # per-kernel: algorithmic bytes / mean event duration
-    per_dir = {}
-    for (d, first, mode), (ms, cnt) in prof.items():
-        b = sweep_bytes_per_cell(first, mode) * N
-        e = per_dir.setdefault(d, {"ms": 0.0, "launches": 0, "bytes": 0})
-        e["ms"] += ms
-        e["launches"] += cnt
-        e["bytes"] += b * cnt
-    kernels = {}
-    for d, e in sorted(per_dir.items()):
-        mean_ms = e["ms"] / e["launches"]
-        bytes_per_launch = e["bytes"] / e["launches"]
-        kernels[KERNEL_NAMES[d]] = {
-            "mean_us": mean_ms * 1e3,
-            "launches": e["launches"],
-            "share": e["ms"] / ms_total,
-            "alg_bytes_per_launch": bytes_per_launch,
-            "achieved_GBs": bytes_per_launch / (mean_ms * 1e-3) / 1e9,
-        }
+    kernels, step_bytes = kernel_table(prof, ms_total, STATE_BYTES)
+    print(f"[bench] fp64: {ms_step:.3f} ms/step, {grind:.4f} ns/cell/stage", file=sys.stderr, flush=True)
     dom = max(kernels, key=lambda k: kernels[k]["mean_us"] * kernels[k]["launches"])
     kd = kernels[dom]
-    traffic = load_traffic(dom)
-    step_bytes = sum(e["bytes"] for e in per_dir.values()) / args.steps
     roofline = {
         "bound": "hbm",
-        "achieved": round(kd["achieved_GBs"], 1),
+        "achieved": kd["achieved_GBs"],
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4),
-        "traffic": traffic,
+        "traffic": load_traffic(dom),
         "kernel": dom,
-        "mean_us": round(kd["mean_us"], 2),
+        "mean_us": kd["mean_us"],
         "alg_bytes_per_launch": kd["alg_bytes_per_launch"],
     }
+
+    forms = {"fp64": {"ms_per_step": round(ms_step, 4), "grind": round(grind, 5), "kernels": kernels,
+                      "step_alg_bytes_hbm_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+
+    # ---- FP32 mixed form: timing, then accuracy against FP64 on replayed time steps
+    if args.compare_steps >= 0:
+        print(f"[bench] accuracy: fp64 vs fp32 over {args.compare_steps} replayed steps", file=sys.stderr, flush=True)
+        s64 = new_solver(MFX_FP64)
+        dts = [s64.rk3_step(sync=True) for _ in range(args.compare_steps)]
+        q64 = s64.get_state().cpu().numpy().reshape(7, -1)
+        s64.destroy()
+        del s64
+        s32 = new_solver(MFX_FP32_MIXED)
+        for dt in dts:
+            s32.rk3_step(dt)
+        q32 = s32.get_state().cpu().numpy().reshape(7, -1)
+        s32.destroy()
+        del s32
+        den = np.abs(q64).sum(axis=1)
+        den[2:5] = den[2:5].max()
+        l1 = (np.abs(q32 - q64).sum(axis=1) / den).tolist()
+        rho64 = q64[0] + q64[1]
+        rho_l1 = float(np.abs(q32[0] + q32[1] - rho64).sum() / np.abs(rho64).sum())
+        dt_fixed = dts[0] if dts else 1e-9
+        del q32, q64
+        print(f"[bench] fp32: timing {args.steps} steps", file=sys.stderr, flush=True)
+        ms32, prof32 = time_form(MFX_FP32_MIXED, dt_fixed)
+        ms32_step = ms32 / args.steps
+        k32, sb32 = kernel_table(prof32, ms32, 28)
+        forms["fp32_mixed"] = {
+            "ms_per_step": round(ms32_step, 4),
+            "grind": round(ms32_step * 1e6 / (N * 3), 5),
+            "speedup_vs_fp64": round(ms_step / ms32_step, 3),
+            "compare_steps": args.compare_steps,
+            "l1_rel_vs_fp64": [float(f"{x:.3e}") for x in l1],
+            "density_l1_rel_vs_fp64": float(f"{rho_l1:.3e}"),
+            "kernels": k32,
+        }
+        print(f"[bench] fp32: {ms32_step:.3f} ms/step (x{ms_step / ms32_step:.2f}), density L1 {rho_l1:.2e}",
+              file=sys.stderr, flush=True)
+    del w_dev
 
     out = {
         "metric": METRIC,
@@ -228,9 +283,8 @@ def main():
             "precision": "fp64",
         },
         "grind_ns_per_cell_pde_rhs": round(grind / 7, 6),
-        "step_alg_bytes_hbm_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-        "kernels": kernels,
         "roofline": roofline,
+        "forms": forms,
     }
     if not args.no_cpu:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)

@@ -63,26 +63,26 @@ struct SweepGeom {
 
 // The x sweep takes whole rows when a row fits the row kernel (nx <=
 // XROW_MAX and its LDS fits a workgroup), else it marches along x.
-bool use_xrows(const int n[3], int mode_override)
+bool use_xrows(const int n[3], int mode_override, size_t elem)
 {
     if (mode_override == 1) return false;
-    return n[0] <= XROW_MAX && xrow_lds_bytes(n[0]) <= 64 * 1024;
+    return n[0] <= XROW_MAX && xrow_lds_bytes(n[0], elem) <= 64 * 1024;
 }
 
-SweepGeom sweep_geom(const int n[3], int d, int seg_override, int xmode_override)
+SweepGeom sweep_geom(const int n[3], int d, int seg_override, int xmode_override, size_t elem)
 {
     int seg = seg_override > 0 ? seg_override : 64;
     SweepGeom g;
     g.lds = 0;
     g.xrows = false;
-    if (d == 0 && use_xrows(n, xmode_override)) {
+    if (d == 0 && use_xrows(n, xmode_override, elem)) {
         const long long rows = (long long)n[1] * n[2];
         // about 2048 blocks, at least one row each
         const long long rpb = std::max<long long>(1, rows / 2048);
         g.grid = dim3((unsigned)((rows + rpb - 1) / rpb), 1, 1);
         g.block = 64 * ((n[0] + 63) / 64);
         g.seg = (int)rpb;
-        g.lds = xrow_lds_bytes(n[0]);
+        g.lds = xrow_lds_bytes(n[0], elem);
         g.xrows = true;
     } else if (d == 0) {
         // blocks of XROWS rows (y,z flattened), segments along x
@@ -110,10 +110,11 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     Layout L{};
     const long long N = (long long)d->n[0] * d->n[1] * d->n[2];
     const size_t state = align_up(sizeof(double) * 7 * (size_t)N);
+    const size_t elem = d->precision == MFX_FP32_MIXED ? sizeof(float) : sizeof(double);
     long long np = CFL_BLOCKS;
     for (int k = 0; k < 3; ++k) {
         if (d->n[k] <= 1 && !(k == 0 && d->n[1] == 1 && d->n[2] == 1)) continue;
-        SweepGeom g = sweep_geom(d->n, k, seg_override, xmode_override);
+        SweepGeom g = sweep_geom(d->n, k, seg_override, xmode_override, elem);
         np = std::max(np, (long long)g.grid.x * g.grid.y * g.grid.z);
     }
     const long long nrows = (long long)d->n[1] * d->n[2];
@@ -125,13 +126,13 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     L.q2 = off;
     off += state;
     L.r = off;
-    off += state;
+    off += align_up(elem * 7 * (size_t)N);
     L.scal = off;
     off += align_up(64);
     L.partial = off;
     off += align_up(sizeof(double) * (size_t)np);
     L.bface = off;
-    off += align_up(sizeof(double) * BFACE * 2 * (size_t)nrows);
+    off += align_up(elem * BFACE * 2 * (size_t)nrows);
     L.total = off;
     L.n_partial = np;
     return L;
@@ -277,7 +278,9 @@ struct mfx_ctx {
     char* ws;
     size_t ws_bytes;
     Layout L;
-    double *q, *q1, *q2, *r, *scal, *partial, *bface;
+    double *q, *q1, *q2, *scal, *partial;
+    void *r, *bface;  // compute-type buffers
+    size_t elem;      // sizeof the compute type
     unsigned* status;
     int dirs[3];
     int ndirs;
@@ -342,61 +345,74 @@ hipEvent_t take_event(mfx_ctx* c)
     return e;
 }
 
+// Pointers and scalars of one sweep launch.
+struct LaunchArgs {
+    const SweepGeom* sg;
+    hipStream_t st;
+    const Grid* g;
+    const double* qs;
+    const double* qn;
+    void* r;  // partial RHS buffer (compute type)
+    double* out;
+    const double* dt_dev;
+    double dt_arg;
+    double* partial;
+    unsigned* status;
+    void* bface;  // boundary faces of the x row sweep (compute type)
+};
+
 // The x row sweep reads the boundary faces that boundary_faces_x leaves in
 // `bface` (launched just before it on the same stream).
-template <int DIR, bool FIRST, int MODE>
-void launch_one(const SweepGeom& sg, hipStream_t st, const Grid& g, const double* qs, const double* qn, double* r,
-                double* out, const double* dt_dev, double dt_arg, double* partial, unsigned* status,
-                double* bface)
+template <int DIR, typename T, bool FIRST, int MODE>
+void launch_one(const LaunchArgs& a)
 {
+    const SweepGeom& sg = *a.sg;
+    T* r = static_cast<T*>(a.r);
     if constexpr (DIR == 0) {
         if (sg.xrows) {
-            const long long faces = 2LL * g.n[1] * g.n[2];
-            boundary_faces_x<<<(unsigned)((faces + 255) / 256), 256, 0, st>>>(g, qs, bface);
-            sweep_x_rows<FIRST, MODE><<<sg.grid, sg.block, sg.lds, st>>>(g, qs, qn, r, out, sg.seg, bface, dt_dev,
-                                                                        dt_arg, partial, status);
+            T* bf = static_cast<T*>(a.bface);
+            const long long faces = 2LL * a.g->n[1] * a.g->n[2];
+            boundary_faces_x<T><<<(unsigned)((faces + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf);
+            sweep_x_rows<T, FIRST, MODE><<<sg.grid, sg.block, sg.lds, a.st>>>(
+                *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.partial, a.status);
         } else {
-            sweep_x_fp64<FIRST, MODE><<<sg.grid, XROWS, 0, st>>>(g, qs, qn, r, out, sg.seg, dt_dev, dt_arg, partial,
-                                                                status);
+            sweep_x_march<T, FIRST, MODE><<<sg.grid, XROWS, 0, a.st>>>(*a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev,
+                                                                      a.dt_arg, a.partial, a.status);
         }
-    } else
-        sweep_yz_fp64<DIR, FIRST, MODE><<<sg.grid, SWEEP_BLOCK, 0, st>>>(g, qs, qn, r, out, sg.seg, dt_dev, dt_arg,
-                                                                        partial, status);
+    } else {
+        sweep_yz<DIR, T, FIRST, MODE><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(*a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev,
+                                                                        a.dt_arg, a.partial, a.status);
+    }
 }
 
-template <int DIR, bool FIRST>
-void launch_mode(int mode, const SweepGeom& sg, hipStream_t st, const Grid& g, const double* qs, const double* qn,
-                 double* r, double* out, const double* dt_dev, double dt_arg, double* partial, unsigned* status,
-                 double* bface)
+template <int DIR, typename T, bool FIRST>
+void launch_mode(int mode, const LaunchArgs& a)
 {
     switch (mode) {
-    case OUT_ACCUM: launch_one<DIR, FIRST, OUT_ACCUM>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface); break;
-    case OUT_RHS: launch_one<DIR, FIRST, OUT_RHS>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface); break;
-    case OUT_STAGE1: launch_one<DIR, FIRST, OUT_STAGE1>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface); break;
-    case OUT_STAGE2: launch_one<DIR, FIRST, OUT_STAGE2>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface); break;
-    default: launch_one<DIR, FIRST, OUT_STAGE3>(sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface); break;
+    case OUT_ACCUM: launch_one<DIR, T, FIRST, OUT_ACCUM>(a); break;
+    case OUT_RHS: launch_one<DIR, T, FIRST, OUT_RHS>(a); break;
+    case OUT_STAGE1: launch_one<DIR, T, FIRST, OUT_STAGE1>(a); break;
+    case OUT_STAGE2: launch_one<DIR, T, FIRST, OUT_STAGE2>(a); break;
+    default: launch_one<DIR, T, FIRST, OUT_STAGE3>(a); break;
     }
 }
 
 // The x sweep, when active, is always the first direction of a pass.
-void launch_dispatch(int d, bool first, int mode, const SweepGeom& sg, hipStream_t st, const Grid& g,
-                     const double* qs, const double* qn, double* r, double* out, const double* dt_dev, double dt_arg,
-                     double* partial, unsigned* status, double* bface)
+template <typename T>
+void launch_dispatch(int d, bool first, int mode, const LaunchArgs& a)
 {
     if (d == 0)
-        launch_mode<0, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface);
+        launch_mode<0, T, true>(mode, a);
     else if (d == 1)
-        first ? launch_mode<1, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface)
-              : launch_mode<1, false>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface);
+        first ? launch_mode<1, T, true>(mode, a) : launch_mode<1, T, false>(mode, a);
     else
-        first ? launch_mode<2, true>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface)
-              : launch_mode<2, false>(mode, sg, st, g, qs, qn, r, out, dt_dev, dt_arg, partial, status, bface);
+        first ? launch_mode<2, T, true>(mode, a) : launch_mode<2, T, false>(mode, a);
 }
 
 int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* out, int first, int mode,
                  const double* dt_dev, double dt_arg)
 {
-    SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override);
+    SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem);
     if ((long long)sg.grid.x * sg.grid.y * sg.grid.z > c->L.n_partial)
         return fail(c, MFX_EINVAL, "internal: partial buffer smaller than sweep grid");
     mfx_ctx::Pending pend{(d * 2 + (first ? 1 : 0)) * 5 + mode, nullptr, nullptr};
@@ -406,8 +422,11 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
         if (!pend.a || !pend.b) return fail(c, MFX_EHIP, "hipEventCreate failed");
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
-    launch_dispatch(d, first != 0, mode, sg, c->stream, c->g, qs, qn, c->r, out, dt_dev, dt_arg, c->partial,
-                    c->status, c->bface);
+    const LaunchArgs la{&sg, c->stream, &c->g, qs, qn, c->r, out, dt_dev, dt_arg, c->partial, c->status, c->bface};
+    if (c->desc.precision == MFX_FP32_MIXED)
+        launch_dispatch<float>(d, first != 0, mode, la);
+    else
+        launch_dispatch<double>(d, first != 0, mode, la);
     int rc = launch_check(c, "sweep kernel");
     if (rc) return rc;
     if (c->profiling) {
@@ -429,7 +448,7 @@ int run_passes(mfx_ctx* c, const double* qs, const double* qn, double* out, int 
                               dt_arg);
         if (rc != MFX_OK) return rc;
         if (last && last_blocks) {
-            SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override);
+            SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem);
             *last_blocks = (long long)sg.grid.x * sg.grid.y * sg.grid.z;
         }
     }
@@ -472,8 +491,8 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     *out = nullptr;
     std::string why;
     if (!validate(desc, why)) return fail(nullptr, MFX_EINVAL, why);
-    if (desc->weights == MFX_WENO5_LEARNED || desc->precision == MFX_FP32_MIXED)
-        return fail(nullptr, MFX_EINVAL, "this build supports precision MFX_FP64 with MFX_WENO5_JS only");
+    if (desc->weights == MFX_WENO5_LEARNED)
+        return fail(nullptr, MFX_EINVAL, "learned weights are not available in this build");
     if (!ws_dev) return fail(nullptr, MFX_EINVAL, "workspace pointer is NULL");
     if (reinterpret_cast<uintptr_t>(ws_dev) % ALIGN != 0)
         return fail(nullptr, MFX_EINVAL, "workspace must be 256-byte aligned");
@@ -501,11 +520,12 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     c->q = reinterpret_cast<double*>(c->ws + L.q);
     c->q1 = reinterpret_cast<double*>(c->ws + L.q1);
     c->q2 = reinterpret_cast<double*>(c->ws + L.q2);
-    c->r = reinterpret_cast<double*>(c->ws + L.r);
+    c->r = c->ws + L.r;
+    c->elem = desc->precision == MFX_FP32_MIXED ? sizeof(float) : sizeof(double);
     c->scal = reinterpret_cast<double*>(c->ws + L.scal);
     c->status = reinterpret_cast<unsigned*>(c->ws + L.scal + 4 * sizeof(double));
     c->partial = reinterpret_cast<double*>(c->ws + L.partial);
-    c->bface = reinterpret_cast<double*>(c->ws + L.bface);
+    c->bface = c->ws + L.bface;
 
     Grid& g = c->g;
     g.N = (long long)desc->n[0] * desc->n[1] * desc->n[2];

@@ -117,6 +117,23 @@ __device__ __forceinline__ void weno5_js_ratio(float a, float b, float c, float 
     left = (wl0 * l0 + wl1 * l1 + wl2 * l2) / (6.f * (wl0 + wl1 + wl2));
 }
 
+// WENO5 in the compute type: the product form in float64, the ratio form
+// in float32.
+template <typename T>
+__device__ __forceinline__ void weno5(T a, T b, T c, T d, T e, T eps, T& left, T& right);
+template <>
+__device__ __forceinline__ void weno5<double>(double a, double b, double c, double d, double e, double eps,
+                                              double& left, double& right)
+{
+    weno5_js<double>(a, b, c, d, e, eps, left, right);
+}
+template <>
+__device__ __forceinline__ void weno5<float>(float a, float b, float c, float d, float e, float eps, float& left,
+                                             float& right)
+{
+    weno5_js_ratio(a, b, c, d, e, eps, left, right);
+}
+
 // HLLC flux across a face normal to direction DIR (Toro 2009, Sec. 10.4),
 // Davis wave-speed estimates, extended to the five-equation model: each
 // partial density and alpha1 are scaled by xi = (S_K - u_K)/(S_K - S*) in

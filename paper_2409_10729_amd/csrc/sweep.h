@@ -4,6 +4,11 @@
 // and alpha1 div(u) source, and -- in the last active direction of a stage --
 // the SSP-RK3 combine and the CFL wave-speed maximum.
 //
+// T is the arithmetic of reconstruction, Riemann solve and flux difference
+// (double, or float for the mixed-precision form).  The conserved ->
+// primitive conversion, the stage update and the CFL reduction are always
+// float64; the partial RHS buffer holds T.
+//
 // Work decomposition: one thread marches along the sweep direction over a
 // segment of `seg` cells of one pencil, keeping a 5-cell window of
 // primitives in registers; each cell is reconstructed once (both edges from
@@ -121,27 +126,30 @@ __device__ __forceinline__ double rk3_combine(int mode, double qn, double qs, do
     return (1.0 / 3.0) * qn + (2.0 / 3.0) * a;
 }
 
+// Everything an output needs: the stage state (for the stage update), the
+// step's initial state (aliases out in stage 3), the partial RHS buffer (of
+// the compute type) and the caller RHS or new state.
+template <typename T>
+struct OutArgs {
+    const double* qs;
+    const double* qn;
+    T* racc;
+    double* out;
+    double dt;
+};
+
 // What a pass does with a cell's contribution of this direction: fd[v] =
 // (F_{c-1/2} - F_{c+1/2}) / dx and the alpha1 source term src, added to the
 // running sum as (R + fd) + src for alpha1 and R + fd otherwise.  FIRST
 // (no running sum yet) and MODE (what is written) are compile-time so each
-// kernel carries only its own path.
-struct OutArgs {
-    const double* qs;  // stage state (for the stage update)
-    const double* qn;  // step's initial state (aliases out in stage 3)
-    double* racc;      // partial RHS buffer
-    double* out;       // caller RHS or new state
-    double dt;
-};
-
-// Output of one cell at linear offset `cell`; returns the CFL speed of the
-// new state in stage 3 (else 0).
-template <bool FIRST, int MODE>
-__device__ __forceinline__ double emit_cell(const Grid& g, const OutArgs& o, long long cell, const double fd[NV],
-                                            double src, unsigned& bad)
+// kernel carries only its own path.  Returns the CFL speed of the new state
+// in stage 3 (else 0).
+template <typename T, bool FIRST, int MODE>
+__device__ __forceinline__ double emit_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T fd[NV],
+                                            T src, unsigned& bad)
 {
     const long long N = g.N;
-    double r[NV];
+    T r[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) r[v] = FIRST ? fd[v] : o.racc[v * N + cell] + fd[v];
     r[6] += src;
@@ -151,14 +159,14 @@ __device__ __forceinline__ double emit_cell(const Grid& g, const OutArgs& o, lon
         return 0.0;
     } else if constexpr (MODE == OUT_RHS) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) o.out[v * N + cell] = r[v];
+        for (int v = 0; v < NV; ++v) o.out[v * N + cell] = (double)r[v];
         return 0.0;
     } else {
         double qo[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const double qnv = MODE == OUT_STAGE1 ? 0.0 : o.qn[v * N + cell];
-            qo[v] = rk3_combine(MODE, qnv, o.qs[v * N + cell], o.dt, r[v]);
+            qo[v] = rk3_combine(MODE, qnv, o.qs[v * N + cell], o.dt, (double)r[v]);
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) o.out[v * N + cell] = qo[v];
@@ -166,18 +174,28 @@ __device__ __forceinline__ double emit_cell(const Grid& g, const OutArgs& o, lon
     }
 }
 
+// Primitives of one cell in the compute type: the inversion is float64.
+template <typename T>
+__device__ __forceinline__ void prim_of(const Mix<double>& mix, const double q[NV], T w[NV])
+{
+    double wd[NV];
+    cons_to_prim(mix, q, wd);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = (T)wd[v];
+}
+
 // Sink of the y and z sweeps: each lane writes its own cell (lanes are
 // consecutive x, so every access is a contiguous row).
-template <bool FIRST, int MODE>
+template <typename T, bool FIRST, int MODE>
 struct GlobalSink {
-    OutArgs o;
+    OutArgs<T> o;
     long long base, sd;
     bool valid;
     double smax;
     unsigned bad;
-    __device__ __forceinline__ void put(const Grid& g, int c, const double fd[NV], double src)
+    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src)
     {
-        if (valid) smax = fmax(smax, emit_cell<FIRST, MODE>(g, o, base + (long long)c * sd, fd, src, bad));
+        if (valid) smax = fmax(smax, emit_cell<T, FIRST, MODE>(g, o, base + (long long)c * sd, fd, src, bad));
     }
 };
 
@@ -185,41 +203,42 @@ struct GlobalSink {
 // the conserved state of cell `pos` along the sweep (boundary map applied);
 // it is called for positions c0-3, c0-2, ..., c1+2 in that order, and
 // Sink::put for cells c0..c1-1 in order, the same sequence on every lane.
-template <int DIR, class Src, class Sink>
+template <int DIR, typename T, class Src, class Sink>
 __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, int c0, int c1)
 {
-    const double idx = g.inv_dx[DIR];
-    const double eps = g.eps;
-    const Mix<double> mix{g.G1, g.G2, g.P1, g.P2};
+    const T idx = (T)g.inv_dx[DIR];
+    const T eps = (T)g.eps;
+    const Mix<double> mixd{g.G1, g.G2, g.P1, g.P2};
+    const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
 
     // window: W[k] = primitives of cell c-2+k while reconstructing cell c
-    double W[5][NV];
+    T W[5][NV];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         double qc[NV];
         src.load(c0 - 3 + k, qc);
-        cons_to_prim(mix, qc, W[k]);
+        prim_of<T>(mixd, qc, W[k]);
     }
 
-    double rprev[NV], Fprev[NV], ufprev = 0.0;
+    T rprev[NV], Fprev[NV], ufprev = T(0);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) rprev[v] = Fprev[v] = 0.0;
+    for (int v = 0; v < NV; ++v) rprev[v] = Fprev[v] = T(0);
 
     for (int c = c0 - 1; c <= c1; ++c) {
         // next cell entering the window (c+3), fetched early
         double qnext[NV];
         if (c < c1) src.load(c + 3, qnext);
 
-        double lft[NV], rgt[NV];
+        T lft[NV], rgt[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) weno5_js<double>(W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, lft[v], rgt[v]);
+        for (int v = 0; v < NV; ++v) weno5<T>(W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, lft[v], rgt[v]);
 
         if (c >= c0) {
-            double F[NV], uf;
-            hllc<DIR, double>(mix, rprev, lft, F, uf);
+            T F[NV], uf;
+            hllc<DIR, T>(mix, rprev, lft, F, uf);
             if (c > c0) {
                 // cell c-1: faces c-3/2 (Fprev) and c-1/2 (F)
-                double fd[NV];
+                T fd[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) fd[v] = (Fprev[v] - F[v]) * idx;
                 sink.put(g, c - 1, fd, W[1][6] * ((uf - ufprev) * idx));
@@ -236,7 +255,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, int c
             for (int k = 0; k < 4; ++k)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) W[k][v] = W[k + 1][v];
-            cons_to_prim(mix, qnext, W[4]);
+            prim_of<T>(mixd, qnext, W[4]);
         }
     }
 }
@@ -261,11 +280,11 @@ struct GlobalSrc {
 // qn and out alias in the third stage (the new state overwrites q in place;
 // each cell's q is read only by the thread that then writes it), so neither
 // is declared __restrict__.
-template <int DIR, bool FIRST, int MODE>
-__global__ void __launch_bounds__(256, 2) sweep_yz_fp64(Grid g, const double* __restrict__ qs, const double* qn,
-                                                        double* __restrict__ racc, double* out, int seg,
-                                                        const double* __restrict__ dt_dev, double dt_arg,
-                                                        double* __restrict__ partial, unsigned* __restrict__ status)
+template <int DIR, typename T, bool FIRST, int MODE>
+__global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
+                                                   T* __restrict__ racc, double* out, int seg,
+                                                   const double* __restrict__ dt_dev, double dt_arg,
+                                                   double* __restrict__ partial, unsigned* __restrict__ status)
 {
     constexpr int BLOCK = 256;
     static_assert(DIR == 1 || DIR == 2, "y or z sweep");
@@ -280,9 +299,9 @@ __global__ void __launch_bounds__(256, 2) sweep_yz_fp64(Grid g, const double* __
     const int c0 = blockIdx.z * seg;
     const int c1 = min(c0 + seg, n);
     GlobalSrc src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
-    GlobalSink<FIRST, MODE> sink{OutArgs{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid,
-                                 0.0, 0u};
-    march<DIR>(g, src, sink, c0, c1);
+    GlobalSink<T, FIRST, MODE> sink{OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR],
+                                    valid, 0.0, 0u};
+    march<DIR, T>(g, src, sink, c0, c1);
 
     if constexpr (MODE == OUT_STAGE3) {
         if (sink.bad) atomicOr(status, sink.bad);
@@ -291,14 +310,14 @@ __global__ void __launch_bounds__(256, 2) sweep_yz_fp64(Grid g, const double* __
     }
 }
 
-// x sweep.  The 64 lanes of the (one-wave) block own 64 consecutive rows
-// (row = k * ny + j, x-contiguous in memory) and march along x together.
-// Inputs: every XCHUNK positions the block stages the next XCHUNK cells of
-// all 64 rows through LDS with row-contiguous reads, then each lane reads
-// its own row.  Outputs: each lane parks its cell's contribution in LDS and
-// every XCHUNK cells the block writes them out row-contiguously (including
-// the partial-RHS read and the stage update), so no global access is
-// strided across lanes.
+// Marching x sweep, for rows longer than the whole-row kernel takes.  The 64
+// lanes of the (one-wave) block own 64 consecutive rows (row = k * ny + j,
+// x-contiguous in memory) and march along x together.  Inputs: every XCHUNK
+// positions the block stages the next XCHUNK cells of all 64 rows through
+// LDS with row-contiguous reads, then each lane reads its own row.  Outputs:
+// each lane parks its cell's contribution in LDS and every XCHUNK cells the
+// block writes them out row-contiguously (including the partial-RHS read and
+// the stage update), so no global access is strided across lanes.
 constexpr int XROWS = 64;
 constexpr int XCHUNK = 4;
 
@@ -332,16 +351,16 @@ struct LdsSrc {
     }
 };
 
-template <bool FIRST, int MODE>
+template <typename T, bool FIRST, int MODE>
 struct LdsSink {
-    double (*buf)[NV + 1][XROWS];  // [XCHUNK][fd 0..6, src][XROWS]
-    OutArgs o;
+    T (*buf)[NV + 1][XROWS];  // [XCHUNK][fd 0..6, src][XROWS]
+    OutArgs<T> o;
     long long row0, nrows;
     int nx, c0, c1;
     double smax;
     unsigned bad;
 
-    __device__ __forceinline__ void put(const Grid& g, int c, const double fd[NV], double src)
+    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src)
     {
         const int slot = (c - c0) % XCHUNK;
 #pragma unroll
@@ -355,11 +374,11 @@ struct LdsSink {
                 const int item = threadIdx.x + it * XROWS;
                 const int r = item / XCHUNK, cx = item % XCHUNK;
                 if (cx < cnt && row0 + r < nrows) {
-                    double f[NV];
+                    T f[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) f[v] = buf[cx][v][r];
                     const long long cell = (row0 + r) * nx + p0 + cx;
-                    smax = fmax(smax, emit_cell<FIRST, MODE>(g, o, cell, f, buf[cx][NV][r], bad));
+                    smax = fmax(smax, emit_cell<T, FIRST, MODE>(g, o, cell, f, buf[cx][NV][r], bad));
                 }
             }
             __syncthreads();  // the buffer is refilled next
@@ -367,14 +386,14 @@ struct LdsSink {
     }
 };
 
-template <bool FIRST, int MODE>
-__global__ void __launch_bounds__(XROWS, 2) sweep_x_fp64(Grid g, const double* __restrict__ qs, const double* qn,
-                                                         double* __restrict__ racc, double* out, int seg,
-                                                         const double* __restrict__ dt_dev, double dt_arg,
-                                                         double* __restrict__ partial, unsigned* __restrict__ status)
+template <typename T, bool FIRST, int MODE>
+__global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* __restrict__ qs, const double* qn,
+                                                          T* __restrict__ racc, double* out, int seg,
+                                                          const double* __restrict__ dt_dev, double dt_arg,
+                                                          double* __restrict__ partial, unsigned* __restrict__ status)
 {
     __shared__ double ibuf[XCHUNK][NV][XROWS];
-    __shared__ double obuf[XCHUNK][NV + 1][XROWS];
+    __shared__ T obuf[XCHUNK][NV + 1][XROWS];
     const int nx = g.n[0];
     const long long nrows = (long long)g.n[1] * g.n[2];
     const long long row0 = (long long)blockIdx.x * XROWS;
@@ -382,9 +401,9 @@ __global__ void __launch_bounds__(XROWS, 2) sweep_x_fp64(Grid g, const double* _
     const int c1 = min(c0 + seg, nx);
 
     LdsSrc src{ibuf, qs, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
-    LdsSink<FIRST, MODE> sink{obuf, OutArgs{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx, c0, c1,
-                              0.0, 0u};
-    march<0>(g, src, sink, c0, c1);
+    LdsSink<T, FIRST, MODE> sink{obuf, OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx,
+                                 c0, c1, 0.0, 0u};
+    march<0, T>(g, src, sink, c0, c1);
 
     if constexpr (MODE == OUT_STAGE3) {
         if (sink.bad) atomicOr(status, sink.bad);

@@ -23,8 +23,8 @@ constexpr int BFACE = NV + 1;       // flux components + face velocity
 // Boundary faces of every row: thread t -> (row t/2, side t%2); side 0 is
 // the face between ghost cell -1 and cell 0, side 1 between cell nx-1 and
 // ghost cell nx.  Output bface[(row*2 + side) * BFACE + k].
-__global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __restrict__ qs,
-                                                         double* __restrict__ bface)
+template <typename T>
+__global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __restrict__ qs, T* __restrict__ bface)
 {
     const long long nrows = (long long)g.n[1] * g.n[2];
     const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -32,26 +32,28 @@ __global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __
     const long long row = t >> 1;
     const int side = (int)(t & 1);
     const int nx = g.n[0];
-    const Mix<double> mix{g.G1, g.G2, g.P1, g.P2};
+    const Mix<double> mixd{g.G1, g.G2, g.P1, g.P2};
+    const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
+    const T eps = (T)g.eps;
     const int first = side == 0 ? -3 : nx - 3;  // cells first .. first+5
-    double w[6][NV];
+    T w[6][NV];
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
         const long long off = row * nx + map_cell(first + k, nx, g.bc[0][0], g.bc[0][1]);
         double q[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) q[v] = qs[v * g.N + off];
-        cons_to_prim(mix, q, w[k]);
+        prim_of<T>(mixd, q, w[k]);
     }
-    double wl[NV], wr[NV], dummy;
+    T wl[NV], wr[NV], dummy;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
-        weno5_js<double>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], g.eps, dummy, wl[v]);  // right edge of first+2
-        weno5_js<double>(w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], g.eps, wr[v], dummy);  // left edge of first+3
+        weno5<T>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], eps, dummy, wl[v]);  // right edge of first+2
+        weno5<T>(w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps, wr[v], dummy);  // left edge of first+3
     }
-    double F[NV], uf;
-    hllc<0, double>(mix, wl, wr, F, uf);
-    double* o = bface + t * BFACE;
+    T F[NV], uf;
+    hllc<0, T>(mix, wl, wr, F, uf);
+    T* o = bface + t * BFACE;
 #pragma unroll
     for (int v = 0; v < NV; ++v) o[v] = F[v];
     o[NV] = uf;
@@ -60,37 +62,40 @@ __global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __
 // LDS bytes of the row kernel: primitives P[NV][nx+4] (two ghost slots on
 // each side) sharing storage with the face fluxes F[BFACE][nx] (P is dead
 // once every lane has reconstructed), plus left-edge states L[NV][nx].
-inline size_t xrow_lds_bytes(int nx)
+inline size_t xrow_lds_bytes(int nx, size_t elem)
 {
     const size_t pf = (size_t)NV * (nx + 4) > (size_t)BFACE * nx ? (size_t)NV * (nx + 4) : (size_t)BFACE * nx;
-    return sizeof(double) * (pf + (size_t)NV * nx);
+    return elem * (pf + (size_t)NV * nx);
 }
 
 // Row kernel.
-template <bool FIRST, int MODE>
+template <typename T, bool FIRST, int MODE>
 __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const double* __restrict__ qs, const double* qn,
-                                                             double* __restrict__ racc, double* out, int rows_per_block,
-                                                             const double* __restrict__ bface,
+                                                             T* __restrict__ racc, double* out, int rows_per_block,
+                                                             const T* __restrict__ bface,
                                                              const double* __restrict__ dt_dev, double dt_arg,
                                                              double* __restrict__ partial,
                                                              unsigned* __restrict__ status)
 {
-    extern __shared__ double lds[];
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* lds = reinterpret_cast<T*>(lds_raw);
     const int nx = g.n[0];
     const int np = nx + 4;
     const int pf = NV * np > BFACE * nx ? NV * np : BFACE * nx;
-    double* P = lds;       // [NV][np], cell x at index x + 2
-    double* Fs = lds;      // [BFACE][nx], same storage as P
-    double* L = lds + pf;  // [NV][nx]
+    T* P = lds;       // [NV][np], cell x at index x + 2
+    T* Fs = lds;      // [BFACE][nx], same storage as P
+    T* L = lds + pf;  // [NV][nx]
     const long long nrows = (long long)g.n[1] * g.n[2];
     const long long r0 = (long long)blockIdx.x * rows_per_block;
     const long long r1 = min(r0 + rows_per_block, nrows);
     const int x = threadIdx.x;
     const bool has = x < nx;
     const int xc = has ? x : nx - 1;
-    const double idx = g.inv_dx[0];
-    const Mix<double> mix{g.G1, g.G2, g.P1, g.P2};
-    const OutArgs o{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg};
+    const T idx = (T)g.inv_dx[0];
+    const T eps = (T)g.eps;
+    const Mix<double> mixd{g.G1, g.G2, g.P1, g.P2};
+    const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
+    const OutArgs<T> o{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg};
     // ghost slots this lane fills: positions -2, -1, nx, nx+1 map to cells
     const int gsrc0 = map_cell(-2, nx, g.bc[0][0], g.bc[0][1]);
     const int gsrc1 = map_cell(-1, nx, g.bc[0][0], g.bc[0][1]);
@@ -107,8 +112,8 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
     for (long long row = r0; row < r1; ++row) {
         __syncthreads();  // the previous row's F (same storage as P) is consumed
         // 1. own cell -> primitives in LDS (and the ghost slots that copy it)
-        double w[NV];
-        cons_to_prim(mix, qc, w);
+        T w[NV];
+        prim_of<T>(mixd, qc, w);
         if (has) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -126,26 +131,26 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
             for (int v = 0; v < NV; ++v) qc[v] = qs[v * g.N + (row + 1) * nx + xc];
         }
         // 2. reconstruct own cell: left edge to LDS, right edge kept
-        double rgt[NV];
+        T rgt[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double* p = P + v * np + xc;
-            double lft;
-            weno5_js<double>(p[0], p[1], p[2], p[3], p[4], g.eps, lft, rgt[v]);
+            const T* p = P + v * np + xc;
+            T lft;
+            weno5<T>(p[0], p[1], p[2], p[3], p[4], eps, lft, rgt[v]);
             if (has) L[v * nx + x] = lft;
         }
-        const double a1 = w[6];
+        const T a1 = w[6];
         __syncthreads();
         // 3. face x+1/2 (the row's last face comes from boundary_faces_x)
-        double F[BFACE];
+        T F[BFACE];
         {
-            double wr[NV];
+            T wr[NV];
             const int xr = min(xc + 1, nx - 1);
 #pragma unroll
             for (int v = 0; v < NV; ++v) wr[v] = L[v * nx + xr];
-            double Fh[NV], ufh;
-            hllc<0, double>(mix, rgt, wr, Fh, ufh);
-            const double* b = bface + (row * 2 + 1) * BFACE;
+            T Fh[NV], ufh;
+            hllc<0, T>(mix, rgt, wr, Fh, ufh);
+            const T* b = bface + (row * 2 + 1) * BFACE;
             const bool last = xc == nx - 1;
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] = last ? b[v] : Fh[v];
@@ -158,20 +163,20 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
         __syncthreads();
         // 4. cell x: faces x-1/2 (left neighbour, or the row's first face) and x+1/2
         if (has) {
-            double Fm[BFACE];
+            T Fm[BFACE];
             if (x == 0) {
-                const double* b = bface + (row * 2 + 0) * BFACE;
+                const T* b = bface + (row * 2 + 0) * BFACE;
 #pragma unroll
                 for (int k = 0; k < BFACE; ++k) Fm[k] = b[k];
             } else {
 #pragma unroll
                 for (int k = 0; k < BFACE; ++k) Fm[k] = Fs[k * nx + x - 1];
             }
-            double fd[NV];
+            T fd[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) fd[v] = (Fm[v] - F[v]) * idx;
-            const double src = a1 * ((F[NV] - Fm[NV]) * idx);
-            smax = fmax(smax, emit_cell<FIRST, MODE>(g, o, row * nx + x, fd, src, bad));
+            const T src = a1 * ((F[NV] - Fm[NV]) * idx);
+            smax = fmax(smax, emit_cell<T, FIRST, MODE>(g, o, row * nx + x, fd, src, bad));
         }
     }
     if constexpr (MODE == OUT_STAGE3) {

@@ -33,10 +33,13 @@ def rel_linf(x: np.ndarray, y: np.ndarray) -> np.ndarray:
 
 
 def flux_scale(q: np.ndarray, spec) -> np.ndarray:
-    """Size of the terms a right-hand side is a difference of: per field,
-    max over cells of sum over active d of |F_k,d(q)| / dx_d, with the
-    model's physical flux F (partial densities and alpha1 times u_d;
-    momentum rho u u_d + p delta; energy (rho E + p) u_d)."""
+    """Size of the terms a right-hand side is a difference of.  An HLLC flux
+    is the physical flux of one side plus a wave speed times a jump of the
+    state, so per field the terms are bounded by
+        max over cells of sum_d |F_k,d(q)| / dx_d  +  lambda * max |q_k|,
+    with the model's physical flux F (partial densities and alpha1 times u_d;
+    momentum rho u u_d + p delta; energy (rho E + p) u_d) and lambda =
+    max over cells of sum_d (|u_d| + c) / dx_d."""
     g = oracle.make_grid(spec)
     w = oracle.cons_to_prim(g, q).reshape(7, -1)
     qq = q.reshape(7, -1)
@@ -50,7 +53,9 @@ def flux_scale(q: np.ndarray, spec) -> np.ndarray:
         F[2 + d] = np.abs(qq[2 + d] * ud + p)
         F[5] = np.abs((qq[5] + p) * ud)
         tot += F / spec["dx"][d]
-    return _shared_momentum(tot.max(axis=1))
+    dt = oracle.cfl_dt(g, q)
+    lam = spec.get("cfl", 0.4) / dt if np.isfinite(dt) else 0.0
+    return _shared_momentum(tot.max(axis=1) + lam * np.abs(qq).max(axis=1))
 
 
 def rhs_rel_linf(x: np.ndarray, y: np.ndarray, q: np.ndarray, spec) -> np.ndarray:
