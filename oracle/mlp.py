@@ -1,0 +1,153 @@
+"""FP64 oracle for the learned WENO weights: features, MLP forward and
+backward, loss.
+
+TEST INFRASTRUCTURE ONLY (part of the oracle).
+
+What it computes (the learned-weights form; the paper's WENO5 is Sec. II-B,
+Shu 2006; the network is this project's addition):
+  features of a 5-cell stencil v0..v4 reconstructed at its right edge, with
+  the Jiang-Shu indicators beta_k and S = beta0 + beta1 + beta2 + eps:
+      x = (beta0/S, beta1/S, beta2/S, |beta0 - beta2|/S, D^2/(S + D^2)),
+      D = v0 - 4 v1 + 6 v2 - 4 v3 + v4;
+  network 5 -> 32 (GELU, tanh form) -> 32 (GELU) -> 3 logits z, added to the
+  Jiang-Shu log-weights: omega = softmax(log omega_JS + z) (a zero output
+  layer gives the Jiang-Shu weights exactly);
+  value = sum_k omega_k p_k with the three third-order candidates p_k;
+  loss  = mean((value' - target')^2) + lam * mean(sum_k (omega_k - omega_JS,k)^2),
+  where primes are stencil-normalised: (. - v2) / scale.
+Parameters, flat float vector of 1347: W1[32][5], b1[32], W2[32][32], b2[32],
+W3[3][32], b3[3].
+"""
+from __future__ import annotations
+
+import numpy as np
+
+H = 32
+N_PARAMS = H * 5 + H + H * H + H + 3 * H + 3  # 1347
+GELU_C = np.sqrt(2.0 / np.pi)
+GELU_A = 0.044715
+
+
+def unpack(theta):
+    theta = np.asarray(theta, dtype=np.float64)
+    assert theta.size == N_PARAMS
+    o = 0
+    out = {}
+    for name, shape in (("W1", (H, 5)), ("b1", (H,)), ("W2", (H, H)), ("b2", (H,)), ("W3", (3, H)), ("b3", (3,))):
+        n = int(np.prod(shape))
+        out[name] = theta[o:o + n].reshape(shape)
+        o += n
+    return out
+
+
+def pack(p) -> np.ndarray:
+    return np.concatenate([np.asarray(p[k], dtype=np.float64).ravel() for k in ("W1", "b1", "W2", "b2", "W3", "b3")])
+
+
+def betas(v):
+    """Jiang-Shu smoothness indicators, v: [..., 5]."""
+    v = np.asarray(v, dtype=np.float64)
+    a, b, c, d, e = (v[..., i] for i in range(5))
+    b0 = 13.0 / 12.0 * (a - 2 * b + c) ** 2 + 0.25 * (a - 4 * b + 3 * c) ** 2
+    b1 = 13.0 / 12.0 * (b - 2 * c + d) ** 2 + 0.25 * (b - d) ** 2
+    b2 = 13.0 / 12.0 * (c - 2 * d + e) ** 2 + 0.25 * (3 * c - 4 * d + e) ** 2
+    return np.stack([b0, b1, b2], axis=-1)
+
+
+def candidates_right(v):
+    """Third-order candidate values at the right edge of the middle cell."""
+    v = np.asarray(v, dtype=np.float64)
+    a, b, c, d, e = (v[..., i] for i in range(5))
+    return np.stack([(2 * a - 7 * b + 11 * c) / 6.0, (-b + 5 * c + 2 * d) / 6.0, (2 * c + 5 * d - e) / 6.0], axis=-1)
+
+
+def js_weights_right(v, eps=1e-6):
+    bt = betas(v)
+    alpha = np.array([0.1, 0.6, 0.3]) / (eps + bt) ** 2
+    return alpha / alpha.sum(axis=-1, keepdims=True)
+
+
+def features(v, eps=1e-6):
+    v = np.asarray(v, dtype=np.float64)
+    bt = betas(v)
+    S = bt.sum(axis=-1) + eps
+    D = v[..., 0] - 4 * v[..., 1] + 6 * v[..., 2] - 4 * v[..., 3] + v[..., 4]
+    return np.stack([bt[..., 0] / S, bt[..., 1] / S, bt[..., 2] / S, np.abs(bt[..., 0] - bt[..., 2]) / S,
+                     D * D / (S + D * D)], axis=-1)
+
+
+def gelu(x):
+    return 0.5 * x * (1.0 + np.tanh(GELU_C * (x + GELU_A * x ** 3)))
+
+
+def gelu_grad(x):
+    u = GELU_C * (x + GELU_A * x ** 3)
+    t = np.tanh(u)
+    return 0.5 * (1.0 + t) + 0.5 * x * (1.0 - t * t) * GELU_C * (1.0 + 3.0 * GELU_A * x * x)
+
+
+def forward(theta, X, OJS):
+    """omega [n, 3] and the intermediates; OJS: Jiang-Shu weights [n, 3]."""
+    p = unpack(theta)
+    A1 = X @ p["W1"].T + p["b1"]
+    H1 = gelu(A1)
+    A2 = H1 @ p["W2"].T + p["b2"]
+    H2 = gelu(A2)
+    Z = H2 @ p["W3"].T + p["b3"] + np.log(OJS)
+    Z = Z - Z.max(axis=1, keepdims=True)
+    E = np.exp(Z)
+    om = E / E.sum(axis=1, keepdims=True)
+    return om, (X, A1, H1, A2, H2)
+
+
+def loss(theta, X, C, T, OJS, lam):
+    """C: normalised candidates [n,3]; T: normalised targets [n]; OJS: JS weights [n,3]."""
+    om, _ = forward(theta, X, OJS)
+    r = (om * C).sum(axis=1) - T
+    return float(np.mean(r * r) + lam * np.mean(((om - OJS) ** 2).sum(axis=1)))
+
+
+def loss_grad(theta, X, C, T, OJS, lam):
+    """(loss, d loss / d theta) by reverse-mode differentiation."""
+    p = unpack(theta)
+    n = X.shape[0]
+    om, (X, A1, H1, A2, H2) = forward(theta, X, OJS)
+    r = (om * C).sum(axis=1) - T
+    L = float(np.mean(r * r) + lam * np.mean(((om - OJS) ** 2).sum(axis=1)))
+    dom = (2.0 / n) * r[:, None] * C + (2.0 * lam / n) * (om - OJS)
+    # softmax backward
+    dZ = om * (dom - (dom * om).sum(axis=1, keepdims=True))
+    g = {}
+    g["W3"] = dZ.T @ H2
+    g["b3"] = dZ.sum(axis=0)
+    dH2 = dZ @ p["W3"]
+    dA2 = dH2 * gelu_grad(A2)
+    g["W2"] = dA2.T @ H1
+    g["b2"] = dA2.sum(axis=0)
+    dH1 = dA2 @ p["W2"]
+    dA1 = dH1 * gelu_grad(A1)
+    g["W1"] = dA1.T @ X
+    g["b1"] = dA1.sum(axis=0)
+    return L, pack(g)
+
+
+def init_params(seed=0, out_scale=0.0):
+    """He-style hidden layers; output layer zero (omega = omega_JS) unless
+    out_scale > 0, which draws it with that standard deviation."""
+    rng = np.random.default_rng(seed)
+    p = {
+        "W1": rng.normal(0, np.sqrt(2.0 / 5), (H, 5)),
+        "b1": np.zeros(H),
+        "W2": rng.normal(0, np.sqrt(2.0 / H), (H, H)),
+        "b2": np.zeros(H),
+        "W3": rng.normal(0, out_scale, (3, H)) if out_scale > 0 else np.zeros((3, H)),
+        "b3": np.zeros(3),
+    }
+    return pack(p)
+
+
+def bf16_round(x):
+    """Round float64 values to bfloat16 (via float32, round to nearest even)."""
+    f = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    r = ((f + 0x7FFF + ((f >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
