@@ -114,8 +114,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--compare-steps", type=int, default=200,
-                    help="steps of the FP64 run whose time steps the FP32 form replays for its L1 error "
-                         "(negative: skip the FP32 form)")
+                    help="steps of the FP64 run whose time steps the FP32 and learned forms replay for their L1 "
+                         "error (negative: skip both forms)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-weights form")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device-to-device copy of 7 * n^3 float64 (known bytes), five times, "
                          "to scale rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -129,7 +130,8 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2409_10729_amd import MFX_FP32_MIXED, MFX_FP64, Solver
+    from paper_2409_10729_amd import MFX_FP32_MIXED, MFX_FP64, MFX_WENO5_JS, MFX_WENO5_LEARNED, Solver
+    from paper_2409_10729_amd import learned
     from paper_2409_10729_amd import workloads as wl
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -147,16 +149,22 @@ def main():
     N = args.n ** 3
     w_dev = torch.from_numpy(P["w"]).cuda()
 
-    def new_solver(precision):
-        s = Solver(P["spec"], precision=precision)
+    mlp_dev = None
+    if not args.no_learned and os.path.exists(learned.DEFAULT_PARAMS):
+        mlp_dev = torch.from_numpy(learned.load_params()).cuda()
+
+    def new_solver(precision, weights=MFX_WENO5_JS):
+        s = Solver(P["spec"], precision=precision, weights=weights)
+        if weights == MFX_WENO5_LEARNED:
+            s.set_mlp(mlp_dev)
         s.set_primitive(w_dev)
         return s
 
-    def time_form(precision, dt):
+    def time_form(precision, dt, weights=MFX_WENO5_JS):
         """Warm-up, then `steps` timed steps with HIP events on the solver's
         stream; per-kernel event times from the library.  dt <= 0 uses the
         device CFL step (FP64 headline run)."""
-        s = new_solver(precision)
+        s = new_solver(precision, weights)
         for _ in range(args.warmup):
             s.rk3_step(dt)
         torch.cuda.synchronize()
@@ -177,6 +185,24 @@ def main():
             raise RuntimeError(f"solver flagged a non-physical state: {st}")
         s.destroy()
         return ms_total, prof
+
+    def replay(precision, dts, weights=MFX_WENO5_JS):
+        """Final state (host, [7, N]) and fallback count after replaying dts."""
+        s = new_solver(precision, weights)
+        for dt in dts:
+            s.rk3_step(dt)
+        q = s.get_state().cpu().numpy().reshape(7, -1)
+        fb = s.stats()["fallback_faces"]
+        s.destroy()
+        return q, fb
+
+    def l1_vs(q, q64):
+        den = np.abs(q64).sum(axis=1)
+        den[2:5] = den[2:5].max()
+        l1 = (np.abs(q - q64).sum(axis=1) / den).tolist()
+        rho64 = q64[0] + q64[1]
+        rho_l1 = float(np.abs(q[0] + q[1] - rho64).sum() / np.abs(rho64).sum())
+        return [float(f"{x:.3e}") for x in l1], float(f"{rho_l1:.3e}")
 
     def kernel_table(prof, ms_total, rhs_bytes):
         per_dir = {}
@@ -224,42 +250,45 @@ def main():
     forms = {"fp64": {"ms_per_step": round(ms_step, 4), "grind": round(grind, 5), "kernels": kernels,
                       "step_alg_bytes_hbm_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
 
-    # ---- FP32 mixed form: timing, then accuracy against FP64 on replayed time steps
+    # ---- FP32 mixed and learned forms: accuracy against FP64 on replayed
+    # time steps, then timing at a fixed step
     if args.compare_steps >= 0:
-        print(f"[bench] accuracy: fp64 vs fp32 over {args.compare_steps} replayed steps", file=sys.stderr, flush=True)
+        print(f"[bench] accuracy: fp64 reference over {args.compare_steps} steps", file=sys.stderr, flush=True)
         s64 = new_solver(MFX_FP64)
         dts = [s64.rk3_step(sync=True) for _ in range(args.compare_steps)]
         q64 = s64.get_state().cpu().numpy().reshape(7, -1)
         s64.destroy()
         del s64
-        s32 = new_solver(MFX_FP32_MIXED)
-        for dt in dts:
-            s32.rk3_step(dt)
-        q32 = s32.get_state().cpu().numpy().reshape(7, -1)
-        s32.destroy()
-        del s32
-        den = np.abs(q64).sum(axis=1)
-        den[2:5] = den[2:5].max()
-        l1 = (np.abs(q32 - q64).sum(axis=1) / den).tolist()
-        rho64 = q64[0] + q64[1]
-        rho_l1 = float(np.abs(q32[0] + q32[1] - rho64).sum() / np.abs(rho64).sum())
         dt_fixed = dts[0] if dts else 1e-9
-        del q32, q64
-        print(f"[bench] fp32: timing {args.steps} steps", file=sys.stderr, flush=True)
-        ms32, prof32 = time_form(MFX_FP32_MIXED, dt_fixed)
-        ms32_step = ms32 / args.steps
-        k32, sb32 = kernel_table(prof32, ms32, 28)
-        forms["fp32_mixed"] = {
-            "ms_per_step": round(ms32_step, 4),
-            "grind": round(ms32_step * 1e6 / (N * 3), 5),
-            "speedup_vs_fp64": round(ms_step / ms32_step, 3),
-            "compare_steps": args.compare_steps,
-            "l1_rel_vs_fp64": [float(f"{x:.3e}") for x in l1],
-            "density_l1_rel_vs_fp64": float(f"{rho_l1:.3e}"),
-            "kernels": k32,
-        }
-        print(f"[bench] fp32: {ms32_step:.3f} ms/step (x{ms_step / ms32_step:.2f}), density L1 {rho_l1:.2e}",
-              file=sys.stderr, flush=True)
+        variants = [("fp32_mixed", MFX_WENO5_JS)]
+        if mlp_dev is not None:
+            variants.append(("learned", MFX_WENO5_LEARNED))
+        for name, weights in variants:
+            print(f"[bench] {name}: replaying {len(dts)} steps", file=sys.stderr, flush=True)
+            q, fb = replay(MFX_FP32_MIXED, dts, weights)
+            l1, rho_l1 = l1_vs(q, q64)
+            del q
+            print(f"[bench] {name}: timing {args.steps} steps", file=sys.stderr, flush=True)
+            ms_f, prof_f = time_form(MFX_FP32_MIXED, dt_fixed, weights)
+            msf_step = ms_f / args.steps
+            kf, _ = kernel_table(prof_f, ms_f, 28)
+            forms[name] = {
+                "ms_per_step": round(msf_step, 4),
+                "grind": round(msf_step * 1e6 / (N * 3), 5),
+                "speedup_vs_fp64": round(ms_step / msf_step, 3),
+                "compare_steps": args.compare_steps,
+                "l1_rel_vs_fp64": l1,
+                "density_l1_rel_vs_fp64": rho_l1,
+                "kernels": kf,
+            }
+            if weights == MFX_WENO5_LEARNED:
+                edges = 2 * N * sum(1 for k in P["spec"]["n"] if k > 1) * 3 * len(dts)
+                forms[name]["fallback_edges"] = fb
+                forms[name]["fallback_fraction"] = float(f"{fb / max(edges, 1):.3e}")
+                forms[name]["network"] = os.path.relpath(learned.DEFAULT_PARAMS, os.path.dirname(__file__))
+            print(f"[bench] {name}: {msf_step:.3f} ms/step (x{ms_step / msf_step:.2f}), density L1 {rho_l1:.2e}",
+                  file=sys.stderr, flush=True)
+        del q64
     del w_dev
 
     out = {

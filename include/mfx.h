@@ -131,15 +131,96 @@ int mfx_rhs(mfx_ctx* ctx, double* rhs_dev_out);
  * the new state is computed inside the step for the next call. */
 int mfx_rk3_step(mfx_ctx* ctx, double dt, double* dt_used_host);
 
-/* Learned-weight parameters: n_params float32 values on the device, laid
- * out W1[32][5], b1[32], W2[32][32], b2[32], W3[3][32], b3[3] (1347 values).
- * Copied and packed to bfloat16 for inference. */
+/* Learned-weight parameters: n_params (= 1347) float32 values on the
+ * device, laid out W1[32][5], b1[32], W2[32][32], b2[32], W3[3][32], b3[3].
+ * Copied into the context and packed to bfloat16 for the matrix cores.
+ * Needed before the first step of a context created with
+ * MFX_WENO5_LEARNED (which runs in the MFX_FP32_MIXED precision form).  In
+ * that form every cell's two edge states come from the network's weights,
+ * and an edge whose weights are not finite or whose state is not admissible
+ * (negative partial density, alpha1 outside [0,1], non-positive squared
+ * sound speed) falls back to Jiang-Shu for all seven variables; mfx_stats
+ * counts those edges. */
 int mfx_set_mlp(mfx_ctx* ctx, const float* params_dev, int32_t n_params);
 
 /* Synchronise and report simulated time, step count, faces that fell back
  * to Jiang-Shu weights (learned mode), and the device status word.  Any
  * pointer may be NULL.  Returns MFX_ESTATE if the status word is non-zero. */
 int mfx_stats(mfx_ctx* ctx, double* t, int64_t* step, int64_t* fallback_faces, uint32_t* status);
+
+/* ------------------------------------------------------------------------
+ * Learned WENO weights: training and stand-alone inference.
+ *
+ * The network maps five features of a 5-cell stencil w0..w4 reconstructed
+ * at its right edge -- with the Jiang-Shu indicators beta_k (Shu 2006, the
+ * WENO5 of Sec. II-B) and S = beta0 + beta1 + beta2 + eps:
+ *   (beta0/S, beta1/S, beta2/S, |beta0 - beta2|/S, D^2/(S + D^2)),
+ *   D = w0 - 4 w1 + 6 w2 - 4 w3 + w4
+ * -- through 5 -> 32 (GELU, tanh form) -> 32 (GELU) -> 3 logits z, which
+ * correct the Jiang-Shu weights of the third-order candidates:
+ *   omega = softmax(ln omega_JS + z)
+ * (a zero output layer reproduces Jiang-Shu exactly).  Parameters: 1347
+ * float32, layout of mfx_set_mlp.  A left edge is the right edge of the
+ * mirrored stencil.  These calls are not bound to a context; all pointers
+ * are device pointers, work is enqueued on `stream` (hipStream_t as void*,
+ * NULL = default stream), and errors are returned as codes with the message
+ * in mfx_mlp_last_error().
+ * ---------------------------------------------------------------------- */
+#define MFX_MLP_PARAMS 1347
+
+/* Training samples from a 1D state q[7][nx] (desc->n = {nx,1,1}; its x
+ * boundary conditions give the ghost cells).  For every cell i and variable
+ * v two samples are written: sample (0*7+v)*nx+i = primitives w[v] of cells
+ * i-2..i+2 with target face_prim[v][i+1]; sample (1*7+v)*nx+i = the
+ * mirrored stencil i+2..i-2 with target face_prim[v][i].  face_prim holds
+ * reference primitive values at the nx+1 faces, [7][nx+1].  Outputs:
+ * stencil_out[14*nx][5], target_out[14*nx] (float64). */
+int mfx_mlp_sample_stencils(const mfx_grid_desc* desc, const double* q_dev, const double* face_prim_dev,
+                            double* stencil_out, double* target_out, void* stream);
+
+/* Reference face values for training targets from a 1D state on a grid
+ * `refine` times finer than the sampled one (same domain and boundary
+ * conditions): coarse face i lies on fine face refine*i, whose primitive
+ * value is the mean of the two fine cells beside it.  face_prim_out[7][nc+1]
+ * with nc = fine nx / refine. */
+int mfx_mlp_face_targets(const mfx_grid_desc* fine_desc, const double* q_fine_dev, int32_t refine, double* face_prim_out,
+                         void* stream);
+
+/* Features (float32 [n][5]), Jiang-Shu weights (omega_js [n][3]) and the
+ * stencil-normalised candidates cand[n][3] and target tnorm[n] of n
+ * samples: (x - w2) / (max - min of the stencil), zero for a flat stencil. */
+int mfx_mlp_features(const double* stencils, const double* targets, int64_t n, double eps, float* feat, float* cand,
+                     float* tnorm, float* omega_js, void* stream);
+
+/* Bytes of the packed bfloat16 matrix-core operands (mfx_mlp_pack). */
+size_t mfx_mlp_packed_bytes(void);
+/* Pack float32 parameters into the per-lane bfloat16 operand layout. */
+int mfx_mlp_pack(const float* params, void* packed, void* stream);
+
+/* Network weights omega[n][3] for features feat[n][5] and Jiang-Shu
+ * weights omega_js[n][3]: pass params (float32 arithmetic) or packed
+ * (bfloat16 matrix cores, float32 accumulation, as inside the solver), not
+ * both. */
+int mfx_mlp_forward(const float* params, const void* packed, const float* feat, const float* omega_js, int64_t n,
+                    float* omega, void* stream);
+
+/* Loss and gradient of one minibatch, float32, deterministic (per-block
+ * sums in a fixed order, then a fixed-order sum over blocks):
+ *   L = mean_i (sum_k omega_ik cand_ik - tnorm_i)^2
+ *     + lambda * mean_i sum_k (omega_ik - omega_js_ik)^2.
+ * grad_out[1347]; loss_out (device float, may be NULL); ws of at least
+ * mfx_mlp_grad_workspace(n) bytes. */
+size_t mfx_mlp_grad_workspace(int64_t n);
+int mfx_mlp_loss_grad(const float* params, const float* feat, const float* cand, const float* tnorm,
+                      const float* omega_js, int64_t n, float lambda, void* ws, size_t ws_bytes, float* grad_out,
+                      float* loss_out, void* stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) of the parameters with
+ * first/second moment buffers m, v (1347 each); step counts from 1. */
+int mfx_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t step, float lr, void* stream);
+
+/* Message of the last failed learned-weights call of this thread. */
+const char* mfx_mlp_last_error(void);
 
 /* Kernel timing for measurement.  mfx_profile(ctx, 1) clears the counters
  * and brackets every sweep launch with HIP events on the context's stream

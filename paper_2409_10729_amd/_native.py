@@ -20,8 +20,11 @@ MFX_WENO5_JS, MFX_WENO5_LEARNED = 0, 1
 EXPORTED = (
     "mfx_workspace_bytes", "mfx_init_grid", "mfx_set_state", "mfx_set_primitive", "mfx_get_state",
     "mfx_rhs", "mfx_rk3_step", "mfx_set_mlp", "mfx_stats", "mfx_profile", "mfx_profile_read",
-    "mfx_destroy", "mfx_last_error",
+    "mfx_destroy", "mfx_last_error", "mfx_mlp_sample_stencils", "mfx_mlp_face_targets", "mfx_mlp_features", "mfx_mlp_packed_bytes",
+    "mfx_mlp_pack", "mfx_mlp_forward", "mfx_mlp_grad_workspace", "mfx_mlp_loss_grad", "mfx_mlp_adam",
+    "mfx_mlp_last_error",
 )
+MLP_PARAMS = 1347
 PROF_KINDS = 30
 
 
@@ -78,6 +81,27 @@ def lib():
         L.mfx_profile.restype = ctypes.c_int
         L.mfx_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         L.mfx_profile_read.restype = ctypes.c_int
+        i64 = ctypes.c_int64
+        L.mfx_mlp_sample_stencils.argtypes = [dp, vp, vp, vp, vp, vp]
+        L.mfx_mlp_sample_stencils.restype = ctypes.c_int
+        L.mfx_mlp_face_targets.argtypes = [dp, vp, ctypes.c_int32, vp, vp]
+        L.mfx_mlp_face_targets.restype = ctypes.c_int
+        L.mfx_mlp_features.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp, vp, vp]
+        L.mfx_mlp_features.restype = ctypes.c_int
+        L.mfx_mlp_packed_bytes.argtypes = []
+        L.mfx_mlp_packed_bytes.restype = ctypes.c_size_t
+        L.mfx_mlp_pack.argtypes = [vp, vp, vp]
+        L.mfx_mlp_pack.restype = ctypes.c_int
+        L.mfx_mlp_forward.argtypes = [vp, vp, vp, vp, i64, vp, vp]
+        L.mfx_mlp_forward.restype = ctypes.c_int
+        L.mfx_mlp_grad_workspace.argtypes = [i64]
+        L.mfx_mlp_grad_workspace.restype = ctypes.c_size_t
+        L.mfx_mlp_loss_grad.argtypes = [vp, vp, vp, vp, vp, i64, ctypes.c_float, vp, ctypes.c_size_t, vp, vp, vp]
+        L.mfx_mlp_loss_grad.restype = ctypes.c_int
+        L.mfx_mlp_adam.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp]
+        L.mfx_mlp_adam.restype = ctypes.c_int
+        L.mfx_mlp_last_error.argtypes = []
+        L.mfx_mlp_last_error.restype = ctypes.c_char_p
         L.mfx_destroy.argtypes = [vp]
         L.mfx_destroy.restype = None
         L.mfx_last_error.argtypes = [vp]
@@ -101,6 +125,12 @@ def make_desc(spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS
     d.precision = int(precision)
     d.weights = int(weights)
     return d
+
+
+def check_mlp(rc: int):
+    if rc != MFX_OK:
+        msg = lib().mfx_mlp_last_error()
+        raise MfxError(rc, msg.decode() if msg else "")
 
 
 def check(rc: int, ctx=None):

@@ -18,6 +18,10 @@
 #include "sweep.h"
 #include "xrow.h"
 
+namespace mfx {
+int mlp_pack_on_stream(const float* params, void* packed, hipStream_t st);
+}
+
 using namespace mfx;
 
 namespace {
@@ -48,7 +52,7 @@ Overrides read_overrides()
 }
 
 struct Layout {
-    size_t q, q1, q2, r, scal, partial, bface, total;
+    size_t q, q1, q2, r, scal, partial, bface, mlp, mlp_params, total;
     long long n_partial;
 };
 
@@ -133,6 +137,10 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     off += align_up(sizeof(double) * (size_t)np);
     L.bface = off;
     off += align_up(elem * BFACE * 2 * (size_t)nrows);
+    L.mlp = off;
+    off += align_up(sizeof(MlpLane) * 64);
+    L.mlp_params = off;
+    off += align_up(sizeof(float) * MLP_PARAMS);
     L.total = off;
     L.n_partial = np;
     return L;
@@ -281,6 +289,10 @@ struct mfx_ctx {
     double *q, *q1, *q2, *scal, *partial;
     void *r, *bface;  // compute-type buffers
     size_t elem;      // sizeof the compute type
+    MlpLane* mlp;                 // packed network operands (learned weights)
+    float* mlp_params;            // float32 copy of the network
+    unsigned long long* fallback; // edges that fell back to Jiang-Shu
+    bool has_mlp;
     unsigned* status;
     int dirs[3];
     int ndirs;
@@ -359,11 +371,13 @@ struct LaunchArgs {
     double* partial;
     unsigned* status;
     void* bface;  // boundary faces of the x row sweep (compute type)
+    const MlpLane* mlp;       // packed network (learned weights only)
+    unsigned long long* fb;   // fallback counter (learned weights only)
 };
 
 // The x row sweep reads the boundary faces that boundary_faces_x leaves in
 // `bface` (launched just before it on the same stream).
-template <int DIR, typename T, bool FIRST, int MODE>
+template <int DIR, typename T, bool FIRST, int MODE, bool L>
 void launch_one(const LaunchArgs& a)
 {
     const SweepGeom& sg = *a.sg;
@@ -372,41 +386,41 @@ void launch_one(const LaunchArgs& a)
         if (sg.xrows) {
             T* bf = static_cast<T*>(a.bface);
             const long long faces = 2LL * a.g->n[1] * a.g->n[2];
-            boundary_faces_x<T><<<(unsigned)((faces + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf);
-            sweep_x_rows<T, FIRST, MODE><<<sg.grid, sg.block, sg.lds, a.st>>>(
-                *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.partial, a.status);
+            boundary_faces_x<T, L><<<(unsigned)((faces + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf, a.mlp, a.fb);
+            sweep_x_rows<T, FIRST, MODE, L><<<sg.grid, sg.block, sg.lds, a.st>>>(
+                *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.partial, a.status, a.mlp, a.fb);
         } else {
-            sweep_x_march<T, FIRST, MODE><<<sg.grid, XROWS, 0, a.st>>>(*a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev,
-                                                                      a.dt_arg, a.partial, a.status);
+            sweep_x_march<T, FIRST, MODE, L><<<sg.grid, XROWS, 0, a.st>>>(
+                *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.partial, a.status, a.mlp, a.fb);
         }
     } else {
-        sweep_yz<DIR, T, FIRST, MODE><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(*a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev,
-                                                                        a.dt_arg, a.partial, a.status);
+        sweep_yz<DIR, T, FIRST, MODE, L><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(
+            *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.partial, a.status, a.mlp, a.fb);
     }
 }
 
-template <int DIR, typename T, bool FIRST>
+template <int DIR, typename T, bool FIRST, bool L>
 void launch_mode(int mode, const LaunchArgs& a)
 {
     switch (mode) {
-    case OUT_ACCUM: launch_one<DIR, T, FIRST, OUT_ACCUM>(a); break;
-    case OUT_RHS: launch_one<DIR, T, FIRST, OUT_RHS>(a); break;
-    case OUT_STAGE1: launch_one<DIR, T, FIRST, OUT_STAGE1>(a); break;
-    case OUT_STAGE2: launch_one<DIR, T, FIRST, OUT_STAGE2>(a); break;
-    default: launch_one<DIR, T, FIRST, OUT_STAGE3>(a); break;
+    case OUT_ACCUM: launch_one<DIR, T, FIRST, OUT_ACCUM, L>(a); break;
+    case OUT_RHS: launch_one<DIR, T, FIRST, OUT_RHS, L>(a); break;
+    case OUT_STAGE1: launch_one<DIR, T, FIRST, OUT_STAGE1, L>(a); break;
+    case OUT_STAGE2: launch_one<DIR, T, FIRST, OUT_STAGE2, L>(a); break;
+    default: launch_one<DIR, T, FIRST, OUT_STAGE3, L>(a); break;
     }
 }
 
 // The x sweep, when active, is always the first direction of a pass.
-template <typename T>
+template <typename T, bool L>
 void launch_dispatch(int d, bool first, int mode, const LaunchArgs& a)
 {
     if (d == 0)
-        launch_mode<0, T, true>(mode, a);
+        launch_mode<0, T, true, L>(mode, a);
     else if (d == 1)
-        first ? launch_mode<1, T, true>(mode, a) : launch_mode<1, T, false>(mode, a);
+        first ? launch_mode<1, T, true, L>(mode, a) : launch_mode<1, T, false, L>(mode, a);
     else
-        first ? launch_mode<2, T, true>(mode, a) : launch_mode<2, T, false>(mode, a);
+        first ? launch_mode<2, T, true, L>(mode, a) : launch_mode<2, T, false, L>(mode, a);
 }
 
 int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* out, int first, int mode,
@@ -422,11 +436,14 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
         if (!pend.a || !pend.b) return fail(c, MFX_EHIP, "hipEventCreate failed");
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
-    const LaunchArgs la{&sg, c->stream, &c->g, qs, qn, c->r, out, dt_dev, dt_arg, c->partial, c->status, c->bface};
-    if (c->desc.precision == MFX_FP32_MIXED)
-        launch_dispatch<float>(d, first != 0, mode, la);
+    const LaunchArgs la{&sg,       c->stream, &c->g,     qs,       qn,       c->r,     out,     dt_dev,
+                        dt_arg,    c->partial, c->status, c->bface, c->mlp, c->fallback};
+    if (c->desc.weights == MFX_WENO5_LEARNED)
+        launch_dispatch<float, true>(d, first != 0, mode, la);
+    else if (c->desc.precision == MFX_FP32_MIXED)
+        launch_dispatch<float, false>(d, first != 0, mode, la);
     else
-        launch_dispatch<double>(d, first != 0, mode, la);
+        launch_dispatch<double, false>(d, first != 0, mode, la);
     int rc = launch_check(c, "sweep kernel");
     if (rc) return rc;
     if (c->profiling) {
@@ -491,8 +508,8 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     *out = nullptr;
     std::string why;
     if (!validate(desc, why)) return fail(nullptr, MFX_EINVAL, why);
-    if (desc->weights == MFX_WENO5_LEARNED)
-        return fail(nullptr, MFX_EINVAL, "learned weights are not available in this build");
+    if (desc->weights == MFX_WENO5_LEARNED && desc->precision != MFX_FP32_MIXED)
+        return fail(nullptr, MFX_EINVAL, "learned weights run in the MFX_FP32_MIXED precision form");
     if (!ws_dev) return fail(nullptr, MFX_EINVAL, "workspace pointer is NULL");
     if (reinterpret_cast<uintptr_t>(ws_dev) % ALIGN != 0)
         return fail(nullptr, MFX_EINVAL, "workspace must be 256-byte aligned");
@@ -526,6 +543,10 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     c->status = reinterpret_cast<unsigned*>(c->ws + L.scal + 4 * sizeof(double));
     c->partial = reinterpret_cast<double*>(c->ws + L.partial);
     c->bface = c->ws + L.bface;
+    c->mlp = reinterpret_cast<MlpLane*>(c->ws + L.mlp);
+    c->mlp_params = reinterpret_cast<float*>(c->ws + L.mlp_params);
+    c->fallback = reinterpret_cast<unsigned long long*>(c->ws + L.scal + 40);
+    c->has_mlp = false;
 
     Grid& g = c->g;
     g.N = (long long)desc->n[0] * desc->n[1] * desc->n[2];
@@ -608,9 +629,19 @@ int mfx_get_state(mfx_ctx* c, double* q_dev_out)
     return MFX_OK;
 }
 
+namespace {
+int need_mlp(mfx_ctx* c)
+{
+    if (c->desc.weights == MFX_WENO5_LEARNED && !c->has_mlp)
+        return fail(c, MFX_EINVAL, "learned weights selected but no network set (mfx_set_mlp)");
+    return MFX_OK;
+}
+}  // namespace
+
 int mfx_rhs(mfx_ctx* c, double* rhs_out)
 {
     if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
+    if (int rc = need_mlp(c)) return rc;
     if (!rhs_out) return fail(c, MFX_EINVAL, "rhs_dev_out is NULL");
     if (!c->has_state) return fail(c, MFX_EINVAL, "no state set");
     const char* o = reinterpret_cast<const char*>(rhs_out);
@@ -624,6 +655,7 @@ int mfx_rhs(mfx_ctx* c, double* rhs_out)
 int mfx_rk3_step(mfx_ctx* c, double dt, double* dt_used_host)
 {
     if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
+    if (int rc = need_mlp(c)) return rc;
     if (!c->has_state) return fail(c, MFX_EINVAL, "no state set");
     if (!std::isfinite(dt)) return fail(c, MFX_EINVAL, "dt is not finite");
     if (!(dt > 0.0) && !(c->g.active[0] || c->g.active[1] || c->g.active[2]))
@@ -659,9 +691,16 @@ int mfx_rk3_step(mfx_ctx* c, double dt, double* dt_used_host)
 int mfx_set_mlp(mfx_ctx* c, const float* params_dev, int32_t n_params)
 {
     if (!c) return fail(nullptr, MFX_EINVAL, "ctx is NULL");
-    (void)params_dev;
-    (void)n_params;
-    return fail(c, MFX_EINVAL, "learned weights are not available in this build");
+    if (!params_dev) return fail(c, MFX_EINVAL, "params_dev is NULL");
+    if (n_params != MLP_PARAMS) return fail(c, MFX_EINVAL, "the network has " + std::to_string(MLP_PARAMS) + " parameters");
+    int rc = set_device(c);
+    if (rc) return rc;
+    HIP_TRY(c, hipMemcpyAsync(c->mlp_params, params_dev, sizeof(float) * MLP_PARAMS, hipMemcpyDeviceToDevice,
+                              c->stream));
+    rc = mlp_pack_on_stream(c->mlp_params, c->mlp, c->stream);
+    if (rc) return fail(c, rc, "packing the network failed");
+    c->has_mlp = true;
+    return MFX_OK;
 }
 
 int mfx_stats(mfx_ctx* c, double* t, int64_t* step, int64_t* fallback_faces, uint32_t* status)
@@ -671,12 +710,14 @@ int mfx_stats(mfx_ctx* c, double* t, int64_t* step, int64_t* fallback_faces, uin
     if (rc) return rc;
     double sc[4];
     unsigned st = 0;
+    unsigned long long fb = 0;
     HIP_TRY(c, hipMemcpyAsync(sc, c->scal, sizeof(sc), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipMemcpyAsync(&st, c->status, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(&fb, c->fallback, sizeof(fb), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     if (t) *t = sc[1];
     if (step) *step = (int64_t)sc[2];
-    if (fallback_faces) *fallback_faces = 0;
+    if (fallback_faces) *fallback_faces = (int64_t)fb;
     if (status) *status = st;
     if (st) return fail(c, MFX_ESTATE, "non-physical state flagged (status " + std::to_string(st) + ")");
     return MFX_OK;

@@ -19,6 +19,7 @@
 // boundary branches are wave-uniform.
 #pragma once
 
+#include "learned.h"
 #include "physics.h"
 
 namespace mfx {
@@ -199,12 +200,90 @@ struct GlobalSink {
     }
 };
 
+// Reconstruction of one cell's two edge states (all seven primitives) from
+// its 5-cell window W[k][v] = w_v of cell c-2+k.
+template <typename T>
+struct ReconJS {
+    __device__ __forceinline__ void cell(const T W[5][NV], T eps, T lft[NV], T rgt[NV])
+    {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) weno5<T>(W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, lft[v], rgt[v]);
+    }
+    __device__ __forceinline__ void flush(unsigned long long*) {}
+};
+
+// Learned weights (float32 form); the whole wave must call cell() together.
+// An edge state whose weights are not finite or that is not admissible is
+// replaced by the Jiang-Shu edge state of all seven variables.
+struct ReconLearned {
+    MlpLane m;
+    LearnedLds* lds;  // this wave's slot
+    Mix<float> mix;
+    bool valid;  // this lane owns a real cell (only those are counted)
+    unsigned fallbacks;
+    __device__ __forceinline__ void cell(const float W[5][NV], float eps, float lft[NV], float rgt[NV])
+    {
+        float lj[NV], rj[NV], ll[NV], rl[NV];
+        bool fin = true;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            weno5<float>(W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, lj[v], rj[v]);
+            bool f;
+            weno5_learned(m, lds, W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, ll[v], rl[v], f);
+            fin = fin && f;
+        }
+        const bool okR = fin && admissible(mix, rl);
+        const bool okL = fin && admissible(mix, ll);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            rgt[v] = okR ? rl[v] : rj[v];
+            lft[v] = okL ? ll[v] : lj[v];
+        }
+        if (valid) fallbacks += (okR ? 0u : 1u) + (okL ? 0u : 1u);
+    }
+    // wave sum of the fallback counts, one atomic per wave
+    __device__ __forceinline__ void flush(unsigned long long* counter)
+    {
+        unsigned long long c = fallbacks;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+        if ((threadIdx.x & 63) == 0 && c) atomicAdd(counter, c);
+    }
+};
+
+constexpr int LEARNED_MAX_WAVES = 8;  // largest block of a learned sweep: 512 threads
+
+template <typename T, bool LEARNED>
+struct ReconOf {
+    using type = ReconJS<T>;
+};
+template <>
+struct ReconOf<float, true> {
+    using type = ReconLearned;
+};
+
+template <typename T, bool LEARNED>
+__device__ __forceinline__ typename ReconOf<T, LEARNED>::type make_recon(const Grid& g, const MlpLane* mlp, bool valid)
+{
+    if constexpr (LEARNED) {
+        // one 4 KB slot per wave; blocks have at most XROW_WAVES waves
+        __shared__ LearnedLds slots[LEARNED_MAX_WAVES];
+        return ReconLearned{mlp[threadIdx.x & 63], &slots[threadIdx.x >> 6],
+                            Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u};
+    } else {
+        (void)g;
+        (void)mlp;
+        (void)valid;
+        return ReconJS<T>{};
+    }
+}
+
 // The marching loop over the segment [c0, c1).  Src::load(pos, q) returns
 // the conserved state of cell `pos` along the sweep (boundary map applied);
 // it is called for positions c0-3, c0-2, ..., c1+2 in that order, and
 // Sink::put for cells c0..c1-1 in order, the same sequence on every lane.
-template <int DIR, typename T, class Src, class Sink>
-__device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, int c0, int c1)
+template <int DIR, typename T, class Src, class Sink, class Recon>
+__device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon& recon, int c0, int c1)
 {
     const T idx = (T)g.inv_dx[DIR];
     const T eps = (T)g.eps;
@@ -230,8 +309,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, int c
         if (c < c1) src.load(c + 3, qnext);
 
         T lft[NV], rgt[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) weno5<T>(W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, lft[v], rgt[v]);
+        recon.cell(W, eps, lft, rgt);
 
         if (c >= c0) {
             T F[NV], uf;
@@ -280,11 +358,12 @@ struct GlobalSrc {
 // qn and out alias in the third stage (the new state overwrites q in place;
 // each cell's q is read only by the thread that then writes it), so neither
 // is declared __restrict__.
-template <int DIR, typename T, bool FIRST, int MODE>
+template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED>
 __global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
                                                    T* __restrict__ racc, double* out, int seg,
                                                    const double* __restrict__ dt_dev, double dt_arg,
-                                                   double* __restrict__ partial, unsigned* __restrict__ status)
+                                                   double* __restrict__ partial, unsigned* __restrict__ status,
+                                                   const MlpLane* __restrict__ mlp, unsigned long long* fb)
 {
     constexpr int BLOCK = 256;
     static_assert(DIR == 1 || DIR == 2, "y or z sweep");
@@ -301,7 +380,9 @@ __global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restr
     GlobalSrc src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
     GlobalSink<T, FIRST, MODE> sink{OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR],
                                     valid, 0.0, 0u};
-    march<DIR, T>(g, src, sink, c0, c1);
+    auto recon = make_recon<T, LEARNED>(g, mlp, valid);
+    march<DIR, T>(g, src, sink, recon, c0, c1);
+    recon.flush(fb);
 
     if constexpr (MODE == OUT_STAGE3) {
         if (sink.bad) atomicOr(status, sink.bad);
@@ -386,11 +467,12 @@ struct LdsSink {
     }
 };
 
-template <typename T, bool FIRST, int MODE>
+template <typename T, bool FIRST, int MODE, bool LEARNED>
 __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* __restrict__ qs, const double* qn,
                                                           T* __restrict__ racc, double* out, int seg,
                                                           const double* __restrict__ dt_dev, double dt_arg,
-                                                          double* __restrict__ partial, unsigned* __restrict__ status)
+                                                          double* __restrict__ partial, unsigned* __restrict__ status,
+                                                          const MlpLane* __restrict__ mlp, unsigned long long* fb)
 {
     __shared__ double ibuf[XCHUNK][NV][XROWS];
     __shared__ T obuf[XCHUNK][NV + 1][XROWS];
@@ -403,7 +485,9 @@ __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* 
     LdsSrc src{ibuf, qs, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
     LdsSink<T, FIRST, MODE> sink{obuf, OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx,
                                  c0, c1, 0.0, 0u};
-    march<0, T>(g, src, sink, c0, c1);
+    auto recon = make_recon<T, LEARNED>(g, mlp, row0 + threadIdx.x < nrows);
+    march<0, T>(g, src, sink, recon, c0, c1);
+    recon.flush(fb);
 
     if constexpr (MODE == OUT_STAGE3) {
         if (sink.bad) atomicOr(status, sink.bad);

@@ -23,12 +23,14 @@ constexpr int BFACE = NV + 1;       // flux components + face velocity
 // Boundary faces of every row: thread t -> (row t/2, side t%2); side 0 is
 // the face between ghost cell -1 and cell 0, side 1 between cell nx-1 and
 // ghost cell nx.  Output bface[(row*2 + side) * BFACE + k].
-template <typename T>
-__global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __restrict__ qs, T* __restrict__ bface)
+template <typename T, bool LEARNED>
+__global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __restrict__ qs, T* __restrict__ bface,
+                                                        const MlpLane* __restrict__ mlp, unsigned long long* fb)
 {
     const long long nrows = (long long)g.n[1] * g.n[2];
-    const long long t = (long long)blockIdx.x * 256 + threadIdx.x;
-    if (t >= 2 * nrows) return;
+    const long long t_raw = (long long)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = t_raw < 2 * nrows;  // every lane computes (the learned weights need whole waves)
+    const long long t = valid ? t_raw : 2 * nrows - 1;
     const long long row = t >> 1;
     const int side = (int)(t & 1);
     const int nx = g.n[0];
@@ -45,18 +47,20 @@ __global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __
         for (int v = 0; v < NV; ++v) q[v] = qs[v * g.N + off];
         prim_of<T>(mixd, q, w[k]);
     }
-    T wl[NV], wr[NV], dummy;
-#pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        weno5<T>(w[0][v], w[1][v], w[2][v], w[3][v], w[4][v], eps, dummy, wl[v]);  // right edge of first+2
-        weno5<T>(w[1][v], w[2][v], w[3][v], w[4][v], w[5][v], eps, wr[v], dummy);  // left edge of first+3
-    }
+    // right edge of cell first+2 (window w[0..4]) and left edge of cell first+3 (w[1..5])
+    auto recon = make_recon<T, LEARNED>(g, mlp, valid);
+    T wl[NV], wr[NV], dummy[NV];
+    recon.cell(w, eps, dummy, wl);
+    recon.cell(w + 1, eps, wr, dummy);
+    recon.flush(fb);
     T F[NV], uf;
     hllc<0, T>(mix, wl, wr, F, uf);
-    T* o = bface + t * BFACE;
+    if (valid) {
+        T* o = bface + t * BFACE;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) o[v] = F[v];
-    o[NV] = uf;
+        for (int v = 0; v < NV; ++v) o[v] = F[v];
+        o[NV] = uf;
+    }
 }
 
 // LDS bytes of the row kernel: primitives P[NV][nx+4] (two ghost slots on
@@ -69,13 +73,14 @@ inline size_t xrow_lds_bytes(int nx, size_t elem)
 }
 
 // Row kernel.
-template <typename T, bool FIRST, int MODE>
+template <typename T, bool FIRST, int MODE, bool LEARNED>
 __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const double* __restrict__ qs, const double* qn,
                                                              T* __restrict__ racc, double* out, int rows_per_block,
                                                              const T* __restrict__ bface,
                                                              const double* __restrict__ dt_dev, double dt_arg,
                                                              double* __restrict__ partial,
-                                                             unsigned* __restrict__ status)
+                                                             unsigned* __restrict__ status,
+                                                             const MlpLane* __restrict__ mlp, unsigned long long* fb)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
     T* lds = reinterpret_cast<T*>(lds_raw);
@@ -104,6 +109,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
 
     double smax = 0.0;
     unsigned bad = 0;
+    auto recon = make_recon<T, LEARNED>(g, mlp, has);
     double qc[NV];
     if (r0 < r1) {
 #pragma unroll
@@ -131,13 +137,15 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
             for (int v = 0; v < NV; ++v) qc[v] = qs[v * g.N + (row + 1) * nx + xc];
         }
         // 2. reconstruct own cell: left edge to LDS, right edge kept
-        T rgt[NV];
+        T rgt[NV], lft[NV], Wc[5][NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const T* p = P + v * np + xc;
-            T lft;
-            weno5<T>(p[0], p[1], p[2], p[3], p[4], eps, lft, rgt[v]);
-            if (has) L[v * nx + x] = lft;
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int k = 0; k < 5; ++k) Wc[k][v] = P[v * np + xc + k];
+        recon.cell(Wc, eps, lft, rgt);
+        if (has) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) L[v * nx + x] = lft[v];
         }
         const T a1 = w[6];
         __syncthreads();
@@ -179,6 +187,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
             smax = fmax(smax, emit_cell<T, FIRST, MODE>(g, o, row * nx + x, fd, src, bad));
         }
     }
+    recon.flush(fb);
     if constexpr (MODE == OUT_STAGE3) {
         if (bad) atomicOr(status, bad);
         block_max_dyn(smax, partial + blockIdx.x);

@@ -19,6 +19,8 @@ shock-bubble-cloud runs; these are single-GPU blocks of the same physics):
   bubble_cloud    3D Mach-1.5 water shock on several air bubbles
   droplet_cloud   3D Mach-2 air shock on many log-uniform droplets
   random_smooth   small random valid states for RHS parity
+  advected_slab, shock_tube_family
+                  1D families for training and evaluating the learned weights
 """
 from __future__ import annotations
 
@@ -100,6 +102,52 @@ def advected_bubble(n=128, seed=0, velocity=(1.0, 0.5, 0.25), p0=1.0e5):
     a1 = ALPHA_EPS + (1.0 - 2.0 * ALPHA_EPS) * 0.5 * (1.0 + np.tanh((r - R) / width))
     w = _pack(a1, 1000.0, 1.2, velocity[0], velocity[1], velocity[2], p0)
     return {"name": "advected_bubble", "spec": s, "w": w, "meta": {"R": R, "centre": c.tolist()}}
+
+
+def advected_slab(n=256, seed=0, u_range=(100.0, 400.0), p0=1.0e5):
+    """1D periodic water slab in air (centre U(0.3,0.7), half-width
+    U(0.1,0.2), tanh interfaces over 1.5 cells) moving at a uniform speed
+    U(u_range).  Returns the problem and `face_prims(t)`: the translated
+    profile evaluated at the n+1 faces at time t, [7][n+1] (the exact
+    solution of pure advection, used as training and error reference)."""
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.3, 0.7)
+    R = rng.uniform(0.1, 0.2)
+    u = rng.uniform(*u_range)
+    width = 1.5 / n
+    s = spec((n, 1, 1), ((PERIODIC, PERIODIC),) * 3)
+
+    def profile(x):
+        d = x - c
+        d = d - np.round(d)
+        return ALPHA_EPS + (1.0 - 2.0 * ALPHA_EPS) * 0.5 * (1.0 - np.tanh((np.abs(d) - R) / width))
+
+    x = (np.arange(n) + 0.5) / n
+    a1 = profile(x)
+    w = _pack(a1, 1000.0, 1.2, u, 0.0, 0.0, p0).reshape(7, 1, 1, n)
+
+    def face_prims(t):
+        xf = np.arange(n + 1) / n - u * t
+        return _pack(profile(xf), 1000.0, 1.2, u, 0.0, 0.0, p0)
+
+    def alpha_cell_avg(t, sub=32):
+        """Cell averages of the translated alpha1 profile (midpoint rule, `sub` points per cell)."""
+        xs = (np.arange(n)[:, None] + (np.arange(sub)[None, :] + 0.5) / sub) / n - u * t
+        return profile(xs).mean(axis=1)
+
+    return {"name": "advected_slab", "spec": s, "w": w, "face_prims": face_prims, "alpha_cell_avg": alpha_cell_avg,
+            "meta": {"u": u, "c": c, "R": R}}
+
+
+def shock_tube_family(n=500, seed=0):
+    """Water|air tube of the shock_tube kind with a seeded interface position
+    U(0.3,0.7) and left pressure log-uniform in [1e8, 1e9]."""
+    rng = np.random.default_rng(seed)
+    x0 = rng.uniform(0.3, 0.7)
+    pl = float(np.exp(rng.uniform(np.log(1e8), np.log(1e9))))
+    P = shock_tube(n=n, x0=x0, p_left=pl)
+    P["meta"] = {"x0": x0, "p_left": pl}
+    return P
 
 
 def _ideal_gas_shock(M, rho1, p1, gamma):
