@@ -105,12 +105,12 @@ __device__ __forceinline__ void weno_features(float a, float b, float c, float d
     const float b2 = k13 * q2 * q2 + 0.25f * h2 * h2;
     const float S = b0 + b1 + b2 + eps;
     const float D = a - 4.f * b + 6.f * c - 4.f * d + e;
-    const float iS = 1.0f / S;
+    const float iS = __builtin_amdgcn_rcpf(S);  // features go to bfloat16: 1 ulp is ample
     x[0] = b0 * iS;
     x[1] = b1 * iS;
     x[2] = b2 * iS;
     x[3] = fabsf(b0 - b2) * iS;
-    x[4] = D * D / (S + D * D);
+    x[4] = D * D * __builtin_amdgcn_rcpf(S + D * D);
     nlb[0] = -2.0f * log2f(eps + b0);
     nlb[1] = -2.0f * log2f(eps + b1);
     nlb[2] = -2.0f * log2f(eps + b2);
@@ -127,7 +127,7 @@ __device__ __forceinline__ void softmax3(const float z[3], const float lw[3], fl
     const float l0 = z[0] * LOG2E + lw[0], l1 = z[1] * LOG2E + lw[1], l2 = z[2] * LOG2E + lw[2];
     const float lm = fmaxf(l0, fmaxf(l1, l2));
     const float e0 = exp2f(l0 - lm), e1 = exp2f(l1 - lm), e2 = exp2f(l2 - lm);
-    const float inv = 1.0f / (e0 + e1 + e2);
+    const float inv = __builtin_amdgcn_rcpf(e0 + e1 + e2);
     om[0] = e0 * inv;
     om[1] = e1 * inv;
     om[2] = e2 * inv;

@@ -58,6 +58,21 @@ __device__ __forceinline__ void cons_to_prim(const Mix<double>& mix, const doubl
 //   value = sum_k d_k t_k p_k / sum_k d_k t_k,  t_0 = s1 s2, t_1 = s0 s2, t_2 = s0 s1.
 // In float64 the products stay far from overflow for physical data
 // (beta <= 1e20 gives t <= 1e80).
+// Quotient for the steps outside the FP64 path's parity-critical ones: IEEE
+// division in double; in float, the numerator times the hardware reciprocal
+// (1 ulp; denominators here are positive and far from the denormal range),
+// which the float form's accuracy bound absorbs.
+template <typename T>
+__device__ __forceinline__ T qdiv(T a, T b)
+{
+    return a / b;
+}
+template <>
+__device__ __forceinline__ float qdiv<float>(float a, float b)
+{
+    return a * __builtin_amdgcn_rcpf(b);
+}
+
 template <typename T>
 __device__ __forceinline__ void weno5_js(T a, T b, T c, T d, T e, T eps, T& left, T& right)
 {
@@ -101,7 +116,7 @@ __device__ __forceinline__ void weno5_js_ratio(float a, float b, float c, float 
     const float s1 = eps + (k13 * q1 * q1 + 0.25f * h1 * h1);
     const float s2 = eps + (k13 * q2 * q2 + 0.25f * h2 * h2);
     const float smin = fminf(s0, fminf(s1, s2));
-    float x0 = smin / s0, x1 = smin / s1, x2 = smin / s2;
+    float x0 = qdiv(smin, s0), x1 = qdiv(smin, s1), x2 = qdiv(smin, s2);
     x0 *= x0;
     x1 *= x1;
     x2 *= x2;
@@ -113,8 +128,8 @@ __device__ __forceinline__ void weno5_js_ratio(float a, float b, float c, float 
     const float l2 = 11.f * c - 7.f * d + 2.f * e;
     const float wr0 = 0.1f * x0, wr1 = 0.6f * x1, wr2 = 0.3f * x2;
     const float wl0 = 0.3f * x0, wl1 = 0.6f * x1, wl2 = 0.1f * x2;
-    right = (wr0 * r0 + wr1 * r1 + wr2 * r2) / (6.f * (wr0 + wr1 + wr2));
-    left = (wl0 * l0 + wl1 * l1 + wl2 * l2) / (6.f * (wl0 + wl1 + wl2));
+    right = qdiv(wr0 * r0 + wr1 * r1 + wr2 * r2, 6.f * (wr0 + wr1 + wr2));
+    left = qdiv(wl0 * l0 + wl1 * l1 + wl2 * l2, 6.f * (wl0 + wl1 + wl2));
 }
 
 // WENO5 in the compute type: the product form in float64, the ratio form
@@ -150,13 +165,13 @@ __device__ __forceinline__ void hllc(const Mix<T>& mix, const T wl[NV], const T 
     const T Pl = mix.Pi(wl[6]), Pr = mix.Pi(wr[6]);
     const T El = Gl * pl + Pl + T(0.5) * rl * (wl[2] * wl[2] + wl[3] * wl[3] + wl[4] * wl[4]);
     const T Er = Gr * pr + Pr + T(0.5) * rr * (wr[2] * wr[2] + wr[3] * wr[3] + wr[4] * wr[4]);
-    const T cl = sqrt(((Gl + T(1)) * pl + Pl) / (Gl * rl));
-    const T cr = sqrt(((Gr + T(1)) * pr + Pr) / (Gr * rr));
+    const T cl = sqrt(qdiv((Gl + T(1)) * pl + Pl, Gl * rl));
+    const T cr = sqrt(qdiv((Gr + T(1)) * pr + Pr, Gr * rr));
 
     const T SL = fmin(unl - cl, unr - cr);
     const T SR = fmax(unl + cl, unr + cr);
     const T ml = rl * (SL - unl), mr = rr * (SR - unr);
-    const T Ss = (pr - pl + ml * unl - mr * unr) / (ml - mr);
+    const T Ss = qdiv(pr - pl + ml * unl - mr * unr, ml - mr);
 
     const bool left = Ss >= T(0);
     T w[NV];
@@ -169,8 +184,8 @@ __device__ __forceinline__ void hllc(const Mix<T>& mix, const T wl[NV], const T 
     const T S = left ? SL : SR;
     const T s = left ? fmin(T(0), SL) : fmax(T(0), SR);
 
-    const T xi = (S - un) / (S - Ss);
-    const T Eratio = p / (S - un);
+    const T xi = qdiv(S - un, S - Ss);
+    const T Eratio = qdiv(p, S - un);
 
     T U[NV], Us[NV];
     U[0] = w[0];
