@@ -115,12 +115,9 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     const long long N = (long long)d->n[0] * d->n[1] * d->n[2];
     const size_t state = align_up(sizeof(double) * 7 * (size_t)N);
     const size_t elem = d->precision == MFX_FP32_MIXED ? sizeof(float) : sizeof(double);
-    long long np = CFL_BLOCKS;
-    for (int k = 0; k < 3; ++k) {
-        if (d->n[k] <= 1 && !(k == 0 && d->n[1] == 1 && d->n[2] == 1)) continue;
-        SweepGeom g = sweep_geom(d->n, k, seg_override, xmode_override, elem);
-        np = std::max(np, (long long)g.grid.x * g.grid.y * g.grid.z);
-    }
+    (void)seg_override;
+    (void)xmode_override;
+    const long long np = CFL_BLOCKS;  // per-block maxima of the CFL reduction
     const long long nrows = (long long)d->n[1] * d->n[2];
     size_t off = 0;
     L.q = off;
@@ -368,8 +365,6 @@ struct LaunchArgs {
     double* out;
     const double* dt_dev;
     double dt_arg;
-    double* partial;
-    unsigned* status;
     void* bface;  // boundary faces of the x row sweep (compute type)
     const MlpLane* mlp;       // packed network (learned weights only)
     unsigned long long* fb;   // fallback counter (learned weights only)
@@ -388,14 +383,14 @@ void launch_one(const LaunchArgs& a)
             const long long faces = 2LL * a.g->n[1] * a.g->n[2];
             boundary_faces_x<T, L><<<(unsigned)((faces + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf, a.mlp, a.fb);
             sweep_x_rows<T, FIRST, MODE, L><<<sg.grid, sg.block, sg.lds, a.st>>>(
-                *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.partial, a.status, a.mlp, a.fb);
+                *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.mlp, a.fb);
         } else {
             sweep_x_march<T, FIRST, MODE, L><<<sg.grid, XROWS, 0, a.st>>>(
-                *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.partial, a.status, a.mlp, a.fb);
+                *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb);
         }
     } else {
         sweep_yz<DIR, T, FIRST, MODE, L><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(
-            *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.partial, a.status, a.mlp, a.fb);
+            *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb);
     }
 }
 
@@ -427,8 +422,6 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
                  const double* dt_dev, double dt_arg)
 {
     SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem);
-    if ((long long)sg.grid.x * sg.grid.y * sg.grid.z > c->L.n_partial)
-        return fail(c, MFX_EINVAL, "internal: partial buffer smaller than sweep grid");
     mfx_ctx::Pending pend{(d * 2 + (first ? 1 : 0)) * 5 + mode, nullptr, nullptr};
     if (c->profiling) {
         pend.a = take_event(c);
@@ -436,8 +429,7 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
         if (!pend.a || !pend.b) return fail(c, MFX_EHIP, "hipEventCreate failed");
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
-    const LaunchArgs la{&sg,       c->stream, &c->g,     qs,       qn,       c->r,     out,     dt_dev,
-                        dt_arg,    c->partial, c->status, c->bface, c->mlp, c->fallback};
+    const LaunchArgs la{&sg, c->stream, &c->g, qs, qn, c->r, out, dt_dev, dt_arg, c->bface, c->mlp, c->fallback};
     if (c->desc.weights == MFX_WENO5_LEARNED)
         launch_dispatch<float, true>(d, first != 0, mode, la);
     else if (c->desc.precision == MFX_FP32_MIXED)
@@ -456,7 +448,7 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
 // All direction passes of one right-hand-side evaluation; the last active
 // direction applies `last_mode` with output `out`.
 int run_passes(mfx_ctx* c, const double* qs, const double* qn, double* out, int last_mode, const double* dt_dev,
-               double dt_arg, long long* last_blocks)
+               double dt_arg)
 {
     for (int i = 0; i < c->ndirs; ++i) {
         const int d = c->dirs[i];
@@ -464,20 +456,20 @@ int run_passes(mfx_ctx* c, const double* qs, const double* qn, double* out, int 
         int rc = launch_sweep(c, d, qs, qn, last ? out : nullptr, i == 0, last ? last_mode : OUT_ACCUM, dt_dev,
                               dt_arg);
         if (rc != MFX_OK) return rc;
-        if (last && last_blocks) {
-            SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem);
-            *last_blocks = (long long)sg.grid.x * sg.grid.y * sg.grid.z;
-        }
     }
     return MFX_OK;
 }
 
-int standalone_cfl(mfx_ctx* c)
+// CFL time step of the current state (per-block maxima, then one block),
+// which also flags a non-physical state in the status word; with advance,
+// t and the step count first move on by the step just taken (dt_arg, or
+// the device time step when dt_arg is 0).
+int standalone_cfl(mfx_ctx* c, int advance = 0, double dt_arg = 0.0)
 {
     cfl_partial_kernel<<<CFL_BLOCKS, UTIL_BLOCK, 0, c->stream>>>(c->g, c->q, c->partial, c->status);
     int rc = launch_check(c, "cfl_partial_kernel");
     if (rc != MFX_OK) return rc;
-    cfl_finalize_kernel<<<1, UTIL_BLOCK, 0, c->stream>>>(c->partial, CFL_BLOCKS, c->g.cfl, c->scal, 0, 0.0);
+    cfl_finalize_kernel<<<1, UTIL_BLOCK, 0, c->stream>>>(c->partial, CFL_BLOCKS, c->g.cfl, c->scal, advance, dt_arg);
     return launch_check(c, "cfl_finalize_kernel");
 }
 
@@ -649,7 +641,7 @@ int mfx_rhs(mfx_ctx* c, double* rhs_out)
         return fail(c, MFX_EINVAL, "rhs_dev_out overlaps the workspace");
     int rc = set_device(c);
     if (rc) return rc;
-    return run_passes(c, c->q, c->q, rhs_out, OUT_RHS, nullptr, 0.0, nullptr);
+    return run_passes(c, c->q, c->q, rhs_out, OUT_RHS, nullptr, 0.0);
 }
 
 int mfx_rk3_step(mfx_ctx* c, double dt, double* dt_used_host)
@@ -668,15 +660,14 @@ int mfx_rk3_step(mfx_ctx* c, double dt, double* dt_used_host)
     if (dt_used_host && !(dt > 0.0)) {
         HIP_TRY(c, hipMemcpyAsync(&dt_seen, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     }
-    long long nb = 0;
-    rc = run_passes(c, c->q, c->q, c->q1, OUT_STAGE1, dt_dev, dt_arg, nullptr);
+    rc = run_passes(c, c->q, c->q, c->q1, OUT_STAGE1, dt_dev, dt_arg);
     if (rc) return rc;
-    rc = run_passes(c, c->q1, c->q, c->q2, OUT_STAGE2, dt_dev, dt_arg, nullptr);
+    rc = run_passes(c, c->q1, c->q, c->q2, OUT_STAGE2, dt_dev, dt_arg);
     if (rc) return rc;
-    rc = run_passes(c, c->q2, c->q, c->q, OUT_STAGE3, dt_dev, dt_arg, &nb);
+    rc = run_passes(c, c->q2, c->q, c->q, OUT_STAGE3, dt_dev, dt_arg);
     if (rc) return rc;
-    cfl_finalize_kernel<<<1, UTIL_BLOCK, 0, c->stream>>>(c->partial, nb, c->g.cfl, c->scal, 1, dt_arg);
-    rc = launch_check(c, "cfl_finalize_kernel");
+    // time step of the new state for the next step, and its physicality check
+    rc = standalone_cfl(c, 1, dt_arg);
     if (rc) return rc;
     if (dt_used_host) {
         unsigned st = 0;

@@ -2,7 +2,9 @@
 // (arXiv 2409.10729, Sec. II-B, eq. rhs): ghost-cell index map, conserved ->
 // primitive, WENO5 face states, HLLC flux + face velocity, flux difference
 // and alpha1 div(u) source, and -- in the last active direction of a stage --
-// the SSP-RK3 combine and the CFL wave-speed maximum.
+// the SSP-RK3 combine.  (The CFL wave-speed maximum of the new state is a
+// separate streaming pass: inside the marching loop its running maximum
+// spilled and every reload drained the loop's prefetched loads.)
 //
 // T is the arithmetic of reconstruction, Riemann solve and flux difference
 // (double, or float for the mixed-precision form).  The conserved ->
@@ -32,7 +34,7 @@ enum : int {
     OUT_RHS = 1,     // write the total to the caller's RHS array
     OUT_STAGE1 = 2,  // q1 = q + dt L
     OUT_STAGE2 = 3,  // q2 = 3/4 q + 1/4 (q1 + dt L)
-    OUT_STAGE3 = 4,  // q  = 1/3 q + 2/3 (q2 + dt L), plus CFL partial maxima
+    OUT_STAGE3 = 4,  // q  = 1/3 q + 2/3 (q2 + dt L)
 };
 
 struct Grid {
@@ -98,22 +100,6 @@ __device__ __forceinline__ void block_max_to(double v, double* slot)
     }
 }
 
-// Block-wide maximum for any block of whole waves (up to 16).
-__device__ __forceinline__ void block_max_dyn(double v, double* slot)
-{
-    __shared__ double red[16];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) red[wid] = v;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double m = red[0];
-        for (int i = 1; i < (int)(blockDim.x >> 6); ++i) m = fmax(m, red[i]);
-        *slot = m;
-    }
-}
-
 // SSP-RK3 stage combination of one cell, in the operation order of the
 // plain definition and without contraction: rho E feeds the pressure
 // inversion, which turns one unit in the last place of rho E into ~1e-7 Pa
@@ -143,11 +129,9 @@ struct OutArgs {
 // (F_{c-1/2} - F_{c+1/2}) / dx and the alpha1 source term src, added to the
 // running sum as (R + fd) + src for alpha1 and R + fd otherwise.  FIRST
 // (no running sum yet) and MODE (what is written) are compile-time so each
-// kernel carries only its own path.  Returns the CFL speed of the new state
-// in stage 3 (else 0).
+// kernel carries only its own path.
 template <typename T, bool FIRST, int MODE>
-__device__ __forceinline__ double emit_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T fd[NV],
-                                            T src, unsigned& bad)
+__device__ __forceinline__ void emit_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T fd[NV], T src)
 {
     const long long N = g.N;
     T r[NV];
@@ -157,11 +141,9 @@ __device__ __forceinline__ double emit_cell(const Grid& g, const OutArgs<T>& o, 
     if constexpr (MODE == OUT_ACCUM) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) o.racc[v * N + cell] = r[v];
-        return 0.0;
     } else if constexpr (MODE == OUT_RHS) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) o.out[v * N + cell] = (double)r[v];
-        return 0.0;
     } else {
         double qo[NV];
 #pragma unroll
@@ -171,7 +153,6 @@ __device__ __forceinline__ double emit_cell(const Grid& g, const OutArgs<T>& o, 
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) o.out[v * N + cell] = qo[v];
-        return MODE == OUT_STAGE3 ? cfl_speed(g, qo, bad) : 0.0;
     }
 }
 
@@ -192,22 +173,55 @@ struct GlobalSink {
     OutArgs<T> o;
     long long base, sd;
     bool valid;
-    double smax;
-    unsigned bad;
     __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src)
     {
-        if (valid) smax = fmax(smax, emit_cell<T, FIRST, MODE>(g, o, base + (long long)c * sd, fd, src, bad));
+        if (valid) emit_cell<T, FIRST, MODE>(g, o, base + (long long)c * sd, fd, src);
     }
 };
 
-// Reconstruction of one cell's two edge states (all seven primitives) from
-// its 5-cell window W[k][v] = w_v of cell c-2+k.
+// Views of a 5-cell window: w(k, v) = primitive v of cell c-2+k.
 template <typename T>
-struct ReconJS {
-    __device__ __forceinline__ void cell(const T W[5][NV], T eps, T lft[NV], T rgt[NV])
+struct ArrayWindow {
+    const T (*W)[NV];
+    __device__ __forceinline__ T operator()(int k, int v) const { return W[k][v]; }
+};
+
+// A lane's private ring of five cells in LDS (no other lane touches its
+// column, so no barriers): element (slot, v) at col[(slot * NV + v) * LANES],
+// consecutive lanes in consecutive words.  s0 is the slot of cell c-2.
+// Keeping the window here instead of in registers leaves the registers to
+// one variable's reconstruction at a time and needs no shifting.
+template <typename T, int LANES>
+struct LdsWindow {
+    T* col;
+    int s0;
+    __device__ __forceinline__ int slot(int k) const
+    {
+        const int s = s0 + k;
+        return s >= 5 ? s - 5 : s;
+    }
+    __device__ __forceinline__ T operator()(int k, int v) const { return col[(slot(k) * NV + v) * LANES]; }
+    __device__ __forceinline__ void store(int k, const T w[NV]) const
     {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) weno5<T>(W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, lft[v], rgt[v]);
+        for (int v = 0; v < NV; ++v) col[(slot(k) * NV + v) * LANES] = w[v];
+    }
+    __device__ __forceinline__ void advance() { s0 = s0 == 4 ? 0 : s0 + 1; }
+};
+
+// Reconstruction of one cell's two edge states (all seven primitives) from
+// its 5-cell window.
+template <typename T>
+struct ReconJS {
+    template <class Win>
+    __device__ __forceinline__ void cell_win(const Win& W, T eps, T lft[NV], T rgt[NV])
+    {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) weno5<T>(W(0, v), W(1, v), W(2, v), W(3, v), W(4, v), eps, lft[v], rgt[v]);
+    }
+    __device__ __forceinline__ void cell(const T W[5][NV], T eps, T lft[NV], T rgt[NV])
+    {
+        cell_win(ArrayWindow<T>{W}, eps, lft, rgt);
     }
     __device__ __forceinline__ void flush(unsigned long long*) {}
 };
@@ -221,15 +235,17 @@ struct ReconLearned {
     Mix<float> mix;
     bool valid;  // this lane owns a real cell (only those are counted)
     unsigned fallbacks;
-    __device__ __forceinline__ void cell(const float W[5][NV], float eps, float lft[NV], float rgt[NV])
+    template <class Win>
+    __device__ __forceinline__ void cell_win(const Win& W, float eps, float lft[NV], float rgt[NV])
     {
         float lj[NV], rj[NV], ll[NV], rl[NV];
         bool fin = true;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            weno5<float>(W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, lj[v], rj[v]);
+            const float a = W(0, v), b = W(1, v), c = W(2, v), d = W(3, v), e = W(4, v);
+            weno5<float>(a, b, c, d, e, eps, lj[v], rj[v]);
             bool f;
-            weno5_learned(m, lds, W[0][v], W[1][v], W[2][v], W[3][v], W[4][v], eps, ll[v], rl[v], f);
+            weno5_learned(m, lds, a, b, c, d, e, eps, ll[v], rl[v], f);
             fin = fin && f;
         }
         const bool okR = fin && admissible(mix, rl);
@@ -240,6 +256,10 @@ struct ReconLearned {
             lft[v] = okL ? ll[v] : lj[v];
         }
         if (valid) fallbacks += (okR ? 0u : 1u) + (okL ? 0u : 1u);
+    }
+    __device__ __forceinline__ void cell(const float W[5][NV], float eps, float lft[NV], float rgt[NV])
+    {
+        cell_win(ArrayWindow<float>{W}, eps, lft, rgt);
     }
     // wave sum of the fallback counts, one atomic per wave
     __device__ __forceinline__ void flush(unsigned long long* counter)
@@ -282,21 +302,24 @@ __device__ __forceinline__ typename ReconOf<T, LEARNED>::type make_recon(const G
 // the conserved state of cell `pos` along the sweep (boundary map applied);
 // it is called for positions c0-3, c0-2, ..., c1+2 in that order, and
 // Sink::put for cells c0..c1-1 in order, the same sequence on every lane.
-template <int DIR, typename T, class Src, class Sink, class Recon>
-__device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon& recon, int c0, int c1)
+// col: this lane's column of a [5][NV][LANES] LDS array holding the window.
+template <int DIR, typename T, int LANES, class Src, class Sink, class Recon>
+__device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon& recon, int c0, int c1, T* col)
 {
     const T idx = (T)g.inv_dx[DIR];
     const T eps = (T)g.eps;
     const Mix<double> mixd{g.G1, g.G2, g.P1, g.P2};
     const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
 
-    // window: W[k] = primitives of cell c-2+k while reconstructing cell c
-    T W[5][NV];
-#pragma unroll
+    // window: W(k) = primitives of cell c-2+k while reconstructing cell c
+    LdsWindow<T, LANES> W{col, 0};
+#pragma unroll 1
     for (int k = 0; k < 5; ++k) {
         double qc[NV];
         src.load(c0 - 3 + k, qc);
-        prim_of<T>(mixd, qc, W[k]);
+        T w[NV];
+        prim_of<T>(mixd, qc, w);
+        W.store(k, w);
     }
 
     T rprev[NV], Fprev[NV], ufprev = T(0);
@@ -309,7 +332,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
         if (c < c1) src.load(c + 3, qnext);
 
         T lft[NV], rgt[NV];
-        recon.cell(W, eps, lft, rgt);
+        recon.cell_win(W, eps, lft, rgt);
 
         if (c >= c0) {
             T F[NV], uf;
@@ -319,7 +342,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
                 T fd[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) fd[v] = (Fprev[v] - F[v]) * idx;
-                sink.put(g, c - 1, fd, W[1][6] * ((uf - ufprev) * idx));
+                sink.put(g, c - 1, fd, W(1, 6) * ((uf - ufprev) * idx));
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fprev[v] = F[v];
@@ -329,12 +352,12 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
         for (int v = 0; v < NV; ++v) rprev[v] = rgt[v];
 
         if (c < c1) {
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-#pragma unroll
-                for (int v = 0; v < NV; ++v) W[k][v] = W[k + 1][v];
-            prim_of<T>(mixd, qnext, W[4]);
+            // cell c+3 takes the slot of cell c-2, which is no longer needed
+            T w[NV];
+            prim_of<T>(mixd, qnext, w);
+            W.store(0, w);
         }
+        W.advance();
     }
 }
 
@@ -362,7 +385,6 @@ template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED>
 __global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
                                                    T* __restrict__ racc, double* out, int seg,
                                                    const double* __restrict__ dt_dev, double dt_arg,
-                                                   double* __restrict__ partial, unsigned* __restrict__ status,
                                                    const MlpLane* __restrict__ mlp, unsigned long long* fb)
 {
     constexpr int BLOCK = 256;
@@ -379,16 +401,11 @@ __global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restr
     const int c1 = min(c0 + seg, n);
     GlobalSrc src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
     GlobalSink<T, FIRST, MODE> sink{OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR],
-                                    valid, 0.0, 0u};
+                                    valid};
     auto recon = make_recon<T, LEARNED>(g, mlp, valid);
-    march<DIR, T>(g, src, sink, recon, c0, c1);
+    __shared__ T win[5][NV][BLOCK];
+    march<DIR, T, BLOCK>(g, src, sink, recon, c0, c1, &win[0][0][threadIdx.x]);
     recon.flush(fb);
-
-    if constexpr (MODE == OUT_STAGE3) {
-        if (sink.bad) atomicOr(status, sink.bad);
-        const long long bid = ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-        block_max_to<BLOCK>(sink.smax, partial + bid);
-    }
 }
 
 // Marching x sweep, for rows longer than the whole-row kernel takes.  The 64
@@ -438,8 +455,6 @@ struct LdsSink {
     OutArgs<T> o;
     long long row0, nrows;
     int nx, c0, c1;
-    double smax;
-    unsigned bad;
 
     __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src)
     {
@@ -459,7 +474,7 @@ struct LdsSink {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) f[v] = buf[cx][v][r];
                     const long long cell = (row0 + r) * nx + p0 + cx;
-                    smax = fmax(smax, emit_cell<T, FIRST, MODE>(g, o, cell, f, buf[cx][NV][r], bad));
+                    emit_cell<T, FIRST, MODE>(g, o, cell, f, buf[cx][NV][r]);
                 }
             }
             __syncthreads();  // the buffer is refilled next
@@ -471,7 +486,6 @@ template <typename T, bool FIRST, int MODE, bool LEARNED>
 __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* __restrict__ qs, const double* qn,
                                                           T* __restrict__ racc, double* out, int seg,
                                                           const double* __restrict__ dt_dev, double dt_arg,
-                                                          double* __restrict__ partial, unsigned* __restrict__ status,
                                                           const MlpLane* __restrict__ mlp, unsigned long long* fb)
 {
     __shared__ double ibuf[XCHUNK][NV][XROWS];
@@ -484,16 +498,11 @@ __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* 
 
     LdsSrc src{ibuf, qs, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
     LdsSink<T, FIRST, MODE> sink{obuf, OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx,
-                                 c0, c1, 0.0, 0u};
+                                 c0, c1};
     auto recon = make_recon<T, LEARNED>(g, mlp, row0 + threadIdx.x < nrows);
-    march<0, T>(g, src, sink, recon, c0, c1);
+    __shared__ T win[5][NV][XROWS];
+    march<0, T, XROWS>(g, src, sink, recon, c0, c1, &win[0][0][threadIdx.x]);
     recon.flush(fb);
-
-    if constexpr (MODE == OUT_STAGE3) {
-        if (sink.bad) atomicOr(status, sink.bad);
-        const long long bid = (long long)blockIdx.z * gridDim.x + blockIdx.x;
-        block_max_to<XROWS>(sink.smax, partial + bid);
-    }
 }
 
 }  // namespace mfx

@@ -78,8 +78,6 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
                                                              T* __restrict__ racc, double* out, int rows_per_block,
                                                              const T* __restrict__ bface,
                                                              const double* __restrict__ dt_dev, double dt_arg,
-                                                             double* __restrict__ partial,
-                                                             unsigned* __restrict__ status,
                                                              const MlpLane* __restrict__ mlp, unsigned long long* fb)
 {
     extern __shared__ __align__(16) unsigned char lds_raw[];
@@ -107,8 +105,6 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
     const int gsrc2 = map_cell(nx, nx, g.bc[0][0], g.bc[0][1]);
     const int gsrc3 = map_cell(nx + 1, nx, g.bc[0][0], g.bc[0][1]);
 
-    double smax = 0.0;
-    unsigned bad = 0;
     auto recon = make_recon<T, LEARNED>(g, mlp, has);
     double qc[NV];
     if (r0 < r1) {
@@ -184,14 +180,10 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
 #pragma unroll
             for (int v = 0; v < NV; ++v) fd[v] = (Fm[v] - F[v]) * idx;
             const T src = a1 * ((F[NV] - Fm[NV]) * idx);
-            smax = fmax(smax, emit_cell<T, FIRST, MODE>(g, o, row * nx + x, fd, src, bad));
+            emit_cell<T, FIRST, MODE>(g, o, row * nx + x, fd, src);
         }
     }
     recon.flush(fb);
-    if constexpr (MODE == OUT_STAGE3) {
-        if (bad) atomicOr(status, bad);
-        block_max_dyn(smax, partial + blockIdx.x);
-    }
 }
 
 }  // namespace mfx
