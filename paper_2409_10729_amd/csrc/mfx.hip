@@ -380,8 +380,8 @@ void launch_one(const LaunchArgs& a)
     if constexpr (DIR == 0) {
         if (sg.xrows) {
             T* bf = static_cast<T*>(a.bface);
-            const long long faces = 2LL * a.g->n[1] * a.g->n[2];
-            boundary_faces_x<T, L><<<(unsigned)((faces + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf, a.mlp, a.fb);
+            const long long rows = (long long)a.g->n[1] * a.g->n[2];
+            boundary_faces_x<T, L><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf, a.mlp, a.fb);
             sweep_x_rows<T, FIRST, MODE, L><<<sg.grid, sg.block, sg.lds, a.st>>>(
                 *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.mlp, a.fb);
         } else {

@@ -83,6 +83,15 @@ __device__ __forceinline__ float qdiv<float>(float a, float b)
     return a * __builtin_amdgcn_rcpf(b);
 }
 
+// Square root of a sound speed squared in the float form.
+template <typename T>
+__device__ __forceinline__ T qsqrt(T x);
+template <>
+__device__ __forceinline__ float qsqrt<float>(float x)
+{
+    return sqrtf(x);
+}
+
 template <typename T>
 __device__ __forceinline__ void weno5_js(T a, T b, T c, T d, T e, T eps, T& left, T& right)
 {
@@ -159,14 +168,73 @@ __device__ __forceinline__ void weno5<float>(float a, float b, float c, float d,
     weno5_js_ratio(a, b, c, d, e, eps, left, right);
 }
 
-// HLLC flux across a face normal to direction DIR (Toro 2009, Sec. 10.4),
-// Davis wave-speed estimates, extended to the five-equation model: each
-// partial density and alpha1 are scaled by xi = (S_K - u_K)/(S_K - S*) in
-// the star state.  Also returns the face velocity u_f used for div(u) in
-// the alpha1 source; the side of the contact is chosen by S* >= 0 (ties go
-// left), and only that side's star state is formed.
+// FP64 HLLC in the plain definition's operation order, without contraction
+// and with IEEE division and square root.  The star-state flux
+// F = F_K + s (U*_K - U_K) subtracts energies of size Pi (7.8e8 in water)
+// and multiplies the difference by a wave speed of ~1.6e3, which amplifies
+// rounding in U* about a thousand-fold; evaluated exactly as the definition
+// states, that amplified noise is the same in every implementation of it.
+template <int DIR>
+__device__ __forceinline__ void hllc_fp64(const Mix<double>& mix, const double wl[NV], const double wr[NV],
+                                          double F[NV], double& uf)
+{
+#pragma clang fp contract(off)
+    const double rl = wl[0] + wl[1], rr = wr[0] + wr[1];
+    const double pl = wl[5], pr = wr[5];
+    const double unl = wl[2 + DIR], unr = wr[2 + DIR];
+    // mixture rules written out (Mix's members may be contracted)
+    const double Gl = wl[6] * mix.G1 + (1.0 - wl[6]) * mix.G2, Gr = wr[6] * mix.G1 + (1.0 - wr[6]) * mix.G2;
+    const double Pl = wl[6] * mix.P1 + (1.0 - wl[6]) * mix.P2, Pr = wr[6] * mix.P1 + (1.0 - wr[6]) * mix.P2;
+    const double El = Gl * pl + Pl + 0.5 * rl * (wl[2] * wl[2] + wl[3] * wl[3] + wl[4] * wl[4]);
+    const double Er = Gr * pr + Pr + 0.5 * rr * (wr[2] * wr[2] + wr[3] * wr[3] + wr[4] * wr[4]);
+    const double cl = sqrt(((Gl + 1.0) * pl + Pl) / (Gl * rl));
+    const double cr = sqrt(((Gr + 1.0) * pr + Pr) / (Gr * rr));
+
+    const double SL = fmin(unl - cl, unr - cr);
+    const double SR = fmax(unl + cl, unr + cr);
+    const double Ss = (pr - pl + rl * unl * (SL - unl) - rr * unr * (SR - unr)) / (rl * (SL - unl) - rr * (SR - unr));
+
+    const bool left = Ss >= 0.0;
+    double w[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) w[v] = left ? wl[v] : wr[v];
+    const double rho = left ? rl : rr;
+    const double p = left ? pl : pr;
+    const double un = left ? unl : unr;
+    const double E = left ? El : Er;
+    const double S = left ? SL : SR;
+    const double s = left ? fmin(0.0, SL) : fmax(0.0, SR);
+
+    double U[NV], Us[NV], Fk[NV];
+    U[0] = w[0];
+    U[1] = w[1];
+    U[2] = rho * w[2];
+    U[3] = rho * w[3];
+    U[4] = rho * w[4];
+    U[5] = E;
+    U[6] = w[6];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Fk[v] = U[v] * un;
+    Fk[2 + DIR] = Fk[2 + DIR] + p;
+    Fk[5] = (E + p) * un;
+
+    const double xi = (S - un) / (S - Ss);
+    Us[0] = xi * w[0];
+    Us[1] = xi * w[1];
+    Us[2] = xi * (rho * w[2]);
+    Us[3] = xi * (rho * w[3]);
+    Us[4] = xi * (rho * w[4]);
+    Us[2 + DIR] = xi * (rho * Ss);
+    Us[5] = xi * (E + (Ss - un) * (rho * Ss + p / (S - un)));
+    Us[6] = xi * w[6];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) F[v] = Fk[v] + s * (Us[v] - U[v]);
+    uf = un + s * (xi - 1.0);
+}
+
+// The same flux in the float form: contraction allowed, reciprocal quotients.
 template <int DIR, typename T>
-__device__ __forceinline__ void hllc(const Mix<T>& mix, const T wl[NV], const T wr[NV], T F[NV], T& uf)
+__device__ __forceinline__ void hllc_fast(const Mix<T>& mix, const T wl[NV], const T wr[NV], T F[NV], T& uf)
 {
     const T rl = wl[0] + wl[1], rr = wr[0] + wr[1];
     const T pl = wl[5], pr = wr[5];
@@ -175,8 +243,8 @@ __device__ __forceinline__ void hllc(const Mix<T>& mix, const T wl[NV], const T 
     const T Pl = mix.Pi(wl[6]), Pr = mix.Pi(wr[6]);
     const T El = Gl * pl + Pl + T(0.5) * rl * (wl[2] * wl[2] + wl[3] * wl[3] + wl[4] * wl[4]);
     const T Er = Gr * pr + Pr + T(0.5) * rr * (wr[2] * wr[2] + wr[3] * wr[3] + wr[4] * wr[4]);
-    const T cl = sqrt(qdiv((Gl + T(1)) * pl + Pl, Gl * rl));
-    const T cr = sqrt(qdiv((Gr + T(1)) * pr + Pr, Gr * rr));
+    const T cl = qsqrt(qdiv((Gl + T(1)) * pl + Pl, Gl * rl));
+    const T cr = qsqrt(qdiv((Gr + T(1)) * pr + Pr, Gr * rr));
 
     const T SL = fmin(unl - cl, unr - cr);
     const T SR = fmax(unl + cl, unr + cr);
@@ -218,6 +286,21 @@ __device__ __forceinline__ void hllc(const Mix<T>& mix, const T wl[NV], const T 
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v] = Fk[v] + s * (Us[v] - U[v]);
     uf = un + s * (xi - T(1));
+}
+
+// HLLC flux across a face normal to direction DIR (Toro 2009, Sec. 10.4),
+// Davis wave-speed estimates, extended to the five-equation model: each
+// partial density and alpha1 are scaled by xi = (S_K - u_K)/(S_K - S*) in
+// the star state.  Also returns the face velocity u_f used for div(u) in
+// the alpha1 source; the side of the contact is chosen by S* >= 0 (ties go
+// left), and only that side's star state is formed.
+template <int DIR, typename T>
+__device__ __forceinline__ void hllc(const Mix<T>& mix, const T wl[NV], const T wr[NV], T F[NV], T& uf)
+{
+    if constexpr (sizeof(T) == sizeof(double))
+        hllc_fp64<DIR>(mix, wl, wr, F, uf);
+    else
+        hllc_fast<DIR, T>(mix, wl, wr, F, uf);
 }
 
 }  // namespace mfx

@@ -20,57 +20,118 @@ constexpr int XROW_MAX = 512;       // longest row the row kernel takes
 constexpr int XROW_THREADS = 512;   // launch bound (blockDim = 64 * ceil(nx / 64))
 constexpr int BFACE = NV + 1;       // flux components + face velocity
 
-// Boundary faces of every row: thread t -> (row t/2, side t%2); side 0 is
-// the face between ghost cell -1 and cell 0, side 1 between cell nx-1 and
-// ghost cell nx.  Output bface[(row*2 + side) * BFACE + k].
+// Boundary faces of every row, one lane per row: face 0 lies between ghost
+// cell -1 and cell 0, face 1 between cell nx-1 and ghost cell nx; output
+// bface[(row*2 + side) * BFACE + k].  For nx >= 6 every stencil position
+// either face reaches maps onto one of six anchor cells (0, 1, 2, nx-3,
+// nx-2, nx-1) at both periodic and transmissive ends, so each lane loads
+// and converts those six cells once and assembles both 6-cell stencils from
+// them; with periodic ends the two faces are one face, solved once.
+// Shorter rows map every position through the boundary rule.
 template <typename T, bool LEARNED>
 __global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __restrict__ qs, T* __restrict__ bface,
                                                         const MlpLane* __restrict__ mlp, unsigned long long* fb)
 {
     const long long nrows = (long long)g.n[1] * g.n[2];
-    const long long t_raw = (long long)blockIdx.x * 256 + threadIdx.x;
-    const bool valid = t_raw < 2 * nrows;  // every lane computes (the learned weights need whole waves)
-    const long long t = valid ? t_raw : 2 * nrows - 1;
-    const long long row = t >> 1;
-    const int side = (int)(t & 1);
+    const long long r_raw = (long long)blockIdx.x * 256 + threadIdx.x;
+    const bool valid = r_raw < nrows;  // every lane computes (the learned weights need whole waves)
+    const long long row = valid ? r_raw : nrows - 1;
     const int nx = g.n[0];
+    const int blo = g.bc[0][0], bhi = g.bc[0][1];
+    const bool anchored = nx >= 6;
     const Mix<double> mixd{g.G1, g.G2, g.P1, g.P2};
     const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
     const T eps = (T)g.eps;
-    const int first = side == 0 ? -3 : nx - 3;  // cells first .. first+5
-    T w[6][NV];
+    T a[6][NV];
+    if (anchored) {
 #pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const long long off = row * nx + map_cell(first + k, nx, g.bc[0][0], g.bc[0][1]);
-        double q[NV];
+        for (int j = 0; j < 6; ++j) {
+            const int cell = j < 3 ? j : nx - 6 + j;
+            double q[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) q[v] = qs[v * g.N + off];
-        prim_of<T>(mixd, q, w[k]);
+            for (int v = 0; v < NV; ++v) q[v] = qs[v * g.N + row * nx + cell];
+            prim_of<T>(mixd, q, a[j]);
+        }
     }
-    // right edge of cell first+2 (window w[0..4]) and left edge of cell first+3 (w[1..5])
     auto recon = make_recon<T, LEARNED>(g, mlp, valid);
-    T wl[NV], wr[NV], dummy[NV];
-    recon.cell(w, eps, dummy, wl);
-    recon.cell(w + 1, eps, wr, dummy);
-    recon.flush(fb);
-    T F[NV], uf;
-    hllc<0, T>(mix, wl, wr, F, uf);
-    if (valid) {
-        T* o = bface + t * BFACE;
+    const int sides = blo == BC_PERIODIC ? 1 : 2;  // periodic ends pair up
+#pragma unroll 1
+    for (int side = 0; side < sides; ++side) {
+        // stencil positions -3..2 (face 0) or nx-3..nx+2 (face 1)
+        T w[6][NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) o[v] = F[v];
-        o[NV] = uf;
+        for (int k = 0; k < 6; ++k) {
+            const int cell = map_cell(side == 0 ? k - 3 : nx - 3 + k, nx, blo, bhi);
+            if (anchored) {
+                const int j = cell < 3 ? cell : cell - nx + 6;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    T x = a[0][v];
+#pragma unroll
+                    for (int m = 1; m < 6; ++m) x = j == m ? a[m][v] : x;
+                    w[k][v] = x;
+                }
+            } else {
+                double q[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) q[v] = qs[v * g.N + row * nx + cell];
+                prim_of<T>(mixd, q, w[k]);
+            }
+        }
+        // right edge of the cell before the face (window w[0..4]) and left
+        // edge of the cell after it (window w[1..5])
+        T wl[NV], wr[NV], dummy[NV];
+        recon.cell(w, eps, dummy, wl);
+        recon.cell(w + 1, eps, wr, dummy);
+        T F[NV], uf;
+        hllc<0, T>(mix, wl, wr, F, uf);
+        if (valid) {
+            for (int out = side; out < 2; out += sides) {
+                T* o = bface + (row * 2 + out) * BFACE;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) o[v] = F[v];
+                o[NV] = uf;
+            }
+        }
     }
+    recon.flush(fb);
 }
 
-// LDS bytes of the row kernel: primitives P[NV][nx+4] (two ghost slots on
-// each side) sharing storage with the face fluxes F[BFACE][nx] (P is dead
-// once every lane has reconstructed), plus left-edge states L[NV][nx].
-inline size_t xrow_lds_bytes(int nx, size_t elem)
+// LDS layout of the row kernel (offsets in elements of T): primitives
+// P[NV][nx+4] (two ghost slots on each side), face fluxes Fs[BFACE][nx] and
+// left-edge states L[NV][nx].  P and Fs get storage of their own when all
+// three fit in 64 KB; then a row can start overwriting P without waiting for
+// the previous row's flux reads (the barriers inside the row order every
+// other reuse).  Longer rows let Fs share P's storage (P is dead once every
+// lane has reconstructed) and start each row with a barrier.
+struct XrowLayout {
+    size_t p, fs, l, elems;
+    bool alias;
+};
+
+__host__ __device__ inline XrowLayout xrow_layout(int nx, size_t elem)
 {
-    const size_t pf = (size_t)NV * (nx + 4) > (size_t)BFACE * nx ? (size_t)NV * (nx + 4) : (size_t)BFACE * nx;
-    return elem * (pf + (size_t)NV * nx);
+    const size_t np = (size_t)nx + 4;
+    const size_t pe = (size_t)NV * np, fe = (size_t)BFACE * nx, le = (size_t)NV * nx;
+    XrowLayout L{};
+    if (elem * (pe + fe + le) <= 64 * 1024) {
+        L.p = 0;
+        L.fs = pe;
+        L.l = pe + fe;
+        L.elems = pe + fe + le;
+        L.alias = false;
+    } else {
+        const size_t pf = pe > fe ? pe : fe;
+        L.p = 0;
+        L.fs = 0;
+        L.l = pf;
+        L.elems = pf + le;
+        L.alias = true;
+    }
+    return L;
 }
+
+inline size_t xrow_lds_bytes(int nx, size_t elem) { return elem * xrow_layout(nx, elem).elems; }
 
 // Row kernel.
 template <typename T, bool FIRST, int MODE, bool LEARNED>
@@ -84,10 +145,10 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
     T* lds = reinterpret_cast<T*>(lds_raw);
     const int nx = g.n[0];
     const int np = nx + 4;
-    const int pf = NV * np > BFACE * nx ? NV * np : BFACE * nx;
-    T* P = lds;       // [NV][np], cell x at index x + 2
-    T* Fs = lds;      // [BFACE][nx], same storage as P
-    T* L = lds + pf;  // [NV][nx]
+    const XrowLayout lay = xrow_layout(nx, sizeof(T));
+    T* P = lds + lay.p;    // [NV][np], cell x at index x + 2
+    T* Fs = lds + lay.fs;  // [BFACE][nx]
+    T* L = lds + lay.l;    // [NV][nx]
     const long long nrows = (long long)g.n[1] * g.n[2];
     const long long r0 = (long long)blockIdx.x * rows_per_block;
     const long long r1 = min(r0 + rows_per_block, nrows);
@@ -112,7 +173,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
         for (int v = 0; v < NV; ++v) qc[v] = qs[v * g.N + r0 * nx + xc];
     }
     for (long long row = r0; row < r1; ++row) {
-        __syncthreads();  // the previous row's F (same storage as P) is consumed
+        if (lay.alias) __syncthreads();  // the previous row's fluxes (P's storage) are consumed
         // 1. own cell -> primitives in LDS (and the ghost slots that copy it)
         T w[NV];
         prim_of<T>(mixd, qc, w);
