@@ -133,10 +133,20 @@ __device__ __forceinline__ void softmax3(const float z[3], const float lw[3], fl
     om[2] = e2 * inv;
 }
 
+// Orders this wave's LDS writes before reads of them by its other lanes.
+// The slot is private to the wave and LDS instructions of one wave execute
+// in order, so only the compiler must be kept from moving accesses across.
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Learned weights of 2 samples per lane (x0: side 0, x1: side 1) for the
-// whole block, which must call this together (block barriers inside).  Each
-// wave stages its 128 samples in its LDS slot and runs them as four
-// 32-sample tiles on the matrix cores.
+// whole wave, which must call this together.  The wave stages its 128
+// samples in its own LDS slot and runs them as four 32-sample tiles on the
+// matrix cores.
 __device__ __forceinline__ void mlp_omega_pair(const MlpLane& m, LearnedLds* L, const float x0[5], const float x1[5],
                                                const float lw0[3], const float lw1[3], float om0[3], float om1[3])
 {
@@ -151,7 +161,7 @@ __device__ __forceinline__ void mlp_omega_pair(const MlpLane& m, LearnedLds* L, 
     L->feat[1][lane][5] = one;
     L->feat[0][lane][6] = L->feat[0][lane][7] = 0;
     L->feat[1][lane][6] = L->feat[1][lane][7] = 0;
-    __syncthreads();
+    wave_lds_sync();
 #pragma unroll 1
     for (int t = 0; t < 4; ++t) {
         const int side = t >> 1, half = t & 1;
@@ -163,7 +173,7 @@ __device__ __forceinline__ void mlp_omega_pair(const MlpLane& m, LearnedLds* L, 
             L->z[side][32 * half + lane][2] = z[2];
         }
     }
-    __syncthreads();
+    wave_lds_sync();
     const float z0[3] = {L->z[0][lane][0], L->z[0][lane][1], L->z[0][lane][2]};
     const float z1[3] = {L->z[1][lane][0], L->z[1][lane][1], L->z[1][lane][2]};
     softmax3(z0, lw0, om0);

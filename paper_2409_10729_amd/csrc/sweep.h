@@ -244,9 +244,17 @@ struct ReconLearned {
         for (int v = 0; v < NV; ++v) {
             const float a = W(0, v), b = W(1, v), c = W(2, v), d = W(3, v), e = W(4, v);
             weno5<float>(a, b, c, d, e, eps, lj[v], rj[v]);
-            bool f;
-            weno5_learned(m, lds, a, b, c, d, e, eps, ll[v], rl[v], f);
-            fin = fin && f;
+            // A constant stencil reconstructs to its value under any convex
+            // weights: where the whole wave has one, the network is skipped.
+            const bool flat = a == b && b == c && c == d && d == e;
+            if (__all(flat)) {
+                ll[v] = lj[v];
+                rl[v] = rj[v];
+            } else {
+                bool f;
+                weno5_learned(m, lds, a, b, c, d, e, eps, ll[v], rl[v], f);
+                fin = fin && f;
+            }
         }
         const bool okR = fin && admissible(mix, rl);
         const bool okL = fin && admissible(mix, ll);
@@ -286,7 +294,7 @@ template <typename T, bool LEARNED>
 __device__ __forceinline__ typename ReconOf<T, LEARNED>::type make_recon(const Grid& g, const MlpLane* mlp, bool valid)
 {
     if constexpr (LEARNED) {
-        // one 4 KB slot per wave; blocks have at most XROW_WAVES waves
+        // one 4 KB slot per wave; blocks have at most LEARNED_MAX_WAVES waves
         __shared__ LearnedLds slots[LEARNED_MAX_WAVES];
         return ReconLearned{mlp[threadIdx.x & 63], &slots[threadIdx.x >> 6],
                             Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u};
