@@ -179,12 +179,16 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
         prim_of<T>(mixd, qc, w);
         if (has) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                P[v * np + x + 2] = w[v];
-                if (x == gsrc0) P[v * np + 0] = w[v];
-                if (x == gsrc1) P[v * np + 1] = w[v];
-                if (x == gsrc2) P[v * np + nx + 2] = w[v];
-                if (x == gsrc3) P[v * np + nx + 3] = w[v];
+            for (int v = 0; v < NV; ++v) P[v * np + x + 2] = w[v];
+            // ghost slots: one branch per slot (at most four lanes take them)
+            const int gslot[4] = {0, 1, nx + 2, nx + 3};
+            const int gsrc[4] = {gsrc0, gsrc1, gsrc2, gsrc3};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (x == gsrc[k]) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) P[v * np + gslot[k]] = w[v];
+                }
             }
         }
         __syncthreads();
