@@ -73,3 +73,23 @@ def test_fp32_shock_tube_tracks_fp64():
     e = rel_l1(s32.get_state().cpu().numpy(), s64.get_state().cpu().numpy())
     print("fp32 shock tube L1: " + " ".join(f"{x:.2e}" for x in e), flush=True)
     assert np.all(e[[0, 1, 5]] <= 1e-4), e
+
+
+@pytest.mark.parametrize("n,bc", [((72, 40, 36), ((1, 1), (0, 0), (0, 0))), ((600, 4, 3), ((0, 0), (1, 1), (0, 0)))])
+def test_fp32_x_sweep_variants_and_long_rows(monkeypatch, n, bc):
+    """Float form: the whole-row and the marching x sweep agree to float
+    rounding, and rows longer than the row kernel takes (marching sweep by
+    default) match the oracle like any other shape."""
+    P = wl.random_smooth(n=n, seed=11, bc=bc)
+    g, q0 = _q0(P)
+    r_ref = oracle.rhs(g, q0)
+    rs = {}
+    for mode in ("rows", "march"):
+        monkeypatch.setenv("MFX_XSWEEP", mode)
+        s = gpu_solver(P["spec"], q0=q0, precision=MFX_FP32_MIXED)
+        rs[mode] = s.rhs().cpu().numpy()
+        err = rhs_rel_linf(rs[mode], r_ref, q0, P["spec"])
+        print(f"fp32 rhs {n} {mode}: " + " ".join(f"{e:.1e}" for e in err), flush=True)
+        assert np.all(err <= 1e-5), err
+    d = rhs_rel_linf(rs["rows"], rs["march"], q0, P["spec"])
+    assert np.all(d <= 1e-6), d

@@ -221,6 +221,47 @@ def test_zero_output_layer_reproduces_js_run():
     assert np.all(d <= 1e-4)
 
 
+def test_uniform_state_skips_the_network():
+    """A uniform state makes every stencil constant, so every wave skips the
+    network: the learned right-hand side equals the Jiang-Shu float form's
+    bit for bit, and both vanish to float rounding (the two x-boundary faces
+    of a row come from a separate kernel, whose multiply-adds the compiler may
+    fuse differently, so exact zeros are not guaranteed in float)."""
+    n = (40, 24, 20)
+    P = wl.random_smooth(n=n, seed=1, bc=((0, 0), (0, 0), (0, 0)))
+    w = np.empty_like(P["w"])
+    for v, val in enumerate((998.0, 0.0012, 12.0, -3.0, 0.5, 2.0e5, 0.999)):
+        w[v] = val
+    P = dict(P, w=w)
+    r_l = _solver(P, MFX_WENO5_LEARNED, omlp.init_params(2, out_scale=0.5)).rhs().cpu().numpy()
+    r_j = _solver(P, MFX_WENO5_JS).rhs().cpu().numpy()
+    assert np.array_equal(r_l, r_j)
+    scale = 998.0 * (12.0 ** 2) * n[0] + 2.0e5 * n[0]  # momentum flux over dx
+    print("uniform state: max |rhs| =", np.abs(r_l).max(), "nonzero", np.count_nonzero(r_l), flush=True)
+    assert np.abs(r_l).max() <= 1e-6 * scale
+
+
+@pytest.mark.parametrize("nx", [72, 600])
+def test_learned_x_sweep_variants_agree(monkeypatch, nx):
+    """Learned form: the whole-row and the marching x sweep take the same
+    decisions and agree to float rounding (600-cell rows use the marching
+    sweep in both settings)."""
+    P = wl.shock_droplet(n=(nx, 20, 16), seed=3)
+    params = omlp.init_params(4, out_scale=0.5)
+    out = {}
+    for mode in ("rows", "march"):
+        monkeypatch.setenv("MFX_XSWEEP", mode)
+        s = _solver(P, MFX_WENO5_LEARNED, params)
+        for _ in range(2):
+            s.rk3_step(2e-7)
+        out[mode] = (s.get_state().cpu().numpy(), s.stats())
+    d = rel_linf(out["rows"][0], out["march"][0])
+    print(f"learned x variants nx={nx}:", d, out["rows"][1]["fallback_faces"], out["march"][1]["fallback_faces"],
+          flush=True)
+    assert np.all(d <= 1e-4)
+    assert out["rows"][1]["status"] == 0 and out["march"][1]["status"] == 0
+
+
 def test_learned_needs_a_network():
     from paper_2409_10729_amd import MfxError
 

@@ -48,6 +48,7 @@ def test_set_primitive_matches_oracle_conversion():
     ((257, 1, 1), ((1, 1), (0, 0), (0, 0)), 6),
     ((2, 3, 2), ((0, 0), (0, 0), (1, 1)), 7),
     ((1, 1, 1), ((0, 0), (0, 0), (0, 0)), 8),
+    ((600, 3, 2), ((1, 1), (0, 0), (0, 0)), 9),  # rows longer than the row kernel takes: marching x sweep
 ])
 def test_rhs_matches_oracle(n, bc, seed):
     P = wl.random_smooth(n=n, seed=seed, bc=bc)
