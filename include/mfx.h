@@ -140,7 +140,11 @@ int mfx_rk3_step(mfx_ctx* ctx, double dt, double* dt_used_host);
  * and an edge whose weights are not finite or whose state is not admissible
  * (negative partial density, alpha1 outside [0,1], non-positive squared
  * sound speed) falls back to Jiang-Shu for all seven variables; mfx_stats
- * counts those edges. */
+ * counts those edges.  A variable whose 5-cell stencil is constant on all
+ * 64 cells a wavefront handles takes the Jiang-Shu edge values without
+ * evaluating the network (any convex weights give the constant).  The
+ * parameters may be replaced between steps; the call is ordered on the
+ * context's stream. */
 int mfx_set_mlp(mfx_ctx* ctx, const float* params_dev, int32_t n_params);
 
 /* Synchronise and report simulated time, step count, faces that fell back
