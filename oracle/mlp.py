@@ -17,6 +17,13 @@ Shu 2006; the network is this project's addition):
   where primes are stencil-normalised: (. - v2) / scale.
 Parameters, flat float vector of 1347: W1[32][5], b1[32], W2[32][32], b2[32],
 W3[3][32], b3[3].
+
+Shared (per-edge) form: one evaluation serves all variables of an edge.  Its
+input is the componentwise maximum over the variables of their features, its
+baseline the componentwise minimum over the variables of their Jiang-Shu
+weights, renormalised (the most cautious weights any variable asks for); the
+loss averages the squared normalised error over the variables.  A left edge
+is the right edge of the reversed stencils.
 """
 from __future__ import annotations
 
@@ -100,21 +107,34 @@ def forward(theta, X, OJS):
     return om, (X, A1, H1, A2, H2)
 
 
+def _per_var(C, T):
+    """Candidates [n,V,3] and targets [n,V] (a single variable may come as [n,3], [n])."""
+    C = np.asarray(C, dtype=np.float64)
+    T = np.asarray(T, dtype=np.float64)
+    if C.ndim == 2:
+        C, T = C[:, None, :], T[:, None]
+    return C, T
+
+
 def loss(theta, X, C, T, OJS, lam):
-    """C: normalised candidates [n,3]; T: normalised targets [n]; OJS: JS weights [n,3]."""
+    """C: normalised candidates [n,3] or [n,V,3]; T: normalised targets [n] or
+    [n,V]; OJS: baseline (Jiang-Shu) weights [n,3].  The error term is the
+    mean over samples of the mean over variables of the squared error."""
+    C, T = _per_var(C, T)
     om, _ = forward(theta, X, OJS)
-    r = (om * C).sum(axis=1) - T
-    return float(np.mean(r * r) + lam * np.mean(((om - OJS) ** 2).sum(axis=1)))
+    r = (om[:, None, :] * C).sum(axis=2) - T
+    return float(np.mean((r * r).mean(axis=1)) + lam * np.mean(((om - OJS) ** 2).sum(axis=1)))
 
 
 def loss_grad(theta, X, C, T, OJS, lam):
     """(loss, d loss / d theta) by reverse-mode differentiation."""
+    C, T = _per_var(C, T)
     p = unpack(theta)
-    n = X.shape[0]
+    n, nv = X.shape[0], C.shape[1]
     om, (X, A1, H1, A2, H2) = forward(theta, X, OJS)
-    r = (om * C).sum(axis=1) - T
-    L = float(np.mean(r * r) + lam * np.mean(((om - OJS) ** 2).sum(axis=1)))
-    dom = (2.0 / n) * r[:, None] * C + (2.0 * lam / n) * (om - OJS)
+    r = (om[:, None, :] * C).sum(axis=2) - T
+    L = float(np.mean((r * r).mean(axis=1)) + lam * np.mean(((om - OJS) ** 2).sum(axis=1)))
+    dom = (2.0 / (n * nv)) * (r[:, :, None] * C).sum(axis=1) + (2.0 * lam / n) * (om - OJS)
     # softmax backward
     dZ = om * (dom - (dom * om).sum(axis=1, keepdims=True))
     g = {}
@@ -129,6 +149,18 @@ def loss_grad(theta, X, C, T, OJS, lam):
     g["W1"] = dA1.T @ X
     g["b1"] = dA1.sum(axis=0)
     return L, pack(g)
+
+
+def edge_inputs(V, eps=1e-6):
+    """Shared form: V [n, V, 5] holds every variable's stencil at one edge
+    (right edge; pass the reversed stencils for a left edge).  Returns the
+    pooled features [n,5] (maximum over the variables) and the baseline
+    weights [n,3] (minimum over the variables of the Jiang-Shu weights,
+    renormalised)."""
+    V = np.asarray(V, dtype=np.float64)
+    f = features(V, eps).max(axis=1)
+    w = js_weights_right(V, eps).min(axis=1)
+    return f, w / w.sum(axis=1, keepdims=True)
 
 
 def init_params(seed=0, out_scale=0.0):

@@ -105,3 +105,75 @@ def test_bf16_round():
     assert r[0] == 1.0 and r[1] == 1.0078125 and r[2] == 1.0
     assert r[3] == -3.5
     assert abs(r[4] - 1e-3) / 1e-3 < 2 ** -8
+
+
+# ---- shared (per-edge) form
+
+def _edge_data(n=30, nv=7, seed=0):
+    rng = np.random.default_rng(seed)
+    V = rng.normal(size=(n, nv, 5)) * rng.uniform(0.1, 3.0, size=(n, nv, 1))
+    V[::3, 2, 3:] += 5.0
+    V[1::4, 4, :] = 1.5  # flat variables
+    f, B = mlp.edge_inputs(V)
+    C = mlp.candidates_right(V)
+    sc = V.max(axis=2, keepdims=True) - V.min(axis=2, keepdims=True)
+    Cn = np.where(sc > 0, (C - V[:, :, 2:3]) / np.where(sc > 0, sc, 1.0), 0.0)
+    T = rng.normal(size=(n, nv)) * 0.3
+    return f, Cn, T, B
+
+
+def test_edge_inputs_of_identical_variables_are_the_single_variable_ones():
+    rng = np.random.default_rng(4)
+    V1 = rng.normal(size=(50, 5)) * 2.0
+    f, B = mlp.edge_inputs(np.repeat(V1[:, None, :], 7, axis=1))
+    np.testing.assert_array_equal(f, mlp.features(V1))
+    np.testing.assert_allclose(B, mlp.js_weights_right(V1), rtol=1e-15)
+
+
+def test_edge_inputs_pool_by_max_and_min():
+    """Features are the componentwise maxima; the baseline is the normalised
+    componentwise minimum of the weights; flat variables contribute zero
+    features and the linear weights (1/10, 6/10, 3/10)."""
+    rng = np.random.default_rng(5)
+    V = rng.normal(size=(40, 3, 5))
+    V[:, 1, :] = 7.0  # flat
+    f, B = mlp.edge_inputs(V)
+    X = np.stack([mlp.features(V[:, v]) for v in range(3)], axis=1)
+    W = np.stack([mlp.js_weights_right(V[:, v]) for v in range(3)], axis=1)
+    assert np.array_equal(X[:, 1], np.zeros((40, 5)))
+    np.testing.assert_allclose(W[:, 1], np.broadcast_to([0.1, 0.6, 0.3], (40, 3)), rtol=1e-12)
+    np.testing.assert_array_equal(f, np.maximum(np.maximum(X[:, 0], X[:, 1]), X[:, 2]))
+    m = np.minimum(np.minimum(W[:, 0], W[:, 1]), W[:, 2])
+    np.testing.assert_allclose(B, m / m.sum(axis=1, keepdims=True), rtol=1e-15)
+    # mirrored edge: the reversed stencils swap beta0 and beta2
+    fm, _ = mlp.edge_inputs(V[:, :, ::-1])
+    np.testing.assert_allclose(fm, f[:, [2, 1, 0, 3, 4]], rtol=1e-15)
+
+
+def test_single_variable_loss_is_the_one_variable_case():
+    X, C, T, OJS = _data()
+    theta = mlp.init_params(3, out_scale=0.3)
+    a = mlp.loss_grad(theta, X, C, T, OJS, 0.05)
+    b = mlp.loss_grad(theta, X, C[:, None, :], T[:, None], OJS, 0.05)
+    assert a[0] == b[0] and np.array_equal(a[1], b[1])
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.1])
+def test_shared_backward_matches_finite_differences(lam):
+    X, C, T, OJS = _edge_data()
+    theta = mlp.init_params(6, out_scale=0.3)
+    L, g = mlp.loss_grad(theta, X, C, T, OJS, lam)
+    assert L == pytest.approx(mlp.loss(theta, X, C, T, OJS, lam), rel=1e-14)
+    h = 1e-6
+    fd = np.empty_like(theta)
+    for i in range(theta.size):
+        tp = theta.copy()
+        tm = theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd[i] = (mlp.loss(tp, X, C, T, OJS, lam) - mlp.loss(tm, X, C, T, OJS, lam)) / (2 * h)
+    o = 0
+    for name, size in (("W1", 160), ("b1", 32), ("W2", 1024), ("b2", 32), ("W3", 96), ("b3", 3)):
+        a, b = g[o:o + size], fd[o:o + size]
+        o += size
+        assert np.linalg.norm(a - b) <= 1e-6 * max(np.linalg.norm(b), 1e-12), name
