@@ -130,7 +130,8 @@ def main():
     import numpy as np
     import torch
 
-    from paper_2409_10729_amd import MFX_FP32_MIXED, MFX_FP64, MFX_WENO5_JS, MFX_WENO5_LEARNED, Solver
+    from paper_2409_10729_amd import (MFX_FP32_MIXED, MFX_FP64, MFX_WENO5_JS, MFX_WENO5_LEARNED,
+                                      MFX_WENO5_LEARNED_EDGE, Solver)
     from paper_2409_10729_amd import learned
     from paper_2409_10729_amd import workloads as wl
 
@@ -149,14 +150,16 @@ def main():
     N = args.n ** 3
     w_dev = torch.from_numpy(P["w"]).cuda()
 
-    mlp_dev = None
-    if not args.no_learned and os.path.exists(learned.DEFAULT_PARAMS):
-        mlp_dev = torch.from_numpy(learned.load_params()).cuda()
+    nets = {}
+    if not args.no_learned:
+        for wmode, path in ((MFX_WENO5_LEARNED, learned.DEFAULT_PARAMS), (MFX_WENO5_LEARNED_EDGE, learned.EDGE_PARAMS)):
+            if os.path.exists(path):
+                nets[wmode] = (torch.from_numpy(learned.load_params(path)).cuda(), path)
 
     def new_solver(precision, weights=MFX_WENO5_JS):
         s = Solver(P["spec"], precision=precision, weights=weights)
-        if weights == MFX_WENO5_LEARNED:
-            s.set_mlp(mlp_dev)
+        if weights != MFX_WENO5_JS:
+            s.set_mlp(nets[weights][0])
         s.set_primitive(w_dev)
         return s
 
@@ -261,8 +264,10 @@ def main():
         del s64
         dt_fixed = dts[0] if dts else 1e-9
         variants = [("fp32_mixed", MFX_WENO5_JS)]
-        if mlp_dev is not None:
+        if MFX_WENO5_LEARNED in nets:
             variants.append(("learned", MFX_WENO5_LEARNED))
+        if MFX_WENO5_LEARNED_EDGE in nets:
+            variants.append(("learned_edge", MFX_WENO5_LEARNED_EDGE))
         for name, weights in variants:
             print(f"[bench] {name}: replaying {len(dts)} steps", file=sys.stderr, flush=True)
             q, fb = replay(MFX_FP32_MIXED, dts, weights)
@@ -281,11 +286,11 @@ def main():
                 "density_l1_rel_vs_fp64": rho_l1,
                 "kernels": kf,
             }
-            if weights == MFX_WENO5_LEARNED:
+            if weights != MFX_WENO5_JS:
                 edges = 2 * N * sum(1 for k in P["spec"]["n"] if k > 1) * 3 * len(dts)
                 forms[name]["fallback_edges"] = fb
                 forms[name]["fallback_fraction"] = float(f"{fb / max(edges, 1):.3e}")
-                forms[name]["network"] = os.path.relpath(learned.DEFAULT_PARAMS, os.path.dirname(__file__))
+                forms[name]["network"] = os.path.relpath(nets[weights][1], os.path.dirname(os.path.abspath(__file__)))
             print(f"[bench] {name}: {msf_step:.3f} ms/step (x{ms_step / msf_step:.2f}), density L1 {rho_l1:.2e}",
                   file=sys.stderr, flush=True)
         del q64

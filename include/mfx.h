@@ -64,8 +64,13 @@ enum { MFX_FP64 = 0, MFX_FP32_MIXED = 1 };
 /* Nonlinear WENO weights.  MFX_WENO5_JS: Jiang-Shu.  MFX_WENO5_LEARNED: a
  * 5-32-32-3 MLP (set with mfx_set_mlp) maps scale-free smoothness features
  * to the three weights, with Jiang-Shu as the fallback wherever the learned
- * weights leave the convex set or the face state fails a positivity check. */
-enum { MFX_WENO5_JS = 0, MFX_WENO5_LEARNED = 1 };
+ * weights leave the convex set or the face state fails a positivity check;
+ * one evaluation per variable and edge.  MFX_WENO5_LEARNED_EDGE: the same
+ * network evaluated once per edge for all seven variables, on the
+ * componentwise maximum of the variables' features and correcting the
+ * componentwise minimum of their Jiang-Shu weights (renormalised); same
+ * fallback.  Both learned modes run in the MFX_FP32_MIXED form. */
+enum { MFX_WENO5_JS = 0, MFX_WENO5_LEARNED = 1, MFX_WENO5_LEARNED_EDGE = 2 };
 
 typedef struct {
     int32_t n[3];      /* interior cells (nx, ny, nz), each >= 1; n == 1 makes a direction inactive */
@@ -77,7 +82,7 @@ typedef struct {
     double cfl;        /* CFL number for the automatic time step, in (0, 1] */
     double weno_eps;   /* WENO epsilon (absolute), > 0; 1e-6 is Jiang-Shu's value */
     int32_t precision; /* MFX_FP64 or MFX_FP32_MIXED */
-    int32_t weights;   /* MFX_WENO5_JS or MFX_WENO5_LEARNED */
+    int32_t weights;   /* MFX_WENO5_JS, MFX_WENO5_LEARNED or MFX_WENO5_LEARNED_EDGE */
 } mfx_grid_desc;
 
 typedef struct mfx_ctx mfx_ctx;
@@ -134,8 +139,8 @@ int mfx_rk3_step(mfx_ctx* ctx, double dt, double* dt_used_host);
 /* Learned-weight parameters: n_params (= 1347) float32 values on the
  * device, laid out W1[32][5], b1[32], W2[32][32], b2[32], W3[3][32], b3[3].
  * Copied into the context and packed to bfloat16 for the matrix cores.
- * Needed before the first step of a context created with
- * MFX_WENO5_LEARNED (which runs in the MFX_FP32_MIXED precision form).  In
+ * Needed before the first step of a context created with a learned
+ * weights mode (which runs in the MFX_FP32_MIXED precision form).  In
  * that form every cell's two edge states come from the network's weights,
  * and an edge whose weights are not finite or whose state is not admissible
  * (negative partial density, alpha1 outside [0,1], non-positive squared
@@ -196,6 +201,17 @@ int mfx_mlp_face_targets(const mfx_grid_desc* fine_desc, const double* q_fine_de
 int mfx_mlp_features(const double* stencils, const double* targets, int64_t n, double eps, float* feat, float* cand,
                      float* tnorm, float* omega_js, void* stream);
 
+/* Shared (per-edge) form: samples of a 1D sample set as
+ * mfx_mlp_sample_stencils lays it out (stencils [14*ncell][5], targets
+ * [14*ncell]).  Sample j = side*ncell + i (j < 2*ncell) gets feat[j][5] =
+ * componentwise maximum over the seven variables of their features,
+ * omega_base[j][3] = their componentwise minimum Jiang-Shu weights,
+ * renormalised, and per variable cand[j][7][3], tnorm[j][7] normalised as
+ * in mfx_mlp_features; a variable with a flat stencil or with
+ * |tnorm| > tmax contributes zeros. */
+int mfx_mlp_features_edge(const double* stencils, const double* targets, int64_t ncell, double eps, double tmax,
+                          float* feat, float* cand, float* tnorm, float* omega_base, void* stream);
+
 /* Bytes of the packed bfloat16 matrix-core operands (mfx_mlp_pack). */
 size_t mfx_mlp_packed_bytes(void);
 /* Pack float32 parameters into the per-lane bfloat16 operand layout. */
@@ -209,15 +225,16 @@ int mfx_mlp_forward(const float* params, const void* packed, const float* feat, 
                     float* omega, void* stream);
 
 /* Loss and gradient of one minibatch, float32, deterministic (per-block
- * sums in a fixed order, then a fixed-order sum over blocks):
- *   L = mean_i (sum_k omega_ik cand_ik - tnorm_i)^2
- *     + lambda * mean_i sum_k (omega_ik - omega_js_ik)^2.
- * grad_out[1347]; loss_out (device float, may be NULL); ws of at least
- * mfx_mlp_grad_workspace(n) bytes. */
+ * sums in a fixed order, then a fixed-order sum over blocks), with nvar
+ * (1, or 7 for the shared form) variables per sample sharing its weights:
+ *   L = mean_i (1/nvar) sum_v (sum_k omega_ik cand_ivk - tnorm_iv)^2
+ *     + lambda * mean_i sum_k (omega_ik - omega_js_ik)^2,
+ * cand[n][nvar][3], tnorm[n][nvar].  grad_out[1347]; loss_out (device
+ * float, may be NULL); ws of at least mfx_mlp_grad_workspace(n) bytes. */
 size_t mfx_mlp_grad_workspace(int64_t n);
 int mfx_mlp_loss_grad(const float* params, const float* feat, const float* cand, const float* tnorm,
-                      const float* omega_js, int64_t n, float lambda, void* ws, size_t ws_bytes, float* grad_out,
-                      float* loss_out, void* stream);
+                      const float* omega_js, int64_t n, int32_t nvar, float lambda, void* ws, size_t ws_bytes,
+                      float* grad_out, float* loss_out, void* stream);
 
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) of the parameters with
  * first/second moment buffers m, v (1347 each); step counts from 1. */

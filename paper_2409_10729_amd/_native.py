@@ -15,12 +15,13 @@ LIB_PATH = os.path.join(_HERE, "libmfx.so")
 MFX_OK, MFX_EINVAL, MFX_EHIP, MFX_ENOMEM, MFX_ESTATE = 0, -1, -2, -3, -4
 MFX_BC_PERIODIC, MFX_BC_TRANSMISSIVE = 0, 1
 MFX_FP64, MFX_FP32_MIXED = 0, 1
-MFX_WENO5_JS, MFX_WENO5_LEARNED = 0, 1
+MFX_WENO5_JS, MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE = 0, 1, 2
 
 EXPORTED = (
     "mfx_workspace_bytes", "mfx_init_grid", "mfx_set_state", "mfx_set_primitive", "mfx_get_state",
     "mfx_rhs", "mfx_rk3_step", "mfx_set_mlp", "mfx_stats", "mfx_profile", "mfx_profile_read",
-    "mfx_destroy", "mfx_last_error", "mfx_mlp_sample_stencils", "mfx_mlp_face_targets", "mfx_mlp_features", "mfx_mlp_packed_bytes",
+    "mfx_destroy", "mfx_last_error", "mfx_mlp_sample_stencils", "mfx_mlp_face_targets", "mfx_mlp_features", "mfx_mlp_features_edge",
+    "mfx_mlp_packed_bytes",
     "mfx_mlp_pack", "mfx_mlp_forward", "mfx_mlp_grad_workspace", "mfx_mlp_loss_grad", "mfx_mlp_adam",
     "mfx_mlp_last_error",
 )
@@ -88,6 +89,8 @@ def lib():
         L.mfx_mlp_face_targets.restype = ctypes.c_int
         L.mfx_mlp_features.argtypes = [vp, vp, i64, ctypes.c_double, vp, vp, vp, vp, vp]
         L.mfx_mlp_features.restype = ctypes.c_int
+        L.mfx_mlp_features_edge.argtypes = [vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp, vp, vp, vp]
+        L.mfx_mlp_features_edge.restype = ctypes.c_int
         L.mfx_mlp_packed_bytes.argtypes = []
         L.mfx_mlp_packed_bytes.restype = ctypes.c_size_t
         L.mfx_mlp_pack.argtypes = [vp, vp, vp]
@@ -96,7 +99,8 @@ def lib():
         L.mfx_mlp_forward.restype = ctypes.c_int
         L.mfx_mlp_grad_workspace.argtypes = [i64]
         L.mfx_mlp_grad_workspace.restype = ctypes.c_size_t
-        L.mfx_mlp_loss_grad.argtypes = [vp, vp, vp, vp, vp, i64, ctypes.c_float, vp, ctypes.c_size_t, vp, vp, vp]
+        L.mfx_mlp_loss_grad.argtypes = [vp, vp, vp, vp, vp, i64, ctypes.c_int32, ctypes.c_float, vp, ctypes.c_size_t,
+                                         vp, vp, vp]
         L.mfx_mlp_loss_grad.restype = ctypes.c_int
         L.mfx_mlp_adam.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp]
         L.mfx_mlp_adam.restype = ctypes.c_int

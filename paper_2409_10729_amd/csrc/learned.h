@@ -87,6 +87,21 @@ struct LearnedLds {
     float z[2][64][4];     // network outputs (logits)
 };
 
+// Jiang-Shu smoothness indicators of the stencil a..e and its fourth
+// difference D.
+__device__ __forceinline__ void weno_betas(float a, float b, float c, float d, float e, float& b0, float& b1,
+                                           float& b2, float& D)
+{
+    const float k13 = 13.0f / 12.0f;
+    const float q0 = a - 2.f * b + c, h0 = a - 4.f * b + 3.f * c;
+    const float q1 = b - 2.f * c + d, h1 = b - d;
+    const float q2 = c - 2.f * d + e, h2 = 3.f * c - 4.f * d + e;
+    b0 = k13 * q0 * q0 + 0.25f * h0 * h0;
+    b1 = k13 * q1 * q1 + 0.25f * h1 * h1;
+    b2 = k13 * q2 * q2 + 0.25f * h2 * h2;
+    D = a - 4.f * b + 6.f * c - 4.f * d + e;
+}
+
 // Features of the stencil a..e reconstructed at its right edge: the
 // Jiang-Shu indicators over their sum S (with eps), |beta0 - beta2| / S, and
 // D^2 / (S + D^2) with D the fourth difference.  All in [0, 1].
@@ -96,15 +111,9 @@ struct LearnedLds {
 __device__ __forceinline__ void weno_features(float a, float b, float c, float d, float e, float eps, float x[5],
                                               float nlb[3])
 {
-    const float k13 = 13.0f / 12.0f;
-    const float q0 = a - 2.f * b + c, h0 = a - 4.f * b + 3.f * c;
-    const float q1 = b - 2.f * c + d, h1 = b - d;
-    const float q2 = c - 2.f * d + e, h2 = 3.f * c - 4.f * d + e;
-    const float b0 = k13 * q0 * q0 + 0.25f * h0 * h0;
-    const float b1 = k13 * q1 * q1 + 0.25f * h1 * h1;
-    const float b2 = k13 * q2 * q2 + 0.25f * h2 * h2;
+    float b0, b1, b2, D;
+    weno_betas(a, b, c, d, e, b0, b1, b2, D);
     const float S = b0 + b1 + b2 + eps;
-    const float D = a - 4.f * b + 6.f * c - 4.f * d + e;
     const float iS = __builtin_amdgcn_rcpf(S);  // features go to bfloat16: 1 ulp is ample
     x[0] = b0 * iS;
     x[1] = b1 * iS;
@@ -114,6 +123,50 @@ __device__ __forceinline__ void weno_features(float a, float b, float c, float d
     nlb[0] = -2.0f * log2f(eps + b0);
     nlb[1] = -2.0f * log2f(eps + b1);
     nlb[2] = -2.0f * log2f(eps + b2);
+}
+
+// Shared form, per variable: the features (as above) and the normalised
+// Jiang-Shu weights of the right edge (o) and of the mirrored left edge
+// (om, in the mirrored candidates' order), in the overflow-free ratio form
+// d_k (min_j s_j / s_k)^2, s_k = eps + beta_k.
+__device__ __forceinline__ void edge_stats(float a, float b, float c, float d, float e, float eps, float x[5],
+                                           float o[3], float om[3])
+{
+    float b0, b1, b2, D;
+    weno_betas(a, b, c, d, e, b0, b1, b2, D);
+    const float S = b0 + b1 + b2 + eps;
+    const float iS = __builtin_amdgcn_rcpf(S);
+    x[0] = b0 * iS;
+    x[1] = b1 * iS;
+    x[2] = b2 * iS;
+    x[3] = fabsf(b0 - b2) * iS;
+    x[4] = D * D * __builtin_amdgcn_rcpf(S + D * D);
+    const float s0 = eps + b0, s1 = eps + b1, s2 = eps + b2;
+    const float smin = fminf(s0, fminf(s1, s2));
+    float q0 = smin * __builtin_amdgcn_rcpf(s0), q1 = smin * __builtin_amdgcn_rcpf(s1),
+          q2 = smin * __builtin_amdgcn_rcpf(s2);
+    q0 *= q0;
+    q1 *= q1;
+    q2 *= q2;
+    const float ir = __builtin_amdgcn_rcpf(0.1f * q0 + 0.6f * q1 + 0.3f * q2);
+    o[0] = 0.1f * q0 * ir;
+    o[1] = 0.6f * q1 * ir;
+    o[2] = 0.3f * q2 * ir;
+    const float im = __builtin_amdgcn_rcpf(0.1f * q2 + 0.6f * q1 + 0.3f * q0);
+    om[0] = 0.1f * q2 * im;
+    om[1] = 0.6f * q1 * im;
+    om[2] = 0.3f * q0 * im;
+}
+
+// Both edge values of the stencil a..e with the right edge's weights om
+// and the mirrored left edge's weights oml.
+__device__ __forceinline__ void weno5_apply(const float om[3], const float oml[3], float a, float b, float c, float d,
+                                            float e, float& left, float& right)
+{
+    const float r0 = 2.f * a - 7.f * b + 11.f * c, r1 = -b + 5.f * c + 2.f * d, r2 = 2.f * c + 5.f * d - e;
+    const float l0 = 2.f * e - 7.f * d + 11.f * c, l1 = -d + 5.f * c + 2.f * b, l2 = 2.f * c + 5.f * b - a;
+    right = (om[0] * r0 + om[1] * r1 + om[2] * r2) * (1.0f / 6.0f);
+    left = (oml[0] * l0 + oml[1] * l1 + oml[2] * l2) * (1.0f / 6.0f);
 }
 
 constexpr float LOG2_D0 = -3.321928094887362f;  // log2(0.1)
@@ -205,10 +258,7 @@ __device__ __forceinline__ void weno5_learned(const MlpLane& m, LearnedLds* L, f
     const float lw[3] = {LOG2_D0 + nlb[0], LOG2_D1 + nlb[1], LOG2_D2 + nlb[2]};
     const float lwm[3] = {LOG2_D0 + nlb[2], LOG2_D1 + nlb[1], LOG2_D2 + nlb[0]};
     mlp_omega_pair(m, L, x, xm, lw, lwm, om, oml);
-    const float r0 = 2.f * a - 7.f * b + 11.f * c, r1 = -b + 5.f * c + 2.f * d, r2 = 2.f * c + 5.f * d - e;
-    const float l0 = 2.f * e - 7.f * d + 11.f * c, l1 = -d + 5.f * c + 2.f * b, l2 = 2.f * c + 5.f * b - a;
-    right = (om[0] * r0 + om[1] * r1 + om[2] * r2) * (1.0f / 6.0f);
-    left = (oml[0] * l0 + oml[1] * l1 + oml[2] * l2) * (1.0f / 6.0f);
+    weno5_apply(om, oml, a, b, c, d, e, left, right);
     finite_w = isfinite(om[0] + om[1] + om[2] + oml[0] + oml[1] + oml[2]);
 }
 

@@ -131,6 +131,56 @@ __global__ void __launch_bounds__(256) features_kernel(const double* __restrict_
     tn[i] = (float)((tg[i] - c) * inv);
 }
 
+// Shared form: one sample per (side, cell) of a 1D sample set laid out as
+// mfx_mlp_sample_stencils writes it (stencil (side*7 + v)*ncell + i).
+// Sample j = side*ncell + i gets the componentwise maximum of the seven
+// variables' features, the normalised componentwise minimum of their
+// Jiang-Shu weights, and per variable the stencil-normalised candidates and
+// target; a variable whose stencil is flat, or whose normalised target lies
+// more than `tmax` from the stencil value, contributes zeros.
+__global__ void __launch_bounds__(256) features_edge_kernel(const double* __restrict__ st,
+                                                            const double* __restrict__ tg, long long ncell, double eps,
+                                                            double tmax, float* __restrict__ feat,
+                                                            float* __restrict__ cand, float* __restrict__ tn,
+                                                            float* __restrict__ base)
+{
+    const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
+    if (j >= 2 * ncell) return;
+    const long long side = j / ncell, i = j % ncell;
+    double f[5] = {0, 0, 0, 0, 0}, wmin[3] = {1, 1, 1};
+    for (int v = 0; v < NV; ++v) {
+        const long long s = (side * NV + v) * ncell + i;
+        const double a = st[s * 5 + 0], b = st[s * 5 + 1], c = st[s * 5 + 2], d = st[s * 5 + 3], e = st[s * 5 + 4];
+        const double b0 = 13.0 / 12.0 * (a - 2 * b + c) * (a - 2 * b + c) + 0.25 * (a - 4 * b + 3 * c) * (a - 4 * b + 3 * c);
+        const double b1 = 13.0 / 12.0 * (b - 2 * c + d) * (b - 2 * c + d) + 0.25 * (b - d) * (b - d);
+        const double b2 = 13.0 / 12.0 * (c - 2 * d + e) * (c - 2 * d + e) + 0.25 * (3 * c - 4 * d + e) * (3 * c - 4 * d + e);
+        const double S = b0 + b1 + b2 + eps;
+        const double D = a - 4 * b + 6 * c - 4 * d + e;
+        const double x[5] = {b0 / S, b1 / S, b2 / S, fabs(b0 - b2) / S, D * D / (S + D * D)};
+        for (int k = 0; k < 5; ++k) f[k] = fmax(f[k], x[k]);
+        const double al0 = 0.1 / ((eps + b0) * (eps + b0)), al1 = 0.6 / ((eps + b1) * (eps + b1)),
+                     al2 = 0.3 / ((eps + b2) * (eps + b2));
+        const double sa = al0 + al1 + al2;
+        wmin[0] = fmin(wmin[0], al0 / sa);
+        wmin[1] = fmin(wmin[1], al1 / sa);
+        wmin[2] = fmin(wmin[2], al2 / sa);
+        const double mx = fmax(fmax(fmax(a, b), fmax(c, d)), e), mn = fmin(fmin(fmin(a, b), fmin(c, d)), e);
+        const double sc = mx - mn;
+        const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
+        double c0 = ((2 * a - 7 * b + 11 * c) / 6.0 - c) * inv, c1 = ((-b + 5 * c + 2 * d) / 6.0 - c) * inv,
+               c2 = ((2 * c + 5 * d - e) / 6.0 - c) * inv, t = (tg[s] - c) * inv;
+        if (!(fabs(t) <= tmax)) c0 = c1 = c2 = t = 0.0;
+        float* cv = cand + (j * NV + v) * 3;
+        cv[0] = (float)c0;
+        cv[1] = (float)c1;
+        cv[2] = (float)c2;
+        tn[j * NV + v] = (float)t;
+    }
+    for (int k = 0; k < 5; ++k) feat[j * 5 + k] = (float)f[k];
+    const double sw = wmin[0] + wmin[1] + wmin[2];
+    for (int k = 0; k < 3; ++k) base[j * 3 + k] = (float)(wmin[k] / sw);
+}
+
 // Float32 forward of one sample (ojs: its Jiang-Shu weights); h1, h2 hidden
 // activations and a1, a2 pre-activations returned for the backward pass.
 __device__ __forceinline__ void mlp_forward_f32(const float* P, const float x[5], const float ojs[3], float a1[MLP_H],
@@ -225,6 +275,9 @@ __global__ void __launch_bounds__(64) pack_kernel(const float* __restrict__ P, M
 // Stage 1 of the gradient: each block of TB samples runs forward and
 // backward per sample, parks the vectors the weight gradients need in LDS,
 // then sums each parameter's gradient over its samples in a fixed order.
+// NVAR variables share one sample's weights (cand[n][NVAR][3], tn[n][NVAR]);
+// the error term averages over them.
+template <int NVAR>
 __global__ void __launch_bounds__(TB) grad_partial_kernel(const float* __restrict__ P, const float* __restrict__ feat,
                                                           const float* __restrict__ cand, const float* __restrict__ tn,
                                                           const float* __restrict__ ojs, long long n, float lam,
@@ -239,18 +292,21 @@ __global__ void __launch_bounds__(TB) grad_partial_kernel(const float* __restric
     const long long i = (long long)blockIdx.x * TB + t;
     const bool valid = i < n;
     const long long ic = valid ? i : n - 1;
-    float x[5], c[3], o[3], a1[MLP_H], a2[MLP_H], h1[MLP_H], h2[MLP_H], om[3];
+    float x[5], o[3], a1[MLP_H], a2[MLP_H], h1[MLP_H], h2[MLP_H], om[3];
     for (int k = 0; k < 5; ++k) x[k] = feat[ic * 5 + k];
-    for (int k = 0; k < 3; ++k) {
-        c[k] = cand[ic * 3 + k];
-        o[k] = ojs[ic * 3 + k];
-    }
+    for (int k = 0; k < 3; ++k) o[k] = ojs[ic * 3 + k];
     mlp_forward_f32(sP, x, o, a1, a2, h1, h2, om);
-    const float r = om[0] * c[0] + om[1] * c[1] + om[2] * c[2] - tn[ic];
-    float reg = 0.f, dom[3];
+    float err = 0.f, dom[3] = {0.f, 0.f, 0.f};
+    for (int v = 0; v < NVAR; ++v) {
+        const float* c = cand + (ic * NVAR + v) * 3;
+        const float r = om[0] * c[0] + om[1] * c[1] + om[2] * c[2] - tn[ic * NVAR + v];
+        err += r * r;
+        for (int k = 0; k < 3; ++k) dom[k] += r * c[k];
+    }
+    float reg = 0.f;
     for (int k = 0; k < 3; ++k) {
         reg += (om[k] - o[k]) * (om[k] - o[k]);
-        dom[k] = 2.f * inv_n * r * c[k] + 2.f * lam * inv_n * (om[k] - o[k]);
+        dom[k] = 2.f * inv_n * (dom[k] * (1.f / NVAR)) + 2.f * lam * inv_n * (om[k] - o[k]);
     }
     const float sdo = dom[0] * om[0] + dom[1] * om[1] + dom[2] * om[2];
     float dz[3];
@@ -272,7 +328,7 @@ __global__ void __launch_bounds__(TB) grad_partial_kernel(const float* __restric
     }
     for (int k = 0; k < 5; ++k) sx[t][k] = x[k];
     for (int k = 0; k < 3; ++k) sdz[t][k] = dz[k];
-    sl[t] = valid ? (r * r + lam * reg) * inv_n : 0.f;
+    sl[t] = valid ? (err * (1.f / NVAR) + lam * reg) * inv_n : 0.f;
     __syncthreads();
     float* out = partial + (long long)blockIdx.x * GRAD_SLOTS;
     for (int p = t; p < GRAD_SLOTS; p += TB) {
@@ -415,6 +471,19 @@ int mfx_mlp_features(const double* stencils, const double* targets, int64_t n, d
     return check_launch("features_kernel");
 }
 
+int mfx_mlp_features_edge(const double* stencils, const double* targets, int64_t ncell, double eps, double tmax,
+                          float* feat, float* cand, float* tnorm, float* omega_base, void* stream)
+{
+    if (ncell < 0 || (ncell > 0 && (!stencils || !targets || !feat || !cand || !tnorm || !omega_base)))
+        return err(MFX_EINVAL, "bad arguments");
+    if (!(eps > 0.0) || !(tmax > 0.0)) return err(MFX_EINVAL, "eps and tmax must be > 0");
+    if (ncell == 0) return MFX_OK;
+    features_edge_kernel<<<blocks_for(2 * ncell, 256), 256, 0, (hipStream_t)stream>>>(stencils, targets, ncell, eps,
+                                                                                      tmax, feat, cand, tnorm,
+                                                                                      omega_base);
+    return check_launch("features_edge_kernel");
+}
+
 int mfx_mlp_pack(const float* params, void* packed, void* stream)
 {
     if (!params || !packed) return err(MFX_EINVAL, "NULL argument");
@@ -442,15 +511,20 @@ size_t mfx_mlp_grad_workspace(int64_t n)
 }
 
 int mfx_mlp_loss_grad(const float* params, const float* feat, const float* cand, const float* tnorm,
-                      const float* omega_js, int64_t n, float lambda, void* ws, size_t ws_bytes, float* grad_out,
-                      float* loss_out, void* stream)
+                      const float* omega_js, int64_t n, int32_t nvar, float lambda, void* ws, size_t ws_bytes,
+                      float* grad_out, float* loss_out, void* stream)
 {
     if (n <= 0 || !params || !feat || !cand || !tnorm || !omega_js || !grad_out) return err(MFX_EINVAL, "bad arguments");
+    if (nvar != 1 && nvar != NV) return err(MFX_EINVAL, "nvar must be 1 or 7");
     if (!ws || ws_bytes < mfx_mlp_grad_workspace(n)) return err(MFX_ENOMEM, "gradient workspace too small");
     const unsigned nb = blocks_for(n, TB);
     float* partial = static_cast<float*>(ws);
-    grad_partial_kernel<<<nb, TB, 0, (hipStream_t)stream>>>(params, feat, cand, tnorm, omega_js, n, lambda,
-                                                            1.0f / (float)n, partial);
+    if (nvar == 1)
+        grad_partial_kernel<1><<<nb, TB, 0, (hipStream_t)stream>>>(params, feat, cand, tnorm, omega_js, n, lambda,
+                                                                   1.0f / (float)n, partial);
+    else
+        grad_partial_kernel<NV><<<nb, TB, 0, (hipStream_t)stream>>>(params, feat, cand, tnorm, omega_js, n, lambda,
+                                                                    1.0f / (float)n, partial);
     int rc = check_launch("grad_partial_kernel");
     if (rc) return rc;
     grad_reduce_kernel<<<blocks_for(GRAD_SLOTS, 256), 256, 0, (hipStream_t)stream>>>(partial, nb, grad_out, loss_out);

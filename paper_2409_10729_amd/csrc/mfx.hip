@@ -196,7 +196,7 @@ bool validate(const mfx_grid_desc* d, std::string& why)
         why = "unknown precision";
         return false;
     }
-    if (d->weights != MFX_WENO5_JS && d->weights != MFX_WENO5_LEARNED) {
+    if (d->weights != MFX_WENO5_JS && d->weights != MFX_WENO5_LEARNED && d->weights != MFX_WENO5_LEARNED_EDGE) {
         why = "unknown weights mode";
         return false;
     }
@@ -430,7 +430,7 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
     const LaunchArgs la{&sg, c->stream, &c->g, qs, qn, c->r, out, dt_dev, dt_arg, c->bface, c->mlp, c->fallback};
-    if (c->desc.weights == MFX_WENO5_LEARNED)
+    if (c->desc.weights != MFX_WENO5_JS)
         launch_dispatch<float, true>(d, first != 0, mode, la);
     else if (c->desc.precision == MFX_FP32_MIXED)
         launch_dispatch<float, false>(d, first != 0, mode, la);
@@ -500,7 +500,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     *out = nullptr;
     std::string why;
     if (!validate(desc, why)) return fail(nullptr, MFX_EINVAL, why);
-    if (desc->weights == MFX_WENO5_LEARNED && desc->precision != MFX_FP32_MIXED)
+    if (desc->weights != MFX_WENO5_JS && desc->precision != MFX_FP32_MIXED)
         return fail(nullptr, MFX_EINVAL, "learned weights run in the MFX_FP32_MIXED precision form");
     if (!ws_dev) return fail(nullptr, MFX_EINVAL, "workspace pointer is NULL");
     if (reinterpret_cast<uintptr_t>(ws_dev) % ALIGN != 0)
@@ -561,6 +561,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     g.P1 = desc->gamma[0] * desc->pi_inf[0] / (desc->gamma[0] - 1.0);
     g.P2 = desc->gamma[1] * desc->pi_inf[1] / (desc->gamma[1] - 1.0);
     g.eps = desc->weno_eps;
+    g.edge_weights = desc->weights == MFX_WENO5_LEARNED_EDGE ? 1 : 0;
     g.cfl = desc->cfl;
 
     if (hipMemsetAsync(c->ws + L.scal, 0, 64, c->stream) != hipSuccess) {
@@ -624,7 +625,7 @@ int mfx_get_state(mfx_ctx* c, double* q_dev_out)
 namespace {
 int need_mlp(mfx_ctx* c)
 {
-    if (c->desc.weights == MFX_WENO5_LEARNED && !c->has_mlp)
+    if (c->desc.weights != MFX_WENO5_JS && !c->has_mlp)
         return fail(c, MFX_EINVAL, "learned weights selected but no network set (mfx_set_mlp)");
     return MFX_OK;
 }

@@ -48,6 +48,7 @@ struct Grid {
     double G1, G2, P1, P2;  // per-fluid 1/(gamma-1) and gamma pi/(gamma-1)
     double eps;
     double cfl;
+    int edge_weights;  // learned weights: one network evaluation per edge for all variables
 };
 
 __device__ __forceinline__ int map_cell(int c, int n, int bclo, int bchi)
@@ -235,8 +236,82 @@ struct ReconLearned {
     Mix<float> mix;
     bool valid;  // this lane owns a real cell (only those are counted)
     unsigned fallbacks;
+    bool edge;  // one evaluation per edge for all variables
     template <class Win>
     __device__ __forceinline__ void cell_win(const Win& W, float eps, float lft[NV], float rgt[NV])
+    {
+        if (edge)
+            cell_edge(W, eps, lft, rgt);
+        else
+            cell_var(W, eps, lft, rgt);
+    }
+
+    // Shared form: the features of all variables pooled by their maximum,
+    // the Jiang-Shu weights pooled by their minimum (renormalisation is left
+    // to the softmax, which ignores a common offset of the log-weights);
+    // one pair of network evaluations (right edge, mirrored left edge) for
+    // the cell, its weights applied to every variable.
+    template <class Win>
+    __device__ __forceinline__ void cell_edge(const Win& W, float eps, float lft[NV], float rgt[NV])
+    {
+        float lj[NV], rj[NV];
+        float f[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+        float wr[3] = {1.f, 1.f, 1.f}, wm[3] = {1.f, 1.f, 1.f};
+        bool flat = true;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const float a = W(0, v), b = W(1, v), c = W(2, v), d = W(3, v), e = W(4, v);
+            weno5<float>(a, b, c, d, e, eps, lj[v], rj[v]);
+            flat = flat && a == b && b == c && c == d && d == e;
+            float x[5], o[3], om[3];
+            edge_stats(a, b, c, d, e, eps, x, o, om);
+#pragma unroll
+            for (int k = 0; k < 5; ++k) f[k] = fmaxf(f[k], x[k]);
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                wr[k] = fminf(wr[k], o[k]);
+                wm[k] = fminf(wm[k], om[k]);
+            }
+        }
+        if (__all(flat)) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                lft[v] = lj[v];
+                rgt[v] = rj[v];
+            }
+            return;
+        }
+        const float fm[5] = {f[2], f[1], f[0], f[3], f[4]};
+        const float lw[3] = {log2f(wr[0]), log2f(wr[1]), log2f(wr[2])};
+        const float lwm[3] = {log2f(wm[0]), log2f(wm[1]), log2f(wm[2])};
+        float om[3], oml[3];
+        mlp_omega_pair(m, lds, f, fm, lw, lwm, om, oml);
+        const bool fin = isfinite(om[0] + om[1] + om[2] + oml[0] + oml[1] + oml[2]);
+        float ll[NV], rl[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const float a = W(0, v), b = W(1, v), c = W(2, v), d = W(3, v), e = W(4, v);
+            weno5_apply(om, oml, a, b, c, d, e, ll[v], rl[v]);
+        }
+        finish(fin, lj, rj, ll, rl, lft, rgt);
+    }
+
+    // Fallback per edge and counting (both forms).
+    __device__ __forceinline__ void finish(bool fin, const float lj[NV], const float rj[NV], const float ll[NV],
+                                           const float rl[NV], float lft[NV], float rgt[NV])
+    {
+        const bool okR = fin && admissible(mix, rl);
+        const bool okL = fin && admissible(mix, ll);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            rgt[v] = okR ? rl[v] : rj[v];
+            lft[v] = okL ? ll[v] : lj[v];
+        }
+        if (valid) fallbacks += (okR ? 0u : 1u) + (okL ? 0u : 1u);
+    }
+
+    template <class Win>
+    __device__ __forceinline__ void cell_var(const Win& W, float eps, float lft[NV], float rgt[NV])
     {
         float lj[NV], rj[NV], ll[NV], rl[NV];
         bool fin = true;
@@ -256,14 +331,7 @@ struct ReconLearned {
                 fin = fin && f;
             }
         }
-        const bool okR = fin && admissible(mix, rl);
-        const bool okL = fin && admissible(mix, ll);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            rgt[v] = okR ? rl[v] : rj[v];
-            lft[v] = okL ? ll[v] : lj[v];
-        }
-        if (valid) fallbacks += (okR ? 0u : 1u) + (okL ? 0u : 1u);
+        finish(fin, lj, rj, ll, rl, lft, rgt);
     }
     __device__ __forceinline__ void cell(const float W[5][NV], float eps, float lft[NV], float rgt[NV])
     {
@@ -297,7 +365,8 @@ __device__ __forceinline__ typename ReconOf<T, LEARNED>::type make_recon(const G
         // one 4 KB slot per wave; blocks have at most LEARNED_MAX_WAVES waves
         __shared__ LearnedLds slots[LEARNED_MAX_WAVES];
         return ReconLearned{mlp[threadIdx.x & 63], &slots[threadIdx.x >> 6],
-                            Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u};
+                            Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u,
+                            g.edge_weights != 0};
     } else {
         (void)g;
         (void)mlp;

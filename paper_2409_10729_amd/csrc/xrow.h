@@ -133,6 +133,15 @@ __host__ __device__ inline XrowLayout xrow_layout(int nx, size_t elem)
 
 inline size_t xrow_lds_bytes(int nx, size_t elem) { return elem * xrow_layout(nx, elem).elems; }
 
+// Window of cell x inside the row's primitives in LDS: w(k, v) = P[v][x + k]
+// (cell x-2+k; ghost slots included).
+template <typename T>
+struct RowWindow {
+    const T* p;  // P + x
+    int np;
+    __device__ __forceinline__ T operator()(int k, int v) const { return p[v * np + k]; }
+};
+
 // Row kernel.
 template <typename T, bool FIRST, int MODE, bool LEARNED>
 __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const double* __restrict__ qs, const double* qn,
@@ -198,12 +207,18 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
             for (int v = 0; v < NV; ++v) qc[v] = qs[v * g.N + (row + 1) * nx + xc];
         }
         // 2. reconstruct own cell: left edge to LDS, right edge kept
-        T rgt[NV], lft[NV], Wc[5][NV];
+        T rgt[NV], lft[NV];
+        if constexpr (LEARNED) {
+            // the learned forms read the window from LDS as they go
+            recon.cell_win(RowWindow<T>{P + xc, np}, eps, lft, rgt);
+        } else {
+            T Wc[5][NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+            for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int k = 0; k < 5; ++k) Wc[k][v] = P[v * np + xc + k];
-        recon.cell(Wc, eps, lft, rgt);
+                for (int k = 0; k < 5; ++k) Wc[k][v] = P[v * np + xc + k];
+            recon.cell(Wc, eps, lft, rgt);
+        }
         if (has) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) L[v * nx + x] = lft[v];

@@ -31,7 +31,8 @@ Training, two stages:
      loss yet leaves the solution error at or above Jiang-Shu's; stage 2 is
      what makes the learned form more accurate.
 
-    python -m paper_2409_10729_amd.learned --out paper_2409_10729_amd/data/mlp_weno5.npy
+    python -m paper_2409_10729_amd.learned            # per-variable form
+    python -m paper_2409_10729_amd.learned --edge     # shared per-edge form
 """
 from __future__ import annotations
 
@@ -49,7 +50,8 @@ from . import MFX_FP64, Solver, _native
 from . import workloads as wl
 
 DATA_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data")
-DEFAULT_PARAMS = os.path.join(DATA_DIR, "mlp_weno5.npy")
+DEFAULT_PARAMS = os.path.join(DATA_DIR, "mlp_weno5.npy")  # per-variable form
+EDGE_PARAMS = os.path.join(DATA_DIR, "mlp_weno5_edge.npy")  # shared per-edge form
 N_PARAMS = _native.MLP_PARAMS
 H = 32
 
@@ -149,9 +151,28 @@ def features(stencils, targets, eps: float = 1e-6):
     return feat, cand, tn, ojs
 
 
-def build_dataset(tube_seeds, slab_seeds, log=print):
+def features_edge(stencils, targets, tmax: float = 2.0, eps: float = 1e-6):
+    """Shared form: (feat [2n,5], cand [2n,7,3], tnorm [2n,7], base [2n,3])
+    of one 1D sample set of n cells (``mfx_mlp_features_edge``)."""
+    import torch
+
+    ncell = stencils.shape[0] // 14
+    m = 2 * ncell
+    f32 = dict(dtype=torch.float32, device="cuda")
+    feat = torch.empty((m, 5), **f32)
+    cand = torch.empty((m, 7, 3), **f32)
+    tn = torch.empty((m, 7), **f32)
+    base = torch.empty((m, 3), **f32)
+    _native.check_mlp(_native.lib().mfx_mlp_features_edge(_p(stencils), _p(targets), ncell, eps, tmax, _p(feat),
+                                                          _p(cand), _p(tn), _p(base), _stream()))
+    return feat, cand, tn, base
+
+
+def build_dataset(tube_seeds, slab_seeds, edge: bool = False, log=print):
     """Samples from seeded runs, flat stencils dropped; returns the feature
-    tensors and the raw sample count before filtering."""
+    tensors and the raw sample count before filtering.  edge=True builds the
+    shared per-edge samples (all seven variables of an edge together;
+    edges where every variable is flat or off target are dropped)."""
     import torch
 
     chunks = []
@@ -159,6 +180,14 @@ def build_dataset(tube_seeds, slab_seeds, log=print):
         chunks += shock_tube_samples(s)
     for s in slab_seeds:
         chunks += slab_samples(s)
+    if edge:
+        parts = [features_edge(st, tg) for st, tg in chunks]
+        feat, cand, tn, base = (torch.cat([p[k] for p in parts]) for k in range(4))
+        raw = feat.shape[0]
+        keep = (cand.abs().sum(dim=(1, 2)) > 0) | (tn.abs().sum(dim=1) > 0)
+        out = tuple(x[keep].contiguous() for x in (feat, cand, tn, base))
+        log(f"[learned] edge samples: {raw} drawn, {out[0].shape[0]} kept")
+        return out + (raw,)
     st = torch.cat([c[0] for c in chunks])
     tg = torch.cat([c[1] for c in chunks])
     raw = st.shape[0]
@@ -178,15 +207,17 @@ def build_dataset(tube_seeds, slab_seeds, log=print):
 # ------------------------------------------------------------------ training
 
 def loss_grad(params, feat, cand, tn, ojs, lam, ws=None):
+    """Loss and gradient; cand [m,3] or [m,7,3] (shared form)."""
     import torch
 
     m = feat.shape[0]
+    nvar = cand.shape[1] if cand.dim() == 3 else 1
     need = int(_native.lib().mfx_mlp_grad_workspace(m))
     if ws is None or ws.numel() < need:
         ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     grad = torch.empty(N_PARAMS, dtype=torch.float32, device="cuda")
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    _native.check_mlp(_native.lib().mfx_mlp_loss_grad(_p(params), _p(feat), _p(cand), _p(tn), _p(ojs), m,
+    _native.check_mlp(_native.lib().mfx_mlp_loss_grad(_p(params), _p(feat), _p(cand), _p(tn), _p(ojs), m, nvar,
                                                       ctypes.c_float(lam), _p(ws), ws.numel(), _p(grad), _p(loss),
                                                       _stream()))
     return loss, grad, ws
@@ -268,10 +299,12 @@ class SolutionObjective:
     """
 
     def __init__(self, tube_seeds=(0, 1, 2, 3), slab_seeds=(1000, 1001, 1002, 1003), n_tube=500, tube_steps=150,
-                 refine=8, n_slab=256, slab_steps=200, penalty=10.0):
+                 refine=8, n_slab=256, slab_steps=200, penalty=10.0, weights=None):
         import torch
 
         from . import MFX_FP32_MIXED, MFX_WENO5_JS, MFX_WENO5_LEARNED
+
+        weights = MFX_WENO5_LEARNED if weights is None else weights
 
         self.penalty = penalty
         self.runs = []
@@ -303,7 +336,7 @@ class SolutionObjective:
         # single-row) runs of one evaluation overlap on the device
         for r in self.runs:
             r["stream"] = torch.cuda.Stream()
-            r["learned"] = Solver(r["spec"], MFX_FP32_MIXED, MFX_WENO5_LEARNED, stream=r["stream"])
+            r["learned"] = Solver(r["spec"], MFX_FP32_MIXED, weights, stream=r["stream"])
             r["js"] = Solver(r["spec"], MFX_FP32_MIXED, MFX_WENO5_JS, stream=r["stream"])
         for r, e in zip(self.runs, self._run_all("js")):
             assert math.isfinite(e), "Jiang-Shu reference run failed"
@@ -400,13 +433,17 @@ def js_validation_loss(data, lam):
     """Loss of the Jiang-Shu weights themselves on the same samples (the
     reference the network has to beat): error term only, regulariser 0."""
     feat, cand, tn, ojs = data
-    r = (ojs * cand).sum(dim=1) - tn
+    if cand.dim() == 3:
+        r = (ojs[:, None, :] * cand).sum(dim=2) - tn
+    else:
+        r = (ojs * cand).sum(dim=1) - tn
     return float((r * r).mean().item())
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
-    ap.add_argument("--out", default=DEFAULT_PARAMS)
+    ap.add_argument("--out", default=None, help="default: data/mlp_weno5.npy, or data/mlp_weno5_edge.npy with --edge")
+    ap.add_argument("--edge", action="store_true", help="train the shared per-edge form")
     ap.add_argument("--tubes", type=int, default=96, help="shock-tube runs (seeds 0..N-1)")
     ap.add_argument("--slabs", type=int, default=48, help="advected-slab runs (seeds 1000..)")
     ap.add_argument("--epochs", type=int, default=20)
@@ -416,19 +453,27 @@ def main(argv=None):
     ap.add_argument("--ft-pairs", type=int, default=16)
     ap.add_argument("--ft-sigma", type=float, default=0.05)
     ap.add_argument("--ft-lr", type=float, default=0.05)
+    ap.add_argument("--ft-tubes", type=int, default=4, help="fine-tuning shock tubes (seeds 0..N-1)")
+    ap.add_argument("--ft-slabs", type=int, default=4, help="fine-tuning slabs (seeds 1000..)")
     args = ap.parse_args(argv)
     import torch
 
+    from . import MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE
+
     assert torch.cuda.is_available(), "training runs on the GPU"
+    if args.out is None:
+        args.out = EDGE_PARAMS if args.edge else DEFAULT_PARAMS
     t0 = time.time()
-    *data, raw = build_dataset(range(args.tubes), range(1000, 1000 + args.slabs))
+    *data, raw = build_dataset(range(args.tubes), range(1000, 1000 + args.slabs), edge=args.edge)
     t1 = time.time()
     params, hist = train(tuple(data), epochs=args.epochs, lam=args.lam, lr=args.lr)
     t2 = time.time()
     js = js_validation_loss(tuple(data), args.lam)
     ft_hist = []
     if args.ft_iters > 0:
-        obj = SolutionObjective()
+        obj = SolutionObjective(tube_seeds=tuple(range(args.ft_tubes)),
+                                slab_seeds=tuple(range(1000, 1000 + args.ft_slabs)),
+                                weights=MFX_WENO5_LEARNED_EDGE if args.edge else MFX_WENO5_LEARNED)
         params, ft_hist = finetune(params, obj, iters=args.ft_iters, pairs=args.ft_pairs, sigma=args.ft_sigma,
                                    lr=args.ft_lr)
     t3 = time.time()
@@ -437,9 +482,11 @@ def main(argv=None):
     meta = {"samples_drawn": raw, "samples_kept": int(data[0].shape[0]), "epochs": args.epochs, "lam": args.lam,
             "lr": args.lr, "val_loss": hist, "js_error_term_all_samples": js,
             "data_seconds": round(t1 - t0, 1), "train_seconds": round(t2 - t1, 1),
-            "tubes": args.tubes, "slabs": args.slabs,
+            "tubes": args.tubes, "slabs": args.slabs, "form": "edge" if args.edge else "variable",
             "finetune": {"iters": args.ft_iters, "pairs": args.ft_pairs, "sigma": args.ft_sigma, "lr": args.ft_lr,
-                         "objective": ft_hist, "seconds": round(t3 - t2, 1)}}
+                         "tubes": args.ft_tubes, "slabs": args.ft_slabs, "objective": ft_hist,
+                         "seconds": round(t3 - t2, 1)},
+            "command": "python -m paper_2409_10729_amd.learned " + " ".join(sys.argv[1:] if argv is None else argv)}
     with open(os.path.splitext(args.out)[0] + ".json", "w") as f:
         json.dump(meta, f, indent=1)
     print(json.dumps(meta), flush=True)

@@ -24,7 +24,7 @@ import pytest
 import oracle
 from oracle import exact_riemann as er
 from oracle import mlp as omlp
-from paper_2409_10729_amd import MFX_FP32_MIXED, MFX_WENO5_JS, MFX_WENO5_LEARNED
+from paper_2409_10729_amd import MFX_FP32_MIXED, MFX_WENO5_JS, MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE
 from paper_2409_10729_amd import workloads as wl
 from parity_util import rel_linf
 
@@ -333,3 +333,126 @@ def test_gain_advected_slab():
         errs[name] = _l1(q[6], P["alpha_cell_avg"](t))
     print("advected slab alpha1 L1:", errs, flush=True)
     assert errs["learned"] < errs["js"]
+
+
+# ---- shared (per-edge) form
+
+def _edge_set(ncell, seed):
+    """A 1D sample set in the layout of mfx_mlp_sample_stencils:
+    stencil (side*7 + v)*ncell + i, with flat variables and far targets mixed in."""
+    rng = np.random.default_rng(seed)
+    V = rng.normal(size=(2, 7, ncell, 5)) * rng.uniform(0.01, 100.0, size=(2, 7, ncell, 1))
+    V[:, 3, ::3, :] = 4.0  # flat
+    V[:, 5, 1::5, 3:] += 50.0  # jumps
+    T = V[..., 2] + (V[..., 3] - V[..., 2]) * rng.uniform(-0.5, 0.8, size=V.shape[:3])
+    T[:, 6, ::7] += 1e4  # far off: dropped per variable
+    return V, T
+
+
+def _edge_oracle(V, T, tmax=2.0):
+    ncell = V.shape[2]
+    S = np.transpose(V, (0, 2, 1, 3)).reshape(2 * ncell, 7, 5)  # sample j = side*ncell + i
+    Tj = np.transpose(T, (0, 2, 1)).reshape(2 * ncell, 7)
+    f, B = omlp.edge_inputs(S)
+    sc = S.max(axis=2) - S.min(axis=2)
+    inv = np.where(sc > 0, 1.0 / np.where(sc > 0, sc, 1.0), 0.0)
+    C = (omlp.candidates_right(S) - S[:, :, 2:3]) * inv[:, :, None]
+    t = (Tj - S[:, :, 2]) * inv
+    off = ~(np.abs(t) <= tmax)
+    C[off] = 0.0
+    t[off] = 0.0
+    return f, C, t, B
+
+
+def test_edge_features_match_oracle():
+    from paper_2409_10729_amd import learned
+
+    V, T = _edge_set(500, 0)
+    st = torch.from_numpy(np.ascontiguousarray(V.reshape(-1, 5))).cuda()
+    tg = torch.from_numpy(np.ascontiguousarray(T.reshape(-1))).cuda()
+    feat, cand, tn, base = (x.cpu().numpy().astype(np.float64) for x in learned.features_edge(st, tg))
+    f, C, t, B = _edge_oracle(V, T)
+    np.testing.assert_allclose(feat, f, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(base, B, rtol=1e-6, atol=1e-7)
+    np.testing.assert_allclose(cand, C, rtol=1e-6, atol=1e-6)
+    np.testing.assert_allclose(tn, t, rtol=1e-6, atol=1e-6)
+    assert np.count_nonzero(C[:, 3]) < C[:, 3].size and np.count_nonzero(t[:, 6] == 0) > 0
+
+
+@pytest.mark.parametrize("lam", [0.0, 0.05])
+def test_edge_loss_grad_matches_oracle(lam):
+    from paper_2409_10729_amd import learned
+
+    V, T = _edge_set(700, 1)
+    st = torch.from_numpy(np.ascontiguousarray(V.reshape(-1, 5))).cuda()
+    tg = torch.from_numpy(np.ascontiguousarray(T.reshape(-1))).cuda()
+    feat, cand, tn, base = learned.features_edge(st, tg)
+    theta = omlp.init_params(7, out_scale=0.5).astype(np.float32)
+    loss, grad, _ = learned.loss_grad(torch.from_numpy(theta).cuda(), feat, cand, tn, base, lam)
+    L_ref, g_ref = omlp.loss_grad(theta.astype(np.float64), *(x.cpu().numpy().astype(np.float64)
+                                                                for x in (feat, cand, tn, base)), lam)
+    assert float(loss.item()) == pytest.approx(L_ref, rel=1e-5)
+    g = grad.cpu().numpy().astype(np.float64)
+    o = 0
+    for name, size in (("W1", 160), ("b1", 32), ("W2", 1024), ("b2", 32), ("W3", 96), ("b3", 3)):
+        e = np.linalg.norm(g[o:o + size] - g_ref[o:o + size]) / np.linalg.norm(g_ref[o:o + size])
+        print(f"edge grad {name}: rel L2 {e:.2e}", flush=True)
+        assert e <= 1e-4, name
+        o += size
+
+
+def test_edge_form_nan_network_falls_back_and_uniform_state_skips():
+    P = wl.shock_droplet(n=(40, 24, 20), seed=1)
+    nan = np.full(1347, np.nan, dtype=np.float32)
+    s_e = _solver(P, MFX_WENO5_LEARNED_EDGE, nan)
+    s_j = _solver(P, MFX_WENO5_JS)
+    for _ in range(3):
+        s_e.rk3_step(2e-7)
+        s_j.rk3_step(2e-7)
+    st = s_e.stats()
+    d = rel_linf(s_e.get_state().cpu().numpy(), s_j.get_state().cpu().numpy())
+    print("edge form, nan network vs JS:", d, "fallback edges", st["fallback_faces"], flush=True)
+    assert st["fallback_faces"] > 0 and st["status"] == 0 and np.all(d <= 1e-6)
+    w = np.empty_like(P["w"])
+    for v, val in enumerate((998.0, 0.0012, 12.0, -3.0, 0.5, 2.0e5, 0.999)):
+        w[v] = val
+    U = dict(P, w=w)
+    r_e = _solver(U, MFX_WENO5_LEARNED_EDGE, omlp.init_params(2, out_scale=0.5)).rhs().cpu().numpy()
+    r_j = _solver(U, MFX_WENO5_JS).rhs().cpu().numpy()
+    assert np.array_equal(r_e, r_j)
+
+
+EDGE_TRAINED = os.path.join(os.path.dirname(TRAINED), "mlp_weno5_edge.npy")
+
+
+@pytest.mark.skipif(not os.path.exists(EDGE_TRAINED), reason="no trained shared network committed")
+def test_edge_gain_shock_tube():
+    """Shared form on the held-out 1000-cell tube: L1 of density, velocity and
+    pressure against the exact solution below the Jiang-Shu form's."""
+    params = np.load(EDGE_TRAINED, allow_pickle=False)
+    P = wl.shock_tube()
+    g = oracle.make_grid(P["spec"])
+    errs = {}
+    for name, weights, prm in (("js", MFX_WENO5_JS, None), ("edge", MFX_WENO5_LEARNED_EDGE, params)):
+        s = _solver(P, weights, prm)
+        t = sum(s.rk3_step(sync=True) for _ in range(300))
+        w = oracle.cons_to_prim(g, s.get_state().cpu().numpy()).reshape(7, -1)
+        x = (np.arange(1000) + 0.5) / 1000
+        re, ue, pe, _ = er.sample(er.Side(1000.0, 0, 1e9, 4.4, 6e8), er.Side(50.0, 0, 1e5, 1.4, 0.0), (x - 0.5) / t)
+        errs[name] = (_l1(w[0] + w[1], re), np.abs(w[2] - ue).mean() / np.abs(ue).max(), _l1(w[5], pe))
+    print("edge form, shock tube L1 (rho, u, p):", errs, flush=True)
+    assert np.sum(errs["edge"]) < np.sum(errs["js"])
+
+
+@pytest.mark.skipif(not os.path.exists(EDGE_TRAINED), reason="no trained shared network committed")
+def test_edge_gain_advected_slab():
+    params = np.load(EDGE_TRAINED, allow_pickle=False)
+    P = wl.advected_slab(n=256, seed=7777)
+    errs = {}
+    for name, weights, prm in (("js", MFX_WENO5_JS, None), ("edge", MFX_WENO5_LEARNED_EDGE, params)):
+        s = _solver(P, weights, prm)
+        t = sum(s.rk3_step(sync=True) for _ in range(200))
+        q = s.get_state().cpu().numpy().reshape(7, -1)
+        errs[name] = _l1(q[6], P["alpha_cell_avg"](t))
+    print("edge form, advected slab alpha1 L1:", errs, flush=True)
+    assert errs["edge"] < errs["js"]
