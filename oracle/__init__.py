@@ -36,6 +36,7 @@ class OrcGrid(ctypes.Structure):
         ("pinf", ctypes.c_double * 2),
         ("eps", ctypes.c_double),
         ("cfl", ctypes.c_double),
+        ("weno_z", ctypes.c_int32),
     ]
 
 
@@ -65,6 +66,7 @@ def lib():
         i64p = ctypes.POINTER(ctypes.c_int64)
         L.orc_weno5.argtypes = [dp, ctypes.c_double, dp, dp]
         L.orc_weno5_betas.argtypes = [dp, dp]
+        L.orc_weno5_z.argtypes = [dp, ctypes.c_double, dp, dp]
         L.orc_hllc.argtypes = [gp, dp, dp, ctypes.c_int, dp, dp]
         L.orc_sound_speed.argtypes = [gp, dp]
         L.orc_sound_speed.restype = ctypes.c_double
@@ -90,8 +92,10 @@ def _dp(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def make_grid(spec: dict) -> OrcGrid:
-    """Grid from a problem description dict (keys n, dx, bc, gamma, pinf, eps, cfl)."""
+def make_grid(spec: dict, weno_z: bool = False) -> OrcGrid:
+    """Grid from a problem description dict (keys n, dx, bc, gamma, pinf, eps,
+    cfl).  weno_z selects the WENO-Z weights (a comparison form) instead of
+    Jiang-Shu's."""
     g = OrcGrid()
     for d in range(3):
         g.n[d] = int(spec["n"][d])
@@ -102,6 +106,7 @@ def make_grid(spec: dict) -> OrcGrid:
     g.pinf[0], g.pinf[1] = map(float, spec["pinf"])
     g.eps = float(spec.get("eps", 1e-6))
     g.cfl = float(spec.get("cfl", 0.4))
+    g.weno_z = 1 if weno_z else 0
     return g
 
 
@@ -178,6 +183,15 @@ def weno5(v, eps=1e-6):
     l = ctypes.c_double()
     r = ctypes.c_double()
     lib().orc_weno5(_dp(v), float(eps), ctypes.byref(l), ctypes.byref(r))
+    return l.value, r.value
+
+
+def weno5_z(v, eps=1e-6):
+    """(left edge, right edge) with WENO-Z weights (comparison form)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    l = ctypes.c_double()
+    r = ctypes.c_double()
+    lib().orc_weno5_z(_dp(v), float(eps), ctypes.byref(l), ctypes.byref(r))
     return l.value, r.value
 
 

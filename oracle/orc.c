@@ -59,6 +59,7 @@ typedef struct {
     double pinf[2];
     double eps;        /* WENO epsilon */
     double cfl;
+    int32_t weno_z;    /* 0: Jiang-Shu weights (the paper's WENO5); 1: WENO-Z weights (comparison form) */
 } orc_grid;
 
 /* ---------- equation of state (Sec. II-A) ---------- */
@@ -133,6 +134,34 @@ static void weno5_betas(const double* v, double* b)
            0.25 * (v[1] - v[3]) * (v[1] - v[3]);
     b[2] = 13.0 / 12.0 * (v[2] - 2.0 * v[3] + v[4]) * (v[2] - 2.0 * v[3] + v[4]) +
            0.25 * (3.0 * v[2] - 4.0 * v[3] + v[4]) * (3.0 * v[2] - 4.0 * v[3] + v[4]);
+}
+
+/* WENO-Z weights (Borges, Carmona, Costa & Don, J. Comput. Phys. 227, 2008),
+   exponent 1: alpha_k = d_k (1 + tau5 / (beta_k + eps)), tau5 = |beta0 - beta2|.
+   A comparison form, not the paper's method; same candidates and stencils. */
+static void weno5_z(const double* v, double eps, double* left, double* right)
+{
+    double b[3];
+    weno5_betas(v, b);
+    double tau = fabs(b[0] - b[2]);
+
+    double r0 = (2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2]) / 6.0;
+    double r1 = (-v[1] + 5.0 * v[2] + 2.0 * v[3]) / 6.0;
+    double r2 = (2.0 * v[2] + 5.0 * v[3] - v[4]) / 6.0;
+    double a0 = 0.1 * (1.0 + tau / (b[0] + eps));
+    double a1 = 0.6 * (1.0 + tau / (b[1] + eps));
+    double a2 = 0.3 * (1.0 + tau / (b[2] + eps));
+    double s = a0 + a1 + a2;
+    *right = (a0 / s) * r0 + (a1 / s) * r1 + (a2 / s) * r2;
+
+    double l0 = (-v[0] + 5.0 * v[1] + 2.0 * v[2]) / 6.0;
+    double l1 = (2.0 * v[1] + 5.0 * v[2] - v[3]) / 6.0;
+    double l2 = (11.0 * v[2] - 7.0 * v[3] + 2.0 * v[4]) / 6.0;
+    a0 = 0.3 * (1.0 + tau / (b[0] + eps));
+    a1 = 0.6 * (1.0 + tau / (b[1] + eps));
+    a2 = 0.1 * (1.0 + tau / (b[2] + eps));
+    s = a0 + a1 + a2;
+    *left = (a0 / s) * l0 + (a1 / s) * l1 + (a2 / s) * l2;
 }
 
 static void weno5(const double* v, double eps, double* left, double* right)
@@ -239,6 +268,7 @@ void orc_weno5(const double* v, double eps, double* left, double* right)
     weno5(v, eps, left, right);
 }
 void orc_weno5_betas(const double* v, double* b) { weno5_betas(v, b); }
+void orc_weno5_z(const double* v, double eps, double* left, double* right) { weno5_z(v, eps, left, right); }
 void orc_hllc(const orc_grid* g, const double* wl, const double* wr, int d, double* F, double* uf)
 {
     hllc(g, wl, wr, d, F, uf);
@@ -337,7 +367,7 @@ void orc_rhs(const orc_grid* g, const double* q, double* rhs)
                         double st[5];
                         for (int o = -2; o <= 2; ++o)
                             st[o + 2] = wp[v * NP + base_p + (int64_t)(c + gh[d] + o) * stride_p[d]];
-                        weno5(st, g->eps, &lft[(c + 1) * NV + v], &rgt[(c + 1) * NV + v]);
+                        (g->weno_z ? weno5_z : weno5)(st, g->eps, &lft[(c + 1) * NV + v], &rgt[(c + 1) * NV + v]);
                     }
                 }
                 for (int f = 0; f <= n; ++f)
@@ -387,7 +417,7 @@ void orc_rhs_at(const orc_grid* g, const double* q, int64_t ncell, const int64_t
                 for (int v = 0; v < NV; ++v) {
                     double st[5];
                     for (int o = 0; o < 5; ++o) st[o] = w7[cc + o][v];
-                    weno5(st, g->eps, &lft[cc][v], &rgt[cc][v]);
+                    (g->weno_z ? weno5_z : weno5)(st, g->eps, &lft[cc][v], &rgt[cc][v]);
                 }
             double Fm[NV], Fp[NV], um, up;
             hllc(g, rgt[0], lft[1], d, Fm, &um);

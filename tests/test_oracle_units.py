@@ -149,6 +149,60 @@ def test_weno_essentially_non_oscillatory_at_step():
             assert -1e9 * 1e-6 <= x <= 1e9 * (1 + 1e-6)
 
 
+# ---------------------------------------------------------------- WENO-Z (comparison form)
+
+@pytest.mark.parametrize("seed", range(3))
+def test_weno_z_exact_for_quadratics_and_quartics_with_linear_weights(seed):
+    rng = np.random.default_rng(300 + seed)
+    h = 0.1
+    xs = np.arange(-2, 3) * h
+    c = rng.uniform(-2, 2, size=3)
+    l, r = oracle.weno5_z(_cell_avgs(c, h, xs))
+    P = np.polynomial.Polynomial(c)
+    assert r == pytest.approx(P(h / 2), rel=1e-13, abs=1e-13)
+    assert l == pytest.approx(P(-h / 2), rel=1e-13, abs=1e-13)
+    # tau5 = 0 (symmetric beta0 = beta2) makes the weights linear: quartics even in x exact
+    c4 = np.array([rng.uniform(-2, 2), 0.0, rng.uniform(-2, 2), 0.0, rng.uniform(-2, 2)])
+    l, r = oracle.weno5_z(_cell_avgs(c4, h, xs))
+    P4 = np.polynomial.Polynomial(c4)
+    assert r == pytest.approx(P4(h / 2), rel=1e-12, abs=1e-13)
+    assert l == pytest.approx(P4(-h / 2), rel=1e-12, abs=1e-13)
+
+
+def test_weno_z_keeps_fifth_order_at_a_critical_point():
+    """At a first-order critical point (vanishing first derivative) WENO-Z
+    keeps fifth order and its weights stay closer to the linear ones than
+    the Jiang-Shu weights, so its error is the smaller (Borges et al. 2008)."""
+    f = np.polynomial.Polynomial([0.2, 0.0, 1.0, 0.8, -0.6, 0.3])  # f'(0) = 0
+    F = f.integ()
+    eps = 1e-40
+    err = {"z": [], "js": []}
+    for h in (0.04, 0.02, 0.01, 0.005):
+        xs = np.arange(-2, 3) * h
+        v = np.array([(F(x + h / 2) - F(x - h / 2)) / h for x in xs])
+        err["z"].append(abs(oracle.weno5_z(v, eps=eps)[1] - f(h / 2)))
+        err["js"].append(abs(oracle.weno5(v, eps=eps)[1] - f(h / 2)))
+    oz = np.log2(np.array(err["z"][:-1]) / np.array(err["z"][1:]))
+    oj = np.log2(np.array(err["js"][:-1]) / np.array(err["js"][1:]))
+    print("orders at the critical point: WENO-Z", oz, "Jiang-Shu", oj)
+    assert np.all(oz > 4.5), oz
+    assert np.all(np.array(err["z"]) < np.array(err["js"]))
+
+
+def test_weno_z_non_oscillatory_at_step_and_mirror():
+    for v in ([0, 0, 0, 1, 1], [0, 0, 1, 1, 1], [1, 1, 0, 0, 0], [0, 0, 0, 0, 1]):
+        l, r = oracle.weno5_z(np.array(v, dtype=float) * 1e9)
+        for x in (l, r):
+            assert -1e9 * 1e-6 <= x <= 1e9 * (1 + 1e-6)
+    rng = np.random.default_rng(9)
+    for _ in range(20):
+        v = rng.uniform(-1, 1, size=5)
+        l, r = oracle.weno5_z(v)
+        l2, r2 = oracle.weno5_z(v[::-1])
+        assert l2 == pytest.approx(r, rel=1e-13, abs=1e-15)
+        assert r2 == pytest.approx(l, rel=1e-13, abs=1e-15)
+
+
 # ---------------------------------------------------------------- HLLC
 
 def _phys_flux(w, d):
