@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "grind time (ns/cell/RK-stage) + %HBM peak; FP32/learned vs FP64 at fixed L1"
 HBM_PEAK_GBS = 8000.0
 STATE_BYTES = 56  # 7 float64 per cell
-KERNEL_NAMES = {0: "sweep_x", 1: "sweep_y", 2: "sweep_z"}
+KERNEL_NAMES = {0: "sweep_x", 1: "sweep_y", 2: "sweep_z", 3: "sweep_xy"}
 
 
 def sweep_bytes_per_cell(first: int, mode: int, rhs_bytes: int = STATE_BYTES) -> int:

@@ -248,9 +248,12 @@ const char* mfx_mlp_last_error(void);
  * (0 stops).  mfx_profile_read synchronises and returns, per launch kind,
  * the summed event time in milliseconds and the launch count since the
  * last mfx_profile call; kind = (direction * 2 + first_pass) * 5 + output,
- * output 0 partial RHS, 1 caller RHS, 2/3/4 RK stage 1/2/3.  Arrays hold
- * MFX_PROF_KINDS entries; either may be NULL. */
-#define MFX_PROF_KINDS 30
+ * output 0 partial RHS, 1 caller RHS, 2/3/4 RK stage 1/2/3; direction 3
+ * is the fused x-y pass (x and y in one kernel, used when both are active,
+ * nx <= 512 and the weights are Jiang-Shu; MFX_FUSE_XY=0 in the environment
+ * at mfx_init_grid turns it off).  Arrays hold MFX_PROF_KINDS entries;
+ * either may be NULL. */
+#define MFX_PROF_KINDS 40
 int mfx_profile(mfx_ctx* ctx, int enable);
 int mfx_profile_read(mfx_ctx* ctx, double* ms, int64_t* counts);
 

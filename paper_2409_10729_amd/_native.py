@@ -26,7 +26,7 @@ EXPORTED = (
     "mfx_mlp_last_error",
 )
 MLP_PARAMS = 1347
-PROF_KINDS = 30
+PROF_KINDS = 40
 
 
 class GridDesc(ctypes.Structure):

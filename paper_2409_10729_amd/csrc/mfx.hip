@@ -41,13 +41,15 @@ size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 struct Overrides {
     int seg;
     int xmode;
+    int fuse_xy;
 };
 
 Overrides read_overrides()
 {
-    Overrides o{0, 0};
+    Overrides o{0, 0, 1};
     if (const char* s = std::getenv("MFX_SWEEP_SEG")) o.seg = std::atoi(s);
     if (const char* s = std::getenv("MFX_XSWEEP")) o.xmode = std::strcmp(s, "march") == 0 ? 1 : 0;
+    if (const char* s = std::getenv("MFX_FUSE_XY")) o.fuse_xy = std::atoi(s) != 0;
     return o;
 }
 
@@ -295,6 +297,7 @@ struct mfx_ctx {
     int ndirs;
     int seg_override;
     int xmode_override;  // MFX_XSWEEP: 0 automatic, 1 marching x sweep
+    bool fuse_xy;        // x and y passes as one kernel where it applies (MFX_FUSE_XY=0 disables)
     bool has_state;
     std::string err;
     // kernel timing (mfx_profile): events around each sweep launch
@@ -445,16 +448,86 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
     return MFX_OK;
 }
 
+// The fused x-y pass applies when x and y are the first two active
+// directions, x rows fit the row kernel and the weights are Jiang-Shu.
+bool fused_xy(const mfx_ctx* c)
+{
+    return c->fuse_xy && c->desc.weights == MFX_WENO5_JS && c->ndirs >= 2 && c->dirs[0] == 0 && c->dirs[1] == 1 &&
+           use_xrows(c->g.n, c->xmode_override, c->elem);
+}
+
+template <typename T, int MODE>
+void launch_xy_mode(mfx_ctx* c, const double* qs, const double* qn, double* out, const double* dt_dev, double dt_arg)
+{
+    const Grid& g = c->g;
+    const long long rows = (long long)g.n[1] * g.n[2];
+    T* bf = static_cast<T*>(c->bface);
+    boundary_faces_x<T, false><<<(unsigned)((rows + 255) / 256), 256, 0, c->stream>>>(g, qs, bf, c->mlp, c->fallback);
+    // segments along y as for the y sweep (lanes = x, blocks over z and segments)
+    int seg = c->seg_override > 0 ? c->seg_override : 64;
+    const long long pencils = (long long)g.n[0] * g.n[2];
+    while (seg > 16 && pencils * ((g.n[1] + seg - 1) / seg) < 256LL * 64 * 16) seg /= 2;
+    seg = std::min(seg, g.n[1]);
+    const dim3 grid(1, (unsigned)g.n[2], (unsigned)((g.n[1] + seg - 1) / seg));
+    const int block = 64 * ((g.n[0] + 63) / 64);
+    sweep_xy<T, MODE><<<grid, block, xrow_lds_bytes(g.n[0], sizeof(T)), c->stream>>>(
+        g, qs, qn, static_cast<T*>(c->r), out, seg, bf, dt_dev, dt_arg);
+}
+
+template <typename T>
+void launch_xy(mfx_ctx* c, int mode, const double* qs, const double* qn, double* out, const double* dt_dev,
+               double dt_arg)
+{
+    switch (mode) {
+    case OUT_ACCUM: launch_xy_mode<T, OUT_ACCUM>(c, qs, qn, out, dt_dev, dt_arg); break;
+    case OUT_RHS: launch_xy_mode<T, OUT_RHS>(c, qs, qn, out, dt_dev, dt_arg); break;
+    case OUT_STAGE1: launch_xy_mode<T, OUT_STAGE1>(c, qs, qn, out, dt_dev, dt_arg); break;
+    case OUT_STAGE2: launch_xy_mode<T, OUT_STAGE2>(c, qs, qn, out, dt_dev, dt_arg); break;
+    default: launch_xy_mode<T, OUT_STAGE3>(c, qs, qn, out, dt_dev, dt_arg); break;
+    }
+}
+
+// The fused pass, profiled as direction 3 (first pass).
+int launch_sweep_xy(mfx_ctx* c, const double* qs, const double* qn, double* out, int mode, const double* dt_dev,
+                    double dt_arg)
+{
+    mfx_ctx::Pending pend{(3 * 2 + 1) * 5 + mode, nullptr, nullptr};
+    if (c->profiling) {
+        pend.a = take_event(c);
+        pend.b = take_event(c);
+        if (!pend.a || !pend.b) return fail(c, MFX_EHIP, "hipEventCreate failed");
+        HIP_TRY(c, hipEventRecord(pend.a, c->stream));
+    }
+    if (c->desc.precision == MFX_FP32_MIXED)
+        launch_xy<float>(c, mode, qs, qn, out, dt_dev, dt_arg);
+    else
+        launch_xy<double>(c, mode, qs, qn, out, dt_dev, dt_arg);
+    int rc = launch_check(c, "fused x-y sweep");
+    if (rc) return rc;
+    if (c->profiling) {
+        HIP_TRY(c, hipEventRecord(pend.b, c->stream));
+        c->pending.push_back(pend);
+    }
+    return MFX_OK;
+}
+
 // All direction passes of one right-hand-side evaluation; the last active
 // direction applies `last_mode` with output `out`.
 int run_passes(mfx_ctx* c, const double* qs, const double* qn, double* out, int last_mode, const double* dt_dev,
                double dt_arg)
 {
-    for (int i = 0; i < c->ndirs; ++i) {
+    int i0 = 0;
+    if (fused_xy(c)) {
+        const bool last = c->ndirs == 2;
+        int rc = launch_sweep_xy(c, qs, qn, last ? out : nullptr, last ? last_mode : OUT_ACCUM, dt_dev, dt_arg);
+        if (rc != MFX_OK) return rc;
+        i0 = 2;
+    }
+    for (int i = i0; i < c->ndirs; ++i) {
         const int d = c->dirs[i];
         const bool last = (i == c->ndirs - 1);
-        int rc = launch_sweep(c, d, qs, qn, last ? out : nullptr, i == 0, last ? last_mode : OUT_ACCUM, dt_dev,
-                              dt_arg);
+        int rc = launch_sweep(c, d, qs, qn, last ? out : nullptr, i == 0 && i0 == 0, last ? last_mode : OUT_ACCUM,
+                              dt_dev, dt_arg);
         if (rc != MFX_OK) return rc;
     }
     return MFX_OK;
@@ -518,6 +591,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->seg_override = ov.seg;
     c->xmode_override = ov.xmode;
+    c->fuse_xy = ov.fuse_xy != 0;
 
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;

@@ -131,14 +131,10 @@ struct OutArgs {
 // running sum as (R + fd) + src for alpha1 and R + fd otherwise.  FIRST
 // (no running sum yet) and MODE (what is written) are compile-time so each
 // kernel carries only its own path.
-template <typename T, bool FIRST, int MODE>
-__device__ __forceinline__ void emit_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T fd[NV], T src)
+template <typename T, int MODE>
+__device__ __forceinline__ void store_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T r[NV])
 {
     const long long N = g.N;
-    T r[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) r[v] = FIRST ? fd[v] : o.racc[v * N + cell] + fd[v];
-    r[6] += src;
     if constexpr (MODE == OUT_ACCUM) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) o.racc[v * N + cell] = r[v];
@@ -155,6 +151,16 @@ __device__ __forceinline__ void emit_cell(const Grid& g, const OutArgs<T>& o, lo
 #pragma unroll
         for (int v = 0; v < NV; ++v) o.out[v * N + cell] = qo[v];
     }
+}
+
+template <typename T, bool FIRST, int MODE>
+__device__ __forceinline__ void emit_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T fd[NV], T src)
+{
+    T r[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) r[v] = FIRST ? fd[v] : o.racc[v * g.N + cell] + fd[v];
+    r[6] += src;
+    store_cell<T, MODE>(g, o, cell, r);
 }
 
 // Primitives of one cell in the compute type: the inversion is float64.
@@ -174,7 +180,8 @@ struct GlobalSink {
     OutArgs<T> o;
     long long base, sd;
     bool valid;
-    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src)
+    template <class Win>
+    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src, const Win&)
     {
         if (valid) emit_cell<T, FIRST, MODE>(g, o, base + (long long)c * sd, fd, src);
     }
@@ -210,6 +217,42 @@ struct LdsWindow {
     __device__ __forceinline__ void advance() { s0 = s0 == 4 ? 0 : s0 + 1; }
 };
 
+// The same ring in registers (rotated by moves), for kernels whose LDS
+// holds other data.
+template <typename T>
+struct RegWindow {
+    T w[5][NV];
+    __device__ __forceinline__ T operator()(int k, int v) const { return w[k][v]; }
+    __device__ __forceinline__ void store(int k, const T x[NV])
+    {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w[k][v] = x[v];
+    }
+    __device__ __forceinline__ void advance()
+    {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const T t = w[0][v];
+            w[0][v] = w[1][v];
+            w[1][v] = w[2][v];
+            w[2][v] = w[3][v];
+            w[3][v] = w[4][v];
+            w[4][v] = t;
+        }
+    }
+};
+
+// Marks a variable's edge values as final where they are computed.  Without
+// it the compiler sinks each variable's last multiplications (and keeps
+// their operands live) down to the first use of the values, past the
+// other variables' reconstructions, which nearly doubles the registers of
+// the sweep kernels.  The empty asm statement emits no instruction.
+template <typename T>
+__device__ __forceinline__ void settle(T& a, T& b)
+{
+    asm volatile("" : "+v"(a), "+v"(b));
+}
+
 // Reconstruction of one cell's two edge states (all seven primitives) from
 // its 5-cell window.
 template <typename T>
@@ -218,7 +261,10 @@ struct ReconJS {
     __device__ __forceinline__ void cell_win(const Win& W, T eps, T lft[NV], T rgt[NV])
     {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) weno5<T>(W(0, v), W(1, v), W(2, v), W(3, v), W(4, v), eps, lft[v], rgt[v]);
+        for (int v = 0; v < NV; ++v) {
+            weno5<T>(W(0, v), W(1, v), W(2, v), W(3, v), W(4, v), eps, lft[v], rgt[v]);
+            settle(lft[v], rgt[v]);
+        }
     }
     __device__ __forceinline__ void cell(const T W[5][NV], T eps, T lft[NV], T rgt[NV])
     {
@@ -379,9 +425,10 @@ __device__ __forceinline__ typename ReconOf<T, LEARNED>::type make_recon(const G
 // the conserved state of cell `pos` along the sweep (boundary map applied);
 // it is called for positions c0-3, c0-2, ..., c1+2 in that order, and
 // Sink::put for cells c0..c1-1 in order, the same sequence on every lane.
-// col: this lane's column of a [5][NV][LANES] LDS array holding the window.
-template <int DIR, typename T, int LANES, class Src, class Sink, class Recon>
-__device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon& recon, int c0, int c1, T* col)
+// W: the 5-cell window (LdsWindow or RegWindow), handed to Sink::put too,
+// where W(1, .) holds the primitives of the cell being put.
+template <int DIR, typename T, class Src, class Sink, class Recon, class Win>
+__device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon& recon, int c0, int c1, Win& W)
 {
     const T idx = (T)g.inv_dx[DIR];
     const T eps = (T)g.eps;
@@ -389,8 +436,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
     const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
 
     // window: W(k) = primitives of cell c-2+k while reconstructing cell c
-    LdsWindow<T, LANES> W{col, 0};
-#pragma unroll 1
+#pragma unroll
     for (int k = 0; k < 5; ++k) {
         double qc[NV];
         src.load(c0 - 3 + k, qc);
@@ -419,7 +465,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
                 T fd[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) fd[v] = (Fprev[v] - F[v]) * idx;
-                sink.put(g, c - 1, fd, W(1, 6) * ((uf - ufprev) * idx));
+                sink.put(g, c - 1, fd, W(1, 6) * ((uf - ufprev) * idx), W);
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fprev[v] = F[v];
@@ -481,7 +527,8 @@ __global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restr
                                     valid};
     auto recon = make_recon<T, LEARNED>(g, mlp, valid);
     __shared__ T win[5][NV][BLOCK];
-    march<DIR, T, BLOCK>(g, src, sink, recon, c0, c1, &win[0][0][threadIdx.x]);
+    LdsWindow<T, BLOCK> W{&win[0][0][threadIdx.x], 0};
+    march<DIR, T>(g, src, sink, recon, c0, c1, W);
     recon.flush(fb);
 }
 
@@ -533,7 +580,8 @@ struct LdsSink {
     long long row0, nrows;
     int nx, c0, c1;
 
-    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src)
+    template <class Win>
+    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src, const Win&)
     {
         const int slot = (c - c0) % XCHUNK;
 #pragma unroll
@@ -578,7 +626,8 @@ __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* 
                                  c0, c1};
     auto recon = make_recon<T, LEARNED>(g, mlp, row0 + threadIdx.x < nrows);
     __shared__ T win[5][NV][XROWS];
-    march<0, T, XROWS>(g, src, sink, recon, c0, c1, &win[0][0][threadIdx.x]);
+    LdsWindow<T, XROWS> W{&win[0][0][threadIdx.x], 0};
+    march<0, T>(g, src, sink, recon, c0, c1, W);
     recon.flush(fb);
 }
 

@@ -209,15 +209,14 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
         // 2. reconstruct own cell: left edge to LDS, right edge kept
         T rgt[NV], lft[NV];
         if constexpr (LEARNED) {
-            // the learned forms read the window from LDS as they go
             recon.cell_win(RowWindow<T>{P + xc, np}, eps, lft, rgt);
         } else {
-            T Wc[5][NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v)
-#pragma unroll
-                for (int k = 0; k < 5; ++k) Wc[k][v] = P[v * np + xc + k];
-            recon.cell(Wc, eps, lft, rgt);
+            for (int v = 0; v < NV; ++v) {
+                const T* pv = P + v * np + xc;
+                weno5<T>(pv[0], pv[1], pv[2], pv[3], pv[4], eps, lft[v], rgt[v]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
         }
         if (has) {
 #pragma unroll
@@ -264,6 +263,151 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
         }
     }
     recon.flush(fb);
+}
+
+// Fused x and y passes: a block of 64 * ceil(nx / 64) lanes owns whole x
+// rows of one z plane and marches along y over a segment (lane = x, as in
+// the y sweep).  When the march puts cell row j (window slot W(1)), the
+// block also computes that row's x contribution from the row's primitives,
+// which every lane already holds: the same three-barrier row procedure as
+// sweep_x_rows, with the row's end faces from boundary_faces_x.  Each cell
+// then stores the sum (x part, then y part: the same additions in the same
+// order as the x pass followed by the y pass) once, so the state is read
+// once and the running sum never goes through memory.  The window lives in
+// registers; LDS holds the row buffers of the x part (xrow_layout).
+template <typename T, int MODE>
+struct XYSink {
+    OutArgs<T> o;
+    T* P;   // [NV][nx+4]
+    T* L;   // [NV][nx]
+    T* Fs;  // [BFACE][nx]
+    const T* bface;
+    long long base_z;  // first cell of the z plane
+    long long row_z;   // first row (k * ny) of the z plane
+    int nx, np, x, xc;
+    bool has, alias;
+    int gsrc[4];
+    T idx, eps;
+    Mix<T> mix;
+
+    template <class Win>
+    __device__ __forceinline__ void put(const Grid& g, int c, const T fdy[NV], T srcy, const Win& W)
+    {
+        const long long row = row_z + c;
+        T w[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) w[v] = W(1, v);
+        if (alias) __syncthreads();  // the previous row's fluxes (P's storage) are consumed
+        if (has) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) P[v * np + x + 2] = w[v];
+            const int gslot[4] = {0, 1, nx + 2, nx + 3};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                if (x == gsrc[k]) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) P[v * np + gslot[k]] = w[v];
+                }
+            }
+        }
+        __syncthreads();
+        T rgt[NV], lft[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const T* pv = P + v * np + xc;
+            weno5<T>(pv[0], pv[1], pv[2], pv[3], pv[4], eps, lft[v], rgt[v]);
+            settle(lft[v], rgt[v]);
+        }
+        if (has) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) L[v * nx + x] = lft[v];
+        }
+        __syncthreads();
+        T F[BFACE];
+        {
+            T wr[NV];
+            const int xr = min(xc + 1, nx - 1);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) wr[v] = L[v * nx + xr];
+            T Fh[NV], ufh;
+            hllc<0, T>(mix, rgt, wr, Fh, ufh);
+            const T* b = bface + (row * 2 + 1) * BFACE;
+            const bool last = xc == nx - 1;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[v] = last ? b[v] : Fh[v];
+            F[NV] = last ? b[NV] : ufh;
+        }
+        if (has) {
+#pragma unroll
+            for (int k = 0; k < BFACE; ++k) Fs[k * nx + x] = F[k];
+        }
+        __syncthreads();
+        if (has) {
+            T Fm[BFACE];
+            if (x == 0) {
+                const T* b = bface + (row * 2 + 0) * BFACE;
+#pragma unroll
+                for (int k = 0; k < BFACE; ++k) Fm[k] = b[k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < BFACE; ++k) Fm[k] = Fs[k * nx + x - 1];
+            }
+            // x part, rounded as the x pass stores it
+            T r[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) r[v] = (Fm[v] - F[v]) * idx;
+            r[6] += w[6] * ((F[NV] - Fm[NV]) * idx);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) asm volatile("" : "+v"(r[v]));
+            // plus the y part
+#pragma unroll
+            for (int v = 0; v < NV; ++v) r[v] = r[v] + fdy[v];
+            r[6] += srcy;
+            store_cell<T, MODE>(g, o, base_z + (long long)c * nx + x, r);
+        }
+    }
+};
+
+template <typename T, int MODE>
+__global__ void __launch_bounds__(XROW_THREADS) sweep_xy(Grid g, const double* __restrict__ qs, const double* qn,
+                                                         T* __restrict__ racc, double* out, int seg,
+                                                         const T* __restrict__ bface,
+                                                         const double* __restrict__ dt_dev, double dt_arg)
+{
+    extern __shared__ __align__(16) unsigned char lds_raw[];
+    T* lds = reinterpret_cast<T*>(lds_raw);
+    const int nx = g.n[0], ny = g.n[1];
+    const XrowLayout lay = xrow_layout(nx, sizeof(T));
+    const int x = threadIdx.x;
+    const bool has = x < nx;
+    const int xc = has ? x : nx - 1;
+    const int z = blockIdx.y;
+    const int c0 = blockIdx.z * seg;
+    const int c1 = min(c0 + seg, ny);
+    const long long base_z = (long long)z * g.stride[2];
+
+    GlobalSrc src{qs, base_z + xc, g.stride[1], g.N, ny, g.bc[1][0], g.bc[1][1]};
+    XYSink<T, MODE> sink{OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg},
+                         lds + lay.p,
+                         lds + lay.l,
+                         lds + lay.fs,
+                         bface,
+                         base_z,
+                         (long long)z * ny,
+                         nx,
+                         nx + 4,
+                         x,
+                         xc,
+                         has,
+                         lay.alias,
+                         {map_cell(-2, nx, g.bc[0][0], g.bc[0][1]), map_cell(-1, nx, g.bc[0][0], g.bc[0][1]),
+                          map_cell(nx, nx, g.bc[0][0], g.bc[0][1]), map_cell(nx + 1, nx, g.bc[0][0], g.bc[0][1])},
+                         (T)g.inv_dx[0],
+                         (T)g.eps,
+                         Mix<T>{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2}};
+    ReconJS<T> recon{};
+    RegWindow<T> W;
+    march<1, T>(g, src, sink, recon, c0, c1, W);
 }
 
 }  // namespace mfx

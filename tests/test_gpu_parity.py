@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_2409_10729_amd import MFX_FP32_MIXED, MFX_FP64
 from paper_2409_10729_amd import workloads as wl
 from parity_util import TOL, gpu_solver, oracle_step_at, rel_linf, rhs_rel_linf, sample_cells
 
@@ -49,6 +50,7 @@ def test_set_primitive_matches_oracle_conversion():
     ((2, 3, 2), ((0, 0), (0, 0), (1, 1)), 7),
     ((1, 1, 1), ((0, 0), (0, 0), (0, 0)), 8),
     ((600, 3, 2), ((1, 1), (0, 0), (0, 0)), 9),  # rows longer than the row kernel takes: marching x sweep
+    ((420, 6, 3), ((1, 1), (0, 0), (1, 1)), 10),  # long rows: aliased row buffers in the fused x-y pass
 ])
 def test_rhs_matches_oracle(n, bc, seed):
     P = wl.random_smooth(n=n, seed=seed, bc=bc)
@@ -183,6 +185,38 @@ def test_x_sweep_variants_agree(monkeypatch, n, bc):
     _report(f"x-sweep variants rhs {n}", e_rhs)
     _report(f"x-sweep variants step {n}", e_q)
     assert np.all(e_rhs <= 1e-13) and np.all(e_q <= 1e-13)
+
+
+@pytest.mark.parametrize("precision", [MFX_FP64, MFX_FP32_MIXED])
+@pytest.mark.parametrize("n,bc", [((72, 40, 36), ((1, 1), (0, 0), (0, 0))),
+                                  ((400, 4, 3), ((0, 0), (1, 1), (1, 1))),  # long rows: aliased row buffers
+                                  ((64, 48, 1), ((1, 1), (0, 0), (0, 0))),  # x-y plane: the fused pass is the last
+                                  ((7, 70, 9), ((0, 0), (1, 1), (0, 0))),
+                                  ((2, 3, 2), ((1, 1), (1, 1), (0, 0)))])
+def test_fused_xy_pass_matches_separate_passes(monkeypatch, n, bc, precision):
+    """The fused x-y kernel performs the x pass's and the y pass's
+    arithmetic with their additions in the same order; the compiler may
+    fuse multiply-adds differently in the two kernels, so the agreement is
+    to rounding of the compute type (FP64: 1e-13; float: 1e-6 for the
+    right-hand side relative to the flux scale, 1e-5 for the state after two
+    steps, whose small momentum fields carry the float noise of the large
+    ones)."""
+    P = wl.random_smooth(n=n, seed=12, bc=bc)
+    g, q0 = _q0(P)
+    outs = []
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("MFX_FUSE_XY", fuse)
+        s = gpu_solver(P["spec"], q0=q0, precision=precision)
+        r = s.rhs().cpu().numpy()
+        s.rk3_step()
+        s.rk3_step()
+        outs.append((r, s.get_state().cpu().numpy()))
+    e_rhs = rhs_rel_linf(outs[0][0], outs[1][0], q0, P["spec"])
+    e_q = rel_linf(outs[0][1], outs[1][1])
+    _report(f"fused vs separate rhs {n} precision {precision}", e_rhs)
+    _report(f"fused vs separate step {n} precision {precision}", e_q)
+    tol_r, tol_q = (1e-13, 1e-13) if precision == MFX_FP64 else (1e-6, 1e-5)
+    assert np.all(e_rhs <= tol_r) and np.all(e_q <= tol_q)
 
 
 def test_repeat_runs_bitwise_equal():
