@@ -131,8 +131,10 @@ struct OutArgs {
 // running sum as (R + fd) + src for alpha1 and R + fd otherwise.  FIRST
 // (no running sum yet) and MODE (what is written) are compile-time so each
 // kernel carries only its own path.
+// qsc: the cell's stage state when the caller holds it (else read from o.qs).
 template <typename T, int MODE>
-__device__ __forceinline__ void store_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T r[NV])
+__device__ __forceinline__ void store_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T r[NV],
+                                           const double* qsc = nullptr)
 {
     const long long N = g.N;
     if constexpr (MODE == OUT_ACCUM) {
@@ -146,7 +148,7 @@ __device__ __forceinline__ void store_cell(const Grid& g, const OutArgs<T>& o, l
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const double qnv = MODE == OUT_STAGE1 ? 0.0 : o.qn[v * N + cell];
-            qo[v] = rk3_combine(MODE, qnv, o.qs[v * N + cell], o.dt, (double)r[v]);
+            qo[v] = rk3_combine(MODE, qnv, qsc ? qsc[v] : o.qs[v * N + cell], o.dt, (double)r[v]);
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) o.out[v * N + cell] = qo[v];
@@ -154,13 +156,14 @@ __device__ __forceinline__ void store_cell(const Grid& g, const OutArgs<T>& o, l
 }
 
 template <typename T, bool FIRST, int MODE>
-__device__ __forceinline__ void emit_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T fd[NV], T src)
+__device__ __forceinline__ void emit_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T fd[NV], T src,
+                                          const double* qsc = nullptr)
 {
     T r[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) r[v] = FIRST ? fd[v] : o.racc[v * g.N + cell] + fd[v];
     r[6] += src;
-    store_cell<T, MODE>(g, o, cell, r);
+    store_cell<T, MODE>(g, o, cell, r, qsc);
 }
 
 // Primitives of one cell in the compute type: the inversion is float64.
@@ -174,16 +177,19 @@ __device__ __forceinline__ void prim_of(const Mix<double>& mix, const double q[N
 }
 
 // Sink of the y and z sweeps: each lane writes its own cell (lanes are
-// consecutive x, so every access is a contiguous row).
-template <typename T, bool FIRST, int MODE>
+// consecutive x, so every access is a contiguous row).  KEEPQ: the march
+// hands over the cell's stage state, which it loaded four cells earlier,
+// so the stage update does not read it again.
+template <typename T, bool FIRST, int MODE, bool KEEPQ = false>
 struct GlobalSink {
+    static constexpr bool keeps_q = KEEPQ;
     OutArgs<T> o;
     long long base, sd;
     bool valid;
     template <class Win>
-    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src, const Win&)
+    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src, const Win&, const double* qc)
     {
-        if (valid) emit_cell<T, FIRST, MODE>(g, o, base + (long long)c * sd, fd, src);
+        if (valid) emit_cell<T, FIRST, MODE>(g, o, base + (long long)c * sd, fd, src, KEEPQ ? qc : nullptr);
     }
 };
 
@@ -436,10 +442,19 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
     const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
 
     // window: W(k) = primitives of cell c-2+k while reconstructing cell c
+    // qh (when the sink keeps the stage state): conserved cells c-1 .. c+2
+    constexpr bool KQ = Sink::keeps_q;
+    double qh[KQ ? 4 : 1][NV];
 #pragma unroll
     for (int k = 0; k < 5; ++k) {
         double qc[NV];
         src.load(c0 - 3 + k, qc);
+        if constexpr (KQ) {
+            if (k >= 1) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) qh[k - 1][v] = qc[v];
+            }
+        }
         T w[NV];
         prim_of<T>(mixd, qc, w);
         W.store(k, w);
@@ -465,7 +480,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
                 T fd[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) fd[v] = (Fprev[v] - F[v]) * idx;
-                sink.put(g, c - 1, fd, W(1, 6) * ((uf - ufprev) * idx), W);
+                sink.put(g, c - 1, fd, W(1, 6) * ((uf - ufprev) * idx), W, &qh[0][0]);
             }
 #pragma unroll
             for (int v = 0; v < NV; ++v) Fprev[v] = F[v];
@@ -479,6 +494,15 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
             T w[NV];
             prim_of<T>(mixd, qnext, w);
             W.store(0, w);
+            if constexpr (KQ) {
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    qh[0][v] = qh[1][v];
+                    qh[1][v] = qh[2][v];
+                    qh[2][v] = qh[3][v];
+                    qh[3][v] = qnext[v];
+                }
+            }
         }
         W.advance();
     }
@@ -523,8 +547,8 @@ __global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restr
     const int c0 = blockIdx.z * seg;
     const int c1 = min(c0 + seg, n);
     GlobalSrc src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
-    GlobalSink<T, FIRST, MODE> sink{OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR],
-                                    valid};
+    GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED)> sink{
+        OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid};
     auto recon = make_recon<T, LEARNED>(g, mlp, valid);
     __shared__ T win[5][NV][BLOCK];
     LdsWindow<T, BLOCK> W{&win[0][0][threadIdx.x], 0};
@@ -580,8 +604,9 @@ struct LdsSink {
     long long row0, nrows;
     int nx, c0, c1;
 
+    static constexpr bool keeps_q = false;
     template <class Win>
-    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src, const Win&)
+    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src, const Win&, const double*)
     {
         const int slot = (c - c0) % XCHUNK;
 #pragma unroll

@@ -277,6 +277,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
 // registers; LDS holds the row buffers of the x part (xrow_layout).
 template <typename T, int MODE>
 struct XYSink {
+    static constexpr bool keeps_q = false;
     OutArgs<T> o;
     T* P;   // [NV][nx+4]
     T* L;   // [NV][nx]
@@ -291,7 +292,7 @@ struct XYSink {
     Mix<T> mix;
 
     template <class Win>
-    __device__ __forceinline__ void put(const Grid& g, int c, const T fdy[NV], T srcy, const Win& W)
+    __device__ __forceinline__ void put(const Grid& g, int c, const T fdy[NV], T srcy, const Win& W, const double*)
     {
         const long long row = row_z + c;
         T w[NV];
