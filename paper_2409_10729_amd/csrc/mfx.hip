@@ -42,14 +42,16 @@ struct Overrides {
     int seg;
     int xmode;
     int fuse_xy;
+    int fuse_cfl;
 };
 
 Overrides read_overrides()
 {
-    Overrides o{0, 0, 1};
+    Overrides o{0, 0, 1, 1};
     if (const char* s = std::getenv("MFX_SWEEP_SEG")) o.seg = std::atoi(s);
     if (const char* s = std::getenv("MFX_XSWEEP")) o.xmode = std::strcmp(s, "march") == 0 ? 1 : 0;
     if (const char* s = std::getenv("MFX_FUSE_XY")) o.fuse_xy = std::atoi(s) != 0;
+    if (const char* s = std::getenv("MFX_FUSE_CFL")) o.fuse_cfl = std::atoi(s) != 0;
     return o;
 }
 
@@ -117,9 +119,13 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     const long long N = (long long)d->n[0] * d->n[1] * d->n[2];
     const size_t state = align_up(sizeof(double) * 7 * (size_t)N);
     const size_t elem = d->precision == MFX_FP32_MIXED ? sizeof(float) : sizeof(double);
-    (void)seg_override;
-    (void)xmode_override;
-    const long long np = CFL_BLOCKS;  // per-block maxima of the CFL reduction
+    // per-block maxima of the CFL reduction: the standalone pass, or the
+    // blocks of a y/z sweep that reduces the new state of a step
+    long long np = CFL_BLOCKS;
+    for (int dd = 1; dd < 3; ++dd) {
+        const SweepGeom sg = sweep_geom(d->n, dd, seg_override, xmode_override, elem);
+        np = std::max<long long>(np, (long long)sg.grid.x * sg.grid.y * sg.grid.z);
+    }
     const long long nrows = (long long)d->n[1] * d->n[2];
     size_t off = 0;
     L.q = off;
@@ -298,6 +304,7 @@ struct mfx_ctx {
     int seg_override;
     int xmode_override;  // MFX_XSWEEP: 0 automatic, 1 marching x sweep
     bool fuse_xy;        // x and y passes as one kernel where it applies (MFX_FUSE_XY=0 disables)
+    bool fuse_cfl;       // CFL reduction inside the step's last y/z sweep (MFX_FUSE_CFL=0 disables)
     bool has_state;
     std::string err;
     // kernel timing (mfx_profile): events around each sweep launch
@@ -371,6 +378,9 @@ struct LaunchArgs {
     void* bface;  // boundary faces of the x row sweep (compute type)
     const MlpLane* mlp;       // packed network (learned weights only)
     unsigned long long* fb;   // fallback counter (learned weights only)
+    double* partial;          // CFL block maxima (stage-3 y/z sweep with cfl)
+    unsigned* status;
+    bool cfl;                 // this stage-3 sweep also reduces the CFL speed of its output
 };
 
 // The x row sweep reads the boundary faces that boundary_faces_x leaves in
@@ -392,8 +402,15 @@ void launch_one(const LaunchArgs& a)
                 *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb);
         }
     } else {
+        if constexpr (MODE == OUT_STAGE3 && !L) {
+            if (a.cfl) {
+                sweep_yz<DIR, T, FIRST, MODE, L, true><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(
+                    *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, a.partial, a.status);
+                return;
+            }
+        }
         sweep_yz<DIR, T, FIRST, MODE, L><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(
-            *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb);
+            *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, nullptr, nullptr);
     }
 }
 
@@ -422,7 +439,7 @@ void launch_dispatch(int d, bool first, int mode, const LaunchArgs& a)
 }
 
 int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* out, int first, int mode,
-                 const double* dt_dev, double dt_arg)
+                 const double* dt_dev, double dt_arg, bool cfl = false)
 {
     SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem);
     mfx_ctx::Pending pend{(d * 2 + (first ? 1 : 0)) * 5 + mode, nullptr, nullptr};
@@ -432,7 +449,9 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
         if (!pend.a || !pend.b) return fail(c, MFX_EHIP, "hipEventCreate failed");
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
-    const LaunchArgs la{&sg, c->stream, &c->g, qs, qn, c->r, out, dt_dev, dt_arg, c->bface, c->mlp, c->fallback};
+    const LaunchArgs la{&sg,      c->stream,   &c->g,      qs,        qn,       c->r,
+                        out,      dt_dev,      dt_arg,     c->bface,  c->mlp,   c->fallback,
+                        c->partial, c->status, cfl};
     if (c->desc.weights != MFX_WENO5_JS)
         launch_dispatch<float, true>(d, first != 0, mode, la);
     else if (c->desc.precision == MFX_FP32_MIXED)
@@ -511,10 +530,24 @@ int launch_sweep_xy(mfx_ctx* c, const double* qs, const double* qn, double* out,
     return MFX_OK;
 }
 
+// Blocks of the last pass when that pass (a y or z sweep with Jiang-Shu
+// weights writing a step's new state) also reduces the CFL speed of its
+// output; 0 when the standalone reduction is needed.
+long long cfl_blocks_in_last_pass(const mfx_ctx* c)
+{
+    if (!c->fuse_cfl || c->desc.weights != MFX_WENO5_JS) return 0;
+    const int d = c->dirs[c->ndirs - 1];
+    if (d == 0 || !c->g.active[d]) return 0;
+    if (fused_xy(c) && c->ndirs == 2) return 0;  // the fused x-y pass is the last
+    const SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem);
+    return (long long)sg.grid.x * sg.grid.y * sg.grid.z;
+}
+
 // All direction passes of one right-hand-side evaluation; the last active
-// direction applies `last_mode` with output `out`.
+// direction applies `last_mode` with output `out` (and, with cfl, reduces
+// the CFL speed of that output).
 int run_passes(mfx_ctx* c, const double* qs, const double* qn, double* out, int last_mode, const double* dt_dev,
-               double dt_arg)
+               double dt_arg, bool cfl = false)
 {
     int i0 = 0;
     if (fused_xy(c)) {
@@ -527,7 +560,7 @@ int run_passes(mfx_ctx* c, const double* qs, const double* qn, double* out, int 
         const int d = c->dirs[i];
         const bool last = (i == c->ndirs - 1);
         int rc = launch_sweep(c, d, qs, qn, last ? out : nullptr, i == 0 && i0 == 0, last ? last_mode : OUT_ACCUM,
-                              dt_dev, dt_arg);
+                              dt_dev, dt_arg, last && cfl);
         if (rc != MFX_OK) return rc;
     }
     return MFX_OK;
@@ -592,6 +625,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     c->seg_override = ov.seg;
     c->xmode_override = ov.xmode;
     c->fuse_xy = ov.fuse_xy != 0;
+    c->fuse_cfl = ov.fuse_cfl != 0;
 
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
@@ -739,10 +773,16 @@ int mfx_rk3_step(mfx_ctx* c, double dt, double* dt_used_host)
     if (rc) return rc;
     rc = run_passes(c, c->q1, c->q, c->q2, OUT_STAGE2, dt_dev, dt_arg);
     if (rc) return rc;
-    rc = run_passes(c, c->q2, c->q, c->q, OUT_STAGE3, dt_dev, dt_arg);
+    const long long nb = cfl_blocks_in_last_pass(c);
+    rc = run_passes(c, c->q2, c->q, c->q, OUT_STAGE3, dt_dev, dt_arg, nb > 0);
     if (rc) return rc;
     // time step of the new state for the next step, and its physicality check
-    rc = standalone_cfl(c, 1, dt_arg);
+    if (nb > 0) {
+        cfl_finalize_kernel<<<1, UTIL_BLOCK, 0, c->stream>>>(c->partial, nb, c->g.cfl, c->scal, 1, dt_arg);
+        rc = launch_check(c, "cfl_finalize_kernel");
+    } else {
+        rc = standalone_cfl(c, 1, dt_arg);
+    }
     if (rc) return rc;
     if (dt_used_host) {
         unsigned st = 0;

@@ -84,6 +84,13 @@ __device__ __forceinline__ double cfl_speed(const Grid& g, const double q[NV], u
     return s;
 }
 
+// Running CFL maximum and validity flags of the cells a lane writes.
+struct CflAcc {
+    double smax;
+    unsigned bad;
+    __device__ __forceinline__ void add(const Grid& g, const double q[NV]) { smax = fmax(smax, cfl_speed(g, q, bad)); }
+};
+
 template <int BLOCK>
 __device__ __forceinline__ void block_max_to(double v, double* slot)
 {
@@ -131,10 +138,13 @@ struct OutArgs {
 // running sum as (R + fd) + src for alpha1 and R + fd otherwise.  FIRST
 // (no running sum yet) and MODE (what is written) are compile-time so each
 // kernel carries only its own path.
-// qsc: the cell's stage state when the caller holds it (else read from o.qs).
+// qsc, qnc: the cell's stage state and step state when the caller holds
+// them (else read from o.qs, o.qn).  acc: receives the new state of a stage
+// update (CFL maximum of the result).
 template <typename T, int MODE>
 __device__ __forceinline__ void store_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T r[NV],
-                                           const double* qsc = nullptr)
+                                           const double* qsc = nullptr, CflAcc* acc = nullptr,
+                                           const double* qnc = nullptr)
 {
     const long long N = g.N;
     if constexpr (MODE == OUT_ACCUM) {
@@ -147,23 +157,24 @@ __device__ __forceinline__ void store_cell(const Grid& g, const OutArgs<T>& o, l
         double qo[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const double qnv = MODE == OUT_STAGE1 ? 0.0 : o.qn[v * N + cell];
+            const double qnv = MODE == OUT_STAGE1 ? 0.0 : (qnc ? qnc[v] : o.qn[v * N + cell]);
             qo[v] = rk3_combine(MODE, qnv, qsc ? qsc[v] : o.qs[v * N + cell], o.dt, (double)r[v]);
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) o.out[v * N + cell] = qo[v];
+        if (acc) acc->add(g, qo);
     }
 }
 
 template <typename T, bool FIRST, int MODE>
 __device__ __forceinline__ void emit_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T fd[NV], T src,
-                                          const double* qsc = nullptr)
+                                          const double* qsc = nullptr, CflAcc* acc = nullptr)
 {
     T r[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) r[v] = FIRST ? fd[v] : o.racc[v * g.N + cell] + fd[v];
     r[6] += src;
-    store_cell<T, MODE>(g, o, cell, r, qsc);
+    store_cell<T, MODE>(g, o, cell, r, qsc, acc);
 }
 
 // Primitives of one cell in the compute type: the inversion is float64.
@@ -180,16 +191,44 @@ __device__ __forceinline__ void prim_of(const Mix<double>& mix, const double q[N
 // consecutive x, so every access is a contiguous row).  KEEPQ: the march
 // hands over the cell's stage state, which it loaded four cells earlier,
 // so the stage update does not read it again.
-template <typename T, bool FIRST, int MODE, bool KEEPQ = false>
+// CFL: the pass writes the step's new state and also reduces its CFL
+// wave speed (acc).  prefetch() loads the running sum and the step state
+// of the cell the march puts next at the top of the march step, so the
+// loads are in flight during its reconstruction and Riemann solve (lanes
+// past the grid read the clamped column: in bounds, never stored).
+template <typename T, bool FIRST, int MODE, bool KEEPQ = false, bool CFL = false>
 struct GlobalSink {
     static constexpr bool keeps_q = KEEPQ;
+    static constexpr bool NEEDQN = MODE == OUT_STAGE2 || MODE == OUT_STAGE3;
     OutArgs<T> o;
     long long base, sd;
     bool valid;
+    CflAcc acc;
+    T rin[FIRST ? 1 : NV];
+    double qnin[NEEDQN ? NV : 1];
+    __device__ __forceinline__ void prefetch(const Grid& g, int c)
+    {
+        const long long cell = base + (long long)c * sd;
+        if constexpr (!FIRST) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) rin[v] = o.racc[v * g.N + cell];
+        }
+        if constexpr (NEEDQN) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qnin[v] = o.qn[v * g.N + cell];
+        }
+    }
     template <class Win>
     __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src, const Win&, const double* qc)
     {
-        if (valid) emit_cell<T, FIRST, MODE>(g, o, base + (long long)c * sd, fd, src, KEEPQ ? qc : nullptr);
+        if (valid) {
+            T r[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) r[v] = FIRST ? fd[v] : rin[v] + fd[v];
+            r[6] += src;
+            store_cell<T, MODE>(g, o, base + (long long)c * sd, r, KEEPQ ? qc : nullptr, CFL ? &acc : nullptr,
+                                NEEDQN ? qnin : nullptr);
+        }
     }
 };
 
@@ -465,9 +504,11 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
     for (int v = 0; v < NV; ++v) rprev[v] = Fprev[v] = T(0);
 
     for (int c = c0 - 1; c <= c1; ++c) {
-        // next cell entering the window (c+3), fetched early
+        // next cell entering the window (c+3), and what the output of cell
+        // c-1 needs, fetched early
         double qnext[NV];
         if (c < c1) src.load(c + 3, qnext);
+        if (c > c0) sink.prefetch(g, c - 1);
 
         T lft[NV], rgt[NV];
         recon.cell_win(W, eps, lft, rgt);
@@ -528,11 +569,15 @@ struct GlobalSrc {
 // qn and out alias in the third stage (the new state overwrites q in place;
 // each cell's q is read only by the thread that then writes it), so neither
 // is declared __restrict__.
-template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED>
+// CFL (stage 3 only): the block's CFL maximum of the new state goes to
+// partial[block] and invalid states set bits in *status, as in the
+// standalone reduction.
+template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED, bool CFL = false>
 __global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
                                                    T* __restrict__ racc, double* out, int seg,
                                                    const double* __restrict__ dt_dev, double dt_arg,
-                                                   const MlpLane* __restrict__ mlp, unsigned long long* fb)
+                                                   const MlpLane* __restrict__ mlp, unsigned long long* fb,
+                                                   double* __restrict__ partial, unsigned* __restrict__ status)
 {
     constexpr int BLOCK = 256;
     static_assert(DIR == 1 || DIR == 2, "y or z sweep");
@@ -547,13 +592,18 @@ __global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restr
     const int c0 = blockIdx.z * seg;
     const int c1 = min(c0 + seg, n);
     GlobalSrc src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
-    GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED)> sink{
-        OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid};
+    GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CFL> sink{
+        OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid, CflAcc{0.0, 0u}};
     auto recon = make_recon<T, LEARNED>(g, mlp, valid);
     __shared__ T win[5][NV][BLOCK];
     LdsWindow<T, BLOCK> W{&win[0][0][threadIdx.x], 0};
     march<DIR, T>(g, src, sink, recon, c0, c1, W);
     recon.flush(fb);
+    if constexpr (CFL) {
+        if (sink.acc.bad) atomicOr(status, sink.acc.bad);
+        const unsigned blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        block_max_to<BLOCK>(sink.acc.smax, partial + blk);
+    }
 }
 
 // Marching x sweep, for rows longer than the whole-row kernel takes.  The 64
@@ -605,6 +655,7 @@ struct LdsSink {
     int nx, c0, c1;
 
     static constexpr bool keeps_q = false;
+    __device__ __forceinline__ void prefetch(const Grid&, int) {}
     template <class Win>
     __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src, const Win&, const double*)
     {

@@ -278,6 +278,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
 template <typename T, int MODE>
 struct XYSink {
     static constexpr bool keeps_q = false;
+    __device__ __forceinline__ void prefetch(const Grid&, int) {}
     OutArgs<T> o;
     T* P;   // [NV][nx+4]
     T* L;   // [NV][nx]

@@ -219,6 +219,45 @@ def test_fused_xy_pass_matches_separate_passes(monkeypatch, n, bc, precision):
     assert np.all(e_rhs <= tol_r) and np.all(e_q <= tol_q)
 
 
+@pytest.mark.parametrize("n,bc", [((24, 20, 28), ((1, 1), (0, 0), (0, 0))),  # z sweep reduces
+                                  ((1, 40, 33), ((0, 0), (1, 1), (0, 0))),  # y, z active: z reduces
+                                  ((1, 64, 1), ((0, 0), (1, 1), (0, 0))),  # y only: the y sweep reduces
+                                  ((40, 36, 1), ((1, 1), (0, 0), (0, 0)))])  # fused x-y last: standalone pass
+def test_cfl_in_last_sweep_matches_standalone(monkeypatch, n, bc):
+    """The CFL reduction inside the last sweep of a step gives the same time
+    steps and states as the standalone reduction, and the oracle's CFL time
+    step of the state it reduced."""
+    P = wl.random_smooth(n=n, seed=13, bc=bc)
+    g, q0 = _q0(P)
+    res = []
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("MFX_FUSE_CFL", fuse)
+        s = gpu_solver(P["spec"], q0=q0)
+        dts = [s.rk3_step(sync=True) for _ in range(4)]
+        q = s.get_state().cpu().numpy()
+        dts.append(s.rk3_step(sync=True))  # CFL time step of q, from the fourth step's reduction
+        res.append((dts, q))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1])
+    assert res[1][0][-1] == pytest.approx(oracle.cfl_dt(g, res[1][1]), rel=1e-15)
+
+
+@pytest.mark.parametrize("fuse", ["0", "1"])
+def test_blown_up_step_is_flagged(monkeypatch, fuse):
+    """A time step far above the CFL limit drives the state non-physical;
+    the check after the step reports it (MFX_ESTATE) with either CFL path."""
+    from paper_2409_10729_amd import MfxError
+
+    monkeypatch.setenv("MFX_FUSE_CFL", fuse)
+    P = wl.shock_droplet(n=(32, 24, 20), seed=2)
+    g, q0 = _q0(P)
+    s = gpu_solver(P["spec"], q0=q0)
+    dt_cfl = oracle.cfl_dt(g, q0)
+    with pytest.raises(MfxError, match="non-physical"):
+        for _ in range(3):
+            s.rk3_step(1e3 * dt_cfl, sync=True)
+
+
 def test_repeat_runs_bitwise_equal():
     P = wl.advected_bubble(n=48, seed=5)
     g, q0 = _q0(P)
