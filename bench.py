@@ -43,6 +43,29 @@ def sweep_bytes_per_cell(first: int, mode: int, rhs_bytes: int = STATE_BYTES) ->
     return b
 
 
+# Algorithmic float64 operations per cell (+, -, *, /, sqrt, min, max each
+# one; constants such as 13/12 and the per-fluid 1/(gamma-1) precomputed;
+# a value the formulas use twice counted once), from the definitions:
+# conserved -> primitive 21; WENO5 with Jiang-Shu weights, both edges of one
+# variable: indicators 33, right edge 35, left edge 29 (its (eps + beta)^2
+# shared) = 97; HLLC with Davis speeds, one face: 120; flux difference,
+# alpha1 source and accumulation 25; the RK stage combination 2 (stage 1) or
+# 5 (stages 2, 3) per variable.
+FLOPS_CONV = 21
+FLOPS_WENO_VAR = 97
+FLOPS_HLLC = 120
+FLOPS_FLUXDIFF = 25
+FLOPS_RK = {0: 0, 1: 0, 2: 14, 3: 35, 4: 35}
+FP64_PEAK_TFLOPS = 78.6  # MI355X float64 vector peak (FMA = 2 flops)
+
+
+def sweep_flops_per_cell(d: int, mode: int) -> int:
+    """Algorithmic float64 flops per cell of one launch of pass d (3 = the
+    fused x-y pass: both directions, one conversion)."""
+    ndir = 2 if d == 3 else 1
+    return FLOPS_CONV + ndir * (7 * FLOPS_WENO_VAR + FLOPS_HLLC + FLOPS_FLUXDIFF) + FLOPS_RK[mode]
+
+
 def source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2409_10729_amd", "csrc")
@@ -211,20 +234,25 @@ def main():
         per_dir = {}
         for (d, first, mode), (ms, cnt) in prof.items():
             b = sweep_bytes_per_cell(first, mode, rhs_bytes) * N
-            e = per_dir.setdefault(d, {"ms": 0.0, "launches": 0, "bytes": 0})
+            e = per_dir.setdefault(d, {"ms": 0.0, "launches": 0, "bytes": 0, "flops": 0})
             e["ms"] += ms
             e["launches"] += cnt
             e["bytes"] += b * cnt
+            e["flops"] += sweep_flops_per_cell(d, mode) * N * cnt
         kernels = {}
         for d, e in sorted(per_dir.items()):
             mean_ms = e["ms"] / e["launches"]
             bpl = e["bytes"] / e["launches"]
+            fpl = e["flops"] / e["launches"]
             kernels[KERNEL_NAMES[d]] = {
                 "mean_us": round(mean_ms * 1e3, 2),
                 "launches": e["launches"],
                 "share": round(e["ms"] / ms_total, 4),
                 "alg_bytes_per_launch": bpl,
                 "achieved_GBs": round(bpl / (mean_ms * 1e-3) / 1e9, 1),
+                "alg_flops_per_launch": fpl,
+                "achieved_TFLOPs": round(fpl / (mean_ms * 1e-3) / 1e12, 2),
+                "flop_per_byte": round(fpl / bpl, 2),
             }
         step_bytes = sum(e["bytes"] for e in per_dir.values()) / args.steps
         return kernels, step_bytes
@@ -238,17 +266,25 @@ def main():
     print(f"[bench] fp64: {ms_step:.3f} ms/step, {grind:.4f} ns/cell/stage", file=sys.stderr, flush=True)
     dom = max(kernels, key=lambda k: kernels[k]["mean_us"] * kernels[k]["launches"])
     kd = kernels[dom]
-    roofline = {
-        "bound": "hbm",
-        "achieved": kd["achieved_GBs"],
-        "peak": HBM_PEAK_GBS,
-        "unit": "GB/s",
-        "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4),
+    # the dominant kernel's bound by its arithmetic intensity against the
+    # ridge point of the float64 vector peak and HBM bandwidth
+    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+    if kd["flop_per_byte"] >= ridge:
+        roofline = {"bound": "alu", "achieved": kd["achieved_TFLOPs"], "peak": FP64_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(kd["achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4)}
+    else:
+        roofline = {"bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4)}
+    roofline.update({
         "traffic": load_traffic(dom),
         "kernel": dom,
         "mean_us": kd["mean_us"],
         "alg_bytes_per_launch": kd["alg_bytes_per_launch"],
-    }
+        "alg_flops_per_launch": kd["alg_flops_per_launch"],
+        "flop_per_byte": kd["flop_per_byte"],
+        "ridge_flop_per_byte": round(ridge, 2),
+        "hbm_frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4),
+    })
 
     forms = {"fp64": {"ms_per_step": round(ms_step, 4), "grind": round(grind, 5), "kernels": kernels,
                       "step_alg_bytes_hbm_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
