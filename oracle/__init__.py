@@ -37,6 +37,7 @@ class OrcGrid(ctypes.Structure):
         ("eps", ctypes.c_double),
         ("cfl", ctypes.c_double),
         ("weno_z", ctypes.c_int32),
+        ("weno_order", ctypes.c_int32),
     ]
 
 
@@ -67,6 +68,7 @@ def lib():
         L.orc_weno5.argtypes = [dp, ctypes.c_double, dp, dp]
         L.orc_weno5_betas.argtypes = [dp, dp]
         L.orc_weno5_z.argtypes = [dp, ctypes.c_double, dp, dp]
+        L.orc_weno3.argtypes = [dp, ctypes.c_double, dp, dp]
         L.orc_hllc.argtypes = [gp, dp, dp, ctypes.c_int, dp, dp]
         L.orc_sound_speed.argtypes = [gp, dp]
         L.orc_sound_speed.restype = ctypes.c_double
@@ -94,8 +96,8 @@ def _dp(a: np.ndarray):
 
 def make_grid(spec: dict, weno_z: bool = False) -> OrcGrid:
     """Grid from a problem description dict (keys n, dx, bc, gamma, pinf, eps,
-    cfl).  weno_z selects the WENO-Z weights (a comparison form) instead of
-    Jiang-Shu's."""
+    cfl, and optionally weno_order: 5 or 3).  weno_z selects the WENO-Z
+    weights (a comparison form) instead of Jiang-Shu's."""
     g = OrcGrid()
     for d in range(3):
         g.n[d] = int(spec["n"][d])
@@ -107,6 +109,9 @@ def make_grid(spec: dict, weno_z: bool = False) -> OrcGrid:
     g.eps = float(spec.get("eps", 1e-6))
     g.cfl = float(spec.get("cfl", 0.4))
     g.weno_z = 1 if weno_z else 0
+    g.weno_order = int(spec.get("weno_order", 5))
+    if g.weno_order not in (3, 5):
+        raise ValueError("weno_order must be 3 or 5")
     return g
 
 
@@ -183,6 +188,16 @@ def weno5(v, eps=1e-6):
     l = ctypes.c_double()
     r = ctypes.c_double()
     lib().orc_weno5(_dp(v), float(eps), ctypes.byref(l), ctypes.byref(r))
+    return l.value, r.value
+
+
+def weno3(v, eps=1e-6):
+    """(left edge, right edge) of the middle cell of a 3-value stencil,
+    WENO3 with Jiang-Shu weights."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    l = ctypes.c_double()
+    r = ctypes.c_double()
+    lib().orc_weno3(_dp(v), float(eps), ctypes.byref(l), ctypes.byref(r))
     return l.value, r.value
 
 

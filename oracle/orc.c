@@ -60,6 +60,7 @@ typedef struct {
     double eps;        /* WENO epsilon */
     double cfl;
     int32_t weno_z;    /* 0: Jiang-Shu weights (the paper's WENO5); 1: WENO-Z weights (comparison form) */
+    int32_t weno_order; /* 5 (default; 0 reads as 5) or 3: the two orders Sec. II-B names */
 } orc_grid;
 
 /* ---------- equation of state (Sec. II-A) ---------- */
@@ -191,6 +192,46 @@ static void weno5(const double* v, double eps, double* left, double* right)
     *left = (a0 / s) * l0 + (a1 / s) * l1 + (a2 / s) * l2;
 }
 
+/* WENO3 with Jiang-Shu weights (the third-order reconstruction Sec. II-B
+   names beside WENO5; Jiang & Shu 1996, Shu 2006).  Cell c with stencil
+   values v[0..2] = w_{c-1..c+1}; two candidate stencils {c-1, c} and
+   {c, c+1}.  right = value at c+1/2 (candidates -v0/2 + 3v1/2 and
+   v1/2 + v2/2, linear weights 1/3, 2/3); left = value at c-1/2 (candidates
+   v0/2 + v1/2 and 3v1/2 - v2/2, linear weights 2/3, 1/3).  Indicators:
+   the squared undivided differences of the two stencils. */
+static void weno3(const double* v, double eps, double* left, double* right)
+{
+    double b0 = (v[1] - v[0]) * (v[1] - v[0]);
+    double b1 = (v[2] - v[1]) * (v[2] - v[1]);
+
+    double r0 = -0.5 * v[0] + 1.5 * v[1];
+    double r1 = 0.5 * v[1] + 0.5 * v[2];
+    double a0 = (1.0 / 3.0) / ((eps + b0) * (eps + b0));
+    double a1 = (2.0 / 3.0) / ((eps + b1) * (eps + b1));
+    double s = a0 + a1;
+    *right = (a0 / s) * r0 + (a1 / s) * r1;
+
+    double l0 = 0.5 * v[0] + 0.5 * v[1];
+    double l1 = 1.5 * v[1] - 0.5 * v[2];
+    a0 = (2.0 / 3.0) / ((eps + b0) * (eps + b0));
+    a1 = (1.0 / 3.0) / ((eps + b1) * (eps + b1));
+    s = a0 + a1;
+    *left = (a0 / s) * l0 + (a1 / s) * l1;
+}
+
+/* Face states of the middle cell of a 5-value stencil in the grid's
+   reconstruction: WENO5 (Jiang-Shu or WENO-Z weights), or WENO3 on the
+   middle three values. */
+static void reconstruct(const orc_grid* g, const double* st, double* left, double* right)
+{
+    if (g->weno_order == 3)
+        weno3(st + 1, g->eps, left, right);
+    else if (g->weno_z)
+        weno5_z(st, g->eps, left, right);
+    else
+        weno5(st, g->eps, left, right);
+}
+
 /* ---------- HLLC (Toro 2009, Davis wave speeds) ----------
    Face with normal along direction d; wl, wr primitive states.  Returns
    the 7 flux components and the face velocity used for div(u). */
@@ -269,6 +310,7 @@ void orc_weno5(const double* v, double eps, double* left, double* right)
 }
 void orc_weno5_betas(const double* v, double* b) { weno5_betas(v, b); }
 void orc_weno5_z(const double* v, double eps, double* left, double* right) { weno5_z(v, eps, left, right); }
+void orc_weno3(const double* v, double eps, double* left, double* right) { weno3(v, eps, left, right); }
 void orc_hllc(const orc_grid* g, const double* wl, const double* wr, int d, double* F, double* uf)
 {
     hllc(g, wl, wr, d, F, uf);
@@ -367,7 +409,7 @@ void orc_rhs(const orc_grid* g, const double* q, double* rhs)
                         double st[5];
                         for (int o = -2; o <= 2; ++o)
                             st[o + 2] = wp[v * NP + base_p + (int64_t)(c + gh[d] + o) * stride_p[d]];
-                        (g->weno_z ? weno5_z : weno5)(st, g->eps, &lft[(c + 1) * NV + v], &rgt[(c + 1) * NV + v]);
+                        reconstruct(g, st, &lft[(c + 1) * NV + v], &rgt[(c + 1) * NV + v]);
                     }
                 }
                 for (int f = 0; f <= n; ++f)
@@ -417,7 +459,7 @@ void orc_rhs_at(const orc_grid* g, const double* q, int64_t ncell, const int64_t
                 for (int v = 0; v < NV; ++v) {
                     double st[5];
                     for (int o = 0; o < 5; ++o) st[o] = w7[cc + o][v];
-                    (g->weno_z ? weno5_z : weno5)(st, g->eps, &lft[cc][v], &rgt[cc][v]);
+                    reconstruct(g, st, &lft[cc][v], &rgt[cc][v]);
                 }
             double Fm[NV], Fp[NV], um, up;
             hllc(g, rgt[0], lft[1], d, Fm, &um);

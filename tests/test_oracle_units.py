@@ -149,6 +149,84 @@ def test_weno_essentially_non_oscillatory_at_step():
             assert -1e9 * 1e-6 <= x <= 1e9 * (1 + 1e-6)
 
 
+# ---------------------------------------------------------------- WENO3 (Jiang-Shu weights)
+
+@pytest.mark.parametrize("seed", range(3))
+def test_weno3_exact_for_linear_data(seed):
+    """Each candidate reproduces linear data, so any convex weights do:
+    cell averages a, a+s, a+2s have edge values a+s/2 and a+3s/2."""
+    rng = np.random.default_rng(seed)
+    for _ in range(10):
+        a, sl = rng.uniform(-5, 5, size=2)
+        l, r = oracle.weno3([a, a + sl, a + 2 * sl])
+        assert l == pytest.approx(a + sl / 2, rel=1e-13, abs=1e-13)
+        assert r == pytest.approx(a + 1.5 * sl, rel=1e-13, abs=1e-13)
+
+
+def test_weno3_linear_weights_reproduce_a_symmetric_quadratic():
+    """With equal indicators the weights are the linear ones (1/3, 2/3), and
+    the reconstruction is the third-order one: exact for the point values of
+    a parabola from its cell averages.  Cell averages of x^2 over unit cells
+    centred on -1, 0, 1 are (13/12, 1/12, 13/12); x^2 at +-1/2 is 1/4."""
+    l, r = oracle.weno3([13.0 / 12.0, 1.0 / 12.0, 13.0 / 12.0], eps=1e-6)
+    assert l == pytest.approx(0.25, rel=1e-14) and r == pytest.approx(0.25, rel=1e-14)
+    # scaled and shifted: a x^2 + c
+    l, r = oracle.weno3([3 * 13 / 12 + 2, 3 / 12 + 2, 3 * 13 / 12 + 2], eps=1e-6)
+    assert l == pytest.approx(0.75 + 2, rel=1e-14) and r == pytest.approx(0.75 + 2, rel=1e-14)
+
+
+def test_weno3_constant_and_mirror():
+    l, r = oracle.weno3([7.0] * 3)
+    assert l == pytest.approx(7.0, rel=1e-15) and r == pytest.approx(7.0, rel=1e-15)
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        v = rng.uniform(-1, 1, size=3)
+        l, r = oracle.weno3(v)
+        l2, r2 = oracle.weno3(v[::-1])
+        assert l2 == r and r2 == l
+
+
+def test_weno3_third_order_on_smooth_data():
+    """Smooth data away from critical points, indicators far above eps:
+    error ~ h^3 (the candidates are second order; the weights recover the
+    third-order combination)."""
+    f = np.polynomial.Polynomial([0.3, 1.0, -0.7, 0.4, 0.9, -0.5, 0.2])
+    F = f.integ()
+    x0 = 0.37
+    errs = []
+    for h in [0.04, 0.02, 0.01, 0.005]:
+        xs = x0 + np.arange(-1, 2) * h
+        v = np.array([(F(x + h / 2) - F(x - h / 2)) / h for x in xs])
+        l, r = oracle.weno3(v, eps=1e-40)
+        errs.append(abs(r - f(x0 + h / 2)) + abs(l - f(x0 - h / 2)))
+    orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(orders > 2.7), orders
+
+
+def test_weno3_essentially_non_oscillatory_at_step():
+    """A jump on one side: the smooth stencil takes (almost) all the weight."""
+    for v, (lo, hi) in (([0, 0, 1], (0, 0)), ([1, 1, 0], (1, 1)), ([0, 1, 1], (1, 1)), ([1, 0, 0], (0, 0))):
+        l, r = oracle.weno3(np.array(v, dtype=float) * 1e9)
+        expect_r = (lo if v[2] != v[1] else v[1]) * 1e9
+        expect_l = (v[1] if v[0] != v[1] else v[1]) * 1e9
+        assert r == pytest.approx(expect_r, abs=1e9 * 1e-6)
+        assert l == pytest.approx(expect_l, abs=1e9 * 1e-6)
+        for x in (l, r):
+            assert -1e9 * 1e-6 <= x <= 1e9 * (1 + 1e-6)
+
+
+def test_weno3_rhs_differs_from_weno5_and_matches_per_cell_path():
+    P = wl.random_smooth(n=(20, 12, 8), seed=2)
+    spec3 = dict(P["spec"], weno_order=3)
+    g3, g5 = oracle.make_grid(spec3), oracle.make_grid(P["spec"])
+    q = oracle.prim_to_cons(g5, P["w"])
+    r3, r5 = oracle.rhs(g3, q), oracle.rhs(g5, q)
+    assert not np.allclose(r3, r5, rtol=1e-6, atol=0)
+    cells = np.arange(0, 20 * 12 * 8, 37, dtype=np.int64)
+    at = oracle.rhs_at(g3, q, cells)
+    assert np.array_equal(at, r3.reshape(7, -1)[:, cells].T)
+
+
 # ---------------------------------------------------------------- WENO-Z (comparison form)
 
 @pytest.mark.parametrize("seed", range(3))
