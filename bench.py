@@ -50,20 +50,23 @@ def sweep_bytes_per_cell(first: int, mode: int, rhs_bytes: int = STATE_BYTES) ->
 # variable: indicators 33, right edge 35, left edge 29 (its (eps + beta)^2
 # shared) = 97; HLLC with Davis speeds, one face: 120; flux difference,
 # alpha1 source and accumulation 25; the RK stage combination 2 (stage 1) or
-# 5 (stages 2, 3) per variable.
+# 5 (stages 2, 3) per variable.  WENO3 (Jiang-Shu), one variable, both
+# edges: indicators 4, right edge 18, left edge 14 = 36.
 FLOPS_CONV = 21
 FLOPS_WENO_VAR = 97
+FLOPS_WENO3_VAR = 36
 FLOPS_HLLC = 120
 FLOPS_FLUXDIFF = 25
 FLOPS_RK = {0: 0, 1: 0, 2: 14, 3: 35, 4: 35}
 FP64_PEAK_TFLOPS = 78.6  # MI355X float64 vector peak (FMA = 2 flops)
 
 
-def sweep_flops_per_cell(d: int, mode: int) -> int:
+def sweep_flops_per_cell(d: int, mode: int, order: int = 5) -> int:
     """Algorithmic float64 flops per cell of one launch of pass d (3 = the
     fused x-y pass: both directions, one conversion)."""
     ndir = 2 if d == 3 else 1
-    return FLOPS_CONV + ndir * (7 * FLOPS_WENO_VAR + FLOPS_HLLC + FLOPS_FLUXDIFF) + FLOPS_RK[mode]
+    weno = FLOPS_WENO_VAR if order == 5 else FLOPS_WENO3_VAR
+    return FLOPS_CONV + ndir * (7 * weno + FLOPS_HLLC + FLOPS_FLUXDIFF) + FLOPS_RK[mode]
 
 
 def source_hash() -> str:
@@ -179,18 +182,18 @@ def main():
             if os.path.exists(path):
                 nets[wmode] = (torch.from_numpy(learned.load_params(path)).cuda(), path)
 
-    def new_solver(precision, weights=MFX_WENO5_JS):
-        s = Solver(P["spec"], precision=precision, weights=weights)
+    def new_solver(precision, weights=MFX_WENO5_JS, order=5):
+        s = Solver(dict(P["spec"], weno_order=order), precision=precision, weights=weights)
         if weights != MFX_WENO5_JS:
             s.set_mlp(nets[weights][0])
         s.set_primitive(w_dev)
         return s
 
-    def time_form(precision, dt, weights=MFX_WENO5_JS):
+    def time_form(precision, dt, weights=MFX_WENO5_JS, order=5):
         """Warm-up, then `steps` timed steps with HIP events on the solver's
         stream; per-kernel event times from the library.  dt <= 0 uses the
         device CFL step (FP64 headline run)."""
-        s = new_solver(precision, weights)
+        s = new_solver(precision, weights, order)
         for _ in range(args.warmup):
             s.rk3_step(dt)
         torch.cuda.synchronize()
@@ -212,9 +215,9 @@ def main():
         s.destroy()
         return ms_total, prof
 
-    def replay(precision, dts, weights=MFX_WENO5_JS):
+    def replay(precision, dts, weights=MFX_WENO5_JS, order=5):
         """Final state (host, [7, N]) and fallback count after replaying dts."""
-        s = new_solver(precision, weights)
+        s = new_solver(precision, weights, order)
         for dt in dts:
             s.rk3_step(dt)
         q = s.get_state().cpu().numpy().reshape(7, -1)
@@ -230,7 +233,7 @@ def main():
         rho_l1 = float(np.abs(q[0] + q[1] - rho64).sum() / np.abs(rho64).sum())
         return [float(f"{x:.3e}") for x in l1], float(f"{rho_l1:.3e}")
 
-    def kernel_table(prof, ms_total, rhs_bytes):
+    def kernel_table(prof, ms_total, rhs_bytes, order=5):
         per_dir = {}
         for (d, first, mode), (ms, cnt) in prof.items():
             b = sweep_bytes_per_cell(first, mode, rhs_bytes) * N
@@ -238,7 +241,7 @@ def main():
             e["ms"] += ms
             e["launches"] += cnt
             e["bytes"] += b * cnt
-            e["flops"] += sweep_flops_per_cell(d, mode) * N * cnt
+            e["flops"] += sweep_flops_per_cell(d, mode, order) * N * cnt
         kernels = {}
         for d, e in sorted(per_dir.items()):
             mean_ms = e["ms"] / e["launches"]
@@ -299,20 +302,23 @@ def main():
         s64.destroy()
         del s64
         dt_fixed = dts[0] if dts else 1e-9
-        variants = [("fp32_mixed", MFX_WENO5_JS)]
+        # (name, precision, weights, WENO order); fp64_weno3 is the
+        # third-order reconstruction, a different scheme: its L1 distance to
+        # the fifth-order run is its accuracy difference
+        variants = [("fp32_mixed", MFX_FP32_MIXED, MFX_WENO5_JS, 5), ("fp64_weno3", MFX_FP64, MFX_WENO5_JS, 3)]
         if MFX_WENO5_LEARNED in nets:
-            variants.append(("learned", MFX_WENO5_LEARNED))
+            variants.append(("learned", MFX_FP32_MIXED, MFX_WENO5_LEARNED, 5))
         if MFX_WENO5_LEARNED_EDGE in nets:
-            variants.append(("learned_edge", MFX_WENO5_LEARNED_EDGE))
-        for name, weights in variants:
+            variants.append(("learned_edge", MFX_FP32_MIXED, MFX_WENO5_LEARNED_EDGE, 5))
+        for name, prec, weights, order in variants:
             print(f"[bench] {name}: replaying {len(dts)} steps", file=sys.stderr, flush=True)
-            q, fb = replay(MFX_FP32_MIXED, dts, weights)
+            q, fb = replay(prec, dts, weights, order)
             l1, rho_l1 = l1_vs(q, q64)
             del q
             print(f"[bench] {name}: timing {args.steps} steps", file=sys.stderr, flush=True)
-            ms_f, prof_f = time_form(MFX_FP32_MIXED, dt_fixed, weights)
+            ms_f, prof_f = time_form(prec, dt_fixed, weights, order)
             msf_step = ms_f / args.steps
-            kf, _ = kernel_table(prof_f, ms_f, 28)
+            kf, _ = kernel_table(prof_f, ms_f, 56 if prec == MFX_FP64 else 28, order)
             forms[name] = {
                 "ms_per_step": round(msf_step, 4),
                 "grind": round(msf_step * 1e6 / (N * 3), 5),

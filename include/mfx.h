@@ -83,6 +83,9 @@ typedef struct {
     double weno_eps;   /* WENO epsilon (absolute), > 0; 1e-6 is Jiang-Shu's value */
     int32_t precision; /* MFX_FP64 or MFX_FP32_MIXED */
     int32_t weights;   /* MFX_WENO5_JS, MFX_WENO5_LEARNED or MFX_WENO5_LEARNED_EDGE */
+    int32_t weno_order; /* reconstruction order, 5 or 3 (Sec. II-B names both; 0 reads as 5):
+                           WENO3 with Jiang-Shu weights on the middle three cells of each
+                           stencil; the learned weights need 5 (MFX_EINVAL otherwise) */
 } mfx_grid_desc;
 
 typedef struct mfx_ctx mfx_ctx;

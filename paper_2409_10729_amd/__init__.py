@@ -28,8 +28,9 @@ def workspace_bytes(spec: dict, precision: int = MFX_FP64, weights: int = MFX_WE
 class Solver:
     """One mfx context on the current CUDA(HIP) device.
 
-    ``spec`` is a problem description (n, dx, bc, gamma, pinf, eps, cfl) as
-    produced by :mod:`paper_2409_10729_amd.workloads`.  Arrays passed in and
+    ``spec`` is a problem description (n, dx, bc, gamma, pinf, eps, cfl, and
+    optionally weno_order 5 or 3) as produced by
+    :mod:`paper_2409_10729_amd.workloads`.  Arrays passed in and
     out are torch tensors on the device, float64, shape [7, nz, ny, nx].
     """
 

@@ -41,6 +41,7 @@ class GridDesc(ctypes.Structure):
         ("weno_eps", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("weights", ctypes.c_int32),
+        ("weno_order", ctypes.c_int32),
     ]
 
 
@@ -128,6 +129,7 @@ def make_desc(spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS
     d.weno_eps = float(spec.get("eps", 1e-6))
     d.precision = int(precision)
     d.weights = int(weights)
+    d.weno_order = int(spec.get("weno_order", 5))
     return d
 
 

@@ -151,6 +151,8 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     return L;
 }
 
+int weno_order(const mfx_grid_desc& d) { return d.weno_order == 3 ? 3 : 5; }
+
 bool validate(const mfx_grid_desc* d, std::string& why)
 {
     if (!d) {
@@ -206,6 +208,14 @@ bool validate(const mfx_grid_desc* d, std::string& why)
     }
     if (d->weights != MFX_WENO5_JS && d->weights != MFX_WENO5_LEARNED && d->weights != MFX_WENO5_LEARNED_EDGE) {
         why = "unknown weights mode";
+        return false;
+    }
+    if (d->weno_order != 0 && d->weno_order != 3 && d->weno_order != 5) {
+        why = "weno_order must be 3 or 5 (0 reads as 5)";
+        return false;
+    }
+    if (d->weno_order == 3 && d->weights != MFX_WENO5_JS) {
+        why = "learned weights need weno_order 5";
         return false;
     }
     return true;
@@ -385,7 +395,7 @@ struct LaunchArgs {
 
 // The x row sweep reads the boundary faces that boundary_faces_x leaves in
 // `bface` (launched just before it on the same stream).
-template <int DIR, typename T, bool FIRST, int MODE, bool L>
+template <int DIR, typename T, bool FIRST, int MODE, bool L, int ORDER>
 void launch_one(const LaunchArgs& a)
 {
     const SweepGeom& sg = *a.sg;
@@ -394,48 +404,49 @@ void launch_one(const LaunchArgs& a)
         if (sg.xrows) {
             T* bf = static_cast<T*>(a.bface);
             const long long rows = (long long)a.g->n[1] * a.g->n[2];
-            boundary_faces_x<T, L><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf, a.mlp, a.fb);
-            sweep_x_rows<T, FIRST, MODE, L><<<sg.grid, sg.block, sg.lds, a.st>>>(
+            boundary_faces_x<T, L, ORDER><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf, a.mlp,
+                                                                                             a.fb);
+            sweep_x_rows<T, FIRST, MODE, L, ORDER><<<sg.grid, sg.block, sg.lds, a.st>>>(
                 *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.mlp, a.fb);
         } else {
-            sweep_x_march<T, FIRST, MODE, L><<<sg.grid, XROWS, 0, a.st>>>(
+            sweep_x_march<T, FIRST, MODE, L, ORDER><<<sg.grid, XROWS, 0, a.st>>>(
                 *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb);
         }
     } else {
         if constexpr (MODE == OUT_STAGE3 && !L) {
             if (a.cfl) {
-                sweep_yz<DIR, T, FIRST, MODE, L, true><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(
+                sweep_yz<DIR, T, FIRST, MODE, L, true, ORDER><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(
                     *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, a.partial, a.status);
                 return;
             }
         }
-        sweep_yz<DIR, T, FIRST, MODE, L><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(
+        sweep_yz<DIR, T, FIRST, MODE, L, false, ORDER><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(
             *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, nullptr, nullptr);
     }
 }
 
-template <int DIR, typename T, bool FIRST, bool L>
+template <int DIR, typename T, bool FIRST, bool L, int ORDER>
 void launch_mode(int mode, const LaunchArgs& a)
 {
     switch (mode) {
-    case OUT_ACCUM: launch_one<DIR, T, FIRST, OUT_ACCUM, L>(a); break;
-    case OUT_RHS: launch_one<DIR, T, FIRST, OUT_RHS, L>(a); break;
-    case OUT_STAGE1: launch_one<DIR, T, FIRST, OUT_STAGE1, L>(a); break;
-    case OUT_STAGE2: launch_one<DIR, T, FIRST, OUT_STAGE2, L>(a); break;
-    default: launch_one<DIR, T, FIRST, OUT_STAGE3, L>(a); break;
+    case OUT_ACCUM: launch_one<DIR, T, FIRST, OUT_ACCUM, L, ORDER>(a); break;
+    case OUT_RHS: launch_one<DIR, T, FIRST, OUT_RHS, L, ORDER>(a); break;
+    case OUT_STAGE1: launch_one<DIR, T, FIRST, OUT_STAGE1, L, ORDER>(a); break;
+    case OUT_STAGE2: launch_one<DIR, T, FIRST, OUT_STAGE2, L, ORDER>(a); break;
+    default: launch_one<DIR, T, FIRST, OUT_STAGE3, L, ORDER>(a); break;
     }
 }
 
 // The x sweep, when active, is always the first direction of a pass.
-template <typename T, bool L>
+template <typename T, bool L, int ORDER = 5>
 void launch_dispatch(int d, bool first, int mode, const LaunchArgs& a)
 {
     if (d == 0)
-        launch_mode<0, T, true, L>(mode, a);
+        launch_mode<0, T, true, L, ORDER>(mode, a);
     else if (d == 1)
-        first ? launch_mode<1, T, true, L>(mode, a) : launch_mode<1, T, false, L>(mode, a);
+        first ? launch_mode<1, T, true, L, ORDER>(mode, a) : launch_mode<1, T, false, L, ORDER>(mode, a);
     else
-        first ? launch_mode<2, T, true, L>(mode, a) : launch_mode<2, T, false, L>(mode, a);
+        first ? launch_mode<2, T, true, L, ORDER>(mode, a) : launch_mode<2, T, false, L, ORDER>(mode, a);
 }
 
 int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* out, int first, int mode,
@@ -452,12 +463,15 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
     const LaunchArgs la{&sg,      c->stream,   &c->g,      qs,        qn,       c->r,
                         out,      dt_dev,      dt_arg,     c->bface,  c->mlp,   c->fallback,
                         c->partial, c->status, cfl};
+    const bool o3 = weno_order(c->desc) == 3;
     if (c->desc.weights != MFX_WENO5_JS)
         launch_dispatch<float, true>(d, first != 0, mode, la);
     else if (c->desc.precision == MFX_FP32_MIXED)
-        launch_dispatch<float, false>(d, first != 0, mode, la);
+        o3 ? launch_dispatch<float, false, 3>(d, first != 0, mode, la)
+           : launch_dispatch<float, false, 5>(d, first != 0, mode, la);
     else
-        launch_dispatch<double, false>(d, first != 0, mode, la);
+        o3 ? launch_dispatch<double, false, 3>(d, first != 0, mode, la)
+           : launch_dispatch<double, false, 5>(d, first != 0, mode, la);
     int rc = launch_check(c, "sweep kernel");
     if (rc) return rc;
     if (c->profiling) {
@@ -475,13 +489,14 @@ bool fused_xy(const mfx_ctx* c)
            use_xrows(c->g.n, c->xmode_override, c->elem);
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, int ORDER>
 void launch_xy_mode(mfx_ctx* c, const double* qs, const double* qn, double* out, const double* dt_dev, double dt_arg)
 {
     const Grid& g = c->g;
     const long long rows = (long long)g.n[1] * g.n[2];
     T* bf = static_cast<T*>(c->bface);
-    boundary_faces_x<T, false><<<(unsigned)((rows + 255) / 256), 256, 0, c->stream>>>(g, qs, bf, c->mlp, c->fallback);
+    boundary_faces_x<T, false, ORDER><<<(unsigned)((rows + 255) / 256), 256, 0, c->stream>>>(g, qs, bf, c->mlp,
+                                                                                              c->fallback);
     // segments along y as for the y sweep (lanes = x, blocks over z and segments)
     int seg = c->seg_override > 0 ? c->seg_override : 64;
     const long long pencils = (long long)g.n[0] * g.n[2];
@@ -489,20 +504,20 @@ void launch_xy_mode(mfx_ctx* c, const double* qs, const double* qn, double* out,
     seg = std::min(seg, g.n[1]);
     const dim3 grid(1, (unsigned)g.n[2], (unsigned)((g.n[1] + seg - 1) / seg));
     const int block = 64 * ((g.n[0] + 63) / 64);
-    sweep_xy<T, MODE><<<grid, block, xrow_lds_bytes(g.n[0], sizeof(T)), c->stream>>>(
+    sweep_xy<T, MODE, ORDER><<<grid, block, xrow_lds_bytes(g.n[0], sizeof(T)), c->stream>>>(
         g, qs, qn, static_cast<T*>(c->r), out, seg, bf, dt_dev, dt_arg);
 }
 
-template <typename T>
+template <typename T, int ORDER>
 void launch_xy(mfx_ctx* c, int mode, const double* qs, const double* qn, double* out, const double* dt_dev,
                double dt_arg)
 {
     switch (mode) {
-    case OUT_ACCUM: launch_xy_mode<T, OUT_ACCUM>(c, qs, qn, out, dt_dev, dt_arg); break;
-    case OUT_RHS: launch_xy_mode<T, OUT_RHS>(c, qs, qn, out, dt_dev, dt_arg); break;
-    case OUT_STAGE1: launch_xy_mode<T, OUT_STAGE1>(c, qs, qn, out, dt_dev, dt_arg); break;
-    case OUT_STAGE2: launch_xy_mode<T, OUT_STAGE2>(c, qs, qn, out, dt_dev, dt_arg); break;
-    default: launch_xy_mode<T, OUT_STAGE3>(c, qs, qn, out, dt_dev, dt_arg); break;
+    case OUT_ACCUM: launch_xy_mode<T, OUT_ACCUM, ORDER>(c, qs, qn, out, dt_dev, dt_arg); break;
+    case OUT_RHS: launch_xy_mode<T, OUT_RHS, ORDER>(c, qs, qn, out, dt_dev, dt_arg); break;
+    case OUT_STAGE1: launch_xy_mode<T, OUT_STAGE1, ORDER>(c, qs, qn, out, dt_dev, dt_arg); break;
+    case OUT_STAGE2: launch_xy_mode<T, OUT_STAGE2, ORDER>(c, qs, qn, out, dt_dev, dt_arg); break;
+    default: launch_xy_mode<T, OUT_STAGE3, ORDER>(c, qs, qn, out, dt_dev, dt_arg); break;
     }
 }
 
@@ -517,10 +532,13 @@ int launch_sweep_xy(mfx_ctx* c, const double* qs, const double* qn, double* out,
         if (!pend.a || !pend.b) return fail(c, MFX_EHIP, "hipEventCreate failed");
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
+    const bool o3 = weno_order(c->desc) == 3;
     if (c->desc.precision == MFX_FP32_MIXED)
-        launch_xy<float>(c, mode, qs, qn, out, dt_dev, dt_arg);
+        o3 ? launch_xy<float, 3>(c, mode, qs, qn, out, dt_dev, dt_arg)
+           : launch_xy<float, 5>(c, mode, qs, qn, out, dt_dev, dt_arg);
     else
-        launch_xy<double>(c, mode, qs, qn, out, dt_dev, dt_arg);
+        o3 ? launch_xy<double, 3>(c, mode, qs, qn, out, dt_dev, dt_arg)
+           : launch_xy<double, 5>(c, mode, qs, qn, out, dt_dev, dt_arg);
     int rc = launch_check(c, "fused x-y sweep");
     if (rc) return rc;
     if (c->profiling) {

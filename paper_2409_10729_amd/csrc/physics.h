@@ -168,6 +168,51 @@ __device__ __forceinline__ void weno5<float>(float a, float b, float c, float d,
     weno5_js_ratio(a, b, c, d, e, eps, left, right);
 }
 
+// WENO3 with Jiang-Shu weights (the third-order reconstruction named
+// beside WENO5 in Sec. II-B) for cell c from w_{c-1..c+1} = a, b, c:
+// candidates on {c-1, c} and {c, c+1}; right edge (c+1/2) with linear
+// weights 1/3, 2/3 and candidates (3b - a)/2, (b + c)/2; left edge (c-1/2)
+// with 2/3, 1/3 and (a + b)/2, (3b - c)/2; indicators (b - a)^2, (c - b)^2.
+// float64: weights scaled by the product of the two (eps + beta)^2, one
+// division per edge.
+__device__ __forceinline__ void weno3_js(double a, double b, double c, double eps, double& left, double& right)
+{
+    const double d0 = b - a, d1 = c - b;
+    double s0 = eps + d0 * d0, s1 = eps + d1 * d1;
+    s0 *= s0;
+    s1 *= s1;
+    // right: (s1 (3b - a) + 2 s0 (b + c)) / (2 (s1 + 2 s0))
+    right = qdiv(s1 * (3.0 * b - a) + 2.0 * s0 * (b + c), 2.0 * (s1 + 2.0 * s0));
+    // left: (2 s1 (a + b) + s0 (3b - c)) / (2 (2 s1 + s0))
+    left = qdiv(2.0 * s1 * (a + b) + s0 * (3.0 * b - c), 2.0 * (2.0 * s1 + s0));
+}
+
+// float32: the ratio form, alpha_k ~ d_k ((eps + beta_min) / (eps + beta_k))^2.
+__device__ __forceinline__ void weno3_ratio(float a, float b, float c, float eps, float& left, float& right)
+{
+    const float d0 = b - a, d1 = c - b;
+    const float s0 = eps + d0 * d0, s1 = eps + d1 * d1;
+    const float m = fminf(s0, s1);
+    float x0 = qdiv(m, s0), x1 = qdiv(m, s1);
+    x0 *= x0;
+    x1 *= x1;
+    right = qdiv(x0 * (3.f * b - a) + 2.f * x1 * (b + c), 2.f * (x0 + 2.f * x1));
+    left = qdiv(2.f * x0 * (a + b) + x1 * (3.f * b - c), 2.f * (2.f * x0 + x1));
+}
+
+template <typename T>
+__device__ __forceinline__ void weno3(T a, T b, T c, T eps, T& left, T& right);
+template <>
+__device__ __forceinline__ void weno3<double>(double a, double b, double c, double eps, double& left, double& right)
+{
+    weno3_js(a, b, c, eps, left, right);
+}
+template <>
+__device__ __forceinline__ void weno3<float>(float a, float b, float c, float eps, float& left, float& right)
+{
+    weno3_ratio(a, b, c, eps, left, right);
+}
+
 // FP64 HLLC in the plain definition's operation order, without contraction
 // and with IEEE division and square root.  The star-state flux
 // F = F_K + s (U*_K - U_K) subtracts energies of size Pi (7.8e8 in water)

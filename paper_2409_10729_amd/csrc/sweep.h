@@ -299,15 +299,19 @@ __device__ __forceinline__ void settle(T& a, T& b)
 }
 
 // Reconstruction of one cell's two edge states (all seven primitives) from
-// its 5-cell window.
-template <typename T>
+// its 5-cell window: WENO5, or WENO3 on the middle three cells (ORDER).
+template <typename T, int ORDER = 5>
 struct ReconJS {
+    static_assert(ORDER == 5 || ORDER == 3, "WENO order 5 or 3");
     template <class Win>
     __device__ __forceinline__ void cell_win(const Win& W, T eps, T lft[NV], T rgt[NV])
     {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            weno5<T>(W(0, v), W(1, v), W(2, v), W(3, v), W(4, v), eps, lft[v], rgt[v]);
+            if constexpr (ORDER == 5)
+                weno5<T>(W(0, v), W(1, v), W(2, v), W(3, v), W(4, v), eps, lft[v], rgt[v]);
+            else
+                weno3<T>(W(1, v), W(2, v), W(3, v), eps, lft[v], rgt[v]);
             settle(lft[v], rgt[v]);
         }
     }
@@ -440,17 +444,18 @@ struct ReconLearned {
 
 constexpr int LEARNED_MAX_WAVES = 8;  // largest block of a learned sweep: 512 threads
 
-template <typename T, bool LEARNED>
+template <typename T, bool LEARNED, int ORDER = 5>
 struct ReconOf {
-    using type = ReconJS<T>;
+    using type = ReconJS<T, ORDER>;
 };
 template <>
-struct ReconOf<float, true> {
+struct ReconOf<float, true, 5> {
     using type = ReconLearned;
 };
 
-template <typename T, bool LEARNED>
-__device__ __forceinline__ typename ReconOf<T, LEARNED>::type make_recon(const Grid& g, const MlpLane* mlp, bool valid)
+template <typename T, bool LEARNED, int ORDER = 5>
+__device__ __forceinline__ typename ReconOf<T, LEARNED, ORDER>::type make_recon(const Grid& g, const MlpLane* mlp,
+                                                                               bool valid)
 {
     if constexpr (LEARNED) {
         // one 4 KB slot per wave; blocks have at most LEARNED_MAX_WAVES waves
@@ -462,7 +467,7 @@ __device__ __forceinline__ typename ReconOf<T, LEARNED>::type make_recon(const G
         (void)g;
         (void)mlp;
         (void)valid;
-        return ReconJS<T>{};
+        return ReconJS<T, ORDER>{};
     }
 }
 
@@ -572,7 +577,7 @@ struct GlobalSrc {
 // CFL (stage 3 only): the block's CFL maximum of the new state goes to
 // partial[block] and invalid states set bits in *status, as in the
 // standalone reduction.
-template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED, bool CFL = false>
+template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED, bool CFL = false, int ORDER = 5>
 __global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
                                                    T* __restrict__ racc, double* out, int seg,
                                                    const double* __restrict__ dt_dev, double dt_arg,
@@ -594,7 +599,7 @@ __global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restr
     GlobalSrc src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
     GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CFL> sink{
         OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid, CflAcc{0.0, 0u}};
-    auto recon = make_recon<T, LEARNED>(g, mlp, valid);
+    auto recon = make_recon<T, LEARNED, ORDER>(g, mlp, valid);
     __shared__ T win[5][NV][BLOCK];
     LdsWindow<T, BLOCK> W{&win[0][0][threadIdx.x], 0};
     march<DIR, T>(g, src, sink, recon, c0, c1, W);
@@ -683,7 +688,7 @@ struct LdsSink {
     }
 };
 
-template <typename T, bool FIRST, int MODE, bool LEARNED>
+template <typename T, bool FIRST, int MODE, bool LEARNED, int ORDER = 5>
 __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* __restrict__ qs, const double* qn,
                                                           T* __restrict__ racc, double* out, int seg,
                                                           const double* __restrict__ dt_dev, double dt_arg,
@@ -700,7 +705,7 @@ __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* 
     LdsSrc src{ibuf, qs, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
     LdsSink<T, FIRST, MODE> sink{obuf, OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx,
                                  c0, c1};
-    auto recon = make_recon<T, LEARNED>(g, mlp, row0 + threadIdx.x < nrows);
+    auto recon = make_recon<T, LEARNED, ORDER>(g, mlp, row0 + threadIdx.x < nrows);
     __shared__ T win[5][NV][XROWS];
     LdsWindow<T, XROWS> W{&win[0][0][threadIdx.x], 0};
     march<0, T>(g, src, sink, recon, c0, c1, W);

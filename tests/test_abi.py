@@ -47,7 +47,8 @@ def test_workspace_bytes_scales_with_grid():
 
 
 @pytest.mark.parametrize("field,value", [
-    ("cfl", 0.0), ("cfl", 1.5), ("weno_eps", 0.0), ("precision", 7), ("weights", 9),
+    ("cfl", 0.0), ("cfl", 1.5), ("weno_eps", 0.0), ("precision", 7), ("weights", 9), ("weno_order", 4),
+    ("weno_order", 1),
 ])
 def test_bad_scalars_rejected(field, value):
     L = _native.lib()
@@ -102,3 +103,12 @@ def test_null_context_calls_rejected():
     assert L.mfx_rhs(None, None) == _native.MFX_EINVAL
     assert L.mfx_rk3_step(None, 0.0, None) == _native.MFX_EINVAL
     assert L.mfx_stats(None, None, None, None, None) == _native.MFX_EINVAL
+
+
+def test_weno_order_options():
+    """Orders 5 and 3 are accepted (0 reads as 5); the learned weights need 5."""
+    L = _native.lib()
+    for order in (0, 3, 5):
+        assert L.mfx_workspace_bytes(ctypes.byref(_desc(weno_order=order))) > 0
+    d = _desc(weno_order=3, weights=_native.MFX_WENO5_LEARNED, precision=_native.MFX_FP32_MIXED)
+    assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0
