@@ -1,13 +1,16 @@
 #!/usr/bin/env python3
 """Benchmark: SSP-RK3 steps of the five-equation finite-volume solver on one
-MI355X, 256^3 Mach-2 shock-droplet workload, FP64 path.
+MI355X, 256^3 Mach-2 shock-droplet workload, FP64 path (other synthetic
+workloads with --workload).
 
-One step = three right-hand-side evaluations (x, y, z sweeps each) plus the
-stage updates and the CFL reduction, on a state already resident in HBM.
-Prints one JSON line:
+One step = three right-hand-side evaluations (each a fused x-y pass and a z
+pass) plus the stage updates and the CFL reduction, on a state already
+resident in HBM.  Prints one JSON line:
   value        grind time, ns per cell per RK stage (lower is better)
-  roofline     the dominant kernel's algorithmic bytes per launch over its
-               mean HIP-event duration, against 8 TB/s HBM
+  roofline     the dominant kernel against the roof its arithmetic intensity
+               selects: algorithmic float64 flops per launch over its mean
+               HIP-event duration against 78.6 TFLOP/s, or algorithmic bytes
+               against 8 TB/s HBM
   cpu_baseline the FP64 CPU oracle on a bounded sample of the same workload
 """
 from __future__ import annotations
@@ -26,6 +29,16 @@ METRIC = "grind time (ns/cell/RK-stage) + %HBM peak; FP32/learned vs FP64 at fix
 HBM_PEAK_GBS = 8000.0
 STATE_BYTES = 56  # 7 float64 per cell
 KERNEL_NAMES = {0: "sweep_x", 1: "sweep_y", 2: "sweep_z", 3: "sweep_xy"}
+# synthetic workloads: description, default cells per direction
+WORKLOADS = {
+    "shock_droplet": ("Mach-2 air shock on a water droplet (R=0.15), 1% density noise, x transmissive / y,z "
+                      "periodic", 256),
+    "bubble_cloud": ("Mach-1.5 water shock on 4-16 seeded air bubbles (R 0.05-0.15), x transmissive / y,z "
+                     "periodic", 192),
+    "droplet_cloud": ("Mach-2 air shock on 32 seeded water droplets (R log-uniform 0.02-0.1), 1% density noise, "
+                      "x transmissive / y,z periodic", 384),
+    "advected_bubble": ("air bubble advected through water at u=(1,0.5,0.25), periodic", 128),
+}
 
 
 def sweep_bytes_per_cell(first: int, mode: int, rhs_bytes: int = STATE_BYTES) -> int:
@@ -135,7 +148,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=256, help="cells per direction")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="shock_droplet",
+                    help="synthetic 3D problem (the headline line is shock_droplet at 256^3)")
+    ap.add_argument("--n", type=int, default=None, help="cells per direction (default: the workload's size)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
@@ -147,6 +162,8 @@ def main():
                     help="run only a plain device-to-device copy of 7 * n^3 float64 (known bytes), five times, "
                          "to scale rocprofv3 FETCH_SIZE / WRITE_SIZE")
     args = ap.parse_args()
+    if args.n is None:
+        args.n = WORKLOADS[args.workload][1]
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
@@ -171,8 +188,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_each_way": a.numel() * 8, "launches": 5}), flush=True)
         return
-    print(f"[bench] generating shock_droplet n={args.n} seed={args.seed}", file=sys.stderr, flush=True)
-    P = wl.shock_droplet(n=args.n, seed=args.seed)
+    print(f"[bench] generating {args.workload} n={args.n} seed={args.seed}", file=sys.stderr, flush=True)
+    P = getattr(wl, args.workload)(n=args.n, seed=args.seed)
     N = args.n ** 3
     w_dev = torch.from_numpy(P["w"]).cuda()
 
@@ -352,8 +369,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"shock_droplet {args.n}^3: Mach-2 air shock on a water droplet (R=0.15), 1% density "
-                        f"noise, x transmissive / y,z periodic, CFL 0.4, WENO5-JS + HLLC + SSP-RK3, FP64",
+            "workload": f"{args.workload} {args.n}^3: {WORKLOADS[args.workload][0]}, CFL 0.4, WENO5-JS + HLLC + "
+                        f"SSP-RK3, FP64",
             "cells": N,
             "seed": args.seed,
             "precision": "fp64",

@@ -26,7 +26,7 @@ using namespace mfx;
 
 namespace {
 
-constexpr int SWEEP_BLOCK = 256;
+constexpr int SWEEP_BLOCK = 64;  // y/z sweeps: one wave per block (no waste for nx % 256 != 0)
 constexpr int UTIL_BLOCK = 256;
 constexpr int CFL_BLOCKS = 1024;  // grid of the standalone CFL reduction
 constexpr size_t ALIGN = 256;

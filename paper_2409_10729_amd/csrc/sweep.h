@@ -578,13 +578,13 @@ struct GlobalSrc {
 // partial[block] and invalid states set bits in *status, as in the
 // standalone reduction.
 template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED, bool CFL = false, int ORDER = 5>
-__global__ void __launch_bounds__(256, 2) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
+__global__ void __launch_bounds__(64) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
                                                    T* __restrict__ racc, double* out, int seg,
                                                    const double* __restrict__ dt_dev, double dt_arg,
                                                    const MlpLane* __restrict__ mlp, unsigned long long* fb,
                                                    double* __restrict__ partial, unsigned* __restrict__ status)
 {
-    constexpr int BLOCK = 256;
+    constexpr int BLOCK = 64;  // one wave: any nx that is a multiple of 64 fills every lane
     static_assert(DIR == 1 || DIR == 2, "y or z sweep");
     constexpr int SA = (DIR == 2) ? 1 : 2;  // slow transverse axis
     const int n = g.n[DIR];
