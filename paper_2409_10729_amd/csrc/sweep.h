@@ -1,24 +1,26 @@
-// One fused pass per direction of the finite-volume right-hand side
-// (arXiv 2409.10729, Sec. II-B, eq. rhs): ghost-cell index map, conserved ->
-// primitive, WENO5 face states, HLLC flux + face velocity, flux difference
-// and alpha1 div(u) source, and -- in the last active direction of a stage --
-// the SSP-RK3 combine.  (The CFL wave-speed maximum of the new state is a
-// separate streaming pass: inside the marching loop its running maximum
-// spilled and every reload drained the loop's prefetched loads.)
+// Fused passes of the finite-volume right-hand side (arXiv 2409.10729,
+// Sec. II-B, eq. rhs): ghost-cell index map, conserved -> primitive, WENO
+// face states (fifth order, or third), HLLC flux + face velocity, flux
+// difference and alpha1 div(u) source, and -- in the last active direction
+// of a stage -- the SSP-RK3 combine; the stage-3 pass also reduces the CFL
+// wave speed of the new state.
 //
 // T is the arithmetic of reconstruction, Riemann solve and flux difference
 // (double, or float for the mixed-precision form).  The conserved ->
 // primitive conversion, the stage update and the CFL reduction are always
 // float64; the partial RHS buffer holds T.
 //
-// Work decomposition: one thread marches along the sweep direction over a
-// segment of `seg` cells of one pencil, keeping a 5-cell window of
-// primitives in registers; each cell is reconstructed once (both edges from
-// one set of smoothness indicators), each face solved once, each output
-// written once.  Lanes of a wave are consecutive pencils: consecutive x for
-// the y and z sweeps (coalesced 512-byte rows), consecutive y for the x sweep.
+// Work decomposition of a marching pass: one thread marches along the sweep
+// direction over a segment of `seg` cells of one pencil, keeping a 5-cell
+// window of primitives (a ring in the lane's own LDS column, or in
+// registers); each cell is reconstructed once (both edges from one set of
+// smoothness indicators), each face solved once, each output written once.
+// Lanes of a wave are consecutive pencils: consecutive x for the y and z
+// sweeps (coalesced 512-byte rows), consecutive y for the marching x sweep.
 // Every lane of a wave sits at the same position along the sweep, so the
-// boundary branches are wave-uniform.
+// boundary branches are wave-uniform.  The x direction normally goes
+// through whole rows in LDS (xrow.h), inside the y march where both are
+// active.
 #pragma once
 
 #include "learned.h"
