@@ -26,7 +26,6 @@ using namespace mfx;
 
 namespace {
 
-constexpr int SWEEP_BLOCK = 64;  // y/z sweeps: one wave per block (no waste for nx % 256 != 0)
 constexpr int UTIL_BLOCK = 256;
 constexpr int CFL_BLOCKS = 1024;  // grid of the standalone CFL reduction
 constexpr size_t ALIGN = 256;
@@ -77,7 +76,7 @@ bool use_xrows(const int n[3], int mode_override, size_t elem)
     return n[0] <= XROW_MAX && xrow_lds_bytes(n[0], elem) <= 64 * 1024;
 }
 
-SweepGeom sweep_geom(const int n[3], int d, int seg_override, int xmode_override, size_t elem)
+SweepGeom sweep_geom(const int n[3], int d, int seg_override, int xmode_override, size_t elem, bool learned)
 {
     int seg = seg_override > 0 ? seg_override : 64;
     SweepGeom g;
@@ -106,8 +105,9 @@ SweepGeom sweep_geom(const int n[3], int d, int seg_override, int xmode_override
         // keep enough waves in flight: shrink segments while the pencil count is small
         while (seg > 16 && pencils * ((n[d] + seg - 1) / seg) < 256LL * 64 * 16) seg /= 2;
         seg = std::min(seg, n[d]);
-        g.grid = dim3((n[0] + SWEEP_BLOCK - 1) / SWEEP_BLOCK, n[sa], (n[d] + seg - 1) / seg);
-        g.block = SWEEP_BLOCK;
+        const int block = learned ? yz_block<true>() : yz_block<false>();
+        g.grid = dim3((n[0] + block - 1) / block, n[sa], (n[d] + seg - 1) / seg);
+        g.block = block;
         g.seg = seg;
     }
     return g;
@@ -123,7 +123,7 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     // blocks of a y/z sweep that reduces the new state of a step
     long long np = CFL_BLOCKS;
     for (int dd = 1; dd < 3; ++dd) {
-        const SweepGeom sg = sweep_geom(d->n, dd, seg_override, xmode_override, elem);
+        const SweepGeom sg = sweep_geom(d->n, dd, seg_override, xmode_override, elem, false);
         np = std::max<long long>(np, (long long)sg.grid.x * sg.grid.y * sg.grid.z);
     }
     const long long nrows = (long long)d->n[1] * d->n[2];
@@ -415,12 +415,12 @@ void launch_one(const LaunchArgs& a)
     } else {
         if constexpr (MODE == OUT_STAGE3 && !L) {
             if (a.cfl) {
-                sweep_yz<DIR, T, FIRST, MODE, L, true, ORDER><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(
+                sweep_yz<DIR, T, FIRST, MODE, L, true, ORDER><<<sg.grid, sg.block, 0, a.st>>>(
                     *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, a.partial, a.status);
                 return;
             }
         }
-        sweep_yz<DIR, T, FIRST, MODE, L, false, ORDER><<<sg.grid, SWEEP_BLOCK, 0, a.st>>>(
+        sweep_yz<DIR, T, FIRST, MODE, L, false, ORDER><<<sg.grid, sg.block, 0, a.st>>>(
             *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, nullptr, nullptr);
     }
 }
@@ -452,7 +452,8 @@ void launch_dispatch(int d, bool first, int mode, const LaunchArgs& a)
 int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* out, int first, int mode,
                  const double* dt_dev, double dt_arg, bool cfl = false)
 {
-    SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem);
+    SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem,
+                              c->desc.weights != MFX_WENO5_JS);
     mfx_ctx::Pending pend{(d * 2 + (first ? 1 : 0)) * 5 + mode, nullptr, nullptr};
     if (c->profiling) {
         pend.a = take_event(c);
@@ -557,7 +558,7 @@ long long cfl_blocks_in_last_pass(const mfx_ctx* c)
     const int d = c->dirs[c->ndirs - 1];
     if (d == 0 || !c->g.active[d]) return 0;
     if (fused_xy(c) && c->ndirs == 2) return 0;  // the fused x-y pass is the last
-    const SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem);
+    const SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem, false);
     return (long long)sg.grid.x * sg.grid.y * sg.grid.z;
 }
 

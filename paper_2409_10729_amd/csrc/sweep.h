@@ -198,7 +198,9 @@ __device__ __forceinline__ void prim_of(const Mix<double>& mix, const double q[N
 // of the cell the march puts next at the top of the march step, so the
 // loads are in flight during its reconstruction and Riemann solve (lanes
 // past the grid read the clamped column: in bounds, never stored).
-template <typename T, bool FIRST, int MODE, bool KEEPQ = false, bool CFL = false>
+// PREFETCH off (the learned passes): the loads stay where the output needs
+// them, so they do not hold registers across the network evaluations.
+template <typename T, bool FIRST, int MODE, bool KEEPQ = false, bool CFL = false, bool PREFETCH = true>
 struct GlobalSink {
     static constexpr bool keeps_q = KEEPQ;
     static constexpr bool NEEDQN = MODE == OUT_STAGE2 || MODE == OUT_STAGE3;
@@ -209,6 +211,10 @@ struct GlobalSink {
     T rin[FIRST ? 1 : NV];
     double qnin[NEEDQN ? NV : 1];
     __device__ __forceinline__ void prefetch(const Grid& g, int c)
+    {
+        if constexpr (PREFETCH) load_out(g, c);
+    }
+    __device__ __forceinline__ void load_out(const Grid& g, int c)
     {
         const long long cell = base + (long long)c * sd;
         if constexpr (!FIRST) {
@@ -224,6 +230,7 @@ struct GlobalSink {
     __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src, const Win&, const double* qc)
     {
         if (valid) {
+            if constexpr (!PREFETCH) load_out(g, c);
             T r[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) r[v] = FIRST ? fd[v] : rin[v] + fd[v];
@@ -248,6 +255,7 @@ struct ArrayWindow {
 // one variable's reconstruction at a time and needs no shifting.
 template <typename T, int LANES>
 struct LdsWindow {
+    static constexpr bool in_registers = false;
     T* col;
     int s0;
     __device__ __forceinline__ int slot(int k) const
@@ -268,6 +276,7 @@ struct LdsWindow {
 // holds other data.
 template <typename T>
 struct RegWindow {
+    static constexpr bool in_registers = true;
     T w[5][NV];
     __device__ __forceinline__ T operator()(int k, int v) const { return w[k][v]; }
     __device__ __forceinline__ void store(int k, const T x[NV])
@@ -455,13 +464,16 @@ struct ReconOf<float, true, 5> {
     using type = ReconLearned;
 };
 
-template <typename T, bool LEARNED, int ORDER = 5>
+// WAVES: the most waves a block of the calling kernel has (the learned
+// form's LDS slots are static, so the count sizes the kernel's LDS).
+template <typename T, bool LEARNED, int ORDER = 5, int WAVES = LEARNED_MAX_WAVES>
 __device__ __forceinline__ typename ReconOf<T, LEARNED, ORDER>::type make_recon(const Grid& g, const MlpLane* mlp,
                                                                                bool valid)
 {
     if constexpr (LEARNED) {
-        // one 4 KB slot per wave; blocks have at most LEARNED_MAX_WAVES waves
-        __shared__ LearnedLds slots[LEARNED_MAX_WAVES];
+        static_assert(WAVES >= 1 && WAVES <= LEARNED_MAX_WAVES, "waves per block");
+        // one 4 KB slot per wave of the block
+        __shared__ LearnedLds slots[WAVES];
         return ReconLearned{mlp[threadIdx.x & 63], &slots[threadIdx.x >> 6],
                             Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u,
                             g.edge_weights != 0};
@@ -488,11 +500,12 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
     const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
 
     // window: W(k) = primitives of cell c-2+k while reconstructing cell c
-    // qh (when the sink keeps the stage state): conserved cells c-1 .. c+2
+    // qh (when the sink keeps the stage state): conserved cells c-1 .. c+2.
+    // Register-held windows and qh need constant indices (unrolled fill);
+    // an LDS ring without qh is filled by a rolled loop (smaller code).
     constexpr bool KQ = Sink::keeps_q;
     double qh[KQ ? 4 : 1][NV];
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
+    auto fill = [&](int k) {
         double qc[NV];
         src.load(c0 - 3 + k, qc);
         if constexpr (KQ) {
@@ -504,6 +517,13 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
         T w[NV];
         prim_of<T>(mixd, qc, w);
         W.store(k, w);
+    };
+    if constexpr (KQ || Win::in_registers) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) fill(k);
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < 5; ++k) fill(k);
     }
 
     T rprev[NV], Fprev[NV], ufprev = T(0);
@@ -579,14 +599,25 @@ struct GlobalSrc {
 // CFL (stage 3 only): the block's CFL maximum of the new state goes to
 // partial[block] and invalid states set bits in *status, as in the
 // standalone reduction.
+// Block size: the Jiang-Shu passes run one wave per block (waves do not
+// cooperate, so every lane is used for any nx that is a multiple of 64);
+// the learned passes run four (measured faster for them).
+template <bool LEARNED>
+constexpr int yz_block()
+{
+    return LEARNED ? 256 : 64;
+}
+
+// (The learned passes keep the occupancy hint of two waves per SIMD: without
+// it the compiler schedules them for a higher occupancy they cannot reach.)
 template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED, bool CFL = false, int ORDER = 5>
-__global__ void __launch_bounds__(64) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
+__global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 2 : 1) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
                                                    T* __restrict__ racc, double* out, int seg,
                                                    const double* __restrict__ dt_dev, double dt_arg,
                                                    const MlpLane* __restrict__ mlp, unsigned long long* fb,
                                                    double* __restrict__ partial, unsigned* __restrict__ status)
 {
-    constexpr int BLOCK = 64;  // one wave: any nx that is a multiple of 64 fills every lane
+    constexpr int BLOCK = yz_block<LEARNED>();
     static_assert(DIR == 1 || DIR == 2, "y or z sweep");
     constexpr int SA = (DIR == 2) ? 1 : 2;  // slow transverse axis
     const int n = g.n[DIR];
@@ -599,9 +630,9 @@ __global__ void __launch_bounds__(64) sweep_yz(Grid g, const double* __restrict_
     const int c0 = blockIdx.z * seg;
     const int c1 = min(c0 + seg, n);
     GlobalSrc src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
-    GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CFL> sink{
+    GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CFL, !LEARNED> sink{
         OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid, CflAcc{0.0, 0u}};
-    auto recon = make_recon<T, LEARNED, ORDER>(g, mlp, valid);
+    auto recon = make_recon<T, LEARNED, ORDER, BLOCK / 64>(g, mlp, valid);
     __shared__ T win[5][NV][BLOCK];
     LdsWindow<T, BLOCK> W{&win[0][0][threadIdx.x], 0};
     march<DIR, T>(g, src, sink, recon, c0, c1, W);
@@ -707,7 +738,7 @@ __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* 
     LdsSrc src{ibuf, qs, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
     LdsSink<T, FIRST, MODE> sink{obuf, OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx,
                                  c0, c1};
-    auto recon = make_recon<T, LEARNED, ORDER>(g, mlp, row0 + threadIdx.x < nrows);
+    auto recon = make_recon<T, LEARNED, ORDER, XROWS / 64>(g, mlp, row0 + threadIdx.x < nrows);
     __shared__ T win[5][NV][XROWS];
     LdsWindow<T, XROWS> W{&win[0][0][threadIdx.x], 0};
     march<0, T>(g, src, sink, recon, c0, c1, W);
