@@ -99,7 +99,15 @@ size_t mfx_workspace_bytes(const mfx_grid_desc* desc);
  * context to the caller's workspace (device pointer, >= mfx_workspace_bytes)
  * and HIP stream (hipStream_t passed as void*, NULL = default stream).
  * On success *out receives the context.  The state is undefined until
- * mfx_set_state or mfx_set_primitive. */
+ * mfx_set_state or mfx_set_primitive.
+ * Kernel-choice switches read from the environment here (and by
+ * mfx_workspace_bytes), for testing the equivalent paths against each
+ * other; results agree to rounding either way:
+ *   MFX_FUSE_XY=0    separate x and y passes instead of the fused x-y pass;
+ *   MFX_FUSE_CFL=0   the CFL reduction as its own pass after each step
+ *                    instead of inside the step's last y/z pass;
+ *   MFX_XSWEEP=march the marching x pass instead of whole rows;
+ *   MFX_SWEEP_SEG=n  segment length of the marching passes (default 64). */
 int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void* hip_stream,
                   mfx_ctx** out);
 
