@@ -270,6 +270,12 @@ struct LdsWindow {
         for (int v = 0; v < NV; ++v) col[(slot(k) * NV + v) * LANES] = w[v];
     }
     __device__ __forceinline__ void advance() { s0 = s0 == 4 ? 0 : s0 + 1; }
+    // the new cell takes the slot of the oldest, which becomes the newest
+    __device__ __forceinline__ void push(const T w[NV])
+    {
+        store(0, w);
+        advance();
+    }
 };
 
 // The same ring in registers (rotated by moves), for kernels whose LDS
@@ -284,16 +290,16 @@ struct RegWindow {
 #pragma unroll
         for (int v = 0; v < NV; ++v) w[k][v] = x[v];
     }
-    __device__ __forceinline__ void advance()
+    // shift out the oldest cell, the new one becomes the newest
+    __device__ __forceinline__ void push(const T x[NV])
     {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            const T t = w[0][v];
             w[0][v] = w[1][v];
             w[1][v] = w[2][v];
             w[2][v] = w[3][v];
             w[3][v] = w[4][v];
-            w[4][v] = t;
+            w[4][v] = x[v];
         }
     }
 };
@@ -558,10 +564,10 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
         for (int v = 0; v < NV; ++v) rprev[v] = rgt[v];
 
         if (c < c1) {
-            // cell c+3 takes the slot of cell c-2, which is no longer needed
+            // cell c+3 enters, cell c-2 (no longer needed) leaves
             T w[NV];
             prim_of<T>(mixd, qnext, w);
-            W.store(0, w);
+            W.push(w);
             if constexpr (KQ) {
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
@@ -572,7 +578,6 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
                 }
             }
         }
-        W.advance();
     }
 }
 
