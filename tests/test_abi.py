@@ -112,3 +112,17 @@ def test_weno_order_options():
         assert L.mfx_workspace_bytes(ctypes.byref(_desc(weno_order=order))) > 0
     d = _desc(weno_order=3, weights=_native.MFX_WENO5_LEARNED, precision=_native.MFX_FP32_MIXED)
     assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0
+
+
+def test_size_limits():
+    """Extents up to 65535 per direction and up to 2^31 cells are accepted
+    (workspace sized with 64-bit arithmetic); beyond either, rejected."""
+    L = _native.lib()
+    ok = _native.make_desc(wl.spec((65535, 1, 1), ((1, 1), (0, 0), (0, 0))))
+    assert L.mfx_workspace_bytes(ctypes.byref(ok)) > 4 * 7 * 8 * 65535
+    big = _native.make_desc(wl.spec((2048, 1024, 1024), ((1, 1), (0, 0), (0, 0))))  # exactly 2^31 cells
+    b = L.mfx_workspace_bytes(ctypes.byref(big))
+    assert b >= 4 * 7 * 8 * (1 << 31)
+    for n in ((65536, 1, 1), (2048, 1024, 1025)):
+        d = _native.make_desc(wl.spec(n, ((1, 1), (0, 0), (0, 0))))
+        assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0

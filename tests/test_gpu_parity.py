@@ -184,6 +184,20 @@ def test_weno3_matches_oracle(n, bc, seed):
     assert np.all(err32 <= 1e-5), err32
 
 
+def test_longest_allowed_row_matches_oracle():
+    """The largest extent one direction may have (65535 cells, marching x
+    sweep in 64-cell segments): three steps against the oracle."""
+    P = wl.random_smooth(n=(65535, 1, 1), seed=30, bc=((1, 1), (0, 0), (0, 0)))
+    g, q0 = _q0(P)
+    s = gpu_solver(P["spec"], q0=q0)
+    dts = [s.rk3_step(sync=True) for _ in range(3)]
+    q_ref, dts_ref = oracle.run(g, q0, 3)
+    assert np.abs(np.array(dts) / dts_ref - 1).max() <= 1e-12
+    err = rel_linf(s.get_state().cpu().numpy(), q_ref)
+    _report("65535 x 1 x 1, 3 steps", err)
+    assert np.all(err <= TOL), err
+
+
 def test_segment_length_does_not_change_results(monkeypatch):
     P = wl.shock_droplet(n=(40, 36, 44), seed=4)
     g, q0 = _q0(P)
