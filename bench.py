@@ -174,7 +174,7 @@ def main():
     import torch
 
     from paper_2409_10729_amd import (MFX_FP32_MIXED, MFX_FP64, MFX_WENO5_JS, MFX_WENO5_LEARNED,
-                                      MFX_WENO5_LEARNED_EDGE, Solver)
+                                      MFX_WENO5_LEARNED_EDGE, MFX_WENO5_Z, Solver)
     from paper_2409_10729_amd import learned
     from paper_2409_10729_amd import workloads as wl
 
@@ -201,7 +201,7 @@ def main():
 
     def new_solver(precision, weights=MFX_WENO5_JS, order=5):
         s = Solver(dict(P["spec"], weno_order=order), precision=precision, weights=weights)
-        if weights != MFX_WENO5_JS:
+        if weights in (MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE):
             s.set_mlp(nets[weights][0])
         s.set_primitive(w_dev)
         return s
@@ -319,10 +319,11 @@ def main():
         s64.destroy()
         del s64
         dt_fixed = dts[0] if dts else 1e-9
-        # (name, precision, weights, WENO order); fp64_weno3 is the
-        # third-order reconstruction, a different scheme: its L1 distance to
-        # the fifth-order run is its accuracy difference
-        variants = [("fp32_mixed", MFX_FP32_MIXED, MFX_WENO5_JS, 5), ("fp64_weno3", MFX_FP64, MFX_WENO5_JS, 3)]
+        # (name, precision, weights, WENO order); fp64_weno3 (third order) and
+        # fp64_wenoz (WENO-Z weights) are different schemes: their L1
+        # distance to the fifth-order Jiang-Shu run is a scheme difference
+        variants = [("fp32_mixed", MFX_FP32_MIXED, MFX_WENO5_JS, 5), ("fp64_weno3", MFX_FP64, MFX_WENO5_JS, 3),
+                    ("fp64_wenoz", MFX_FP64, MFX_WENO5_Z, 5)]
         if MFX_WENO5_LEARNED in nets:
             variants.append(("learned", MFX_FP32_MIXED, MFX_WENO5_LEARNED, 5))
         if MFX_WENO5_LEARNED_EDGE in nets:
@@ -345,7 +346,7 @@ def main():
                 "density_l1_rel_vs_fp64": rho_l1,
                 "kernels": kf,
             }
-            if weights != MFX_WENO5_JS:
+            if weights in nets:
                 edges = 2 * N * sum(1 for k in P["spec"]["n"] if k > 1) * 3 * len(dts)
                 forms[name]["fallback_edges"] = fb
                 forms[name]["fallback_fraction"] = float(f"{fb / max(edges, 1):.3e}")

@@ -69,8 +69,11 @@ enum { MFX_FP64 = 0, MFX_FP32_MIXED = 1 };
  * network evaluated once per edge for all seven variables, on the
  * componentwise maximum of the variables' features and correcting the
  * componentwise minimum of their Jiang-Shu weights (renormalised); same
- * fallback.  Both learned modes run in the MFX_FP32_MIXED form. */
-enum { MFX_WENO5_JS = 0, MFX_WENO5_LEARNED = 1, MFX_WENO5_LEARNED_EDGE = 2 };
+ * fallback.  Both learned modes run in the MFX_FP32_MIXED form.
+ * MFX_WENO5_Z: WENO-Z weights (Borges, Carmona, Costa & Don 2008, exponent
+ * 1), alpha_k = d_k (1 + |beta_0 - beta_2| / (beta_k + eps)), a comparison
+ * form for the learned weights; any precision form. */
+enum { MFX_WENO5_JS = 0, MFX_WENO5_LEARNED = 1, MFX_WENO5_LEARNED_EDGE = 2, MFX_WENO5_Z = 3 };
 
 typedef struct {
     int32_t n[3];      /* interior cells (nx, ny, nz), each >= 1; n == 1 makes a direction inactive */
@@ -82,10 +85,10 @@ typedef struct {
     double cfl;        /* CFL number for the automatic time step, in (0, 1] */
     double weno_eps;   /* WENO epsilon (absolute), > 0; 1e-6 is Jiang-Shu's value */
     int32_t precision; /* MFX_FP64 or MFX_FP32_MIXED */
-    int32_t weights;   /* MFX_WENO5_JS, MFX_WENO5_LEARNED or MFX_WENO5_LEARNED_EDGE */
+    int32_t weights;   /* MFX_WENO5_JS, MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE or MFX_WENO5_Z */
     int32_t weno_order; /* reconstruction order, 5 or 3 (Sec. II-B names both; 0 reads as 5):
                            WENO3 with Jiang-Shu weights on the middle three cells of each
-                           stencil; the learned weights need 5 (MFX_EINVAL otherwise) */
+                           stencil; the learned and WENO-Z weights need 5 (MFX_EINVAL otherwise) */
 } mfx_grid_desc;
 
 typedef struct mfx_ctx mfx_ctx;

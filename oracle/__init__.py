@@ -96,8 +96,9 @@ def _dp(a: np.ndarray):
 
 def make_grid(spec: dict, weno_z: bool = False) -> OrcGrid:
     """Grid from a problem description dict (keys n, dx, bc, gamma, pinf, eps,
-    cfl, and optionally weno_order: 5 or 3).  weno_z selects the WENO-Z
-    weights (a comparison form) instead of Jiang-Shu's."""
+    cfl, and optionally weno_order: 5 or 3, weno_z: bool).  weno_z (argument
+    or key) selects the WENO-Z weights (a comparison form) instead of
+    Jiang-Shu's."""
     g = OrcGrid()
     for d in range(3):
         g.n[d] = int(spec["n"][d])
@@ -108,7 +109,7 @@ def make_grid(spec: dict, weno_z: bool = False) -> OrcGrid:
     g.pinf[0], g.pinf[1] = map(float, spec["pinf"])
     g.eps = float(spec.get("eps", 1e-6))
     g.cfl = float(spec.get("cfl", 0.4))
-    g.weno_z = 1 if weno_z else 0
+    g.weno_z = 1 if (weno_z or spec.get("weno_z", False)) else 0
     g.weno_order = int(spec.get("weno_order", 5))
     if g.weno_order not in (3, 5):
         raise ValueError("weno_order must be 3 or 5")

@@ -12,6 +12,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/mfx.h"
@@ -151,7 +152,28 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     return L;
 }
 
-int weno_order(const mfx_grid_desc& d) { return d.weno_order == 3 ? 3 : 5; }
+bool learned_weights(const mfx_grid_desc& d)
+{
+    return d.weights == MFX_WENO5_LEARNED || d.weights == MFX_WENO5_LEARNED_EDGE;
+}
+
+// Reconstruction scheme of the non-learned passes.
+int scheme_of(const mfx_grid_desc& d)
+{
+    if (d.weights == MFX_WENO5_Z) return SCHEME_WENO5Z;
+    return d.weno_order == 3 ? SCHEME_WENO3 : SCHEME_WENO5;
+}
+
+// Calls f with std::integral_constant<int, scheme> (one instantiation per scheme).
+template <class F>
+void by_scheme(int scheme, F&& f)
+{
+    switch (scheme) {
+    case SCHEME_WENO3: f(std::integral_constant<int, SCHEME_WENO3>{}); break;
+    case SCHEME_WENO5Z: f(std::integral_constant<int, SCHEME_WENO5Z>{}); break;
+    default: f(std::integral_constant<int, SCHEME_WENO5>{}); break;
+    }
+}
 
 bool validate(const mfx_grid_desc* d, std::string& why)
 {
@@ -206,7 +228,8 @@ bool validate(const mfx_grid_desc* d, std::string& why)
         why = "unknown precision";
         return false;
     }
-    if (d->weights != MFX_WENO5_JS && d->weights != MFX_WENO5_LEARNED && d->weights != MFX_WENO5_LEARNED_EDGE) {
+    if (d->weights != MFX_WENO5_JS && d->weights != MFX_WENO5_LEARNED && d->weights != MFX_WENO5_LEARNED_EDGE &&
+        d->weights != MFX_WENO5_Z) {
         why = "unknown weights mode";
         return false;
     }
@@ -215,7 +238,7 @@ bool validate(const mfx_grid_desc* d, std::string& why)
         return false;
     }
     if (d->weno_order == 3 && d->weights != MFX_WENO5_JS) {
-        why = "learned weights need weno_order 5";
+        why = "the learned and WENO-Z weights need weno_order 5";
         return false;
     }
     return true;
@@ -395,7 +418,7 @@ struct LaunchArgs {
 
 // The x row sweep reads the boundary faces that boundary_faces_x leaves in
 // `bface` (launched just before it on the same stream).
-template <int DIR, typename T, bool FIRST, int MODE, bool L, int ORDER>
+template <int DIR, typename T, bool FIRST, int MODE, bool L, int SCHEME>
 void launch_one(const LaunchArgs& a)
 {
     const SweepGeom& sg = *a.sg;
@@ -404,56 +427,56 @@ void launch_one(const LaunchArgs& a)
         if (sg.xrows) {
             T* bf = static_cast<T*>(a.bface);
             const long long rows = (long long)a.g->n[1] * a.g->n[2];
-            boundary_faces_x<T, L, ORDER><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf, a.mlp,
+            boundary_faces_x<T, L, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf, a.mlp,
                                                                                              a.fb);
-            sweep_x_rows<T, FIRST, MODE, L, ORDER><<<sg.grid, sg.block, sg.lds, a.st>>>(
+            sweep_x_rows<T, FIRST, MODE, L, SCHEME><<<sg.grid, sg.block, sg.lds, a.st>>>(
                 *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.mlp, a.fb);
         } else {
-            sweep_x_march<T, FIRST, MODE, L, ORDER><<<sg.grid, XROWS, 0, a.st>>>(
+            sweep_x_march<T, FIRST, MODE, L, SCHEME><<<sg.grid, XROWS, 0, a.st>>>(
                 *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb);
         }
     } else {
         if constexpr (MODE == OUT_STAGE3 && !L) {
             if (a.cfl) {
-                sweep_yz<DIR, T, FIRST, MODE, L, true, ORDER><<<sg.grid, sg.block, 0, a.st>>>(
+                sweep_yz<DIR, T, FIRST, MODE, L, true, SCHEME><<<sg.grid, sg.block, 0, a.st>>>(
                     *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, a.partial, a.status);
                 return;
             }
         }
-        sweep_yz<DIR, T, FIRST, MODE, L, false, ORDER><<<sg.grid, sg.block, 0, a.st>>>(
+        sweep_yz<DIR, T, FIRST, MODE, L, false, SCHEME><<<sg.grid, sg.block, 0, a.st>>>(
             *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, nullptr, nullptr);
     }
 }
 
-template <int DIR, typename T, bool FIRST, bool L, int ORDER>
+template <int DIR, typename T, bool FIRST, bool L, int SCHEME>
 void launch_mode(int mode, const LaunchArgs& a)
 {
     switch (mode) {
-    case OUT_ACCUM: launch_one<DIR, T, FIRST, OUT_ACCUM, L, ORDER>(a); break;
-    case OUT_RHS: launch_one<DIR, T, FIRST, OUT_RHS, L, ORDER>(a); break;
-    case OUT_STAGE1: launch_one<DIR, T, FIRST, OUT_STAGE1, L, ORDER>(a); break;
-    case OUT_STAGE2: launch_one<DIR, T, FIRST, OUT_STAGE2, L, ORDER>(a); break;
-    default: launch_one<DIR, T, FIRST, OUT_STAGE3, L, ORDER>(a); break;
+    case OUT_ACCUM: launch_one<DIR, T, FIRST, OUT_ACCUM, L, SCHEME>(a); break;
+    case OUT_RHS: launch_one<DIR, T, FIRST, OUT_RHS, L, SCHEME>(a); break;
+    case OUT_STAGE1: launch_one<DIR, T, FIRST, OUT_STAGE1, L, SCHEME>(a); break;
+    case OUT_STAGE2: launch_one<DIR, T, FIRST, OUT_STAGE2, L, SCHEME>(a); break;
+    default: launch_one<DIR, T, FIRST, OUT_STAGE3, L, SCHEME>(a); break;
     }
 }
 
 // The x sweep, when active, is always the first direction of a pass.
-template <typename T, bool L, int ORDER = 5>
+template <typename T, bool L, int SCHEME = 5>
 void launch_dispatch(int d, bool first, int mode, const LaunchArgs& a)
 {
     if (d == 0)
-        launch_mode<0, T, true, L, ORDER>(mode, a);
+        launch_mode<0, T, true, L, SCHEME>(mode, a);
     else if (d == 1)
-        first ? launch_mode<1, T, true, L, ORDER>(mode, a) : launch_mode<1, T, false, L, ORDER>(mode, a);
+        first ? launch_mode<1, T, true, L, SCHEME>(mode, a) : launch_mode<1, T, false, L, SCHEME>(mode, a);
     else
-        first ? launch_mode<2, T, true, L, ORDER>(mode, a) : launch_mode<2, T, false, L, ORDER>(mode, a);
+        first ? launch_mode<2, T, true, L, SCHEME>(mode, a) : launch_mode<2, T, false, L, SCHEME>(mode, a);
 }
 
 int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* out, int first, int mode,
                  const double* dt_dev, double dt_arg, bool cfl = false)
 {
     SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem,
-                              c->desc.weights != MFX_WENO5_JS);
+                              learned_weights(c->desc));
     mfx_ctx::Pending pend{(d * 2 + (first ? 1 : 0)) * 5 + mode, nullptr, nullptr};
     if (c->profiling) {
         pend.a = take_event(c);
@@ -464,15 +487,12 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
     const LaunchArgs la{&sg,      c->stream,   &c->g,      qs,        qn,       c->r,
                         out,      dt_dev,      dt_arg,     c->bface,  c->mlp,   c->fallback,
                         c->partial, c->status, cfl};
-    const bool o3 = weno_order(c->desc) == 3;
-    if (c->desc.weights != MFX_WENO5_JS)
+    if (learned_weights(c->desc))
         launch_dispatch<float, true>(d, first != 0, mode, la);
     else if (c->desc.precision == MFX_FP32_MIXED)
-        o3 ? launch_dispatch<float, false, 3>(d, first != 0, mode, la)
-           : launch_dispatch<float, false, 5>(d, first != 0, mode, la);
+        by_scheme(scheme_of(c->desc), [&](auto s) { launch_dispatch<float, false, decltype(s)::value>(d, first != 0, mode, la); });
     else
-        o3 ? launch_dispatch<double, false, 3>(d, first != 0, mode, la)
-           : launch_dispatch<double, false, 5>(d, first != 0, mode, la);
+        by_scheme(scheme_of(c->desc), [&](auto s) { launch_dispatch<double, false, decltype(s)::value>(d, first != 0, mode, la); });
     int rc = launch_check(c, "sweep kernel");
     if (rc) return rc;
     if (c->profiling) {
@@ -486,17 +506,17 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
 // directions, x rows fit the row kernel and the weights are Jiang-Shu.
 bool fused_xy(const mfx_ctx* c)
 {
-    return c->fuse_xy && c->desc.weights == MFX_WENO5_JS && c->ndirs >= 2 && c->dirs[0] == 0 && c->dirs[1] == 1 &&
+    return c->fuse_xy && !learned_weights(c->desc) && c->ndirs >= 2 && c->dirs[0] == 0 && c->dirs[1] == 1 &&
            use_xrows(c->g.n, c->xmode_override, c->elem);
 }
 
-template <typename T, int MODE, int ORDER>
+template <typename T, int MODE, int SCHEME>
 void launch_xy_mode(mfx_ctx* c, const double* qs, const double* qn, double* out, const double* dt_dev, double dt_arg)
 {
     const Grid& g = c->g;
     const long long rows = (long long)g.n[1] * g.n[2];
     T* bf = static_cast<T*>(c->bface);
-    boundary_faces_x<T, false, ORDER><<<(unsigned)((rows + 255) / 256), 256, 0, c->stream>>>(g, qs, bf, c->mlp,
+    boundary_faces_x<T, false, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, c->stream>>>(g, qs, bf, c->mlp,
                                                                                               c->fallback);
     // segments along y as for the y sweep (lanes = x, blocks over z and segments)
     int seg = c->seg_override > 0 ? c->seg_override : 64;
@@ -505,20 +525,20 @@ void launch_xy_mode(mfx_ctx* c, const double* qs, const double* qn, double* out,
     seg = std::min(seg, g.n[1]);
     const dim3 grid(1, (unsigned)g.n[2], (unsigned)((g.n[1] + seg - 1) / seg));
     const int block = 64 * ((g.n[0] + 63) / 64);
-    sweep_xy<T, MODE, ORDER><<<grid, block, xrow_lds_bytes(g.n[0], sizeof(T)), c->stream>>>(
+    sweep_xy<T, MODE, SCHEME><<<grid, block, xrow_lds_bytes(g.n[0], sizeof(T)), c->stream>>>(
         g, qs, qn, static_cast<T*>(c->r), out, seg, bf, dt_dev, dt_arg);
 }
 
-template <typename T, int ORDER>
+template <typename T, int SCHEME>
 void launch_xy(mfx_ctx* c, int mode, const double* qs, const double* qn, double* out, const double* dt_dev,
                double dt_arg)
 {
     switch (mode) {
-    case OUT_ACCUM: launch_xy_mode<T, OUT_ACCUM, ORDER>(c, qs, qn, out, dt_dev, dt_arg); break;
-    case OUT_RHS: launch_xy_mode<T, OUT_RHS, ORDER>(c, qs, qn, out, dt_dev, dt_arg); break;
-    case OUT_STAGE1: launch_xy_mode<T, OUT_STAGE1, ORDER>(c, qs, qn, out, dt_dev, dt_arg); break;
-    case OUT_STAGE2: launch_xy_mode<T, OUT_STAGE2, ORDER>(c, qs, qn, out, dt_dev, dt_arg); break;
-    default: launch_xy_mode<T, OUT_STAGE3, ORDER>(c, qs, qn, out, dt_dev, dt_arg); break;
+    case OUT_ACCUM: launch_xy_mode<T, OUT_ACCUM, SCHEME>(c, qs, qn, out, dt_dev, dt_arg); break;
+    case OUT_RHS: launch_xy_mode<T, OUT_RHS, SCHEME>(c, qs, qn, out, dt_dev, dt_arg); break;
+    case OUT_STAGE1: launch_xy_mode<T, OUT_STAGE1, SCHEME>(c, qs, qn, out, dt_dev, dt_arg); break;
+    case OUT_STAGE2: launch_xy_mode<T, OUT_STAGE2, SCHEME>(c, qs, qn, out, dt_dev, dt_arg); break;
+    default: launch_xy_mode<T, OUT_STAGE3, SCHEME>(c, qs, qn, out, dt_dev, dt_arg); break;
     }
 }
 
@@ -533,13 +553,10 @@ int launch_sweep_xy(mfx_ctx* c, const double* qs, const double* qn, double* out,
         if (!pend.a || !pend.b) return fail(c, MFX_EHIP, "hipEventCreate failed");
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
-    const bool o3 = weno_order(c->desc) == 3;
     if (c->desc.precision == MFX_FP32_MIXED)
-        o3 ? launch_xy<float, 3>(c, mode, qs, qn, out, dt_dev, dt_arg)
-           : launch_xy<float, 5>(c, mode, qs, qn, out, dt_dev, dt_arg);
+        by_scheme(scheme_of(c->desc), [&](auto s) { launch_xy<float, decltype(s)::value>(c, mode, qs, qn, out, dt_dev, dt_arg); });
     else
-        o3 ? launch_xy<double, 3>(c, mode, qs, qn, out, dt_dev, dt_arg)
-           : launch_xy<double, 5>(c, mode, qs, qn, out, dt_dev, dt_arg);
+        by_scheme(scheme_of(c->desc), [&](auto s) { launch_xy<double, decltype(s)::value>(c, mode, qs, qn, out, dt_dev, dt_arg); });
     int rc = launch_check(c, "fused x-y sweep");
     if (rc) return rc;
     if (c->profiling) {
@@ -554,7 +571,7 @@ int launch_sweep_xy(mfx_ctx* c, const double* qs, const double* qn, double* out,
 // output; 0 when the standalone reduction is needed.
 long long cfl_blocks_in_last_pass(const mfx_ctx* c)
 {
-    if (!c->fuse_cfl || c->desc.weights != MFX_WENO5_JS) return 0;
+    if (!c->fuse_cfl || learned_weights(c->desc)) return 0;
     const int d = c->dirs[c->ndirs - 1];
     if (d == 0 || !c->g.active[d]) return 0;
     if (fused_xy(c) && c->ndirs == 2) return 0;  // the fused x-y pass is the last
@@ -625,7 +642,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     *out = nullptr;
     std::string why;
     if (!validate(desc, why)) return fail(nullptr, MFX_EINVAL, why);
-    if (desc->weights != MFX_WENO5_JS && desc->precision != MFX_FP32_MIXED)
+    if (learned_weights(*desc) && desc->precision != MFX_FP32_MIXED)
         return fail(nullptr, MFX_EINVAL, "learned weights run in the MFX_FP32_MIXED precision form");
     if (!ws_dev) return fail(nullptr, MFX_EINVAL, "workspace pointer is NULL");
     if (reinterpret_cast<uintptr_t>(ws_dev) % ALIGN != 0)
@@ -752,7 +769,7 @@ int mfx_get_state(mfx_ctx* c, double* q_dev_out)
 namespace {
 int need_mlp(mfx_ctx* c)
 {
-    if (c->desc.weights != MFX_WENO5_JS && !c->has_mlp)
+    if (learned_weights(c->desc) && !c->has_mlp)
         return fail(c, MFX_EINVAL, "learned weights selected but no network set (mfx_set_mlp)");
     return MFX_OK;
 }

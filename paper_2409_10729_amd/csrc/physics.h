@@ -168,6 +168,79 @@ __device__ __forceinline__ void weno5<float>(float a, float b, float c, float d,
     weno5_js_ratio(a, b, c, d, e, eps, left, right);
 }
 
+// WENO5 with WENO-Z weights (Borges, Carmona, Costa & Don, J. Comput. Phys.
+// 227, 2008; exponent 1), a comparison form for the learned weights: the
+// same candidates and indicators as Jiang-Shu, weights
+// alpha_k = d_k (1 + tau / (beta_k + eps)) with tau = |beta_0 - beta_2|.
+// float64: alpha_k scaled by the product of the three (beta + eps), one
+// division per edge: alpha_k ~ d_k (e_k + tau) prod_{j != k} e_j.
+__device__ __forceinline__ void weno5z_prod(double a, double b, double c, double d, double e, double eps,
+                                            double& left, double& right)
+{
+    const double k13 = 13.0 / 12.0;
+    const double q0 = a - 2.0 * b + c, h0 = a - 4.0 * b + 3.0 * c;
+    const double q1 = b - 2.0 * c + d, h1 = b - d;
+    const double q2 = c - 2.0 * d + e, h2 = 3.0 * c - 4.0 * d + e;
+    const double b0 = k13 * q0 * q0 + 0.25 * h0 * h0;
+    const double b1 = k13 * q1 * q1 + 0.25 * h1 * h1;
+    const double b2 = k13 * q2 * q2 + 0.25 * h2 * h2;
+    const double tau = fabs(b0 - b2);
+    const double e0 = b0 + eps, e1 = b1 + eps, e2 = b2 + eps;
+    const double g0 = (e0 + tau) * (e1 * e2), g1 = (e1 + tau) * (e0 * e2), g2 = (e2 + tau) * (e0 * e1);
+    // six times the candidate values
+    const double r0 = 2.0 * a - 7.0 * b + 11.0 * c;
+    const double r1 = -b + 5.0 * c + 2.0 * d;
+    const double r2 = 2.0 * c + 5.0 * d - e;
+    const double l0 = -a + 5.0 * b + 2.0 * c;
+    const double l1 = 2.0 * b + 5.0 * c - d;
+    const double l2 = 11.0 * c - 7.0 * d + 2.0 * e;
+    const double wr0 = 0.1 * g0, wr1 = 0.6 * g1, wr2 = 0.3 * g2;
+    const double wl0 = 0.3 * g0, wl1 = 0.6 * g1, wl2 = 0.1 * g2;
+    right = qdiv(wr0 * r0 + wr1 * r1 + wr2 * r2, 6.0 * (wr0 + wr1 + wr2));
+    left = qdiv(wl0 * l0 + wl1 * l1 + wl2 * l2, 6.0 * (wl0 + wl1 + wl2));
+}
+
+// float32: the weights as defined (three reciprocal quotients), which cannot
+// overflow: 1 <= 1 + tau / (beta + eps) <= 1 + tau / eps.
+__device__ __forceinline__ void weno5z_direct(float a, float b, float c, float d, float e, float eps, float& left,
+                                              float& right)
+{
+    const float k13 = 13.0f / 12.0f;
+    const float q0 = a - 2.f * b + c, h0 = a - 4.f * b + 3.f * c;
+    const float q1 = b - 2.f * c + d, h1 = b - d;
+    const float q2 = c - 2.f * d + e, h2 = 3.f * c - 4.f * d + e;
+    const float b0 = k13 * q0 * q0 + 0.25f * h0 * h0;
+    const float b1 = k13 * q1 * q1 + 0.25f * h1 * h1;
+    const float b2 = k13 * q2 * q2 + 0.25f * h2 * h2;
+    const float tau = fabsf(b0 - b2);
+    const float z0 = 1.f + qdiv(tau, b0 + eps), z1 = 1.f + qdiv(tau, b1 + eps), z2 = 1.f + qdiv(tau, b2 + eps);
+    const float r0 = 2.f * a - 7.f * b + 11.f * c;
+    const float r1 = -b + 5.f * c + 2.f * d;
+    const float r2 = 2.f * c + 5.f * d - e;
+    const float l0 = -a + 5.f * b + 2.f * c;
+    const float l1 = 2.f * b + 5.f * c - d;
+    const float l2 = 11.f * c - 7.f * d + 2.f * e;
+    const float wr0 = 0.1f * z0, wr1 = 0.6f * z1, wr2 = 0.3f * z2;
+    const float wl0 = 0.3f * z0, wl1 = 0.6f * z1, wl2 = 0.1f * z2;
+    right = qdiv(wr0 * r0 + wr1 * r1 + wr2 * r2, 6.f * (wr0 + wr1 + wr2));
+    left = qdiv(wl0 * l0 + wl1 * l1 + wl2 * l2, 6.f * (wl0 + wl1 + wl2));
+}
+
+template <typename T>
+__device__ __forceinline__ void weno5z(T a, T b, T c, T d, T e, T eps, T& left, T& right);
+template <>
+__device__ __forceinline__ void weno5z<double>(double a, double b, double c, double d, double e, double eps,
+                                               double& left, double& right)
+{
+    weno5z_prod(a, b, c, d, e, eps, left, right);
+}
+template <>
+__device__ __forceinline__ void weno5z<float>(float a, float b, float c, float d, float e, float eps, float& left,
+                                              float& right)
+{
+    weno5z_direct(a, b, c, d, e, eps, left, right);
+}
+
 // WENO3 with Jiang-Shu weights (the third-order reconstruction named
 // beside WENO5 in Sec. II-B) for cell c from w_{c-1..c+1} = a, b, c:
 // candidates on {c-1, c} and {c, c+1}; right edge (c+1/2) with linear

@@ -315,20 +315,36 @@ __device__ __forceinline__ void settle(T& a, T& b)
     asm volatile("" : "+v"(a), "+v"(b));
 }
 
+// Reconstruction schemes of the non-learned passes (a compile-time
+// parameter of every sweep kernel).
+enum : int {
+    SCHEME_WENO3 = 3,   // WENO3, Jiang-Shu weights, on the middle three cells
+    SCHEME_WENO5 = 5,   // WENO5, Jiang-Shu weights
+    SCHEME_WENO5Z = 6,  // WENO5, WENO-Z weights (comparison form)
+};
+
 // Reconstruction of one cell's two edge states (all seven primitives) from
-// its 5-cell window: WENO5, or WENO3 on the middle three cells (ORDER).
-template <typename T, int ORDER = 5>
+// its 5-cell window in the given scheme.
+template <typename T, int SCHEME = SCHEME_WENO5>
+__device__ __forceinline__ void recon_scheme(T a, T b, T c, T d, T e, T eps, T& left, T& right)
+{
+    static_assert(SCHEME == SCHEME_WENO5 || SCHEME == SCHEME_WENO3 || SCHEME == SCHEME_WENO5Z, "scheme");
+    if constexpr (SCHEME == SCHEME_WENO5)
+        weno5<T>(a, b, c, d, e, eps, left, right);
+    else if constexpr (SCHEME == SCHEME_WENO3)
+        weno3<T>(b, c, d, eps, left, right);
+    else
+        weno5z<T>(a, b, c, d, e, eps, left, right);
+}
+
+template <typename T, int SCHEME = 5>
 struct ReconJS {
-    static_assert(ORDER == 5 || ORDER == 3, "WENO order 5 or 3");
     template <class Win>
     __device__ __forceinline__ void cell_win(const Win& W, T eps, T lft[NV], T rgt[NV])
     {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            if constexpr (ORDER == 5)
-                weno5<T>(W(0, v), W(1, v), W(2, v), W(3, v), W(4, v), eps, lft[v], rgt[v]);
-            else
-                weno3<T>(W(1, v), W(2, v), W(3, v), eps, lft[v], rgt[v]);
+            recon_scheme<T, SCHEME>(W(0, v), W(1, v), W(2, v), W(3, v), W(4, v), eps, lft[v], rgt[v]);
             settle(lft[v], rgt[v]);
         }
     }
@@ -461,9 +477,9 @@ struct ReconLearned {
 
 constexpr int LEARNED_MAX_WAVES = 8;  // largest block of a learned sweep: 512 threads
 
-template <typename T, bool LEARNED, int ORDER = 5>
+template <typename T, bool LEARNED, int SCHEME = 5>
 struct ReconOf {
-    using type = ReconJS<T, ORDER>;
+    using type = ReconJS<T, SCHEME>;
 };
 template <>
 struct ReconOf<float, true, 5> {
@@ -472,8 +488,8 @@ struct ReconOf<float, true, 5> {
 
 // WAVES: the most waves a block of the calling kernel has (the learned
 // form's LDS slots are static, so the count sizes the kernel's LDS).
-template <typename T, bool LEARNED, int ORDER = 5, int WAVES = LEARNED_MAX_WAVES>
-__device__ __forceinline__ typename ReconOf<T, LEARNED, ORDER>::type make_recon(const Grid& g, const MlpLane* mlp,
+template <typename T, bool LEARNED, int SCHEME = 5, int WAVES = LEARNED_MAX_WAVES>
+__device__ __forceinline__ typename ReconOf<T, LEARNED, SCHEME>::type make_recon(const Grid& g, const MlpLane* mlp,
                                                                                bool valid)
 {
     if constexpr (LEARNED) {
@@ -487,7 +503,7 @@ __device__ __forceinline__ typename ReconOf<T, LEARNED, ORDER>::type make_recon(
         (void)g;
         (void)mlp;
         (void)valid;
-        return ReconJS<T, ORDER>{};
+        return ReconJS<T, SCHEME>{};
     }
 }
 
@@ -615,7 +631,7 @@ constexpr int yz_block()
 
 // (The learned passes keep the occupancy hint of two waves per SIMD: without
 // it the compiler schedules them for a higher occupancy they cannot reach.)
-template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED, bool CFL = false, int ORDER = 5>
+template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED, bool CFL = false, int SCHEME = 5>
 __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 2 : 1) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
                                                    T* __restrict__ racc, double* out, int seg,
                                                    const double* __restrict__ dt_dev, double dt_arg,
@@ -637,7 +653,7 @@ __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 2 : 1) sweep_yz
     GlobalSrc src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
     GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CFL, !LEARNED> sink{
         OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid, CflAcc{0.0, 0u}};
-    auto recon = make_recon<T, LEARNED, ORDER, BLOCK / 64>(g, mlp, valid);
+    auto recon = make_recon<T, LEARNED, SCHEME, BLOCK / 64>(g, mlp, valid);
     __shared__ T win[5][NV][BLOCK];
     LdsWindow<T, BLOCK> W{&win[0][0][threadIdx.x], 0};
     march<DIR, T>(g, src, sink, recon, c0, c1, W);
@@ -726,7 +742,7 @@ struct LdsSink {
     }
 };
 
-template <typename T, bool FIRST, int MODE, bool LEARNED, int ORDER = 5>
+template <typename T, bool FIRST, int MODE, bool LEARNED, int SCHEME = 5>
 __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* __restrict__ qs, const double* qn,
                                                           T* __restrict__ racc, double* out, int seg,
                                                           const double* __restrict__ dt_dev, double dt_arg,
@@ -743,7 +759,7 @@ __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* 
     LdsSrc src{ibuf, qs, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
     LdsSink<T, FIRST, MODE> sink{obuf, OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx,
                                  c0, c1};
-    auto recon = make_recon<T, LEARNED, ORDER, XROWS / 64>(g, mlp, row0 + threadIdx.x < nrows);
+    auto recon = make_recon<T, LEARNED, SCHEME, XROWS / 64>(g, mlp, row0 + threadIdx.x < nrows);
     __shared__ T win[5][NV][XROWS];
     LdsWindow<T, XROWS> W{&win[0][0][threadIdx.x], 0};
     march<0, T>(g, src, sink, recon, c0, c1, W);

@@ -28,7 +28,7 @@ constexpr int BFACE = NV + 1;       // flux components + face velocity
 // and converts those six cells once and assembles both 6-cell stencils from
 // them; with periodic ends the two faces are one face, solved once.
 // Shorter rows map every position through the boundary rule.
-template <typename T, bool LEARNED, int ORDER = 5>
+template <typename T, bool LEARNED, int SCHEME = 5>
 __global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __restrict__ qs, T* __restrict__ bface,
                                                         const MlpLane* __restrict__ mlp, unsigned long long* fb)
 {
@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __
             prim_of<T>(mixd, q, a[j]);
         }
     }
-    auto recon = make_recon<T, LEARNED, ORDER, 4>(g, mlp, valid);  // 256 threads
+    auto recon = make_recon<T, LEARNED, SCHEME, 4>(g, mlp, valid);  // 256 threads
     const int sides = blo == BC_PERIODIC ? 1 : 2;  // periodic ends pair up
 #pragma unroll 1
     for (int side = 0; side < sides; ++side) {
@@ -143,7 +143,7 @@ struct RowWindow {
 };
 
 // Row kernel.
-template <typename T, bool FIRST, int MODE, bool LEARNED, int ORDER = 5>
+template <typename T, bool FIRST, int MODE, bool LEARNED, int SCHEME = 5>
 __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const double* __restrict__ qs, const double* qn,
                                                              T* __restrict__ racc, double* out, int rows_per_block,
                                                              const T* __restrict__ bface,
@@ -175,7 +175,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
     const int gsrc2 = map_cell(nx, nx, g.bc[0][0], g.bc[0][1]);
     const int gsrc3 = map_cell(nx + 1, nx, g.bc[0][0], g.bc[0][1]);
 
-    auto recon = make_recon<T, LEARNED, ORDER>(g, mlp, has);
+    auto recon = make_recon<T, LEARNED, SCHEME>(g, mlp, has);
     double qc[NV];
     if (r0 < r1) {
 #pragma unroll
@@ -267,7 +267,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
 // order as the x pass followed by the y pass) once, so the state is read
 // once and the running sum never goes through memory.  The window lives in
 // registers; LDS holds the row buffers of the x part (xrow_layout).
-template <typename T, int MODE, int ORDER = 5>
+template <typename T, int MODE, int SCHEME = 5>
 struct XYSink {
     static constexpr bool keeps_q = false;
     __device__ __forceinline__ void prefetch(const Grid&, int) {}
@@ -309,10 +309,7 @@ struct XYSink {
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const T* pv = P + v * np + xc;
-            if constexpr (ORDER == 5)
-                weno5<T>(pv[0], pv[1], pv[2], pv[3], pv[4], eps, lft[v], rgt[v]);
-            else
-                weno3<T>(pv[1], pv[2], pv[3], eps, lft[v], rgt[v]);
+            recon_scheme<T, SCHEME>(pv[0], pv[1], pv[2], pv[3], pv[4], eps, lft[v], rgt[v]);
             settle(lft[v], rgt[v]);
         }
         if (has) {
@@ -365,7 +362,7 @@ struct XYSink {
     }
 };
 
-template <typename T, int MODE, int ORDER = 5>
+template <typename T, int MODE, int SCHEME = 5>
 __global__ void __launch_bounds__(XROW_THREADS) sweep_xy(Grid g, const double* __restrict__ qs, const double* qn,
                                                          T* __restrict__ racc, double* out, int seg,
                                                          const T* __restrict__ bface,
@@ -384,7 +381,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_xy(Grid g, const double* _
     const long long base_z = (long long)z * g.stride[2];
 
     GlobalSrc src{qs, base_z + xc, g.stride[1], g.N, ny, g.bc[1][0], g.bc[1][1]};
-    XYSink<T, MODE, ORDER> sink{OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg},
+    XYSink<T, MODE, SCHEME> sink{OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg},
                          lds + lay.p,
                          lds + lay.l,
                          lds + lay.fs,
@@ -402,7 +399,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_xy(Grid g, const double* _
                          (T)g.inv_dx[0],
                          (T)g.eps,
                          Mix<T>{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2}};
-    ReconJS<T, ORDER> recon{};
+    ReconJS<T, SCHEME> recon{};
     RegWindow<T> W;
     march<1, T>(g, src, sink, recon, c0, c1, W);
 }

@@ -112,6 +112,10 @@ def test_weno_order_options():
         assert L.mfx_workspace_bytes(ctypes.byref(_desc(weno_order=order))) > 0
     d = _desc(weno_order=3, weights=_native.MFX_WENO5_LEARNED, precision=_native.MFX_FP32_MIXED)
     assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0
+    # WENO-Z weights: fifth order only, either precision form
+    for prec in (_native.MFX_FP64, _native.MFX_FP32_MIXED):
+        assert L.mfx_workspace_bytes(ctypes.byref(_desc(weights=_native.MFX_WENO5_Z, precision=prec))) > 0
+    assert L.mfx_workspace_bytes(ctypes.byref(_desc(weights=_native.MFX_WENO5_Z, weno_order=3))) == 0
 
 
 def test_size_limits():

@@ -198,6 +198,39 @@ def test_longest_allowed_row_matches_oracle():
     assert np.all(err <= TOL), err
 
 
+@pytest.mark.parametrize("n,bc,seed", [
+    ((37, 29, 23), ((1, 1), (0, 0), (1, 1)), 40),  # fused x-y pass, z
+    ((1, 40, 33), ((0, 0), (1, 1), (0, 0)), 41),  # y and z sweeps
+    ((600, 3, 2), ((1, 1), (0, 0), (0, 0)), 42),  # marching x sweep
+])
+def test_weno_z_matches_oracle(n, bc, seed):
+    """WENO5 with WENO-Z weights (the comparison form for the learned
+    weights): right-hand side and one step against the oracle's WENO-Z."""
+    from paper_2409_10729_amd import MFX_WENO5_Z
+
+    P = wl.random_smooth(n=n, seed=seed, bc=bc)
+    spec = dict(P["spec"], weno_z=True)
+    g = oracle.make_grid(spec)
+    q0 = oracle.prim_to_cons(g, P["w"])
+    s = gpu_solver(spec, q0=q0, weights=MFX_WENO5_Z)
+    r_ref = oracle.rhs(g, q0)
+    err = rhs_rel_linf(s.rhs().cpu().numpy(), r_ref, q0, spec)
+    _report(f"weno-z rhs {n}", err)
+    assert np.all(err <= TOL), err
+    dt = s.rk3_step(sync=True)
+    q = s.get_state().cpu().numpy()
+    cells = sample_cells(spec, 300, seed=4, q0=q0)
+    ref = oracle_step_at(spec, q0, cells, dt)
+    err = rel_linf(q.reshape(7, -1)[:, cells], ref)
+    _report(f"weno-z step {n}", err)
+    assert np.all(err <= TOL), err
+    # the JS and WENO-Z right-hand sides differ (the option is live)
+    assert not np.allclose(oracle.rhs(oracle.make_grid(P["spec"]), q0), r_ref, rtol=1e-8, atol=0)
+    s32 = gpu_solver(spec, q0=q0, precision=MFX_FP32_MIXED, weights=MFX_WENO5_Z)
+    err32 = rhs_rel_linf(s32.rhs().cpu().numpy(), r_ref, q0, spec)
+    assert np.all(err32 <= 1e-5), err32
+
+
 def test_segment_length_does_not_change_results(monkeypatch):
     P = wl.shock_droplet(n=(40, 36, 44), seed=4)
     g, q0 = _q0(P)
