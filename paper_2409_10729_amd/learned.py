@@ -440,6 +440,27 @@ def js_validation_loss(data, lam):
     return float((r * r).mean().item())
 
 
+def calibrate(path: str, scale: float, command: str) -> int:
+    """Scale the output layer (W3, b3) of a saved network by `scale`: in the
+    residual form the logits z = W3 h + b3 correct log(omega_JS), so this
+    applies the learned correction at the given strength.  Recorded in the
+    network's metadata (applied scales multiply)."""
+    p = np.load(path, allow_pickle=False)
+    lo, hi = OUT_LAYER
+    p[lo:hi] *= np.float32(scale)
+    np.save(path, p)
+    mpath = os.path.splitext(path)[0] + ".json"
+    meta = {}
+    if os.path.exists(mpath):
+        with open(mpath) as f:
+            meta = json.load(f)
+    meta.setdefault("calibration", []).append({"correction_scale": scale, "command": command})
+    with open(mpath, "w") as f:
+        json.dump(meta, f, indent=1)
+    print(json.dumps(meta["calibration"]), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", default=None, help="default: data/mlp_weno5.npy, or data/mlp_weno5_edge.npy with --edge")
@@ -455,14 +476,20 @@ def main(argv=None):
     ap.add_argument("--ft-lr", type=float, default=0.05)
     ap.add_argument("--ft-tubes", type=int, default=4, help="fine-tuning shock tubes (seeds 0..N-1)")
     ap.add_argument("--ft-slabs", type=int, default=4, help="fine-tuning slabs (seeds 1000..)")
+    ap.add_argument("--calibrate", type=float, default=None,
+                    help="no training: scale the output layer of the existing --out network (the network's "
+                         "correction to the Jiang-Shu log-weights is linear in it) by this factor and record it")
     args = ap.parse_args(argv)
+    if args.out is None:
+        args.out = EDGE_PARAMS if args.edge else DEFAULT_PARAMS
+    if args.calibrate is not None:
+        return calibrate(args.out, args.calibrate,
+                         "python -m paper_2409_10729_amd.learned " + " ".join(sys.argv[1:] if argv is None else argv))
     import torch
 
     from . import MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE
 
     assert torch.cuda.is_available(), "training runs on the GPU"
-    if args.out is None:
-        args.out = EDGE_PARAMS if args.edge else DEFAULT_PARAMS
     t0 = time.time()
     *data, raw = build_dataset(range(args.tubes), range(1000, 1000 + args.slabs), edge=args.edge)
     t1 = time.time()

@@ -2,6 +2,9 @@
 against central finite differences, closed-form special cases (zero output
 layer gives uniform weights, softmax rows sum to one), the feature map's
 invariances, and its smoothness indicators against the C oracle's."""
+import json
+import os
+
 import numpy as np
 import pytest
 
@@ -177,3 +180,35 @@ def test_shared_backward_matches_finite_differences(lam):
         a, b = g[o:o + size], fd[o:o + size]
         o += size
         assert np.linalg.norm(a - b) <= 1e-6 * max(np.linalg.norm(b), 1e-12), name
+
+
+def test_calibration_scales_the_correction(tmp_path):
+    """learned.calibrate scales the output layer; in the residual form the
+    logits that correct log(omega_JS) scale by the same factor, so the
+    calibrated weights are softmax(log omega_JS + s z)."""
+    import shutil
+
+    from paper_2409_10729_amd import learned
+
+    src = learned.DEFAULT_PARAMS
+    if not os.path.exists(src):
+        pytest.skip("no trained network committed")
+    dst = tmp_path / "net.npy"
+    shutil.copy(src, dst)
+    theta = np.load(dst).astype(np.float64)
+    learned.calibrate(str(dst), 0.8, "test")
+    theta_s = np.load(dst).astype(np.float64)
+    rng = np.random.default_rng(5)
+    V = rng.normal(size=(64, 5)) * rng.uniform(0.01, 10.0, size=(64, 1))
+    X = np.stack([mlp.features(v) for v in V])
+    ojs = np.stack([mlp.js_weights_right(v) for v in V])
+    w1 = mlp.forward(theta, X, ojs)[0]
+    w_s = mlp.forward(theta_s, X, ojs)[0]
+    # z = log(omega) - log(omega_JS) up to a per-row constant
+    z1 = np.log(w1) - np.log(ojs)
+    zs = np.log(w_s) - np.log(ojs)
+    z1 -= z1.mean(axis=1, keepdims=True)
+    zs -= zs.mean(axis=1, keepdims=True)
+    np.testing.assert_allclose(zs, 0.8 * z1, rtol=1e-5, atol=1e-6)
+    meta = json.load(open(tmp_path / "net.json"))
+    assert meta["calibration"][-1]["correction_scale"] == 0.8
