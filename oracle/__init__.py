@@ -113,6 +113,12 @@ def make_grid(spec: dict, weno_z: bool = False) -> OrcGrid:
     g.weno_order = int(spec.get("weno_order", 5))
     if g.weno_order not in (3, 5):
         raise ValueError("weno_order must be 3 or 5")
+    for d in range(3):
+        kinds = (g.bc[d][0], g.bc[d][1])
+        if any(k not in (0, 1, 2) for k in kinds):
+            raise ValueError("bc must be 0 (periodic), 1 (transmissive) or 2 (reflective)")
+        if 2 in kinds and 1 < g.n[d] < 3:
+            raise ValueError("a reflective side needs at least 3 cells in its direction")
     return g
 
 

@@ -54,7 +54,8 @@
 typedef struct {
     int32_t n[3];      /* interior cells per direction; 1 = inactive */
     double dx[3];      /* uniform spacing per direction */
-    int32_t bc[3][2];  /* 0 = periodic, 1 = transmissive (zero gradient) */
+    int32_t bc[3][2];  /* 0 = periodic, 1 = transmissive (zero gradient),
+                          2 = reflective (slip wall) */
     double gamma[2];   /* fluid 1, fluid 2 */
     double pinf[2];
     double eps;        /* WENO epsilon */
@@ -288,17 +289,26 @@ static void hllc(const orc_grid* g, const double* wl, const double* wr, int d, d
     *uf = un + s * (xi - 1.0);
 }
 
-/* ---------- boundary index map ---------- */
-static int64_t map_index(const orc_grid* g, int d, int64_t i)
+/* ---------- boundary index map ----------
+   The cell whose state ghost cell i (outside 0..n-1) takes: periodic wraps
+   around, transmissive repeats the edge cell (zero gradient), reflective
+   mirrors about the boundary face (ghost -1-k <- cell k, ghost n+k <- cell
+   n-1-k) and sets *flip: that ghost carries the mirrored cell's state with
+   the momentum normal to the wall negated (a stationary slip wall; the
+   paper names no boundary type, this is the standard ghost construction).
+   Reflective sides need n >= 3 (checked by the Python wrapper). */
+static int64_t map_index(const orc_grid* g, int d, int64_t i, int* flip)
 {
     int64_t n = g->n[d];
+    *flip = 0;
     if (i >= 0 && i < n) return i;
-    if (i < 0) {
-        if (g->bc[d][0] == 0) return ((i % n) + n) % n;
-        return 0;
+    int t = g->bc[d][i < 0 ? 0 : 1];
+    if (t == 2) {
+        *flip = 1;
+        return i < 0 ? -1 - i : 2 * n - 1 - i;
     }
-    if (g->bc[d][1] == 0) return i % n;
-    return n - 1;
+    if (i < 0) return t == 0 ? ((i % n) + n) % n : 0;
+    return t == 0 ? i % n : n - 1;
 }
 
 static int active(const orc_grid* g, int d) { return g->n[d] > 1; }
@@ -371,14 +381,19 @@ void orc_rhs(const orc_grid* g, const double* q, double* rhs)
 #pragma omp parallel for collapse(2) schedule(static)
     for (int k = 0; k < P[2]; ++k)
         for (int j = 0; j < P[1]; ++j) {
-            int64_t sk = map_index(g, 2, k - gh[2]);
-            int64_t sj = map_index(g, 1, j - gh[1]);
+            int fk, fj, fi;
+            int64_t sk = map_index(g, 2, k - gh[2], &fk);
+            int64_t sj = map_index(g, 1, j - gh[1], &fj);
             for (int i = 0; i < P[0]; ++i) {
-                int64_t si = map_index(g, 0, i - gh[0]);
+                int64_t si = map_index(g, 0, i - gh[0], &fi);
                 int64_t src = (sk * g->n[1] + sj) * g->n[0] + si;
                 int64_t dst = ((int64_t)k * P[1] + j) * P[0] + i;
                 double qc[NV], wc[NV];
                 for (int v = 0; v < NV; ++v) qc[v] = q[v * N + src];
+                /* reflective ghosts: normal momentum of each mirrored direction negated */
+                if (fi) qc[2] = -qc[2];
+                if (fj) qc[3] = -qc[3];
+                if (fk) qc[4] = -qc[4];
                 cons_to_prim(g, qc, wc);
                 for (int v = 0; v < NV; ++v) wp[v * NP + dst] = wc[v];
             }
@@ -448,10 +463,12 @@ void orc_rhs_at(const orc_grid* g, const double* q, int64_t ncell, const int64_t
             double w7[7][NV];
             for (int o = -3; o <= 3; ++o) {
                 int64_t p2[3] = {pos[0], pos[1], pos[2]};
-                p2[d] = map_index(g, d, pos[d] + o);
+                int flip;
+                p2[d] = map_index(g, d, pos[d] + o, &flip);
                 int64_t src = p2[0] * stride_n[0] + p2[1] * stride_n[1] + p2[2] * stride_n[2];
                 double qc[NV];
                 for (int v = 0; v < NV; ++v) qc[v] = q[v * N + src];
+                if (flip) qc[2 + d] = -qc[2 + d];
                 cons_to_prim(g, qc, w7[o + 3]);
             }
             double lft[3][NV], rgt[3][NV];
