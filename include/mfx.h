@@ -52,7 +52,13 @@ enum {
     MFX_ESTATE = -4  /* non-physical or non-finite state detected on the device */
 };
 
-enum { MFX_BC_PERIODIC = 0, MFX_BC_TRANSMISSIVE = 1 };
+/* Boundary types (ghost cells, Sec. III-A structured mesh; the paper names
+ * none, these are the standard constructions).  Periodic wraps around and
+ * must be paired; transmissive repeats the edge cell (zero gradient);
+ * reflective is a stationary slip wall: the ghost cells mirror the cells
+ * beside the wall face with the momentum normal to it negated, so no mass
+ * or energy crosses it; it needs at least 3 cells in its direction. */
+enum { MFX_BC_PERIODIC = 0, MFX_BC_TRANSMISSIVE = 1, MFX_BC_REFLECTIVE = 2 };
 
 /* Arithmetic of the reconstruction and flux passes.
  * MFX_FP64: everything in float64.
@@ -79,7 +85,7 @@ typedef struct {
     int32_t n[3];      /* interior cells (nx, ny, nz), each >= 1; n == 1 makes a direction inactive */
     double lo[3];      /* domain origin (informational) */
     double dx[3];      /* uniform spacing per direction, > 0 */
-    int32_t bc[3][2];  /* lower/upper boundary per direction; periodic must be paired */
+    int32_t bc[3][2];  /* lower/upper MFX_BC_* per direction; periodic must be paired */
     double gamma[2];   /* stiffened-gas gamma of fluid 1 and fluid 2, > 1 */
     double pi_inf[2];  /* stiffened-gas pi_inf of fluid 1 and fluid 2, >= 0 */
     double cfl;        /* CFL number for the automatic time step, in (0, 1] */
@@ -197,7 +203,8 @@ int mfx_stats(mfx_ctx* ctx, double* t, int64_t* step, int64_t* fallback_faces, u
  * i-2..i+2 with target face_prim[v][i+1]; sample (1*7+v)*nx+i = the
  * mirrored stencil i+2..i-2 with target face_prim[v][i].  face_prim holds
  * reference primitive values at the nx+1 faces, [7][nx+1].  Outputs:
- * stencil_out[14*nx][5], target_out[14*nx] (float64). */
+ * stencil_out[14*nx][5], target_out[14*nx] (float64).  Reflective ends are
+ * rejected (MFX_EINVAL). */
 int mfx_mlp_sample_stencils(const mfx_grid_desc* desc, const double* q_dev, const double* face_prim_dev,
                             double* stencil_out, double* target_out, void* stream);
 
@@ -205,7 +212,7 @@ int mfx_mlp_sample_stencils(const mfx_grid_desc* desc, const double* q_dev, cons
  * `refine` times finer than the sampled one (same domain and boundary
  * conditions): coarse face i lies on fine face refine*i, whose primitive
  * value is the mean of the two fine cells beside it.  face_prim_out[7][nc+1]
- * with nc = fine nx / refine. */
+ * with nc = fine nx / refine.  Reflective ends are rejected (MFX_EINVAL). */
 int mfx_mlp_face_targets(const mfx_grid_desc* fine_desc, const double* q_fine_dev, int32_t refine, double* face_prim_out,
                          void* stream);
 

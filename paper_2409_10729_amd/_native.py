@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmfx.so")
 
 MFX_OK, MFX_EINVAL, MFX_EHIP, MFX_ENOMEM, MFX_ESTATE = 0, -1, -2, -3, -4
-MFX_BC_PERIODIC, MFX_BC_TRANSMISSIVE = 0, 1
+MFX_BC_PERIODIC, MFX_BC_TRANSMISSIVE, MFX_BC_REFLECTIVE = 0, 1, 2
 MFX_FP64, MFX_FP32_MIXED = 0, 1
 MFX_WENO5_JS, MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE, MFX_WENO5_Z = 0, 1, 2, 3
 

@@ -193,12 +193,17 @@ bool validate(const mfx_grid_desc* d, std::string& why)
             return false;
         }
         for (int s = 0; s < 2; ++s)
-            if (d->bc[k][s] != MFX_BC_PERIODIC && d->bc[k][s] != MFX_BC_TRANSMISSIVE) {
+            if (d->bc[k][s] != MFX_BC_PERIODIC && d->bc[k][s] != MFX_BC_TRANSMISSIVE &&
+                d->bc[k][s] != MFX_BC_REFLECTIVE) {
                 why = "bc[" + std::to_string(k) + "] holds an unknown boundary type";
                 return false;
             }
         if ((d->bc[k][0] == MFX_BC_PERIODIC) != (d->bc[k][1] == MFX_BC_PERIODIC)) {
             why = "periodic boundaries must be paired (bc[" + std::to_string(k) + "])";
+            return false;
+        }
+        if ((d->bc[k][0] == MFX_BC_REFLECTIVE || d->bc[k][1] == MFX_BC_REFLECTIVE) && d->n[k] == 2) {
+            why = "a reflective side needs n[" + std::to_string(k) + "] >= 3 (the mirror of three ghost cells)";
             return false;
         }
     }

@@ -23,12 +23,14 @@
 // active.
 #pragma once
 
+#include <climits>
+
 #include "learned.h"
 #include "physics.h"
 
 namespace mfx {
 
-enum : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1 };
+enum : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
 
 // What the pass does with the accumulated right-hand side of a cell.
 enum : int {
@@ -53,12 +55,42 @@ struct Grid {
     int edge_weights;  // learned weights: one network evaluation per edge for all variables
 };
 
+// Cell whose state stencil position c takes.  Ghost positions (outside
+// 0..n-1): periodic wraps around, transmissive repeats the edge cell,
+// reflective mirrors about the wall face (-1-k <- k, n+k <- n-1-k; the three
+// ghosts a stencil reaches need n >= 3) and the ghost carries the mirrored
+// cell with its momentum normal to the wall negated (see mirrored()), a
+// stationary slip wall.  Positions further out (the marching x sweep stages
+// whole chunks, up to n+5) are clamped into the row; no stencil uses them.
 __device__ __forceinline__ int map_cell(int c, int n, int bclo, int bchi)
 {
-    if (c < 0) return bclo == BC_PERIODIC ? ((c % n) + n) % n : 0;
-    if (c >= n) return bchi == BC_PERIODIC ? c % n : n - 1;
+    if (c < 0) return bclo == BC_PERIODIC ? ((c % n) + n) % n : (bclo == BC_REFLECTIVE ? min(-1 - c, n - 1) : 0);
+    if (c >= n) return bchi == BC_PERIODIC ? c % n : (bchi == BC_REFLECTIVE ? max(2 * n - 1 - c, 0) : n - 1);
     return c;
 }
+
+// True when stencil position c is a ghost of a reflective side: its normal
+// momentum (normal velocity) enters negated.
+__device__ __forceinline__ bool mirrored(int c, int n, int bclo, int bchi)
+{
+    return (c < 0 && bclo == BC_REFLECTIVE) || (c >= n && bchi == BC_REFLECTIVE);
+}
+
+// Ghost slots of the x-row kernels (positions -2, -1, n, n+1): bit k is set
+// when slot k is a reflective ghost.
+__device__ __forceinline__ unsigned ghost_flips(int n, int bclo, int bchi)
+{
+    return (bclo == BC_REFLECTIVE ? 3u : 0u) | (bchi == BC_REFLECTIVE ? 12u : 0u);
+}
+
+// Ghost slots of the x-row kernels that cell x fills: bit k set when slot k
+// (positions -2, -1, n, n+1) takes cell x's state.
+__device__ __forceinline__ unsigned ghost_slots_of(int x, int n, int bclo, int bchi)
+{
+    return (map_cell(-2, n, bclo, bchi) == x ? 1u : 0u) | (map_cell(-1, n, bclo, bchi) == x ? 2u : 0u) |
+           (map_cell(n, n, bclo, bchi) == x ? 4u : 0u) | (map_cell(n + 1, n, bclo, bchi) == x ? 8u : 0u);
+}
+
 
 // CFL wave speed sum_d (|u_d| + c) / dx_d of one cell, written in the same
 // operation order as the plain definition and without contraction, so the
@@ -538,6 +570,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
         }
         T w[NV];
         prim_of<T>(mixd, qc, w);
+        src.finish(c0 - 3 + k, w);
         W.store(k, w);
     };
     if constexpr (KQ || Win::in_registers) {
@@ -583,6 +616,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
             // cell c+3 enters, cell c-2 (no longer needed) leaves
             T w[NV];
             prim_of<T>(mixd, qnext, w);
+            src.finish_ahead(c + 3, w);  // c + 3 >= c0 + 2 >= 2
             W.push(w);
             if constexpr (KQ) {
 #pragma unroll
@@ -597,17 +631,37 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
     }
 }
 
-// Cell source for the y and z sweeps: straight from global memory; the
-// lanes of a wave are consecutive x, so each load is a contiguous row.
+// Cell source for the y and z sweeps (DIR 1 or 2): straight from global
+// memory; the lanes of a wave are consecutive x, so each load is a
+// contiguous row.
+template <int DIR>
 struct GlobalSrc {
     const double* __restrict__ qs;
     long long base, sd, N;
     int n, bclo, bchi;
+    // positions below flo or at/above fhi are reflective ghosts
+    int flo = bclo == BC_REFLECTIVE ? 0 : INT_MIN;
+    int fhi = bchi == BC_REFLECTIVE ? n : INT_MAX;
     __device__ __forceinline__ void load(int pos, double q[NV]) const
     {
         const long long off = base + (long long)map_cell(pos, n, bclo, bchi) * sd;
 #pragma unroll
         for (int v = 0; v < NV; ++v) q[v] = qs[v * N + off];
+    }
+    // A reflective ghost enters with its normal velocity negated; applied to
+    // the primitives where they are used (the same bits as negating the
+    // momentum before the conversion), so the load stays in flight until then.
+    template <typename T>
+    __device__ __forceinline__ void finish(int pos, T w[NV]) const
+    {
+        if (pos < flo || pos >= fhi) w[2 + DIR] = -w[2 + DIR];
+    }
+    // the same for a position known to be >= 0 (cells entering the window
+    // ahead of the march)
+    template <typename T>
+    __device__ __forceinline__ void finish_ahead(int pos, T w[NV]) const
+    {
+        if (pos >= fhi) w[2 + DIR] = -w[2 + DIR];
     }
 };
 
@@ -650,7 +704,7 @@ __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 2 : 1) sweep_yz
     const long long base = (long long)i + (long long)blockIdx.y * g.stride[SA];
     const int c0 = blockIdx.z * seg;
     const int c1 = min(c0 + seg, n);
-    GlobalSrc src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
+    GlobalSrc<DIR> src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
     GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CFL, !LEARNED> sink{
         OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid, CflAcc{0.0, 0u}};
     auto recon = make_recon<T, LEARNED, SCHEME, BLOCK / 64>(g, mlp, valid);
@@ -696,14 +750,20 @@ struct LdsSrc {
                 const int r = item / XCHUNK, cx = item % XCHUNK;
                 const long long row = min(row0 + r, nrows - 1);
                 const long long off = row * nx + map_cell(pos + cx, nx, bclo, bchi);
+                const double sgn = mirrored(pos + cx, nx, bclo, bchi) ? -1.0 : 1.0;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) buf[cx][v][r] = qs[v * N + off];
+                for (int v = 0; v < NV; ++v) buf[cx][v][r] = v == 2 ? sgn * qs[v * N + off] : qs[v * N + off];
             }
             __syncthreads();
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) q[v] = buf[slot][v][threadIdx.x];
     }
+    // reflective ghosts are flipped while staging
+    template <typename T>
+    __device__ __forceinline__ void finish(int, T*) const {}
+    template <typename T>
+    __device__ __forceinline__ void finish_ahead(int, T*) const {}
 };
 
 template <typename T, bool FIRST, int MODE>

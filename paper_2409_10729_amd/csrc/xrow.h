@@ -61,7 +61,8 @@ __global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __
         T w[6][NV];
 #pragma unroll
         for (int k = 0; k < 6; ++k) {
-            const int cell = map_cell(side == 0 ? k - 3 : nx - 3 + k, nx, blo, bhi);
+            const int pos = side == 0 ? k - 3 : nx - 3 + k;
+            const int cell = map_cell(pos, nx, blo, bhi);
             if (anchored) {
                 const int j = cell < 3 ? cell : cell - nx + 6;
 #pragma unroll
@@ -77,6 +78,9 @@ __global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __
                 for (int v = 0; v < NV; ++v) q[v] = qs[v * g.N + row * nx + cell];
                 prim_of<T>(mixd, q, w[k]);
             }
+            // reflective ghost: normal velocity negated (the same bits as
+            // converting the state with its momentum negated)
+            if (mirrored(pos, nx, blo, bhi)) w[k][2] = -w[k][2];
         }
         // right edge of the cell before the face (window w[0..4]) and left
         // edge of the cell after it (window w[1..5])
@@ -169,11 +173,10 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
     const Mix<double> mixd{g.G1, g.G2, g.P1, g.P2};
     const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
     const OutArgs<T> o{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg};
-    // ghost slots this lane fills: positions -2, -1, nx, nx+1 map to cells
-    const int gsrc0 = map_cell(-2, nx, g.bc[0][0], g.bc[0][1]);
-    const int gsrc1 = map_cell(-1, nx, g.bc[0][0], g.bc[0][1]);
-    const int gsrc2 = map_cell(nx, nx, g.bc[0][0], g.bc[0][1]);
-    const int gsrc3 = map_cell(nx + 1, nx, g.bc[0][0], g.bc[0][1]);
+    // ghost slots (positions -2, -1, nx, nx+1) this lane's cell fills, and
+    // which of them are reflective ghosts
+    const unsigned gneg = ghost_flips(nx, g.bc[0][0], g.bc[0][1]);
+    const unsigned gmine = has ? ghost_slots_of(x, nx, g.bc[0][0], g.bc[0][1]) : 0u;
 
     auto recon = make_recon<T, LEARNED, SCHEME>(g, mlp, has);
     double qc[NV];
@@ -189,14 +192,15 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
         if (has) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) P[v * np + x + 2] = w[v];
-            // ghost slots: one branch per slot (at most four lanes take them)
+            // ghost slots: at most four lanes take them, one test per lane
             const int gslot[4] = {0, 1, nx + 2, nx + 3};
-            const int gsrc[4] = {gsrc0, gsrc1, gsrc2, gsrc3};
+            if (gmine) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (x == gsrc[k]) {
+                for (int k = 0; k < 4; ++k) {
+                    if (gmine >> k & 1u) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) P[v * np + gslot[k]] = w[v];
+                        for (int v = 0; v < NV; ++v) P[v * np + gslot[k]] = v == 2 && (gneg >> k & 1u) ? -w[v] : w[v];
+                    }
                 }
             }
         }
@@ -280,7 +284,8 @@ struct XYSink {
     long long row_z;   // first row (k * ny) of the z plane
     int nx, np, x, xc;
     bool has, alias;
-    int gsrc[4];
+    unsigned gmine;  // bit k: this lane's cell fills ghost slot k (positions -2, -1, nx, nx+1)
+    unsigned gneg;   // bit k: ghost slot k is a reflective ghost (normal velocity negated)
     T idx, eps;
     Mix<T> mix;
 
@@ -296,11 +301,14 @@ struct XYSink {
 #pragma unroll
             for (int v = 0; v < NV; ++v) P[v * np + x + 2] = w[v];
             const int gslot[4] = {0, 1, nx + 2, nx + 3};
+            if (gmine) {  // at most four lanes
 #pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                if (x == gsrc[k]) {
+                for (int k = 0; k < 4; ++k) {
+                    if (gmine >> k & 1u) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) P[v * np + gslot[k]] = w[v];
+                        for (int v = 0; v < NV; ++v)
+                            P[v * np + gslot[k]] = v == 2 && (gneg >> k & 1u) ? -w[v] : w[v];
+                    }
                 }
             }
         }
@@ -380,7 +388,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_xy(Grid g, const double* _
     const int c1 = min(c0 + seg, ny);
     const long long base_z = (long long)z * g.stride[2];
 
-    GlobalSrc src{qs, base_z + xc, g.stride[1], g.N, ny, g.bc[1][0], g.bc[1][1]};
+    GlobalSrc<1> src{qs, base_z + xc, g.stride[1], g.N, ny, g.bc[1][0], g.bc[1][1]};
     XYSink<T, MODE, SCHEME> sink{OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg},
                          lds + lay.p,
                          lds + lay.l,
@@ -394,8 +402,8 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_xy(Grid g, const double* _
                          xc,
                          has,
                          lay.alias,
-                         {map_cell(-2, nx, g.bc[0][0], g.bc[0][1]), map_cell(-1, nx, g.bc[0][0], g.bc[0][1]),
-                          map_cell(nx, nx, g.bc[0][0], g.bc[0][1]), map_cell(nx + 1, nx, g.bc[0][0], g.bc[0][1])},
+                         has ? ghost_slots_of(x, nx, g.bc[0][0], g.bc[0][1]) : 0u,
+                         ghost_flips(nx, g.bc[0][0], g.bc[0][1]),
                          (T)g.inv_dx[0],
                          (T)g.eps,
                          Mix<T>{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2}};

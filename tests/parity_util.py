@@ -85,7 +85,8 @@ def gpu_solver(spec, q0=None, w0=None, **kw):
 
 def cross_cells(spec, cells: np.ndarray, reach: int = 3) -> np.ndarray:
     """All cells within `reach` along one active axis of any cell in `cells`
-    (boundary index map applied), as sorted unique linear indices."""
+    (boundary index map applied: periodic wraps, transmissive clamps,
+    reflective mirrors), as sorted unique linear indices."""
     n = spec["n"]
     i = cells % n[0]
     j = (cells // n[0]) % n[1]
@@ -103,7 +104,8 @@ def cross_cells(spec, cells: np.ndarray, reach: int = 3) -> np.ndarray:
             if lo == 0:
                 p = np.mod(p, n[d])
             else:
-                p = np.clip(p, 0, n[d] - 1)
+                p = np.where(p < 0, -1 - p if lo == 2 else 0, p)
+                p = np.where(p >= n[d], 2 * n[d] - 1 - p if hi == 2 else n[d] - 1, p)
             q = list(pos)
             q[d] = p
             out.append((q[2] * n[1] + q[1]) * n[0] + q[0])

@@ -85,6 +85,28 @@ def test_unpaired_periodic_rejected():
     assert b"paired" in L.mfx_last_error(None)
 
 
+def test_reflective_sides_accepted_and_checked():
+    """Reflective (slip-wall) sides pass validation alone or beside a
+    transmissive side; a reflective direction with 2 cells is rejected."""
+    L = _native.lib()
+    for k in range(3):
+        for pair in ((2, 2), (2, 1), (1, 2)):
+            d = _desc()
+            d.bc[k][0], d.bc[k][1] = pair
+            assert L.mfx_workspace_bytes(ctypes.byref(d)) > 0, (k, pair)
+    d = _desc()
+    d.bc[0][0] = d.bc[0][1] = _native.MFX_BC_REFLECTIVE
+    d.n[0] = 2
+    assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0
+    ctx = ctypes.c_void_p()
+    assert L.mfx_init_grid(ctypes.byref(d), ctypes.c_void_p(256), 1 << 30, None,
+                           ctypes.byref(ctx)) == _native.MFX_EINVAL
+    assert b"reflective" in L.mfx_last_error(None)
+    d = _desc()
+    d.bc[2][1] = 3
+    assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0
+
+
 def test_small_or_misaligned_workspace_rejected():
     L = _native.lib()
     d = _desc()
