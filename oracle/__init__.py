@@ -38,6 +38,7 @@ class OrcGrid(ctypes.Structure):
         ("cfl", ctypes.c_double),
         ("weno_z", ctypes.c_int32),
         ("weno_order", ctypes.c_int32),
+        ("inflow", ((ctypes.c_double * NV) * 2) * 3),
     ]
 
 
@@ -96,9 +97,10 @@ def _dp(a: np.ndarray):
 
 def make_grid(spec: dict, weno_z: bool = False) -> OrcGrid:
     """Grid from a problem description dict (keys n, dx, bc, gamma, pinf, eps,
-    cfl, and optionally weno_order: 5 or 3, weno_z: bool).  weno_z (argument
-    or key) selects the WENO-Z weights (a comparison form) instead of
-    Jiang-Shu's."""
+    cfl, and optionally weno_order: 5 or 3, weno_z: bool, inflow: the
+    conserved ghost state [3][2][7] of inflow sides).  weno_z (argument or
+    key) selects the WENO-Z weights (a comparison form) instead of
+    Jiang-Shu's.  bc: 0 periodic, 1 transmissive, 2 reflective, 3 inflow."""
     g = OrcGrid()
     for d in range(3):
         g.n[d] = int(spec["n"][d])
@@ -115,10 +117,16 @@ def make_grid(spec: dict, weno_z: bool = False) -> OrcGrid:
         raise ValueError("weno_order must be 3 or 5")
     for d in range(3):
         kinds = (g.bc[d][0], g.bc[d][1])
-        if any(k not in (0, 1, 2) for k in kinds):
-            raise ValueError("bc must be 0 (periodic), 1 (transmissive) or 2 (reflective)")
+        if any(k not in (0, 1, 2, 3) for k in kinds):
+            raise ValueError("bc must be 0 (periodic), 1 (transmissive), 2 (reflective) or 3 (inflow)")
         if 2 in kinds and 1 < g.n[d] < 3:
             raise ValueError("a reflective side needs at least 3 cells in its direction")
+    if "inflow" in spec:
+        a = np.asarray(spec["inflow"], dtype=np.float64).reshape(3, 2, NV)
+        for d in range(3):
+            for side in range(2):
+                for v in range(NV):
+                    g.inflow[d][side][v] = float(a[d, side, v])
     return g
 
 

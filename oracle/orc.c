@@ -55,13 +55,14 @@ typedef struct {
     int32_t n[3];      /* interior cells per direction; 1 = inactive */
     double dx[3];      /* uniform spacing per direction */
     int32_t bc[3][2];  /* 0 = periodic, 1 = transmissive (zero gradient),
-                          2 = reflective (slip wall) */
+                          2 = reflective (slip wall), 3 = inflow (fixed state) */
     double gamma[2];   /* fluid 1, fluid 2 */
     double pinf[2];
     double eps;        /* WENO epsilon */
     double cfl;
     int32_t weno_z;    /* 0: Jiang-Shu weights (the paper's WENO5); 1: WENO-Z weights (comparison form) */
     int32_t weno_order; /* 5 (default; 0 reads as 5) or 3: the two orders Sec. II-B names */
+    double inflow[3][2][NV]; /* conserved state of the ghost cells of an inflow side */
 } orc_grid;
 
 /* ---------- equation of state (Sec. II-A) ---------- */
@@ -296,7 +297,10 @@ static void hllc(const orc_grid* g, const double* wl, const double* wr, int d, d
    n-1-k) and sets *flip: that ghost carries the mirrored cell's state with
    the momentum normal to the wall negated (a stationary slip wall; the
    paper names no boundary type, this is the standard ghost construction).
-   Reflective sides need n >= 3 (checked by the Python wrapper). */
+   Reflective sides need n >= 3 (checked by the Python wrapper).  An inflow
+   side sets *flip = 2: its ghosts hold the side's fixed state
+   (g->inflow[d][side]) instead of a cell's (the returned index is the
+   edge cell, a placeholder). */
 static int64_t map_index(const orc_grid* g, int d, int64_t i, int* flip)
 {
     int64_t n = g->n[d];
@@ -307,8 +311,19 @@ static int64_t map_index(const orc_grid* g, int d, int64_t i, int* flip)
         *flip = 1;
         return i < 0 ? -1 - i : 2 * n - 1 - i;
     }
+    if (t == 3) *flip = 2;
     if (i < 0) return t == 0 ? ((i % n) + n) % n : 0;
     return t == 0 ? i % n : n - 1;
+}
+
+/* Ghost state adjustment for what map_index reported: reflective ghosts
+   negate the momentum normal to the wall, inflow ghosts take the side's
+   fixed state. */
+static void ghost_state(const orc_grid* g, int d, int64_t i, int kind, double* qc)
+{
+    if (kind == 1) qc[2 + d] = -qc[2 + d];
+    if (kind == 2)
+        for (int v = 0; v < NV; ++v) qc[v] = g->inflow[d][i < 0 ? 0 : 1][v];
 }
 
 static int active(const orc_grid* g, int d) { return g->n[d] > 1; }
@@ -390,10 +405,10 @@ void orc_rhs(const orc_grid* g, const double* q, double* rhs)
                 int64_t dst = ((int64_t)k * P[1] + j) * P[0] + i;
                 double qc[NV], wc[NV];
                 for (int v = 0; v < NV; ++v) qc[v] = q[v * N + src];
-                /* reflective ghosts: normal momentum of each mirrored direction negated */
-                if (fi) qc[2] = -qc[2];
-                if (fj) qc[3] = -qc[3];
-                if (fk) qc[4] = -qc[4];
+                /* reflective and inflow ghosts, per direction */
+                ghost_state(g, 0, i - gh[0], fi, qc);
+                ghost_state(g, 1, j - gh[1], fj, qc);
+                ghost_state(g, 2, k - gh[2], fk, qc);
                 cons_to_prim(g, qc, wc);
                 for (int v = 0; v < NV; ++v) wp[v * NP + dst] = wc[v];
             }
@@ -468,7 +483,7 @@ void orc_rhs_at(const orc_grid* g, const double* q, int64_t ncell, const int64_t
                 int64_t src = p2[0] * stride_n[0] + p2[1] * stride_n[1] + p2[2] * stride_n[2];
                 double qc[NV];
                 for (int v = 0; v < NV; ++v) qc[v] = q[v * N + src];
-                if (flip) qc[2 + d] = -qc[2 + d];
+                ghost_state(g, d, pos[d] + o, flip, qc);
                 cons_to_prim(g, qc, w7[o + 3]);
             }
             double lft[3][NV], rgt[3][NV];

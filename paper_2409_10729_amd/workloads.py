@@ -28,7 +28,7 @@ import math
 
 import numpy as np
 
-PERIODIC, TRANSMISSIVE, REFLECTIVE = 0, 1, 2
+PERIODIC, TRANSMISSIVE, REFLECTIVE, INFLOW = 0, 1, 2, 3
 WATER = (4.4, 6.0e8)
 AIR = (1.4, 0.0)
 ALPHA_EPS = 1.0e-6

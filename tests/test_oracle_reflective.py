@@ -157,6 +157,6 @@ def test_reflective_needs_three_cells():
     s = wl.spec((2, 8, 8), [(R_, R_), (P_, P_), (P_, P_)])
     with pytest.raises(ValueError):
         oracle.make_grid(s)
-    s = wl.spec((8, 8, 8), [(R_, 3), (P_, P_), (P_, P_)])
+    s = wl.spec((8, 8, 8), [(R_, 4), (P_, P_), (P_, P_)])
     with pytest.raises(ValueError):
         oracle.make_grid(s)
