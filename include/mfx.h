@@ -57,8 +57,10 @@ enum {
  * must be paired; transmissive repeats the edge cell (zero gradient);
  * reflective is a stationary slip wall: the ghost cells mirror the cells
  * beside the wall face with the momentum normal to it negated, so no mass
- * or energy crosses it; it needs at least 3 cells in its direction. */
-enum { MFX_BC_PERIODIC = 0, MFX_BC_TRANSMISSIVE = 1, MFX_BC_REFLECTIVE = 2 };
+ * or energy crosses it; it needs at least 3 cells in its direction.
+ * Inflow: every ghost cell of the side holds the fixed conserved state
+ * mfx_grid_desc.inflow[direction][side]. */
+enum { MFX_BC_PERIODIC = 0, MFX_BC_TRANSMISSIVE = 1, MFX_BC_REFLECTIVE = 2, MFX_BC_INFLOW = 3 };
 
 /* Arithmetic of the reconstruction and flux passes.
  * MFX_FP64: everything in float64.
@@ -95,6 +97,10 @@ typedef struct {
     int32_t weno_order; /* reconstruction order, 5 or 3 (Sec. II-B names both; 0 reads as 5):
                            WENO3 with Jiang-Shu weights on the middle three cells of each
                            stencil; the learned and WENO-Z weights need 5 (MFX_EINVAL otherwise) */
+    double inflow[3][2][7]; /* conserved ghost state (alpha1 rho1, alpha2 rho2, rho u, rho v, rho w,
+                               rho E, alpha1) of each MFX_BC_INFLOW side [direction][lower/upper];
+                               finite, partial densities >= 0 with a positive sum, alpha1 in
+                               [0, 1] (MFX_EINVAL otherwise); ignored for other sides */
 } mfx_grid_desc;
 
 typedef struct mfx_ctx mfx_ctx;
@@ -203,8 +209,8 @@ int mfx_stats(mfx_ctx* ctx, double* t, int64_t* step, int64_t* fallback_faces, u
  * i-2..i+2 with target face_prim[v][i+1]; sample (1*7+v)*nx+i = the
  * mirrored stencil i+2..i-2 with target face_prim[v][i].  face_prim holds
  * reference primitive values at the nx+1 faces, [7][nx+1].  Outputs:
- * stencil_out[14*nx][5], target_out[14*nx] (float64).  Reflective ends are
- * rejected (MFX_EINVAL). */
+ * stencil_out[14*nx][5], target_out[14*nx] (float64).  Reflective and inflow
+ * ends are rejected (MFX_EINVAL). */
 int mfx_mlp_sample_stencils(const mfx_grid_desc* desc, const double* q_dev, const double* face_prim_dev,
                             double* stencil_out, double* target_out, void* stream);
 
@@ -212,7 +218,8 @@ int mfx_mlp_sample_stencils(const mfx_grid_desc* desc, const double* q_dev, cons
  * `refine` times finer than the sampled one (same domain and boundary
  * conditions): coarse face i lies on fine face refine*i, whose primitive
  * value is the mean of the two fine cells beside it.  face_prim_out[7][nc+1]
- * with nc = fine nx / refine.  Reflective ends are rejected (MFX_EINVAL). */
+ * with nc = fine nx / refine.  Reflective and inflow ends are rejected
+ * (MFX_EINVAL). */
 int mfx_mlp_face_targets(const mfx_grid_desc* fine_desc, const double* q_fine_dev, int32_t refine, double* face_prim_out,
                          void* stream);
 

@@ -12,12 +12,13 @@ from __future__ import annotations
 import ctypes
 
 from . import _native
-from ._native import (MFX_BC_PERIODIC, MFX_BC_REFLECTIVE, MFX_BC_TRANSMISSIVE, MFX_FP32_MIXED, MFX_FP64, MFX_WENO5_JS,
-                      MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE, MFX_WENO5_Z, MfxError)
+from ._native import (MFX_BC_INFLOW, MFX_BC_PERIODIC, MFX_BC_REFLECTIVE, MFX_BC_TRANSMISSIVE, MFX_FP32_MIXED,
+                      MFX_FP64, MFX_WENO5_JS, MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE, MFX_WENO5_Z, MfxError)
 
 __all__ = ["Solver", "MfxError", "MFX_FP64", "MFX_FP32_MIXED", "MFX_WENO5_JS", "MFX_WENO5_LEARNED",
            "MFX_WENO5_LEARNED_EDGE", "MFX_WENO5_Z",
-           "MFX_BC_PERIODIC", "MFX_BC_TRANSMISSIVE", "MFX_BC_REFLECTIVE", "workspace_bytes"]
+           "MFX_BC_PERIODIC", "MFX_BC_TRANSMISSIVE", "MFX_BC_REFLECTIVE", "MFX_BC_INFLOW",
+           "workspace_bytes"]
 
 
 def workspace_bytes(spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS) -> int:

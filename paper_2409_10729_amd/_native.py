@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmfx.so")
 
 MFX_OK, MFX_EINVAL, MFX_EHIP, MFX_ENOMEM, MFX_ESTATE = 0, -1, -2, -3, -4
-MFX_BC_PERIODIC, MFX_BC_TRANSMISSIVE, MFX_BC_REFLECTIVE = 0, 1, 2
+MFX_BC_PERIODIC, MFX_BC_TRANSMISSIVE, MFX_BC_REFLECTIVE, MFX_BC_INFLOW = 0, 1, 2, 3
 MFX_FP64, MFX_FP32_MIXED = 0, 1
 MFX_WENO5_JS, MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE, MFX_WENO5_Z = 0, 1, 2, 3
 
@@ -42,6 +42,7 @@ class GridDesc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("weights", ctypes.c_int32),
         ("weno_order", ctypes.c_int32),
+        ("inflow", ((ctypes.c_double * 7) * 2) * 3),
     ]
 
 
@@ -130,6 +131,12 @@ def make_desc(spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS
     d.precision = int(precision)
     d.weights = int(weights)
     d.weno_order = int(spec.get("weno_order", 5))
+    if "inflow" in spec:
+        a = [[list(map(float, side)) for side in pair] for pair in spec["inflow"]]
+        for k in range(3):
+            for s in range(2):
+                for v in range(7):
+                    d.inflow[k][s][v] = a[k][s][v]
     return d
 
 

@@ -56,7 +56,7 @@ Overrides read_overrides()
 }
 
 struct Layout {
-    size_t q, q1, q2, r, scal, partial, bface, mlp, mlp_params, total;
+    size_t q, q1, q2, r, scal, inflow, partial, bface, mlp, mlp_params, total;
     long long n_partial;
 };
 
@@ -71,10 +71,22 @@ struct SweepGeom {
 
 // The x sweep takes whole rows when a row fits the row kernel (nx <=
 // XROW_MAX and its LDS fits a workgroup), else it marches along x.
+// (x_mode() below sends an inflow x side with aliased row buffers to the
+// march: the row kernels write inflow ghost slots once per block.)
 bool use_xrows(const int n[3], int mode_override, size_t elem)
 {
     if (mode_override == 1) return false;
     return n[0] <= XROW_MAX && xrow_lds_bytes(n[0], elem) <= 64 * 1024;
+}
+
+// x sweep mode for a descriptor: the override, or the march (1) when an x
+// side is inflow and the row buffers would be aliased.
+int x_mode(const mfx_grid_desc* d, int xmode_override)
+{
+    const size_t elem = d->precision == MFX_FP32_MIXED ? sizeof(float) : sizeof(double);
+    const bool inflow_x = d->bc[0][0] == MFX_BC_INFLOW || d->bc[0][1] == MFX_BC_INFLOW;
+    if (inflow_x && d->n[0] <= XROW_MAX && xrow_layout(d->n[0], elem).alias) return 1;
+    return xmode_override;
 }
 
 SweepGeom sweep_geom(const int n[3], int d, int seg_override, int xmode_override, size_t elem, bool learned)
@@ -139,6 +151,8 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     off += align_up(elem * 7 * (size_t)N);
     L.scal = off;
     off += align_up(64);
+    L.inflow = off;  // the inflow ghost states [3][2][7], read by the loaders
+    off += align_up(sizeof(double) * 3 * 2 * NV);
     L.partial = off;
     off += align_up(sizeof(double) * (size_t)np);
     L.bface = off;
@@ -192,18 +206,34 @@ bool validate(const mfx_grid_desc* d, std::string& why)
             why = "dx[" + std::to_string(k) + "] must be finite and > 0";
             return false;
         }
-        for (int s = 0; s < 2; ++s)
+        for (int s = 0; s < 2; ++s) {
             if (d->bc[k][s] != MFX_BC_PERIODIC && d->bc[k][s] != MFX_BC_TRANSMISSIVE &&
-                d->bc[k][s] != MFX_BC_REFLECTIVE) {
+                d->bc[k][s] != MFX_BC_REFLECTIVE && d->bc[k][s] != MFX_BC_INFLOW) {
                 why = "bc[" + std::to_string(k) + "] holds an unknown boundary type";
                 return false;
             }
+            if (d->bc[k][s] == MFX_BC_INFLOW) {
+                const double* q = d->inflow[k][s];
+                bool ok = true;
+                for (int v = 0; v < 7; ++v) ok = ok && std::isfinite(q[v]);
+                ok = ok && q[0] >= 0.0 && q[1] >= 0.0 && q[0] + q[1] > 0.0 && q[6] >= 0.0 && q[6] <= 1.0;
+                if (!ok) {
+                    why = "inflow[" + std::to_string(k) + "][" + std::to_string(s) +
+                          "] must be finite, with partial densities >= 0, a positive density and alpha_1 in [0, 1]";
+                    return false;
+                }
+            }
+        }
         if ((d->bc[k][0] == MFX_BC_PERIODIC) != (d->bc[k][1] == MFX_BC_PERIODIC)) {
             why = "periodic boundaries must be paired (bc[" + std::to_string(k) + "])";
             return false;
         }
         if ((d->bc[k][0] == MFX_BC_REFLECTIVE || d->bc[k][1] == MFX_BC_REFLECTIVE) && d->n[k] == 2) {
             why = "a reflective side needs n[" + std::to_string(k) + "] >= 3 (the mirror of three ghost cells)";
+            return false;
+        }
+        if ((d->bc[k][0] >= MFX_BC_REFLECTIVE || d->bc[k][1] >= MFX_BC_REFLECTIVE) && d->n[k] == 1) {
+            why = "reflective and inflow sides need an active direction (n[" + std::to_string(k) + "] > 1)";
             return false;
         }
     }
@@ -638,7 +668,7 @@ size_t mfx_workspace_bytes(const mfx_grid_desc* desc)
     std::string why;
     if (!validate(desc, why)) return 0;
     const Overrides o = read_overrides();
-    return make_layout(desc, o.seg, o.xmode).total;
+    return make_layout(desc, o.seg, x_mode(desc, o.xmode)).total;
 }
 
 int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void* hip_stream, mfx_ctx** out)
@@ -654,7 +684,8 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
         return fail(nullptr, MFX_EINVAL, "workspace must be 256-byte aligned");
 
     const Overrides ov = read_overrides();
-    Layout L = make_layout(desc, ov.seg, ov.xmode);
+    const int xmode = x_mode(desc, ov.xmode);
+    Layout L = make_layout(desc, ov.seg, xmode);
     if (ws_bytes < L.total)
         return fail(nullptr, MFX_ENOMEM, "workspace has " + std::to_string(ws_bytes) + " bytes, needs " +
                                              std::to_string(L.total));
@@ -664,7 +695,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     c->desc = *desc;
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->seg_override = ov.seg;
-    c->xmode_override = ov.xmode;
+    c->xmode_override = xmode;
     c->fuse_xy = ov.fuse_xy != 0;
     c->fuse_cfl = ov.fuse_cfl != 0;
 
@@ -701,9 +732,12 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
         g.inv_dx[k] = 1.0 / desc->dx[k];
         g.bc[k][0] = desc->bc[k][0];
         g.bc[k][1] = desc->bc[k][1];
+        for (int s = 0; s < 2; ++s)
+            for (int v = 0; v < NV; ++v) g.inflow[k][s][v] = desc->bc[k][s] == MFX_BC_INFLOW ? desc->inflow[k][s][v] : 0.0;
         g.active[k] = desc->n[k] > 1;
         if (g.active[k]) c->dirs[c->ndirs++] = k;
     }
+    g.inflow_dev = reinterpret_cast<const double*>(c->ws + L.inflow);
     if (c->ndirs == 0) c->dirs[c->ndirs++] = 0;  // a single cell still sweeps x (all faces from ghosts)
     g.G1 = 1.0 / (desc->gamma[0] - 1.0);
     g.G2 = 1.0 / (desc->gamma[1] - 1.0);
@@ -716,6 +750,14 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     if (hipMemsetAsync(c->ws + L.scal, 0, 64, c->stream) != hipSuccess) {
         delete c;
         return fail(nullptr, MFX_EHIP, "hipMemsetAsync of the scalar block failed");
+    }
+    // the inflow states for the loaders (zero for other sides); the source
+    // lives in the context
+    if (hipMemcpyAsync(c->ws + L.inflow, &g.inflow[0][0][0], sizeof(double) * 3 * 2 * NV, hipMemcpyHostToDevice,
+                       c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        delete c;
+        return fail(nullptr, MFX_EHIP, "copy of the inflow states failed");
     }
     c->has_state = false;
     c->profiling = false;

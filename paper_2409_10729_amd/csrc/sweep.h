@@ -30,7 +30,7 @@
 
 namespace mfx {
 
-enum : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2 };
+enum : int { BC_PERIODIC = 0, BC_TRANSMISSIVE = 1, BC_REFLECTIVE = 2, BC_INFLOW = 3 };
 
 // What the pass does with the accumulated right-hand side of a cell.
 enum : int {
@@ -53,15 +53,19 @@ struct Grid {
     double eps;
     double cfl;
     int edge_weights;  // learned weights: one network evaluation per edge for all variables
+    double inflow[3][2][NV];  // conserved state of the ghost cells of an inflow side
+    const double* inflow_dev; // the same states in device memory, [3][2][NV]
 };
 
 // Cell whose state stencil position c takes.  Ghost positions (outside
 // 0..n-1): periodic wraps around, transmissive repeats the edge cell,
 // reflective mirrors about the wall face (-1-k <- k, n+k <- n-1-k; the three
 // ghosts a stencil reaches need n >= 3) and the ghost carries the mirrored
-// cell with its momentum normal to the wall negated (see mirrored()), a
-// stationary slip wall.  Positions further out (the marching x sweep stages
-// whole chunks, up to n+5) are clamped into the row; no stencil uses them.
+// cell with its momentum normal to the wall negated (see ghost_fix()), a
+// stationary slip wall.  An inflow ghost holds the side's fixed state; the
+// map returns the edge cell as a placeholder load (see ghost_fix()).
+// Positions further out (the marching x sweep stages whole chunks, up to
+// n+5) are clamped into the row; no stencil uses them.
 __device__ __forceinline__ int map_cell(int c, int n, int bclo, int bchi)
 {
     if (c < 0) return bclo == BC_PERIODIC ? ((c % n) + n) % n : (bclo == BC_REFLECTIVE ? min(-1 - c, n - 1) : 0);
@@ -69,19 +73,28 @@ __device__ __forceinline__ int map_cell(int c, int n, int bclo, int bchi)
     return c;
 }
 
-// True when stencil position c is a ghost of a reflective side: its normal
-// momentum (normal velocity) enters negated.
-__device__ __forceinline__ bool mirrored(int c, int n, int bclo, int bchi)
+// Sides whose ghosts are not a plain copy of a cell: reflective and inflow.
+__device__ __forceinline__ bool special_side(int bc) { return bc == BC_REFLECTIVE || bc == BC_INFLOW; }
+
+// Ghost slots of the x-row kernels taking the inflow state: bit k set when
+// slot k (positions -2, -1, n, n+1) lies on an inflow side.
+__device__ __forceinline__ unsigned ghost_inflow(int bclo, int bchi)
 {
-    return (c < 0 && bclo == BC_REFLECTIVE) || (c >= n && bchi == BC_REFLECTIVE);
+    return (bclo == BC_INFLOW ? 3u : 0u) | (bchi == BC_INFLOW ? 12u : 0u);
 }
 
-// Ghost slots of the x-row kernels (positions -2, -1, n, n+1): bit k is set
-// when slot k is a reflective ghost.
-__device__ __forceinline__ unsigned ghost_flips(int n, int bclo, int bchi)
+// Ghost slots of the x-row kernels on a reflective side.
+__device__ __forceinline__ unsigned ghost_reflect(int bclo, int bchi)
 {
     return (bclo == BC_REFLECTIVE ? 3u : 0u) | (bchi == BC_REFLECTIVE ? 12u : 0u);
 }
+
+// True when stencil position c is a ghost of a reflective or inflow side.
+__device__ __forceinline__ bool special_ghost(int c, int n, int bclo, int bchi)
+{
+    return (c < 0 && special_side(bclo)) || (c >= n && special_side(bchi));
+}
+
 
 // Ghost slots of the x-row kernels that cell x fills: bit k set when slot k
 // (positions -2, -1, n, n+1) takes cell x's state.
@@ -219,6 +232,25 @@ __device__ __forceinline__ void prim_of(const Mix<double>& mix, const double q[N
     cons_to_prim(mix, q, wd);
 #pragma unroll
     for (int v = 0; v < NV; ++v) w[v] = (T)wd[v];
+}
+
+// Primitives w of a reflective or inflow ghost at position pos (outside the
+// row, on the side pos names), given the primitives of the cell the index
+// map loaded for it: a reflective ghost negates the normal velocity (the
+// same bits as negating the momentum before the conversion), an inflow
+// ghost takes the side's fixed state.
+template <int DIR, typename T>
+__device__ __forceinline__ void ghost_fix(const Grid& g, const Mix<double>& mixd, int pos, int bclo, int bchi, T w[NV])
+{
+    const int side = pos < 0 ? 0 : 1;
+    if ((side ? bchi : bclo) == BC_REFLECTIVE) {
+        w[2 + DIR] = -w[2 + DIR];
+    } else {
+        double qi[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) qi[v] = g.inflow[DIR][side][v];
+        prim_of<T>(mixd, qi, w);
+    }
 }
 
 // Sink of the y and z sweeps: each lane writes its own cell (lanes are
@@ -637,20 +669,28 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
 template <int DIR>
 struct GlobalSrc {
     const double* __restrict__ qs;
+    const double* inf;  // device copy of this direction's inflow states [2][NV] (required)
     long long base, sd, N;
     int n, bclo, bchi;
-    // positions below flo or at/above fhi are reflective ghosts
+    // inflow ghosts: positions below ilo or at/above ihi; reflective ghosts:
+    // below flo or at/above fhi
+    int ilo = bclo == BC_INFLOW ? 0 : INT_MIN;
+    int ihi = bchi == BC_INFLOW ? n : INT_MAX;
     int flo = bclo == BC_REFLECTIVE ? 0 : INT_MIN;
     int fhi = bchi == BC_REFLECTIVE ? n : INT_MAX;
+    // An inflow ghost reads the side's state instead of a cell: only the
+    // (wave-uniform) base pointer and stride of the same loads change.
     __device__ __forceinline__ void load(int pos, double q[NV]) const
     {
-        const long long off = base + (long long)map_cell(pos, n, bclo, bchi) * sd;
+        const bool lo = pos < ilo, hi = pos >= ihi;
+        const double* p = lo ? inf : (hi ? inf + NV : qs + base + (long long)map_cell(pos, n, bclo, bchi) * sd);
+        const long long st = (lo || hi) ? 1 : N;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) q[v] = qs[v * N + off];
+        for (int v = 0; v < NV; ++v) q[v] = p[v * st];
     }
     // A reflective ghost enters with its normal velocity negated; applied to
-    // the primitives where they are used (the same bits as negating the
-    // momentum before the conversion), so the load stays in flight until then.
+    // the primitives where the march uses them (the same bits as negating
+    // the momentum before the conversion), so the load stays in flight.
     template <typename T>
     __device__ __forceinline__ void finish(int pos, T w[NV]) const
     {
@@ -704,7 +744,7 @@ __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 2 : 1) sweep_yz
     const long long base = (long long)i + (long long)blockIdx.y * g.stride[SA];
     const int c0 = blockIdx.z * seg;
     const int c1 = min(c0 + seg, n);
-    GlobalSrc<DIR> src{qs, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
+    GlobalSrc<DIR> src{qs, g.inflow_dev + DIR * 2 * NV, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
     GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CFL, !LEARNED> sink{
         OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid, CflAcc{0.0, 0u}};
     auto recon = make_recon<T, LEARNED, SCHEME, BLOCK / 64>(g, mlp, valid);
@@ -733,6 +773,7 @@ constexpr int XCHUNK = 4;
 struct LdsSrc {
     double (*buf)[NV][XROWS];  // [XCHUNK][NV][XROWS]
     const double* __restrict__ qs;
+    const double* inf;  // device copy of the x inflow states [2][NV] (required)
     long long N;
     long long row0;  // first row of the block
     long long nrows;
@@ -749,21 +790,35 @@ struct LdsSrc {
                 const int item = threadIdx.x + it * XROWS;
                 const int r = item / XCHUNK, cx = item % XCHUNK;
                 const long long row = min(row0 + r, nrows - 1);
-                const long long off = row * nx + map_cell(pos + cx, nx, bclo, bchi);
-                const double sgn = mirrored(pos + cx, nx, bclo, bchi) ? -1.0 : 1.0;
+                // inflow ghosts read the side's state (base pointer and stride)
+                const int pp = pos + cx;
+                const bool lo = pp < ilo, hi = pp >= ihi;
+                const double* p = lo ? inf : (hi ? inf + NV : qs + row * nx + map_cell(pp, nx, bclo, bchi));
+                const long long st = (lo || hi) ? 1 : N;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) buf[cx][v][r] = v == 2 ? sgn * qs[v * N + off] : qs[v * N + off];
+                for (int v = 0; v < NV; ++v) buf[cx][v][r] = p[v * st];
             }
             __syncthreads();
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) q[v] = buf[slot][v][threadIdx.x];
     }
-    // reflective ghosts are flipped while staging
+    int ilo = bclo == BC_INFLOW ? 0 : INT_MIN;
+    int ihi = bchi == BC_INFLOW ? nx : INT_MAX;
+    // every lane marches at the same x position: reflective ghosts are
+    // fixed on the primitives as in GlobalSrc
+    int flo = bclo == BC_REFLECTIVE ? 0 : INT_MIN;
+    int fhi = bchi == BC_REFLECTIVE ? nx : INT_MAX;
     template <typename T>
-    __device__ __forceinline__ void finish(int, T*) const {}
+    __device__ __forceinline__ void finish(int pos, T w[NV]) const
+    {
+        if (pos < flo || pos >= fhi) w[2] = -w[2];
+    }
     template <typename T>
-    __device__ __forceinline__ void finish_ahead(int, T*) const {}
+    __device__ __forceinline__ void finish_ahead(int pos, T w[NV]) const
+    {
+        if (pos >= fhi) w[2] = -w[2];
+    }
 };
 
 template <typename T, bool FIRST, int MODE>
@@ -816,7 +871,7 @@ __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* 
     const int c0 = blockIdx.z * seg;
     const int c1 = min(c0 + seg, nx);
 
-    LdsSrc src{ibuf, qs, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
+    LdsSrc src{ibuf, qs, g.inflow_dev, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
     LdsSink<T, FIRST, MODE> sink{obuf, OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx,
                                  c0, c1};
     auto recon = make_recon<T, LEARNED, SCHEME, XROWS / 64>(g, mlp, row0 + threadIdx.x < nrows);

@@ -78,9 +78,7 @@ __global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __
                 for (int v = 0; v < NV; ++v) q[v] = qs[v * g.N + row * nx + cell];
                 prim_of<T>(mixd, q, w[k]);
             }
-            // reflective ghost: normal velocity negated (the same bits as
-            // converting the state with its momentum negated)
-            if (mirrored(pos, nx, blo, bhi)) w[k][2] = -w[k][2];
+            if (special_ghost(pos, nx, blo, bhi)) ghost_fix<0, T>(g, mixd, pos, blo, bhi, w[k]);
         }
         // right edge of the cell before the face (window w[0..4]) and left
         // edge of the cell after it (window w[1..5])
@@ -137,6 +135,41 @@ __host__ __device__ inline XrowLayout xrow_layout(int nx, size_t elem)
 
 inline size_t xrow_lds_bytes(int nx, size_t elem) { return elem * xrow_layout(nx, elem).elems; }
 
+// Ghost slot of the row buffer (p = P + slot, stride np between variables)
+// filled, row by row, by the lane whose cell the index map names: a copy of
+// its primitives w, with the normal velocity negated on a reflective side.
+template <typename T>
+__device__ __forceinline__ void put_ghost_slot(T* p, int np, const T w[NV], unsigned refl)
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) p[v * np] = v == 2 && refl ? -w[v] : w[v];
+}
+
+// Ghost slots of an inflow side hold the primitives of the side's state for
+// every row: written once per block (mask: the inflow slots this lane
+// owns).  Only the unaliased row buffer keeps them between rows; the host
+// sends rows that need the aliased layout and have an inflow x side to the
+// marching x sweep.
+template <typename T>
+__device__ __forceinline__ void inflow_slots_init(const Grid& g, const Mix<double>& mixd, unsigned mask, T* P, int np,
+                                                  int nx)
+{
+    if (!mask) return;
+#pragma unroll 1
+    for (int s = 0; s < 2; ++s) {
+        if ((mask >> (2 * s)) & 3u) {
+            double qi[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) qi[v] = g.inflow[0][s][v];
+            T wi[NV];
+            prim_of<T>(mixd, qi, wi);
+            const int slot0 = s == 0 ? 0 : nx + 2;
+#pragma unroll
+            for (int v = 0; v < NV; ++v) P[v * np + slot0] = P[v * np + slot0 + 1] = wi[v];
+        }
+    }
+}
+
 // Window of cell x inside the row's primitives in LDS: w(k, v) = P[v][x + k]
 // (cell x-2+k; ghost slots included).
 template <typename T>
@@ -173,10 +206,13 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
     const Mix<double> mixd{g.G1, g.G2, g.P1, g.P2};
     const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
     const OutArgs<T> o{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg};
-    // ghost slots (positions -2, -1, nx, nx+1) this lane's cell fills, and
-    // which of them are reflective ghosts
-    const unsigned gneg = ghost_flips(nx, g.bc[0][0], g.bc[0][1]);
-    const unsigned gmine = has ? ghost_slots_of(x, nx, g.bc[0][0], g.bc[0][1]) : 0u;
+    // ghost slots (positions -2, -1, nx, nx+1) this lane's cell fills, which
+    // of them are reflective ghosts, and the inflow slots (written once)
+    const unsigned gref = ghost_reflect(g.bc[0][0], g.bc[0][1]);
+    const unsigned ginf = ghost_inflow(g.bc[0][0], g.bc[0][1]);
+    const unsigned gall = has ? ghost_slots_of(x, nx, g.bc[0][0], g.bc[0][1]) : 0u;
+    inflow_slots_init<T>(g, mixd, gall & ginf, P, np, nx);
+    const unsigned gmine = gall & ~ginf;  // slots this lane refills every row
 
     auto recon = make_recon<T, LEARNED, SCHEME>(g, mlp, has);
     double qc[NV];
@@ -197,10 +233,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
             if (gmine) {
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    if (gmine >> k & 1u) {
-#pragma unroll
-                        for (int v = 0; v < NV; ++v) P[v * np + gslot[k]] = v == 2 && (gneg >> k & 1u) ? -w[v] : w[v];
-                    }
+                    if (gmine >> k & 1u) put_ghost_slot<T>(P + gslot[k], np, w, gref >> k & 1u);
                 }
             }
         }
@@ -285,7 +318,7 @@ struct XYSink {
     int nx, np, x, xc;
     bool has, alias;
     unsigned gmine;  // bit k: this lane's cell fills ghost slot k (positions -2, -1, nx, nx+1)
-    unsigned gneg;   // bit k: ghost slot k is a reflective ghost (normal velocity negated)
+    unsigned gref;   // bit k: ghost slot k is on a reflective side (normal velocity negated)
     T idx, eps;
     Mix<T> mix;
 
@@ -304,11 +337,7 @@ struct XYSink {
             if (gmine) {  // at most four lanes
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    if (gmine >> k & 1u) {
-#pragma unroll
-                        for (int v = 0; v < NV; ++v)
-                            P[v * np + gslot[k]] = v == 2 && (gneg >> k & 1u) ? -w[v] : w[v];
-                    }
+                    if (gmine >> k & 1u) put_ghost_slot<T>(P + gslot[k], np, w, gref >> k & 1u);
                 }
             }
         }
@@ -388,7 +417,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_xy(Grid g, const double* _
     const int c1 = min(c0 + seg, ny);
     const long long base_z = (long long)z * g.stride[2];
 
-    GlobalSrc<1> src{qs, base_z + xc, g.stride[1], g.N, ny, g.bc[1][0], g.bc[1][1]};
+    GlobalSrc<1> src{qs, g.inflow_dev + 1 * 2 * NV, base_z + xc, g.stride[1], g.N, ny, g.bc[1][0], g.bc[1][1]};
     XYSink<T, MODE, SCHEME> sink{OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg},
                          lds + lay.p,
                          lds + lay.l,
@@ -402,11 +431,14 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_xy(Grid g, const double* _
                          xc,
                          has,
                          lay.alias,
-                         has ? ghost_slots_of(x, nx, g.bc[0][0], g.bc[0][1]) : 0u,
-                         ghost_flips(nx, g.bc[0][0], g.bc[0][1]),
+                         (has ? ghost_slots_of(x, nx, g.bc[0][0], g.bc[0][1]) : 0u) & ~ghost_inflow(g.bc[0][0], g.bc[0][1]),
+                         ghost_reflect(g.bc[0][0], g.bc[0][1]),
                          (T)g.inv_dx[0],
                          (T)g.eps,
                          Mix<T>{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2}};
+    inflow_slots_init<T>(g, Mix<double>{g.G1, g.G2, g.P1, g.P2},
+                         (has ? ghost_slots_of(x, nx, g.bc[0][0], g.bc[0][1]) : 0u) & ghost_inflow(g.bc[0][0], g.bc[0][1]),
+                         lds + lay.p, nx + 4, nx);
     ReconJS<T, SCHEME> recon{};
     RegWindow<T> W;
     march<1, T>(g, src, sink, recon, c0, c1, W);

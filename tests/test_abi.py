@@ -107,6 +107,45 @@ def test_reflective_sides_accepted_and_checked():
     assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0
 
 
+def test_inflow_sides_accepted_and_checked():
+    """An inflow side needs a valid conserved ghost state: finite, partial
+    densities >= 0 with a positive sum, alpha_1 in [0, 1]."""
+    L = _native.lib()
+    good = [1.0, 1.2, 10.0, 0.0, 0.0, 3.0e5, 0.5]
+    for k in range(3):
+        for pair in ((3, 1), (1, 3), (3, 3), (3, 2)):
+            d = _desc()
+            d.bc[k][0], d.bc[k][1] = pair
+            for s in range(2):
+                for v in range(7):
+                    d.inflow[k][s][v] = good[v]
+            assert L.mfx_workspace_bytes(ctypes.byref(d)) > 0, (k, pair)
+    for v, bad in ((0, -1.0), (6, 1.5), (5, float("nan")), (1, float("inf"))):
+        d = _desc()
+        d.bc[0][0] = _native.MFX_BC_INFLOW
+        for u in range(7):
+            d.inflow[0][0][u] = good[u]
+        d.inflow[0][0][v] = bad
+        assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0, (v, bad)
+        ctx = ctypes.c_void_p()
+        assert L.mfx_init_grid(ctypes.byref(d), ctypes.c_void_p(256), 1 << 30, None,
+                               ctypes.byref(ctx)) == _native.MFX_EINVAL
+        assert b"inflow" in L.mfx_last_error(None)
+    # the state of a side that is not inflow is ignored
+    d = _desc()
+    d.inflow[1][0][0] = float("nan")
+    assert L.mfx_workspace_bytes(ctypes.byref(d)) > 0
+    # reflective and inflow sides need an active direction
+    for kind in (_native.MFX_BC_REFLECTIVE, _native.MFX_BC_INFLOW):
+        d = _desc()
+        d.n[2] = 1
+        d.bc[2][0] = d.bc[2][1] = kind
+        for s in range(2):
+            for v in range(7):
+                d.inflow[2][s][v] = good[v]
+        assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0
+
+
 def test_small_or_misaligned_workspace_rejected():
     L = _native.lib()
     d = _desc()

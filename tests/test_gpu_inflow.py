@@ -1,0 +1,130 @@
+"""Inflow (fixed ghost state) boundaries on the HIP path against the
+oracle, through the C ABI.
+
+Covers every kernel that builds ghost cells, as for the reflective sides:
+the y and z loaders, the ghost slots of the fused x-y pass and of the x-row
+kernel (the inflow primitives converted once per block into LDS), the
+marching x sweep, and the x boundary faces with and without anchor cells.
+Inflow sides are mixed with reflective and transmissive ones.  Bar: FP64
+relative 1e-12; the float form 1e-5 of the flux scale.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2409_10729_amd import MFX_FP32_MIXED, MFX_WENO5_JS, MFX_WENO5_LEARNED
+from paper_2409_10729_amd import workloads as wl
+from parity_util import TOL, gpu_solver, oracle_step_at, rel_linf, rhs_rel_linf, sample_cells
+
+pytestmark = pytest.mark.gpu
+
+P_, T_, R_, I_ = wl.PERIODIC, wl.TRANSMISSIVE, wl.REFLECTIVE, wl.INFLOW
+
+CASES = [
+    ((37, 29, 23), ((I_, T_), (R_, I_), (I_, I_)), 70),  # fused x-y pass, z
+    ((5, 40, 33), ((I_, I_), (P_, P_), (T_, I_)), 71),   # rows under 6 cells: faces without anchors
+    ((600, 3, 4), ((I_, R_), (I_, T_), (R_, I_)), 72),   # marching x sweep
+    ((420, 6, 3), ((T_, I_), (P_, P_), (I_, R_)), 73),   # long rows: aliased row buffers
+    ((3, 70, 9), ((I_, T_), (T_, I_), (P_, P_)), 74),
+    ((64, 48, 1), ((I_, R_), (I_, I_), (P_, P_)), 75),   # x-y plane: the fused pass is the last
+]
+
+
+def _report(name, err):
+    print(f"{name}: relLinf per field = " + " ".join(f"{e:.2e}" for e in err), flush=True)
+
+
+def _inflow_states(seed):
+    """Conserved states [3][2][7] of random valid primitive states (air with
+    some water, moving in any direction)."""
+    rng = np.random.default_rng(seed)
+    g1 = oracle.make_grid(wl.spec((1, 1, 1), ((P_, P_),) * 3))
+    out = np.zeros((3, 2, 7))
+    for d in range(3):
+        for s in range(2):
+            a1 = rng.uniform(0.0, 0.3)
+            w = np.array([a1 * 1000.0, (1 - a1) * rng.uniform(1.0, 4.0), rng.uniform(-80, 80),
+                          rng.uniform(-80, 80), rng.uniform(-80, 80), rng.uniform(0.8e5, 3e5), a1])
+            out[d, s] = oracle.prim_to_cons(g1, w.reshape(7, 1, 1, 1)).reshape(7)
+    return out
+
+
+def _setup(n, bc, seed):
+    P = wl.random_smooth(n=n, seed=seed, bc=bc)
+    spec = dict(P["spec"], inflow=_inflow_states(seed))
+    g = oracle.make_grid(spec)
+    return P, spec, g, oracle.prim_to_cons(g, P["w"])
+
+
+@pytest.mark.parametrize("mode", ["default", "separate_xy", "march"])
+@pytest.mark.parametrize("n,bc,seed", CASES)
+def test_inflow_rhs_and_step_match_oracle(monkeypatch, n, bc, seed, mode):
+    if mode == "separate_xy":
+        monkeypatch.setenv("MFX_FUSE_XY", "0")
+    elif mode == "march":
+        monkeypatch.setenv("MFX_XSWEEP", "march")
+    P, spec, g, q0 = _setup(n, bc, seed)
+    s = gpu_solver(spec, q0=q0)
+    r_ref = oracle.rhs(g, q0)
+    err = rhs_rel_linf(s.rhs().cpu().numpy(), r_ref, q0, spec)
+    _report(f"inflow rhs {n} {mode}", err)
+    assert np.all(err <= TOL), err
+    dt = s.rk3_step(sync=True)
+    assert dt == pytest.approx(oracle.cfl_dt(g, q0), rel=1e-15)
+    cells = sample_cells(spec, 300, seed=seed, q0=q0)
+    ref = oracle_step_at(spec, q0, cells, dt)
+    err = rel_linf(s.get_state().cpu().numpy().reshape(7, -1)[:, cells], ref)
+    _report(f"inflow step {n} {mode}", err)
+    assert np.all(err <= TOL), err
+    s32 = gpu_solver(spec, q0=q0, precision=MFX_FP32_MIXED)
+    err32 = rhs_rel_linf(s32.rhs().cpu().numpy(), r_ref, q0, spec)
+    assert np.all(err32 <= 1e-5), err32
+
+
+def test_shock_driven_through_an_inflow_side():
+    """The shock droplet with its x-lower side held at the post-shock state
+    (the shock keeps being driven), walls in y and z: 8 steps against the
+    oracle's whole-grid run."""
+    P = wl.shock_droplet(n=(48, 40, 36), seed=1)
+    g0 = oracle.make_grid(P["spec"])
+    q_post = oracle.prim_to_cons(g0, P["w"])[:, 0, 0, 0]  # the left edge holds the post-shock state
+    inflow = np.zeros((3, 2, 7))
+    inflow[0, 0] = q_post
+    spec = dict(P["spec"], bc=((I_, T_), (R_, R_), (R_, R_)), inflow=inflow)
+    g = oracle.make_grid(spec)
+    q0 = oracle.prim_to_cons(g, P["w"])
+    s = gpu_solver(spec, q0=q0)
+    for _ in range(8):
+        s.rk3_step()
+    q = s.get_state().cpu().numpy()
+    q_ref, _ = oracle.run(g, q0, 8)
+    err = rel_linf(q, q_ref)
+    _report("shock droplet, inflow x-lower, x8", err)
+    assert np.all(err <= TOL), err
+
+
+def test_learned_zero_output_layer_matches_js_with_inflow():
+    """The learned kernels build ghosts through the same loaders and slots:
+    with a zero output layer the run tracks the Jiang-Shu float run."""
+    import torch
+
+    from paper_2409_10729_amd import Solver, learned
+
+    P = wl.shock_droplet(n=(40, 24, 20), seed=2)
+    spec = dict(P["spec"], bc=((I_, T_), (I_, R_), (T_, I_)), inflow=_inflow_states(5))
+
+    def solver(weights, params=None):
+        s = Solver(spec, precision=MFX_FP32_MIXED, weights=weights)
+        if params is not None:
+            s.set_mlp(torch.from_numpy(np.ascontiguousarray(params, dtype=np.float32)).cuda())
+        s.set_primitive(torch.from_numpy(P["w"]).cuda())
+        return s
+
+    s_l = solver(MFX_WENO5_LEARNED, learned.init_params(1))
+    s_j = solver(MFX_WENO5_JS)
+    for _ in range(3):
+        s_l.rk3_step(2e-7)
+        s_j.rk3_step(2e-7)
+    d = rel_linf(s_l.get_state().cpu().numpy(), s_j.get_state().cpu().numpy())
+    print("learned (zero output layer) vs JS, inflow sides:", d, flush=True)
+    assert np.all(d <= 1e-4)
