@@ -30,9 +30,12 @@ class Solver:
     """One mfx context on the current CUDA(HIP) device.
 
     ``spec`` is a problem description (n, dx, bc, gamma, pinf, eps, cfl, and
-    optionally weno_order 5 or 3) as produced by
-    :mod:`paper_2409_10729_amd.workloads`.  Arrays passed in and
-    out are torch tensors on the device, float64, shape [7, nz, ny, nx].
+    optionally weno_order 5 or 3, and inflow: the conserved ghost state
+    [3][2][7] of MFX_BC_INFLOW sides) as produced by
+    :mod:`paper_2409_10729_amd.workloads`.  bc per direction and side:
+    MFX_BC_PERIODIC, MFX_BC_TRANSMISSIVE, MFX_BC_REFLECTIVE or MFX_BC_INFLOW.
+    Arrays passed in and out are torch tensors on the device, float64,
+    shape [7, nz, ny, nx].
     """
 
     def __init__(self, spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS, stream=None):

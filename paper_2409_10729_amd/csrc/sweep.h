@@ -61,9 +61,10 @@ struct Grid {
 // 0..n-1): periodic wraps around, transmissive repeats the edge cell,
 // reflective mirrors about the wall face (-1-k <- k, n+k <- n-1-k; the three
 // ghosts a stencil reaches need n >= 3) and the ghost carries the mirrored
-// cell with its momentum normal to the wall negated (see ghost_fix()), a
-// stationary slip wall.  An inflow ghost holds the side's fixed state; the
-// map returns the edge cell as a placeholder load (see ghost_fix()).
+// cell with its momentum normal to the wall negated (the loaders' finish(),
+// the x-row ghost slots, ghost_fix()), a stationary slip wall.  An inflow
+// ghost holds the side's fixed state: the loaders read it from the device
+// copy instead, and the map's edge cell is only a placeholder.
 // Positions further out (the marching x sweep stages whole chunks, up to
 // n+5) are clamped into the row; no stencil uses them.
 __device__ __forceinline__ int map_cell(int c, int n, int bclo, int bchi)
