@@ -38,6 +38,8 @@ WORKLOADS = {
     "droplet_cloud": ("Mach-2 air shock on 32 seeded water droplets (R log-uniform 0.02-0.1), 1% density noise, "
                       "x transmissive / y,z periodic", 384),
     "advected_bubble": ("air bubble advected through water at u=(1,0.5,0.25), periodic", 128),
+    "shock_droplet_walls": ("Mach-2 air shock on a water droplet (R=0.15), 1% density noise, x inflow at the "
+                            "post-shock state / transmissive, y,z reflective walls", 256),
 }
 
 
@@ -190,6 +192,10 @@ def main():
         return
     print(f"[bench] generating {args.workload} n={args.n} seed={args.seed}", file=sys.stderr, flush=True)
     P = getattr(wl, args.workload)(n=args.n, seed=args.seed)
+    if "inflow_prim" in P:
+        from paper_2409_10729_amd import inflow_states
+
+        P["spec"] = dict(P["spec"], inflow=inflow_states(P["spec"], P["inflow_prim"]))
     N = args.n ** 3
     w_dev = torch.from_numpy(P["w"]).cuda()
 
@@ -384,8 +390,15 @@ def main():
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
         import oracle
 
-        q_ic = oracle.prim_to_cons(oracle.make_grid(P["spec"]), P["w"])
-        cb = cpu_baseline(P, q_ic, args.cpu_budget)
+        P_cpu = dict(P)
+        if "inflow_prim" in P:  # the oracle converts the inflow states itself
+            one = {k: v for k, v in P["spec"].items() if k != "inflow"}
+            g1 = oracle.make_grid(dict(one, n=(1, 1, 1), bc=((0, 0),) * 3))
+            conv = [[oracle.prim_to_cons(g1, np.asarray(w7, dtype=np.float64).reshape(7, 1, 1, 1)).reshape(7)
+                     for w7 in pair] for pair in P["inflow_prim"]]
+            P_cpu["spec"] = dict(one, inflow=np.array(conv))
+        q_ic = oracle.prim_to_cons(oracle.make_grid(P_cpu["spec"]), P["w"])
+        cb = cpu_baseline(P_cpu, q_ic, args.cpu_budget)
         out["cpu_baseline"] = cb
         out["gpu_over_cpu"] = round(cb["value"] / grind, 1)
     print(json.dumps(out), flush=True)

@@ -18,12 +18,35 @@ from ._native import (MFX_BC_INFLOW, MFX_BC_PERIODIC, MFX_BC_REFLECTIVE, MFX_BC_
 __all__ = ["Solver", "MfxError", "MFX_FP64", "MFX_FP32_MIXED", "MFX_WENO5_JS", "MFX_WENO5_LEARNED",
            "MFX_WENO5_LEARNED_EDGE", "MFX_WENO5_Z",
            "MFX_BC_PERIODIC", "MFX_BC_TRANSMISSIVE", "MFX_BC_REFLECTIVE", "MFX_BC_INFLOW",
-           "workspace_bytes"]
+           "workspace_bytes", "inflow_states"]
 
 
 def workspace_bytes(spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS) -> int:
     d = _native.make_desc(spec, precision, weights)
     return int(_native.lib().mfx_workspace_bytes(ctypes.byref(d)))
+
+
+def inflow_states(spec: dict, prim) -> "np.ndarray":
+    """Conserved ghost states [3][2][7] of inflow sides from primitive
+    states prim[3][2][7] (alpha1 rho1, alpha2 rho2, u, v, w, p, alpha1),
+    converted on the device by the library's own set_primitive on a
+    one-cell grid with the spec's fluids.  Sides whose primitive state is
+    all zero stay zero."""
+    import numpy as np
+    import torch
+
+    prim = np.asarray(prim, dtype=np.float64).reshape(3, 2, 7)
+    out = np.zeros((3, 2, 7))
+    one = dict(spec, n=(1, 1, 1), bc=((MFX_BC_PERIODIC, MFX_BC_PERIODIC),) * 3)
+    one.pop("inflow", None)
+    for d in range(3):
+        for s in range(2):
+            if not prim[d, s].any():
+                continue
+            sol = Solver(one)
+            sol.set_primitive(torch.from_numpy(prim[d, s].reshape(7, 1, 1, 1).copy()).cuda())
+            out[d, s] = sol.get_state().cpu().numpy().reshape(7)
+    return out
 
 
 class Solver:

@@ -202,6 +202,22 @@ def shock_droplet(n=256, seed=0, mach=2.0, radius=0.15, noise=0.01):
             "meta": {"centre": c.tolist(), "radius": radius, "shock_x": xs}}
 
 
+def shock_droplet_walls(n=256, seed=0, mach=2.0, radius=0.15, noise=0.01):
+    """The shock droplet in a closed channel: the x-lower side is an inflow
+    held at the post-shock air state (the shock keeps being driven), the
+    x-upper side transmissive, walls (reflective) in y and z; the same
+    initial state as shock_droplet.  The inflow state comes as primitives
+    (inflow_prim [3][2][7], zero for the other sides); each consumer
+    converts it to the conserved ghost state with its own EOS code."""
+    P = shock_droplet(n=n, seed=seed, mach=mach, radius=radius, noise=noise)
+    s = dict(P["spec"])
+    s["bc"] = ((INFLOW, TRANSMISSIVE), (REFLECTIVE, REFLECTIVE), (REFLECTIVE, REFLECTIVE))
+    rho_a2, p_a2, u_a2 = _ideal_gas_shock(mach, 1.2, 1.0e5, AIR[0])
+    prim = np.zeros((3, 2, 7))
+    prim[0, 0] = [ALPHA_EPS * 1000.0, (1.0 - ALPHA_EPS) * rho_a2, u_a2, 0.0, 0.0, p_a2, ALPHA_EPS]
+    return {"name": "shock_droplet_walls", "spec": s, "w": P["w"], "inflow_prim": prim, "meta": P["meta"]}
+
+
 def _sphere_union(n3, centres, radii, width):
     """max over spheres of _smooth_indicator(distance to centre, R, width) on
     the cell centres.  Each sphere is evaluated only on the index box within

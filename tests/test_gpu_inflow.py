@@ -128,3 +128,33 @@ def test_learned_zero_output_layer_matches_js_with_inflow():
     d = rel_linf(s_l.get_state().cpu().numpy(), s_j.get_state().cpu().numpy())
     print("learned (zero output layer) vs JS, inflow sides:", d, flush=True)
     assert np.all(d <= 1e-4)
+
+
+def test_full_size_channel_step_sampled():
+    """The 256^3 shock droplet in a channel (x inflow at the post-shock state,
+    walls in y and z), as the benchmark runs it: one CFL step on sampled
+    cells against the oracle computing them one by one.  The inflow state
+    is converted by the oracle for the oracle and by the library's own
+    conversion for the GPU run."""
+    from paper_2409_10729_amd import inflow_states
+
+    P = wl.shock_droplet_walls(n=256, seed=0)
+    g1 = oracle.make_grid(wl.spec((1, 1, 1), ((P_, P_),) * 3))
+    conv = np.array([[oracle.prim_to_cons(g1, w7.reshape(7, 1, 1, 1)).reshape(7) for w7 in pair]
+                     for pair in P["inflow_prim"]])
+    spec = dict(P["spec"], inflow=conv)
+    gpu_conv = inflow_states(P["spec"], P["inflow_prim"])
+    np.testing.assert_allclose(gpu_conv, conv, rtol=1e-15, atol=0)
+    g = oracle.make_grid(spec)
+    q0 = oracle.prim_to_cons(g, P["w"])
+    del P
+    s = gpu_solver(dict(spec, inflow=gpu_conv), q0=q0)
+    dt = s.rk3_step(sync=True)
+    assert dt == pytest.approx(oracle.cfl_dt(g, q0), rel=1e-15)
+    q = s.get_state().cpu().numpy().reshape(7, -1)
+    s.destroy()
+    cells = sample_cells(spec, 200, seed=3, q0=q0)
+    ref = oracle_step_at(spec, q0, cells, dt)
+    err = rel_linf(q[:, cells], ref)
+    _report(f"channel step 256^3 on {cells.size} cells", err)
+    assert np.all(err <= TOL), err
