@@ -27,6 +27,7 @@ CASES = [
     ((420, 6, 3), ((T_, I_), (P_, P_), (I_, R_)), 73),   # long rows: aliased row buffers
     ((3, 70, 9), ((I_, T_), (T_, I_), (P_, P_)), 74),
     ((64, 48, 1), ((I_, R_), (I_, I_), (P_, P_)), 75),   # x-y plane: the fused pass is the last
+    ((2, 5, 4), ((I_, I_), (I_, T_), (R_, I_)), 76),     # 2 cells between inflow sides
 ]
 
 
@@ -157,4 +158,21 @@ def test_full_size_channel_step_sampled():
     ref = oracle_step_at(spec, q0, cells, dt)
     err = rel_linf(q[:, cells], ref)
     _report(f"channel step 256^3 on {cells.size} cells", err)
+    assert np.all(err <= TOL), err
+
+
+def test_longest_row_between_a_wall_and_an_inflow():
+    """The largest extent a direction may have (65535 cells, marching x
+    sweep), reflective below and inflow above: three steps against the
+    oracle."""
+    P = wl.random_smooth(n=(65535, 1, 1), seed=31, bc=((R_, I_), (P_, P_), (P_, P_)))
+    spec = dict(P["spec"], inflow=_inflow_states(31))
+    g = oracle.make_grid(spec)
+    q0 = oracle.prim_to_cons(g, P["w"])
+    s = gpu_solver(spec, q0=q0)
+    dts = [s.rk3_step(sync=True) for _ in range(3)]
+    q_ref, dts_ref = oracle.run(g, q0, 3)
+    assert np.abs(np.array(dts) / dts_ref - 1).max() <= 1e-12
+    err = rel_linf(s.get_state().cpu().numpy(), q_ref)
+    _report("65535 x 1 x 1 wall|inflow, 3 steps", err)
     assert np.all(err <= TOL), err
