@@ -79,6 +79,10 @@ def lib():
         L.orc_cons_to_prim.argtypes = [gp, dp, dp]
         L.orc_rhs.argtypes = [gp, dp, dp]
         L.orc_rhs_at.argtypes = [gp, dp, ctypes.c_int64, i64p, dp]
+        L.orc_rhs_learned.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_int, dp, i64p]
+        L.orc_mlp_omega.argtypes = [dp, ctypes.c_int64, dp, dp, dp]
+        L.orc_gelu.argtypes = [ctypes.c_double]
+        L.orc_gelu.restype = ctypes.c_double
         L.orc_cfl_dt.argtypes = [gp, dp]
         L.orc_cfl_dt.restype = ctypes.c_double
         L.orc_rk3_combine.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, dp, ctypes.c_double, dp]
@@ -86,6 +90,9 @@ def lib():
         L.orc_rk3_step.restype = ctypes.c_double
         L.orc_run.argtypes = [gp, dp, ctypes.c_int, dp, dp]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_team_size.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_set_threads.restype = None
         _lib = L
     return _lib
 
@@ -163,6 +170,44 @@ def rhs_at(g: OrcGrid, q: np.ndarray, cells: np.ndarray) -> np.ndarray:
     lib().orc_rhs_at(ctypes.byref(g), _dp(q), cells.size,
                      cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out))
     return out
+
+
+LEARNED_PER_VARIABLE, LEARNED_SHARED = 1, 2
+
+
+def rhs_learned(g: OrcGrid, q: np.ndarray, theta, mode: int = LEARNED_PER_VARIABLE, plant: int = 0):
+    """Right-hand side with learned WENO weights (fifth order) as the solver
+    applies them: features of every edge's stencil (the left edge as the
+    reversed stencil's right edge), the network with bfloat16 operands,
+    omega = softmax(ln omega_JS + z), and the per-edge Jiang-Shu fallback.
+    theta: the 1347 parameters (float32 values); mode 1 per variable, 2
+    shared per edge.  Returns (rhs, fallback edges, near-threshold
+    decisions), counting the two edges of every distinct face once.
+    plant != 0 (tests only) builds in a deliberate mistake (see orc.c)."""
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32), dtype=np.float64)
+    assert th.size == 1347
+    out = np.empty_like(q)
+    counts = np.zeros(2, dtype=np.int64)
+    lib().orc_rhs_learned(ctypes.byref(g), _dp(q), _dp(th), int(mode), int(plant), _dp(out),
+                          counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
+    return out, int(counts[0]), int(counts[1])
+
+
+def mlp_omega(theta, X, base) -> np.ndarray:
+    """Weights softmax(ln base + z(X)) of single samples, the network with
+    bfloat16 operands as in rhs_learned.  X [n, 5], base [n, 3]."""
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32), dtype=np.float64)
+    X = np.ascontiguousarray(X, dtype=np.float64).reshape(-1, 5)
+    base = np.ascontiguousarray(base, dtype=np.float64).reshape(-1, 3)
+    om = np.empty((X.shape[0], 3))
+    lib().orc_mlp_omega(_dp(th), X.shape[0], _dp(X), _dp(base), _dp(om))
+    return om
+
+
+def gelu(a: float) -> float:
+    """The tanh form of GELU the learned weights use."""
+    return lib().orc_gelu(float(a))
 
 
 def cfl_dt(g: OrcGrid, q: np.ndarray) -> float:
@@ -249,3 +294,14 @@ def sound_speed(g: OrcGrid, w) -> float:
 
 def max_threads() -> int:
     return lib().orc_max_threads()
+
+
+def team_size() -> int:
+    """Threads the oracle's parallel regions actually run with."""
+    return lib().orc_team_size()
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the oracle's later parallel regions (results do not
+    depend on it)."""
+    lib().orc_set_threads(int(n))

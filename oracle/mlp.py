@@ -178,6 +178,25 @@ def init_params(seed=0, out_scale=0.0):
     return pack(p)
 
 
+def forward_bf16(theta, X, OJS):
+    """omega [n, 3] with the network evaluated as the solver's matrix cores
+    do: bfloat16 features, weights of all three layers, first-layer bias and
+    hidden activations (each rounded through float32, nearest, ties to
+    even); second- and third-layer biases as given (float32 values); sums,
+    softmax and everything else in float64."""
+    p = unpack(np.asarray(theta, dtype=np.float32).astype(np.float64))
+    r = bf16_round
+    A1 = r(X) @ r(p["W1"]).T + r(p["b1"])
+    H1 = r(gelu(A1))
+    A2 = H1 @ r(p["W2"]).T + p["b2"]
+    H2 = r(gelu(A2))
+    with np.errstate(divide="ignore"):
+        Z = H2 @ r(p["W3"]).T + p["b3"] + np.log(OJS)
+    Z = Z - Z.max(1, keepdims=True)
+    E = np.exp(Z)
+    return E / E.sum(1, keepdims=True)
+
+
 def bf16_round(x):
     """Round float64 values to bfloat16 (via float32, round to nearest even)."""
     f = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)

@@ -353,6 +353,31 @@ int orc_max_threads(void)
 #endif
 }
 
+/* Threads a parallel region of the oracle actually runs with. */
+int orc_team_size(void)
+{
+    int n = 1;
+#ifdef _OPENMP
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+#endif
+    return n;
+}
+
+/* Thread count of later parallel regions (timing only; results do not
+   depend on it). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 static int64_t ncells(const orc_grid* g) { return (int64_t)g->n[0] * g->n[1] * g->n[2]; }
 
 /* Whole-array conversions, layout [7][nz][ny][nx]. */
@@ -380,8 +405,272 @@ void orc_cons_to_prim(const orc_grid* g, const double* q, double* w)
     }
 }
 
-/* ---------- right-hand side on the whole grid ---------- */
-void orc_rhs(const orc_grid* g, const double* q, double* rhs)
+/* ---------- learned WENO weights (an addition to the paper's method) ----------
+   The paper's WENO5 (Sec. II-B) with the Jiang-Shu weights corrected by a
+   small network, as the solver applies it:
+     features of a 5-value stencil v reconstructed at its right edge, with
+     the Jiang-Shu indicators beta_k and S = beta0 + beta1 + beta2 + eps:
+       x = (beta0/S, beta1/S, beta2/S, |beta0 - beta2|/S, D^2/(S + D^2)),
+       D = v0 - 4 v1 + 6 v2 - 4 v3 + v4;
+     network 5 -> 32 -> 32 -> 3 with the tanh form of GELU,
+       GELU(a) = a (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3))) / 2,
+     giving logits z; weights omega = softmax(ln omega_JS + z) on the three
+     third-order candidates (a zero output layer is Jiang-Shu);
+     a cell's left edge is the right edge of its reversed stencil.
+   Inference precision of the method: the features, the weights of all
+   three layers, the first layer's bias and both hidden activations are
+   rounded to bfloat16 (through float32, nearest, ties to even); the second
+   and third layers' biases stay as given (float32 values); sums, softmax
+   and candidates are evaluated here in float64.
+   Two forms:
+     per variable (mode 1): every variable and edge evaluates the network on
+       its own stencil;
+     shared per edge (mode 2): one evaluation per edge for all seven
+       variables, on the componentwise maximum of their features, and the
+       baseline the network corrects is the componentwise minimum of their
+       Jiang-Shu weights, renormalised.
+   Fallback per edge: if any weight of the edge is not finite, or its
+   learned state (all seven primitives) is not admissible -- a negative
+   partial density, alpha1 outside [0, 1], (Gamma + 1) p + Pi <= 0, or a
+   non-finite value -- every variable of that edge takes its Jiang-Shu
+   value. */
+#define MLP_H 32
+
+typedef struct {
+    double W1[MLP_H][5], b1[MLP_H], W2[MLP_H][MLP_H], b2[MLP_H], W3[3][MLP_H], b3[3];
+} orc_mlp;
+
+/* float64 -> float32 -> bfloat16 (round to nearest, ties to even), back as double */
+static double bf16(double x)
+{
+    float f = (float)x;
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+    memcpy(&f, &u, 4);
+    return (double)f;
+}
+
+static double gelu_tanh(double a)
+{
+    const double c = sqrt(2.0 / 3.14159265358979323846); /* sqrt(2 / pi) */
+    return 0.5 * a * (1.0 + tanh(c * (a + 0.044715 * a * a * a)));
+}
+
+/* Parameters in the order W1[32][5], b1[32], W2[32][32], b2[32], W3[3][32],
+   b3[3], with the bfloat16 rounding of the operands applied once. */
+static void mlp_load(const double* theta, orc_mlp* m)
+{
+    int o = 0;
+    for (int j = 0; j < MLP_H; ++j)
+        for (int k = 0; k < 5; ++k) m->W1[j][k] = bf16(theta[o++]);
+    for (int j = 0; j < MLP_H; ++j) m->b1[j] = bf16(theta[o++]);
+    for (int j = 0; j < MLP_H; ++j)
+        for (int k = 0; k < MLP_H; ++k) m->W2[j][k] = bf16(theta[o++]);
+    for (int j = 0; j < MLP_H; ++j) m->b2[j] = theta[o++];
+    for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < MLP_H; ++k) m->W3[i][k] = bf16(theta[o++]);
+    for (int i = 0; i < 3; ++i) m->b3[i] = theta[o++];
+}
+
+/* Logits of one feature vector (operands in bfloat16 as above). */
+static void mlp_logits(const orc_mlp* m, const double x[5], double z[3])
+{
+    double xb[5], h1[MLP_H], h2[MLP_H];
+    for (int k = 0; k < 5; ++k) xb[k] = bf16(x[k]);
+    for (int j = 0; j < MLP_H; ++j) {
+        double a = m->b1[j];
+        for (int k = 0; k < 5; ++k) a += m->W1[j][k] * xb[k];
+        h1[j] = bf16(gelu_tanh(a));
+    }
+    for (int j = 0; j < MLP_H; ++j) {
+        double a = m->b2[j];
+        for (int k = 0; k < MLP_H; ++k) a += m->W2[j][k] * h1[k];
+        h2[j] = bf16(gelu_tanh(a));
+    }
+    for (int i = 0; i < 3; ++i) {
+        double a = m->b3[i];
+        for (int k = 0; k < MLP_H; ++k) a += m->W3[i][k] * h2[k];
+        z[i] = a;
+    }
+}
+
+/* Right-edge statistics of a stencil: features, normalised Jiang-Shu
+   weights, candidate values. */
+static void right_edge_stats(const double* v, double eps, double x[5], double ojs[3], double cand[3])
+{
+    double b[3];
+    weno5_betas(v, b);
+    const double S = b[0] + b[1] + b[2] + eps;
+    const double D = v[0] - 4.0 * v[1] + 6.0 * v[2] - 4.0 * v[3] + v[4];
+    x[0] = b[0] / S;
+    x[1] = b[1] / S;
+    x[2] = b[2] / S;
+    x[3] = fabs(b[0] - b[2]) / S;
+    x[4] = D * D / (S + D * D);
+    const double a0 = 0.1 / ((eps + b[0]) * (eps + b[0]));
+    const double a1 = 0.6 / ((eps + b[1]) * (eps + b[1]));
+    const double a2 = 0.3 / ((eps + b[2]) * (eps + b[2]));
+    const double s = a0 + a1 + a2;
+    ojs[0] = a0 / s;
+    ojs[1] = a1 / s;
+    ojs[2] = a2 / s;
+    cand[0] = (2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2]) / 6.0;
+    cand[1] = (-v[1] + 5.0 * v[2] + 2.0 * v[3]) / 6.0;
+    cand[2] = (2.0 * v[2] + 5.0 * v[3] - v[4]) / 6.0;
+}
+
+/* omega = softmax(ln base + z); returns 0 if a weight is not finite */
+static int corrected_weights(const double base[3], const double z[3], double om[3])
+{
+    double l[3], lm = -INFINITY;
+    for (int k = 0; k < 3; ++k) {
+        l[k] = log(base[k]) + z[k];
+        if (l[k] > lm) lm = l[k];
+    }
+    double s = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        om[k] = exp(l[k] - lm);
+        s += om[k];
+    }
+    int fin = 1;
+    for (int k = 0; k < 3; ++k) {
+        om[k] = om[k] / s;
+        fin = fin && isfinite(om[k]);
+    }
+    return fin;
+}
+
+/* Admissibility of an edge state w (primitives).  *near is set when a test
+   is decided by a margin another evaluation could cross: 2^-20 of the
+   stencil's magnitude (scale[v], the largest |value| of variable v's
+   stencil; float32 rounding) plus 1/32 of the spread of its candidates
+   (spread[v]; a few per cent change of the weights, as a bfloat16 rounding
+   of an operand of the network can cause). */
+static int admissible_edge(const orc_grid* g, const double w[NV], const double scale[NV], const double spread[NV],
+                           int* near)
+{
+    const double G = mix_Gamma(g, w[6]), P = mix_Pi(g, w[6]);
+    const double c2n = (G + 1.0) * w[5] + P;
+    int fin = 1;
+    for (int v = 0; v < NV; ++v) fin = fin && isfinite(w[v]);
+    const int ok = fin && w[0] >= 0.0 && w[1] >= 0.0 && w[6] >= 0.0 && w[6] <= 1.0 && c2n > 0.0;
+    double m[NV];
+    for (int v = 0; v < NV; ++v) m[v] = 0x1p-20 * scale[v] + 0x1p-5 * spread[v];
+    const double dG = fabs(fluid_Gamma(g, 0) - fluid_Gamma(g, 1)), dP = fabs(fluid_Pi(g, 0) - fluid_Pi(g, 1));
+    const double mc = 0x1p-20 * (fabs((G + 1.0) * w[5]) + fabs(P)) +
+                      fabs(G + 1.0) * m[5] + (dG * fabs(w[5]) + dP) * m[6];
+    if (fin && (fabs(w[0]) <= m[0] || fabs(w[1]) <= m[1] || fabs(w[6]) <= m[6] || fabs(w[6] - 1.0) <= m[6] ||
+                fabs(c2n) <= mc))
+        *near = 1;
+    return ok;
+}
+
+typedef struct {
+    const orc_mlp* m;
+    int mode;       /* 1 per variable, 2 shared per edge */
+    int plant;      /* tests only: a deliberate mistake (0 none), see orc_rhs_learned */
+} orc_learn;
+
+/* Both edge states of one cell (all seven variables) from its stencils
+   st[v][0..4] with learned weights.  fb[0], fb[1]: the right and left edge
+   fell back; nr[0], nr[1]: the decision was near a threshold. */
+static void learned_cell(const orc_grid* g, const orc_learn* L, double st[NV][5], double* lft, double* rgt, int fb[2],
+                         int nr[2])
+{
+    double scale[NV];
+    double jl[NV], jr[NV];
+    for (int v = 0; v < NV; ++v) {
+        weno5(st[v], g->eps, &jl[v], &jr[v]);
+        scale[v] = 0.0;
+        for (int k = 0; k < 5; ++k)
+            if (fabs(st[v][k]) > scale[v]) scale[v] = fabs(st[v][k]);
+    }
+    /* side 0: right edge (the stencil as it is); side 1: left edge (the
+       reversed stencil's right edge) */
+    double val[2][NV];
+    int fin[2] = {1, 1};
+    double X[2][NV][5], O[2][NV][3], C[2][NV][3];
+    for (int side = 0; side < 2; ++side)
+        for (int v = 0; v < NV; ++v) {
+            double sv[5];
+            for (int k = 0; k < 5; ++k) sv[k] = side == 0 ? st[v][k] : st[v][4 - k];
+            right_edge_stats(sv, g->eps, X[side][v], O[side][v], C[side][v]);
+        }
+    if (L->plant == 1) /* mistake: the left edge takes the unreversed stencil's features */
+        for (int v = 0; v < NV; ++v)
+            for (int k = 0; k < 5; ++k) X[1][v][k] = X[0][v][k];
+    for (int side = 0; side < 2; ++side) {
+        if (L->mode == 2) {
+            double f[5], base[3], z[3], om[3];
+            for (int k = 0; k < 5; ++k) {
+                f[k] = X[side][0][k];
+                for (int v = 1; v < NV; ++v)
+                    if (X[side][v][k] > f[k]) f[k] = X[side][v][k];
+            }
+            double bs = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                base[k] = O[side][0][k];
+                for (int v = 1; v < NV; ++v) {
+                    if (L->plant == 4)
+                        base[k] += O[side][v][k]; /* mistake: mean instead of minimum */
+                    else if (O[side][v][k] < base[k])
+                        base[k] = O[side][v][k];
+                }
+                bs += base[k];
+            }
+            for (int k = 0; k < 3; ++k) base[k] = base[k] / bs;
+            mlp_logits(L->m, f, z);
+            fin[side] = corrected_weights(base, z, om);
+            for (int v = 0; v < NV; ++v)
+                val[side][v] = om[0] * C[side][v][0] + om[1] * C[side][v][1] + om[2] * C[side][v][2];
+        } else {
+            for (int v = 0; v < NV; ++v) {
+                double z[3], om[3];
+                mlp_logits(L->m, X[side][v], z);
+                fin[side] = corrected_weights(O[side][v], z, om) && fin[side];
+                val[side][v] = om[0] * C[side][v][0] + om[1] * C[side][v][1] + om[2] * C[side][v][2];
+            }
+        }
+    }
+    for (int side = 0; side < 2; ++side) {
+        double spread[NV];
+        for (int v = 0; v < NV; ++v) {
+            const double* c = C[side][v];
+            spread[v] = fmax(c[0], fmax(c[1], c[2])) - fmin(c[0], fmin(c[1], c[2]));
+        }
+        nr[side] = 0;
+        const int ok = fin[side] && admissible_edge(g, val[side], scale, spread, &nr[side]);
+        fb[side] = !ok;
+        double* out = side == 0 ? rgt : lft;
+        const double* js = side == 0 ? jr : jl;
+        if (L->plant == 3) { /* mistake: fallback per variable (only the variables that fail their own test) */
+            const double* w = val[side];
+            const double c2n = (mix_Gamma(g, w[6]) + 1.0) * w[5] + mix_Pi(g, w[6]);
+            for (int v = 0; v < NV; ++v) {
+                int vok = fin[side] && isfinite(w[v]);
+                if (v == 0 || v == 1) vok = vok && w[v] >= 0.0;
+                if (v == 6) vok = vok && w[6] >= 0.0 && w[6] <= 1.0;
+                if (v == 5) vok = vok && c2n > 0.0;
+                out[v] = vok ? w[v] : js[v];
+            }
+        } else {
+            for (int v = 0; v < NV; ++v) out[v] = ok ? val[side][v] : js[v];
+        }
+    }
+    if (L->plant == 2) /* mistake: the edges exchanged */
+        for (int v = 0; v < NV; ++v) {
+            const double t = lft[v];
+            lft[v] = rgt[v];
+            rgt[v] = t;
+        }
+}
+
+/* ---------- right-hand side on the whole grid ----------
+   L: learned weights (NULL for the grid's own reconstruction); counts[0]
+   receives the edges that fell back (each edge a face uses, each distinct
+   face once), counts[1] those whose decision was near a threshold. */
+static void rhs_impl(const orc_grid* g, const double* q, double* rhs, const orc_learn* L, int64_t* counts)
 {
     int gh[3], P[3];
     for (int d = 0; d < 3; ++d) {
@@ -391,6 +680,7 @@ void orc_rhs(const orc_grid* g, const double* q, double* rhs)
     const int64_t N = ncells(g);
     const int64_t NP = (int64_t)P[0] * P[1] * P[2];
     double* wp = (double*)malloc(sizeof(double) * NV * NP);
+    int64_t nfb = 0, nnear = 0;
 
     /* padded primitive array: ghosts filled by the BC map, then converted */
 #pragma omp parallel for collapse(2) schedule(static)
@@ -424,7 +714,9 @@ void orc_rhs(const orc_grid* g, const double* q, double* rhs)
         int64_t stride_p[3] = {1, P[0], (int64_t)P[0] * P[1]};
         int64_t stride_n[3] = {1, g->n[0], (int64_t)g->n[0] * g->n[1]};
         int n = g->n[d];
-#pragma omp parallel for collapse(2) schedule(static)
+        /* distinct faces of a pencil: with periodic ends faces 0 and n coincide */
+        const int nfaces = g->bc[d][0] == 0 ? n : n + 1;
+#pragma omp parallel for collapse(2) schedule(static) reduction(+ : nfb, nnear)
         for (int ib = 0; ib < g->n[b]; ++ib)
             for (int ia = 0; ia < g->n[a]; ++ia) {
                 /* edges of cells -1..n, faces 0..n (face f sits between f-1 and f) */
@@ -432,14 +724,27 @@ void orc_rhs(const orc_grid* g, const double* q, double* rhs)
                 double* rgt = (double*)malloc(sizeof(double) * NV * (n + 2));
                 double* F = (double*)malloc(sizeof(double) * NV * (n + 1));
                 double* uf = (double*)malloc(sizeof(double) * (n + 1));
+                int* flag = L ? (int*)malloc(sizeof(int) * 4 * (n + 2)) : NULL;
                 int64_t base_p = (ia + gh[a]) * stride_p[a] + (ib + gh[b]) * stride_p[b];
                 int64_t base_n = ia * stride_n[a] + ib * stride_n[b];
                 for (int c = -1; c <= n; ++c) {
-                    for (int v = 0; v < NV; ++v) {
-                        double st[5];
+                    double st7[NV][5];
+                    for (int v = 0; v < NV; ++v)
                         for (int o = -2; o <= 2; ++o)
-                            st[o + 2] = wp[v * NP + base_p + (int64_t)(c + gh[d] + o) * stride_p[d]];
-                        reconstruct(g, st, &lft[(c + 1) * NV + v], &rgt[(c + 1) * NV + v]);
+                            st7[v][o + 2] = wp[v * NP + base_p + (int64_t)(c + gh[d] + o) * stride_p[d]];
+                    if (L) {
+                        int* fl = &flag[4 * (c + 1)];
+                        learned_cell(g, L, st7, &lft[(c + 1) * NV], &rgt[(c + 1) * NV], fl, fl + 2);
+                    } else {
+                        for (int v = 0; v < NV; ++v)
+                            reconstruct(g, st7[v], &lft[(c + 1) * NV + v], &rgt[(c + 1) * NV + v]);
+                    }
+                }
+                if (L) {
+                    /* face f: right edge of cell f-1 (index f), left edge of cell f (index f+1) */
+                    for (int f = 0; f < nfaces; ++f) {
+                        nfb += flag[4 * f + 0] + flag[4 * (f + 1) + 1];
+                        nnear += flag[4 * f + 2] + flag[4 * (f + 1) + 3];
                     }
                 }
                 for (int f = 0; f <= n; ++f)
@@ -455,10 +760,50 @@ void orc_rhs(const orc_grid* g, const double* q, double* rhs)
                 free(rgt);
                 free(F);
                 free(uf);
+                free(flag);
             }
     }
     free(wp);
+    if (counts) {
+        counts[0] = nfb;
+        counts[1] = nnear;
+    }
 }
+
+void orc_rhs(const orc_grid* g, const double* q, double* rhs) { rhs_impl(g, q, rhs, NULL, NULL); }
+
+/* Right-hand side with learned WENO weights (fifth order; the grid's
+   weno_z / weno_order are not used).  theta: the 1347 network parameters
+   (float32 values); mode 1 per variable, 2 shared per edge; counts[2] as
+   in rhs_impl (may be NULL).  plant (tests only, 0 otherwise) builds in a
+   deliberate mistake to show what the comparisons catch: 1 the left edge
+   takes the unreversed stencil's features, 2 the two edges exchanged, 3 the
+   fallback per variable (only the variables that fail their own test take
+   the Jiang-Shu value) instead of per edge, 4 the shared baseline the mean
+   of the Jiang-Shu weights instead of their minimum. */
+void orc_rhs_learned(const orc_grid* g, const double* q, const double* theta, int mode, int plant, double* rhs,
+                     int64_t* counts)
+{
+    orc_mlp m;
+    mlp_load(theta, &m);
+    orc_learn L = {&m, mode == 2 ? 2 : 1, plant};
+    rhs_impl(g, q, rhs, &L, counts);
+}
+
+/* Logits and weights of single samples (pins): features x[n][5], baseline
+   base[n][3] -> omega[n][3] with the bfloat16 operands as in the solver. */
+void orc_mlp_omega(const double* theta, int64_t n, const double* x, const double* base, double* omega)
+{
+    orc_mlp m;
+    mlp_load(theta, &m);
+    for (int64_t i = 0; i < n; ++i) {
+        double z[3];
+        mlp_logits(&m, x + 5 * i, z);
+        corrected_weights(base + 3 * i, z, omega + 3 * i);
+    }
+}
+
+double orc_gelu(double a) { return gelu_tanh(a); }
 
 /* ---------- right-hand side at selected cells, one by one ----------
    cells: linear indices (k*ny + j)*nx + i; out: [ncell][7].  Uses the same

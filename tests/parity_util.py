@@ -32,6 +32,26 @@ def rel_linf(x: np.ndarray, y: np.ndarray) -> np.ndarray:
     return np.abs(x - y).max(axis=1) / den
 
 
+def physical_flux_scale(q: np.ndarray, spec) -> np.ndarray:
+    """Per field, max over cells of sum_d |F_k,d(q)| / dx_d with the model's
+    physical flux F alone (the scale the FP64 right-hand-side bar was first
+    written with; flux_scale adds the wave-speed term)."""
+    g = oracle.make_grid(spec)
+    w = oracle.cons_to_prim(g, q).reshape(7, -1)
+    qq = q.reshape(7, -1)
+    p = w[5]
+    tot = np.zeros_like(qq)
+    for d in range(3):
+        if spec["n"][d] <= 1:
+            continue
+        ud = w[2 + d]
+        F = np.abs(qq * ud)
+        F[2 + d] = np.abs(qq[2 + d] * ud + p)
+        F[5] = np.abs((qq[5] + p) * ud)
+        tot += F / spec["dx"][d]
+    return _shared_momentum(tot.max(axis=1))
+
+
 def flux_scale(q: np.ndarray, spec) -> np.ndarray:
     """Size of the terms a right-hand side is a difference of.  An HLLC flux
     is the physical flux of one side plus a wave speed times a jump of the
@@ -68,6 +88,22 @@ def rhs_rel_linf(x: np.ndarray, y: np.ndarray, q: np.ndarray, spec) -> np.ndarra
     den = np.maximum(np.abs(y).max(axis=1), flux_scale(q, spec))
     den = np.where(den > 0, den, 1.0)  # no active direction: L == 0 exactly
     return np.abs(x - y).max(axis=1) / den
+
+
+def rhs_rel_linf_physical(x: np.ndarray, y: np.ndarray, q: np.ndarray, spec) -> np.ndarray:
+    """The same error scaled by max(max|L_k|, physical_flux_scale): the
+    stricter scale without the wave-speed term."""
+    x = x.reshape(7, -1)
+    y = y.reshape(7, -1)
+    den = np.maximum(np.abs(y).max(axis=1), physical_flux_scale(q, spec))
+    den = np.where(den > 0, den, 1.0)
+    return np.abs(x - y).max(axis=1) / den
+
+
+def fp64_rhs_errors(x: np.ndarray, y: np.ndarray, q: np.ndarray, spec):
+    """(error under flux_scale, error under the physical-flux scale alone):
+    the FP64 path must meet the 1e-12 bar under both."""
+    return rhs_rel_linf(x, y, q, spec), rhs_rel_linf_physical(x, y, q, spec)
 
 
 def gpu_solver(spec, q0=None, w0=None, **kw):
@@ -155,3 +191,37 @@ def sample_cells(spec, count: int, seed: int, q0: np.ndarray | None = None) -> n
             kk, jj, ii = np.unravel_index(top, g.shape)
             cells.append((kk * n[1] + jj) * n[0] + ii)
     return np.unique(np.concatenate(cells)).astype(np.int64)
+
+
+def learned_reference(spec, q0: np.ndarray, theta, mode: int):
+    """The oracle's learned right-hand side for a GPU comparison, with what
+    sizes the comparison's tolerance.
+
+    The kernel forms the network's operands in float32 from the float32
+    primitives and rounds them to bfloat16; a different rounding of an
+    operand moves the weights, so the learned right-hand side is only as
+    well defined as the quantisation's response to float32 rounding of its
+    inputs.  That response is measured on the oracle itself: the same
+    right-hand side of the state whose primitives are first rounded to
+    float32 (sens, per field, relative to flux_scale; and the change of the
+    fallback count).  Returns a dict: rhs, fallbacks, near (decisions near a
+    threshold), sens [7], fallback_shift."""
+    g = oracle.make_grid(spec)
+    r, fb, near = oracle.rhs_learned(g, q0, theta, mode)
+    w = oracle.cons_to_prim(g, q0)
+    q32 = oracle.prim_to_cons(g, w.astype(np.float32).astype(np.float64))
+    r32, fb32, _ = oracle.rhs_learned(g, q32, theta, mode)
+    sc = flux_scale(q0, spec)
+    sens = np.abs(r - r32).reshape(7, -1).max(axis=1) / np.where(sc > 0, sc, 1.0)
+    return {"rhs": r, "fallbacks": fb, "near": near, "sens": sens, "fallback_shift": abs(fb - fb32)}
+
+
+# Float32 arithmetic bar of the reconstruction and Riemann solve (the FP32
+# form's right-hand side against the oracle, relative to flux_scale).
+FP32_BAR = 1e-5
+
+
+def learned_tolerance(ref) -> np.ndarray:
+    """Per-field tolerance of a learned right-hand side against the oracle:
+    the float32 bar plus four times the oracle's own quantisation response."""
+    return FP32_BAR + 4.0 * ref["sens"]
