@@ -107,16 +107,36 @@ def load_traffic(kernel: str):
     return t.get("kernels", {}).get(kernel)
 
 
+def _host_cpus():
+    """Logical CPUs of the host, the ones this process may run on, and the
+    CPU model (from /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        allowed = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        allowed = None
+    return os.cpu_count(), allowed, model
+
+
 def cpu_baseline(P, q0_np, budget_s: float):
-    """Oracle (plain FP64 C, OpenMP) timed on the host: one SSP-RK3 step of
-    the same state, on an x-slab of the grid sized to the time budget."""
+    """Oracle (plain FP64 C, OpenMP over pencils) timed on the host: one
+    SSP-RK3 step of the same state, on an x-slab of the grid sized to the
+    time budget, with every thread OpenMP runs and again on one thread (a
+    smaller slab)."""
     import numpy as np
 
     import oracle
 
     nx, ny, nz = P["spec"]["n"]
-    threads = oracle.max_threads()
-    # probe on a thin slab to size the sample
+
     def slab(k):
         spec = dict(P["spec"])
         spec["n"] = (nx, ny, k)
@@ -125,23 +145,45 @@ def cpu_baseline(P, q0_np, budget_s: float):
         q = np.ascontiguousarray(q0_np[:, :k])
         return g, q
 
-    g, q = slab(4)
-    t0 = time.perf_counter()
-    oracle.rk3_step(g, q)
-    per_cell = (time.perf_counter() - t0) / (nx * ny * 4 * 3)
-    k = int(max(4, min(nz, budget_s / max(per_cell * nx * ny * 3, 1e-12))))
-    g, q = slab(k)
-    t0 = time.perf_counter()
-    oracle.rk3_step(g, q)
-    dt = time.perf_counter() - t0
+    def timed(budget):
+        # probe on a thin slab to size the sample
+        g, q = slab(4)
+        t0 = time.perf_counter()
+        oracle.rk3_step(g, q)
+        per_cell = (time.perf_counter() - t0) / (nx * ny * 4 * 3)
+        k = int(max(4, min(nz, budget / max(per_cell * nx * ny * 3, 1e-12))))
+        g, q = slab(k)
+        t0 = time.perf_counter()
+        oracle.rk3_step(g, q)
+        dt = time.perf_counter() - t0
+        return dt, k
+
+    cpus, allowed, model = _host_cpus()
+    threads = oracle.team_size()
+    dt, k = timed(budget_s)
     cells = nx * ny * k
+    oracle.set_threads(1)
+    try:
+        dt1, k1 = timed(max(2.0, budget_s / 3))
+    finally:
+        oracle.set_threads(threads)
+    cells1 = nx * ny * k1
     return {
         "value": dt * 1e9 / (cells * 3),
         "unit": "ns/cell/RK-stage",
         "cores": threads,
         "kind": "oracle",
         "sample": f"one SSP-RK3 step of the first {k} z-planes ({nx}x{ny}x{k} = {cells} cells, "
-                  f"z periodic) of the same initial state; {dt:.1f} s wall",
+                  f"z periodic) of the same initial state on {threads} OpenMP threads; {dt:.1f} s wall",
+        "host_cpus": cpus,
+        "cpus_allowed": allowed,
+        "cpu_model": model,
+        "single_thread": {
+            "value": dt1 * 1e9 / (cells1 * 3),
+            "unit": "ns/cell/RK-stage",
+            "sample": f"one SSP-RK3 step of the first {k1} z-planes ({cells1} cells) on 1 thread; "
+                      f"{dt1:.1f} s wall",
+        },
     }
 
 
@@ -233,7 +275,7 @@ def main():
         prof = s.profile_read()
         s.profile(False)
         st = s.stats()
-        if st["status"] != 0:
+        if st["error"] != 0:
             raise RuntimeError(f"solver flagged a non-physical state: {st}")
         s.destroy()
         return ms_total, prof

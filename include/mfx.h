@@ -29,10 +29,10 @@
  * Errors: every int-returning call returns MFX_OK (0) or a negative code;
  * the message is available from mfx_last_error.  Bad arguments are
  * reported synchronously (MFX_EINVAL) before anything is enqueued.
- * Non-physical states seen by a kernel (rho <= 0, non-positive squared
- * sound speed, non-finite values) raise a device status bit that the next
+ * Non-physical states seen by a kernel raise bits of a device status word
+ * (MFX_STATUS_* below); an error bit is returned as MFX_ESTATE by the next
  * synchronising call (mfx_stats, mfx_get_state, mfx_rk3_step with a host
- * dt readback) returns as MFX_ESTATE.  No C++ exception crosses the ABI.
+ * dt readback).  No C++ exception crosses the ABI.
  */
 #ifndef MFX_H
 #define MFX_H
@@ -43,6 +43,20 @@
 #ifdef __cplusplus
 extern "C" {
 #endif
+
+/* Status word bits.  The state a call sets (mfx_set_state,
+ * mfx_set_primitive) and the new state of every step are checked for all
+ * four; the intermediate RK stages for the first three when their last pass
+ * is a y or z sweep (3D grids and grids with z active).  MFX_STATUS_ALPHA
+ * is recorded but is not an error: the unlimited scheme (no clipping) can
+ * carry alpha1 slightly outside [0, 1] next to a sharp interface (about
+ * 1e-6 below 0 and 2e-4 above 1 in the water/air shock tube), and such a
+ * state stays computable. */
+#define MFX_STATUS_RHO 1u        /* density alpha1 rho1 + alpha2 rho2 not positive */
+#define MFX_STATUS_SOUND 2u      /* squared sound speed ((Gamma+1) p + Pi)/(Gamma rho) not positive */
+#define MFX_STATUS_NONFINITE 4u  /* a non-finite value */
+#define MFX_STATUS_ALPHA 8u      /* alpha1 outside [0, 1] (recorded, not an error) */
+#define MFX_STATUS_ERRORS (MFX_STATUS_RHO | MFX_STATUS_SOUND | MFX_STATUS_NONFINITE)
 
 enum {
     MFX_OK = 0,
@@ -138,16 +152,20 @@ int mfx_set_state(mfx_ctx* ctx, const double* q_dev);
 int mfx_set_primitive(mfx_ctx* ctx, const double* w_dev);
 
 /* Copy the current conserved state out (same layout).  Synchronises the
- * stream; returns MFX_ESTATE if a kernel flagged a non-physical state. */
+ * stream; returns MFX_ESTATE if a kernel set an error bit of the status
+ * word. */
 int mfx_get_state(mfx_ctx* ctx, double* q_dev_out);
 
 /* Right-hand side L(q) of eq. (rhs) for the current state: for each active
- * direction in the order x, y, z, WENO5 face states of the primitive
- * variables, HLLC fluxes and face velocities, flux differences over dx, and
- * the alpha1 source alpha1 (u_f,+1/2 - u_f,-1/2) / dx.  Ghost cells come
- * from the boundary conditions (periodic wrap; transmissive = zero-gradient
- * copy of the boundary cell).  Written as float64 in the state layout to
- * rhs_dev_out (which must not alias the workspace).  Asynchronous. */
+ * direction in the order x, y, z, WENO face states of the primitive
+ * variables (the descriptor's order and weights), HLLC fluxes and face
+ * velocities, flux differences over dx, and the alpha1 source
+ * alpha1 (u_f,+1/2 - u_f,-1/2) / dx.  Ghost cells come from the boundary
+ * conditions (MFX_BC_*: periodic wrap, transmissive zero-gradient copy,
+ * reflective mirror with the normal momentum negated, inflow fixed state).
+ * Written as float64 in the state layout to rhs_dev_out (which must not
+ * alias the workspace).  Asynchronous.  The state was checked when it was
+ * set or stepped (status word); this call checks nothing further. */
 int mfx_rhs(mfx_ctx* ctx, double* rhs_dev_out);
 
 /* One SSP-RK3 step (Shu-Osher form) of the current state:
@@ -158,7 +176,7 @@ int mfx_rhs(mfx_ctx* ctx, double* rhs_dev_out);
  * which stays on the device (no synchronisation); a grid with no active
  * direction (1x1x1) has no CFL time step and needs dt > 0 (else MFX_EINVAL).  If dt_used_host is not
  * NULL the call synchronises and stores the time step used there (and
- * reports MFX_ESTATE if a kernel flagged a state).  The CFL time step of
+ * returns MFX_ESTATE if an error bit of the status word is set).  The CFL time step of
  * the new state is computed inside the step for the next call. */
 int mfx_rk3_step(mfx_ctx* ctx, double dt, double* dt_used_host);
 
@@ -179,8 +197,10 @@ int mfx_rk3_step(mfx_ctx* ctx, double dt, double* dt_used_host);
 int mfx_set_mlp(mfx_ctx* ctx, const float* params_dev, int32_t n_params);
 
 /* Synchronise and report simulated time, step count, faces that fell back
- * to Jiang-Shu weights (learned mode), and the device status word.  Any
- * pointer may be NULL.  Returns MFX_ESTATE if the status word is non-zero. */
+ * to Jiang-Shu weights (learned mode), and the device status word
+ * (MFX_STATUS_* bits, accumulated since the state was set).  Any pointer
+ * may be NULL.  Returns MFX_ESTATE if an error bit (MFX_STATUS_ERRORS) is
+ * set. */
 int mfx_stats(mfx_ctx* ctx, double* t, int64_t* step, int64_t* fallback_faces, uint32_t* status);
 
 /* ------------------------------------------------------------------------

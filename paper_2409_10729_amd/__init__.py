@@ -133,13 +133,17 @@ class Solver:
         self._check(_native.lib().mfx_set_mlp(self._ctx, ctypes.c_void_p(params.data_ptr()), params.numel()))
 
     def stats(self):
+        """Time, step count, fallback edges and the status word; "error" holds
+        its error bits, "alpha_out" whether alpha1 left [0, 1]."""
         t = ctypes.c_double()
         step = ctypes.c_int64()
         fb = ctypes.c_int64()
         st = ctypes.c_uint32()
         rc = _native.lib().mfx_stats(self._ctx, ctypes.byref(t), ctypes.byref(step), ctypes.byref(fb),
                                      ctypes.byref(st))
-        out = {"t": t.value, "step": step.value, "fallback_faces": fb.value, "status": st.value}
+        out = {"t": t.value, "step": step.value, "fallback_faces": fb.value, "status": st.value,
+               "error": st.value & _native.MFX_STATUS_ERRORS,
+               "alpha_out": bool(st.value & _native.MFX_STATUS_ALPHA)}
         if rc not in (_native.MFX_OK, _native.MFX_ESTATE):
             self._check(rc)
         out["rc"] = rc

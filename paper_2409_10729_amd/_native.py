@@ -16,6 +16,8 @@ MFX_OK, MFX_EINVAL, MFX_EHIP, MFX_ENOMEM, MFX_ESTATE = 0, -1, -2, -3, -4
 MFX_BC_PERIODIC, MFX_BC_TRANSMISSIVE, MFX_BC_REFLECTIVE, MFX_BC_INFLOW = 0, 1, 2, 3
 MFX_FP64, MFX_FP32_MIXED = 0, 1
 MFX_WENO5_JS, MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE, MFX_WENO5_Z = 0, 1, 2, 3
+MFX_STATUS_RHO, MFX_STATUS_SOUND, MFX_STATUS_NONFINITE, MFX_STATUS_ALPHA = 1, 2, 4, 8
+MFX_STATUS_ERRORS = MFX_STATUS_RHO | MFX_STATUS_SOUND | MFX_STATUS_NONFINITE
 
 EXPORTED = (
     "mfx_workspace_bytes", "mfx_init_grid", "mfx_set_state", "mfx_set_primitive", "mfx_get_state",

@@ -245,7 +245,8 @@ __device__ __forceinline__ void mlp_omega(const MlpLane& m, LearnedLds* L, const
 // as computed; left edge: the mirrored stencil, i.e. features with beta0 and
 // beta2 swapped, weights applied to the mirrored candidates).
 __device__ __forceinline__ void weno5_learned(const MlpLane& m, LearnedLds* L, float a, float b, float c, float d,
-                                              float e, float eps, float& left, float& right, bool& finite_w)
+                                              float e, float eps, float& left, float& right, bool& finite_r,
+                                              bool& finite_l)
 {
     float x[5], xm[5], nlb[3], om[3], oml[3];
     weno_features(a, b, c, d, e, eps, x, nlb);
@@ -259,7 +260,8 @@ __device__ __forceinline__ void weno5_learned(const MlpLane& m, LearnedLds* L, f
     const float lwm[3] = {LOG2_D0 + nlb[2], LOG2_D1 + nlb[1], LOG2_D2 + nlb[0]};
     mlp_omega_pair(m, L, x, xm, lw, lwm, om, oml);
     weno5_apply(om, oml, a, b, c, d, e, left, right);
-    finite_w = isfinite(om[0] + om[1] + om[2] + oml[0] + oml[1] + oml[2]);
+    finite_r = isfinite(om[0] + om[1] + om[2]);
+    finite_l = isfinite(oml[0] + oml[1] + oml[2]);
 }
 
 // A face state is admissible if its partial densities are non-negative,

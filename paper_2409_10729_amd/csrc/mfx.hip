@@ -479,7 +479,7 @@ void launch_one(const LaunchArgs& a)
             }
         }
         sweep_yz<DIR, T, FIRST, MODE, L, false, SCHEME><<<sg.grid, sg.block, 0, a.st>>>(
-            *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, nullptr, nullptr);
+            *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, nullptr, a.status);
     }
 }
 
@@ -657,6 +657,47 @@ int read_status(mfx_ctx* c, unsigned* st)
     return MFX_OK;
 }
 
+// MFX_ESTATE for a status word with an error bit (alpha1 outside [0, 1]
+// alone is recorded, not an error).
+int status_error(mfx_ctx* c, unsigned st)
+{
+    if (st & MFX_STATUS_ERRORS)
+        return fail(c, MFX_ESTATE, "non-physical state flagged (status " + std::to_string(st) + ")");
+    return MFX_OK;
+}
+
+// Grid constants and the active directions of a context from its
+// descriptor; inflow_dev: device copy of the inflow states.
+void setup_grid(const mfx_grid_desc* desc, mfx_ctx* c, const double* inflow_dev)
+{
+    Grid& g = c->g;
+    g.N = (long long)desc->n[0] * desc->n[1] * desc->n[2];
+    g.stride[0] = 1;
+    g.stride[1] = desc->n[0];
+    g.stride[2] = (long long)desc->n[0] * desc->n[1];
+    c->ndirs = 0;
+    for (int k = 0; k < 3; ++k) {
+        g.n[k] = desc->n[k];
+        g.dx[k] = desc->dx[k];
+        g.inv_dx[k] = 1.0 / desc->dx[k];
+        g.bc[k][0] = desc->bc[k][0];
+        g.bc[k][1] = desc->bc[k][1];
+        for (int s = 0; s < 2; ++s)
+            for (int v = 0; v < NV; ++v) g.inflow[k][s][v] = desc->bc[k][s] == MFX_BC_INFLOW ? desc->inflow[k][s][v] : 0.0;
+        g.active[k] = desc->n[k] > 1;
+        if (g.active[k]) c->dirs[c->ndirs++] = k;
+    }
+    g.inflow_dev = inflow_dev;
+    if (c->ndirs == 0) c->dirs[c->ndirs++] = 0;  // a single cell still sweeps x (all faces from ghosts)
+    g.G1 = 1.0 / (desc->gamma[0] - 1.0);
+    g.G2 = 1.0 / (desc->gamma[1] - 1.0);
+    g.P1 = desc->gamma[0] * desc->pi_inf[0] / (desc->gamma[0] - 1.0);
+    g.P2 = desc->gamma[1] * desc->pi_inf[1] / (desc->gamma[1] - 1.0);
+    g.eps = desc->weno_eps;
+    g.edge_weights = desc->weights == MFX_WENO5_LEARNED_EDGE ? 1 : 0;
+    g.cfl = desc->cfl;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- C ABI
@@ -720,32 +761,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     c->fallback = reinterpret_cast<unsigned long long*>(c->ws + L.scal + 40);
     c->has_mlp = false;
 
-    Grid& g = c->g;
-    g.N = (long long)desc->n[0] * desc->n[1] * desc->n[2];
-    g.stride[0] = 1;
-    g.stride[1] = desc->n[0];
-    g.stride[2] = (long long)desc->n[0] * desc->n[1];
-    c->ndirs = 0;
-    for (int k = 0; k < 3; ++k) {
-        g.n[k] = desc->n[k];
-        g.dx[k] = desc->dx[k];
-        g.inv_dx[k] = 1.0 / desc->dx[k];
-        g.bc[k][0] = desc->bc[k][0];
-        g.bc[k][1] = desc->bc[k][1];
-        for (int s = 0; s < 2; ++s)
-            for (int v = 0; v < NV; ++v) g.inflow[k][s][v] = desc->bc[k][s] == MFX_BC_INFLOW ? desc->inflow[k][s][v] : 0.0;
-        g.active[k] = desc->n[k] > 1;
-        if (g.active[k]) c->dirs[c->ndirs++] = k;
-    }
-    g.inflow_dev = reinterpret_cast<const double*>(c->ws + L.inflow);
-    if (c->ndirs == 0) c->dirs[c->ndirs++] = 0;  // a single cell still sweeps x (all faces from ghosts)
-    g.G1 = 1.0 / (desc->gamma[0] - 1.0);
-    g.G2 = 1.0 / (desc->gamma[1] - 1.0);
-    g.P1 = desc->gamma[0] * desc->pi_inf[0] / (desc->gamma[0] - 1.0);
-    g.P2 = desc->gamma[1] * desc->pi_inf[1] / (desc->gamma[1] - 1.0);
-    g.eps = desc->weno_eps;
-    g.edge_weights = desc->weights == MFX_WENO5_LEARNED_EDGE ? 1 : 0;
-    g.cfl = desc->cfl;
+    setup_grid(desc, c, reinterpret_cast<const double*>(c->ws + L.inflow));
 
     if (hipMemsetAsync(c->ws + L.scal, 0, 64, c->stream) != hipSuccess) {
         delete c;
@@ -753,7 +769,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     }
     // the inflow states for the loaders (zero for other sides); the source
     // lives in the context
-    if (hipMemcpyAsync(c->ws + L.inflow, &g.inflow[0][0][0], sizeof(double) * 3 * 2 * NV, hipMemcpyHostToDevice,
+    if (hipMemcpyAsync(c->ws + L.inflow, &c->g.inflow[0][0][0], sizeof(double) * 3 * 2 * NV, hipMemcpyHostToDevice,
                        c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         delete c;
@@ -809,8 +825,7 @@ int mfx_get_state(mfx_ctx* c, double* q_dev_out)
     unsigned st = 0;
     rc = read_status(c, &st);
     if (rc) return rc;
-    if (st) return fail(c, MFX_ESTATE, "non-physical state flagged (status " + std::to_string(st) + ")");
-    return MFX_OK;
+    return status_error(c, st);
 }
 
 namespace {
@@ -848,9 +863,12 @@ int mfx_rk3_step(mfx_ctx* c, double dt, double* dt_used_host)
     if (rc) return rc;
     const double* dt_dev = dt > 0.0 ? nullptr : c->scal;
     const double dt_arg = dt > 0.0 ? dt : 0.0;
+    // the CFL time step this step uses, read before the step overwrites it
+    // (the caller asked for it, so the call synchronises anyway)
     double dt_seen = 0.0;
     if (dt_used_host && !(dt > 0.0)) {
         HIP_TRY(c, hipMemcpyAsync(&dt_seen, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     rc = run_passes(c, c->q, c->q, c->q1, OUT_STAGE1, dt_dev, dt_arg);
     if (rc) return rc;
@@ -872,7 +890,7 @@ int mfx_rk3_step(mfx_ctx* c, double dt, double* dt_used_host)
         rc = read_status(c, &st);
         if (rc) return rc;
         *dt_used_host = dt > 0.0 ? dt : dt_seen;
-        if (st) return fail(c, MFX_ESTATE, "non-physical state flagged (status " + std::to_string(st) + ")");
+        return status_error(c, st);
     }
     return MFX_OK;
 }
@@ -908,8 +926,7 @@ int mfx_stats(mfx_ctx* c, double* t, int64_t* step, int64_t* fallback_faces, uin
     if (step) *step = (int64_t)sc[2];
     if (fallback_faces) *fallback_faces = (int64_t)fb;
     if (status) *status = st;
-    if (st) return fail(c, MFX_ESTATE, "non-physical state flagged (status " + std::to_string(st) + ")");
-    return MFX_OK;
+    return status_error(c, st);
 }
 
 int mfx_profile(mfx_ctx* c, int enable)
@@ -967,3 +984,4 @@ void mfx_destroy(mfx_ctx* c)
 const char* mfx_last_error(const mfx_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
 
 }  // extern "C"
+

@@ -129,14 +129,44 @@ __device__ __forceinline__ double cfl_speed(const Grid& g, const double q[NV], u
     if (!(rho > 0.0)) bad |= 1u;
     if (!(c2 > 0.0)) bad |= 2u;
     if (!isfinite(s)) bad |= 4u;
+    if (!(a1 >= 0.0 && a1 <= 1.0)) bad |= 8u;
     return s;
 }
+
+// Status bits of a state (the same bits as cfl_speed without the sound
+// speed): density not positive (1), a non-finite value (4), alpha1 outside
+// [0, 1] (8).
+__device__ __forceinline__ unsigned state_bits(const double q[NV])
+{
+    unsigned bad = 0;
+    if (!(q[0] + q[1] > 0.0)) bad |= 1u;
+    bool fin = true;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fin = fin && isfinite(q[v]);
+    if (!fin) bad |= 4u;
+    if (!(q[6] >= 0.0 && q[6] <= 1.0)) bad |= 8u;
+    return bad;
+}
+
+// What the last pass of a stage checks in the state it writes.
+enum : int {
+    CHK_NONE = 0,   // nothing (not the last pass of a stage, or the standalone reduction follows)
+    CHK_STATE = 1,  // the status bits of state_bits (stages 1 and 2)
+    CHK_CFL = 2,    // the CFL maximum and every status bit (stage 3)
+};
 
 // Running CFL maximum and validity flags of the cells a lane writes.
 struct CflAcc {
     double smax;
     unsigned bad;
-    __device__ __forceinline__ void add(const Grid& g, const double q[NV]) { smax = fmax(smax, cfl_speed(g, q, bad)); }
+    bool cfl;  // false: only the status bits, no CFL speed
+    __device__ __forceinline__ void add(const Grid& g, const double q[NV])
+    {
+        if (cfl)
+            smax = fmax(smax, cfl_speed(g, q, bad));
+        else
+            bad |= state_bits(q);
+    }
 };
 
 template <int BLOCK>
@@ -258,14 +288,15 @@ __device__ __forceinline__ void ghost_fix(const Grid& g, const Mix<double>& mixd
 // consecutive x, so every access is a contiguous row).  KEEPQ: the march
 // hands over the cell's stage state, which it loaded four cells earlier,
 // so the stage update does not read it again.
-// CFL: the pass writes the step's new state and also reduces its CFL
-// wave speed (acc).  prefetch() loads the running sum and the step state
+// CHK: what the pass checks in the state it writes (acc): the status bits
+// (stages 1 and 2), or also the CFL wave speed of the step's new state
+// (stage 3).  prefetch() loads the running sum and the step state
 // of the cell the march puts next at the top of the march step, so the
 // loads are in flight during its reconstruction and Riemann solve (lanes
 // past the grid read the clamped column: in bounds, never stored).
 // PREFETCH off (the learned passes): the loads stay where the output needs
 // them, so they do not hold registers across the network evaluations.
-template <typename T, bool FIRST, int MODE, bool KEEPQ = false, bool CFL = false, bool PREFETCH = true>
+template <typename T, bool FIRST, int MODE, bool KEEPQ = false, int CHK = CHK_NONE, bool PREFETCH = true>
 struct GlobalSink {
     static constexpr bool keeps_q = KEEPQ;
     static constexpr bool NEEDQN = MODE == OUT_STAGE2 || MODE == OUT_STAGE3;
@@ -300,7 +331,7 @@ struct GlobalSink {
 #pragma unroll
             for (int v = 0; v < NV; ++v) r[v] = FIRST ? fd[v] : rin[v] + fd[v];
             r[6] += src;
-            store_cell<T, MODE>(g, o, base + (long long)c * sd, r, KEEPQ ? qc : nullptr, CFL ? &acc : nullptr,
+            store_cell<T, MODE>(g, o, base + (long long)c * sd, r, KEEPQ ? qc : nullptr, CHK ? &acc : nullptr,
                                 NEEDQN ? qnin : nullptr);
         }
     }
@@ -417,12 +448,16 @@ struct ReconJS {
     {
         cell_win(ArrayWindow<T>{W}, eps, lft, rgt);
     }
+    __device__ __forceinline__ void count_edges(bool, bool) {}
     __device__ __forceinline__ void flush(unsigned long long*) {}
 };
 
 // Learned weights (float32 form); the whole wave must call cell() together.
 // An edge state whose weights are not finite or that is not admissible is
 // replaced by the Jiang-Shu edge state of all seven variables.
+// Fallbacks are counted for the edges the caller names with count_edges()
+// before each cell: those a face of the launch uses, each distinct face
+// once (a face two segments both solve is counted by one of them).
 struct ReconLearned {
     MlpLane m;
     LearnedLds* lds;  // this wave's slot
@@ -430,6 +465,12 @@ struct ReconLearned {
     bool valid;  // this lane owns a real cell (only those are counted)
     unsigned fallbacks;
     bool edge;  // one evaluation per edge for all variables
+    bool cnt_r = true, cnt_l = true;  // count the right / left edge of the next cell
+    __device__ __forceinline__ void count_edges(bool r, bool l)
+    {
+        cnt_r = r;
+        cnt_l = l;
+    }
     template <class Win>
     __device__ __forceinline__ void cell_win(const Win& W, float eps, float lft[NV], float rgt[NV])
     {
@@ -479,35 +520,36 @@ struct ReconLearned {
         const float lwm[3] = {log2f(wm[0]), log2f(wm[1]), log2f(wm[2])};
         float om[3], oml[3];
         mlp_omega_pair(m, lds, f, fm, lw, lwm, om, oml);
-        const bool fin = isfinite(om[0] + om[1] + om[2] + oml[0] + oml[1] + oml[2]);
+        const bool finR = isfinite(om[0] + om[1] + om[2]);
+        const bool finL = isfinite(oml[0] + oml[1] + oml[2]);
         float ll[NV], rl[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const float a = W(0, v), b = W(1, v), c = W(2, v), d = W(3, v), e = W(4, v);
             weno5_apply(om, oml, a, b, c, d, e, ll[v], rl[v]);
         }
-        finish(fin, lj, rj, ll, rl, lft, rgt);
+        finish(finR, finL, lj, rj, ll, rl, lft, rgt);
     }
 
     // Fallback per edge and counting (both forms).
-    __device__ __forceinline__ void finish(bool fin, const float lj[NV], const float rj[NV], const float ll[NV],
-                                           const float rl[NV], float lft[NV], float rgt[NV])
+    __device__ __forceinline__ void finish(bool finR, bool finL, const float lj[NV], const float rj[NV],
+                                           const float ll[NV], const float rl[NV], float lft[NV], float rgt[NV])
     {
-        const bool okR = fin && admissible(mix, rl);
-        const bool okL = fin && admissible(mix, ll);
+        const bool okR = finR && admissible(mix, rl);
+        const bool okL = finL && admissible(mix, ll);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             rgt[v] = okR ? rl[v] : rj[v];
             lft[v] = okL ? ll[v] : lj[v];
         }
-        if (valid) fallbacks += (okR ? 0u : 1u) + (okL ? 0u : 1u);
+        if (valid) fallbacks += (okR || !cnt_r ? 0u : 1u) + (okL || !cnt_l ? 0u : 1u);
     }
 
     template <class Win>
     __device__ __forceinline__ void cell_var(const Win& W, float eps, float lft[NV], float rgt[NV])
     {
         float lj[NV], rj[NV], ll[NV], rl[NV];
-        bool fin = true;
+        bool finR = true, finL = true;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const float a = W(0, v), b = W(1, v), c = W(2, v), d = W(3, v), e = W(4, v);
@@ -519,12 +561,13 @@ struct ReconLearned {
                 ll[v] = lj[v];
                 rl[v] = rj[v];
             } else {
-                bool f;
-                weno5_learned(m, lds, a, b, c, d, e, eps, ll[v], rl[v], f);
-                fin = fin && f;
+                bool fr, fl;
+                weno5_learned(m, lds, a, b, c, d, e, eps, ll[v], rl[v], fr, fl);
+                finR = finR && fr;
+                finL = finL && fl;
             }
         }
-        finish(fin, lj, rj, ll, rl, lft, rgt);
+        finish(finR, finL, lj, rj, ll, rl, lft, rgt);
     }
     __device__ __forceinline__ void cell(const float W[5][NV], float eps, float lft[NV], float rgt[NV])
     {
@@ -618,6 +661,10 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
 #pragma unroll
     for (int v = 0; v < NV; ++v) rprev[v] = Fprev[v] = T(0);
 
+    // faces this segment counts (learned fallbacks): c0+1/2 .. c1-1/2, and
+    // c0-1/2 in the first segment unless it is the periodic image of the
+    // last segment's c1-1/2
+    const bool own_first = c0 == 0 && g.bc[DIR][0] != BC_PERIODIC;
     for (int c = c0 - 1; c <= c1; ++c) {
         // next cell entering the window (c+3), and what the output of cell
         // c-1 needs, fetched early
@@ -626,6 +673,8 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
         if (c > c0) sink.prefetch(g, c - 1);
 
         T lft[NV], rgt[NV];
+        recon.count_edges((c >= c0 && c < c1) || (c == c0 - 1 && own_first),
+                          (c > c0 && c <= c1) || (c == c0 && own_first));
         recon.cell_win(W, eps, lft, rgt);
 
         if (c >= c0) {
@@ -714,7 +763,8 @@ struct GlobalSrc {
 // is declared __restrict__.
 // CFL (stage 3 only): the block's CFL maximum of the new state goes to
 // partial[block] and invalid states set bits in *status, as in the
-// standalone reduction.
+// standalone reduction.  Stages 1 and 2 set the status bits of the states
+// they write (state_bits) in *status.
 // Block size: the Jiang-Shu passes run one wave per block (waves do not
 // cooperate, so every lane is used for any nx that is a multiple of 64);
 // the learned passes run four (measured faster for them).
@@ -746,15 +796,19 @@ __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 2 : 1) sweep_yz
     const int c0 = blockIdx.z * seg;
     const int c1 = min(c0 + seg, n);
     GlobalSrc<DIR> src{qs, g.inflow_dev + DIR * 2 * NV, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
-    GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CFL, !LEARNED> sink{
-        OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid, CflAcc{0.0, 0u}};
+    constexpr int CHK = (MODE == OUT_STAGE1 || MODE == OUT_STAGE2) ? CHK_STATE : (CFL ? CHK_CFL : CHK_NONE);
+    GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CHK, !LEARNED> sink{
+        OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid,
+        CflAcc{0.0, 0u, CHK == CHK_CFL}};
     auto recon = make_recon<T, LEARNED, SCHEME, BLOCK / 64>(g, mlp, valid);
     __shared__ T win[5][NV][BLOCK];
     LdsWindow<T, BLOCK> W{&win[0][0][threadIdx.x], 0};
     march<DIR, T>(g, src, sink, recon, c0, c1, W);
     recon.flush(fb);
-    if constexpr (CFL) {
+    if constexpr (CHK != CHK_NONE) {
         if (sink.acc.bad) atomicOr(status, sink.acc.bad);
+    }
+    if constexpr (CHK == CHK_CFL) {
         const unsigned blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
         block_max_to<BLOCK>(sink.acc.smax, partial + blk);
     }

@@ -83,7 +83,9 @@ __global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __
         // right edge of the cell before the face (window w[0..4]) and left
         // edge of the cell after it (window w[1..5])
         T wl[NV], wr[NV], dummy[NV];
+        recon.count_edges(true, false);  // the face uses this cell's right edge
         recon.cell(w, eps, dummy, wl);
+        recon.count_edges(false, true);  // and the next cell's left edge
         recon.cell(w + 1, eps, wr, dummy);
         T F[NV], uf;
         hllc<0, T>(mix, wl, wr, F, uf);
@@ -246,6 +248,8 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
         // 2. reconstruct own cell (window read from the LDS row as it goes):
         // left edge to LDS, right edge kept
         T rgt[NV], lft[NV];
+        // interior faces only: the row's end faces come from boundary_faces_x
+        recon.count_edges(xc < nx - 1, xc > 0);
         recon.cell_win(RowWindow<T>{P + xc, np}, eps, lft, rgt);
         if (has) {
 #pragma unroll

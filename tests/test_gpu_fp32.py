@@ -59,7 +59,7 @@ def test_fp32_shock_droplet_density_l1():
     e_rho = np.abs(rho32 - rho64).sum() / np.abs(rho64).sum()
     print("fp32 vs fp64 L1 per field: " + " ".join(f"{x:.2e}" for x in e) + f"  density {e_rho:.2e}", flush=True)
     assert e_rho <= 1e-4
-    assert s32.stats()["status"] == 0
+    assert s32.stats()["error"] == 0
 
 
 def test_fp32_shock_tube_tracks_fp64():

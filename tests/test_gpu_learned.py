@@ -76,22 +76,6 @@ def test_forward_f32_matches_oracle():
     np.testing.assert_allclose(om, ref, rtol=0, atol=2e-6)
 
 
-def _bf16_oracle(theta, X, OJS):
-    """The network as the matrix cores evaluate it: bfloat16 features,
-    weights and hidden activations, float32-level accumulation (emulated in
-    float64), biases of layers 2 and 3 unrounded, layer-1 bias rounded."""
-    p = omlp.unpack(theta.astype(np.float32).astype(np.float64))
-    r = omlp.bf16_round
-    A1 = r(X) @ r(p["W1"]).T + r(p["b1"])
-    H1 = r(omlp.gelu(A1))
-    A2 = H1 @ r(p["W2"]).T + p["b2"]
-    H2 = r(omlp.gelu(A2))
-    Z = H2 @ r(p["W3"]).T + p["b3"] + np.log(OJS)
-    Z = Z - Z.max(1, keepdims=True)
-    E = np.exp(Z)
-    return E / E.sum(1, keepdims=True)
-
-
 @pytest.mark.parametrize("n", [64, 1000, 4099])
 def test_forward_mfma_matches_bf16_oracle(n):
     from paper_2409_10729_amd import learned
@@ -102,7 +86,7 @@ def test_forward_mfma_matches_bf16_oracle(n):
     om = learned.forward(torch.from_numpy(_f32(theta)).cuda(), torch.from_numpy(X).cuda(),
                          torch.from_numpy(OJS).cuda(), packed=True).cpu().numpy()
     with np.errstate(divide="ignore"):
-        ref = _bf16_oracle(theta, X.astype(np.float64), OJS.astype(np.float64))
+        ref = omlp.forward_bf16(theta, X.astype(np.float64), OJS.astype(np.float64))
     err = np.abs(om - ref).max()
     print(f"mfma forward n={n}: max |omega - bf16 oracle| = {err:.2e}", flush=True)
     assert err <= 5e-3
@@ -259,7 +243,7 @@ def test_learned_x_sweep_variants_agree(monkeypatch, nx):
     print(f"learned x variants nx={nx}:", d, out["rows"][1]["fallback_faces"], out["march"][1]["fallback_faces"],
           flush=True)
     assert np.all(d <= 1e-4)
-    assert out["rows"][1]["status"] == 0 and out["march"][1]["status"] == 0
+    assert out["rows"][1]["error"] == 0 and out["march"][1]["error"] == 0
 
 
 def test_learned_needs_a_network():
@@ -283,7 +267,7 @@ def test_nan_network_falls_back_everywhere(maker):
     ql = s_l.get_state().cpu().numpy()
     qj = s_j.get_state().cpu().numpy()
     st = s_l.stats()
-    assert st["fallback_faces"] > 0 and st["status"] == 0
+    assert st["fallback_faces"] > 0 and st["error"] == 0
     d = rel_linf(ql, qj)
     print("nan network vs JS:", d, "fallback edges", st["fallback_faces"], flush=True)
     assert np.all(d <= 1e-6)
@@ -412,7 +396,7 @@ def test_edge_form_nan_network_falls_back_and_uniform_state_skips():
     st = s_e.stats()
     d = rel_linf(s_e.get_state().cpu().numpy(), s_j.get_state().cpu().numpy())
     print("edge form, nan network vs JS:", d, "fallback edges", st["fallback_faces"], flush=True)
-    assert st["fallback_faces"] > 0 and st["status"] == 0 and np.all(d <= 1e-6)
+    assert st["fallback_faces"] > 0 and st["error"] == 0 and np.all(d <= 1e-6)
     w = np.empty_like(P["w"])
     for v, val in enumerate((998.0, 0.0012, 12.0, -3.0, 0.5, 2.0e5, 0.999)):
         w[v] = val
