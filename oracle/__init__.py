@@ -24,7 +24,15 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "orc.c")
 _LIB = os.path.join(_HERE, "liborc.so")
 
-NV = 7
+NV = 7  # variables of the two-fluid model
+NFMAX = 4  # fluids the oracle takes
+NVMAX = 2 * NFMAX + 3
+
+
+def nvars(nf: int) -> int:
+    """Variables of the nf-fluid model: nf partial densities, three momenta,
+    energy and nf - 1 volume fractions."""
+    return 2 * nf + 3
 
 
 class OrcGrid(ctypes.Structure):
@@ -32,13 +40,14 @@ class OrcGrid(ctypes.Structure):
         ("n", ctypes.c_int32 * 3),
         ("dx", ctypes.c_double * 3),
         ("bc", (ctypes.c_int32 * 2) * 3),
-        ("gamma", ctypes.c_double * 2),
-        ("pinf", ctypes.c_double * 2),
+        ("gamma", ctypes.c_double * NFMAX),
+        ("pinf", ctypes.c_double * NFMAX),
         ("eps", ctypes.c_double),
         ("cfl", ctypes.c_double),
         ("weno_z", ctypes.c_int32),
         ("weno_order", ctypes.c_int32),
-        ("inflow", ((ctypes.c_double * NV) * 2) * 3),
+        ("inflow", ((ctypes.c_double * NVMAX) * 2) * 3),
+        ("nf", ctypes.c_int32),
     ]
 
 
@@ -114,8 +123,12 @@ def make_grid(spec: dict, weno_z: bool = False) -> OrcGrid:
         g.dx[d] = float(spec["dx"][d])
         g.bc[d][0] = int(spec["bc"][d][0])
         g.bc[d][1] = int(spec["bc"][d][1])
-    g.gamma[0], g.gamma[1] = map(float, spec["gamma"])
-    g.pinf[0], g.pinf[1] = map(float, spec["pinf"])
+    gam, pin = list(map(float, spec["gamma"])), list(map(float, spec["pinf"]))
+    if not (2 <= len(gam) <= NFMAX and len(pin) == len(gam)):
+        raise ValueError(f"gamma and pinf must list 2..{NFMAX} fluids alike")
+    g.nf = len(gam)
+    for f in range(g.nf):
+        g.gamma[f], g.pinf[f] = gam[f], pin[f]
     g.eps = float(spec.get("eps", 1e-6))
     g.cfl = float(spec.get("cfl", 0.4))
     g.weno_z = 1 if (weno_z or spec.get("weno_z", False)) else 0
@@ -129,16 +142,17 @@ def make_grid(spec: dict, weno_z: bool = False) -> OrcGrid:
         if 2 in kinds and 1 < g.n[d] < 3:
             raise ValueError("a reflective side needs at least 3 cells in its direction")
     if "inflow" in spec:
-        a = np.asarray(spec["inflow"], dtype=np.float64).reshape(3, 2, NV)
+        nv = nvars(g.nf)
+        a = np.asarray(spec["inflow"], dtype=np.float64).reshape(3, 2, nv)
         for d in range(3):
             for side in range(2):
-                for v in range(NV):
+                for v in range(nv):
                     g.inflow[d][side][v] = float(a[d, side, v])
     return g
 
 
 def _shape(g: OrcGrid):
-    return (NV, g.n[2], g.n[1], g.n[0])
+    return (nvars(g.nf), g.n[2], g.n[1], g.n[0])
 
 
 def prim_to_cons(g: OrcGrid, w: np.ndarray) -> np.ndarray:
@@ -166,7 +180,7 @@ def rhs_at(g: OrcGrid, q: np.ndarray, cells: np.ndarray) -> np.ndarray:
     """RHS at linear cell indices ``cells``; returns [ncell, 7]."""
     q = np.ascontiguousarray(q, dtype=np.float64)
     cells = np.ascontiguousarray(cells, dtype=np.int64)
-    out = np.empty((cells.size, NV), dtype=np.float64)
+    out = np.empty((cells.size, nvars(g.nf)), dtype=np.float64)
     lib().orc_rhs_at(ctypes.byref(g), _dp(q), cells.size,
                      cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out))
     return out
@@ -184,6 +198,8 @@ def rhs_learned(g: OrcGrid, q: np.ndarray, theta, mode: int = LEARNED_PER_VARIAB
     shared per edge.  Returns (rhs, fallback edges, near-threshold
     decisions), counting the two edges of every distinct face once.
     plant != 0 (tests only) builds in a deliberate mistake (see orc.c)."""
+    if g.nf != 2:
+        raise ValueError("the learned weights are defined for two fluids")
     q = np.ascontiguousarray(q, dtype=np.float64)
     th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32), dtype=np.float64)
     assert th.size == 1347
@@ -281,7 +297,7 @@ def weno5_betas(v):
 def hllc(g: OrcGrid, wl, wr, d: int):
     wl = np.ascontiguousarray(wl, dtype=np.float64)
     wr = np.ascontiguousarray(wr, dtype=np.float64)
-    F = np.empty(NV, dtype=np.float64)
+    F = np.empty(nvars(g.nf), dtype=np.float64)
     uf = ctypes.c_double()
     lib().orc_hllc(ctypes.byref(g), _dp(wl), _dp(wr), int(d), _dp(F), ctypes.byref(uf))
     return F, uf.value

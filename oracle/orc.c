@@ -48,22 +48,42 @@
 #include <omp.h>
 #endif
 
-#define NV 7
+#define NV 7 /* variables of the two-fluid model (the learned weights) */
 #define NG 3
+#define NFMAX 4 /* fluids */
+#define NVMAX (2 * NFMAX + 3)
 
 typedef struct {
     int32_t n[3];      /* interior cells per direction; 1 = inactive */
     double dx[3];      /* uniform spacing per direction */
     int32_t bc[3][2];  /* 0 = periodic, 1 = transmissive (zero gradient),
                           2 = reflective (slip wall), 3 = inflow (fixed state) */
-    double gamma[2];   /* fluid 1, fluid 2 */
-    double pinf[2];
+    double gamma[NFMAX]; /* per fluid */
+    double pinf[NFMAX];
     double eps;        /* WENO epsilon */
     double cfl;
     int32_t weno_z;    /* 0: Jiang-Shu weights (the paper's WENO5); 1: WENO-Z weights (comparison form) */
     int32_t weno_order; /* 5 (default; 0 reads as 5) or 3: the two orders Sec. II-B names */
-    double inflow[3][2][NV]; /* conserved state of the ghost cells of an inflow side */
+    double inflow[3][2][NVMAX]; /* conserved state of the ghost cells of an inflow side */
+    int32_t nf;        /* fluids, 2..NFMAX (0 reads as 2) */
 } orc_grid;
+
+/* Variables of the nf-fluid model (Sec. II-A states the two-fluid system
+   with a continuity and a volume-fraction equation per component; this is
+   the same system for nf components), stored in this order:
+     0 .. nf-1          partial densities alpha_i rho_i
+     nf, nf+1, nf+2     momentum rho u, rho v, rho w
+     nf+3               total energy rho E
+     nf+4 .. 2 nf+2     volume fractions alpha_1 .. alpha_{nf-1}
+   with alpha_nf = 1 - (alpha_1 + ... + alpha_{nf-1}).  Two fluids give the
+   seven variables (alpha1 rho1, alpha2 rho2, rho u, rho v, rho w, rho E,
+   alpha1).  Primitives: the same with (u, v, w, p) in place of momentum
+   and energy. */
+static int nfl(const orc_grid* g) { return g->nf >= 2 ? g->nf : 2; }
+static int nvar(const orc_grid* g) { return 2 * nfl(g) + 3; }
+static int imom(const orc_grid* g) { return nfl(g); }
+static int iene(const orc_grid* g) { return nfl(g) + 3; }
+static int ialf(const orc_grid* g) { return nfl(g) + 4; }
 
 /* ---------- equation of state (Sec. II-A) ---------- */
 
@@ -72,52 +92,64 @@ static double fluid_Pi(const orc_grid* g, int f)
 {
     return g->gamma[f] * g->pinf[f] / (g->gamma[f] - 1.0);
 }
-/* mixture 1/(gamma-1) */
-static double mix_Gamma(const orc_grid* g, double a1)
+/* Mixture rules, linear in the volume fractions a[0 .. nf-2] (the last
+   fluid takes 1 minus their sum): sum_i alpha_i c_i of the per-fluid
+   constants c_i.  For two fluids a1 c_1 + (1 - a1) c_2. */
+static double mix_linear(const orc_grid* g, const double* a, int pi)
 {
-    return a1 * fluid_Gamma(g, 0) + (1.0 - a1) * fluid_Gamma(g, 1);
+    const int nf = nfl(g);
+    double m = 0.0, s = 0.0;
+    for (int i = 0; i < nf - 1; ++i) {
+        m = m + a[i] * (pi ? fluid_Pi(g, i) : fluid_Gamma(g, i));
+        s = s + a[i];
+    }
+    return m + (1.0 - s) * (pi ? fluid_Pi(g, nf - 1) : fluid_Gamma(g, nf - 1));
 }
+/* mixture 1/(gamma-1) */
+static double mix_Gamma(const orc_grid* g, const double* a) { return mix_linear(g, a, 0); }
 /* mixture gamma*pi_inf/(gamma-1) */
-static double mix_Pi(const orc_grid* g, double a1)
+static double mix_Pi(const orc_grid* g, const double* a) { return mix_linear(g, a, 1); }
+
+static double mix_density(const orc_grid* g, const double* x)
 {
-    return a1 * fluid_Pi(g, 0) + (1.0 - a1) * fluid_Pi(g, 1);
+    double rho = x[0];
+    for (int i = 1; i < nfl(g); ++i) rho = rho + x[i];
+    return rho;
 }
 
 static void cons_to_prim(const orc_grid* g, const double* q, double* w)
 {
-    double rho = q[0] + q[1];
-    double u = q[2] / rho, v = q[3] / rho, ww = q[4] / rho;
+    const int m = imom(g), e = iene(g), a = ialf(g);
+    double rho = mix_density(g, q);
+    double u = q[m] / rho, v = q[m + 1] / rho, ww = q[m + 2] / rho;
     double ke = 0.5 * rho * (u * u + v * v + ww * ww);
-    double G = mix_Gamma(g, q[6]), P = mix_Pi(g, q[6]);
-    w[0] = q[0];
-    w[1] = q[1];
-    w[2] = u;
-    w[3] = v;
-    w[4] = ww;
-    w[5] = (q[5] - ke - P) / G;
-    w[6] = q[6];
+    double G = mix_Gamma(g, q + a), P = mix_Pi(g, q + a);
+    for (int i = 0; i < nvar(g); ++i) w[i] = q[i];
+    w[m] = u;
+    w[m + 1] = v;
+    w[m + 2] = ww;
+    w[e] = (q[e] - ke - P) / G;
 }
 
 static void prim_to_cons(const orc_grid* g, const double* w, double* q)
 {
-    double rho = w[0] + w[1];
-    double ke = 0.5 * rho * (w[2] * w[2] + w[3] * w[3] + w[4] * w[4]);
-    q[0] = w[0];
-    q[1] = w[1];
-    q[2] = rho * w[2];
-    q[3] = rho * w[3];
-    q[4] = rho * w[4];
-    q[5] = mix_Gamma(g, w[6]) * w[5] + mix_Pi(g, w[6]) + ke;
-    q[6] = w[6];
+    const int m = imom(g), e = iene(g), a = ialf(g);
+    double rho = mix_density(g, w);
+    double ke = 0.5 * rho * (w[m] * w[m] + w[m + 1] * w[m + 1] + w[m + 2] * w[m + 2]);
+    for (int i = 0; i < nvar(g); ++i) q[i] = w[i];
+    q[m] = rho * w[m];
+    q[m + 1] = rho * w[m + 1];
+    q[m + 2] = rho * w[m + 2];
+    q[e] = mix_Gamma(g, w + a) * w[e] + mix_Pi(g, w + a) + ke;
 }
 
 /* c^2 = ((Gamma+1) p + Pi) / (Gamma rho); for one pure fluid this is
    gamma (p + pi_inf) / rho. */
 static double sound_speed(const orc_grid* g, const double* w)
 {
-    double rho = w[0] + w[1];
-    double G = mix_Gamma(g, w[6]), P = mix_Pi(g, w[6]);
-    return sqrt(((G + 1.0) * w[5] + P) / (G * rho));
+    double rho = mix_density(g, w);
+    double G = mix_Gamma(g, w + ialf(g)), P = mix_Pi(g, w + ialf(g));
+    return sqrt(((G + 1.0) * w[iene(g)] + P) / (G * rho));
 }
 
 /* ---------- WENO5 (Jiang-Shu weights) ----------
@@ -236,17 +268,20 @@ static void reconstruct(const orc_grid* g, const double* st, double* left, doubl
 
 /* ---------- HLLC (Toro 2009, Davis wave speeds) ----------
    Face with normal along direction d; wl, wr primitive states.  Returns
-   the 7 flux components and the face velocity used for div(u). */
+   the flux of every variable and the face velocity used for div(u).  In
+   the star state every partial density and every volume fraction is
+   scaled by xi. */
 static void hllc(const orc_grid* g, const double* wl, const double* wr, int d, double* F,
                  double* uf)
 {
-    double rl = wl[0] + wl[1], rr = wr[0] + wr[1];
-    double pl = wl[5], pr = wr[5];
-    double unl = wl[2 + d], unr = wr[2 + d];
-    double El = mix_Gamma(g, wl[6]) * pl + mix_Pi(g, wl[6]) +
-                0.5 * rl * (wl[2] * wl[2] + wl[3] * wl[3] + wl[4] * wl[4]);
-    double Er = mix_Gamma(g, wr[6]) * pr + mix_Pi(g, wr[6]) +
-                0.5 * rr * (wr[2] * wr[2] + wr[3] * wr[3] + wr[4] * wr[4]);
+    const int nv = nvar(g), m = imom(g), e = iene(g), a = ialf(g), nf = nfl(g);
+    double rl = mix_density(g, wl), rr = mix_density(g, wr);
+    double pl = wl[e], pr = wr[e];
+    double unl = wl[m + d], unr = wr[m + d];
+    double El = mix_Gamma(g, wl + a) * pl + mix_Pi(g, wl + a) +
+                0.5 * rl * (wl[m] * wl[m] + wl[m + 1] * wl[m + 1] + wl[m + 2] * wl[m + 2]);
+    double Er = mix_Gamma(g, wr + a) * pr + mix_Pi(g, wr + a) +
+                0.5 * rr * (wr[m] * wr[m] + wr[m + 1] * wr[m + 1] + wr[m + 2] * wr[m + 2]);
     double cl = sound_speed(g, wl), cr = sound_speed(g, wr);
 
     double SL = fmin(unl - cl, unr - cr);
@@ -263,30 +298,28 @@ static void hllc(const orc_grid* g, const double* wl, const double* wr, int d, d
         w = wr; rho = rr; p = pr; un = unr; E = Er; S = SR; s = fmax(0.0, SR);
     }
 
-    double U[NV], Fk[NV], Us[NV];
-    U[0] = w[0];
-    U[1] = w[1];
-    U[2] = rho * w[2];
-    U[3] = rho * w[3];
-    U[4] = rho * w[4];
-    U[5] = E;
-    U[6] = w[6];
+    double U[NVMAX], Fk[NVMAX], Us[NVMAX];
+    for (int i = 0; i < nf; ++i) U[i] = w[i];
+    U[m] = rho * w[m];
+    U[m + 1] = rho * w[m + 1];
+    U[m + 2] = rho * w[m + 2];
+    U[e] = E;
+    for (int i = a; i < nv; ++i) U[i] = w[i];
 
-    for (int v = 0; v < NV; ++v) Fk[v] = U[v] * un;
-    Fk[2 + d] = Fk[2 + d] + p;
-    Fk[5] = (E + p) * un;
+    for (int v = 0; v < nv; ++v) Fk[v] = U[v] * un;
+    Fk[m + d] = Fk[m + d] + p;
+    Fk[e] = (E + p) * un;
 
     double xi = (S - un) / (S - Ss);
-    Us[0] = xi * w[0];
-    Us[1] = xi * w[1];
-    Us[2] = xi * (rho * w[2]);
-    Us[3] = xi * (rho * w[3]);
-    Us[4] = xi * (rho * w[4]);
-    Us[2 + d] = xi * (rho * Ss);
-    Us[5] = xi * (E + (Ss - un) * (rho * Ss + p / (S - un)));
-    Us[6] = xi * w[6];
+    for (int i = 0; i < nf; ++i) Us[i] = xi * w[i];
+    Us[m] = xi * (rho * w[m]);
+    Us[m + 1] = xi * (rho * w[m + 1]);
+    Us[m + 2] = xi * (rho * w[m + 2]);
+    Us[m + d] = xi * (rho * Ss);
+    Us[e] = xi * (E + (Ss - un) * (rho * Ss + p / (S - un)));
+    for (int i = a; i < nv; ++i) Us[i] = xi * w[i];
 
-    for (int v = 0; v < NV; ++v) F[v] = Fk[v] + s * (Us[v] - U[v]);
+    for (int v = 0; v < nv; ++v) F[v] = Fk[v] + s * (Us[v] - U[v]);
     *uf = un + s * (xi - 1.0);
 }
 
@@ -321,9 +354,9 @@ static int64_t map_index(const orc_grid* g, int d, int64_t i, int* flip)
    fixed state. */
 static void ghost_state(const orc_grid* g, int d, int64_t i, int kind, double* qc)
 {
-    if (kind == 1) qc[2 + d] = -qc[2 + d];
+    if (kind == 1) qc[imom(g) + d] = -qc[imom(g) + d];
     if (kind == 2)
-        for (int v = 0; v < NV; ++v) qc[v] = g->inflow[d][i < 0 ? 0 : 1][v];
+        for (int v = 0; v < nvar(g); ++v) qc[v] = g->inflow[d][i < 0 ? 0 : 1][v];
 }
 
 static int active(const orc_grid* g, int d) { return g->n[d] > 1; }
@@ -380,28 +413,30 @@ void orc_set_threads(int n)
 
 static int64_t ncells(const orc_grid* g) { return (int64_t)g->n[0] * g->n[1] * g->n[2]; }
 
-/* Whole-array conversions, layout [7][nz][ny][nx]. */
+/* Whole-array conversions, layout [nvar][nz][ny][nx]. */
 void orc_prim_to_cons(const orc_grid* g, const double* w, double* q)
 {
     int64_t N = ncells(g);
+    const int nv = nvar(g);
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < N; ++c) {
-        double wc[NV], qc[NV];
-        for (int v = 0; v < NV; ++v) wc[v] = w[v * N + c];
+        double wc[NVMAX], qc[NVMAX];
+        for (int v = 0; v < nv; ++v) wc[v] = w[v * N + c];
         prim_to_cons(g, wc, qc);
-        for (int v = 0; v < NV; ++v) q[v * N + c] = qc[v];
+        for (int v = 0; v < nv; ++v) q[v * N + c] = qc[v];
     }
 }
 
 void orc_cons_to_prim(const orc_grid* g, const double* q, double* w)
 {
     int64_t N = ncells(g);
+    const int nv = nvar(g);
 #pragma omp parallel for schedule(static)
     for (int64_t c = 0; c < N; ++c) {
-        double wc[NV], qc[NV];
-        for (int v = 0; v < NV; ++v) qc[v] = q[v * N + c];
+        double wc[NVMAX], qc[NVMAX];
+        for (int v = 0; v < nv; ++v) qc[v] = q[v * N + c];
         cons_to_prim(g, qc, wc);
-        for (int v = 0; v < NV; ++v) w[v * N + c] = wc[v];
+        for (int v = 0; v < nv; ++v) w[v * N + c] = wc[v];
     }
 }
 
@@ -550,7 +585,7 @@ static int corrected_weights(const double base[3], const double z[3], double om[
 static int admissible_edge(const orc_grid* g, const double w[NV], const double scale[NV], const double spread[NV],
                            int* near)
 {
-    const double G = mix_Gamma(g, w[6]), P = mix_Pi(g, w[6]);
+    const double G = mix_Gamma(g, w + 6), P = mix_Pi(g, w + 6);
     const double c2n = (G + 1.0) * w[5] + P;
     int fin = 1;
     for (int v = 0; v < NV; ++v) fin = fin && isfinite(w[v]);
@@ -646,7 +681,7 @@ static void learned_cell(const orc_grid* g, const orc_learn* L, double st[NV][5]
         const double* js = side == 0 ? jr : jl;
         if (L->plant == 3) { /* mistake: fallback per variable (only the variables that fail their own test) */
             const double* w = val[side];
-            const double c2n = (mix_Gamma(g, w[6]) + 1.0) * w[5] + mix_Pi(g, w[6]);
+            const double c2n = (mix_Gamma(g, w + 6) + 1.0) * w[5] + mix_Pi(g, w + 6);
             for (int v = 0; v < NV; ++v) {
                 int vok = fin[side] && isfinite(w[v]);
                 if (v == 0 || v == 1) vok = vok && w[v] >= 0.0;
@@ -679,7 +714,8 @@ static void rhs_impl(const orc_grid* g, const double* q, double* rhs, const orc_
     }
     const int64_t N = ncells(g);
     const int64_t NP = (int64_t)P[0] * P[1] * P[2];
-    double* wp = (double*)malloc(sizeof(double) * NV * NP);
+    const int nv = nvar(g), ia0 = ialf(g);
+    double* wp = (double*)malloc(sizeof(double) * nv * NP);
     int64_t nfb = 0, nnear = 0;
 
     /* padded primitive array: ghosts filled by the BC map, then converted */
@@ -693,18 +729,18 @@ static void rhs_impl(const orc_grid* g, const double* q, double* rhs, const orc_
                 int64_t si = map_index(g, 0, i - gh[0], &fi);
                 int64_t src = (sk * g->n[1] + sj) * g->n[0] + si;
                 int64_t dst = ((int64_t)k * P[1] + j) * P[0] + i;
-                double qc[NV], wc[NV];
-                for (int v = 0; v < NV; ++v) qc[v] = q[v * N + src];
+                double qc[NVMAX], wc[NVMAX];
+                for (int v = 0; v < nv; ++v) qc[v] = q[v * N + src];
                 /* reflective and inflow ghosts, per direction */
                 ghost_state(g, 0, i - gh[0], fi, qc);
                 ghost_state(g, 1, j - gh[1], fj, qc);
                 ghost_state(g, 2, k - gh[2], fk, qc);
                 cons_to_prim(g, qc, wc);
-                for (int v = 0; v < NV; ++v) wp[v * NP + dst] = wc[v];
+                for (int v = 0; v < nv; ++v) wp[v * NP + dst] = wc[v];
             }
         }
 
-    for (int64_t x = 0; x < NV * N; ++x) rhs[x] = 0.0;
+    for (int64_t x = 0; x < nv * N; ++x) rhs[x] = 0.0;
 
     /* one sweep per active direction, in the order x, y, z */
     for (int d = 0; d < 3; ++d) {
@@ -720,24 +756,24 @@ static void rhs_impl(const orc_grid* g, const double* q, double* rhs, const orc_
         for (int ib = 0; ib < g->n[b]; ++ib)
             for (int ia = 0; ia < g->n[a]; ++ia) {
                 /* edges of cells -1..n, faces 0..n (face f sits between f-1 and f) */
-                double* lft = (double*)malloc(sizeof(double) * NV * (n + 2));
-                double* rgt = (double*)malloc(sizeof(double) * NV * (n + 2));
-                double* F = (double*)malloc(sizeof(double) * NV * (n + 1));
+                double* lft = (double*)malloc(sizeof(double) * nv * (n + 2));
+                double* rgt = (double*)malloc(sizeof(double) * nv * (n + 2));
+                double* F = (double*)malloc(sizeof(double) * nv * (n + 1));
                 double* uf = (double*)malloc(sizeof(double) * (n + 1));
                 int* flag = L ? (int*)malloc(sizeof(int) * 4 * (n + 2)) : NULL;
                 int64_t base_p = (ia + gh[a]) * stride_p[a] + (ib + gh[b]) * stride_p[b];
                 int64_t base_n = ia * stride_n[a] + ib * stride_n[b];
                 for (int c = -1; c <= n; ++c) {
-                    double st7[NV][5];
-                    for (int v = 0; v < NV; ++v)
+                    double st[NVMAX][5];
+                    for (int v = 0; v < nv; ++v)
                         for (int o = -2; o <= 2; ++o)
-                            st7[v][o + 2] = wp[v * NP + base_p + (int64_t)(c + gh[d] + o) * stride_p[d]];
-                    if (L) {
+                            st[v][o + 2] = wp[v * NP + base_p + (int64_t)(c + gh[d] + o) * stride_p[d]];
+                    if (L) { /* two fluids (nv == NV) */
                         int* fl = &flag[4 * (c + 1)];
-                        learned_cell(g, L, st7, &lft[(c + 1) * NV], &rgt[(c + 1) * NV], fl, fl + 2);
+                        learned_cell(g, L, st, &lft[(c + 1) * nv], &rgt[(c + 1) * nv], fl, fl + 2);
                     } else {
-                        for (int v = 0; v < NV; ++v)
-                            reconstruct(g, st7[v], &lft[(c + 1) * NV + v], &rgt[(c + 1) * NV + v]);
+                        for (int v = 0; v < nv; ++v)
+                            reconstruct(g, st[v], &lft[(c + 1) * nv + v], &rgt[(c + 1) * nv + v]);
                     }
                 }
                 if (L) {
@@ -748,13 +784,16 @@ static void rhs_impl(const orc_grid* g, const double* q, double* rhs, const orc_
                     }
                 }
                 for (int f = 0; f <= n; ++f)
-                    hllc(g, &rgt[f * NV], &lft[(f + 1) * NV], d, &F[f * NV], &uf[f]);
+                    hllc(g, &rgt[f * nv], &lft[(f + 1) * nv], d, &F[f * nv], &uf[f]);
                 for (int i = 0; i < n; ++i) {
                     int64_t cell = base_n + (int64_t)i * stride_n[d];
-                    double a1 = wp[6 * NP + base_p + (int64_t)(i + gh[d]) * stride_p[d]];
-                    for (int v = 0; v < NV; ++v)
-                        rhs[v * N + cell] += (F[i * NV + v] - F[(i + 1) * NV + v]) / g->dx[d];
-                    rhs[6 * N + cell] += a1 * ((uf[i + 1] - uf[i]) / g->dx[d]);
+                    for (int v = 0; v < nv; ++v)
+                        rhs[v * N + cell] += (F[i * nv + v] - F[(i + 1) * nv + v]) / g->dx[d];
+                    /* every volume-fraction equation carries alpha_i div(u) */
+                    for (int v = ia0; v < nv; ++v) {
+                        double ai = wp[v * NP + base_p + (int64_t)(i + gh[d]) * stride_p[d]];
+                        rhs[v * N + cell] += ai * ((uf[i + 1] - uf[i]) / g->dx[d]);
+                    }
                 }
                 free(lft);
                 free(rgt);
@@ -784,6 +823,10 @@ void orc_rhs(const orc_grid* g, const double* q, double* rhs) { rhs_impl(g, q, r
 void orc_rhs_learned(const orc_grid* g, const double* q, const double* theta, int mode, int plant, double* rhs,
                      int64_t* counts)
 {
+    if (nvar(g) != NV) { /* the learned weights are defined for two fluids */
+        for (int64_t x = 0; x < nvar(g) * ncells(g); ++x) rhs[x] = NAN;
+        return;
+    }
     orc_mlp m;
     mlp_load(theta, &m);
     orc_learn L = {&m, mode == 2 ? 2 : 1, plant};
@@ -806,45 +849,47 @@ void orc_mlp_omega(const double* theta, int64_t n, const double* x, const double
 double orc_gelu(double a) { return gelu_tanh(a); }
 
 /* ---------- right-hand side at selected cells, one by one ----------
-   cells: linear indices (k*ny + j)*nx + i; out: [ncell][7].  Uses the same
+   cells: linear indices (k*ny + j)*nx + i; out: [ncell][nvar].  Uses the same
    per-cell formulas with the BC map applied to each stencil index, and the
    same accumulation order, so it equals orc_rhs at those cells. */
 void orc_rhs_at(const orc_grid* g, const double* q, int64_t ncell, const int64_t* cells, double* out)
 {
     const int64_t N = ncells(g);
+    const int nv = nvar(g), ia0 = ialf(g);
     int64_t stride_n[3] = {1, g->n[0], (int64_t)g->n[0] * g->n[1]};
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t c = 0; c < ncell; ++c) {
         int64_t lin = cells[c];
         int64_t pos[3] = {lin % g->n[0], (lin / g->n[0]) % g->n[1], lin / ((int64_t)g->n[0] * g->n[1])};
-        double r[NV] = {0, 0, 0, 0, 0, 0, 0};
+        double r[NVMAX];
+        for (int v = 0; v < nv; ++v) r[v] = 0.0;
         for (int d = 0; d < 3; ++d) {
             if (!active(g, d)) continue;
-            double w7[7][NV];
+            double w7[7][NVMAX];
             for (int o = -3; o <= 3; ++o) {
                 int64_t p2[3] = {pos[0], pos[1], pos[2]};
                 int flip;
                 p2[d] = map_index(g, d, pos[d] + o, &flip);
                 int64_t src = p2[0] * stride_n[0] + p2[1] * stride_n[1] + p2[2] * stride_n[2];
-                double qc[NV];
-                for (int v = 0; v < NV; ++v) qc[v] = q[v * N + src];
+                double qc[NVMAX];
+                for (int v = 0; v < nv; ++v) qc[v] = q[v * N + src];
                 ghost_state(g, d, pos[d] + o, flip, qc);
                 cons_to_prim(g, qc, w7[o + 3]);
             }
-            double lft[3][NV], rgt[3][NV];
+            double lft[3][NVMAX], rgt[3][NVMAX];
             for (int cc = 0; cc < 3; ++cc)
-                for (int v = 0; v < NV; ++v) {
+                for (int v = 0; v < nv; ++v) {
                     double st[5];
                     for (int o = 0; o < 5; ++o) st[o] = w7[cc + o][v];
                     reconstruct(g, st, &lft[cc][v], &rgt[cc][v]);
                 }
-            double Fm[NV], Fp[NV], um, up;
+            double Fm[NVMAX], Fp[NVMAX], um, up;
             hllc(g, rgt[0], lft[1], d, Fm, &um);
             hllc(g, rgt[1], lft[2], d, Fp, &up);
-            for (int v = 0; v < NV; ++v) r[v] += (Fm[v] - Fp[v]) / g->dx[d];
-            r[6] += w7[3][6] * ((up - um) / g->dx[d]);
+            for (int v = 0; v < nv; ++v) r[v] += (Fm[v] - Fp[v]) / g->dx[d];
+            for (int v = ia0; v < nv; ++v) r[v] += w7[3][v] * ((up - um) / g->dx[d]);
         }
-        for (int v = 0; v < NV; ++v) out[c * NV + v] = r[v];
+        for (int v = 0; v < nv; ++v) out[c * nv + v] = r[v];
     }
 }
 
@@ -855,13 +900,13 @@ double orc_cfl_dt(const orc_grid* g, const double* q)
     double smax = 0.0;
 #pragma omp parallel for reduction(max : smax) schedule(static)
     for (int64_t c = 0; c < N; ++c) {
-        double qc[NV], wc[NV];
-        for (int v = 0; v < NV; ++v) qc[v] = q[v * N + c];
+        double qc[NVMAX], wc[NVMAX];
+        for (int v = 0; v < nvar(g); ++v) qc[v] = q[v * N + c];
         cons_to_prim(g, qc, wc);
         double cs = sound_speed(g, wc);
         double s = 0.0;
         for (int d = 0; d < 3; ++d)
-            if (active(g, d)) s = s + (fabs(wc[2 + d]) + cs) / g->dx[d];
+            if (active(g, d)) s = s + (fabs(wc[imom(g) + d]) + cs) / g->dx[d];
         if (s > smax) smax = s;
     }
     return g->cfl / smax;
@@ -889,7 +934,7 @@ void orc_rk3_combine(int stage, int64_t n, const double* qn, const double* qs, c
    Returns the time step used. */
 double orc_rk3_step(const orc_grid* g, double* q, double dt)
 {
-    const int64_t M = NV * ncells(g);
+    const int64_t M = nvar(g) * ncells(g);
     if (!(dt > 0.0)) dt = orc_cfl_dt(g, q);
     double* L = (double*)malloc(sizeof(double) * M);
     double* q1 = (double*)malloc(sizeof(double) * M);

@@ -21,6 +21,9 @@ shock-bubble-cloud runs; these are single-GPU blocks of the same physics):
   random_smooth   small random valid states for RHS parity
   advected_slab, shock_tube_family
                   1D families for training and evaluating the learned weights
+  random_smooth_nf, droplet_bubble
+                  the same for more than two fluids (variables: nf partial
+                  densities, u, v, w, p, volume fractions 1 .. nf-1)
 """
 from __future__ import annotations
 
@@ -31,6 +34,9 @@ import numpy as np
 PERIODIC, TRANSMISSIVE, REFLECTIVE, INFLOW = 0, 1, 2, 3
 WATER = (4.4, 6.0e8)
 AIR = (1.4, 0.0)
+HELIUM = (5.0 / 3.0, 0.0)
+SF6 = (1.1, 0.0)
+FLUIDS = (WATER, AIR, HELIUM, SF6)  # fluid i of an nf-fluid problem is FLUIDS[i]
 ALPHA_EPS = 1.0e-6
 
 
@@ -46,6 +52,28 @@ def spec(n, bc, cfl=0.4, eps=1e-6):
         "eps": float(eps),
         "cfl": float(cfl),
     }
+
+
+def spec_fluids(n, bc, nf, cfl=0.4, eps=1e-6):
+    """Grid description of an nf-fluid problem (fluids FLUIDS[:nf])."""
+    s = spec(n, bc, cfl, eps)
+    s["gamma"] = tuple(f[0] for f in FLUIDS[:nf])
+    s["pinf"] = tuple(f[1] for f in FLUIDS[:nf])
+    return s
+
+
+def _pack_nf(alphas, rhos, u, v, w, p):
+    """Primitives of the nf-fluid model: alpha_i rho_i (i = 1..nf), u, v, w,
+    p, alpha_1 .. alpha_{nf-1}; the alphas are the nf volume fractions."""
+    nf = len(alphas)
+    shape = np.broadcast(*alphas, *rhos, u, v, w, p).shape
+    out = np.empty((2 * nf + 3,) + shape, dtype=np.float64)
+    for i in range(nf):
+        out[i] = alphas[i] * rhos[i]
+    out[nf], out[nf + 1], out[nf + 2], out[nf + 3] = u, v, w, p
+    for i in range(nf - 1):
+        out[nf + 4 + i] = alphas[i]
+    return out
 
 
 def _centres(n):
@@ -340,3 +368,73 @@ def random_smooth(n=(24, 20, 16), seed=0, bc=None, jumps=True):
         p = np.where(Y < rng.uniform(0.3, 0.7), p * 20.0, p)
     w = _pack(a1, rho1, rho2, u, v, w_, p)
     return {"name": "random_smooth", "spec": s, "w": w}
+
+
+def random_smooth_nf(n=(24, 20, 16), seed=0, bc=None, nf=3, jumps=True):
+    """Random valid nf-fluid state: smooth Fourier-mode volume fractions
+    (each in about [0.05, 0.8], summing to 1), phase densities, velocity and
+    pressure, plus (optionally) a region of nearly pure fluid 1 and a 20x
+    pressure jump.  bc defaults to periodic."""
+    n3 = tuple(int(v) for v in n)
+    rng = np.random.default_rng(seed)
+    if bc is None:
+        bc = ((PERIODIC, PERIODIC),) * 3
+    s = spec_fluids(n3, bc, nf)
+    Z, Y, X = _centres(n3)
+
+    def field(amp):
+        f = np.zeros(X.shape)
+        for _ in range(3):
+            k = rng.integers(1, 3, size=3)
+            ph = rng.uniform(0, 2 * math.pi, size=3)
+            f += rng.uniform(-1, 1) * np.sin(2 * math.pi * k[0] * X + ph[0]) * \
+                np.sin(2 * math.pi * k[1] * Y + ph[1]) * np.sin(2 * math.pi * k[2] * Z + ph[2])
+        return amp * f / 3.0
+
+    raw = [1.0 + field(0.8) for _ in range(nf)]
+    tot = sum(raw)
+    alphas = [r / tot for r in raw]
+    base = (1000.0, 1.2, 0.17, 6.0)
+    rhos = [base[i] * (1.0 + field(0.2)) for i in range(nf)]
+    u, v, w_ = field(50.0), field(50.0), field(50.0)
+    p = 1.0e5 * (1.0 + field(0.5))
+    if jumps:
+        inside = X < rng.uniform(0.3, 0.7)
+        alphas = [np.where(inside, 1.0 - (nf - 1) * ALPHA_EPS if i == 0 else ALPHA_EPS, a)
+                  for i, a in enumerate(alphas)]
+        p = np.where(Y < rng.uniform(0.3, 0.7), p * 20.0, p)
+    return {"name": f"random_smooth_{nf}f", "spec": s, "w": _pack_nf(alphas, rhos, u, v, w_, p)}
+
+
+def droplet_bubble(n=256, seed=0, mach=2.0, radius=0.15, bubble=0.08, noise=0.01):
+    """Three fluids: the shock_droplet problem (Mach-2 air shock 4 cells
+    upstream of a water droplet of radius 0.15, 1% density noise) with a
+    helium bubble (radius 0.08) in the air beside the droplet, at a seeded
+    centre.  Fluids: water, air, helium; x transmissive, y/z periodic."""
+    n3 = (n, n, n) if np.isscalar(n) else tuple(n)
+    rng = np.random.default_rng(seed)
+    c = 0.5 + rng.uniform(-0.05, 0.05, size=3)
+    cb = np.array([c[0] + rng.uniform(-0.05, 0.05), c[1] + radius + bubble + 0.06, c[2] + rng.uniform(-0.05, 0.05)])
+    s = spec_fluids(n3, ((TRANSMISSIVE, TRANSMISSIVE), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)), 3)
+    Z, Y, X = _centres(n3)
+    h = 1.0 / n3[0]
+    r = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)
+    rb = np.sqrt((X - cb[0]) ** 2 + (Y - cb[1]) ** 2 + (Z - cb[2]) ** 2)
+    water = _smooth_indicator(r, radius, 1.5 * h)
+    helium = _smooth_indicator(rb, bubble, 1.5 * h) * (1.0 - water)
+    a_w = ALPHA_EPS + (1.0 - 3.0 * ALPHA_EPS) * water
+    a_h = ALPHA_EPS + (1.0 - 3.0 * ALPHA_EPS) * helium
+    a_a = 1.0 - a_w - a_h
+    rho_a1, p_a1 = 1.2, 1.0e5
+    rho_a2, p_a2, u_a2 = _ideal_gas_shock(mach, rho_a1, p_a1, AIR[0])
+    xs = min(c[0] - radius, cb[0] - bubble) - 4.0 * h
+    post = X < xs
+    rho_air = np.where(post, rho_a2, rho_a1)
+    p = np.where(post, p_a2, p_a1)
+    u = np.where(post, u_a2, 0.0)
+    w = _pack_nf([a_w, a_a, a_h], [1000.0, rho_air, 0.17], u, 0.0, 0.0, p)
+    f = _noise(rng, a_w.shape, noise)
+    for i in range(3):
+        w[i] *= f
+    return {"name": "droplet_bubble", "spec": s, "w": w,
+            "meta": {"centre": c.tolist(), "bubble_centre": cb.tolist(), "shock_x": xs}}
