@@ -14,10 +14,12 @@
  * conditions) are fixed as documented for each call below.
  *
  * Data layout (every call): conserved state q is float64, structure of
- * arrays, q[v][k][j][i] with x (i) fastest, no ghost cells, v =
- *   0 alpha1*rho1, 1 alpha2*rho2, 2 rho*u, 3 rho*v, 4 rho*w, 5 rho*E, 6 alpha1.
+ * arrays, q[v][k][j][i] with x (i) fastest, no ghost cells; two fluids:
+ *   0 alpha1*rho1, 1 alpha2*rho2, 2 rho*u, 3 rho*v, 4 rho*w, 5 rho*E, 6 alpha1;
+ * nf fluids (mfx_grid_desc.num_fluids): alpha_i rho_i (i = 1..nf), rho u,
+ * rho v, rho w, rho E, alpha_1 .. alpha_{nf-1}, 2 nf + 3 variables.
  * Primitive layout (mfx_set_primitive) is the same with (u, v, w, p) in
- * slots 2..5.  All pointers named *_dev are device pointers on the device
+ * place of momentum and energy.  All pointers named *_dev are device pointers on the device
  * current when mfx_init_grid was called.
  *
  * Ownership: the caller owns the workspace and every state buffer; the
@@ -97,13 +99,18 @@ enum { MFX_FP64 = 0, MFX_FP32_MIXED = 1 };
  * form for the learned weights; any precision form. */
 enum { MFX_WENO5_JS = 0, MFX_WENO5_LEARNED = 1, MFX_WENO5_LEARNED_EDGE = 2, MFX_WENO5_Z = 3 };
 
+/* Fluids the library takes (num_fluids), and the variables of the largest
+ * model (2 * fluids + 3). */
+#define MFX_MAX_FLUIDS 3
+#define MFX_MAX_VARS (2 * MFX_MAX_FLUIDS + 3)
+
 typedef struct {
     int32_t n[3];      /* interior cells (nx, ny, nz), each >= 1; n == 1 makes a direction inactive */
     double lo[3];      /* domain origin (informational) */
     double dx[3];      /* uniform spacing per direction, > 0 */
     int32_t bc[3][2];  /* lower/upper MFX_BC_* per direction; periodic must be paired */
-    double gamma[2];   /* stiffened-gas gamma of fluid 1 and fluid 2, > 1 */
-    double pi_inf[2];  /* stiffened-gas pi_inf of fluid 1 and fluid 2, >= 0 */
+    double gamma[MFX_MAX_FLUIDS];  /* stiffened-gas gamma of each fluid, > 1 (the first num_fluids used) */
+    double pi_inf[MFX_MAX_FLUIDS]; /* stiffened-gas pi_inf of each fluid, >= 0 */
     double cfl;        /* CFL number for the automatic time step, in (0, 1] */
     double weno_eps;   /* WENO epsilon (absolute), > 0; 1e-6 is Jiang-Shu's value */
     int32_t precision; /* MFX_FP64 or MFX_FP32_MIXED */
@@ -111,10 +118,19 @@ typedef struct {
     int32_t weno_order; /* reconstruction order, 5 or 3 (Sec. II-B names both; 0 reads as 5):
                            WENO3 with Jiang-Shu weights on the middle three cells of each
                            stencil; the learned and WENO-Z weights need 5 (MFX_EINVAL otherwise) */
-    double inflow[3][2][7]; /* conserved ghost state (alpha1 rho1, alpha2 rho2, rho u, rho v, rho w,
-                               rho E, alpha1) of each MFX_BC_INFLOW side [direction][lower/upper];
-                               finite, partial densities >= 0 with a positive sum, alpha1 in
-                               [0, 1] (MFX_EINVAL otherwise); ignored for other sides */
+    double inflow[3][2][MFX_MAX_VARS]; /* conserved ghost state (the first 2 num_fluids + 3 entries,
+                               in the state layout) of each MFX_BC_INFLOW side [direction][lower/upper];
+                               finite, partial densities >= 0 with a positive sum, volume fractions
+                               in [0, 1] summing to at most 1 (MFX_EINVAL otherwise); ignored for
+                               other sides */
+    int32_t num_fluids; /* fluids of the model, 2 .. MFX_MAX_FLUIDS (0 reads as 2).  Sec. II-A
+                           states the system for two components with a continuity and a
+                           volume-fraction equation per component; with nf components the state
+                           holds nf partial densities, the momentum, the energy and the volume
+                           fractions alpha_1 .. alpha_{nf-1} (alpha_nf = 1 - their sum), the mixture
+                           rules stay linear in every fraction and every fraction carries its
+                           alpha_i div(u) source.  More than two fluids: Jiang-Shu or WENO-Z
+                           weights (the learned weights are for two), marching x sweep */
 } mfx_grid_desc;
 
 typedef struct mfx_ctx mfx_ctx;

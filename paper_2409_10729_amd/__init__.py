@@ -35,8 +35,9 @@ def inflow_states(spec: dict, prim) -> "np.ndarray":
     import numpy as np
     import torch
 
-    prim = np.asarray(prim, dtype=np.float64).reshape(3, 2, 7)
-    out = np.zeros((3, 2, 7))
+    nv = _native.nvars(spec)
+    prim = np.asarray(prim, dtype=np.float64).reshape(3, 2, nv)
+    out = np.zeros((3, 2, nv))
     one = dict(spec, n=(1, 1, 1), bc=((MFX_BC_PERIODIC, MFX_BC_PERIODIC),) * 3)
     one.pop("inflow", None)
     for d in range(3):
@@ -44,8 +45,8 @@ def inflow_states(spec: dict, prim) -> "np.ndarray":
             if not prim[d, s].any():
                 continue
             sol = Solver(one)
-            sol.set_primitive(torch.from_numpy(prim[d, s].reshape(7, 1, 1, 1).copy()).cuda())
-            out[d, s] = sol.get_state().cpu().numpy().reshape(7)
+            sol.set_primitive(torch.from_numpy(prim[d, s].reshape(nv, 1, 1, 1).copy()).cuda())
+            out[d, s] = sol.get_state().cpu().numpy().reshape(nv)
     return out
 
 
@@ -58,7 +59,8 @@ class Solver:
     :mod:`paper_2409_10729_amd.workloads`.  bc per direction and side:
     MFX_BC_PERIODIC, MFX_BC_TRANSMISSIVE, MFX_BC_REFLECTIVE or MFX_BC_INFLOW.
     Arrays passed in and out are torch tensors on the device, float64,
-    shape [7, nz, ny, nx].
+    shape [nv, nz, ny, nx] with nv = 2 * (number of fluids in spec["gamma"]) + 3
+    (7 for two fluids).
     """
 
     def __init__(self, spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS, stream=None):
@@ -68,7 +70,7 @@ class Solver:
             raise RuntimeError("mfx needs a HIP device; none is visible to torch")
         self._torch = torch
         self.spec = spec
-        self.shape = (7, int(spec["n"][2]), int(spec["n"][1]), int(spec["n"][0]))
+        self.shape = (_native.nvars(spec), int(spec["n"][2]), int(spec["n"][1]), int(spec["n"][0]))
         L = _native.lib()
         self._desc = _native.make_desc(spec, precision, weights)
         nbytes = int(L.mfx_workspace_bytes(ctypes.byref(self._desc)))

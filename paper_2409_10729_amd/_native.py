@@ -28,6 +28,13 @@ EXPORTED = (
     "mfx_mlp_last_error",
 )
 MLP_PARAMS = 1347
+MAX_FLUIDS = 3
+MAX_VARS = 2 * MAX_FLUIDS + 3
+
+
+def nvars(spec: dict) -> int:
+    """Variables per cell of a problem: 2 * (number of fluids) + 3."""
+    return 2 * len(spec["gamma"]) + 3
 PROF_KINDS = 40
 
 
@@ -37,14 +44,15 @@ class GridDesc(ctypes.Structure):
         ("lo", ctypes.c_double * 3),
         ("dx", ctypes.c_double * 3),
         ("bc", (ctypes.c_int32 * 2) * 3),
-        ("gamma", ctypes.c_double * 2),
-        ("pi_inf", ctypes.c_double * 2),
+        ("gamma", ctypes.c_double * MAX_FLUIDS),
+        ("pi_inf", ctypes.c_double * MAX_FLUIDS),
         ("cfl", ctypes.c_double),
         ("weno_eps", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("weights", ctypes.c_int32),
         ("weno_order", ctypes.c_int32),
-        ("inflow", ((ctypes.c_double * 7) * 2) * 3),
+        ("inflow", ((ctypes.c_double * MAX_VARS) * 2) * 3),
+        ("num_fluids", ctypes.c_int32),
     ]
 
 
@@ -126,18 +134,23 @@ def make_desc(spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS
         d.dx[k] = float(spec["dx"][k])
         d.bc[k][0] = int(spec["bc"][k][0])
         d.bc[k][1] = int(spec["bc"][k][1])
-    d.gamma[0], d.gamma[1] = map(float, spec["gamma"])
-    d.pi_inf[0], d.pi_inf[1] = map(float, spec["pinf"])
+    gam, pin = list(map(float, spec["gamma"])), list(map(float, spec["pinf"]))
+    if not (2 <= len(gam) <= MAX_FLUIDS and len(pin) == len(gam)):
+        raise ValueError(f"gamma and pinf must list 2..{MAX_FLUIDS} fluids alike")
+    d.num_fluids = len(gam)
+    for f in range(len(gam)):
+        d.gamma[f], d.pi_inf[f] = gam[f], pin[f]
     d.cfl = float(spec.get("cfl", 0.4))
     d.weno_eps = float(spec.get("eps", 1e-6))
     d.precision = int(precision)
     d.weights = int(weights)
     d.weno_order = int(spec.get("weno_order", 5))
     if "inflow" in spec:
+        nv = 2 * len(gam) + 3
         a = [[list(map(float, side)) for side in pair] for pair in spec["inflow"]]
         for k in range(3):
             for s in range(2):
-                for v in range(7):
+                for v in range(nv):
                     d.inflow[k][s][v] = a[k][s][v]
     return d
 

@@ -425,6 +425,7 @@ int mfx_mlp_sample_stencils(const mfx_grid_desc* desc, const double* q_dev, cons
 {
     if (!desc || !q_dev || !face_prim_dev || !stencil_out || !target_out) return err(MFX_EINVAL, "NULL argument");
     if (desc->n[1] != 1 || desc->n[2] != 1 || desc->n[0] < 1) return err(MFX_EINVAL, "sampling needs a 1D grid (n = nx,1,1)");
+    if (desc->num_fluids != 0 && desc->num_fluids != 2) return err(MFX_EINVAL, "the learned weights are for two fluids");
     if (desc->bc[0][0] >= MFX_BC_REFLECTIVE || desc->bc[0][1] >= MFX_BC_REFLECTIVE)
         return err(MFX_EINVAL, "sampling takes periodic or transmissive ends");
     Grid g{};
@@ -446,6 +447,8 @@ int mfx_mlp_face_targets(const mfx_grid_desc* fine_desc, const double* q_fine_de
 {
     if (!fine_desc || !q_fine_dev || !face_prim_out) return err(MFX_EINVAL, "NULL argument");
     if (fine_desc->n[1] != 1 || fine_desc->n[2] != 1) return err(MFX_EINVAL, "face targets need a 1D grid");
+    if (fine_desc->num_fluids != 0 && fine_desc->num_fluids != 2)
+        return err(MFX_EINVAL, "the learned weights are for two fluids");
     if (refine < 1 || fine_desc->n[0] % refine != 0) return err(MFX_EINVAL, "refine must divide nx of the fine grid");
     if (fine_desc->bc[0][0] >= MFX_BC_REFLECTIVE || fine_desc->bc[0][1] >= MFX_BC_REFLECTIVE)
         return err(MFX_EINVAL, "face targets take periodic or transmissive ends");

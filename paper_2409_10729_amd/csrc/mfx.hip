@@ -35,6 +35,10 @@ thread_local std::string g_init_error;
 
 size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
+// Fluids and variables of a descriptor (num_fluids 0 reads as 2).
+int fluids_of(const mfx_grid_desc* d) { return d->num_fluids == 0 ? 2 : d->num_fluids; }
+int vars_of(const mfx_grid_desc* d) { return 2 * fluids_of(d) + 3; }
+
 // Launch-shape overrides for tuning and tests (results do not depend on
 // them): MFX_SWEEP_SEG = segment length of the marching sweeps,
 // MFX_XSWEEP = "march" to force the marching x sweep.
@@ -80,9 +84,11 @@ bool use_xrows(const int n[3], int mode_override, size_t elem)
 }
 
 // x sweep mode for a descriptor: the override, or the march (1) when an x
-// side is inflow and the row buffers would be aliased.
+// side is inflow and the row buffers would be aliased, or for more than two
+// fluids.
 int x_mode(const mfx_grid_desc* d, int xmode_override)
 {
+    if (fluids_of(d) != 2) return 1;  // the row kernels are written for two fluids
     const size_t elem = d->precision == MFX_FP32_MIXED ? sizeof(float) : sizeof(double);
     const bool inflow_x = d->bc[0][0] == MFX_BC_INFLOW || d->bc[0][1] == MFX_BC_INFLOW;
     if (inflow_x && d->n[0] <= XROW_MAX && xrow_layout(d->n[0], elem).alias) return 1;
@@ -130,7 +136,8 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
 {
     Layout L{};
     const long long N = (long long)d->n[0] * d->n[1] * d->n[2];
-    const size_t state = align_up(sizeof(double) * 7 * (size_t)N);
+    const size_t nv = (size_t)vars_of(d);
+    const size_t state = align_up(sizeof(double) * nv * (size_t)N);
     const size_t elem = d->precision == MFX_FP32_MIXED ? sizeof(float) : sizeof(double);
     // per-block maxima of the CFL reduction: the standalone pass, or the
     // blocks of a y/z sweep that reduces the new state of a step
@@ -148,11 +155,11 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     L.q2 = off;
     off += state;
     L.r = off;
-    off += align_up(elem * 7 * (size_t)N);
+    off += align_up(elem * nv * (size_t)N);
     L.scal = off;
     off += align_up(64);
-    L.inflow = off;  // the inflow ghost states [3][2][7], read by the loaders
-    off += align_up(sizeof(double) * 3 * 2 * NV);
+    L.inflow = off;  // the inflow ghost states [3][2][NVMAX], read by the loaders
+    off += align_up(sizeof(double) * 3 * 2 * NVMAX);
     L.partial = off;
     off += align_up(sizeof(double) * (size_t)np);
     L.bface = off;
@@ -195,6 +202,11 @@ bool validate(const mfx_grid_desc* d, std::string& why)
         why = "descriptor is NULL";
         return false;
     }
+    if (d->num_fluids != 0 && (d->num_fluids < 2 || d->num_fluids > MFX_MAX_FLUIDS)) {
+        why = "num_fluids must lie in [2, " + std::to_string(MFX_MAX_FLUIDS) + "] (0 reads as 2)";
+        return false;
+    }
+    const int nf = fluids_of(d), nv = vars_of(d);
     long long N = 1;
     for (int k = 0; k < 3; ++k) {
         if (d->n[k] < 1 || d->n[k] > 65535) {
@@ -215,11 +227,21 @@ bool validate(const mfx_grid_desc* d, std::string& why)
             if (d->bc[k][s] == MFX_BC_INFLOW) {
                 const double* q = d->inflow[k][s];
                 bool ok = true;
-                for (int v = 0; v < 7; ++v) ok = ok && std::isfinite(q[v]);
-                ok = ok && q[0] >= 0.0 && q[1] >= 0.0 && q[0] + q[1] > 0.0 && q[6] >= 0.0 && q[6] <= 1.0;
+                for (int v = 0; v < nv; ++v) ok = ok && std::isfinite(q[v]);
+                double rho = 0.0, asum = 0.0;
+                for (int f = 0; f < nf; ++f) {
+                    ok = ok && q[f] >= 0.0;
+                    rho += q[f];
+                }
+                for (int a = nf + 4; a < nv; ++a) {
+                    ok = ok && q[a] >= 0.0 && q[a] <= 1.0;
+                    asum += q[a];
+                }
+                ok = ok && rho > 0.0 && asum <= 1.0;
                 if (!ok) {
                     why = "inflow[" + std::to_string(k) + "][" + std::to_string(s) +
-                          "] must be finite, with partial densities >= 0, a positive density and alpha_1 in [0, 1]";
+                          "] must be finite, with partial densities >= 0, a positive density and volume fractions in "
+                          "[0, 1] summing to at most 1";
                     return false;
                 }
             }
@@ -241,7 +263,7 @@ bool validate(const mfx_grid_desc* d, std::string& why)
         why = "grid too large for one context (more than 2^31 cells)";
         return false;
     }
-    for (int f = 0; f < 2; ++f) {
+    for (int f = 0; f < nf; ++f) {
         if (!(d->gamma[f] > 1.0) || !std::isfinite(d->gamma[f])) {
             why = "gamma must be finite and > 1";
             return false;
@@ -276,15 +298,42 @@ bool validate(const mfx_grid_desc* d, std::string& why)
         why = "the learned and WENO-Z weights need weno_order 5";
         return false;
     }
+    if (nf != 2 && (d->weights == MFX_WENO5_LEARNED || d->weights == MFX_WENO5_LEARNED_EDGE)) {
+        why = "the learned weights are defined for two fluids";
+        return false;
+    }
     return true;
 }
 
 // ---------------------------------------------------------------- kernels
 
+template <class F>
 __global__ void __launch_bounds__(UTIL_BLOCK) prim_to_cons_kernel(Grid g, const double* __restrict__ w,
                                                                   double* __restrict__ q)
 {
     const long long N = g.N;
+    if constexpr (F::NF != 2) {
+        // the model's total energy rho E = Gamma p + Pi + rho |u|^2 / 2,
+        // Gamma and Pi linear in the volume fractions (Sec. II-A)
+        const MixN<double, F::NF> mix = make_mix<double, F>(g);
+        for (long long c = blockIdx.x * (long long)UTIL_BLOCK + threadIdx.x; c < N;
+             c += (long long)gridDim.x * UTIL_BLOCK) {
+            double wc[F::NV];
+#pragma unroll
+            for (int v = 0; v < F::NV; ++v) wc[v] = w[v * N + c];
+            const double rho = density_n<F::NF>(wc);
+            const double u = wc[F::IM], v = wc[F::IM + 1], ww = wc[F::IM + 2];
+            const double ke = 0.5 * rho * (u * u + v * v + ww * ww);
+            const double G = mix.Gamma(wc + F::IA), P = mix.Pi(wc + F::IA);
+#pragma unroll
+            for (int k = 0; k < F::NV; ++k) q[k * N + c] = wc[k];
+            q[F::IM * N + c] = rho * u;
+            q[(F::IM + 1) * N + c] = rho * v;
+            q[(F::IM + 2) * N + c] = rho * ww;
+            q[F::IE * N + c] = G * wc[F::IE] + P + ke;
+        }
+        return;
+    }
     for (long long c = blockIdx.x * (long long)UTIL_BLOCK + threadIdx.x; c < N;
          c += (long long)gridDim.x * UTIL_BLOCK) {
         const double a1 = w[6 * N + c];
@@ -304,6 +353,7 @@ __global__ void __launch_bounds__(UTIL_BLOCK) prim_to_cons_kernel(Grid g, const 
 }
 
 // CFL partial maxima over the state q, with the validity checks.
+template <class F>
 __global__ void __launch_bounds__(UTIL_BLOCK) cfl_partial_kernel(Grid g, const double* __restrict__ q,
                                                                  double* __restrict__ partial,
                                                                  unsigned* __restrict__ status)
@@ -313,10 +363,10 @@ __global__ void __launch_bounds__(UTIL_BLOCK) cfl_partial_kernel(Grid g, const d
     unsigned bad = 0;
     for (long long c = blockIdx.x * (long long)UTIL_BLOCK + threadIdx.x; c < N;
          c += (long long)gridDim.x * UTIL_BLOCK) {
-        double qc[NV];
+        double qc[F::NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) qc[v] = q[v * N + c];
-        smax = fmax(smax, cfl_speed(g, qc, bad));
+        for (int v = 0; v < F::NV; ++v) qc[v] = q[v * N + c];
+        smax = fmax(smax, cfl_speed<F>(g, qc, bad));
     }
     if (bad) atomicOr(status, bad);
     block_max_to<UTIL_BLOCK>(smax, partial + blockIdx.x);
@@ -354,6 +404,7 @@ __global__ void __launch_bounds__(UTIL_BLOCK) cfl_finalize_kernel(const double* 
 struct mfx_ctx {
     mfx_grid_desc desc;
     Grid g;
+    int nv;  // variables per cell (2 * fluids + 3)
     hipStream_t stream;
     int device;
     char* ws;
@@ -453,58 +504,61 @@ struct LaunchArgs {
 
 // The x row sweep reads the boundary faces that boundary_faces_x leaves in
 // `bface` (launched just before it on the same stream).
-template <int DIR, typename T, bool FIRST, int MODE, bool L, int SCHEME>
+// F: the fluid model (two fluids, or Fl<3> with the marching x sweep only).
+template <int DIR, typename T, bool FIRST, int MODE, bool L, int SCHEME, class F>
 void launch_one(const LaunchArgs& a)
 {
     const SweepGeom& sg = *a.sg;
     T* r = static_cast<T*>(a.r);
     if constexpr (DIR == 0) {
-        if (sg.xrows) {
-            T* bf = static_cast<T*>(a.bface);
-            const long long rows = (long long)a.g->n[1] * a.g->n[2];
-            boundary_faces_x<T, L, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf, a.mlp,
-                                                                                             a.fb);
-            sweep_x_rows<T, FIRST, MODE, L, SCHEME><<<sg.grid, sg.block, sg.lds, a.st>>>(
-                *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.mlp, a.fb);
-        } else {
-            sweep_x_march<T, FIRST, MODE, L, SCHEME><<<sg.grid, XROWS, 0, a.st>>>(
-                *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb);
+        if constexpr (F::NF == 2) {
+            if (sg.xrows) {
+                T* bf = static_cast<T*>(a.bface);
+                const long long rows = (long long)a.g->n[1] * a.g->n[2];
+                boundary_faces_x<T, L, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf,
+                                                                                                 a.mlp, a.fb);
+                sweep_x_rows<T, FIRST, MODE, L, SCHEME><<<sg.grid, sg.block, sg.lds, a.st>>>(
+                    *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.mlp, a.fb);
+                return;
+            }
         }
+        sweep_x_march<T, FIRST, MODE, L, SCHEME, F><<<sg.grid, XROWS, 0, a.st>>>(
+            *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb);
     } else {
         if constexpr (MODE == OUT_STAGE3 && !L) {
             if (a.cfl) {
-                sweep_yz<DIR, T, FIRST, MODE, L, true, SCHEME><<<sg.grid, sg.block, 0, a.st>>>(
+                sweep_yz<DIR, T, FIRST, MODE, L, true, SCHEME, F><<<sg.grid, sg.block, 0, a.st>>>(
                     *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, a.partial, a.status);
                 return;
             }
         }
-        sweep_yz<DIR, T, FIRST, MODE, L, false, SCHEME><<<sg.grid, sg.block, 0, a.st>>>(
+        sweep_yz<DIR, T, FIRST, MODE, L, false, SCHEME, F><<<sg.grid, sg.block, 0, a.st>>>(
             *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, nullptr, a.status);
     }
 }
 
-template <int DIR, typename T, bool FIRST, bool L, int SCHEME>
+template <int DIR, typename T, bool FIRST, bool L, int SCHEME, class F>
 void launch_mode(int mode, const LaunchArgs& a)
 {
     switch (mode) {
-    case OUT_ACCUM: launch_one<DIR, T, FIRST, OUT_ACCUM, L, SCHEME>(a); break;
-    case OUT_RHS: launch_one<DIR, T, FIRST, OUT_RHS, L, SCHEME>(a); break;
-    case OUT_STAGE1: launch_one<DIR, T, FIRST, OUT_STAGE1, L, SCHEME>(a); break;
-    case OUT_STAGE2: launch_one<DIR, T, FIRST, OUT_STAGE2, L, SCHEME>(a); break;
-    default: launch_one<DIR, T, FIRST, OUT_STAGE3, L, SCHEME>(a); break;
+    case OUT_ACCUM: launch_one<DIR, T, FIRST, OUT_ACCUM, L, SCHEME, F>(a); break;
+    case OUT_RHS: launch_one<DIR, T, FIRST, OUT_RHS, L, SCHEME, F>(a); break;
+    case OUT_STAGE1: launch_one<DIR, T, FIRST, OUT_STAGE1, L, SCHEME, F>(a); break;
+    case OUT_STAGE2: launch_one<DIR, T, FIRST, OUT_STAGE2, L, SCHEME, F>(a); break;
+    default: launch_one<DIR, T, FIRST, OUT_STAGE3, L, SCHEME, F>(a); break;
     }
 }
 
 // The x sweep, when active, is always the first direction of a pass.
-template <typename T, bool L, int SCHEME = 5>
+template <typename T, bool L, int SCHEME = 5, class F = Fl2>
 void launch_dispatch(int d, bool first, int mode, const LaunchArgs& a)
 {
     if (d == 0)
-        launch_mode<0, T, true, L, SCHEME>(mode, a);
+        launch_mode<0, T, true, L, SCHEME, F>(mode, a);
     else if (d == 1)
-        first ? launch_mode<1, T, true, L, SCHEME>(mode, a) : launch_mode<1, T, false, L, SCHEME>(mode, a);
+        first ? launch_mode<1, T, true, L, SCHEME, F>(mode, a) : launch_mode<1, T, false, L, SCHEME, F>(mode, a);
     else
-        first ? launch_mode<2, T, true, L, SCHEME>(mode, a) : launch_mode<2, T, false, L, SCHEME>(mode, a);
+        first ? launch_mode<2, T, true, L, SCHEME, F>(mode, a) : launch_mode<2, T, false, L, SCHEME, F>(mode, a);
 }
 
 int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* out, int first, int mode,
@@ -524,6 +578,10 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
                         c->partial, c->status, cfl};
     if (learned_weights(c->desc))
         launch_dispatch<float, true>(d, first != 0, mode, la);
+    else if (c->g.nf == 3 && c->desc.precision == MFX_FP32_MIXED)
+        by_scheme(scheme_of(c->desc), [&](auto s) { launch_dispatch<float, false, decltype(s)::value, Fl<3>>(d, first != 0, mode, la); });
+    else if (c->g.nf == 3)
+        by_scheme(scheme_of(c->desc), [&](auto s) { launch_dispatch<double, false, decltype(s)::value, Fl<3>>(d, first != 0, mode, la); });
     else if (c->desc.precision == MFX_FP32_MIXED)
         by_scheme(scheme_of(c->desc), [&](auto s) { launch_dispatch<float, false, decltype(s)::value>(d, first != 0, mode, la); });
     else
@@ -541,7 +599,7 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
 // directions, x rows fit the row kernel and the weights are Jiang-Shu.
 bool fused_xy(const mfx_ctx* c)
 {
-    return c->fuse_xy && !learned_weights(c->desc) && c->ndirs >= 2 && c->dirs[0] == 0 && c->dirs[1] == 1 &&
+    return c->fuse_xy && !learned_weights(c->desc) && c->g.nf == 2 && c->ndirs >= 2 && c->dirs[0] == 0 && c->dirs[1] == 1 &&
            use_xrows(c->g.n, c->xmode_override, c->elem);
 }
 
@@ -643,7 +701,10 @@ int run_passes(mfx_ctx* c, const double* qs, const double* qn, double* out, int 
 // the device time step when dt_arg is 0).
 int standalone_cfl(mfx_ctx* c, int advance = 0, double dt_arg = 0.0)
 {
-    cfl_partial_kernel<<<CFL_BLOCKS, UTIL_BLOCK, 0, c->stream>>>(c->g, c->q, c->partial, c->status);
+    if (c->g.nf == 3)
+        cfl_partial_kernel<Fl<3>><<<CFL_BLOCKS, UTIL_BLOCK, 0, c->stream>>>(c->g, c->q, c->partial, c->status);
+    else
+        cfl_partial_kernel<Fl2><<<CFL_BLOCKS, UTIL_BLOCK, 0, c->stream>>>(c->g, c->q, c->partial, c->status);
     int rc = launch_check(c, "cfl_partial_kernel");
     if (rc != MFX_OK) return rc;
     cfl_finalize_kernel<<<1, UTIL_BLOCK, 0, c->stream>>>(c->partial, CFL_BLOCKS, c->g.cfl, c->scal, advance, dt_arg);
@@ -683,7 +744,8 @@ void setup_grid(const mfx_grid_desc* desc, mfx_ctx* c, const double* inflow_dev)
         g.bc[k][0] = desc->bc[k][0];
         g.bc[k][1] = desc->bc[k][1];
         for (int s = 0; s < 2; ++s)
-            for (int v = 0; v < NV; ++v) g.inflow[k][s][v] = desc->bc[k][s] == MFX_BC_INFLOW ? desc->inflow[k][s][v] : 0.0;
+            for (int v = 0; v < NVMAX; ++v)
+                g.inflow[k][s][v] = desc->bc[k][s] == MFX_BC_INFLOW && v < vars_of(desc) ? desc->inflow[k][s][v] : 0.0;
         g.active[k] = desc->n[k] > 1;
         if (g.active[k]) c->dirs[c->ndirs++] = k;
     }
@@ -693,6 +755,12 @@ void setup_grid(const mfx_grid_desc* desc, mfx_ctx* c, const double* inflow_dev)
     g.G2 = 1.0 / (desc->gamma[1] - 1.0);
     g.P1 = desc->gamma[0] * desc->pi_inf[0] / (desc->gamma[0] - 1.0);
     g.P2 = desc->gamma[1] * desc->pi_inf[1] / (desc->gamma[1] - 1.0);
+    g.nf = fluids_of(desc);
+    c->nv = vars_of(desc);
+    for (int f = 0; f < MAXF; ++f) {
+        g.Gn[f] = f < g.nf ? 1.0 / (desc->gamma[f] - 1.0) : 0.0;
+        g.Pn[f] = f < g.nf ? desc->gamma[f] * desc->pi_inf[f] / (desc->gamma[f] - 1.0) : 0.0;
+    }
     g.eps = desc->weno_eps;
     g.edge_weights = desc->weights == MFX_WENO5_LEARNED_EDGE ? 1 : 0;
     g.cfl = desc->cfl;
@@ -769,7 +837,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     }
     // the inflow states for the loaders (zero for other sides); the source
     // lives in the context
-    if (hipMemcpyAsync(c->ws + L.inflow, &c->g.inflow[0][0][0], sizeof(double) * 3 * 2 * NV, hipMemcpyHostToDevice,
+    if (hipMemcpyAsync(c->ws + L.inflow, &c->g.inflow[0][0][0], sizeof(double) * 3 * 2 * NVMAX, hipMemcpyHostToDevice,
                        c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess) {
         delete c;
@@ -791,7 +859,7 @@ int mfx_set_state(mfx_ctx* c, const double* q_dev)
     if (!q_dev) return fail(c, MFX_EINVAL, "q_dev is NULL");
     int rc = set_device(c);
     if (rc) return rc;
-    HIP_TRY(c, hipMemcpyAsync(c->q, q_dev, sizeof(double) * 7 * (size_t)c->g.N, hipMemcpyDeviceToDevice,
+    HIP_TRY(c, hipMemcpyAsync(c->q, q_dev, sizeof(double) * c->nv * (size_t)c->g.N, hipMemcpyDeviceToDevice,
                               c->stream));
     HIP_TRY(c, hipMemsetAsync(c->ws + c->L.scal, 0, 64, c->stream));
     c->has_state = true;
@@ -805,7 +873,10 @@ int mfx_set_primitive(mfx_ctx* c, const double* w_dev)
     int rc = set_device(c);
     if (rc) return rc;
     const long long blocks = std::min<long long>((c->g.N + UTIL_BLOCK - 1) / UTIL_BLOCK, 65536);
-    prim_to_cons_kernel<<<(unsigned)blocks, UTIL_BLOCK, 0, c->stream>>>(c->g, w_dev, c->q);
+    if (c->g.nf == 3)
+        prim_to_cons_kernel<Fl<3>><<<(unsigned)blocks, UTIL_BLOCK, 0, c->stream>>>(c->g, w_dev, c->q);
+    else
+        prim_to_cons_kernel<Fl2><<<(unsigned)blocks, UTIL_BLOCK, 0, c->stream>>>(c->g, w_dev, c->q);
     rc = launch_check(c, "prim_to_cons_kernel");
     if (rc) return rc;
     HIP_TRY(c, hipMemsetAsync(c->ws + c->L.scal, 0, 64, c->stream));
@@ -820,7 +891,7 @@ int mfx_get_state(mfx_ctx* c, double* q_dev_out)
     if (!c->has_state) return fail(c, MFX_EINVAL, "no state set");
     int rc = set_device(c);
     if (rc) return rc;
-    HIP_TRY(c, hipMemcpyAsync(q_dev_out, c->q, sizeof(double) * 7 * (size_t)c->g.N, hipMemcpyDeviceToDevice,
+    HIP_TRY(c, hipMemcpyAsync(q_dev_out, c->q, sizeof(double) * c->nv * (size_t)c->g.N, hipMemcpyDeviceToDevice,
                               c->stream));
     unsigned st = 0;
     rc = read_status(c, &st);
@@ -844,7 +915,7 @@ int mfx_rhs(mfx_ctx* c, double* rhs_out)
     if (!rhs_out) return fail(c, MFX_EINVAL, "rhs_dev_out is NULL");
     if (!c->has_state) return fail(c, MFX_EINVAL, "no state set");
     const char* o = reinterpret_cast<const char*>(rhs_out);
-    if (o < c->ws + c->ws_bytes && o + sizeof(double) * 7 * c->g.N > c->ws)
+    if (o < c->ws + c->ws_bytes && o + sizeof(double) * c->nv * c->g.N > c->ws)
         return fail(c, MFX_EINVAL, "rhs_dev_out overlaps the workspace");
     int rc = set_device(c);
     if (rc) return rc;

@@ -9,9 +9,13 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace mfx {
 
 constexpr int NV = 7;  // alpha1 rho1, alpha2 rho2, rho u, rho v, rho w, rho E, alpha1
+constexpr int MAXF = 3;               // fluids the kernels are built for
+constexpr int NVMAX = 2 * MAXF + 3;   // variables of the largest model
 
 // Per-fluid constants of the mixture rules, linear in alpha1:
 //   Gamma(a) = a G1 + (1 - a) G2,  Pi(a) = a P1 + (1 - a) P2
@@ -22,6 +26,41 @@ struct Mix {
     __device__ __forceinline__ T Gamma(T a) const { return a * G1 + (T(1) - a) * G2; }
     __device__ __forceinline__ T Pi(T a) const { return a * P1 + (T(1) - a) * P2; }
 };
+
+// The same rules for NF > 2 fluids (Sec. II-A's model with one continuity
+// and one volume-fraction equation per component), linear in the volume
+// fractions a[0 .. NF-2]; the last fluid takes 1 minus their sum:
+//   Gamma = sum_i a_i G_i + (1 - sum_i a_i) G_NF, likewise Pi.
+template <typename T, int NF>
+struct MixN {
+    T G[NF], P[NF];
+    __device__ __forceinline__ T lin(const T* c, const T* a) const
+    {
+        T m = a[0] * c[0], s = a[0];
+#pragma unroll
+        for (int i = 1; i < NF - 1; ++i) {
+            m = m + a[i] * c[i];
+            s = s + a[i];
+        }
+        return m + (T(1) - s) * c[NF - 1];
+    }
+    __device__ __forceinline__ T Gamma(const T* a) const { return lin(G, a); }
+    __device__ __forceinline__ T Pi(const T* a) const { return lin(P, a); }
+};
+
+// Variable layout of the NF-fluid model: partial densities 0 .. NF-1,
+// momentum (velocity) NF .. NF+2, energy (pressure) NF+3, volume fractions
+// NF+4 .. 2 NF+2 (fluids 1 .. NF-1).  Two fluids: the seven variables above.
+template <int NF_>
+struct Fl {
+    static constexpr int NF = NF_;
+    static constexpr int NV = 2 * NF + 3;
+    static constexpr int IM = NF;      // x momentum / velocity
+    static constexpr int IE = NF + 3;  // energy / pressure
+    static constexpr int IA = NF + 4;  // first volume fraction
+    static constexpr int NA = NF - 1;  // volume fractions carried
+};
+using Fl2 = Fl<2>;
 
 // Conserved -> primitive for one cell, always in float64 and without
 // contraction, in the operation order of the plain definition
@@ -419,6 +458,207 @@ __device__ __forceinline__ void hllc(const Mix<T>& mix, const T wl[NV], const T 
         hllc_fp64<DIR>(mix, wl, wr, F, uf);
     else
         hllc_fast<DIR, T>(mix, wl, wr, F, uf);
+}
+
+// ---- the NF-fluid model (NF > 2): the same definitions with every partial
+// density and volume fraction (two fluids use the functions above)
+
+template <class F>
+using MixOf = typename std::conditional<F::NF == 2, Mix<double>, MixN<double, F::NF>>::type;
+
+template <int NF>
+__device__ __forceinline__ double density_n(const double* x)
+{
+    double rho = x[0];
+#pragma unroll
+    for (int i = 1; i < NF; ++i) rho = rho + x[i];
+    return rho;
+}
+
+// Conserved -> primitive, float64, plain operation order, no contraction.
+template <int NF>
+__device__ __forceinline__ void cons_to_prim_n(const MixN<double, NF>& mix, const double* q, double* w)
+{
+#pragma clang fp contract(off)
+    using F = Fl<NF>;
+    const double rho = density_n<NF>(q);
+    const double u = q[F::IM] / rho, v = q[F::IM + 1] / rho, ww = q[F::IM + 2] / rho;
+    const double ke = 0.5 * rho * (u * u + v * v + ww * ww);
+    double m = q[F::IA] * mix.G[0], s = q[F::IA];
+    double mp = q[F::IA] * mix.P[0];
+#pragma unroll
+    for (int i = 1; i < NF - 1; ++i) {
+        m = m + q[F::IA + i] * mix.G[i];
+        mp = mp + q[F::IA + i] * mix.P[i];
+        s = s + q[F::IA + i];
+    }
+    const double G = m + (1.0 - s) * mix.G[NF - 1];
+    const double P = mp + (1.0 - s) * mix.P[NF - 1];
+#pragma unroll
+    for (int i = 0; i < F::NV; ++i) w[i] = q[i];
+    w[F::IM] = u;
+    w[F::IM + 1] = v;
+    w[F::IM + 2] = ww;
+    w[F::IE] = (q[F::IE] - ke - P) / G;
+}
+
+// HLLC of the NF-fluid model: every partial density and volume fraction is
+// scaled by xi in the star state.  float64: the plain definition's operation
+// order, no contraction, IEEE division and square root (as hllc_fp64).
+template <int DIR, int NF>
+__device__ __forceinline__ void hllc_fp64_n(const MixN<double, NF>& mix, const double* wl, const double* wr, double* F,
+                                            double& uf)
+{
+#pragma clang fp contract(off)
+    using L = Fl<NF>;
+    const double rl = density_n<NF>(wl), rr = density_n<NF>(wr);
+    const double pl = wl[L::IE], pr = wr[L::IE];
+    const double unl = wl[L::IM + DIR], unr = wr[L::IM + DIR];
+    double Gl = wl[L::IA] * mix.G[0], Gr = wr[L::IA] * mix.G[0], Pl = wl[L::IA] * mix.P[0], Pr = wr[L::IA] * mix.P[0];
+    double sl = wl[L::IA], sr = wr[L::IA];
+#pragma unroll
+    for (int i = 1; i < NF - 1; ++i) {
+        Gl = Gl + wl[L::IA + i] * mix.G[i];
+        Gr = Gr + wr[L::IA + i] * mix.G[i];
+        Pl = Pl + wl[L::IA + i] * mix.P[i];
+        Pr = Pr + wr[L::IA + i] * mix.P[i];
+        sl = sl + wl[L::IA + i];
+        sr = sr + wr[L::IA + i];
+    }
+    Gl = Gl + (1.0 - sl) * mix.G[NF - 1];
+    Gr = Gr + (1.0 - sr) * mix.G[NF - 1];
+    Pl = Pl + (1.0 - sl) * mix.P[NF - 1];
+    Pr = Pr + (1.0 - sr) * mix.P[NF - 1];
+    const int m = L::IM;
+    const double El = Gl * pl + Pl + 0.5 * rl * (wl[m] * wl[m] + wl[m + 1] * wl[m + 1] + wl[m + 2] * wl[m + 2]);
+    const double Er = Gr * pr + Pr + 0.5 * rr * (wr[m] * wr[m] + wr[m + 1] * wr[m + 1] + wr[m + 2] * wr[m + 2]);
+    const double cl = sqrt(((Gl + 1.0) * pl + Pl) / (Gl * rl));
+    const double cr = sqrt(((Gr + 1.0) * pr + Pr) / (Gr * rr));
+
+    const double SL = fmin(unl - cl, unr - cr);
+    const double SR = fmax(unl + cl, unr + cr);
+    const double Ss = (pr - pl + rl * unl * (SL - unl) - rr * unr * (SR - unr)) / (rl * (SL - unl) - rr * (SR - unr));
+
+    const bool left = Ss >= 0.0;
+    double w[L::NV];
+#pragma unroll
+    for (int v = 0; v < L::NV; ++v) w[v] = left ? wl[v] : wr[v];
+    const double rho = left ? rl : rr;
+    const double p = left ? pl : pr;
+    const double un = left ? unl : unr;
+    const double E = left ? El : Er;
+    const double S = left ? SL : SR;
+    const double s = left ? fmin(0.0, SL) : fmax(0.0, SR);
+
+    double U[L::NV], Us[L::NV], Fk[L::NV];
+#pragma unroll
+    for (int v = 0; v < L::NV; ++v) U[v] = w[v];
+    U[m] = rho * w[m];
+    U[m + 1] = rho * w[m + 1];
+    U[m + 2] = rho * w[m + 2];
+    U[L::IE] = E;
+#pragma unroll
+    for (int v = 0; v < L::NV; ++v) Fk[v] = U[v] * un;
+    Fk[m + DIR] = Fk[m + DIR] + p;
+    Fk[L::IE] = (E + p) * un;
+
+    const double xi = (S - un) / (S - Ss);
+#pragma unroll
+    for (int v = 0; v < L::NV; ++v) Us[v] = xi * w[v];
+    Us[m] = xi * (rho * w[m]);
+    Us[m + 1] = xi * (rho * w[m + 1]);
+    Us[m + 2] = xi * (rho * w[m + 2]);
+    Us[m + DIR] = xi * (rho * Ss);
+    Us[L::IE] = xi * (E + (Ss - un) * (rho * Ss + p / (S - un)));
+#pragma unroll
+    for (int v = 0; v < L::NV; ++v) F[v] = Fk[v] + s * (Us[v] - U[v]);
+    uf = un + s * (xi - 1.0);
+}
+
+// The same flux in the float form (contraction allowed, reciprocal quotients).
+template <int DIR, typename T, int NF>
+__device__ __forceinline__ void hllc_fast_n(const MixN<T, NF>& mix, const T* wl, const T* wr, T* F, T& uf)
+{
+    using L = Fl<NF>;
+    T rl = wl[0], rr = wr[0];
+#pragma unroll
+    for (int i = 1; i < NF; ++i) {
+        rl += wl[i];
+        rr += wr[i];
+    }
+    const T pl = wl[L::IE], pr = wr[L::IE];
+    const T unl = wl[L::IM + DIR], unr = wr[L::IM + DIR];
+    const T Gl = mix.Gamma(wl + L::IA), Gr = mix.Gamma(wr + L::IA);
+    const T Pl = mix.Pi(wl + L::IA), Pr = mix.Pi(wr + L::IA);
+    const int m = L::IM;
+    const T El = Gl * pl + Pl + T(0.5) * rl * (wl[m] * wl[m] + wl[m + 1] * wl[m + 1] + wl[m + 2] * wl[m + 2]);
+    const T Er = Gr * pr + Pr + T(0.5) * rr * (wr[m] * wr[m] + wr[m + 1] * wr[m + 1] + wr[m + 2] * wr[m + 2]);
+    const T cl = qsqrt(qdiv((Gl + T(1)) * pl + Pl, Gl * rl));
+    const T cr = qsqrt(qdiv((Gr + T(1)) * pr + Pr, Gr * rr));
+
+    const T SL = fmin(unl - cl, unr - cr);
+    const T SR = fmax(unl + cl, unr + cr);
+    const T ml = rl * (SL - unl), mr = rr * (SR - unr);
+    const T Ss = qdiv(pr - pl + ml * unl - mr * unr, ml - mr);
+
+    const bool left = Ss >= T(0);
+    T w[L::NV];
+#pragma unroll
+    for (int v = 0; v < L::NV; ++v) w[v] = left ? wl[v] : wr[v];
+    const T rho = left ? rl : rr;
+    const T p = left ? pl : pr;
+    const T un = left ? unl : unr;
+    const T E = left ? El : Er;
+    const T S = left ? SL : SR;
+    const T s = left ? fmin(T(0), SL) : fmax(T(0), SR);
+
+    const T xi = qdiv(S - un, S - Ss);
+    const T Eratio = qdiv(p, S - un);
+
+    T U[L::NV], Us[L::NV];
+#pragma unroll
+    for (int v = 0; v < L::NV; ++v) U[v] = w[v];
+    U[m] = rho * w[m];
+    U[m + 1] = rho * w[m + 1];
+    U[m + 2] = rho * w[m + 2];
+    U[L::IE] = E;
+#pragma unroll
+    for (int v = 0; v < L::NV; ++v) Us[v] = xi * U[v];
+    Us[m + DIR] = xi * (rho * Ss);
+    Us[L::IE] = xi * (E + (Ss - un) * (rho * Ss + Eratio));
+
+    T Fk[L::NV];
+#pragma unroll
+    for (int v = 0; v < L::NV; ++v) Fk[v] = U[v] * un;
+    Fk[m + DIR] += p;
+    Fk[L::IE] = (E + p) * un;
+#pragma unroll
+    for (int v = 0; v < L::NV; ++v) F[v] = Fk[v] + s * (Us[v] - U[v]);
+    uf = un + s * (xi - T(1));
+}
+
+// Model-generic entry points: two fluids take the functions above, more
+// fluids the _n forms.
+template <class F>
+__device__ __forceinline__ void cons_to_prim_f(const MixOf<F>& mix, const double* q, double* w)
+{
+    if constexpr (F::NF == 2)
+        cons_to_prim(mix, q, w);
+    else
+        cons_to_prim_n<F::NF>(mix, q, w);
+}
+
+template <int DIR, typename T, class F>
+__device__ __forceinline__ void hllc_f(const typename std::conditional<F::NF == 2, Mix<T>, MixN<T, F::NF>>::type& mix,
+                                       const T* wl, const T* wr, T* Fo, T& uf)
+{
+    if constexpr (F::NF == 2) {
+        hllc<DIR, T>(mix, wl, wr, Fo, uf);
+    } else if constexpr (sizeof(T) == sizeof(double)) {
+        hllc_fp64_n<DIR, F::NF>(mix, wl, wr, Fo, uf);
+    } else {
+        hllc_fast_n<DIR, T, F::NF>(mix, wl, wr, Fo, uf);
+    }
 }
 
 }  // namespace mfx

@@ -49,13 +49,32 @@ struct Grid {
     double inv_dx[3];
     int bc[3][2];
     int active[3];
-    double G1, G2, P1, P2;  // per-fluid 1/(gamma-1) and gamma pi/(gamma-1)
+    double G1, G2, P1, P2;  // per-fluid 1/(gamma-1) and gamma pi/(gamma-1) (two fluids)
+    int nf;                 // fluids
+    double Gn[MAXF], Pn[MAXF];  // the same for every fluid
     double eps;
     double cfl;
     int edge_weights;  // learned weights: one network evaluation per edge for all variables
-    double inflow[3][2][NV];  // conserved state of the ghost cells of an inflow side
-    const double* inflow_dev; // the same states in device memory, [3][2][NV]
+    double inflow[3][2][NVMAX];  // conserved state of the ghost cells of an inflow side
+    const double* inflow_dev;    // the same states in device memory, [3][2][NVMAX]
 };
+
+// Mixture constants of the model F from the grid, in the type T.
+template <typename T, class F>
+__device__ __forceinline__ auto make_mix(const Grid& g)
+{
+    if constexpr (F::NF == 2) {
+        return Mix<T>{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
+    } else {
+        MixN<T, F::NF> m;
+#pragma unroll
+        for (int i = 0; i < F::NF; ++i) {
+            m.G[i] = (T)g.Gn[i];
+            m.P[i] = (T)g.Pn[i];
+        }
+        return m;
+    }
+}
 
 // Cell whose state stencil position c takes.  Ghost positions (outside
 // 0..n-1): periodic wraps around, transmissive repeats the edge cell,
@@ -109,17 +128,48 @@ __device__ __forceinline__ unsigned ghost_slots_of(int x, int n, int bclo, int b
 // CFL wave speed sum_d (|u_d| + c) / dx_d of one cell, written in the same
 // operation order as the plain definition and without contraction, so the
 // reduced time step is reproducible across implementations.
-__device__ __forceinline__ double cfl_speed(const Grid& g, const double q[NV], unsigned& bad)
+// Volume fractions outside [0, 1]: alpha_1 .. alpha_{NF-1} and the last
+// fluid's 1 - sum.
+template <class F>
+__device__ __forceinline__ bool alpha_out(const double* q)
+{
+    if constexpr (F::NF == 2) {
+        return !(q[6] >= 0.0 && q[6] <= 1.0);
+    } else {
+        bool out = false;
+        double s = 0.0;
+#pragma unroll
+        for (int i = 0; i < F::NA; ++i) {
+            out = out || !(q[F::IA + i] >= 0.0 && q[F::IA + i] <= 1.0);
+            s += q[F::IA + i];
+        }
+        return out || !(s <= 1.0);
+    }
+}
+
+template <class F = Fl2>
+__device__ __forceinline__ double cfl_speed(const Grid& g, const double* q, unsigned& bad)
 {
 #pragma clang fp contract(off)
-    const double rho = q[0] + q[1];
-    const double u = q[2] / rho, v = q[3] / rho, w = q[4] / rho;
-    const double ke = 0.5 * rho * (u * u + v * v + w * w);
-    const double a1 = q[6];
-    const double G = a1 * g.G1 + (1.0 - a1) * g.G2;
-    const double P = a1 * g.P1 + (1.0 - a1) * g.P2;
-    const double p = (q[5] - ke - P) / G;
-    const double c2 = ((G + 1.0) * p + P) / (G * rho);
+    double c2, u, v, w, rho;
+    if constexpr (F::NF == 2) {
+        rho = q[0] + q[1];
+        u = q[2] / rho, v = q[3] / rho, w = q[4] / rho;
+        const double ke = 0.5 * rho * (u * u + v * v + w * w);
+        const double a1 = q[6];
+        const double G = a1 * g.G1 + (1.0 - a1) * g.G2;
+        const double P = a1 * g.P1 + (1.0 - a1) * g.P2;
+        const double p = (q[5] - ke - P) / G;
+        c2 = ((G + 1.0) * p + P) / (G * rho);
+    } else {
+        const MixN<double, F::NF> mix = make_mix<double, F>(g);
+        double wp[F::NV];
+        cons_to_prim_n<F::NF>(mix, q, wp);
+        rho = density_n<F::NF>(q);
+        u = wp[F::IM], v = wp[F::IM + 1], w = wp[F::IM + 2];
+        const double G = mix.Gamma(q + F::IA), P = mix.Pi(q + F::IA);
+        c2 = ((G + 1.0) * wp[F::IE] + P) / (G * rho);
+    }
     const double c = sqrt(c2);
     double s = 0.0;
     const double vel[3] = {u, v, w};
@@ -129,22 +179,26 @@ __device__ __forceinline__ double cfl_speed(const Grid& g, const double q[NV], u
     if (!(rho > 0.0)) bad |= 1u;
     if (!(c2 > 0.0)) bad |= 2u;
     if (!isfinite(s)) bad |= 4u;
-    if (!(a1 >= 0.0 && a1 <= 1.0)) bad |= 8u;
+    if (alpha_out<F>(q)) bad |= 8u;
     return s;
 }
 
 // Status bits of a state (the same bits as cfl_speed without the sound
-// speed): density not positive (1), a non-finite value (4), alpha1 outside
-// [0, 1] (8).
-__device__ __forceinline__ unsigned state_bits(const double q[NV])
+// speed): density not positive (1), a non-finite value (4), a volume
+// fraction outside [0, 1] (8).
+template <class F = Fl2>
+__device__ __forceinline__ unsigned state_bits(const double* q)
 {
     unsigned bad = 0;
-    if (!(q[0] + q[1] > 0.0)) bad |= 1u;
+    double rho = q[0];
+#pragma unroll
+    for (int i = 1; i < F::NF; ++i) rho = rho + q[i];
+    if (!(rho > 0.0)) bad |= 1u;
     bool fin = true;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) fin = fin && isfinite(q[v]);
+    for (int v = 0; v < F::NV; ++v) fin = fin && isfinite(q[v]);
     if (!fin) bad |= 4u;
-    if (!(q[6] >= 0.0 && q[6] <= 1.0)) bad |= 8u;
+    if (alpha_out<F>(q)) bad |= 8u;
     return bad;
 }
 
@@ -156,16 +210,17 @@ enum : int {
 };
 
 // Running CFL maximum and validity flags of the cells a lane writes.
+template <class F = Fl2>
 struct CflAcc {
     double smax;
     unsigned bad;
     bool cfl;  // false: only the status bits, no CFL speed
-    __device__ __forceinline__ void add(const Grid& g, const double q[NV])
+    __device__ __forceinline__ void add(const Grid& g, const double* q)
     {
         if (cfl)
-            smax = fmax(smax, cfl_speed(g, q, bad));
+            smax = fmax(smax, cfl_speed<F>(g, q, bad));
         else
-            bad |= state_bits(q);
+            bad |= state_bits<F>(q);
     }
 };
 
@@ -219,50 +274,52 @@ struct OutArgs {
 // qsc, qnc: the cell's stage state and step state when the caller holds
 // them (else read from o.qs, o.qn).  acc: receives the new state of a stage
 // update (CFL maximum of the result).
-template <typename T, int MODE>
-__device__ __forceinline__ void store_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T r[NV],
-                                           const double* qsc = nullptr, CflAcc* acc = nullptr,
+template <typename T, int MODE, class F = Fl2>
+__device__ __forceinline__ void store_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T* r,
+                                           const double* qsc = nullptr, CflAcc<F>* acc = nullptr,
                                            const double* qnc = nullptr)
 {
     const long long N = g.N;
     if constexpr (MODE == OUT_ACCUM) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) o.racc[v * N + cell] = r[v];
+        for (int v = 0; v < F::NV; ++v) o.racc[v * N + cell] = r[v];
     } else if constexpr (MODE == OUT_RHS) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) o.out[v * N + cell] = (double)r[v];
+        for (int v = 0; v < F::NV; ++v) o.out[v * N + cell] = (double)r[v];
     } else {
-        double qo[NV];
+        double qo[F::NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
+        for (int v = 0; v < F::NV; ++v) {
             const double qnv = MODE == OUT_STAGE1 ? 0.0 : (qnc ? qnc[v] : o.qn[v * N + cell]);
             qo[v] = rk3_combine(MODE, qnv, qsc ? qsc[v] : o.qs[v * N + cell], o.dt, (double)r[v]);
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) o.out[v * N + cell] = qo[v];
+        for (int v = 0; v < F::NV; ++v) o.out[v * N + cell] = qo[v];
         if (acc) acc->add(g, qo);
     }
 }
 
-template <typename T, bool FIRST, int MODE>
-__device__ __forceinline__ void emit_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T fd[NV], T src,
-                                          const double* qsc = nullptr, CflAcc* acc = nullptr)
+// src[a]: the volume-fraction sources alpha_a div(u) (F::NA of them).
+template <typename T, bool FIRST, int MODE, class F = Fl2>
+__device__ __forceinline__ void emit_cell(const Grid& g, const OutArgs<T>& o, long long cell, const T* fd,
+                                          const T* src, const double* qsc = nullptr, CflAcc<F>* acc = nullptr)
 {
-    T r[NV];
+    T r[F::NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) r[v] = FIRST ? fd[v] : o.racc[v * g.N + cell] + fd[v];
-    r[6] += src;
-    store_cell<T, MODE>(g, o, cell, r, qsc, acc);
+    for (int v = 0; v < F::NV; ++v) r[v] = FIRST ? fd[v] : o.racc[v * g.N + cell] + fd[v];
+#pragma unroll
+    for (int a = 0; a < F::NA; ++a) r[F::IA + a] += src[a];
+    store_cell<T, MODE, F>(g, o, cell, r, qsc, acc);
 }
 
 // Primitives of one cell in the compute type: the inversion is float64.
-template <typename T>
-__device__ __forceinline__ void prim_of(const Mix<double>& mix, const double q[NV], T w[NV])
+template <typename T, class F = Fl2>
+__device__ __forceinline__ void prim_of(const MixOf<F>& mix, const double* q, T* w)
 {
-    double wd[NV];
-    cons_to_prim(mix, q, wd);
+    double wd[F::NV];
+    cons_to_prim_f<F>(mix, q, wd);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) w[v] = (T)wd[v];
+    for (int v = 0; v < F::NV; ++v) w[v] = (T)wd[v];
 }
 
 // Primitives w of a reflective or inflow ghost at position pos (outside the
@@ -270,17 +327,17 @@ __device__ __forceinline__ void prim_of(const Mix<double>& mix, const double q[N
 // map loaded for it: a reflective ghost negates the normal velocity (the
 // same bits as negating the momentum before the conversion), an inflow
 // ghost takes the side's fixed state.
-template <int DIR, typename T>
-__device__ __forceinline__ void ghost_fix(const Grid& g, const Mix<double>& mixd, int pos, int bclo, int bchi, T w[NV])
+template <int DIR, typename T, class F = Fl2>
+__device__ __forceinline__ void ghost_fix(const Grid& g, const MixOf<F>& mixd, int pos, int bclo, int bchi, T* w)
 {
     const int side = pos < 0 ? 0 : 1;
     if ((side ? bchi : bclo) == BC_REFLECTIVE) {
-        w[2 + DIR] = -w[2 + DIR];
+        w[F::IM + DIR] = -w[F::IM + DIR];
     } else {
-        double qi[NV];
+        double qi[F::NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) qi[v] = g.inflow[DIR][side][v];
-        prim_of<T>(mixd, qi, w);
+        for (int v = 0; v < F::NV; ++v) qi[v] = g.inflow[DIR][side][v];
+        prim_of<T, F>(mixd, qi, w);
     }
 }
 
@@ -296,16 +353,17 @@ __device__ __forceinline__ void ghost_fix(const Grid& g, const Mix<double>& mixd
 // past the grid read the clamped column: in bounds, never stored).
 // PREFETCH off (the learned passes): the loads stay where the output needs
 // them, so they do not hold registers across the network evaluations.
-template <typename T, bool FIRST, int MODE, bool KEEPQ = false, int CHK = CHK_NONE, bool PREFETCH = true>
+template <typename T, bool FIRST, int MODE, bool KEEPQ = false, int CHK = CHK_NONE, bool PREFETCH = true,
+          class F = Fl2>
 struct GlobalSink {
     static constexpr bool keeps_q = KEEPQ;
     static constexpr bool NEEDQN = MODE == OUT_STAGE2 || MODE == OUT_STAGE3;
     OutArgs<T> o;
     long long base, sd;
     bool valid;
-    CflAcc acc;
-    T rin[FIRST ? 1 : NV];
-    double qnin[NEEDQN ? NV : 1];
+    CflAcc<F> acc;
+    T rin[FIRST ? 1 : F::NV];
+    double qnin[NEEDQN ? F::NV : 1];
     __device__ __forceinline__ void prefetch(const Grid& g, int c)
     {
         if constexpr (PREFETCH) load_out(g, c);
@@ -315,32 +373,34 @@ struct GlobalSink {
         const long long cell = base + (long long)c * sd;
         if constexpr (!FIRST) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) rin[v] = o.racc[v * g.N + cell];
+            for (int v = 0; v < F::NV; ++v) rin[v] = o.racc[v * g.N + cell];
         }
         if constexpr (NEEDQN) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) qnin[v] = o.qn[v * g.N + cell];
+            for (int v = 0; v < F::NV; ++v) qnin[v] = o.qn[v * g.N + cell];
         }
     }
     template <class Win>
-    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src, const Win&, const double* qc)
+    __device__ __forceinline__ void put(const Grid& g, int c, const T* fd, const T* src, const Win&, const double* qc)
     {
         if (valid) {
             if constexpr (!PREFETCH) load_out(g, c);
-            T r[NV];
+            T r[F::NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) r[v] = FIRST ? fd[v] : rin[v] + fd[v];
-            r[6] += src;
-            store_cell<T, MODE>(g, o, base + (long long)c * sd, r, KEEPQ ? qc : nullptr, CHK ? &acc : nullptr,
-                                NEEDQN ? qnin : nullptr);
+            for (int v = 0; v < F::NV; ++v) r[v] = FIRST ? fd[v] : rin[v] + fd[v];
+#pragma unroll
+            for (int a = 0; a < F::NA; ++a) r[F::IA + a] += src[a];
+            store_cell<T, MODE, F>(g, o, base + (long long)c * sd, r, KEEPQ ? qc : nullptr, CHK ? &acc : nullptr,
+                                   NEEDQN ? qnin : nullptr);
         }
     }
 };
 
 // Views of a 5-cell window: w(k, v) = primitive v of cell c-2+k.
-template <typename T>
+template <typename T, int NVV = NV>
 struct ArrayWindow {
-    const T (*W)[NV];
+    static constexpr int nv = NVV;
+    const T (*W)[NVV];
     __device__ __forceinline__ T operator()(int k, int v) const { return W[k][v]; }
 };
 
@@ -349,9 +409,10 @@ struct ArrayWindow {
 // consecutive lanes in consecutive words.  s0 is the slot of cell c-2.
 // Keeping the window here instead of in registers leaves the registers to
 // one variable's reconstruction at a time and needs no shifting.
-template <typename T, int LANES>
+template <typename T, int LANES, int NVV = NV>
 struct LdsWindow {
     static constexpr bool in_registers = false;
+    static constexpr int nv = NVV;
     T* col;
     int s0;
     __device__ __forceinline__ int slot(int k) const
@@ -359,15 +420,15 @@ struct LdsWindow {
         const int s = s0 + k;
         return s >= 5 ? s - 5 : s;
     }
-    __device__ __forceinline__ T operator()(int k, int v) const { return col[(slot(k) * NV + v) * LANES]; }
-    __device__ __forceinline__ void store(int k, const T w[NV]) const
+    __device__ __forceinline__ T operator()(int k, int v) const { return col[(slot(k) * NVV + v) * LANES]; }
+    __device__ __forceinline__ void store(int k, const T* w) const
     {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) col[(slot(k) * NV + v) * LANES] = w[v];
+        for (int v = 0; v < NVV; ++v) col[(slot(k) * NVV + v) * LANES] = w[v];
     }
     __device__ __forceinline__ void advance() { s0 = s0 == 4 ? 0 : s0 + 1; }
     // the new cell takes the slot of the oldest, which becomes the newest
-    __device__ __forceinline__ void push(const T w[NV])
+    __device__ __forceinline__ void push(const T* w)
     {
         store(0, w);
         advance();
@@ -376,21 +437,22 @@ struct LdsWindow {
 
 // The same ring in registers (rotated by moves), for kernels whose LDS
 // holds other data.
-template <typename T>
+template <typename T, int NVV = NV>
 struct RegWindow {
     static constexpr bool in_registers = true;
-    T w[5][NV];
+    static constexpr int nv = NVV;
+    T w[5][NVV];
     __device__ __forceinline__ T operator()(int k, int v) const { return w[k][v]; }
-    __device__ __forceinline__ void store(int k, const T x[NV])
+    __device__ __forceinline__ void store(int k, const T* x)
     {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) w[k][v] = x[v];
+        for (int v = 0; v < NVV; ++v) w[k][v] = x[v];
     }
     // shift out the oldest cell, the new one becomes the newest
-    __device__ __forceinline__ void push(const T x[NV])
+    __device__ __forceinline__ void push(const T* x)
     {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
+        for (int v = 0; v < NVV; ++v) {
             w[0][v] = w[1][v];
             w[1][v] = w[2][v];
             w[2][v] = w[3][v];
@@ -436,10 +498,10 @@ __device__ __forceinline__ void recon_scheme(T a, T b, T c, T d, T e, T eps, T& 
 template <typename T, int SCHEME = 5>
 struct ReconJS {
     template <class Win>
-    __device__ __forceinline__ void cell_win(const Win& W, T eps, T lft[NV], T rgt[NV])
+    __device__ __forceinline__ void cell_win(const Win& W, T eps, T* lft, T* rgt)
     {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
+        for (int v = 0; v < Win::nv; ++v) {
             recon_scheme<T, SCHEME>(W(0, v), W(1, v), W(2, v), W(3, v), W(4, v), eps, lft[v], rgt[v]);
             settle(lft[v], rgt[v]);
         }
@@ -621,31 +683,32 @@ __device__ __forceinline__ typename ReconOf<T, LEARNED, SCHEME>::type make_recon
 // Sink::put for cells c0..c1-1 in order, the same sequence on every lane.
 // W: the 5-cell window (LdsWindow or RegWindow), handed to Sink::put too,
 // where W(1, .) holds the primitives of the cell being put.
-template <int DIR, typename T, class Src, class Sink, class Recon, class Win>
+template <int DIR, typename T, class F, class Src, class Sink, class Recon, class Win>
 __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon& recon, int c0, int c1, Win& W)
 {
+    constexpr int V = F::NV;
     const T idx = (T)g.inv_dx[DIR];
     const T eps = (T)g.eps;
-    const Mix<double> mixd{g.G1, g.G2, g.P1, g.P2};
-    const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
+    const MixOf<F> mixd = make_mix<double, F>(g);
+    const auto mix = make_mix<T, F>(g);
 
     // window: W(k) = primitives of cell c-2+k while reconstructing cell c
     // qh (when the sink keeps the stage state): conserved cells c-1 .. c+2.
     // Register-held windows and qh need constant indices (unrolled fill);
     // an LDS ring without qh is filled by a rolled loop (smaller code).
     constexpr bool KQ = Sink::keeps_q;
-    double qh[KQ ? 4 : 1][NV];
+    double qh[KQ ? 4 : 1][V];
     auto fill = [&](int k) {
-        double qc[NV];
+        double qc[V];
         src.load(c0 - 3 + k, qc);
         if constexpr (KQ) {
             if (k >= 1) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) qh[k - 1][v] = qc[v];
+                for (int v = 0; v < V; ++v) qh[k - 1][v] = qc[v];
             }
         }
-        T w[NV];
-        prim_of<T>(mixd, qc, w);
+        T w[V];
+        prim_of<T, F>(mixd, qc, w);
         src.finish(c0 - 3 + k, w);
         W.store(k, w);
     };
@@ -657,9 +720,9 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
         for (int k = 0; k < 5; ++k) fill(k);
     }
 
-    T rprev[NV], Fprev[NV], ufprev = T(0);
+    T rprev[V], Fprev[V], ufprev = T(0);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) rprev[v] = Fprev[v] = T(0);
+    for (int v = 0; v < V; ++v) rprev[v] = Fprev[v] = T(0);
 
     // faces this segment counts (learned fallbacks): c0+1/2 .. c1-1/2, and
     // c0-1/2 in the first segment unless it is the periodic image of the
@@ -668,41 +731,45 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
     for (int c = c0 - 1; c <= c1; ++c) {
         // next cell entering the window (c+3), and what the output of cell
         // c-1 needs, fetched early
-        double qnext[NV];
+        double qnext[V];
         if (c < c1) src.load(c + 3, qnext);
         if (c > c0) sink.prefetch(g, c - 1);
 
-        T lft[NV], rgt[NV];
+        T lft[V], rgt[V];
         recon.count_edges((c >= c0 && c < c1) || (c == c0 - 1 && own_first),
                           (c > c0 && c <= c1) || (c == c0 && own_first));
         recon.cell_win(W, eps, lft, rgt);
 
         if (c >= c0) {
-            T F[NV], uf;
-            hllc<DIR, T>(mix, rprev, lft, F, uf);
+            T Fl[V], uf;
+            hllc_f<DIR, T, F>(mix, rprev, lft, Fl, uf);
             if (c > c0) {
-                // cell c-1: faces c-3/2 (Fprev) and c-1/2 (F)
-                T fd[NV];
+                // cell c-1: faces c-3/2 (Fprev) and c-1/2 (Fl)
+                T fd[V];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) fd[v] = (Fprev[v] - F[v]) * idx;
-                sink.put(g, c - 1, fd, W(1, 6) * ((uf - ufprev) * idx), W, &qh[0][0]);
+                for (int v = 0; v < V; ++v) fd[v] = (Fprev[v] - Fl[v]) * idx;
+                // every volume fraction's source alpha_a div(u)
+                T src_a[F::NA];
+#pragma unroll
+                for (int a = 0; a < F::NA; ++a) src_a[a] = W(1, F::IA + a) * ((uf - ufprev) * idx);
+                sink.put(g, c - 1, fd, src_a, W, &qh[0][0]);
             }
 #pragma unroll
-            for (int v = 0; v < NV; ++v) Fprev[v] = F[v];
+            for (int v = 0; v < V; ++v) Fprev[v] = Fl[v];
             ufprev = uf;
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) rprev[v] = rgt[v];
+        for (int v = 0; v < V; ++v) rprev[v] = rgt[v];
 
         if (c < c1) {
             // cell c+3 enters, cell c-2 (no longer needed) leaves
-            T w[NV];
-            prim_of<T>(mixd, qnext, w);
+            T w[V];
+            prim_of<T, F>(mixd, qnext, w);
             src.finish_ahead(c + 3, w);  // c + 3 >= c0 + 2 >= 2
             W.push(w);
             if constexpr (KQ) {
 #pragma unroll
-                for (int v = 0; v < NV; ++v) {
+                for (int v = 0; v < V; ++v) {
                     qh[0][v] = qh[1][v];
                     qh[1][v] = qh[2][v];
                     qh[2][v] = qh[3][v];
@@ -716,10 +783,10 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
 // Cell source for the y and z sweeps (DIR 1 or 2): straight from global
 // memory; the lanes of a wave are consecutive x, so each load is a
 // contiguous row.
-template <int DIR>
+template <int DIR, class F = Fl2>
 struct GlobalSrc {
     const double* __restrict__ qs;
-    const double* inf;  // device copy of this direction's inflow states [2][NV] (required)
+    const double* inf;  // device copy of this direction's inflow states [2][NVMAX] (required)
     long long base, sd, N;
     int n, bclo, bchi;
     // inflow ghosts: positions below ilo or at/above ihi; reflective ghosts:
@@ -730,28 +797,28 @@ struct GlobalSrc {
     int fhi = bchi == BC_REFLECTIVE ? n : INT_MAX;
     // An inflow ghost reads the side's state instead of a cell: only the
     // (wave-uniform) base pointer and stride of the same loads change.
-    __device__ __forceinline__ void load(int pos, double q[NV]) const
+    __device__ __forceinline__ void load(int pos, double* q) const
     {
         const bool lo = pos < ilo, hi = pos >= ihi;
-        const double* p = lo ? inf : (hi ? inf + NV : qs + base + (long long)map_cell(pos, n, bclo, bchi) * sd);
+        const double* p = lo ? inf : (hi ? inf + NVMAX : qs + base + (long long)map_cell(pos, n, bclo, bchi) * sd);
         const long long st = (lo || hi) ? 1 : N;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) q[v] = p[v * st];
+        for (int v = 0; v < F::NV; ++v) q[v] = p[v * st];
     }
     // A reflective ghost enters with its normal velocity negated; applied to
     // the primitives where the march uses them (the same bits as negating
     // the momentum before the conversion), so the load stays in flight.
     template <typename T>
-    __device__ __forceinline__ void finish(int pos, T w[NV]) const
+    __device__ __forceinline__ void finish(int pos, T* w) const
     {
-        if (pos < flo || pos >= fhi) w[2 + DIR] = -w[2 + DIR];
+        if (pos < flo || pos >= fhi) w[F::IM + DIR] = -w[F::IM + DIR];
     }
     // the same for a position known to be >= 0 (cells entering the window
     // ahead of the march)
     template <typename T>
-    __device__ __forceinline__ void finish_ahead(int pos, T w[NV]) const
+    __device__ __forceinline__ void finish_ahead(int pos, T* w) const
     {
-        if (pos >= fhi) w[2 + DIR] = -w[2 + DIR];
+        if (pos >= fhi) w[F::IM + DIR] = -w[F::IM + DIR];
     }
 };
 
@@ -776,7 +843,7 @@ constexpr int yz_block()
 
 // (The learned passes keep the occupancy hint of two waves per SIMD: without
 // it the compiler schedules them for a higher occupancy they cannot reach.)
-template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED, bool CFL = false, int SCHEME = 5>
+template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED, bool CFL = false, int SCHEME = 5, class F = Fl2>
 __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 2 : 1) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
                                                    T* __restrict__ racc, double* out, int seg,
                                                    const double* __restrict__ dt_dev, double dt_arg,
@@ -795,15 +862,15 @@ __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 2 : 1) sweep_yz
     const long long base = (long long)i + (long long)blockIdx.y * g.stride[SA];
     const int c0 = blockIdx.z * seg;
     const int c1 = min(c0 + seg, n);
-    GlobalSrc<DIR> src{qs, g.inflow_dev + DIR * 2 * NV, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
+    GlobalSrc<DIR, F> src{qs, g.inflow_dev + DIR * 2 * NVMAX, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
     constexpr int CHK = (MODE == OUT_STAGE1 || MODE == OUT_STAGE2) ? CHK_STATE : (CFL ? CHK_CFL : CHK_NONE);
-    GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CHK, !LEARNED> sink{
+    GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CHK, !LEARNED, F> sink{
         OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid,
-        CflAcc{0.0, 0u, CHK == CHK_CFL}};
+        CflAcc<F>{0.0, 0u, CHK == CHK_CFL}};
     auto recon = make_recon<T, LEARNED, SCHEME, BLOCK / 64>(g, mlp, valid);
-    __shared__ T win[5][NV][BLOCK];
-    LdsWindow<T, BLOCK> W{&win[0][0][threadIdx.x], 0};
-    march<DIR, T>(g, src, sink, recon, c0, c1, W);
+    __shared__ T win[5][F::NV][BLOCK];
+    LdsWindow<T, BLOCK, F::NV> W{&win[0][0][threadIdx.x], 0};
+    march<DIR, T, F>(g, src, sink, recon, c0, c1, W);
     recon.flush(fb);
     if constexpr (CHK != CHK_NONE) {
         if (sink.acc.bad) atomicOr(status, sink.acc.bad);
@@ -825,17 +892,18 @@ __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 2 : 1) sweep_yz
 constexpr int XROWS = 64;
 constexpr int XCHUNK = 4;
 
+template <class F = Fl2>
 struct LdsSrc {
-    double (*buf)[NV][XROWS];  // [XCHUNK][NV][XROWS]
+    double (*buf)[F::NV][XROWS];  // [XCHUNK][F::NV][XROWS]
     const double* __restrict__ qs;
-    const double* inf;  // device copy of the x inflow states [2][NV] (required)
+    const double* inf;  // device copy of the x inflow states [2][NVMAX] (required)
     long long N;
     long long row0;  // first row of the block
     long long nrows;
     int nx, bclo, bchi;
     int pstart;  // first position fetched (c0 - 3)
 
-    __device__ __forceinline__ void load(int pos, double q[NV]) const
+    __device__ __forceinline__ void load(int pos, double* q) const
     {
         const int slot = (pos - pstart) % XCHUNK;
         if (slot == 0) {
@@ -848,15 +916,15 @@ struct LdsSrc {
                 // inflow ghosts read the side's state (base pointer and stride)
                 const int pp = pos + cx;
                 const bool lo = pp < ilo, hi = pp >= ihi;
-                const double* p = lo ? inf : (hi ? inf + NV : qs + row * nx + map_cell(pp, nx, bclo, bchi));
+                const double* p = lo ? inf : (hi ? inf + NVMAX : qs + row * nx + map_cell(pp, nx, bclo, bchi));
                 const long long st = (lo || hi) ? 1 : N;
 #pragma unroll
-                for (int v = 0; v < NV; ++v) buf[cx][v][r] = p[v * st];
+                for (int v = 0; v < F::NV; ++v) buf[cx][v][r] = p[v * st];
             }
             __syncthreads();
         }
 #pragma unroll
-        for (int v = 0; v < NV; ++v) q[v] = buf[slot][v][threadIdx.x];
+        for (int v = 0; v < F::NV; ++v) q[v] = buf[slot][v][threadIdx.x];
     }
     int ilo = bclo == BC_INFLOW ? 0 : INT_MIN;
     int ihi = bchi == BC_INFLOW ? nx : INT_MAX;
@@ -865,20 +933,20 @@ struct LdsSrc {
     int flo = bclo == BC_REFLECTIVE ? 0 : INT_MIN;
     int fhi = bchi == BC_REFLECTIVE ? nx : INT_MAX;
     template <typename T>
-    __device__ __forceinline__ void finish(int pos, T w[NV]) const
+    __device__ __forceinline__ void finish(int pos, T* w) const
     {
-        if (pos < flo || pos >= fhi) w[2] = -w[2];
+        if (pos < flo || pos >= fhi) w[F::IM] = -w[F::IM];
     }
     template <typename T>
-    __device__ __forceinline__ void finish_ahead(int pos, T w[NV]) const
+    __device__ __forceinline__ void finish_ahead(int pos, T* w) const
     {
-        if (pos >= fhi) w[2] = -w[2];
+        if (pos >= fhi) w[F::IM] = -w[F::IM];
     }
 };
 
-template <typename T, bool FIRST, int MODE>
+template <typename T, bool FIRST, int MODE, class F = Fl2>
 struct LdsSink {
-    T (*buf)[NV + 1][XROWS];  // [XCHUNK][fd 0..6, src][XROWS]
+    T (*buf)[F::NV + F::NA][XROWS];  // [XCHUNK][flux differences, volume-fraction sources][XROWS]
     OutArgs<T> o;
     long long row0, nrows;
     int nx, c0, c1;
@@ -886,12 +954,13 @@ struct LdsSink {
     static constexpr bool keeps_q = false;
     __device__ __forceinline__ void prefetch(const Grid&, int) {}
     template <class Win>
-    __device__ __forceinline__ void put(const Grid& g, int c, const T fd[NV], T src, const Win&, const double*)
+    __device__ __forceinline__ void put(const Grid& g, int c, const T* fd, const T* src, const Win&, const double*)
     {
         const int slot = (c - c0) % XCHUNK;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) buf[slot][v][threadIdx.x] = fd[v];
-        buf[slot][NV][threadIdx.x] = src;
+        for (int v = 0; v < F::NV; ++v) buf[slot][v][threadIdx.x] = fd[v];
+#pragma unroll
+        for (int a = 0; a < F::NA; ++a) buf[slot][F::NV + a][threadIdx.x] = src[a];
         if (slot == XCHUNK - 1 || c == c1 - 1) {
             const int p0 = c - slot, cnt = slot + 1;
             __syncthreads();
@@ -900,11 +969,13 @@ struct LdsSink {
                 const int item = threadIdx.x + it * XROWS;
                 const int r = item / XCHUNK, cx = item % XCHUNK;
                 if (cx < cnt && row0 + r < nrows) {
-                    T f[NV];
+                    T f[F::NV], sa[F::NA];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) f[v] = buf[cx][v][r];
+                    for (int v = 0; v < F::NV; ++v) f[v] = buf[cx][v][r];
+#pragma unroll
+                    for (int a = 0; a < F::NA; ++a) sa[a] = buf[cx][F::NV + a][r];
                     const long long cell = (row0 + r) * nx + p0 + cx;
-                    emit_cell<T, FIRST, MODE>(g, o, cell, f, buf[cx][NV][r]);
+                    emit_cell<T, FIRST, MODE, F>(g, o, cell, f, sa);
                 }
             }
             __syncthreads();  // the buffer is refilled next
@@ -912,27 +983,27 @@ struct LdsSink {
     }
 };
 
-template <typename T, bool FIRST, int MODE, bool LEARNED, int SCHEME = 5>
+template <typename T, bool FIRST, int MODE, bool LEARNED, int SCHEME = 5, class F = Fl2>
 __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* __restrict__ qs, const double* qn,
                                                           T* __restrict__ racc, double* out, int seg,
                                                           const double* __restrict__ dt_dev, double dt_arg,
                                                           const MlpLane* __restrict__ mlp, unsigned long long* fb)
 {
-    __shared__ double ibuf[XCHUNK][NV][XROWS];
-    __shared__ T obuf[XCHUNK][NV + 1][XROWS];
+    __shared__ double ibuf[XCHUNK][F::NV][XROWS];
+    __shared__ T obuf[XCHUNK][F::NV + F::NA][XROWS];
     const int nx = g.n[0];
     const long long nrows = (long long)g.n[1] * g.n[2];
     const long long row0 = (long long)blockIdx.x * XROWS;
     const int c0 = blockIdx.z * seg;
     const int c1 = min(c0 + seg, nx);
 
-    LdsSrc src{ibuf, qs, g.inflow_dev, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
-    LdsSink<T, FIRST, MODE> sink{obuf, OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx,
-                                 c0, c1};
+    LdsSrc<F> src{ibuf, qs, g.inflow_dev, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
+    LdsSink<T, FIRST, MODE, F> sink{obuf, OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx,
+                                    c0, c1};
     auto recon = make_recon<T, LEARNED, SCHEME, XROWS / 64>(g, mlp, row0 + threadIdx.x < nrows);
-    __shared__ T win[5][NV][XROWS];
-    LdsWindow<T, XROWS> W{&win[0][0][threadIdx.x], 0};
-    march<0, T>(g, src, sink, recon, c0, c1, W);
+    __shared__ T win[5][F::NV][XROWS];
+    LdsWindow<T, XROWS, F::NV> W{&win[0][0][threadIdx.x], 0};
+    march<0, T, F>(g, src, sink, recon, c0, c1, W);
     recon.flush(fb);
 }
 

@@ -176,6 +176,7 @@ __device__ __forceinline__ void inflow_slots_init(const Grid& g, const Mix<doubl
 // (cell x-2+k; ghost slots included).
 template <typename T>
 struct RowWindow {
+    static constexpr int nv = NV;
     const T* p;  // P + x
     int np;
     __device__ __forceinline__ T operator()(int k, int v) const { return p[v * np + k]; }
@@ -292,7 +293,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_x_rows(Grid g, const doubl
 #pragma unroll
             for (int v = 0; v < NV; ++v) fd[v] = (Fm[v] - F[v]) * idx;
             const T src = a1 * ((F[NV] - Fm[NV]) * idx);
-            emit_cell<T, FIRST, MODE>(g, o, row * nx + x, fd, src);
+            emit_cell<T, FIRST, MODE>(g, o, row * nx + x, fd, &src);
         }
     }
     recon.flush(fb);
@@ -327,7 +328,7 @@ struct XYSink {
     Mix<T> mix;
 
     template <class Win>
-    __device__ __forceinline__ void put(const Grid& g, int c, const T fdy[NV], T srcy, const Win& W, const double*)
+    __device__ __forceinline__ void put(const Grid& g, int c, const T* fdy, const T* srcy, const Win& W, const double*)
     {
         const long long row = row_z + c;
         T w[NV];
@@ -397,7 +398,7 @@ struct XYSink {
             // plus the y part
 #pragma unroll
             for (int v = 0; v < NV; ++v) r[v] = r[v] + fdy[v];
-            r[6] += srcy;
+            r[6] += srcy[0];
             store_cell<T, MODE>(g, o, base_z + (long long)c * nx + x, r);
         }
     }
@@ -421,7 +422,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_xy(Grid g, const double* _
     const int c1 = min(c0 + seg, ny);
     const long long base_z = (long long)z * g.stride[2];
 
-    GlobalSrc<1> src{qs, g.inflow_dev + 1 * 2 * NV, base_z + xc, g.stride[1], g.N, ny, g.bc[1][0], g.bc[1][1]};
+    GlobalSrc<1> src{qs, g.inflow_dev + 1 * 2 * NVMAX, base_z + xc, g.stride[1], g.N, ny, g.bc[1][0], g.bc[1][1]};
     XYSink<T, MODE, SCHEME> sink{OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg},
                          lds + lay.p,
                          lds + lay.l,
@@ -445,7 +446,7 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_xy(Grid g, const double* _
                          lds + lay.p, nx + 4, nx);
     ReconJS<T, SCHEME> recon{};
     RegWindow<T> W;
-    march<1, T>(g, src, sink, recon, c0, c1, W);
+    march<1, T, Fl2>(g, src, sink, recon, c0, c1, W);
 }
 
 }  // namespace mfx

@@ -11,7 +11,12 @@ import oracle
 TOL = 1e-12  # FP64 path against the FP64 oracle, per conserved field
 
 
-MOMENTUM = (2, 3, 4)
+MOMENTUM = (2, 3, 4)  # two fluids
+
+
+def _nf(nv: int) -> int:
+    """Fluids of a state with nv variables (2 nf + 3)."""
+    return (nv - 3) // 2
 
 
 def _shared_momentum(scale: np.ndarray) -> np.ndarray:
@@ -19,14 +24,15 @@ def _shared_momentum(scale: np.ndarray) -> np.ndarray:
     not depend on how the axes are oriented (a problem with v = w = 0 has
     max|rho v| = 0, which cannot serve as a scale)."""
     scale = scale.copy()
-    scale[list(MOMENTUM)] = scale[list(MOMENTUM)].max()
+    m = _nf(scale.size)
+    scale[m:m + 3] = scale[m:m + 3].max()
     return scale
 
 
 def rel_linf(x: np.ndarray, y: np.ndarray) -> np.ndarray:
     """State error per field: max|x - y| / max|y|, momentum sharing one scale."""
-    x = x.reshape(7, -1)
-    y = y.reshape(7, -1)
+    x = x.reshape(x.shape[0], -1)
+    y = y.reshape(y.shape[0], -1)
     den = _shared_momentum(np.abs(y).max(axis=1))
     den = np.where(den > 0, den, 1.0)
     return np.abs(x - y).max(axis=1) / den
@@ -37,17 +43,19 @@ def physical_flux_scale(q: np.ndarray, spec) -> np.ndarray:
     physical flux F alone (the scale the FP64 right-hand-side bar was first
     written with; flux_scale adds the wave-speed term)."""
     g = oracle.make_grid(spec)
-    w = oracle.cons_to_prim(g, q).reshape(7, -1)
-    qq = q.reshape(7, -1)
-    p = w[5]
+    nv = q.shape[0]
+    m, e = _nf(nv), _nf(nv) + 3
+    w = oracle.cons_to_prim(g, q).reshape(nv, -1)
+    qq = q.reshape(nv, -1)
+    p = w[e]
     tot = np.zeros_like(qq)
     for d in range(3):
         if spec["n"][d] <= 1:
             continue
-        ud = w[2 + d]
+        ud = w[m + d]
         F = np.abs(qq * ud)
-        F[2 + d] = np.abs(qq[2 + d] * ud + p)
-        F[5] = np.abs((qq[5] + p) * ud)
+        F[m + d] = np.abs(qq[m + d] * ud + p)
+        F[e] = np.abs((qq[e] + p) * ud)
         tot += F / spec["dx"][d]
     return _shared_momentum(tot.max(axis=1))
 
@@ -61,17 +69,19 @@ def flux_scale(q: np.ndarray, spec) -> np.ndarray:
     momentum rho u u_d + p delta; energy (rho E + p) u_d) and lambda =
     max over cells of sum_d (|u_d| + c) / dx_d."""
     g = oracle.make_grid(spec)
-    w = oracle.cons_to_prim(g, q).reshape(7, -1)
-    qq = q.reshape(7, -1)
-    p = w[5]
+    nv = q.shape[0]
+    m, e = _nf(nv), _nf(nv) + 3
+    w = oracle.cons_to_prim(g, q).reshape(nv, -1)
+    qq = q.reshape(nv, -1)
+    p = w[e]
     tot = np.zeros_like(qq)
     for d in range(3):
         if spec["n"][d] <= 1:
             continue
-        ud = w[2 + d]
+        ud = w[m + d]
         F = np.abs(qq * ud)
-        F[2 + d] = np.abs(qq[2 + d] * ud + p)
-        F[5] = np.abs((qq[5] + p) * ud)
+        F[m + d] = np.abs(qq[m + d] * ud + p)
+        F[e] = np.abs((qq[e] + p) * ud)
         tot += F / spec["dx"][d]
     dt = oracle.cfl_dt(g, q)
     lam = spec.get("cfl", 0.4) / dt if np.isfinite(dt) else 0.0
@@ -83,8 +93,8 @@ def rhs_rel_linf(x: np.ndarray, y: np.ndarray, q: np.ndarray, spec) -> np.ndarra
     is a difference of (flux_scale).  Where L_k vanishes in exact arithmetic
     (uniform alpha1, or uniform pressure for the transverse momentum) both
     sides hold rounding noise of those terms, so max|L_k| is no scale."""
-    x = x.reshape(7, -1)
-    y = y.reshape(7, -1)
+    x = x.reshape(x.shape[0], -1)
+    y = y.reshape(y.shape[0], -1)
     den = np.maximum(np.abs(y).max(axis=1), flux_scale(q, spec))
     den = np.where(den > 0, den, 1.0)  # no active direction: L == 0 exactly
     return np.abs(x - y).max(axis=1) / den
@@ -93,8 +103,8 @@ def rhs_rel_linf(x: np.ndarray, y: np.ndarray, q: np.ndarray, spec) -> np.ndarra
 def rhs_rel_linf_physical(x: np.ndarray, y: np.ndarray, q: np.ndarray, spec) -> np.ndarray:
     """The same error scaled by max(max|L_k|, physical_flux_scale): the
     stricter scale without the wave-speed term."""
-    x = x.reshape(7, -1)
-    y = y.reshape(7, -1)
+    x = x.reshape(x.shape[0], -1)
+    y = y.reshape(y.shape[0], -1)
     den = np.maximum(np.abs(y).max(axis=1), physical_flux_scale(q, spec))
     den = np.where(den > 0, den, 1.0)
     return np.abs(x - y).max(axis=1) / den
@@ -153,7 +163,7 @@ def oracle_step_at(spec, q0: np.ndarray, cells: np.ndarray, dt: float) -> np.nda
     Each stage's state is formed on the cells the next stage's stencils reach."""
     g = oracle.make_grid(spec)
     Nc = q0[0].size
-    qf = q0.reshape(7, Nc)
+    qf = q0.reshape(q0.shape[0], Nc)
     S2 = cross_cells(spec, cells)
     S1 = cross_cells(spec, S2)
     L0 = oracle.rhs_at(g, q0, S1).T

@@ -191,3 +191,4 @@ def test_size_limits():
     for n in ((65536, 1, 1), (2048, 1024, 1025)):
         d = _native.make_desc(wl.spec(n, ((1, 1), (0, 0), (0, 0))))
         assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0
+
