@@ -321,6 +321,29 @@ const char* mfx_mlp_last_error(void);
 int mfx_profile(mfx_ctx* ctx, int enable);
 int mfx_profile_read(mfx_ctx* ctx, double* ms, int64_t* counts);
 
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc: the
+ * right-hand side of mfx_rhs for the state q_dev (layout above) on the
+ * descriptor's grid, with no context and no workspace.  Its scratch (the
+ * partial right-hand side, the x rows' boundary faces, the inflow states)
+ * lives in a static device array of MFX_STATIC_SCRATCH_BYTES that every GPU
+ * the library runs on holds until the process ends; the call allocates
+ * nothing.  Scratch a grid needs: 768 + a(e * 16 * ny * nz) + a(e * nv * nx *
+ * ny * nz) bytes, a() rounding up to a multiple of 256, e = 8 for MFX_FP64
+ * and 4 for MFX_FP32_MIXED, nv = 2 num_fluids + 3 (two fluids: up to about
+ * 2.3 million cells in float64, e.g. 128^3, and 4.6 million in float32); a
+ * larger grid is rejected with MFX_ENOMEM before anything is enqueued.  Jiang-Shu or WENO-Z weights,
+ * order 5 or 3 (learned weights need a context: MFX_EINVAL).  q_dev and
+ * rhs_dev_out are device pointers on the current device and must not
+ * overlap.  Enqueued on hip_stream (hipStream_t as void*, NULL = default
+ * stream); asynchronous.  Every call on one GPU uses that GPU's one array,
+ * which keeps the last call's contents (nothing in it is read before the
+ * call writes it): calls that overlap in time on one GPU (other streams,
+ * other threads) race, and the caller must order them.  Errors are returned
+ * as codes with the message in mfx_last_error(NULL). */
+#define MFX_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+int mfx_rhs_static(const mfx_grid_desc* desc, const double* q_dev, double* rhs_dev_out, void* hip_stream);
+
 /* Release the host-side context (the workspace stays the caller's). */
 void mfx_destroy(mfx_ctx* ctx);
 

@@ -18,7 +18,7 @@ from ._native import (MFX_BC_INFLOW, MFX_BC_PERIODIC, MFX_BC_REFLECTIVE, MFX_BC_
 __all__ = ["Solver", "MfxError", "MFX_FP64", "MFX_FP32_MIXED", "MFX_WENO5_JS", "MFX_WENO5_LEARNED",
            "MFX_WENO5_LEARNED_EDGE", "MFX_WENO5_Z",
            "MFX_BC_PERIODIC", "MFX_BC_TRANSMISSIVE", "MFX_BC_REFLECTIVE", "MFX_BC_INFLOW",
-           "workspace_bytes", "inflow_states"]
+           "workspace_bytes", "inflow_states", "rhs_static"]
 
 
 def workspace_bytes(spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS) -> int:
@@ -47,6 +47,32 @@ def inflow_states(spec: dict, prim) -> "np.ndarray":
             sol = Solver(one)
             sol.set_primitive(torch.from_numpy(prim[d, s].reshape(nv, 1, 1, 1).copy()).cuda())
             out[d, s] = sol.get_state().cpu().numpy().reshape(nv)
+    return out
+
+
+def rhs_static(spec: dict, q, out=None, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS, stream=None):
+    """mfx_rhs_static: the right-hand side of the state q (float64 device
+    tensor [nv, nz, ny, nx]) with no context, no workspace and no device
+    allocation in the library (its scratch is a static device array).  out
+    (same shape) receives it; it is allocated here (by torch) only if not
+    given."""
+    import torch
+
+    shape = (_native.nvars(spec), int(spec["n"][2]), int(spec["n"][1]), int(spec["n"][0]))
+    for name, t in (("q", q), ("out", out)):
+        if t is None:
+            continue
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous float64 tensor on the device")
+        if tuple(t.shape) != shape:
+            raise ValueError(f"{name} must have shape {shape}")
+    if out is None:
+        out = torch.empty(shape, dtype=torch.float64, device=q.device)
+    st = stream if stream is not None else torch.cuda.current_stream(q.device)
+    d = _native.make_desc(spec, precision, weights)
+    rc = _native.lib().mfx_rhs_static(ctypes.byref(d), ctypes.c_void_p(q.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                      ctypes.c_void_p(st.cuda_stream))
+    _native.check(rc, None)
     return out
 
 

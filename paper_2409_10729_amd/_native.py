@@ -25,8 +25,9 @@ EXPORTED = (
     "mfx_destroy", "mfx_last_error", "mfx_mlp_sample_stencils", "mfx_mlp_face_targets", "mfx_mlp_features", "mfx_mlp_features_edge",
     "mfx_mlp_packed_bytes",
     "mfx_mlp_pack", "mfx_mlp_forward", "mfx_mlp_grad_workspace", "mfx_mlp_loss_grad", "mfx_mlp_adam",
-    "mfx_mlp_last_error",
+    "mfx_mlp_last_error", "mfx_rhs_static",
 )
+STATIC_SCRATCH_BYTES = 128 << 20
 MLP_PARAMS = 1347
 MAX_FLUIDS = 3
 MAX_VARS = 2 * MAX_FLUIDS + 3
@@ -118,6 +119,8 @@ def lib():
         L.mfx_mlp_adam.restype = ctypes.c_int
         L.mfx_mlp_last_error.argtypes = []
         L.mfx_mlp_last_error.restype = ctypes.c_char_p
+        L.mfx_rhs_static.argtypes = [dp, vp, vp, vp]
+        L.mfx_rhs_static.restype = ctypes.c_int
         L.mfx_destroy.argtypes = [vp]
         L.mfx_destroy.restype = None
         L.mfx_last_error.argtypes = [vp]

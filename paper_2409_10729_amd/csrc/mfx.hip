@@ -10,6 +10,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -1056,3 +1057,125 @@ const char* mfx_last_error(const mfx_ctx* c) { return c ? c->err.c_str() : g_ini
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- right-hand side without allocation
+//
+// mfx_rhs_static: the passes of mfx_rhs on a context built on the stack,
+// with every buffer besides the caller's state and output in `scratch`.
+
+// One copy per GPU the library runs on, held until the process ends.  In
+// host code this name is only a handle: the array's device address comes
+// from hipGetSymbolAddress, once per device (static_scratch below).
+static __device__ __align__(256) unsigned char scratch[MFX_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr size_t SCR_INFLOW = 0;    // inflow states [3][2][NVMAX] float64 (432 bytes)
+constexpr size_t SCR_STATUS = 512;  // status word (unused by the right-hand side, kept zero)
+constexpr size_t SCR_FB = 520;      // fallback counter (learned weights only; kept zero)
+constexpr size_t SCR_BFACE = 768;   // x rows' boundary faces, then the partial right-hand side
+constexpr int MAX_DEVICES = 64;
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+size_t static_bface_bytes(const mfx_grid_desc* d, size_t elem)
+{
+    return align_up(elem * BFACE * 2 * (size_t)d->n[1] * (size_t)d->n[2]);
+}
+
+size_t static_need(const mfx_grid_desc* d)
+{
+    const size_t elem = d->precision == MFX_FP32_MIXED ? sizeof(float) : sizeof(double);
+    const size_t N = (size_t)d->n[0] * d->n[1] * d->n[2];
+    return SCR_BFACE + static_bface_bytes(d, elem) + align_up(elem * vars_of(d) * N);
+}
+
+// Device address of `scratch` on device dev (current), looked up once per device.
+int static_scratch(int dev, char** out, std::string& why)
+{
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        why = "device index " + std::to_string(dev) + " beyond the scratch table";
+        return MFX_EINVAL;
+    }
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return MFX_EHIP;
+        }
+        g_scratch_ptr[dev] = p;
+    }
+    *out = static_cast<char*>(g_scratch_ptr[dev]);
+    return MFX_OK;
+}
+
+// Inflow states into the scratch (from the kernel arguments, so no copy
+// call), status word and fallback counter cleared.
+__global__ void __launch_bounds__(64) static_setup_kernel(Grid g, double* __restrict__ inflow,
+                                                           unsigned* __restrict__ status,
+                                                           unsigned long long* __restrict__ fb)
+{
+    const int t = threadIdx.x;
+    if (t < 3 * 2 * NVMAX) inflow[t] = (&g.inflow[0][0][0])[t];
+    if (t == 0) {
+        *status = 0u;
+        *fb = 0ull;
+    }
+}
+
+int static_fail(int code, const std::string& msg)
+{
+    g_init_error = msg;
+    return code;
+}
+
+}  // namespace
+
+extern "C" int mfx_rhs_static(const mfx_grid_desc* desc, const double* q_dev, double* rhs_dev_out,
+                              void* hip_stream)
+{
+    std::string why;
+    if (!validate(desc, why)) return static_fail(MFX_EINVAL, why);
+    if (learned_weights(*desc))
+        return static_fail(MFX_EINVAL, "mfx_rhs_static takes Jiang-Shu or WENO-Z weights (a network needs a context)");
+    if (!q_dev || !rhs_dev_out) return static_fail(MFX_EINVAL, "q_dev and rhs_dev_out must not be NULL");
+    const size_t N = (size_t)desc->n[0] * desc->n[1] * desc->n[2];
+    const size_t bytes = sizeof(double) * vars_of(desc) * N;
+    const char* qa = reinterpret_cast<const char*>(q_dev);
+    const char* ra = reinterpret_cast<const char*>(rhs_dev_out);
+    if (ra < qa + bytes && qa < ra + bytes) return static_fail(MFX_EINVAL, "q_dev and rhs_dev_out overlap");
+    const size_t need = static_need(desc);
+    if (need > MFX_STATIC_SCRATCH_BYTES)
+        return static_fail(MFX_ENOMEM, "the grid needs " + std::to_string(need) + " bytes of scratch; the static array holds " +
+                                           std::to_string((size_t)MFX_STATIC_SCRATCH_BYTES));
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return static_fail(MFX_EHIP, "hipGetDevice failed");
+    char* sb = nullptr;
+    if (int rc = static_scratch(dev, &sb, why)) return static_fail(rc, why);
+
+    mfx_ctx c{};  // zero-initialised; lives for this call only
+    c.desc = *desc;
+    c.stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c.device = dev;
+    const Overrides ov = read_overrides();
+    c.seg_override = ov.seg;
+    c.xmode_override = x_mode(desc, ov.xmode);
+    c.fuse_xy = ov.fuse_xy != 0;
+    c.fuse_cfl = ov.fuse_cfl != 0;
+    c.elem = desc->precision == MFX_FP32_MIXED ? sizeof(float) : sizeof(double);
+    c.ws = sb;
+    c.ws_bytes = need;
+    c.status = reinterpret_cast<unsigned*>(sb + SCR_STATUS);
+    c.fallback = reinterpret_cast<unsigned long long*>(sb + SCR_FB);
+    c.bface = sb + SCR_BFACE;
+    c.r = sb + SCR_BFACE + static_bface_bytes(desc, c.elem);
+    c.has_state = true;
+    setup_grid(desc, &c, reinterpret_cast<const double*>(sb + SCR_INFLOW));
+    static_setup_kernel<<<1, 64, 0, c.stream>>>(c.g, reinterpret_cast<double*>(sb + SCR_INFLOW), c.status, c.fallback);
+    int rc = launch_check(&c, "static_setup_kernel");
+    if (rc == MFX_OK) rc = run_passes(&c, q_dev, q_dev, rhs_dev_out, OUT_RHS, nullptr, 0.0);
+    if (rc != MFX_OK) return static_fail(rc, c.err);
+    return MFX_OK;
+}
