@@ -48,6 +48,7 @@ class OrcGrid(ctypes.Structure):
         ("weno_order", ctypes.c_int32),
         ("inflow", ((ctypes.c_double * NVMAX) * 2) * 3),
         ("nf", ctypes.c_int32),
+        ("xf", ctypes.c_void_p * 3),
     ]
 
 
@@ -79,6 +80,9 @@ def lib():
         L.orc_weno5_betas.argtypes = [dp, dp]
         L.orc_weno5_z.argtypes = [dp, ctypes.c_double, dp, dp]
         L.orc_weno3.argtypes = [dp, ctypes.c_double, dp, dp]
+        L.orc_weno5_nu.argtypes = [dp, dp, ctypes.c_double, dp, dp]
+        L.orc_weno5_nu_betas.argtypes = [dp, dp, dp]
+        L.orc_ideal_weights_nu.argtypes = [dp, dp, dp]
         L.orc_hllc.argtypes = [gp, dp, dp, ctypes.c_int, dp, dp]
         L.orc_sound_speed.argtypes = [gp, dp]
         L.orc_sound_speed.restype = ctypes.c_double
@@ -141,6 +145,19 @@ def make_grid(spec: dict, weno_z: bool = False) -> OrcGrid:
             raise ValueError("bc must be 0 (periodic), 1 (transmissive), 2 (reflective) or 3 (inflow)")
         if 2 in kinds and 1 < g.n[d] < 3:
             raise ValueError("a reflective side needs at least 3 cells in its direction")
+    faces = spec.get("faces")
+    g._faces = []  # keeps the face arrays alive while the grid is used
+    if faces is not None:
+        for d in range(3):
+            if faces[d] is None:
+                continue
+            xf = np.ascontiguousarray(faces[d], dtype=np.float64)
+            if xf.shape != (g.n[d] + 1,) or not np.all(np.diff(xf) > 0):
+                raise ValueError(f"faces[{d}] must hold n[{d}] + 1 increasing coordinates")
+            if g.weno_order != 5 or g.weno_z:
+                raise ValueError("non-uniform cells take WENO5 with Jiang-Shu weights")
+            g._faces.append(xf)
+            g.xf[d] = xf.ctypes.data
     if "inflow" in spec:
         nv = nvars(g.nf)
         a = np.asarray(spec["inflow"], dtype=np.float64).reshape(3, 2, nv)
@@ -200,6 +217,8 @@ def rhs_learned(g: OrcGrid, q: np.ndarray, theta, mode: int = LEARNED_PER_VARIAB
     plant != 0 (tests only) builds in a deliberate mistake (see orc.c)."""
     if g.nf != 2:
         raise ValueError("the learned weights are defined for two fluids")
+    if any(g.xf[d] for d in range(3)):
+        raise ValueError("the learned weights are defined on uniform cells")
     q = np.ascontiguousarray(q, dtype=np.float64)
     th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32), dtype=np.float64)
     assert th.size == 1347
@@ -275,6 +294,34 @@ def weno3(v, eps=1e-6):
     r = ctypes.c_double()
     lib().orc_weno3(_dp(v), float(eps), ctypes.byref(l), ctypes.byref(r))
     return l.value, r.value
+
+
+def weno5_nu(h, v, eps=1e-6):
+    """(left edge, right edge) of the middle cell of five cells of widths h
+    with averages v: WENO5 with Jiang-Shu weights on non-uniform cells."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    l = ctypes.c_double()
+    r = ctypes.c_double()
+    lib().orc_weno5_nu(_dp(h), _dp(v), float(eps), ctypes.byref(l), ctypes.byref(r))
+    return l.value, r.value
+
+
+def weno5_nu_betas(h, v):
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    b = np.empty(3)
+    lib().orc_weno5_nu_betas(_dp(h), _dp(v), _dp(b))
+    return b
+
+
+def ideal_weights_nu(h):
+    """(right-edge, left-edge) ideal weights of the middle of five cells of widths h."""
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    dr = np.empty(3)
+    dl = np.empty(3)
+    lib().orc_ideal_weights_nu(_dp(h), _dp(dr), _dp(dl))
+    return dr, dl
 
 
 def weno5_z(v, eps=1e-6):

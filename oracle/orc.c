@@ -66,6 +66,8 @@ typedef struct {
     int32_t weno_order; /* 5 (default; 0 reads as 5) or 3: the two orders Sec. II-B names */
     double inflow[3][2][NVMAX]; /* conserved state of the ghost cells of an inflow side */
     int32_t nf;        /* fluids, 2..NFMAX (0 reads as 2) */
+    const double* xf[3]; /* face coordinates of a non-uniform direction (n + 1, increasing),
+                            or NULL for uniform cells of width dx */
 } orc_grid;
 
 /* Variables of the nf-fluid model (Sec. II-A states the two-fluid system
@@ -256,6 +258,131 @@ static void weno3(const double* v, double eps, double* left, double* right)
 /* Face states of the middle cell of a 5-value stencil in the grid's
    reconstruction: WENO5 (Jiang-Shu or WENO-Z weights), or WENO3 on the
    middle three values. */
+/* ---------- WENO5 on non-uniform cells (Jiang-Shu weights) ----------
+   The paper's mesh is structured with local refinement by a hyperbolic
+   tangent stretching (Sec. III-A, Vinokur); the same reconstruction on cells
+   of unequal widths, from its definition: cell c with stencil values
+   v[0..4] (cell averages of cells c-2..c+2) and widths h[0..4].  In the
+   coordinate xi = (x - x_c) / h_c (cell c spans [-1/2, 1/2]):
+     candidate k (cells c-2+k .. c+k): the quadratic A + B xi + C xi^2 whose
+       averages over those three cells are their values; its values at
+       xi = 1/2 (right edge) and -1/2 (left edge);
+     indicator beta_k = h_c int_c (p')^2 dx + h_c^3 int_c (p'')^2 dx
+       = B^2 + 13/3 C^2;
+     ideal weights d_k of an edge: the combination of the three candidates
+       that equals the quartic through all five averages at that edge (the
+       outer coefficients fix d_0 and d_2, the middle one d_1);
+     alpha_k = d_k / (eps + beta_k)^2, omega = alpha / sum alpha.
+   On equal widths this is weno5(). */
+
+/* Solve the m x m system K y = r (m <= 5) by Gaussian elimination with
+   partial pivoting; K and r are overwritten. */
+static void solve_small(int m, double K[5][5], double* r)
+{
+    for (int c = 0; c < m; ++c) {
+        int p = c;
+        for (int i = c + 1; i < m; ++i)
+            if (fabs(K[i][c]) > fabs(K[p][c])) p = i;
+        for (int j = 0; j < m; ++j) {
+            const double t = K[c][j];
+            K[c][j] = K[p][j];
+            K[p][j] = t;
+        }
+        const double t = r[c];
+        r[c] = r[p];
+        r[p] = t;
+        for (int i = c + 1; i < m; ++i) {
+            const double f = K[i][c] / K[c][c];
+            for (int j = c; j < m; ++j) K[i][j] = K[i][j] - f * K[c][j];
+            r[i] = r[i] - f * r[c];
+        }
+    }
+    for (int c = m - 1; c >= 0; --c) {
+        double a = r[c];
+        for (int j = c + 1; j < m; ++j) a = a - K[c][j] * r[j];
+        r[c] = a / K[c][c];
+    }
+}
+
+/* Cell boundaries of cells c-2..c+2 in the coordinate xi of cell c. */
+static void stencil_bounds(const double* h, double lo[5], double hi[5])
+{
+    lo[2] = -0.5;
+    hi[2] = 0.5;
+    for (int k = 1; k >= 0; --k) {
+        hi[k] = lo[k + 1];
+        lo[k] = hi[k] - h[k] / h[2];
+    }
+    for (int k = 3; k < 5; ++k) {
+        lo[k] = hi[k - 1];
+        hi[k] = lo[k] + h[k] / h[2];
+    }
+}
+
+/* Average of xi^m over [a, b]. */
+static double avg_pow(int m, double a, double b)
+{
+    return (pow(b, m + 1) - pow(a, m + 1)) / ((m + 1) * (b - a));
+}
+
+/* Coefficients g[j] of the value at xi = x0 of the polynomial of degree
+   m-1 whose averages over cells first .. first+m-1 are the values v: the
+   value is sum_j g[j] v[first+j]. */
+static void face_row(int m, int first, const double lo[5], const double hi[5], double x0, double* gout)
+{
+    double K[5][5], r[5];
+    /* K^T g = phi, with K[i][e] = average of xi^e over cell first+i */
+    for (int e = 0; e < m; ++e) {
+        for (int i = 0; i < m; ++i) K[e][i] = avg_pow(e, lo[first + i], hi[first + i]);
+        r[e] = pow(x0, e);
+    }
+    solve_small(m, K, r);
+    for (int i = 0; i < m; ++i) gout[i] = r[i];
+}
+
+/* Ideal weights of the edge at xi = x0. */
+static void ideal_weights(const double lo[5], const double hi[5], double x0, double d[3])
+{
+    double g5[5], r0[3], r1[3], r2[3];
+    face_row(5, 0, lo, hi, x0, g5);
+    face_row(3, 0, lo, hi, x0, r0);
+    face_row(3, 1, lo, hi, x0, r1);
+    face_row(3, 2, lo, hi, x0, r2);
+    d[0] = g5[0] / r0[0];
+    d[2] = g5[4] / r2[2];
+    d[1] = (g5[2] - d[0] * r0[2] - d[2] * r2[0]) / r1[1];
+}
+
+static void weno5_nu(const double* h, const double* v, double eps, double* left, double* right)
+{
+    double lo[5], hi[5];
+    stencil_bounds(h, lo, hi);
+    double beta[3], pr[3], pl[3];
+    for (int k = 0; k < 3; ++k) {
+        double K[5][5], y[5];
+        for (int i = 0; i < 3; ++i) {
+            for (int e = 0; e < 3; ++e) K[i][e] = avg_pow(e, lo[k + i], hi[k + i]);
+            y[i] = v[k + i];
+        }
+        solve_small(3, K, y); /* y = (A, B, C) */
+        beta[k] = y[1] * y[1] + 13.0 / 3.0 * (y[2] * y[2]);
+        pr[k] = y[0] + 0.5 * y[1] + 0.25 * y[2];
+        pl[k] = y[0] - 0.5 * y[1] + 0.25 * y[2];
+    }
+    double dr[3], dl[3];
+    ideal_weights(lo, hi, 0.5, dr);
+    ideal_weights(lo, hi, -0.5, dl);
+    double ar[3], al[3], sr = 0.0, sl = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        ar[k] = dr[k] / ((eps + beta[k]) * (eps + beta[k]));
+        al[k] = dl[k] / ((eps + beta[k]) * (eps + beta[k]));
+        sr += ar[k];
+        sl += al[k];
+    }
+    *right = (ar[0] / sr) * pr[0] + (ar[1] / sr) * pr[1] + (ar[2] / sr) * pr[2];
+    *left = (al[0] / sl) * pl[0] + (al[1] / sl) * pl[1] + (al[2] / sl) * pl[2];
+}
+
 static void reconstruct(const orc_grid* g, const double* st, double* left, double* right)
 {
     if (g->weno_order == 3)
@@ -361,6 +488,31 @@ static void ghost_state(const orc_grid* g, int d, int64_t i, int kind, double* q
 
 static int active(const orc_grid* g, int d) { return g->n[d] > 1; }
 
+/* Width of cell i along d; a ghost cell takes the width of the cell whose
+   state the boundary map gives it (periodic: the wrapped cell; transmissive
+   and inflow: the edge cell; reflective: the mirrored cell). */
+static double cell_width(const orc_grid* g, int d, int64_t i)
+{
+    if (!g->xf[d]) return g->dx[d];
+    int flip;
+    const int64_t j = map_index(g, d, i, &flip);
+    return g->xf[d][j + 1] - g->xf[d][j];
+}
+
+/* Face states of the middle cell of a stencil at position c along d:
+   WENO5 on the cells' widths for a non-uniform direction, else the grid's
+   uniform reconstruction. */
+static void reconstruct_at(const orc_grid* g, int d, int64_t c, const double* st, double* left, double* right)
+{
+    if (g->xf[d]) {
+        double h[5];
+        for (int o = 0; o < 5; ++o) h[o] = cell_width(g, d, c - 2 + o);
+        weno5_nu(h, st, g->eps, left, right);
+    } else {
+        reconstruct(g, st, left, right);
+    }
+}
+
 /* ---------- exported helpers for unit tests ---------- */
 void orc_weno5(const double* v, double eps, double* left, double* right)
 {
@@ -369,6 +521,35 @@ void orc_weno5(const double* v, double eps, double* left, double* right)
 void orc_weno5_betas(const double* v, double* b) { weno5_betas(v, b); }
 void orc_weno5_z(const double* v, double eps, double* left, double* right) { weno5_z(v, eps, left, right); }
 void orc_weno3(const double* v, double eps, double* left, double* right) { weno3(v, eps, left, right); }
+void orc_weno5_nu(const double* h, const double* v, double eps, double* left, double* right)
+{
+    weno5_nu(h, v, eps, left, right);
+}
+/* Indicators beta_k of the middle cell of five cells of widths h (pins). */
+void orc_weno5_nu_betas(const double* h, const double* v, double* beta)
+{
+    double lo[5], hi[5];
+    stencil_bounds(h, lo, hi);
+    for (int k = 0; k < 3; ++k) {
+        double K[5][5], y[5];
+        for (int i = 0; i < 3; ++i) {
+            for (int e = 0; e < 3; ++e) K[i][e] = avg_pow(e, lo[k + i], hi[k + i]);
+            y[i] = v[k + i];
+        }
+        solve_small(3, K, y);
+        beta[k] = y[1] * y[1] + 13.0 / 3.0 * (y[2] * y[2]);
+    }
+}
+
+/* Ideal weights of the right and left edge of the middle cell of five cells
+   of widths h (pins). */
+void orc_ideal_weights_nu(const double* h, double* dr, double* dl)
+{
+    double lo[5], hi[5];
+    stencil_bounds(h, lo, hi);
+    ideal_weights(lo, hi, 0.5, dr);
+    ideal_weights(lo, hi, -0.5, dl);
+}
 void orc_hllc(const orc_grid* g, const double* wl, const double* wr, int d, double* F, double* uf)
 {
     hllc(g, wl, wr, d, F, uf);
@@ -773,7 +954,7 @@ static void rhs_impl(const orc_grid* g, const double* q, double* rhs, const orc_
                         learned_cell(g, L, st, &lft[(c + 1) * nv], &rgt[(c + 1) * nv], fl, fl + 2);
                     } else {
                         for (int v = 0; v < nv; ++v)
-                            reconstruct(g, st[v], &lft[(c + 1) * nv + v], &rgt[(c + 1) * nv + v]);
+                            reconstruct_at(g, d, c, st[v], &lft[(c + 1) * nv + v], &rgt[(c + 1) * nv + v]);
                     }
                 }
                 if (L) {
@@ -787,12 +968,13 @@ static void rhs_impl(const orc_grid* g, const double* q, double* rhs, const orc_
                     hllc(g, &rgt[f * nv], &lft[(f + 1) * nv], d, &F[f * nv], &uf[f]);
                 for (int i = 0; i < n; ++i) {
                     int64_t cell = base_n + (int64_t)i * stride_n[d];
+                    const double h = cell_width(g, d, i);
                     for (int v = 0; v < nv; ++v)
-                        rhs[v * N + cell] += (F[i * nv + v] - F[(i + 1) * nv + v]) / g->dx[d];
+                        rhs[v * N + cell] += (F[i * nv + v] - F[(i + 1) * nv + v]) / h;
                     /* every volume-fraction equation carries alpha_i div(u) */
                     for (int v = ia0; v < nv; ++v) {
                         double ai = wp[v * NP + base_p + (int64_t)(i + gh[d]) * stride_p[d]];
-                        rhs[v * N + cell] += ai * ((uf[i + 1] - uf[i]) / g->dx[d]);
+                        rhs[v * N + cell] += ai * ((uf[i + 1] - uf[i]) / h);
                     }
                 }
                 free(lft);
@@ -881,13 +1063,14 @@ void orc_rhs_at(const orc_grid* g, const double* q, int64_t ncell, const int64_t
                 for (int v = 0; v < nv; ++v) {
                     double st[5];
                     for (int o = 0; o < 5; ++o) st[o] = w7[cc + o][v];
-                    reconstruct(g, st, &lft[cc][v], &rgt[cc][v]);
+                    reconstruct_at(g, d, pos[d] - 1 + cc, st, &lft[cc][v], &rgt[cc][v]);
                 }
             double Fm[NVMAX], Fp[NVMAX], um, up;
             hllc(g, rgt[0], lft[1], d, Fm, &um);
             hllc(g, rgt[1], lft[2], d, Fp, &up);
-            for (int v = 0; v < nv; ++v) r[v] += (Fm[v] - Fp[v]) / g->dx[d];
-            for (int v = ia0; v < nv; ++v) r[v] += w7[3][v] * ((up - um) / g->dx[d]);
+            const double h = cell_width(g, d, pos[d]);
+            for (int v = 0; v < nv; ++v) r[v] += (Fm[v] - Fp[v]) / h;
+            for (int v = ia0; v < nv; ++v) r[v] += w7[3][v] * ((up - um) / h);
         }
         for (int v = 0; v < nv; ++v) out[c * nv + v] = r[v];
     }
@@ -900,13 +1083,14 @@ double orc_cfl_dt(const orc_grid* g, const double* q)
     double smax = 0.0;
 #pragma omp parallel for reduction(max : smax) schedule(static)
     for (int64_t c = 0; c < N; ++c) {
+        const int64_t pos[3] = {c % g->n[0], (c / g->n[0]) % g->n[1], c / ((int64_t)g->n[0] * g->n[1])};
         double qc[NVMAX], wc[NVMAX];
         for (int v = 0; v < nvar(g); ++v) qc[v] = q[v * N + c];
         cons_to_prim(g, qc, wc);
         double cs = sound_speed(g, wc);
         double s = 0.0;
         for (int d = 0; d < 3; ++d)
-            if (active(g, d)) s = s + (fabs(wc[imom(g) + d]) + cs) / g->dx[d];
+            if (active(g, d)) s = s + (fabs(wc[imom(g) + d]) + cs) / cell_width(g, d, pos[d]);
         if (s > smax) smax = s;
     }
     return g->cfl / smax;

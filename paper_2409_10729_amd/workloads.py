@@ -438,3 +438,27 @@ def droplet_bubble(n=256, seed=0, mach=2.0, radius=0.15, bubble=0.08, noise=0.01
         w[i] *= f
     return {"name": "droplet_bubble", "spec": s, "w": w,
             "meta": {"centre": c.tolist(), "bubble_centre": cb.tolist(), "shock_x": xs}}
+
+
+def tanh_faces(n, centre=0.5, depth=0.5, sharpness=8.0, lo=0.0, hi=1.0):
+    """Face coordinates (n + 1) of a structured direction refined locally by a
+    hyperbolic tangent: the map x(s) = s - (depth / sharpness) tanh(sharpness
+    (s - centre)) of the uniform coordinate s in [0, 1], rescaled onto
+    [lo, hi], has dx/ds = 1 - depth sech^2(sharpness (s - centre)), so cells
+    near `centre` are finer by up to the factor 1 - depth (0 <= depth < 1)
+    and the widths vary smoothly.  depth = 0 gives uniform cells."""
+    if not 0.0 <= depth < 1.0:
+        raise ValueError("depth must lie in [0, 1)")
+    s = np.arange(n + 1) / n
+    x = s - (depth / sharpness) * np.tanh(sharpness * (s - centre))
+    x = (x - x[0]) / (x[-1] - x[0])
+    out = lo + (hi - lo) * x
+    out[0], out[-1] = lo, hi
+    return out
+
+
+def stretched(P, faces):
+    """The problem P on a non-uniform grid: spec["faces"] = faces (per
+    direction an array of n + 1 face coordinates, or None for uniform
+    cells); the field values are kept cell by cell."""
+    return dict(P, spec=dict(P["spec"], faces=tuple(faces)))
