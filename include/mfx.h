@@ -131,6 +131,16 @@ typedef struct {
                            rules stay linear in every fraction and every fraction carries its
                            alpha_i div(u) source.  More than two fluids: Jiang-Shu or WENO-Z
                            weights (the learned weights are for two), marching x sweep */
+    const double* faces[3]; /* unequal cell widths along a direction (Sec. III-A: a structured mesh
+                           refined locally, e.g. by hyperbolic-tangent stretching): a HOST pointer
+                           to the n[d] + 1 face coordinates of direction d, finite and strictly
+                           increasing, or NULL for uniform cells of width dx[d] (dx[d] is then
+                           ignored).  Read only by mfx_workspace_bytes and mfx_init_grid, which
+                           derive per-cell WENO5 coefficient tables from the widths (the caller may
+                           free the array afterwards); the direction must be active (n[d] > 1) and
+                           the reconstruction WENO5 with Jiang-Shu weights (weno_order 5,
+                           MFX_WENO5_JS).  A ghost cell takes the width of the cell whose state the
+                           boundary rule gives it.  mfx_rhs_static takes uniform grids only */
 } mfx_grid_desc;
 
 typedef struct mfx_ctx mfx_ctx;
@@ -333,7 +343,8 @@ int mfx_profile_read(mfx_ctx* ctx, double* ms, int64_t* counts);
  * and 4 for MFX_FP32_MIXED, nv = 2 num_fluids + 3 (two fluids: up to about
  * 2.3 million cells in float64, e.g. 128^3, and 4.6 million in float32); a
  * larger grid is rejected with MFX_ENOMEM before anything is enqueued.  Jiang-Shu or WENO-Z weights,
- * order 5 or 3 (learned weights need a context: MFX_EINVAL).  q_dev and
+ * order 5 or 3 (learned weights need a context: MFX_EINVAL), uniform cells
+ * (mfx_grid_desc.faces all NULL, else MFX_EINVAL).  q_dev and
  * rhs_dev_out are device pointers on the current device and must not
  * overlap.  Enqueued on hip_stream (hipStream_t as void*, NULL = default
  * stream); asynchronous.  Every call on one GPU uses that GPU's one array,
@@ -343,6 +354,23 @@ int mfx_profile_read(mfx_ctx* ctx, double* ms, int64_t* counts);
  * as codes with the message in mfx_last_error(NULL). */
 #define MFX_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
 int mfx_rhs_static(const mfx_grid_desc* desc, const double* q_dev, double* rhs_dev_out, void* hip_stream);
+
+/* WENO5 coefficients on cells of unequal widths (Sec. III-A local mesh
+ * refinement; Sec. II-B's WENO5 on the refined mesh), as the library derives
+ * them for every stencil position of a direction given by
+ * mfx_grid_desc.faces.  h: the widths of the five cells c-2 .. c+2 (host
+ * array, finite and > 0).  out (host array of MFX_NU_COEFS doubles):
+ *   out[ 0.. 8] a[k][i], out[ 9..17] b[k][i], out[18..26] c[k][i]: candidate
+ *     k (cells c-2+k .. c+k) is A_k + B_k xi + C_k xi^2 in the middle cell's
+ *     coordinate xi = (x - x_c) / h_c, with A_k = sum_i a[k][i] v_{c-2+k+i}
+ *     (likewise B, C) for cell averages v;
+ *   out[27..29] ideal weights of the right edge (xi = 1/2), out[30..32]
+ *     those of the left edge (xi = -1/2).
+ * Smoothness indicator beta_k = B_k^2 + 13/3 C_k^2.  Host-only (touches no
+ * device); MFX_EINVAL for a NULL pointer or a width that is not finite and
+ * positive. */
+#define MFX_NU_COEFS 33
+int mfx_weno5_nu_coefficients(const double* h, double* out);
 
 /* Release the host-side context (the workspace stays the caller's). */
 void mfx_destroy(mfx_ctx* ctx);

@@ -18,12 +18,28 @@ from ._native import (MFX_BC_INFLOW, MFX_BC_PERIODIC, MFX_BC_REFLECTIVE, MFX_BC_
 __all__ = ["Solver", "MfxError", "MFX_FP64", "MFX_FP32_MIXED", "MFX_WENO5_JS", "MFX_WENO5_LEARNED",
            "MFX_WENO5_LEARNED_EDGE", "MFX_WENO5_Z",
            "MFX_BC_PERIODIC", "MFX_BC_TRANSMISSIVE", "MFX_BC_REFLECTIVE", "MFX_BC_INFLOW",
-           "workspace_bytes", "inflow_states", "rhs_static"]
+           "workspace_bytes", "inflow_states", "rhs_static", "weno5_nu_coefficients"]
 
 
 def workspace_bytes(spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS) -> int:
     d = _native.make_desc(spec, precision, weights)
     return int(_native.lib().mfx_workspace_bytes(ctypes.byref(d)))
+
+
+def weno5_nu_coefficients(h) -> "np.ndarray":
+    """mfx_weno5_nu_coefficients: the 33 WENO5 coefficients the library
+    derives for a stencil position from the widths h[0..4] of its five cells
+    (candidate coefficients a, b, c as [3][3] each, then the right- and
+    left-edge ideal weights).  Host-only."""
+    import numpy as np
+
+    h = np.ascontiguousarray(h, dtype=np.float64)
+    if h.shape != (5,):
+        raise ValueError("h must hold five widths")
+    out = np.empty(_native.NU_COEFS)
+    _native.check(_native.lib().mfx_weno5_nu_coefficients(ctypes.c_void_p(h.ctypes.data),
+                                                          ctypes.c_void_p(out.ctypes.data)))
+    return out
 
 
 def inflow_states(spec: dict, prim) -> "np.ndarray":
@@ -80,8 +96,9 @@ class Solver:
     """One mfx context on the current CUDA(HIP) device.
 
     ``spec`` is a problem description (n, dx, bc, gamma, pinf, eps, cfl, and
-    optionally weno_order 5 or 3, and inflow: the conserved ghost state
-    [3][2][7] of MFX_BC_INFLOW sides) as produced by
+    optionally weno_order 5 or 3, inflow: the conserved ghost state
+    [3][2][7] of MFX_BC_INFLOW sides, and faces: per direction the n + 1
+    face coordinates of unequal cells, or None) as produced by
     :mod:`paper_2409_10729_amd.workloads`.  bc per direction and side:
     MFX_BC_PERIODIC, MFX_BC_TRANSMISSIVE, MFX_BC_REFLECTIVE or MFX_BC_INFLOW.
     Arrays passed in and out are torch tensors on the device, float64,

@@ -25,8 +25,9 @@ EXPORTED = (
     "mfx_destroy", "mfx_last_error", "mfx_mlp_sample_stencils", "mfx_mlp_face_targets", "mfx_mlp_features", "mfx_mlp_features_edge",
     "mfx_mlp_packed_bytes",
     "mfx_mlp_pack", "mfx_mlp_forward", "mfx_mlp_grad_workspace", "mfx_mlp_loss_grad", "mfx_mlp_adam",
-    "mfx_mlp_last_error", "mfx_rhs_static",
+    "mfx_mlp_last_error", "mfx_rhs_static", "mfx_weno5_nu_coefficients",
 )
+NU_COEFS = 33
 STATIC_SCRATCH_BYTES = 128 << 20
 MLP_PARAMS = 1347
 MAX_FLUIDS = 3
@@ -54,6 +55,7 @@ class GridDesc(ctypes.Structure):
         ("weno_order", ctypes.c_int32),
         ("inflow", ((ctypes.c_double * MAX_VARS) * 2) * 3),
         ("num_fluids", ctypes.c_int32),
+        ("faces", ctypes.c_void_p * 3),
     ]
 
 
@@ -121,6 +123,8 @@ def lib():
         L.mfx_mlp_last_error.restype = ctypes.c_char_p
         L.mfx_rhs_static.argtypes = [dp, vp, vp, vp]
         L.mfx_rhs_static.restype = ctypes.c_int
+        L.mfx_weno5_nu_coefficients.argtypes = [vp, vp]
+        L.mfx_weno5_nu_coefficients.restype = ctypes.c_int
         L.mfx_destroy.argtypes = [vp]
         L.mfx_destroy.restype = None
         L.mfx_last_error.argtypes = [vp]
@@ -148,6 +152,19 @@ def make_desc(spec: dict, precision: int = MFX_FP64, weights: int = MFX_WENO5_JS
     d.precision = int(precision)
     d.weights = int(weights)
     d.weno_order = int(spec.get("weno_order", 5))
+    faces = spec.get("faces")
+    d._faces = []  # host face arrays, alive as long as the descriptor (read at workspace sizing and init)
+    if faces is not None:
+        import numpy as np
+
+        for k in range(3):
+            if faces[k] is None:
+                continue
+            xf = np.ascontiguousarray(faces[k], dtype=np.float64)
+            if xf.shape != (d.n[k] + 1,):
+                raise ValueError(f"faces[{k}] must hold n[{k}] + 1 coordinates")
+            d._faces.append(xf)
+            d.faces[k] = xf.ctypes.data
     if "inflow" in spec:
         nv = 2 * len(gam) + 3
         a = [[list(map(float, side)) for side in pair] for pair in spec["inflow"]]

@@ -428,6 +428,7 @@ int mfx_mlp_sample_stencils(const mfx_grid_desc* desc, const double* q_dev, cons
     if (desc->num_fluids != 0 && desc->num_fluids != 2) return err(MFX_EINVAL, "the learned weights are for two fluids");
     if (desc->bc[0][0] >= MFX_BC_REFLECTIVE || desc->bc[0][1] >= MFX_BC_REFLECTIVE)
         return err(MFX_EINVAL, "sampling takes periodic or transmissive ends");
+    if (desc->faces[0] || desc->faces[1] || desc->faces[2]) return err(MFX_EINVAL, "sampling takes uniform cells");
     Grid g{};
     g.n[0] = desc->n[0];
     g.n[1] = g.n[2] = 1;
@@ -452,6 +453,8 @@ int mfx_mlp_face_targets(const mfx_grid_desc* fine_desc, const double* q_fine_de
     if (refine < 1 || fine_desc->n[0] % refine != 0) return err(MFX_EINVAL, "refine must divide nx of the fine grid");
     if (fine_desc->bc[0][0] >= MFX_BC_REFLECTIVE || fine_desc->bc[0][1] >= MFX_BC_REFLECTIVE)
         return err(MFX_EINVAL, "face targets take periodic or transmissive ends");
+    if (fine_desc->faces[0] || fine_desc->faces[1] || fine_desc->faces[2])
+        return err(MFX_EINVAL, "face targets take uniform cells");
     Grid g{};
     g.n[0] = fine_desc->n[0];
     g.n[1] = g.n[2] = 1;

@@ -61,7 +61,7 @@ Overrides read_overrides()
 }
 
 struct Layout {
-    size_t q, q1, q2, r, scal, inflow, partial, bface, mlp, mlp_params, total;
+    size_t q, q1, q2, r, scal, inflow, partial, bface, mlp, mlp_params, nu[3], total;
     long long n_partial;
 };
 
@@ -85,11 +85,12 @@ bool use_xrows(const int n[3], int mode_override, size_t elem)
 }
 
 // x sweep mode for a descriptor: the override, or the march (1) when an x
-// side is inflow and the row buffers would be aliased, or for more than two
-// fluids.
+// side is inflow and the row buffers would be aliased, for more than two
+// fluids, or for unequal cells along x.
 int x_mode(const mfx_grid_desc* d, int xmode_override)
 {
     if (fluids_of(d) != 2) return 1;  // the row kernels are written for two fluids
+    if (d->faces[0]) return 1;        // unequal cells along x: the marching pass reads per-position tables
     const size_t elem = d->precision == MFX_FP32_MIXED ? sizeof(float) : sizeof(double);
     const bool inflow_x = d->bc[0][0] == MFX_BC_INFLOW || d->bc[0][1] == MFX_BC_INFLOW;
     if (inflow_x && d->n[0] <= XROW_MAX && xrow_layout(d->n[0], elem).alias) return 1;
@@ -169,6 +170,10 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     off += align_up(sizeof(MlpLane) * 64);
     L.mlp_params = off;
     off += align_up(sizeof(float) * MLP_PARAMS);
+    for (int k = 0; k < 3; ++k) {  // per-position tables of directions with unequal cells
+        L.nu[k] = off;
+        if (d->faces[k]) off += align_up(sizeof(double) * NU_K * ((size_t)d->n[k] + 2));
+    }
     L.total = off;
     L.n_partial = np;
     return L;
@@ -186,15 +191,145 @@ int scheme_of(const mfx_grid_desc& d)
     return d.weno_order == 3 ? SCHEME_WENO3 : SCHEME_WENO5;
 }
 
-// Calls f with std::integral_constant<int, scheme> (one instantiation per scheme).
-template <class F>
+// Calls f with std::integral_constant<int, scheme> (one instantiation per
+// scheme; NU: whether the unequal-cell scheme is one of them).
+template <bool NU = true, class F>
 void by_scheme(int scheme, F&& f)
 {
     switch (scheme) {
     case SCHEME_WENO3: f(std::integral_constant<int, SCHEME_WENO3>{}); break;
     case SCHEME_WENO5Z: f(std::integral_constant<int, SCHEME_WENO5Z>{}); break;
+    case SCHEME_WENO5NU:
+        if constexpr (NU) {
+            f(std::integral_constant<int, SCHEME_WENO5NU>{});
+            break;
+        }
+        [[fallthrough]];
     default: f(std::integral_constant<int, SCHEME_WENO5>{}); break;
     }
+}
+
+// ---------------------------------------------------------------- unequal cells
+//
+// WENO5 coefficients on cells of unequal widths by the primitive-function
+// route (Shu's construction of reconstructions on non-uniform meshes): on the
+// boundaries z_0 < ... < z_m of m consecutive cells, in the coordinate xi of
+// the middle cell of the five (which spans [-1/2, 1/2]), the primitive
+// V(z_j) = sum_{i<j} v_i (z_{i+1} - z_i) is interpolated by the Lagrange
+// polynomial P of degree m, and P' is the polynomial of degree m - 1 whose
+// cell averages are the v_i.  So the coefficient of v_i in any linear
+// functional of P' is (z_{i+1} - z_i) times the sum over the nodes j > i of
+// that functional applied to the derivative of node j's basis polynomial.
+
+// Derivative of the Lagrange basis polynomial of node j (nodes z[0..m]) at node z[s].
+double basis_slope_at_node(const double* z, int m, int j, int s)
+{
+    if (j == s) {
+        double acc = 0.0;
+        for (int q = 0; q <= m; ++q)
+            if (q != s) acc += 1.0 / (z[s] - z[q]);
+        return acc;
+    }
+    double num = 1.0, den = 1.0;
+    for (int q = 0; q <= m; ++q) {
+        if (q == j) continue;
+        den *= z[j] - z[q];
+        if (q != s) num *= z[s] - z[q];
+    }
+    return num / den;
+}
+
+static_assert(NU_DL + 3 == MFX_NU_COEFS, "table layout starts with the exported coefficients");
+
+// The MFX_NU_COEFS values of mfx_weno5_nu_coefficients for widths h[0..4].
+void nu_coefficients(const double h[5], double* out)
+{
+    double z[6];
+    z[2] = -0.5;
+    z[3] = 0.5;
+    z[1] = z[2] - h[1] / h[2];
+    z[0] = z[1] - h[0] / h[2];
+    z[4] = z[3] + h[3] / h[2];
+    z[5] = z[4] + h[4] / h[2];
+    double w[5];
+    for (int i = 0; i < 5; ++i) w[i] = z[i + 1] - z[i];
+    // candidate k, nodes z[k .. k+3]: A = P'(0), B = P''(0), C = P'''(0) / 2.
+    // With node j's basis numerator prod_{q != j} (xi - z_q) = xi^3 - e1 xi^2
+    // + e2 xi - e3 and denominator D = prod_{q != j} (z_j - z_q), its first,
+    // second and third derivatives at 0 are e2 / D, -2 e1 / D and 6 / D.
+    for (int k = 0; k < 3; ++k) {
+        const double* zz = z + k;
+        double fa[4] = {0.0, 0.0, 0.0, 0.0}, fb[4] = {0.0, 0.0, 0.0, 0.0}, fc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int j = 1; j < 4; ++j) {
+            double o[3], D = 1.0;
+            int no = 0;
+            for (int q = 0; q < 4; ++q) {
+                if (q == j) continue;
+                D *= zz[j] - zz[q];
+                o[no++] = zz[q];
+            }
+            const double e1 = o[0] + o[1] + o[2];
+            const double e2 = o[0] * o[1] + o[0] * o[2] + o[1] * o[2];
+            fa[j] = e2 / D;
+            fb[j] = -2.0 * e1 / D;
+            fc[j] = 3.0 / D;
+        }
+        for (int i = 0; i < 3; ++i) {
+            double sa = 0.0, sb = 0.0, sc = 0.0;
+            for (int j = i + 1; j < 4; ++j) {
+                sa += fa[j];
+                sb += fb[j];
+                sc += fc[j];
+            }
+            out[NU_A + 3 * k + i] = w[k + i] * sa;
+            out[NU_B + 3 * k + i] = w[k + i] * sb;
+            out[NU_C + 3 * k + i] = w[k + i] * sc;
+        }
+    }
+    // Ideal weights of an edge (node s of the five cells' boundaries: 3 for
+    // xi = 1/2, 2 for xi = -1/2): the five-cell value there is matched by
+    // the three candidates' values; only candidate 0 holds cell c-2 and only
+    // candidate 2 holds cell c+2, which fixes d_0 and d_2, and the weights
+    // sum to one (every row reproduces constants).
+    for (int e = 0; e < 2; ++e) {
+        const int s = e == 0 ? 3 : 2;
+        double g0 = 0.0;
+        for (int j = 1; j <= 5; ++j) g0 += basis_slope_at_node(z, 5, j, s);
+        g0 *= w[0];
+        const double g4 = w[4] * basis_slope_at_node(z, 5, 5, s);
+        double r0 = 0.0;
+        for (int j = 1; j <= 3; ++j) r0 += basis_slope_at_node(z, 3, j, s);
+        r0 *= w[0];
+        const double r2 = w[4] * basis_slope_at_node(z + 2, 3, 3, s - 2);
+        double* d = out + (e == 0 ? NU_DR : NU_DL);
+        d[0] = g0 / r0;
+        d[2] = g4 / r2;
+        d[1] = 1.0 - d[0] - d[2];
+    }
+}
+
+// Table of direction dir (NU_K values per stencil position -1 .. n): the
+// widths of the five cells each position's stencil reaches, a ghost cell
+// taking the width of the cell the boundary rule maps it to.
+std::vector<double> nu_table(const mfx_grid_desc* d, int dir)
+{
+    const int n = d->n[dir];
+    const double* xf = d->faces[dir];
+    const int blo = d->bc[dir][0], bhi = d->bc[dir][1];
+    auto width = [&](int i) {
+        const int j = map_cell(i, n, blo, bhi);
+        return xf[j + 1] - xf[j];
+    };
+    std::vector<double> t((size_t)NU_K * (n + 2), 0.0);
+    for (int c = -1; c <= n; ++c) {
+        double h[5];
+        for (int o = 0; o < 5; ++o) h[o] = width(c - 2 + o);
+        double* row = t.data() + (size_t)(c + 1) * NU_K;
+        nu_coefficients(h, row);
+        row[NU_H] = width(c);
+        row[NU_IH] = 1.0 / row[NU_H];
+    }
+    return t;
 }
 
 bool validate(const mfx_grid_desc* d, std::string& why)
@@ -303,6 +438,25 @@ bool validate(const mfx_grid_desc* d, std::string& why)
         why = "the learned weights are defined for two fluids";
         return false;
     }
+    for (int k = 0; k < 3; ++k) {
+        const double* xf = d->faces[k];
+        if (!xf) continue;
+        const std::string nm = "faces[" + std::to_string(k) + "]";
+        if (d->n[k] < 2) {
+            why = nm + " needs an active direction (n > 1)";
+            return false;
+        }
+        if (d->weights != MFX_WENO5_JS || (d->weno_order != 0 && d->weno_order != 5)) {
+            why = "unequal cells take WENO5 with Jiang-Shu weights (weno_order 5, MFX_WENO5_JS)";
+            return false;
+        }
+        for (int i = 0; i <= d->n[k]; ++i) {
+            if (!std::isfinite(xf[i]) || (i > 0 && !(xf[i] > xf[i - 1]))) {
+                why = nm + " must hold n + 1 finite, strictly increasing face coordinates";
+                return false;
+            }
+        }
+    }
     return true;
 }
 
@@ -367,7 +521,15 @@ __global__ void __launch_bounds__(UTIL_BLOCK) cfl_partial_kernel(Grid g, const d
         double qc[F::NV];
 #pragma unroll
         for (int v = 0; v < F::NV; ++v) qc[v] = q[v * N + c];
-        smax = fmax(smax, cfl_speed<F>(g, qc, bad));
+        double hw[3];
+        const double* hp = nullptr;
+        if (g.nonuniform) {  // the cell's own widths where a direction has unequal cells
+            const long long pos[3] = {c % g.n[0], (c / g.n[0]) % g.n[1], c / g.stride[2]};
+#pragma unroll
+            for (int d = 0; d < 3; ++d) hw[d] = g.nu[d] ? g.nu[d][(pos[d] + 1) * NU_K + NU_H] : g.dx[d];
+            hp = hw;
+        }
+        smax = fmax(smax, cfl_speed<F>(g, qc, bad, hp));
     }
     if (bad) atomicOr(status, bad);
     block_max_to<UTIL_BLOCK>(smax, partial + blockIdx.x);
@@ -512,7 +674,7 @@ void launch_one(const LaunchArgs& a)
     const SweepGeom& sg = *a.sg;
     T* r = static_cast<T*>(a.r);
     if constexpr (DIR == 0) {
-        if constexpr (F::NF == 2) {
+        if constexpr (F::NF == 2 && SCHEME != SCHEME_WENO5NU) {
             if (sg.xrows) {
                 T* bf = static_cast<T*>(a.bface);
                 const long long rows = (long long)a.g->n[1] * a.g->n[2];
@@ -577,16 +739,18 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
     const LaunchArgs la{&sg,      c->stream,   &c->g,      qs,        qn,       c->r,
                         out,      dt_dev,      dt_arg,     c->bface,  c->mlp,   c->fallback,
                         c->partial, c->status, cfl};
+    // a direction with unequal cells takes the per-position scheme
+    const int sch = c->g.nu[d] ? SCHEME_WENO5NU : scheme_of(c->desc);
     if (learned_weights(c->desc))
         launch_dispatch<float, true>(d, first != 0, mode, la);
     else if (c->g.nf == 3 && c->desc.precision == MFX_FP32_MIXED)
-        by_scheme(scheme_of(c->desc), [&](auto s) { launch_dispatch<float, false, decltype(s)::value, Fl<3>>(d, first != 0, mode, la); });
+        by_scheme(sch, [&](auto s) { launch_dispatch<float, false, decltype(s)::value, Fl<3>>(d, first != 0, mode, la); });
     else if (c->g.nf == 3)
-        by_scheme(scheme_of(c->desc), [&](auto s) { launch_dispatch<double, false, decltype(s)::value, Fl<3>>(d, first != 0, mode, la); });
+        by_scheme(sch, [&](auto s) { launch_dispatch<double, false, decltype(s)::value, Fl<3>>(d, first != 0, mode, la); });
     else if (c->desc.precision == MFX_FP32_MIXED)
-        by_scheme(scheme_of(c->desc), [&](auto s) { launch_dispatch<float, false, decltype(s)::value>(d, first != 0, mode, la); });
+        by_scheme(sch, [&](auto s) { launch_dispatch<float, false, decltype(s)::value>(d, first != 0, mode, la); });
     else
-        by_scheme(scheme_of(c->desc), [&](auto s) { launch_dispatch<double, false, decltype(s)::value>(d, first != 0, mode, la); });
+        by_scheme(sch, [&](auto s) { launch_dispatch<double, false, decltype(s)::value>(d, first != 0, mode, la); });
     int rc = launch_check(c, "sweep kernel");
     if (rc) return rc;
     if (c->profiling) {
@@ -597,11 +761,12 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
 }
 
 // The fused x-y pass applies when x and y are the first two active
-// directions, x rows fit the row kernel and the weights are Jiang-Shu.
+// directions, x rows fit the row kernel, the weights are Jiang-Shu and the
+// cells are equal along x and y.
 bool fused_xy(const mfx_ctx* c)
 {
     return c->fuse_xy && !learned_weights(c->desc) && c->g.nf == 2 && c->ndirs >= 2 && c->dirs[0] == 0 && c->dirs[1] == 1 &&
-           use_xrows(c->g.n, c->xmode_override, c->elem);
+           !c->g.nu[0] && !c->g.nu[1] && use_xrows(c->g.n, c->xmode_override, c->elem);
 }
 
 template <typename T, int MODE, int SCHEME>
@@ -648,9 +813,9 @@ int launch_sweep_xy(mfx_ctx* c, const double* qs, const double* qn, double* out,
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
     if (c->desc.precision == MFX_FP32_MIXED)
-        by_scheme(scheme_of(c->desc), [&](auto s) { launch_xy<float, decltype(s)::value>(c, mode, qs, qn, out, dt_dev, dt_arg); });
+        by_scheme<false>(scheme_of(c->desc), [&](auto s) { launch_xy<float, decltype(s)::value>(c, mode, qs, qn, out, dt_dev, dt_arg); });
     else
-        by_scheme(scheme_of(c->desc), [&](auto s) { launch_xy<double, decltype(s)::value>(c, mode, qs, qn, out, dt_dev, dt_arg); });
+        by_scheme<false>(scheme_of(c->desc), [&](auto s) { launch_xy<double, decltype(s)::value>(c, mode, qs, qn, out, dt_dev, dt_arg); });
     int rc = launch_check(c, "fused x-y sweep");
     if (rc) return rc;
     if (c->profiling) {
@@ -665,7 +830,8 @@ int launch_sweep_xy(mfx_ctx* c, const double* qs, const double* qn, double* out,
 // output; 0 when the standalone reduction is needed.
 long long cfl_blocks_in_last_pass(const mfx_ctx* c)
 {
-    if (!c->fuse_cfl || learned_weights(c->desc)) return 0;
+    // (unequal cells: the standalone reduction reads each cell's widths)
+    if (!c->fuse_cfl || learned_weights(c->desc) || c->g.nonuniform) return 0;
     const int d = c->dirs[c->ndirs - 1];
     if (d == 0 || !c->g.active[d]) return 0;
     if (fused_xy(c) && c->ndirs == 2) return 0;  // the fused x-y pass is the last
@@ -751,6 +917,8 @@ void setup_grid(const mfx_grid_desc* desc, mfx_ctx* c, const double* inflow_dev)
         if (g.active[k]) c->dirs[c->ndirs++] = k;
     }
     g.inflow_dev = inflow_dev;
+    for (int k = 0; k < 3; ++k) g.nu[k] = nullptr;  // mfx_init_grid binds the tables of unequal cells
+    g.nonuniform = 0;
     if (c->ndirs == 0) c->dirs[c->ndirs++] = 0;  // a single cell still sweeps x (all faces from ghosts)
     g.G1 = 1.0 / (desc->gamma[0] - 1.0);
     g.G2 = 1.0 / (desc->gamma[1] - 1.0);
@@ -839,11 +1007,29 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     // the inflow states for the loaders (zero for other sides); the source
     // lives in the context
     if (hipMemcpyAsync(c->ws + L.inflow, &c->g.inflow[0][0][0], sizeof(double) * 3 * 2 * NVMAX, hipMemcpyHostToDevice,
-                       c->stream) != hipSuccess ||
-        hipStreamSynchronize(c->stream) != hipSuccess) {
+                       c->stream) != hipSuccess) {
         delete c;
         return fail(nullptr, MFX_EHIP, "copy of the inflow states failed");
     }
+    // per-position tables of directions with unequal cells (host copies
+    // kept until the stream has taken them)
+    std::vector<double> tabs[3];
+    for (int k = 0; k < 3; ++k) {
+        if (!desc->faces[k]) continue;
+        tabs[k] = nu_table(desc, k);
+        if (hipMemcpyAsync(c->ws + L.nu[k], tabs[k].data(), sizeof(double) * tabs[k].size(), hipMemcpyHostToDevice,
+                           c->stream) != hipSuccess) {
+            delete c;
+            return fail(nullptr, MFX_EHIP, "copy of the unequal-cell tables failed");
+        }
+        c->g.nu[k] = reinterpret_cast<const double*>(c->ws + L.nu[k]);
+        c->g.nonuniform = 1;
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        delete c;
+        return fail(nullptr, MFX_EHIP, "hipStreamSynchronize after the table copies failed");
+    }
+    for (int k = 0; k < 3; ++k) c->desc.faces[k] = nullptr;  // read here only; the caller may free them
     c->has_state = false;
     c->profiling = false;
     for (int k = 0; k < MFX_PROF_KINDS; ++k) {
@@ -851,6 +1037,17 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
         c->prof_n[k] = 0;
     }
     *out = c;
+    return MFX_OK;
+}
+
+int mfx_weno5_nu_coefficients(const double* h, double* out)
+{
+    if (!h || !out) return fail(nullptr, MFX_EINVAL, "h and out must not be NULL");
+    for (int i = 0; i < 5; ++i)
+        if (!(h[i] > 0.0) || !std::isfinite(h[i])) return fail(nullptr, MFX_EINVAL, "widths must be finite and > 0");
+    double t[NU_K];
+    nu_coefficients(h, t);
+    for (int i = 0; i < MFX_NU_COEFS; ++i) out[i] = t[i];
     return MFX_OK;
 }
 
@@ -1140,6 +1337,8 @@ extern "C" int mfx_rhs_static(const mfx_grid_desc* desc, const double* q_dev, do
     if (!validate(desc, why)) return static_fail(MFX_EINVAL, why);
     if (learned_weights(*desc))
         return static_fail(MFX_EINVAL, "mfx_rhs_static takes Jiang-Shu or WENO-Z weights (a network needs a context)");
+    if (desc->faces[0] || desc->faces[1] || desc->faces[2])
+        return static_fail(MFX_EINVAL, "mfx_rhs_static takes uniform cells (faces all NULL): unequal cells need a context");
     if (!q_dev || !rhs_dev_out) return static_fail(MFX_EINVAL, "q_dev and rhs_dev_out must not be NULL");
     const size_t N = (size_t)desc->n[0] * desc->n[1] * desc->n[2];
     const size_t bytes = sizeof(double) * vars_of(desc) * N;

@@ -325,6 +325,59 @@ __device__ __forceinline__ void weno3<float>(float a, float b, float c, float ep
     weno3_ratio(a, b, c, eps, left, right);
 }
 
+// WENO5 with Jiang-Shu weights on cells of unequal widths (a direction of the
+// structured mesh refined locally by a hyperbolic tangent, Sec. III-A), for
+// cell c from w_{c-2..c+2} = v[0..4].  In the cell's own coordinate
+// xi = (x - x_c) / h_c (the cell spans [-1/2, 1/2]) candidate k (cells
+// c-2+k .. c+k) is the quadratic A_k + B_k xi + C_k xi^2 whose averages over
+// its three cells are their values; A, B, C are linear in those values, with
+// coefficients that depend only on the widths (NuCoef, one set per stencil
+// position, computed on the host).  Indicator beta_k = B_k^2 + 13/3 C_k^2
+// (h_c times the integral of p'^2 plus h_c^3 times that of p''^2 over the
+// cell); the ideal weights of each edge (dr at xi = 1/2, dl at xi = -1/2)
+// combine the three candidates into the quartic through all five averages.
+// On equal widths this is weno5_js up to rounding.
+template <typename T>
+struct NuCoef {
+    T a[3][3], b[3][3], c[3][3];  // [candidate][value of cell c-2+k+i]
+    T dr[3], dl[3];
+};
+
+// float64: the weights scaled by the product of the three (eps + beta)^2 as
+// in weno5_js; float32: the ratio form of weno5_js_ratio.
+template <typename T>
+__device__ __forceinline__ void weno5_nu(const NuCoef<T>& K, const T v[5], T eps, T& left, T& right)
+{
+    T pr[3], pl[3], s[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const T A = K.a[k][0] * v[k] + K.a[k][1] * v[k + 1] + K.a[k][2] * v[k + 2];
+        const T B = K.b[k][0] * v[k] + K.b[k][1] * v[k + 1] + K.b[k][2] * v[k + 2];
+        const T C = K.c[k][0] * v[k] + K.c[k][1] * v[k + 1] + K.c[k][2] * v[k + 2];
+        s[k] = eps + (B * B + T(13.0 / 3.0) * (C * C));
+        pr[k] = A + T(0.5) * B + T(0.25) * C;
+        pl[k] = A - T(0.5) * B + T(0.25) * C;
+    }
+    T t[3];
+    if constexpr (sizeof(T) == sizeof(double)) {
+        const T s0 = s[0] * s[0], s1 = s[1] * s[1], s2 = s[2] * s[2];
+        t[0] = s1 * s2;
+        t[1] = s0 * s2;
+        t[2] = s0 * s1;
+    } else {
+        const T m = fminf(s[0], fminf(s[1], s[2]));
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const T x = qdiv(m, s[k]);
+            t[k] = x * x;
+        }
+    }
+    const T wr0 = K.dr[0] * t[0], wr1 = K.dr[1] * t[1], wr2 = K.dr[2] * t[2];
+    const T wl0 = K.dl[0] * t[0], wl1 = K.dl[1] * t[1], wl2 = K.dl[2] * t[2];
+    right = qdiv(wr0 * pr[0] + wr1 * pr[1] + wr2 * pr[2], wr0 + wr1 + wr2);
+    left = qdiv(wl0 * pl[0] + wl1 * pl[1] + wl2 * pl[2], wl0 + wl1 + wl2);
+}
+
 // FP64 HLLC in the plain definition's operation order, without contraction
 // and with IEEE division and square root.  The star-state flux
 // F = F_K + s (U*_K - U_K) subtracts energies of size Pi (7.8e8 in water)

@@ -57,6 +57,24 @@ struct Grid {
     int edge_weights;  // learned weights: one network evaluation per edge for all variables
     double inflow[3][2][NVMAX];  // conserved state of the ghost cells of an inflow side
     const double* inflow_dev;    // the same states in device memory, [3][2][NVMAX]
+    const double* nu[3];         // per-position tables of a non-uniform direction (NU_* below), else null
+    int nonuniform;              // some direction has unequal cell widths
+};
+
+// Table of a direction with unequal cell widths (filled on the host from the
+// face coordinates): the NU_K values of stencil position c (c = -1 .. n:
+// every cell whose edges a face of the direction uses, ghosts included) at
+// nu[(c + 1) * NU_K + k].  One position's values are contiguous, and every
+// lane of a marching sweep reads the same position.
+enum : int {
+    NU_A = 0,    // NuCoef::a[3][3]
+    NU_B = 9,    // NuCoef::b[3][3]
+    NU_C = 18,   // NuCoef::c[3][3]
+    NU_DR = 27,  // ideal weights of the right edge
+    NU_DL = 30,  // ideal weights of the left edge
+    NU_H = 33,   // the cell's width (CFL reduction)
+    NU_IH = 34,  // its reciprocal (flux difference)
+    NU_K = 36,   // values per position (padded to 32-byte rows)
 };
 
 // Mixture constants of the model F from the grid, in the type T.
@@ -86,7 +104,7 @@ __device__ __forceinline__ auto make_mix(const Grid& g)
 // copy instead, and the map's edge cell is only a placeholder.
 // Positions further out (the marching x sweep stages whole chunks, up to
 // n+5) are clamped into the row; no stencil uses them.
-__device__ __forceinline__ int map_cell(int c, int n, int bclo, int bchi)
+__host__ __device__ __forceinline__ int map_cell(int c, int n, int bclo, int bchi)
 {
     if (c < 0) return bclo == BC_PERIODIC ? ((c % n) + n) % n : (bclo == BC_REFLECTIVE ? min(-1 - c, n - 1) : 0);
     if (c >= n) return bchi == BC_PERIODIC ? c % n : (bchi == BC_REFLECTIVE ? max(2 * n - 1 - c, 0) : n - 1);
@@ -147,8 +165,10 @@ __device__ __forceinline__ bool alpha_out(const double* q)
     }
 }
 
+// hw: the cell's widths per direction where they differ from g.dx (unequal
+// cells), else null.
 template <class F = Fl2>
-__device__ __forceinline__ double cfl_speed(const Grid& g, const double* q, unsigned& bad)
+__device__ __forceinline__ double cfl_speed(const Grid& g, const double* q, unsigned& bad, const double* hw = nullptr)
 {
 #pragma clang fp contract(off)
     double c2, u, v, w, rho;
@@ -175,7 +195,7 @@ __device__ __forceinline__ double cfl_speed(const Grid& g, const double* q, unsi
     const double vel[3] = {u, v, w};
 #pragma unroll
     for (int d = 0; d < 3; ++d)
-        if (g.active[d]) s = s + (fabs(vel[d]) + c) / g.dx[d];
+        if (g.active[d]) s = s + (fabs(vel[d]) + c) / (hw ? hw[d] : g.dx[d]);
     if (!(rho > 0.0)) bad |= 1u;
     if (!(c2 > 0.0)) bad |= 2u;
     if (!isfinite(s)) bad |= 4u;
@@ -479,6 +499,7 @@ enum : int {
     SCHEME_WENO3 = 3,   // WENO3, Jiang-Shu weights, on the middle three cells
     SCHEME_WENO5 = 5,   // WENO5, Jiang-Shu weights
     SCHEME_WENO5Z = 6,  // WENO5, WENO-Z weights (comparison form)
+    SCHEME_WENO5NU = 7, // WENO5, Jiang-Shu weights, on unequal cells (marching sweeps only)
 };
 
 // Reconstruction of one cell's two edge states (all seven primitives) from
@@ -509,6 +530,54 @@ struct ReconJS {
     __device__ __forceinline__ void cell(const T W[5][NV], T eps, T lft[NV], T rgt[NV])
     {
         cell_win(ArrayWindow<T>{W}, eps, lft, rgt);
+    }
+    __device__ __forceinline__ void count_edges(bool, bool) {}
+    __device__ __forceinline__ void flush(unsigned long long*) {}
+    // equal cells: no per-position data, one reciprocal width for the direction
+    template <int DIR>
+    __device__ __forceinline__ void bind(const Grid&) {}
+    __device__ __forceinline__ void at(int) {}
+    __device__ __forceinline__ T inv_width(int, T idx) const { return idx; }
+};
+
+// Unequal cells along the sweep: at(c) loads the coefficients of stencil
+// position c from the direction's table (the same position on every lane of
+// a marching sweep, so the loads are uniform), the flux difference of cell c
+// divides by its own width.
+template <typename T>
+struct ReconJS<T, SCHEME_WENO5NU> {
+    const double* tab;
+    NuCoef<T> K;
+    template <int DIR>
+    __device__ __forceinline__ void bind(const Grid& g)
+    {
+        tab = g.nu[DIR];
+    }
+    __device__ __forceinline__ void at(int c)
+    {
+        const double* t = tab + (long long)(c + 1) * NU_K;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                K.a[k][i] = (T)t[NU_A + 3 * k + i];
+                K.b[k][i] = (T)t[NU_B + 3 * k + i];
+                K.c[k][i] = (T)t[NU_C + 3 * k + i];
+            }
+            K.dr[k] = (T)t[NU_DR + k];
+            K.dl[k] = (T)t[NU_DL + k];
+        }
+    }
+    __device__ __forceinline__ T inv_width(int c, T) const { return (T)tab[(long long)(c + 1) * NU_K + NU_IH]; }
+    template <class Win>
+    __device__ __forceinline__ void cell_win(const Win& W, T eps, T* lft, T* rgt)
+    {
+#pragma unroll
+        for (int v = 0; v < Win::nv; ++v) {
+            const T st[5] = {W(0, v), W(1, v), W(2, v), W(3, v), W(4, v)};
+            weno5_nu<T>(K, st, eps, lft[v], rgt[v]);
+            settle(lft[v], rgt[v]);
+        }
     }
     __device__ __forceinline__ void count_edges(bool, bool) {}
     __device__ __forceinline__ void flush(unsigned long long*) {}
@@ -635,6 +704,10 @@ struct ReconLearned {
     {
         cell_win(ArrayWindow<float>{W}, eps, lft, rgt);
     }
+    template <int DIR>
+    __device__ __forceinline__ void bind(const Grid&) {}
+    __device__ __forceinline__ void at(int) {}
+    __device__ __forceinline__ float inv_width(int, float idx) const { return idx; }
     // wave sum of the fallback counts, one atomic per wave
     __device__ __forceinline__ void flush(unsigned long long* counter)
     {
@@ -691,6 +764,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
     const T eps = (T)g.eps;
     const MixOf<F> mixd = make_mix<double, F>(g);
     const auto mix = make_mix<T, F>(g);
+    recon.template bind<DIR>(g);
 
     // window: W(k) = primitives of cell c-2+k while reconstructing cell c
     // qh (when the sink keeps the stage state): conserved cells c-1 .. c+2.
@@ -738,6 +812,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
         T lft[V], rgt[V];
         recon.count_edges((c >= c0 && c < c1) || (c == c0 - 1 && own_first),
                           (c > c0 && c <= c1) || (c == c0 && own_first));
+        recon.at(c);
         recon.cell_win(W, eps, lft, rgt);
 
         if (c >= c0) {
@@ -745,13 +820,14 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
             hllc_f<DIR, T, F>(mix, rprev, lft, Fl, uf);
             if (c > c0) {
                 // cell c-1: faces c-3/2 (Fprev) and c-1/2 (Fl)
+                const T ih = recon.inv_width(c - 1, idx);
                 T fd[V];
 #pragma unroll
-                for (int v = 0; v < V; ++v) fd[v] = (Fprev[v] - Fl[v]) * idx;
+                for (int v = 0; v < V; ++v) fd[v] = (Fprev[v] - Fl[v]) * ih;
                 // every volume fraction's source alpha_a div(u)
                 T src_a[F::NA];
 #pragma unroll
-                for (int a = 0; a < F::NA; ++a) src_a[a] = W(1, F::IA + a) * ((uf - ufprev) * idx);
+                for (int a = 0; a < F::NA; ++a) src_a[a] = W(1, F::IA + a) * ((uf - ufprev) * ih);
                 sink.put(g, c - 1, fd, src_a, W, &qh[0][0]);
             }
 #pragma unroll

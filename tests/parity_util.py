@@ -38,6 +38,15 @@ def rel_linf(x: np.ndarray, y: np.ndarray) -> np.ndarray:
     return np.abs(x - y).max(axis=1) / den
 
 
+def inv_width(spec, d: int) -> float:
+    """Largest 1 / (cell width) along direction d: 1 / dx, or on unequal
+    cells (spec["faces"]) the reciprocal of the narrowest cell."""
+    faces = spec.get("faces")
+    if faces is not None and faces[d] is not None:
+        return 1.0 / np.diff(np.asarray(faces[d], dtype=np.float64)).min()
+    return 1.0 / spec["dx"][d]
+
+
 def physical_flux_scale(q: np.ndarray, spec) -> np.ndarray:
     """Per field, max over cells of sum_d |F_k,d(q)| / dx_d with the model's
     physical flux F alone (the scale the FP64 right-hand-side bar was first
@@ -56,7 +65,7 @@ def physical_flux_scale(q: np.ndarray, spec) -> np.ndarray:
         F = np.abs(qq * ud)
         F[m + d] = np.abs(qq[m + d] * ud + p)
         F[e] = np.abs((qq[e] + p) * ud)
-        tot += F / spec["dx"][d]
+        tot += F * inv_width(spec, d)
     return _shared_momentum(tot.max(axis=1))
 
 
@@ -82,7 +91,7 @@ def flux_scale(q: np.ndarray, spec) -> np.ndarray:
         F = np.abs(qq * ud)
         F[m + d] = np.abs(qq[m + d] * ud + p)
         F[e] = np.abs((qq[e] + p) * ud)
-        tot += F / spec["dx"][d]
+        tot += F * inv_width(spec, d)
     dt = oracle.cfl_dt(g, q)
     lam = spec.get("cfl", 0.4) / dt if np.isfinite(dt) else 0.0
     return _shared_momentum(tot.max(axis=1) + lam * np.abs(qq).max(axis=1))
