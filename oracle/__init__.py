@@ -172,22 +172,32 @@ def _shape(g: OrcGrid):
     return (nvars(g.nf), g.n[2], g.n[1], g.n[0])
 
 
+def _state(g: OrcGrid, a, name: str = "state", copy: bool = False) -> np.ndarray:
+    """a as a C-contiguous float64 array of the grid's state shape
+    [nv, nz, ny, nx]; anything else raises (the C routines index the whole
+    grid and would read or write past a smaller buffer)."""
+    a = np.array(a, dtype=np.float64, order="C", copy=True) if copy else np.ascontiguousarray(a, dtype=np.float64)
+    if a.shape != _shape(g):
+        raise ValueError(f"{name} has shape {a.shape}; the grid's state shape is {_shape(g)}")
+    return a
+
+
 def prim_to_cons(g: OrcGrid, w: np.ndarray) -> np.ndarray:
-    w = np.ascontiguousarray(w, dtype=np.float64)
+    w = _state(g, w, "w")
     q = np.empty_like(w)
     lib().orc_prim_to_cons(ctypes.byref(g), _dp(w), _dp(q))
     return q
 
 
 def cons_to_prim(g: OrcGrid, q: np.ndarray) -> np.ndarray:
-    q = np.ascontiguousarray(q, dtype=np.float64)
+    q = _state(g, q, "q")
     w = np.empty_like(q)
     lib().orc_cons_to_prim(ctypes.byref(g), _dp(q), _dp(w))
     return w
 
 
 def rhs(g: OrcGrid, q: np.ndarray) -> np.ndarray:
-    q = np.ascontiguousarray(q, dtype=np.float64)
+    q = _state(g, q, "q")
     out = np.empty_like(q)
     lib().orc_rhs(ctypes.byref(g), _dp(q), _dp(out))
     return out
@@ -195,8 +205,10 @@ def rhs(g: OrcGrid, q: np.ndarray) -> np.ndarray:
 
 def rhs_at(g: OrcGrid, q: np.ndarray, cells: np.ndarray) -> np.ndarray:
     """RHS at linear cell indices ``cells``; returns [ncell, 7]."""
-    q = np.ascontiguousarray(q, dtype=np.float64)
+    q = _state(g, q, "q")
     cells = np.ascontiguousarray(cells, dtype=np.int64)
+    if cells.size and (cells.min() < 0 or cells.max() >= g.n[0] * g.n[1] * g.n[2]):
+        raise ValueError("cell index outside the grid")
     out = np.empty((cells.size, nvars(g.nf)), dtype=np.float64)
     lib().orc_rhs_at(ctypes.byref(g), _dp(q), cells.size,
                      cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out))
@@ -219,7 +231,7 @@ def rhs_learned(g: OrcGrid, q: np.ndarray, theta, mode: int = LEARNED_PER_VARIAB
         raise ValueError("the learned weights are defined for two fluids")
     if any(g.xf[d] for d in range(3)):
         raise ValueError("the learned weights are defined on uniform cells")
-    q = np.ascontiguousarray(q, dtype=np.float64)
+    q = _state(g, q, "q")
     th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32), dtype=np.float64)
     assert th.size == 1347
     out = np.empty_like(q)
@@ -246,7 +258,7 @@ def gelu(a: float) -> float:
 
 
 def cfl_dt(g: OrcGrid, q: np.ndarray) -> float:
-    q = np.ascontiguousarray(q, dtype=np.float64)
+    q = _state(g, q, "q")
     return lib().orc_cfl_dt(ctypes.byref(g), _dp(q))
 
 
@@ -261,14 +273,14 @@ def rk3_combine(stage: int, qn: np.ndarray, qs: np.ndarray, L: np.ndarray, dt: f
 
 def rk3_step(g: OrcGrid, q: np.ndarray, dt: float = 0.0):
     """One SSP-RK3 step; returns (new q, dt used).  dt <= 0 selects the CFL dt."""
-    q = np.array(q, dtype=np.float64, order="C", copy=True)
+    q = _state(g, q, "q", copy=True)
     used = lib().orc_rk3_step(ctypes.byref(g), _dp(q), float(dt))
     return q, used
 
 
 def run(g: OrcGrid, q: np.ndarray, nsteps: int, dts=None):
     """nsteps steps; returns (q, dts used).  ``dts`` replays a prescribed sequence."""
-    q = np.array(q, dtype=np.float64, order="C", copy=True)
+    q = _state(g, q, "q", copy=True)
     out = np.empty(max(nsteps, 1), dtype=np.float64)
     if dts is not None:
         dts = np.ascontiguousarray(dts, dtype=np.float64)

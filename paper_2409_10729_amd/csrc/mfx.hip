@@ -878,11 +878,19 @@ int standalone_cfl(mfx_ctx* c, int advance = 0, double dt_arg = 0.0)
     return launch_check(c, "cfl_finalize_kernel");
 }
 
-int read_status(mfx_ctx* c, unsigned* st)
+// Device-to-host copy of n bytes into host memory that may live on the
+// caller's stack: the copy is waited for before returning, so no copy is
+// left in flight when an error path returns early.
+int read_device(mfx_ctx* c, void* host, const void* dev, size_t n)
 {
-    HIP_TRY(c, hipMemcpyAsync(st, c->status, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(host, dev, n, hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
     return MFX_OK;
+}
+
+int read_status(mfx_ctx* c, unsigned* st)
+{
+    return read_device(c, st, c->status, sizeof(unsigned));
 }
 
 // MFX_ESTATE for a status word with an error bit (alpha1 outside [0, 1]
@@ -1000,17 +1008,20 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
 
     setup_grid(desc, c, reinterpret_cast<const double*>(c->ws + L.inflow));
 
-    if (hipMemsetAsync(c->ws + L.scal, 0, 64, c->stream) != hipSuccess) {
+    // an error after a copy was queued waits for the stream before the
+    // copy's host source (the context, the tables below) is freed
+    auto abandon = [&](const char* msg) {
+        (void)hipStreamSynchronize(c->stream);
         delete c;
-        return fail(nullptr, MFX_EHIP, "hipMemsetAsync of the scalar block failed");
-    }
+        return fail(nullptr, MFX_EHIP, msg);
+    };
+    if (hipMemsetAsync(c->ws + L.scal, 0, 64, c->stream) != hipSuccess)
+        return abandon("hipMemsetAsync of the scalar block failed");
     // the inflow states for the loaders (zero for other sides); the source
     // lives in the context
     if (hipMemcpyAsync(c->ws + L.inflow, &c->g.inflow[0][0][0], sizeof(double) * 3 * 2 * NVMAX, hipMemcpyHostToDevice,
-                       c->stream) != hipSuccess) {
-        delete c;
-        return fail(nullptr, MFX_EHIP, "copy of the inflow states failed");
-    }
+                       c->stream) != hipSuccess)
+        return abandon("copy of the inflow states failed");
     // per-position tables of directions with unequal cells (host copies
     // kept until the stream has taken them)
     std::vector<double> tabs[3];
@@ -1018,17 +1029,13 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
         if (!desc->faces[k]) continue;
         tabs[k] = nu_table(desc, k);
         if (hipMemcpyAsync(c->ws + L.nu[k], tabs[k].data(), sizeof(double) * tabs[k].size(), hipMemcpyHostToDevice,
-                           c->stream) != hipSuccess) {
-            delete c;
-            return fail(nullptr, MFX_EHIP, "copy of the unequal-cell tables failed");
-        }
+                           c->stream) != hipSuccess)
+            return abandon("copy of the unequal-cell tables failed");
         c->g.nu[k] = reinterpret_cast<const double*>(c->ws + L.nu[k]);
         c->g.nonuniform = 1;
     }
-    if (hipStreamSynchronize(c->stream) != hipSuccess) {
-        delete c;
-        return fail(nullptr, MFX_EHIP, "hipStreamSynchronize after the table copies failed");
-    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess)
+        return abandon("hipStreamSynchronize after the table copies failed");
     for (int k = 0; k < 3; ++k) c->desc.faces[k] = nullptr;  // read here only; the caller may free them
     c->has_state = false;
     c->profiling = false;
@@ -1136,8 +1143,8 @@ int mfx_rk3_step(mfx_ctx* c, double dt, double* dt_used_host)
     // (the caller asked for it, so the call synchronises anyway)
     double dt_seen = 0.0;
     if (dt_used_host && !(dt > 0.0)) {
-        HIP_TRY(c, hipMemcpyAsync(&dt_seen, c->scal, sizeof(double), hipMemcpyDeviceToHost, c->stream));
-        HIP_TRY(c, hipStreamSynchronize(c->stream));
+        rc = read_device(c, &dt_seen, c->scal, sizeof(double));
+        if (rc) return rc;
     }
     rc = run_passes(c, c->q, c->q, c->q1, OUT_STAGE1, dt_dev, dt_arg);
     if (rc) return rc;
@@ -1187,10 +1194,9 @@ int mfx_stats(mfx_ctx* c, double* t, int64_t* step, int64_t* fallback_faces, uin
     double sc[4];
     unsigned st = 0;
     unsigned long long fb = 0;
-    HIP_TRY(c, hipMemcpyAsync(sc, c->scal, sizeof(sc), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(&st, c->status, sizeof(unsigned), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(&fb, c->fallback, sizeof(fb), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if ((rc = read_device(c, sc, c->scal, sizeof(sc))) || (rc = read_device(c, &st, c->status, sizeof(unsigned))) ||
+        (rc = read_device(c, &fb, c->fallback, sizeof(fb))))
+        return rc;
     if (t) *t = sc[1];
     if (step) *step = (int64_t)sc[2];
     if (fallback_faces) *fallback_faces = (int64_t)fb;

@@ -115,9 +115,10 @@ def test_stretched_three_fluids_match_oracle(which):
     spec = wl.stretched(P, _faces(n, which, 90))["spec"]
     nv = 9
     inflow = np.zeros((3, 2, nv))
-    g = oracle.make_grid(dict(spec, faces=None))
-    wz = P["w"][:, :1, :1, :1].copy()  # one cell's primitives as an inflow state
-    inflow[2, 0] = oracle.prim_to_cons(g, wz).reshape(nv)
+    # one cell's primitives as an inflow state, converted on a one-cell grid
+    one = dict(spec, n=(1, 1, 1), faces=None, bc=((P_, P_),) * 3)
+    wz = P["w"][:, :1, :1, :1].copy()
+    inflow[2, 0] = oracle.prim_to_cons(oracle.make_grid(one), wz).reshape(nv)
     spec = dict(spec, inflow=inflow)
     g = oracle.make_grid(spec)
     q0 = oracle.prim_to_cons(g, P["w"])

@@ -371,3 +371,20 @@ def test_rk3_stability_polynomial(z):
     q2 = oracle.rk3_combine(2, q, q1, lam * q1, dt)
     q3 = oracle.rk3_combine(3, q, q2, lam * q2, dt)
     np.testing.assert_allclose(q3, q * (1 + z + z * z / 2 + z ** 3 / 6), rtol=1e-14)
+
+
+def test_wrappers_reject_a_state_of_another_shape():
+    """The oracle's C routines index the whole grid: a state array of any
+    other shape is refused before the call instead of read or written past
+    its end."""
+    spec = wl.random_smooth(n=(6, 5, 4), seed=3, bc=((1, 1), (0, 0), (0, 0)))["spec"]
+    g = oracle.make_grid(spec)
+    small = np.ones((7, 1, 1, 1))
+    for f in (oracle.prim_to_cons, oracle.cons_to_prim, oracle.rhs, oracle.cfl_dt, oracle.rk3_step):
+        with pytest.raises(ValueError):
+            f(g, small)
+    with pytest.raises(ValueError):
+        oracle.run(g, small, 1)
+    q = np.ones((7, 4, 5, 6))
+    with pytest.raises(ValueError):
+        oracle.rhs_at(g, q, np.array([6 * 5 * 4]))
