@@ -96,6 +96,8 @@ def lib():
         L.orc_mlp_omega.argtypes = [dp, ctypes.c_int64, dp, dp, dp]
         L.orc_gelu.argtypes = [ctypes.c_double]
         L.orc_gelu.restype = ctypes.c_double
+        L.orc_gelu_tanh.argtypes = [ctypes.c_double]
+        L.orc_gelu_tanh.restype = ctypes.c_double
         L.orc_cfl_dt.argtypes = [gp, dp]
         L.orc_cfl_dt.restype = ctypes.c_double
         L.orc_rk3_combine.argtypes = [ctypes.c_int, ctypes.c_int64, dp, dp, dp, ctypes.c_double, dp]
@@ -253,8 +255,14 @@ def mlp_omega(theta, X, base) -> np.ndarray:
 
 
 def gelu(a: float) -> float:
-    """The tanh form of GELU the learned weights use."""
+    """GELU as the learned weights' inference evaluates it (the polynomial
+    form of the tanh form's remainder; see orc.c gelu_inference)."""
     return lib().orc_gelu(float(a))
+
+
+def gelu_tanh(a: float) -> float:
+    """The tanh form of GELU (the training form)."""
+    return lib().orc_gelu_tanh(float(a))
 
 
 def cfl_dt(g: OrcGrid, q: np.ndarray) -> float:

@@ -9,12 +9,15 @@ Shu 2006; the network is this project's addition):
   the Jiang-Shu indicators beta_k and S = beta0 + beta1 + beta2 + eps:
       x = (beta0/S, beta1/S, beta2/S, |beta0 - beta2|/S, D^2/(S + D^2)),
       D = v0 - 4 v1 + 6 v2 - 4 v3 + v4;
-  network 5 -> 32 (GELU, tanh form) -> 32 (GELU) -> 3 logits z, added to the
+  network 5 -> 32 (GELU) -> 32 (GELU) -> 3 logits z, added to the
   Jiang-Shu log-weights: omega = softmax(log omega_JS + z) (a zero output
   layer gives the Jiang-Shu weights exactly);
   value = sum_k omega_k p_k with the three third-order candidates p_k;
   loss  = mean((value' - target')^2) + lam * mean(sum_k (omega_k - omega_JS,k)^2),
   where primes are stencil-normalised: (. - v2) / scale.
+GELU: training uses its tanh form (gelu, gelu_grad); the bfloat16 inference
+forward uses gelu_inference, max(x, 0) minus a degree-7 polynomial fit of the
+tanh form's remainder (within 1.2e-4 of the tanh form).
 Parameters, flat float vector of 1347: W1[32][5], b1[32], W2[32][32], b2[32],
 W3[3][32], b3[3].
 
@@ -85,6 +88,24 @@ def features(v, eps=1e-6):
 
 def gelu(x):
     return 0.5 * x * (1.0 + np.tanh(GELU_C * (x + GELU_A * x ** 3)))
+
+
+# Q(t) of gelu_inference, lowest degree first (float32 values)
+GELU_Q = np.array([0.497150153, -0.375513077, -0.0665387958, 0.157749414, -0.0645674914, 0.0113088572,
+                   -0.00075154379], dtype=np.float32).astype(np.float64)
+GELU_T = 3.75
+
+
+def gelu_inference(x):
+    """GELU as the inference evaluates it: max(x, 0) - t Q(t), t = min(|x|, 3.75)."""
+    x = np.asarray(x, dtype=np.float64)
+    t = np.minimum(np.abs(x), GELU_T)
+    Q = np.zeros_like(t)
+    tk = np.ones_like(t)
+    for q in GELU_Q:
+        Q = Q + q * tk
+        tk = tk * t
+    return np.maximum(x, 0.0) - t * Q
 
 
 def gelu_grad(x):
@@ -187,9 +208,9 @@ def forward_bf16(theta, X, OJS):
     p = unpack(np.asarray(theta, dtype=np.float32).astype(np.float64))
     r = bf16_round
     A1 = r(X) @ r(p["W1"]).T + r(p["b1"])
-    H1 = r(gelu(A1))
+    H1 = r(gelu_inference(A1))
     A2 = H1 @ r(p["W2"]).T + p["b2"]
-    H2 = r(gelu(A2))
+    H2 = r(gelu_inference(A2))
     with np.errstate(divide="ignore"):
         Z = H2 @ r(p["W3"]).T + p["b3"] + np.log(OJS)
     Z = Z - Z.max(1, keepdims=True)

@@ -628,9 +628,12 @@ void orc_cons_to_prim(const orc_grid* g, const double* q, double* w)
      the Jiang-Shu indicators beta_k and S = beta0 + beta1 + beta2 + eps:
        x = (beta0/S, beta1/S, beta2/S, |beta0 - beta2|/S, D^2/(S + D^2)),
        D = v0 - 4 v1 + 6 v2 - 4 v3 + v4;
-     network 5 -> 32 -> 32 -> 3 with the tanh form of GELU,
-       GELU(a) = a (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3))) / 2,
-     giving logits z; weights omega = softmax(ln omega_JS + z) on the three
+     network 5 -> 32 -> 32 -> 3 with GELU (trained with its tanh form
+       a (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3))) / 2), evaluated at
+       inference as max(a, 0) - t Q(t), t = min(|a|, 3.75), Q a degree-6
+       polynomial fitted (minimax) to the tanh form's remainder
+       h(t) = t (1 - tanh(sqrt(2/pi) (t + 0.044715 t^3))) / 2, within
+       1.2e-4 of the tanh form (see gelu_inference), giving logits z; weights omega = softmax(ln omega_JS + z) on the three
      third-order candidates (a zero output layer is Jiang-Shu);
      a cell's left edge is the right edge of its reversed stencil.
    Inference precision of the method: the features, the weights of all
@@ -673,6 +676,23 @@ static double gelu_tanh(double a)
     return 0.5 * a * (1.0 + tanh(c * (a + 0.044715 * a * a * a)));
 }
 
+/* GELU as the inference evaluates it: the positive part of a minus the
+   tanh form's remainder h(|a|), h replaced beyond 3.75 by its value there
+   and below by t Q(t) with Q(t) = q0 + q1 t + ... + q6 t^6 (coefficients as
+   float32 values, the definition of the inference network). */
+static double gelu_inference(double a)
+{
+    static const double q[7] = {0.497150153, -0.375513077, -0.0665387958, 0.157749414,
+                                -0.0645674914, 0.0113088572, -0.00075154379};
+    const double t = fmin(fabs(a), 3.75);
+    double Q = 0.0, tk = 1.0;
+    for (int k = 0; k < 7; ++k) {
+        Q += (double)(float)q[k] * tk;
+        tk *= t;
+    }
+    return fmax(a, 0.0) - t * Q;
+}
+
 /* Parameters in the order W1[32][5], b1[32], W2[32][32], b2[32], W3[3][32],
    b3[3], with the bfloat16 rounding of the operands applied once. */
 static void mlp_load(const double* theta, orc_mlp* m)
@@ -697,12 +717,12 @@ static void mlp_logits(const orc_mlp* m, const double x[5], double z[3])
     for (int j = 0; j < MLP_H; ++j) {
         double a = m->b1[j];
         for (int k = 0; k < 5; ++k) a += m->W1[j][k] * xb[k];
-        h1[j] = bf16(gelu_tanh(a));
+        h1[j] = bf16(gelu_inference(a));
     }
     for (int j = 0; j < MLP_H; ++j) {
         double a = m->b2[j];
         for (int k = 0; k < MLP_H; ++k) a += m->W2[j][k] * h1[k];
-        h2[j] = bf16(gelu_tanh(a));
+        h2[j] = bf16(gelu_inference(a));
     }
     for (int i = 0; i < 3; ++i) {
         double a = m->b3[i];
@@ -1028,7 +1048,8 @@ void orc_mlp_omega(const double* theta, int64_t n, const double* x, const double
     }
 }
 
-double orc_gelu(double a) { return gelu_tanh(a); }
+double orc_gelu(double a) { return gelu_inference(a); }
+double orc_gelu_tanh(double a) { return gelu_tanh(a); }
 
 /* ---------- right-hand side at selected cells, one by one ----------
    cells: linear indices (k*ny + j)*nx + i; out: [ncell][nvar].  Uses the same

@@ -5,14 +5,26 @@
 // Jiang-Shu exactly.  Evaluated inside the sweeps on the matrix cores:
 // bfloat16 operands, float32 accumulation.
 //
-// Formulation on v_mfma_f32_32x32x8_bf16 (one wave, 32 samples per tile):
-// each layer computes H^T = W * X^T with the weights as the A operand (rows =
-// output units) and the activations as the B operand (columns = samples).
-// The accumulator of one layer holds, in lane l, unit 8(r/4) + 4(l/32) + r%4
-// of sample l%32 in register r, which is exactly the B-operand layout of the
-// next layer's K-step r/4; so the three layers chain in registers with no
-// data exchange.  Layer 1 takes the 5 features plus a constant 1 (bias) as
-// its K = 8; layers 2 and 3 start from the bias in the accumulator.
+// One wave evaluates 64 samples, one per lane, as two 32-sample tiles (tile
+// h holds the samples of lanes 32h .. 32h+31).  Each layer computes
+// H^T = W * X^T with the weights as the A operand (rows = output units) and
+// the activations as the B operand (columns = samples):
+//   layer 1 on v_mfma_f32_32x32x8_bf16 (K = 5 features, a constant 1 for the
+//     bias, two zeros): lane l supplies k = 4(l/32) .. +3 of sample l%32 of
+//     its tile; the lanes of the other half hold those values, so one
+//     v_permlane32_swap per dword builds both tiles' operands from each
+//     lane's own features;
+//   layers 2 and 3 on v_mfma_f32_32x32x16_bf16 (K = 32 hidden units in two
+//     K-steps): the accumulator of a layer holds, in lane l and register r,
+//     unit 8(r/4) + 4(l/32) + r%4 of sample l%32; K-step s takes registers
+//     8s .. 8s+7 as its k-slots 8(l/32) .. +7, so the next layer's weights
+//     are packed with their input units permuted the same way and the layers
+//     chain in registers;
+//   layer 3 of tile h keeps its three outputs in rows 4h .. 4h+2, which land
+//     in registers 0..2 of the lanes that own the tile's samples: both tiles
+//     accumulate into one register block and every lane reads its own logits.
+// No LDS and no wave synchronisation: the caller needs only uniform control
+// flow across the wave.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -29,63 +41,96 @@ constexpr float GELU_C = 0.7978845608028654f;  // sqrt(2/pi)
 constexpr float GELU_A = 0.044715f;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
-// Per-lane slice of the network in MFMA operand layout (packed once by
-// mlp_pack_kernel).  152 bytes per lane, 64 lanes.
+// Input unit that k-slot i of K-step s feeds in lane half g (layers 2, 3).
+__host__ __device__ constexpr int mlp_kslot_unit(int s, int g, int i) { return 8 * (2 * s + i / 4) + 4 * g + i % 4; }
+
+// Per-lane slice of the network in matrix-core operand layout (packed once
+// by the pack kernel).  192 bytes per lane, 64 lanes.
 struct MlpLane {
-    bf16x4 a1;     // layer 1: row l%32, k = 4(l/32)..+3 of [W1 | b1 | 0 0]
-    bf16x4 a2[4];  // layer 2: row l%32, k = 8s + 4(l/32) + i
-    bf16x4 a3[4];  // layer 3: rows >= 3 are zero
-    f32x16 c2;     // layer-2 bias in accumulator layout
-    float c3[4];   // layer-3 bias for registers 0..2 (zero for lanes >= 32)
+    bf16x4 a1;        // layer 1: row l%32, k = 4(l/32)..+3 of [W1 | b1 | 0 0]
+    bf16x8 a2[2];     // layer 2, K-step s: row l%32, k-slots 8(l/32)..+7
+    bf16x8 a3[2][2];  // layer 3 of tile h, K-step s: rows 4h..4h+2 hold W3, other rows zero
+    f32x16 c2;        // layer-2 bias in accumulator layout
+    float c3[3];      // layer-3 bias
+    float pad[5];
 };
 
 __device__ __forceinline__ short bf16_bits(float x) { return __builtin_bit_cast(short, (__bf16)x); }
 
-// GELU, tanh form: 0.5 x (1 + tanh(y)), y = c (x + a x^3), written as
-// x - x / (1 + e^{2y}) (exact identity; saturates correctly at +-inf: the
-// hardware reciprocal of +inf is 0).  Its result is rounded to bfloat16, so
-// the 1-ulp hardware exponential and reciprocal are ample.
+// GELU as the inference evaluates it: the tanh form of GELU,
+// 0.5 x (1 + tanh(sqrt(2/pi) (x + 0.044715 x^3))), equals max(x, 0) - h(|x|)
+// with h(a) = 0.5 a (1 - tanh(sqrt(2/pi) (a + 0.044715 a^3))) a bump that
+// vanishes quickly; h is replaced by t Q(t), t = min(|x|, 3.75), Q the
+// degree-6 polynomial below (a minimax fit; within 1.2e-4 of the tanh form
+// for every x, about 1/30 of a bfloat16 step at 1, and the result is
+// rounded to bfloat16).  Nine instructions, no transcendental functions.
+constexpr float GELU_T = 3.75f;
+constexpr float GELU_Q[7] = {0.497150153f,   -0.375513077f, -0.0665387958f, 0.157749414f,
+                             -0.0645674914f, 0.0113088572f, -0.00075154379f};
+
 __device__ __forceinline__ float gelu(float x)
 {
-    const float y2 = 2.0f * GELU_C * x * (1.0f + GELU_A * x * x);
-    const float e = __expf(y2);
-    return x - x * __builtin_amdgcn_rcpf(1.0f + e);
+    // min(|x|, T) and max(x, 0) as medians of three (one v_med3_f32 each;
+    // min/max of a matrix-core result would first be quieted, one more
+    // instruction each); the median with the largest float equals max(x, 0)
+    // for every finite x
+    const float t = __builtin_amdgcn_fmed3f(fabsf(x), 0.0f, GELU_T);
+    const float relu = __builtin_amdgcn_fmed3f(x, 0.0f, 3.40282347e38f);
+    float q = GELU_Q[6];
+#pragma unroll
+    for (int k = 5; k >= 0; --k) q = __builtin_fmaf(q, t, GELU_Q[k]);
+    return __builtin_fmaf(-q, t, relu);
 }
 
-__device__ __forceinline__ f32x16 mlp_layers(const MlpLane& m, bf16x4 b1)
+// bfloat16 (nearest, ties to even) of GELU of eight accumulator registers.
+__device__ __forceinline__ bf16x8 gelu8(const f32x16& acc, int r0)
 {
-    f32x16 acc = {};
-    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(m.a1, b1, acc, 0, 0, 0);
-    bf16x4 b2[4];
+    bf16v8 b;
 #pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) b2[s][i] = bf16_bits(gelu(acc[4 * s + i]));
-    f32x16 acc2 = m.c2;
-#pragma unroll
-    for (int s = 0; s < 4; ++s) acc2 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(m.a2[s], b2[s], acc2, 0, 0, 0);
-    bf16x4 b3[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) b3[s][i] = bf16_bits(gelu(acc2[4 * s + i]));
-    f32x16 acc3 = {};
-    acc3[0] = m.c3[0];
-    acc3[1] = m.c3[1];
-    acc3[2] = m.c3[2];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) acc3 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(m.a3[s], b3[s], acc3, 0, 0, 0);
-    return acc3;
+    for (int i = 0; i < 8; ++i) b[i] = (__bf16)gelu(acc[r0 + i]);
+    return __builtin_bit_cast(bf16x8, b);
 }
 
-// Per-wave LDS slot for one variable's samples: the two edge samples (side 0
-// right edge, side 1 mirrored = left edge) of each of the 64 lanes.
-struct LearnedLds {
-    short feat[2][64][8];  // bfloat16 features 0..4, constant 1 (bias), 0, 0
-    float z[2][64][4];     // network outputs (logits)
-};
+// Logits z of the lane's own sample x[0..4] (features in [0, 1]); the whole
+// wave calls this together.
+__device__ __forceinline__ void mlp_logits(const MlpLane& m, const float x[5], float z[3])
+{
+    // one evaluation at a time: the scheduler would otherwise interleave the
+    // matrix-core chains of many samples and run out of registers
+    __builtin_amdgcn_sched_barrier(0);
+    // layer-1 operands of both tiles from the lanes' own features
+    bf16v4 lo4 = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
+    bf16v4 hi4 = {(__bf16)x[4], (__bf16)1.0f, (__bf16)0.0f, (__bf16)0.0f};
+    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+    const u32x2 lo = __builtin_bit_cast(u32x2, lo4), hi = __builtin_bit_cast(u32x2, hi4);
+    const auto s0 = __builtin_amdgcn_permlane32_swap(lo[0], hi[0], false, false);
+    const auto s1 = __builtin_amdgcn_permlane32_swap(lo[1], hi[1], false, false);
+    const u32x2 t0 = {s0[0], s1[0]}, t1 = {s0[1], s1[1]};
+    const bf16x4 b1[2] = {__builtin_bit_cast(bf16x4, t0), __builtin_bit_cast(bf16x4, t1)};
+    f32x16 acc3 = {};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const f32x16 zero = {};
+        const f32x16 acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(m.a1, b1[h], zero, 0, 0, 0);
+        f32x16 acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, m.a2[0]),
+                                                              __builtin_bit_cast(bf16v8, gelu8(acc1, 0)), m.c2, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, m.a2[1]),
+                                                       __builtin_bit_cast(bf16v8, gelu8(acc1, 8)), acc2, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, m.a3[h][0]),
+                                                       __builtin_bit_cast(bf16v8, gelu8(acc2, 0)), acc3, 0, 0, 0);
+        acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, m.a3[h][1]),
+                                                       __builtin_bit_cast(bf16v8, gelu8(acc2, 8)), acc3, 0, 0, 0);
+    }
+    z[0] = acc3[0] + m.c3[0];
+    z[1] = acc3[1] + m.c3[1];
+    z[2] = acc3[2] + m.c3[2];
+    __builtin_amdgcn_sched_barrier(0);
+}
 
 // Jiang-Shu smoothness indicators of the stencil a..e and its fourth
 // difference D.
@@ -186,67 +231,20 @@ __device__ __forceinline__ void softmax3(const float z[3], const float lw[3], fl
     om[2] = e2 * inv;
 }
 
-// Orders this wave's LDS writes before reads of them by its other lanes.
-// The slot is private to the wave and LDS instructions of one wave execute
-// in order, so only the compiler must be kept from moving accesses across.
-__device__ __forceinline__ void wave_lds_sync()
+// Learned weights of the lane's own sample (the whole wave calls this
+// together): omega = softmax(z + ln omega_JS), lw the base-2 log-weights.
+__device__ __forceinline__ void mlp_omega(const MlpLane& m, const float x[5], const float lw[3], float om[3])
 {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
-// Learned weights of 2 samples per lane (x0: side 0, x1: side 1) for the
-// whole wave, which must call this together.  The wave stages its 128
-// samples in its own LDS slot and runs them as four 32-sample tiles on the
-// matrix cores.
-__device__ __forceinline__ void mlp_omega_pair(const MlpLane& m, LearnedLds* L, const float x0[5], const float x1[5],
-                                               const float lw0[3], const float lw1[3], float om0[3], float om1[3])
-{
-    const int lane = threadIdx.x & 63;
-    const short one = bf16_bits(1.0f);
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        L->feat[0][lane][k] = bf16_bits(x0[k]);
-        L->feat[1][lane][k] = bf16_bits(x1[k]);
-    }
-    L->feat[0][lane][5] = one;
-    L->feat[1][lane][5] = one;
-    L->feat[0][lane][6] = L->feat[0][lane][7] = 0;
-    L->feat[1][lane][6] = L->feat[1][lane][7] = 0;
-    wave_lds_sync();
-#pragma unroll 1
-    for (int t = 0; t < 4; ++t) {
-        const int side = t >> 1, half = t & 1;
-        const bf16x4 b = *reinterpret_cast<const bf16x4*>(&L->feat[side][32 * half + (lane & 31)][4 * (lane >> 5)]);
-        const f32x16 z = mlp_layers(m, b);
-        if (lane < 32) {
-            L->z[side][32 * half + lane][0] = z[0];
-            L->z[side][32 * half + lane][1] = z[1];
-            L->z[side][32 * half + lane][2] = z[2];
-        }
-    }
-    wave_lds_sync();
-    const float z0[3] = {L->z[0][lane][0], L->z[0][lane][1], L->z[0][lane][2]};
-    const float z1[3] = {L->z[1][lane][0], L->z[1][lane][1], L->z[1][lane][2]};
-    softmax3(z0, lw0, om0);
-    softmax3(z1, lw1, om1);
-}
-
-// One sample per lane (stand-alone inference): the second side is unused.
-__device__ __forceinline__ void mlp_omega(const MlpLane& m, LearnedLds* L, const float f[5], const float lw[3],
-                                          float om[3])
-{
-    float dummy[3];
-    mlp_omega_pair(m, L, f, f, lw, lw, om, dummy);
+    float z[3];
+    mlp_logits(m, x, z);
+    softmax3(z, lw, om);
 }
 
 // Both edge values of one cell with learned weights (right edge: features
 // as computed; left edge: the mirrored stencil, i.e. features with beta0 and
 // beta2 swapped, weights applied to the mirrored candidates).
-__device__ __forceinline__ void weno5_learned(const MlpLane& m, LearnedLds* L, float a, float b, float c, float d,
-                                              float e, float eps, float& left, float& right, bool& finite_r,
-                                              bool& finite_l)
+__device__ __forceinline__ void weno5_learned(const MlpLane& m, float a, float b, float c, float d, float e,
+                                              float eps, float& left, float& right, bool& finite_r, bool& finite_l)
 {
     float x[5], xm[5], nlb[3], om[3], oml[3];
     weno_features(a, b, c, d, e, eps, x, nlb);
@@ -258,7 +256,8 @@ __device__ __forceinline__ void weno5_learned(const MlpLane& m, LearnedLds* L, f
     // mirrored stencil: indicators reversed, linear weights (0.1, 0.6, 0.3) kept
     const float lw[3] = {LOG2_D0 + nlb[0], LOG2_D1 + nlb[1], LOG2_D2 + nlb[2]};
     const float lwm[3] = {LOG2_D0 + nlb[2], LOG2_D1 + nlb[1], LOG2_D2 + nlb[0]};
-    mlp_omega_pair(m, L, x, xm, lw, lwm, om, oml);
+    mlp_omega(m, x, lw, om);
+    mlp_omega(m, xm, lwm, oml);
     weno5_apply(om, oml, a, b, c, d, e, left, right);
     finite_r = isfinite(om[0] + om[1] + om[2]);
     finite_l = isfinite(oml[0] + oml[1] + oml[2]);

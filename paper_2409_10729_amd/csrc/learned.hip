@@ -236,39 +236,43 @@ __global__ void __launch_bounds__(256) forward_mfma_kernel(const MlpLane* __rest
                                                            const float* __restrict__ ojs, long long n,
                                                            float* __restrict__ omega)
 {
-    __shared__ LearnedLds slots[4];
     const MlpLane m = packed[threadIdx.x & 63];
     const long long i_raw = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long i = i_raw < n ? i_raw : n - 1;
     float x[5], lw[3], om[3];
     for (int k = 0; k < 5; ++k) x[k] = feat[i * 5 + k];
     for (int k = 0; k < 3; ++k) lw[k] = log2f(ojs[i * 3 + k]);
-    mlp_omega(m, &slots[threadIdx.x >> 6], x, lw, om);
+    mlp_omega(m, x, lw, om);
     if (i_raw < n)
         for (int k = 0; k < 3; ++k) omega[i * 3 + k] = om[k];
 }
 
-// Per-lane operand slices for the matrix-core evaluation.
+// Per-lane operand slices for the matrix-core evaluation (layouts in
+// learned.h).
 __global__ void __launch_bounds__(64) pack_kernel(const float* __restrict__ P, MlpLane* __restrict__ packed)
 {
     const int l = threadIdx.x;
-    const int row = l % 32, kh = 4 * (l / 32);
-    MlpLane m;
+    const int row = l % 32, g = l / 32;
+    MlpLane m = {};
     for (int i = 0; i < 4; ++i) {
-        const int k = kh + i;  // layer-1 K index: 0..4 features, 5 bias, 6..7 zero
+        const int k = 4 * g + i;  // layer-1 K index: 0..4 features, 5 bias, 6..7 zero
         float w1 = 0.f;
         if (k < 5) w1 = P[MLP_OFF_W1 + row * 5 + k];
         else if (k == 5) w1 = P[MLP_OFF_B1 + row];
         m.a1[i] = bf16_bits(w1);
     }
-    for (int s = 0; s < 4; ++s)
-        for (int i = 0; i < 4; ++i) {
-            const int k = 8 * s + kh + i;
-            m.a2[s][i] = bf16_bits(P[MLP_OFF_W2 + row * MLP_H + k]);
-            m.a3[s][i] = bf16_bits(row < 3 ? P[MLP_OFF_W3 + row * MLP_H + k] : 0.f);
+    for (int s = 0; s < 2; ++s)
+        for (int i = 0; i < 8; ++i) {
+            const int u = mlp_kslot_unit(s, g, i);
+            m.a2[s][i] = bf16_bits(P[MLP_OFF_W2 + row * MLP_H + u]);
+            // tile h keeps W3 in rows 4h .. 4h+2
+            for (int h = 0; h < 2; ++h) {
+                const int o = row - 4 * h;
+                m.a3[h][s][i] = bf16_bits(o >= 0 && o < 3 ? P[MLP_OFF_W3 + o * MLP_H + u] : 0.f);
+            }
         }
-    for (int r = 0; r < 16; ++r) m.c2[r] = P[MLP_OFF_B2 + 8 * (r / 4) + kh + (r % 4)];
-    for (int r = 0; r < 4; ++r) m.c3[r] = (l < 32 && r < 3) ? P[MLP_OFF_B3 + r] : 0.f;
+    for (int r = 0; r < 16; ++r) m.c2[r] = P[MLP_OFF_B2 + 8 * (r / 4) + 4 * g + (r % 4)];
+    for (int r = 0; r < 3; ++r) m.c3[r] = P[MLP_OFF_B3 + r];
     packed[l] = m;
 }
 

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "../../include/mfx.h"
+#include "launch.h"
 #include "sweep.h"
 #include "xrow.h"
 
@@ -63,15 +64,6 @@ Overrides read_overrides()
 struct Layout {
     size_t q, q1, q2, r, scal, inflow, partial, bface, mlp, mlp_params, nu[3], total;
     long long n_partial;
-};
-
-// Geometry of one sweep launch for direction d.
-struct SweepGeom {
-    dim3 grid;
-    int block;
-    int seg;          // segment length (marching sweeps) or rows per block (x row sweep)
-    size_t lds;       // dynamic LDS bytes
-    bool xrows;       // x sweep by whole rows
 };
 
 // The x sweep takes whole rows when a row fits the row kernel (nx <=
@@ -646,84 +638,6 @@ hipEvent_t take_event(mfx_ctx* c)
     return e;
 }
 
-// Pointers and scalars of one sweep launch.
-struct LaunchArgs {
-    const SweepGeom* sg;
-    hipStream_t st;
-    const Grid* g;
-    const double* qs;
-    const double* qn;
-    void* r;  // partial RHS buffer (compute type)
-    double* out;
-    const double* dt_dev;
-    double dt_arg;
-    void* bface;  // boundary faces of the x row sweep (compute type)
-    const MlpLane* mlp;       // packed network (learned weights only)
-    unsigned long long* fb;   // fallback counter (learned weights only)
-    double* partial;          // CFL block maxima (stage-3 y/z sweep with cfl)
-    unsigned* status;
-    bool cfl;                 // this stage-3 sweep also reduces the CFL speed of its output
-};
-
-// The x row sweep reads the boundary faces that boundary_faces_x leaves in
-// `bface` (launched just before it on the same stream).
-// F: the fluid model (two fluids, or Fl<3> with the marching x sweep only).
-template <int DIR, typename T, bool FIRST, int MODE, bool L, int SCHEME, class F>
-void launch_one(const LaunchArgs& a)
-{
-    const SweepGeom& sg = *a.sg;
-    T* r = static_cast<T*>(a.r);
-    if constexpr (DIR == 0) {
-        if constexpr (F::NF == 2 && SCHEME != SCHEME_WENO5NU) {
-            if (sg.xrows) {
-                T* bf = static_cast<T*>(a.bface);
-                const long long rows = (long long)a.g->n[1] * a.g->n[2];
-                boundary_faces_x<T, L, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf,
-                                                                                                 a.mlp, a.fb);
-                sweep_x_rows<T, FIRST, MODE, L, SCHEME><<<sg.grid, sg.block, sg.lds, a.st>>>(
-                    *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.mlp, a.fb);
-                return;
-            }
-        }
-        sweep_x_march<T, FIRST, MODE, L, SCHEME, F><<<sg.grid, XROWS, 0, a.st>>>(
-            *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb);
-    } else {
-        if constexpr (MODE == OUT_STAGE3 && !L) {
-            if (a.cfl) {
-                sweep_yz<DIR, T, FIRST, MODE, L, true, SCHEME, F><<<sg.grid, sg.block, 0, a.st>>>(
-                    *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, a.partial, a.status);
-                return;
-            }
-        }
-        sweep_yz<DIR, T, FIRST, MODE, L, false, SCHEME, F><<<sg.grid, sg.block, 0, a.st>>>(
-            *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb, nullptr, a.status);
-    }
-}
-
-template <int DIR, typename T, bool FIRST, bool L, int SCHEME, class F>
-void launch_mode(int mode, const LaunchArgs& a)
-{
-    switch (mode) {
-    case OUT_ACCUM: launch_one<DIR, T, FIRST, OUT_ACCUM, L, SCHEME, F>(a); break;
-    case OUT_RHS: launch_one<DIR, T, FIRST, OUT_RHS, L, SCHEME, F>(a); break;
-    case OUT_STAGE1: launch_one<DIR, T, FIRST, OUT_STAGE1, L, SCHEME, F>(a); break;
-    case OUT_STAGE2: launch_one<DIR, T, FIRST, OUT_STAGE2, L, SCHEME, F>(a); break;
-    default: launch_one<DIR, T, FIRST, OUT_STAGE3, L, SCHEME, F>(a); break;
-    }
-}
-
-// The x sweep, when active, is always the first direction of a pass.
-template <typename T, bool L, int SCHEME = 5, class F = Fl2>
-void launch_dispatch(int d, bool first, int mode, const LaunchArgs& a)
-{
-    if (d == 0)
-        launch_mode<0, T, true, L, SCHEME, F>(mode, a);
-    else if (d == 1)
-        first ? launch_mode<1, T, true, L, SCHEME, F>(mode, a) : launch_mode<1, T, false, L, SCHEME, F>(mode, a);
-    else
-        first ? launch_mode<2, T, true, L, SCHEME, F>(mode, a) : launch_mode<2, T, false, L, SCHEME, F>(mode, a);
-}
-
 int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* out, int first, int mode,
                  const double* dt_dev, double dt_arg, bool cfl = false)
 {
@@ -742,15 +656,15 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
     // a direction with unequal cells takes the per-position scheme
     const int sch = c->g.nu[d] ? SCHEME_WENO5NU : scheme_of(c->desc);
     if (learned_weights(c->desc))
-        launch_dispatch<float, true>(d, first != 0, mode, la);
+        launch_dispatch<float, true, SCHEME_WENO5, Fl2>(d, first != 0, mode, la);
     else if (c->g.nf == 3 && c->desc.precision == MFX_FP32_MIXED)
         by_scheme(sch, [&](auto s) { launch_dispatch<float, false, decltype(s)::value, Fl<3>>(d, first != 0, mode, la); });
     else if (c->g.nf == 3)
         by_scheme(sch, [&](auto s) { launch_dispatch<double, false, decltype(s)::value, Fl<3>>(d, first != 0, mode, la); });
     else if (c->desc.precision == MFX_FP32_MIXED)
-        by_scheme(sch, [&](auto s) { launch_dispatch<float, false, decltype(s)::value>(d, first != 0, mode, la); });
+        by_scheme(sch, [&](auto s) { launch_dispatch<float, false, decltype(s)::value, Fl2>(d, first != 0, mode, la); });
     else
-        by_scheme(sch, [&](auto s) { launch_dispatch<double, false, decltype(s)::value>(d, first != 0, mode, la); });
+        by_scheme(sch, [&](auto s) { launch_dispatch<double, false, decltype(s)::value, Fl2>(d, first != 0, mode, la); });
     int rc = launch_check(c, "sweep kernel");
     if (rc) return rc;
     if (c->profiling) {
@@ -769,38 +683,6 @@ bool fused_xy(const mfx_ctx* c)
            !c->g.nu[0] && !c->g.nu[1] && use_xrows(c->g.n, c->xmode_override, c->elem);
 }
 
-template <typename T, int MODE, int SCHEME>
-void launch_xy_mode(mfx_ctx* c, const double* qs, const double* qn, double* out, const double* dt_dev, double dt_arg)
-{
-    const Grid& g = c->g;
-    const long long rows = (long long)g.n[1] * g.n[2];
-    T* bf = static_cast<T*>(c->bface);
-    boundary_faces_x<T, false, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, c->stream>>>(g, qs, bf, c->mlp,
-                                                                                              c->fallback);
-    // segments along y as for the y sweep (lanes = x, blocks over z and segments)
-    int seg = c->seg_override > 0 ? c->seg_override : 64;
-    const long long pencils = (long long)g.n[0] * g.n[2];
-    while (seg > 16 && pencils * ((g.n[1] + seg - 1) / seg) < 256LL * 64 * 16) seg /= 2;
-    seg = std::min(seg, g.n[1]);
-    const dim3 grid(1, (unsigned)g.n[2], (unsigned)((g.n[1] + seg - 1) / seg));
-    const int block = 64 * ((g.n[0] + 63) / 64);
-    sweep_xy<T, MODE, SCHEME><<<grid, block, xrow_lds_bytes(g.n[0], sizeof(T)), c->stream>>>(
-        g, qs, qn, static_cast<T*>(c->r), out, seg, bf, dt_dev, dt_arg);
-}
-
-template <typename T, int SCHEME>
-void launch_xy(mfx_ctx* c, int mode, const double* qs, const double* qn, double* out, const double* dt_dev,
-               double dt_arg)
-{
-    switch (mode) {
-    case OUT_ACCUM: launch_xy_mode<T, OUT_ACCUM, SCHEME>(c, qs, qn, out, dt_dev, dt_arg); break;
-    case OUT_RHS: launch_xy_mode<T, OUT_RHS, SCHEME>(c, qs, qn, out, dt_dev, dt_arg); break;
-    case OUT_STAGE1: launch_xy_mode<T, OUT_STAGE1, SCHEME>(c, qs, qn, out, dt_dev, dt_arg); break;
-    case OUT_STAGE2: launch_xy_mode<T, OUT_STAGE2, SCHEME>(c, qs, qn, out, dt_dev, dt_arg); break;
-    default: launch_xy_mode<T, OUT_STAGE3, SCHEME>(c, qs, qn, out, dt_dev, dt_arg); break;
-    }
-}
-
 // The fused pass, profiled as direction 3 (first pass).
 int launch_sweep_xy(mfx_ctx* c, const double* qs, const double* qn, double* out, int mode, const double* dt_dev,
                     double dt_arg)
@@ -812,10 +694,11 @@ int launch_sweep_xy(mfx_ctx* c, const double* qs, const double* qn, double* out,
         if (!pend.a || !pend.b) return fail(c, MFX_EHIP, "hipEventCreate failed");
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
+    const XYArgs xa{&c->g, c->stream, qs, qn, c->r, out, dt_dev, dt_arg, c->bface, c->mlp, c->fallback, c->seg_override};
     if (c->desc.precision == MFX_FP32_MIXED)
-        by_scheme<false>(scheme_of(c->desc), [&](auto s) { launch_xy<float, decltype(s)::value>(c, mode, qs, qn, out, dt_dev, dt_arg); });
+        by_scheme<false>(scheme_of(c->desc), [&](auto s) { launch_xy<float, decltype(s)::value>(mode, xa); });
     else
-        by_scheme<false>(scheme_of(c->desc), [&](auto s) { launch_xy<double, decltype(s)::value>(c, mode, qs, qn, out, dt_dev, dt_arg); });
+        by_scheme<false>(scheme_of(c->desc), [&](auto s) { launch_xy<double, decltype(s)::value>(mode, xa); });
     int rc = launch_check(c, "fused x-y sweep");
     if (rc) return rc;
     if (c->profiling) {

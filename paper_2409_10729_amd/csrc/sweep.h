@@ -591,7 +591,6 @@ struct ReconJS<T, SCHEME_WENO5NU> {
 // once (a face two segments both solve is counted by one of them).
 struct ReconLearned {
     MlpLane m;
-    LearnedLds* lds;  // this wave's slot
     Mix<float> mix;
     bool valid;  // this lane owns a real cell (only those are counted)
     unsigned fallbacks;
@@ -650,7 +649,8 @@ struct ReconLearned {
         const float lw[3] = {log2f(wr[0]), log2f(wr[1]), log2f(wr[2])};
         const float lwm[3] = {log2f(wm[0]), log2f(wm[1]), log2f(wm[2])};
         float om[3], oml[3];
-        mlp_omega_pair(m, lds, f, fm, lw, lwm, om, oml);
+        mlp_omega(m, f, lw, om);
+        mlp_omega(m, fm, lwm, oml);
         const bool finR = isfinite(om[0] + om[1] + om[2]);
         const bool finL = isfinite(oml[0] + oml[1] + oml[2]);
         float ll[NV], rl[NV];
@@ -693,7 +693,7 @@ struct ReconLearned {
                 rl[v] = rj[v];
             } else {
                 bool fr, fl;
-                weno5_learned(m, lds, a, b, c, d, e, eps, ll[v], rl[v], fr, fl);
+                weno5_learned(m, a, b, c, d, e, eps, ll[v], rl[v], fr, fl);
                 finR = finR && fr;
                 finL = finL && fl;
             }
@@ -718,8 +718,6 @@ struct ReconLearned {
     }
 };
 
-constexpr int LEARNED_MAX_WAVES = 8;  // largest block of a learned sweep: 512 threads
-
 template <typename T, bool LEARNED, int SCHEME = 5>
 struct ReconOf {
     using type = ReconJS<T, SCHEME>;
@@ -729,19 +727,13 @@ struct ReconOf<float, true, 5> {
     using type = ReconLearned;
 };
 
-// WAVES: the most waves a block of the calling kernel has (the learned
-// form's LDS slots are static, so the count sizes the kernel's LDS).
-template <typename T, bool LEARNED, int SCHEME = 5, int WAVES = LEARNED_MAX_WAVES>
+template <typename T, bool LEARNED, int SCHEME = 5>
 __device__ __forceinline__ typename ReconOf<T, LEARNED, SCHEME>::type make_recon(const Grid& g, const MlpLane* mlp,
                                                                                bool valid)
 {
     if constexpr (LEARNED) {
-        static_assert(WAVES >= 1 && WAVES <= LEARNED_MAX_WAVES, "waves per block");
-        // one 4 KB slot per wave of the block
-        __shared__ LearnedLds slots[WAVES];
-        return ReconLearned{mlp[threadIdx.x & 63], &slots[threadIdx.x >> 6],
-                            Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u,
-                            g.edge_weights != 0};
+        return ReconLearned{mlp[threadIdx.x & 63], Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2},
+                            valid, 0u, g.edge_weights != 0};
     } else {
         (void)g;
         (void)mlp;
@@ -943,7 +935,7 @@ __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 2 : 1) sweep_yz
     GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CHK, !LEARNED, F> sink{
         OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid,
         CflAcc<F>{0.0, 0u, CHK == CHK_CFL}};
-    auto recon = make_recon<T, LEARNED, SCHEME, BLOCK / 64>(g, mlp, valid);
+    auto recon = make_recon<T, LEARNED, SCHEME>(g, mlp, valid);
     __shared__ T win[5][F::NV][BLOCK];
     LdsWindow<T, BLOCK, F::NV> W{&win[0][0][threadIdx.x], 0};
     march<DIR, T, F>(g, src, sink, recon, c0, c1, W);
@@ -1076,7 +1068,7 @@ __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* 
     LdsSrc<F> src{ibuf, qs, g.inflow_dev, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
     LdsSink<T, FIRST, MODE, F> sink{obuf, OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx,
                                     c0, c1};
-    auto recon = make_recon<T, LEARNED, SCHEME, XROWS / 64>(g, mlp, row0 + threadIdx.x < nrows);
+    auto recon = make_recon<T, LEARNED, SCHEME>(g, mlp, row0 + threadIdx.x < nrows);
     __shared__ T win[5][F::NV][XROWS];
     LdsWindow<T, XROWS, F::NV> W{&win[0][0][threadIdx.x], 0};
     march<0, T, F>(g, src, sink, recon, c0, c1, W);

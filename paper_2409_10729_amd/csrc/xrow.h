@@ -53,7 +53,7 @@ __global__ void __launch_bounds__(256) boundary_faces_x(Grid g, const double* __
             prim_of<T>(mixd, q, a[j]);
         }
     }
-    auto recon = make_recon<T, LEARNED, SCHEME, 4>(g, mlp, valid);  // 256 threads
+    auto recon = make_recon<T, LEARNED, SCHEME>(g, mlp, valid);
     const int sides = blo == BC_PERIODIC ? 1 : 2;  // periodic ends pair up
 #pragma unroll 1
     for (int side = 0; side < sides; ++side) {

@@ -5,9 +5,12 @@ bfloat16 operands, omega = softmax(ln omega_JS + z), the shared per-edge
 pooling and the per-edge Jiang-Shu fallback).
 
 What fixes each part without an implementation to compare with:
-  * GELU (tanh form): it approximates x Phi(x) to 5e-4 (Hendrycks & Gimpel's
-    approximation; wrong constants miss by 3e-3 or more), and
-    GELU(x) - GELU(-x) = x;
+  * GELU: the training form (tanh form) approximates x Phi(x) to 5e-4
+    (Hendrycks & Gimpel's approximation; wrong constants miss by 3e-3 or
+    more); the inference form (positive part minus a polynomial remainder)
+    stays within 1.2e-4 of the tanh form evaluated here with math.tanh, at
+    interior points and over [-20, 20] (a wrong coefficient or clamp misses
+    by 1e-3 or more); both satisfy GELU(x) - GELU(-x) = x;
   * the network: the C evaluation equals the numpy one of oracle.mlp (whose
     backward pass is pinned by finite differences); a zero output layer
     returns the baseline; logits from the last bias alone give the closed
@@ -45,15 +48,42 @@ def _rel(a, b, spec, q0):
     return np.abs(a - b).reshape(7, -1).max(axis=1) / flux_scale(q0, spec)
 
 
+def _gelu_tanh_here(v):
+    return 0.5 * v * (1.0 + math.tanh(math.sqrt(2.0 / math.pi) * (v + 0.044715 * v ** 3)))
+
+
 def test_gelu_approximates_x_phi():
     x = np.linspace(-8, 8, 4001)
     exact = np.array([v * 0.5 * (1.0 + math.erf(v / math.sqrt(2.0))) for v in x])
-    g = np.array([oracle.gelu(v) for v in x])
+    g = np.array([oracle.gelu_tanh(v) for v in x])
     assert np.abs(g - exact).max() <= 5e-4
-    np.testing.assert_allclose(g - np.array([oracle.gelu(-v) for v in x]), x, rtol=0, atol=1e-14)
+    np.testing.assert_allclose(g - np.array([oracle.gelu_tanh(-v) for v in x]), x, rtol=0, atol=1e-14)
     np.testing.assert_allclose(g, omlp.gelu(x), rtol=0, atol=1e-14)
+    np.testing.assert_allclose(g, [_gelu_tanh_here(v) for v in x], rtol=0, atol=1e-15)
     for v in (-1.0, -0.5, 0.5, 1.0):
-        assert abs(oracle.gelu(v) - v * 0.5 * (1.0 + math.erf(v / math.sqrt(2.0)))) <= 5e-4
+        assert abs(oracle.gelu_tanh(v) - v * 0.5 * (1.0 + math.erf(v / math.sqrt(2.0)))) <= 5e-4
+
+
+def test_inference_gelu_tracks_the_tanh_form():
+    """The inference GELU against the tanh form computed here: within
+    1.2e-4 everywhere (about 1/30 of a bfloat16 step at 1), the odd-part
+    identity exactly, the positive part beyond the clamp, and the numpy and
+    C evaluations alike."""
+    x = np.concatenate([np.linspace(-20, 20, 16001), [-3.75, 3.75, -1.0, -0.5, 0.5, 1.0, 0.0]])
+    g = np.array([oracle.gelu(v) for v in x])
+    ref = np.array([_gelu_tanh_here(v) for v in x])
+    assert np.abs(g - ref).max() <= 1.2e-4
+    for v in (-1.0, -0.5, 0.5, 1.0):
+        assert abs(oracle.gelu(v) - _gelu_tanh_here(v)) <= 1.2e-4
+        assert abs(oracle.gelu(v) - v * 0.5 * (1.0 + math.erf(v / math.sqrt(2.0)))) <= 6e-4
+    np.testing.assert_allclose(g - np.array([oracle.gelu(-v) for v in x]), x, rtol=0, atol=1e-14)
+    assert oracle.gelu(0.0) == 0.0
+    # beyond the clamp: x minus a constant for x > 3.75, the same constant below -3.75
+    tail = oracle.gelu(10.0) - 10.0
+    assert abs(tail) <= 1.2e-4
+    assert oracle.gelu(25.0) - 25.0 == pytest.approx(tail, abs=1e-14)
+    assert oracle.gelu(-10.0) == pytest.approx(tail, abs=1e-15)
+    np.testing.assert_allclose(omlp.gelu_inference(x), g, rtol=0, atol=1e-15)
 
 
 def _samples(n, seed):
