@@ -31,7 +31,7 @@ struct LaunchArgs {
     const double* dt_dev;
     double dt_arg;
     void* bface;             // boundary faces of the x row sweep (compute type)
-    const MlpLane* mlp;      // packed network (learned weights only)
+    const MlpNet* mlp;      // packed network (learned weights only)
     unsigned long long* fb;  // fallback counter (learned weights only)
     double* partial;         // CFL block maxima (stage-3 y/z sweep with cfl)
     unsigned* status;
@@ -49,7 +49,7 @@ struct XYArgs {
     const double* dt_dev;
     double dt_arg;
     void* bface;  // boundary faces of the x rows (compute type)
-    const MlpLane* mlp;
+    const MlpNet* mlp;
     unsigned long long* fb;
     int seg_override;  // segment length along y (0: automatic)
 };

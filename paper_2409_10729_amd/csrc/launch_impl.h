@@ -72,8 +72,6 @@ void launch_xy_mode(const XYArgs& a)
 {
     const Grid& g = *a.g;
     const long long rows = (long long)g.n[1] * g.n[2];
-    T* bf = static_cast<T*>(a.bface);
-    boundary_faces_x<T, false, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(g, a.qs, bf, a.mlp, a.fb);
     // segments along y as for the y sweep (lanes = x, blocks over z and segments)
     int seg = a.seg_override > 0 ? a.seg_override : 64;
     const long long pencils = (long long)g.n[0] * g.n[2];
@@ -81,8 +79,18 @@ void launch_xy_mode(const XYArgs& a)
     seg = std::min(seg, g.n[1]);
     const dim3 grid(1, (unsigned)g.n[2], (unsigned)((g.n[1] + seg - 1) / seg));
     const int block = 64 * ((g.n[0] + 63) / 64);
-    sweep_xy<T, MODE, SCHEME><<<grid, block, xrow_lds_bytes(g.n[0], sizeof(T)), a.st>>>(
-        g, a.qs, a.qn, static_cast<T*>(a.r), a.out, seg, bf, a.dt_dev, a.dt_arg);
+    // the blocks compute their rows' end faces when a segment's fit in LDS
+    // beside the row buffers; otherwise boundary_faces_x leaves them in bface
+    size_t lds = xrow_lds_bytes(g.n[0], sizeof(T));
+    T* bf = static_cast<T*>(a.bface);
+    if (seg <= XY_OWN_ROWS && lds + xy_own_face_bytes<T>() <= 64 * 1024) {
+        lds += xy_own_face_bytes<T>();
+        bf = nullptr;
+    } else {
+        boundary_faces_x<T, false, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(g, a.qs, bf, a.mlp, a.fb);
+    }
+    sweep_xy<T, MODE, SCHEME><<<grid, block, lds, a.st>>>(g, a.qs, a.qn, static_cast<T*>(a.r), a.out, seg, bf,
+                                                          a.dt_dev, a.dt_arg);
 }
 
 template <typename T, int SCHEME>

@@ -49,15 +49,26 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 // Input unit that k-slot i of K-step s feeds in lane half g (layers 2, 3).
 __host__ __device__ constexpr int mlp_kslot_unit(int s, int g, int i) { return 8 * (2 * s + i / 4) + 4 * g + i % 4; }
 
-// Per-lane slice of the network in matrix-core operand layout (packed once
-// by the pack kernel).  192 bytes per lane, 64 lanes.
-struct MlpLane {
-    bf16x4 a1;        // layer 1: row l%32, k = 4(l/32)..+3 of [W1 | b1 | 0 0]
-    bf16x8 a2[2];     // layer 2, K-step s: row l%32, k-slots 8(l/32)..+7
-    bf16x8 a3[2][2];  // layer 3 of tile h, K-step s: rows 4h..4h+2 hold W3, other rows zero
-    f32x16 c2;        // layer-2 bias in accumulator layout
-    float c3[3];      // layer-3 bias
-    float pad[5];
+// The network in matrix-core operand layout (packed once by the pack
+// kernel): MLP_WORDS 16-byte words per lane, stored word-major (word w of
+// lane l at w[w][l]), so a wave reads one word of all its lanes as one
+// contiguous kilobyte (no LDS bank conflicts, coalesced in global memory).
+constexpr int MW_A2 = 0;  // 2 words: layer-2 A operand, K-steps 0, 1 (row l%32, k-slots 8(l/32)..+7)
+constexpr int MW_A3 = 2;  // 4 words: layer-3 A operand of tile h, K-step s, at MW_A3 + 2h + s
+                          //          (rows 4h..4h+2 hold W3, other rows zero)
+constexpr int MW_C2 = 6;  // 4 words: layer-2 bias in accumulator layout (registers 4j..4j+3 in word j)
+constexpr int MW_A1 = 10; // 1 word: layer-1 A operand (row l%32, k = 4(l/32)..+3 of [W1 | b1 | 0 0]) in
+                          //         dwords 0-1, layer-3 bias 0 and 1 in dwords 2-3
+constexpr int MW_C3 = 11; // 1 word: layer-3 bias 2 in dword 0, then zeros
+constexpr int MLP_WORDS = 12;
+
+// (a plain vector type: bit casts to and from HIP's uint4 struct are not
+// reliable)
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+
+struct MlpNet {
+    u32x4 w[MLP_WORDS][64];
 };
 
 __device__ __forceinline__ short bf16_bits(float x) { return __builtin_bit_cast(short, (__bf16)x); }
@@ -97,38 +108,50 @@ __device__ __forceinline__ bf16x8 gelu8(const f32x16& acc, int r0)
 }
 
 // Logits z of the lane's own sample x[0..4] (features in [0, 1]); the whole
-// wave calls this together.
-__device__ __forceinline__ void mlp_logits(const MlpLane& m, const float x[5], float z[3])
+// wave calls this together.  net: the packed network (LDS or global).
+__device__ __forceinline__ void mlp_logits(const MlpNet& net, const float x[5], float z[3])
 {
     // one evaluation at a time: the scheduler would otherwise interleave the
     // matrix-core chains of many samples and run out of registers
     __builtin_amdgcn_sched_barrier(0);
+    const int lane = threadIdx.x & 63;
+    auto word = [&](int w) { return net.w[w][lane]; };
     // layer-1 operands of both tiles from the lanes' own features
     bf16v4 lo4 = {(__bf16)x[0], (__bf16)x[1], (__bf16)x[2], (__bf16)x[3]};
     bf16v4 hi4 = {(__bf16)x[4], (__bf16)1.0f, (__bf16)0.0f, (__bf16)0.0f};
-    typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
     const u32x2 lo = __builtin_bit_cast(u32x2, lo4), hi = __builtin_bit_cast(u32x2, hi4);
     const auto s0 = __builtin_amdgcn_permlane32_swap(lo[0], hi[0], false, false);
     const auto s1 = __builtin_amdgcn_permlane32_swap(lo[1], hi[1], false, false);
     const u32x2 t0 = {s0[0], s1[0]}, t1 = {s0[1], s1[1]};
     const bf16x4 b1[2] = {__builtin_bit_cast(bf16x4, t0), __builtin_bit_cast(bf16x4, t1)};
+    const u32x4 w10 = word(MW_A1);
+    const u32x2 a1w = {w10[0], w10[1]};
+    const bf16x4 a1 = __builtin_bit_cast(bf16x4, a1w);
     f32x16 acc3 = {};
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const f32x16 zero = {};
-        const f32x16 acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(m.a1, b1[h], zero, 0, 0, 0);
-        f32x16 acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, m.a2[0]),
-                                                              __builtin_bit_cast(bf16v8, gelu8(acc1, 0)), m.c2, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, m.a2[1]),
+        const f32x16 acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1, b1[h], zero, 0, 0, 0);
+        f32x16 c2;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const u32x4 cw = word(MW_C2 + j);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c2[4 * j + i] = __uint_as_float(cw[i]);
+        }
+        f32x16 acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, word(MW_A2)),
+                                                              __builtin_bit_cast(bf16v8, gelu8(acc1, 0)), c2, 0, 0, 0);
+        acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, word(MW_A2 + 1)),
                                                        __builtin_bit_cast(bf16v8, gelu8(acc1, 8)), acc2, 0, 0, 0);
-        acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, m.a3[h][0]),
+        acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, word(MW_A3 + 2 * h)),
                                                        __builtin_bit_cast(bf16v8, gelu8(acc2, 0)), acc3, 0, 0, 0);
-        acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, m.a3[h][1]),
+        acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, word(MW_A3 + 2 * h + 1)),
                                                        __builtin_bit_cast(bf16v8, gelu8(acc2, 8)), acc3, 0, 0, 0);
     }
-    z[0] = acc3[0] + m.c3[0];
-    z[1] = acc3[1] + m.c3[1];
-    z[2] = acc3[2] + m.c3[2];
+    const u32x4 w11 = word(MW_C3);
+    z[0] = acc3[0] + __uint_as_float(w10[2]);
+    z[1] = acc3[1] + __uint_as_float(w10[3]);
+    z[2] = acc3[2] + __uint_as_float(w11[0]);
     __builtin_amdgcn_sched_barrier(0);
 }
 
@@ -233,7 +256,7 @@ __device__ __forceinline__ void softmax3(const float z[3], const float lw[3], fl
 
 // Learned weights of the lane's own sample (the whole wave calls this
 // together): omega = softmax(z + ln omega_JS), lw the base-2 log-weights.
-__device__ __forceinline__ void mlp_omega(const MlpLane& m, const float x[5], const float lw[3], float om[3])
+__device__ __forceinline__ void mlp_omega(const MlpNet& m, const float x[5], const float lw[3], float om[3])
 {
     float z[3];
     mlp_logits(m, x, z);
@@ -243,7 +266,7 @@ __device__ __forceinline__ void mlp_omega(const MlpLane& m, const float x[5], co
 // Both edge values of one cell with learned weights (right edge: features
 // as computed; left edge: the mirrored stencil, i.e. features with beta0 and
 // beta2 swapped, weights applied to the mirrored candidates).
-__device__ __forceinline__ void weno5_learned(const MlpLane& m, float a, float b, float c, float d, float e,
+__device__ __forceinline__ void weno5_learned(const MlpNet& m, float a, float b, float c, float d, float e,
                                               float eps, float& left, float& right, bool& finite_r, bool& finite_l)
 {
     float x[5], xm[5], nlb[3], om[3], oml[3];

@@ -231,12 +231,12 @@ __global__ void __launch_bounds__(256) forward_f32_kernel(const float* __restric
 // bfloat16 matrix-core forward, exactly as the sweeps evaluate it.  Every
 // lane of every wave takes part (samples past n are computed on the last
 // sample and not stored).
-__global__ void __launch_bounds__(256) forward_mfma_kernel(const MlpLane* __restrict__ packed,
+__global__ void __launch_bounds__(256) forward_mfma_kernel(const MlpNet* __restrict__ packed,
                                                            const float* __restrict__ feat,
                                                            const float* __restrict__ ojs, long long n,
                                                            float* __restrict__ omega)
 {
-    const MlpLane m = packed[threadIdx.x & 63];
+    const MlpNet& m = *packed;
     const long long i_raw = (long long)blockIdx.x * 256 + threadIdx.x;
     const long long i = i_raw < n ? i_raw : n - 1;
     float x[5], lw[3], om[3];
@@ -247,33 +247,49 @@ __global__ void __launch_bounds__(256) forward_mfma_kernel(const MlpLane* __rest
         for (int k = 0; k < 3; ++k) omega[i * 3 + k] = om[k];
 }
 
-// Per-lane operand slices for the matrix-core evaluation (layouts in
-// learned.h).
-__global__ void __launch_bounds__(64) pack_kernel(const float* __restrict__ P, MlpLane* __restrict__ packed)
+// Operand words of the matrix-core evaluation (layouts in learned.h), one
+// thread per lane.
+__global__ void __launch_bounds__(64) pack_kernel(const float* __restrict__ P, MlpNet* __restrict__ packed)
 {
     const int l = threadIdx.x;
     const int row = l % 32, g = l / 32;
-    MlpLane m = {};
+    bf16x4 a1;
     for (int i = 0; i < 4; ++i) {
         const int k = 4 * g + i;  // layer-1 K index: 0..4 features, 5 bias, 6..7 zero
         float w1 = 0.f;
         if (k < 5) w1 = P[MLP_OFF_W1 + row * 5 + k];
         else if (k == 5) w1 = P[MLP_OFF_B1 + row];
-        m.a1[i] = bf16_bits(w1);
+        a1[i] = bf16_bits(w1);
     }
-    for (int s = 0; s < 2; ++s)
+    for (int s = 0; s < 2; ++s) {
+        bf16x8 a2, a3[2];
         for (int i = 0; i < 8; ++i) {
             const int u = mlp_kslot_unit(s, g, i);
-            m.a2[s][i] = bf16_bits(P[MLP_OFF_W2 + row * MLP_H + u]);
+            a2[i] = bf16_bits(P[MLP_OFF_W2 + row * MLP_H + u]);
             // tile h keeps W3 in rows 4h .. 4h+2
             for (int h = 0; h < 2; ++h) {
                 const int o = row - 4 * h;
-                m.a3[h][s][i] = bf16_bits(o >= 0 && o < 3 ? P[MLP_OFF_W3 + o * MLP_H + u] : 0.f);
+                a3[h][i] = bf16_bits(o >= 0 && o < 3 ? P[MLP_OFF_W3 + o * MLP_H + u] : 0.f);
             }
         }
-    for (int r = 0; r < 16; ++r) m.c2[r] = P[MLP_OFF_B2 + 8 * (r / 4) + 4 * g + (r % 4)];
-    for (int r = 0; r < 3; ++r) m.c3[r] = P[MLP_OFF_B3 + r];
-    packed[l] = m;
+        packed->w[MW_A2 + s][l] = __builtin_bit_cast(u32x4, a2);
+        for (int h = 0; h < 2; ++h) {
+            const bf16x8 t = a3[h];  // (bit casts take whole objects, not elements)
+            packed->w[MW_A3 + 2 * h + s][l] = __builtin_bit_cast(u32x4, t);
+        }
+    }
+    for (int j = 0; j < 4; ++j) {
+        float c[4];
+        for (int i = 0; i < 4; ++i) {
+            const int r = 4 * j + i;  // accumulator register r holds unit 8(r/4) + 4g + r%4
+            c[i] = P[MLP_OFF_B2 + 8 * (r / 4) + 4 * g + (r % 4)];
+        }
+        packed->w[MW_C2 + j][l] = u32x4{__float_as_uint(c[0]), __float_as_uint(c[1]), __float_as_uint(c[2]),
+                                        __float_as_uint(c[3])};
+    }
+    const u32x2 a1w = __builtin_bit_cast(u32x2, a1);
+    packed->w[MW_A1][l] = u32x4{a1w[0], a1w[1], __float_as_uint(P[MLP_OFF_B3]), __float_as_uint(P[MLP_OFF_B3 + 1])};
+    packed->w[MW_C3][l] = u32x4{__float_as_uint(P[MLP_OFF_B3 + 2]), 0u, 0u, 0u};
 }
 
 // Stage 1 of the gradient: each block of TB samples runs forward and
@@ -413,7 +429,7 @@ unsigned blocks_for(long long n, int per) { return (unsigned)((n + per - 1) / pe
 namespace mfx {
 int mlp_pack_on_stream(const float* params, void* packed, hipStream_t st)
 {
-    pack_kernel<<<1, 64, 0, st>>>(params, static_cast<MlpLane*>(packed));
+    pack_kernel<<<1, 64, 0, st>>>(params, static_cast<MlpNet*>(packed));
     return check_launch("pack_kernel");
 }
 }  // namespace mfx
@@ -422,7 +438,7 @@ extern "C" {
 
 const char* mfx_mlp_last_error(void) { return g_mlp_error.c_str(); }
 
-size_t mfx_mlp_packed_bytes(void) { return sizeof(MlpLane) * 64; }
+size_t mfx_mlp_packed_bytes(void) { return sizeof(MlpNet); }
 
 int mfx_mlp_sample_stencils(const mfx_grid_desc* desc, const double* q_dev, const double* face_prim_dev,
                             double* stencil_out, double* target_out, void* stream)
@@ -514,7 +530,7 @@ int mfx_mlp_forward(const float* params, const void* packed, const float* feat, 
         forward_f32_kernel<<<blocks_for(n, 256), 256, 0, (hipStream_t)stream>>>(params, feat, omega_js, n, omega);
     else
         forward_mfma_kernel<<<blocks_for(n, 256), 256, 0, (hipStream_t)stream>>>(
-            static_cast<const MlpLane*>(packed), feat, omega_js, n, omega);
+            static_cast<const MlpNet*>(packed), feat, omega_js, n, omega);
     return check_launch("mlp forward");
 }
 

@@ -159,7 +159,7 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     L.bface = off;
     off += align_up(elem * BFACE * 2 * (size_t)nrows);
     L.mlp = off;
-    off += align_up(sizeof(MlpLane) * 64);
+    off += align_up(sizeof(MlpNet));
     L.mlp_params = off;
     off += align_up(sizeof(float) * MLP_PARAMS);
     for (int k = 0; k < 3; ++k) {  // per-position tables of directions with unequal cells
@@ -568,7 +568,7 @@ struct mfx_ctx {
     double *q, *q1, *q2, *scal, *partial;
     void *r, *bface;  // compute-type buffers
     size_t elem;      // sizeof the compute type
-    MlpLane* mlp;                 // packed network operands (learned weights)
+    MlpNet* mlp;                  // packed network operands (learned weights)
     float* mlp_params;            // float32 copy of the network
     unsigned long long* fallback; // edges that fell back to Jiang-Shu
     bool has_mlp;
@@ -884,7 +884,7 @@ int mfx_init_grid(const mfx_grid_desc* desc, void* ws_dev, size_t ws_bytes, void
     c->status = reinterpret_cast<unsigned*>(c->ws + L.scal + 4 * sizeof(double));
     c->partial = reinterpret_cast<double*>(c->ws + L.partial);
     c->bface = c->ws + L.bface;
-    c->mlp = reinterpret_cast<MlpLane*>(c->ws + L.mlp);
+    c->mlp = reinterpret_cast<MlpNet*>(c->ws + L.mlp);
     c->mlp_params = reinterpret_cast<float*>(c->ws + L.mlp_params);
     c->fallback = reinterpret_cast<unsigned long long*>(c->ws + L.scal + 40);
     c->has_mlp = false;

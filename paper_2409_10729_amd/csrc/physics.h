@@ -156,8 +156,14 @@ __device__ __forceinline__ void weno5_js(T a, T b, T c, T d, T e, T eps, T& left
 
     const T wr0 = T(0.1) * t0, wr1 = T(0.6) * t1, wr2 = T(0.3) * t2;
     const T wl0 = T(0.3) * t0, wl1 = T(0.6) * t1, wl2 = T(0.1) * t2;
-    right = qdiv(wr0 * r0 + wr1 * r1 + wr2 * r2, T(6) * (wr0 + wr1 + wr2));
-    left = qdiv(wl0 * l0 + wl1 * l1 + wl2 * l2, T(6) * (wl0 + wl1 + wl2));
+    // one refined reciprocal of Dr Dl serves both quotients (the weights'
+    // products stay far inside the float64 range: (eps + beta)^2 products up
+    // to ~1e90 for pressure jumps of 1e11, down to ~1e-24 on flat data)
+    const T Nr = wr0 * r0 + wr1 * r1 + wr2 * r2, Dr = T(6) * (wr0 + wr1 + wr2);
+    const T Nl = wl0 * l0 + wl1 * l1 + wl2 * l2, Dl = T(6) * (wl0 + wl1 + wl2);
+    const T inv = qdiv(T(1), Dr * Dl);
+    right = Nr * (Dl * inv);
+    left = Nl * (Dr * inv);
 }
 
 // Same weights in the overflow-free ratio form for float32, where the

@@ -590,7 +590,7 @@ struct ReconJS<T, SCHEME_WENO5NU> {
 // before each cell: those a face of the launch uses, each distinct face
 // once (a face two segments both solve is counted by one of them).
 struct ReconLearned {
-    MlpLane m;
+    const MlpNet& m;  // the packed network (the block's LDS copy, or global memory)
     Mix<float> mix;
     bool valid;  // this lane owns a real cell (only those are counted)
     unsigned fallbacks;
@@ -618,14 +618,12 @@ struct ReconLearned {
     template <class Win>
     __device__ __forceinline__ void cell_edge(const Win& W, float eps, float lft[NV], float rgt[NV])
     {
-        float lj[NV], rj[NV];
         float f[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
         float wr[3] = {1.f, 1.f, 1.f}, wm[3] = {1.f, 1.f, 1.f};
         bool flat = true;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const float a = W(0, v), b = W(1, v), c = W(2, v), d = W(3, v), e = W(4, v);
-            weno5<float>(a, b, c, d, e, eps, lj[v], rj[v]);
             flat = flat && a == b && b == c && c == d && d == e;
             float x[5], o[3], om[3];
             edge_stats(a, b, c, d, e, eps, x, o, om);
@@ -638,11 +636,9 @@ struct ReconLearned {
             }
         }
         if (__all(flat)) {
+            // constant stencils reconstruct to their value under any convex weights
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                lft[v] = lj[v];
-                rgt[v] = rj[v];
-            }
+            for (int v = 0; v < NV; ++v) lft[v] = rgt[v] = W(2, v);
             return;
         }
         const float fm[5] = {f[2], f[1], f[0], f[3], f[4]};
@@ -653,25 +649,33 @@ struct ReconLearned {
         mlp_omega(m, fm, lwm, oml);
         const bool finR = isfinite(om[0] + om[1] + om[2]);
         const bool finL = isfinite(oml[0] + oml[1] + oml[2]);
-        float ll[NV], rl[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const float a = W(0, v), b = W(1, v), c = W(2, v), d = W(3, v), e = W(4, v);
-            weno5_apply(om, oml, a, b, c, d, e, ll[v], rl[v]);
+            weno5_apply(om, oml, a, b, c, d, e, lft[v], rgt[v]);
         }
-        finish(finR, finL, lj, rj, ll, rl, lft, rgt);
+        finish(W, eps, finR, finL, lft, rgt);
     }
 
-    // Fallback per edge and counting (both forms).
-    __device__ __forceinline__ void finish(bool finR, bool finL, const float lj[NV], const float rj[NV],
-                                           const float ll[NV], const float rl[NV], float lft[NV], float rgt[NV])
+    // Fallback per edge and counting (both forms): lft/rgt hold the learned
+    // edge states; an edge whose weights are not finite or whose state is
+    // not admissible takes the Jiang-Shu values of all its variables (the
+    // Jiang-Shu reconstruction runs only when some lane of the wave needs
+    // it).
+    template <class Win>
+    __device__ __forceinline__ void finish(const Win& W, float eps, bool finR, bool finL, float lft[NV], float rgt[NV])
     {
-        const bool okR = finR && admissible(mix, rl);
-        const bool okL = finL && admissible(mix, ll);
+        const bool okR = finR && admissible(mix, rgt);
+        const bool okL = finL && admissible(mix, lft);
+        if (__any(!(okR && okL))) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            rgt[v] = okR ? rl[v] : rj[v];
-            lft[v] = okL ? ll[v] : lj[v];
+            for (int v = 0; v < NV; ++v) {
+                float jl, jr;
+                weno5<float>(W(0, v), W(1, v), W(2, v), W(3, v), W(4, v), eps, jl, jr);
+                rgt[v] = okR ? rgt[v] : jr;
+                lft[v] = okL ? lft[v] : jl;
+                __builtin_amdgcn_sched_barrier(0);  // one variable at a time (registers)
+            }
         }
         if (valid) fallbacks += (okR || !cnt_r ? 0u : 1u) + (okL || !cnt_l ? 0u : 1u);
     }
@@ -679,26 +683,23 @@ struct ReconLearned {
     template <class Win>
     __device__ __forceinline__ void cell_var(const Win& W, float eps, float lft[NV], float rgt[NV])
     {
-        float lj[NV], rj[NV], ll[NV], rl[NV];
         bool finR = true, finL = true;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const float a = W(0, v), b = W(1, v), c = W(2, v), d = W(3, v), e = W(4, v);
-            weno5<float>(a, b, c, d, e, eps, lj[v], rj[v]);
             // A constant stencil reconstructs to its value under any convex
             // weights: where the whole wave has one, the network is skipped.
             const bool flat = a == b && b == c && c == d && d == e;
             if (__all(flat)) {
-                ll[v] = lj[v];
-                rl[v] = rj[v];
+                lft[v] = rgt[v] = c;
             } else {
                 bool fr, fl;
-                weno5_learned(m, a, b, c, d, e, eps, ll[v], rl[v], fr, fl);
+                weno5_learned(m, a, b, c, d, e, eps, lft[v], rgt[v], fr, fl);
                 finR = finR && fr;
                 finL = finL && fl;
             }
         }
-        finish(finR, finL, lj, rj, ll, rl, lft, rgt);
+        finish(W, eps, finR, finL, lft, rgt);
     }
     __device__ __forceinline__ void cell(const float W[5][NV], float eps, float lft[NV], float rgt[NV])
     {
@@ -727,13 +728,25 @@ struct ReconOf<float, true, 5> {
     using type = ReconLearned;
 };
 
-template <typename T, bool LEARNED, int SCHEME = 5>
-__device__ __forceinline__ typename ReconOf<T, LEARNED, SCHEME>::type make_recon(const Grid& g, const MlpLane* mlp,
+// SHARED: the block (every thread calls this) copies the packed network to
+// LDS and the evaluations read it there; otherwise they read it from global
+// memory (one-wave blocks, for which a 12 KB LDS copy per wave would cost
+// occupancy).  Either way it holds no registers across the march.
+template <typename T, bool LEARNED, int SCHEME = 5, bool SHARED = true>
+__device__ __forceinline__ typename ReconOf<T, LEARNED, SCHEME>::type make_recon(const Grid& g, const MlpNet* mlp,
                                                                                bool valid)
 {
-    if constexpr (LEARNED) {
-        return ReconLearned{mlp[threadIdx.x & 63], Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2},
-                            valid, 0u, g.edge_weights != 0};
+    if constexpr (LEARNED && !SHARED) {
+        return ReconLearned{*mlp, Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u,
+                            g.edge_weights != 0};
+    } else if constexpr (LEARNED) {
+        __shared__ MlpNet snet;
+        const u32x4* src = &mlp->w[0][0];
+        u32x4* dst = &snet.w[0][0];
+        for (int i = threadIdx.x; i < MLP_WORDS * 64; i += blockDim.x) dst[i] = src[i];
+        __syncthreads();
+        return ReconLearned{snet, Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u,
+                            g.edge_weights != 0};
     } else {
         (void)g;
         (void)mlp;
@@ -912,10 +925,10 @@ constexpr int yz_block()
 // (The learned passes keep the occupancy hint of two waves per SIMD: without
 // it the compiler schedules them for a higher occupancy they cannot reach.)
 template <int DIR, typename T, bool FIRST, int MODE, bool LEARNED, bool CFL = false, int SCHEME = 5, class F = Fl2>
-__global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 2 : 1) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
+__global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 3 : 1) sweep_yz(Grid g, const double* __restrict__ qs, const double* qn,
                                                    T* __restrict__ racc, double* out, int seg,
                                                    const double* __restrict__ dt_dev, double dt_arg,
-                                                   const MlpLane* __restrict__ mlp, unsigned long long* fb,
+                                                   const MlpNet* __restrict__ mlp, unsigned long long* fb,
                                                    double* __restrict__ partial, unsigned* __restrict__ status)
 {
     constexpr int BLOCK = yz_block<LEARNED>();
@@ -1055,7 +1068,7 @@ template <typename T, bool FIRST, int MODE, bool LEARNED, int SCHEME = 5, class 
 __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* __restrict__ qs, const double* qn,
                                                           T* __restrict__ racc, double* out, int seg,
                                                           const double* __restrict__ dt_dev, double dt_arg,
-                                                          const MlpLane* __restrict__ mlp, unsigned long long* fb)
+                                                          const MlpNet* __restrict__ mlp, unsigned long long* fb)
 {
     __shared__ double ibuf[XCHUNK][F::NV][XROWS];
     __shared__ T obuf[XCHUNK][F::NV + F::NA][XROWS];
@@ -1068,7 +1081,7 @@ __global__ void __launch_bounds__(XROWS, 2) sweep_x_march(Grid g, const double* 
     LdsSrc<F> src{ibuf, qs, g.inflow_dev, g.N, row0, nrows, nx, g.bc[0][0], g.bc[0][1], c0 - 3};
     LdsSink<T, FIRST, MODE, F> sink{obuf, OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, row0, nrows, nx,
                                     c0, c1};
-    auto recon = make_recon<T, LEARNED, SCHEME>(g, mlp, row0 + threadIdx.x < nrows);
+    auto recon = make_recon<T, LEARNED, SCHEME, false>(g, mlp, row0 + threadIdx.x < nrows);
     __shared__ T win[5][F::NV][XROWS];
     LdsWindow<T, XROWS, F::NV> W{&win[0][0][threadIdx.x], 0};
     march<0, T, F>(g, src, sink, recon, c0, c1, W);

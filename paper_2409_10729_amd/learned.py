@@ -418,8 +418,8 @@ def finetune(params, objective, iters=100, pairs=16, sigma=0.05, lr=0.05, seed=0
         shaped = ranks / (2 * pairs - 1) - 0.5
         g = np.zeros_like(base)
         g[lo:hi] = ((shaped[0::2] - shaped[1::2])[:, None] * eps).sum(axis=0) / (2 * pairs * sigma)
-        _native.check_mlp(L.mfx_mlp_adam(_p(theta), _p(mom), _p(var), _p(torch.from_numpy(g).cuda()), it,
-                                         ctypes.c_float(lr), _stream()))
+        g_dev = torch.from_numpy(g).cuda()  # held until the step has read it
+        _native.check_mlp(L.mfx_mlp_adam(_p(theta), _p(mom), _p(var), _p(g_dev), it, ctypes.c_float(lr), _stream()))
         base = theta.cpu().numpy()
         f = objective(theta)
         hist.append(f)

@@ -207,22 +207,31 @@ def test_zero_output_layer_reproduces_js_run():
 
 def test_uniform_state_skips_the_network():
     """A uniform state makes every stencil constant, so every wave skips the
-    network: the learned right-hand side equals the Jiang-Shu float form's
-    bit for bit, and both vanish to float rounding (the two x-boundary faces
-    of a row come from a separate kernel, whose multiply-adds the compiler may
-    fuse differently, so exact zeros are not guaranteed in float)."""
+    network and every edge takes the cell value (any convex weights give
+    it): with a network of NaNs nothing falls back and the right-hand side
+    of both learned forms vanishes to float rounding, as the Jiang-Shu float
+    form's does (the two x-boundary faces of a row come from a separate
+    kernel, whose multiply-adds the compiler may fuse differently, so exact
+    zeros are not guaranteed in float)."""
     n = (40, 24, 20)
     P = wl.random_smooth(n=n, seed=1, bc=((0, 0), (0, 0), (0, 0)))
     w = np.empty_like(P["w"])
     for v, val in enumerate((998.0, 0.0012, 12.0, -3.0, 0.5, 2.0e5, 0.999)):
         w[v] = val
     P = dict(P, w=w)
-    r_l = _solver(P, MFX_WENO5_LEARNED, omlp.init_params(2, out_scale=0.5)).rhs().cpu().numpy()
-    r_j = _solver(P, MFX_WENO5_JS).rhs().cpu().numpy()
-    assert np.array_equal(r_l, r_j)
     scale = 998.0 * (12.0 ** 2) * n[0] + 2.0e5 * n[0]  # momentum flux over dx
-    print("uniform state: max |rhs| =", np.abs(r_l).max(), "nonzero", np.count_nonzero(r_l), flush=True)
-    assert np.abs(r_l).max() <= 1e-6 * scale
+    nan_net = np.full(omlp.N_PARAMS, np.nan, dtype=np.float32)
+    r_j = _solver(P, MFX_WENO5_JS).rhs().cpu().numpy()
+    assert np.abs(r_j).max() <= 1e-6 * scale
+    for weights in (MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE):
+        s = _solver(P, weights, nan_net)
+        r_l = s.rhs().cpu().numpy()
+        st = s.stats()
+        print(f"uniform state, weights {weights}: max |rhs| = {np.abs(r_l).max():.3e}, "
+              f"fallback edges {st['fallback_faces']}", flush=True)
+        assert st["fallback_faces"] == 0 and st["error"] == 0
+        assert np.all(np.isfinite(r_l))
+        assert np.abs(r_l).max() <= 1e-6 * scale
 
 
 @pytest.mark.parametrize("nx", [72, 600])
@@ -397,13 +406,8 @@ def test_edge_form_nan_network_falls_back_and_uniform_state_skips():
     d = rel_linf(s_e.get_state().cpu().numpy(), s_j.get_state().cpu().numpy())
     print("edge form, nan network vs JS:", d, "fallback edges", st["fallback_faces"], flush=True)
     assert st["fallback_faces"] > 0 and st["error"] == 0 and np.all(d <= 1e-6)
-    w = np.empty_like(P["w"])
-    for v, val in enumerate((998.0, 0.0012, 12.0, -3.0, 0.5, 2.0e5, 0.999)):
-        w[v] = val
-    U = dict(P, w=w)
-    r_e = _solver(U, MFX_WENO5_LEARNED_EDGE, omlp.init_params(2, out_scale=0.5)).rhs().cpu().numpy()
-    r_j = _solver(U, MFX_WENO5_JS).rhs().cpu().numpy()
-    assert np.array_equal(r_e, r_j)
+    # (the uniform state, where the network is skipped, for both forms:
+    # test_uniform_state_skips_the_network)
 
 
 EDGE_TRAINED = os.path.join(os.path.dirname(TRAINED), "mlp_weno5_edge.npy")
