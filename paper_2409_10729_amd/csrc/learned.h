@@ -109,6 +109,10 @@ __device__ __forceinline__ bf16x8 gelu8(const f32x16& acc, int r0)
 
 // Logits z of the lane's own sample x[0..4] (features in [0, 1]); the whole
 // wave calls this together.  net: the packed network (LDS or global).
+// PIPE: the two tiles in step (each tile's activations on the vector units
+// while the other tile's matrix-core operation runs; about 14 more
+// registers), else one tile after the other.
+template <bool PIPE = true>
 __device__ __forceinline__ void mlp_logits(const MlpNet& net, const float x[5], float z[3])
 {
     // one evaluation at a time: the scheduler would otherwise interleave the
@@ -127,26 +131,38 @@ __device__ __forceinline__ void mlp_logits(const MlpNet& net, const float x[5], 
     const u32x4 w10 = word(MW_A1);
     const u32x2 a1w = {w10[0], w10[1]};
     const bf16x4 a1 = __builtin_bit_cast(bf16x4, a1w);
-    f32x16 acc3 = {};
+    f32x16 c2;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const f32x16 zero = {};
-        const f32x16 acc1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1, b1[h], zero, 0, 0, 0);
-        f32x16 c2;
+    for (int j = 0; j < 4; ++j) {
+        const u32x4 cw = word(MW_C2 + j);
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const u32x4 cw = word(MW_C2 + j);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) c2[4 * j + i] = __uint_as_float(cw[i]);
-        }
-        f32x16 acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, word(MW_A2)),
-                                                              __builtin_bit_cast(bf16v8, gelu8(acc1, 0)), c2, 0, 0, 0);
-        acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, word(MW_A2 + 1)),
-                                                       __builtin_bit_cast(bf16v8, gelu8(acc1, 8)), acc2, 0, 0, 0);
-        acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, word(MW_A3 + 2 * h)),
-                                                       __builtin_bit_cast(bf16v8, gelu8(acc2, 0)), acc3, 0, 0, 0);
-        acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, word(MW_A3 + 2 * h + 1)),
+        for (int i = 0; i < 4; ++i) c2[4 * j + i] = __uint_as_float(cw[i]);
+    }
+    const bf16v8 a2[2] = {__builtin_bit_cast(bf16v8, word(MW_A2)), __builtin_bit_cast(bf16v8, word(MW_A2 + 1))};
+    auto layer2 = [&](const f32x16& acc1) {
+        f32x16 acc2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[0], __builtin_bit_cast(bf16v8, gelu8(acc1, 0)), c2, 0,
+                                                              0, 0);
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a2[1], __builtin_bit_cast(bf16v8, gelu8(acc1, 8)), acc2, 0, 0,
+                                                       0);
+    };
+    auto layer3 = [&](const f32x16& acc2, int h, const f32x16& acc) {
+        f32x16 acc3 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, word(MW_A3 + 2 * h)),
+                                                              __builtin_bit_cast(bf16v8, gelu8(acc2, 0)), acc, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16v8, word(MW_A3 + 2 * h + 1)),
                                                        __builtin_bit_cast(bf16v8, gelu8(acc2, 8)), acc3, 0, 0, 0);
+    };
+    const f32x16 zero = {};
+    f32x16 acc3;
+    if constexpr (PIPE) {
+        const f32x16 acc1_0 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1, b1[0], zero, 0, 0, 0);
+        const f32x16 acc1_1 = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1, b1[1], zero, 0, 0, 0);
+        const f32x16 acc2_0 = layer2(acc1_0);
+        const f32x16 acc2_1 = layer2(acc1_1);
+        acc3 = layer3(acc2_0, 0, zero);
+        acc3 = layer3(acc2_1, 1, acc3);
+    } else {
+        acc3 = layer3(layer2(__builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1, b1[0], zero, 0, 0, 0)), 0, zero);
+        acc3 = layer3(layer2(__builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a1, b1[1], zero, 0, 0, 0)), 1, acc3);
     }
     const u32x4 w11 = word(MW_C3);
     z[0] = acc3[0] + __uint_as_float(w10[2]);
@@ -256,16 +272,18 @@ __device__ __forceinline__ void softmax3(const float z[3], const float lw[3], fl
 
 // Learned weights of the lane's own sample (the whole wave calls this
 // together): omega = softmax(z + ln omega_JS), lw the base-2 log-weights.
+template <bool PIPE = true>
 __device__ __forceinline__ void mlp_omega(const MlpNet& m, const float x[5], const float lw[3], float om[3])
 {
     float z[3];
-    mlp_logits(m, x, z);
+    mlp_logits<PIPE>(m, x, z);
     softmax3(z, lw, om);
 }
 
 // Both edge values of one cell with learned weights (right edge: features
 // as computed; left edge: the mirrored stencil, i.e. features with beta0 and
 // beta2 swapped, weights applied to the mirrored candidates).
+template <bool PIPE = true>
 __device__ __forceinline__ void weno5_learned(const MlpNet& m, float a, float b, float c, float d, float e,
                                               float eps, float& left, float& right, bool& finite_r, bool& finite_l)
 {
@@ -279,8 +297,8 @@ __device__ __forceinline__ void weno5_learned(const MlpNet& m, float a, float b,
     // mirrored stencil: indicators reversed, linear weights (0.1, 0.6, 0.3) kept
     const float lw[3] = {LOG2_D0 + nlb[0], LOG2_D1 + nlb[1], LOG2_D2 + nlb[2]};
     const float lwm[3] = {LOG2_D0 + nlb[2], LOG2_D1 + nlb[1], LOG2_D2 + nlb[0]};
-    mlp_omega(m, x, lw, om);
-    mlp_omega(m, xm, lwm, oml);
+    mlp_omega<PIPE>(m, x, lw, om);
+    mlp_omega<PIPE>(m, xm, lwm, oml);
     weno5_apply(om, oml, a, b, c, d, e, left, right);
     finite_r = isfinite(om[0] + om[1] + om[2]);
     finite_l = isfinite(oml[0] + oml[1] + oml[2]);

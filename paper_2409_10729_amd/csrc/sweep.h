@@ -589,6 +589,8 @@ struct ReconJS<T, SCHEME_WENO5NU> {
 // Fallbacks are counted for the edges the caller names with count_edges()
 // before each cell: those a face of the launch uses, each distinct face
 // once (a face two segments both solve is counted by one of them).
+// PIPE: evaluate the network's two tiles in step (see mlp_logits).
+template <bool PIPE = true>
 struct ReconLearned {
     const MlpNet& m;  // the packed network (the block's LDS copy, or global memory)
     Mix<float> mix;
@@ -645,8 +647,11 @@ struct ReconLearned {
         const float lw[3] = {log2f(wr[0]), log2f(wr[1]), log2f(wr[2])};
         const float lwm[3] = {log2f(wm[0]), log2f(wm[1]), log2f(wm[2])};
         float om[3], oml[3];
-        mlp_omega(m, f, lw, om);
-        mlp_omega(m, fm, lwm, oml);
+        mlp_omega<PIPE>(m, f, lw, om);
+        mlp_omega<PIPE>(m, fm, lwm, oml);
+        // the stencils are read again from the window (LDS) below rather than
+        // held in registers across the network evaluations
+        asm volatile("" ::: "memory");
         const bool finR = isfinite(om[0] + om[1] + om[2]);
         const bool finL = isfinite(oml[0] + oml[1] + oml[2]);
 #pragma unroll
@@ -694,7 +699,7 @@ struct ReconLearned {
                 lft[v] = rgt[v] = c;
             } else {
                 bool fr, fl;
-                weno5_learned(m, a, b, c, d, e, eps, lft[v], rgt[v], fr, fl);
+                weno5_learned<PIPE>(m, a, b, c, d, e, eps, lft[v], rgt[v], fr, fl);
                 finR = finR && fr;
                 finL = finL && fl;
             }
@@ -719,34 +724,34 @@ struct ReconLearned {
     }
 };
 
-template <typename T, bool LEARNED, int SCHEME = 5>
+template <typename T, bool LEARNED, int SCHEME = 5, bool PIPE = true>
 struct ReconOf {
     using type = ReconJS<T, SCHEME>;
 };
-template <>
-struct ReconOf<float, true, 5> {
-    using type = ReconLearned;
+template <bool PIPE>
+struct ReconOf<float, true, 5, PIPE> {
+    using type = ReconLearned<PIPE>;
 };
 
 // SHARED: the block (every thread calls this) copies the packed network to
 // LDS and the evaluations read it there; otherwise they read it from global
 // memory (one-wave blocks, for which a 12 KB LDS copy per wave would cost
 // occupancy).  Either way it holds no registers across the march.
-template <typename T, bool LEARNED, int SCHEME = 5, bool SHARED = true>
-__device__ __forceinline__ typename ReconOf<T, LEARNED, SCHEME>::type make_recon(const Grid& g, const MlpNet* mlp,
-                                                                               bool valid)
+template <typename T, bool LEARNED, int SCHEME = 5, bool SHARED = true, bool PIPE = true>
+__device__ __forceinline__ typename ReconOf<T, LEARNED, SCHEME, PIPE>::type make_recon(const Grid& g,
+                                                                                     const MlpNet* mlp, bool valid)
 {
     if constexpr (LEARNED && !SHARED) {
-        return ReconLearned{*mlp, Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u,
-                            g.edge_weights != 0};
+        return ReconLearned<PIPE>{*mlp, Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u,
+                                  g.edge_weights != 0};
     } else if constexpr (LEARNED) {
         __shared__ MlpNet snet;
         const u32x4* src = &mlp->w[0][0];
         u32x4* dst = &snet.w[0][0];
         for (int i = threadIdx.x; i < MLP_WORDS * 64; i += blockDim.x) dst[i] = src[i];
         __syncthreads();
-        return ReconLearned{snet, Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u,
-                            g.edge_weights != 0};
+        return ReconLearned<PIPE>{snet, Mix<float>{(float)g.G1, (float)g.G2, (float)g.P1, (float)g.P2}, valid, 0u,
+                                  g.edge_weights != 0};
     } else {
         (void)g;
         (void)mlp;

@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(XROW_THREADS) __attribute__((amdgpu_waves_per_
     inflow_slots_init<T>(g, mixd, gall & ginf, P, np, nx);
     const unsigned gmine = gall & ~ginf;  // slots this lane refills every row
 
-    auto recon = make_recon<T, LEARNED, SCHEME>(g, mlp, has);
+    auto recon = make_recon<T, LEARNED, SCHEME, true, false>(g, mlp, has);  // (tiles in turn: registers)
     double qc[NV];
     if (r0 < r1) {
 #pragma unroll
@@ -241,17 +241,23 @@ __global__ void __launch_bounds__(XROW_THREADS) __attribute__((amdgpu_waves_per_
             }
         }
         __syncthreads();
-        // prefetch the next row
-        if (row + 1 < r1) {
+        // prefetch the next row (with learned weights after the
+        // reconstruction: the loads would hold 14 registers across the
+        // network evaluations)
+        auto prefetch = [&]() {
+            if (row + 1 < r1) {
 #pragma unroll
-            for (int v = 0; v < NV; ++v) qc[v] = qs[v * g.N + (row + 1) * nx + xc];
-        }
+                for (int v = 0; v < NV; ++v) qc[v] = qs[v * g.N + (row + 1) * nx + xc];
+            }
+        };
+        if constexpr (!LEARNED) prefetch();
         // 2. reconstruct own cell (window read from the LDS row as it goes):
         // left edge to LDS, right edge kept
         T rgt[NV], lft[NV];
         // interior faces only: the row's end faces come from boundary_faces_x
         recon.count_edges(xc < nx - 1, xc > 0);
         recon.cell_win(RowWindow<T>{P + xc, np}, eps, lft, rgt);
+        if constexpr (LEARNED) prefetch();
         if (has) {
 #pragma unroll
             for (int v = 0; v < NV; ++v) L[v * nx + x] = lft[v];
