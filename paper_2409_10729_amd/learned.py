@@ -461,6 +461,80 @@ def calibrate(path: str, scale: float, command: str) -> int:
     return 0
 
 
+def _applied_scale(meta: dict) -> float:
+    """Product of the correction scales already applied to a saved network."""
+    f = 1.0
+    for c in meta.get("calibration", []):
+        f *= c["correction_scale"]
+    return f
+
+
+def density_l1(q, q64) -> float:
+    """sum |rho - rho64| / sum |rho64| with rho = alpha1 rho1 + alpha2 rho2."""
+    rho, rho64 = q[0] + q[1], q64[0] + q64[1]
+    return float(np.abs(rho - rho64).sum() / np.abs(rho64).sum())
+
+
+def select_strength(path: str, workload: str, n: int, seed: int, steps: int, strengths, bar: float,
+                    command: str, edge: bool = False, apply: bool = True) -> int:
+    """Choose the correction strength of a saved network on a problem other
+    than the one it is benchmarked on: for each strength s (relative to the
+    trained output layer), replay the FP64 run's time steps of `workload`
+    (n^3 cells, `seed`) with the learned weights at strength s and measure
+    the density L1 against the FP64 state; the largest s within `bar` is
+    applied to the network and recorded, with every measurement, in its
+    metadata (apply=False: measure only)."""
+    import torch
+
+    from . import MFX_FP32_MIXED, MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE
+
+    weights = MFX_WENO5_LEARNED_EDGE if edge else MFX_WENO5_LEARNED
+    mpath = os.path.splitext(path)[0] + ".json"
+    meta = {}
+    if os.path.exists(mpath):
+        with open(mpath) as f:
+            meta = json.load(f)
+    base = _applied_scale(meta)
+    p_now = np.load(path, allow_pickle=False).astype(np.float32)
+    lo, hi = OUT_LAYER
+    P = getattr(wl, workload)(n=n, seed=seed)
+    w_dev = torch.from_numpy(P["w"]).cuda()
+    s64 = Solver(P["spec"], MFX_FP64)
+    s64.set_primitive(w_dev)
+    dts = [s64.rk3_step(sync=True) for _ in range(steps)]
+    q64 = s64.get_state().cpu().numpy().reshape(7, -1)
+    s64.destroy()
+    l1 = {}
+    for st in strengths:
+        p = p_now.copy()
+        p[lo:hi] *= np.float32(st / base)
+        s = Solver(P["spec"], MFX_FP32_MIXED, weights)
+        s.set_mlp(torch.from_numpy(p).cuda())
+        s.set_primitive(w_dev)
+        for dt in dts:
+            s.rk3_step(dt)
+        l1[st] = density_l1(s.get_state().cpu().numpy().reshape(7, -1), q64)
+        s.destroy()
+        print(f"[select] strength {st}: density L1 {l1[st]:.3e}", flush=True)
+    ok = [st for st in strengths if l1[st] <= bar]
+    if not apply:
+        print(json.dumps({"workload": workload, "n": n, "seed": seed, "steps": steps,
+                          "density_l1": {str(k): v for k, v in l1.items()}, "within_bar": ok}), flush=True)
+        return 0
+    chosen = max(ok) if ok else min(strengths)
+    p = p_now.copy()
+    p[lo:hi] *= np.float32(chosen / base)
+    np.save(path, p)
+    meta["calibration"] = [{"correction_scale": chosen,
+                            "selected_on": {"workload": workload, "n": n, "seed": seed, "steps": steps, "bar": bar,
+                                            "density_l1": {str(k): v for k, v in l1.items()}},
+                            "command": command}]
+    with open(mpath, "w") as f:
+        json.dump(meta, f, indent=1)
+    print(json.dumps(meta["calibration"]), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--out", default=None, help="default: data/mlp_weno5.npy, or data/mlp_weno5_edge.npy with --edge")
@@ -479,9 +553,25 @@ def main(argv=None):
     ap.add_argument("--calibrate", type=float, default=None,
                     help="no training: scale the output layer of the existing --out network (the network's "
                          "correction to the Jiang-Shu log-weights is linear in it) by this factor and record it")
+    ap.add_argument("--select-strength", action="store_true",
+                    help="no training: choose the correction strength of the existing --out network on a held-out "
+                         "problem (--select-workload/-n/-seed/-steps) as the largest of --strengths whose density "
+                         "L1 against the FP64 path stays within --bar, apply it and record the measurements")
+    ap.add_argument("--select-workload", default="shock_droplet")
+    ap.add_argument("--select-n", type=int, default=256)
+    ap.add_argument("--select-seed", type=int, default=1)
+    ap.add_argument("--select-steps", type=int, default=200)
+    ap.add_argument("--strengths", default="1.0,0.9,0.8,0.7,0.6,0.5")
+    ap.add_argument("--bar", type=float, default=1e-4)
+    ap.add_argument("--measure-only", action="store_true", help="with --select-strength: report, change nothing")
     args = ap.parse_args(argv)
     if args.out is None:
         args.out = EDGE_PARAMS if args.edge else DEFAULT_PARAMS
+    cmd = "python -m paper_2409_10729_amd.learned " + " ".join(sys.argv[1:] if argv is None else argv)
+    if args.select_strength:
+        return select_strength(args.out, args.select_workload, args.select_n, args.select_seed, args.select_steps,
+                               [float(v) for v in args.strengths.split(",")], args.bar, cmd, edge=args.edge,
+                               apply=not args.measure_only)
     if args.calibrate is not None:
         return calibrate(args.out, args.calibrate,
                          "python -m paper_2409_10729_amd.learned " + " ".join(sys.argv[1:] if argv is None else argv))
