@@ -79,16 +79,9 @@ void launch_xy_mode(const XYArgs& a)
     seg = std::min(seg, g.n[1]);
     const dim3 grid(1, (unsigned)g.n[2], (unsigned)((g.n[1] + seg - 1) / seg));
     const int block = 64 * ((g.n[0] + 63) / 64);
-    // the blocks compute their rows' end faces when a segment's fit in LDS
-    // beside the row buffers; otherwise boundary_faces_x leaves them in bface
-    size_t lds = xrow_lds_bytes(g.n[0], sizeof(T));
     T* bf = static_cast<T*>(a.bface);
-    if (seg <= XY_OWN_ROWS && lds + xy_own_face_bytes<T>() <= 64 * 1024) {
-        lds += xy_own_face_bytes<T>();
-        bf = nullptr;
-    } else {
-        boundary_faces_x<T, false, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(g, a.qs, bf, a.mlp, a.fb);
-    }
+    boundary_faces_x<T, false, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(g, a.qs, bf, a.mlp, a.fb);
+    const size_t lds = xrow_lds_bytes(g.n[0], sizeof(T));
     sweep_xy<T, MODE, SCHEME><<<grid, block, lds, a.st>>>(g, a.qs, a.qn, static_cast<T*>(a.r), a.out, seg, bf,
                                                           a.dt_dev, a.dt_arg);
 }

@@ -305,52 +305,12 @@ __global__ void __launch_bounds__(XROW_THREADS) __attribute__((amdgpu_waves_per_
     recon.flush(fb);
 }
 
-// Flux and face velocity (F[0..NV-1], F[NV]) of the x face at one end of a
-// row (side 0: x = 0, side 1: x = nx), from the six cells whose stencils
-// reach it with the boundary rule applied (stencil positions -3..2 or
-// nx-3..nx+2): the right edge of the cell before the face and the left edge
-// of the cell after it, then HLLC.  Jiang-Shu-family reconstructions.
-template <typename T, int SCHEME>
-__device__ __forceinline__ void row_end_face(const Grid& g, const double* __restrict__ qs, long long row, int side,
-                                             T F[BFACE])
-{
-    const int nx = g.n[0], blo = g.bc[0][0], bhi = g.bc[0][1];
-    const Mix<double> mixd{g.G1, g.G2, g.P1, g.P2};
-    const Mix<T> mix{(T)g.G1, (T)g.G2, (T)g.P1, (T)g.P2};
-    T w[6][NV];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) {
-        const int pos = side == 0 ? k - 3 : nx - 3 + k;
-        const int cell = map_cell(pos, nx, blo, bhi);
-        double q[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) q[v] = qs[v * g.N + row * nx + cell];
-        prim_of<T>(mixd, q, w[k]);
-        if (special_ghost(pos, nx, blo, bhi)) ghost_fix<0, T>(g, mixd, pos, blo, bhi, w[k]);
-    }
-    ReconJS<T, SCHEME> recon{};
-    T wl[NV], wr[NV], dummy[NV];
-    recon.cell(w, (T)g.eps, dummy, wl);
-    recon.cell(w + 1, (T)g.eps, wr, dummy);
-    hllc<0, T>(mix, wl, wr, F, F[NV]);
-}
-
-// Rows of a segment whose end faces the fused pass computes itself (in LDS,
-// before its march; longer segments take them from boundary_faces_x).
-constexpr int XY_OWN_ROWS = 64;
-
-template <typename T>
-__host__ __device__ inline size_t xy_own_face_bytes() { return sizeof(T) * (size_t)XY_OWN_ROWS * 2 * BFACE; }
-
 // Fused x and y passes: a block of 64 * ceil(nx / 64) lanes owns whole x
 // rows of one z plane and marches along y over a segment (lane = x, as in
 // the y sweep).  When the march puts cell row j (window slot W(1)), the
 // block also computes that row's x contribution from the row's primitives,
 // which every lane already holds: the same three-barrier row procedure as
-// sweep_x_rows, with the row's end faces computed by the block before the
-// march (segments of up to XY_OWN_ROWS rows, so their loads meet the rows in
-// cache just before the march reads them) or, for longer segments, by
-// boundary_faces_x.  Each cell
+// sweep_x_rows, with the row's end faces from boundary_faces_x.  Each cell
 // then stores the sum (x part, then y part: the same additions in the same
 // order as the x pass followed by the y pass) once, so the state is read
 // once and the running sum never goes through memory.  The window lives in
@@ -363,8 +323,7 @@ struct XYSink {
     T* P;   // [NV][nx+4]
     T* L;   // [NV][nx]
     T* Fs;  // [BFACE][nx]
-    const T* bface;    // end faces [row - brow0][2][BFACE] (LDS or global)
-    long long brow0;
+    const T* bface;
     long long base_z;  // first cell of the z plane
     long long row_z;   // first row (k * ny) of the z plane
     int nx, np, x, xc;
@@ -414,7 +373,7 @@ struct XYSink {
             for (int v = 0; v < NV; ++v) wr[v] = L[v * nx + xr];
             T Fh[NV], ufh;
             hllc<0, T>(mix, rgt, wr, Fh, ufh);
-            const T* b = bface + ((row - brow0) * 2 + 1) * BFACE;
+            const T* b = bface + (row * 2 + 1) * BFACE;
             const bool last = xc == nx - 1;
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] = last ? b[v] : Fh[v];
@@ -428,7 +387,7 @@ struct XYSink {
         if (has) {
             T Fm[BFACE];
             if (x == 0) {
-                const T* b = bface + ((row - brow0) * 2 + 0) * BFACE;
+                const T* b = bface + (row * 2 + 0) * BFACE;
 #pragma unroll
                 for (int k = 0; k < BFACE; ++k) Fm[k] = b[k];
             } else {
@@ -469,36 +428,12 @@ __global__ void __launch_bounds__(XROW_THREADS) sweep_xy(Grid g, const double* _
     const int c1 = min(c0 + seg, ny);
     const long long base_z = (long long)z * g.stride[2];
 
-    // the segment's row-end faces, unless boundary_faces_x left them in bface
-    // (the host passes nullptr when the block computes them: segments of at
-    // most XY_OWN_ROWS rows, LDS after the row buffers)
-    const T* bf = bface;
-    long long brow0 = 0;
-    if (!bface) {
-        T* own = lds + lay.elems;
-        const int sides = g.bc[0][0] == BC_PERIODIC ? 1 : 2;  // periodic ends pair up
-        const int tasks = (c1 - c0) * sides;
-#pragma unroll 1
-        for (int t = threadIdx.x; t < tasks; t += blockDim.x) {
-            const int j = t / sides, side = t - j * sides;
-            T F[BFACE];
-            row_end_face<T, SCHEME>(g, qs, (long long)z * ny + c0 + j, side, F);
-            for (int o = side; o < 2; o += sides) {
-#pragma unroll
-                for (int k = 0; k < BFACE; ++k) own[(j * 2 + o) * BFACE + k] = F[k];
-            }
-        }
-        bf = own;
-        brow0 = (long long)z * ny + c0;  // the march's first row; its barriers order these writes before the reads
-    }
-
     GlobalSrc<1> src{qs, g.inflow_dev + 1 * 2 * NVMAX, base_z + xc, g.stride[1], g.N, ny, g.bc[1][0], g.bc[1][1]};
     XYSink<T, MODE, SCHEME> sink{OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg},
                          lds + lay.p,
                          lds + lay.l,
                          lds + lay.fs,
-                         bf,
-                         brow0,
+                         bface,
                          base_z,
                          (long long)z * ny,
                          nx,
