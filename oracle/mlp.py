@@ -22,11 +22,12 @@ Parameters, flat float vector of 1347: W1[32][5], b1[32], W2[32][32], b2[32],
 W3[3][32], b3[3].
 
 Shared (per-edge) form: one evaluation serves all variables of an edge.  Its
-input is the componentwise maximum over the variables of their features, its
-baseline the componentwise minimum over the variables of their Jiang-Shu
-weights, renormalised (the most cautious weights any variable asks for); the
-loss averages the squared normalised error over the variables.  A left edge
-is the right edge of the reversed stencils.
+input is the componentwise maximum over the variables of their features; its
+logits z correct every variable's own Jiang-Shu weights,
+omega_v = softmax(log omega_JS,v + z), so a zero output layer gives each
+variable its Jiang-Shu weights exactly; the loss averages the squared
+normalised error and the regulariser over the variables.  A left edge is the
+right edge of the reversed stencils.
 """
 from __future__ import annotations
 
@@ -115,49 +116,66 @@ def gelu_grad(x):
 
 
 def forward(theta, X, OJS):
-    """omega [n, 3] and the intermediates; OJS: Jiang-Shu weights [n, 3]."""
+    """omega and the intermediates.  OJS: Jiang-Shu weights [n, 3] (one
+    variable per sample; omega [n, 3]) or [n, V, 3] (shared form: the
+    sample's logits correct each of its V variables' weights; omega
+    [n, V, 3])."""
     p = unpack(theta)
     A1 = X @ p["W1"].T + p["b1"]
     H1 = gelu(A1)
     A2 = H1 @ p["W2"].T + p["b2"]
     H2 = gelu(A2)
-    Z = H2 @ p["W3"].T + p["b3"] + np.log(OJS)
-    Z = Z - Z.max(axis=1, keepdims=True)
+    Zn = H2 @ p["W3"].T + p["b3"]
+    OJS = np.asarray(OJS, dtype=np.float64)
+    Z = (Zn if OJS.ndim == 2 else Zn[:, None, :]) + np.log(OJS)
+    Z = Z - Z.max(axis=-1, keepdims=True)
     E = np.exp(Z)
-    om = E / E.sum(axis=1, keepdims=True)
+    om = E / E.sum(axis=-1, keepdims=True)
     return om, (X, A1, H1, A2, H2)
 
 
-def _per_var(C, T):
-    """Candidates [n,V,3] and targets [n,V] (a single variable may come as [n,3], [n])."""
+def _per_var(C, T, OJS):
+    """Candidates [n,V,3], targets [n,V] and baselines [n,V,3] (a single
+    variable may come as [n,3], [n]; a baseline [n,3] serves every variable
+    of its sample)."""
     C = np.asarray(C, dtype=np.float64)
     T = np.asarray(T, dtype=np.float64)
+    OJS = np.asarray(OJS, dtype=np.float64)
     if C.ndim == 2:
         C, T = C[:, None, :], T[:, None]
-    return C, T
+    if OJS.ndim == 2:
+        OJS = np.broadcast_to(OJS[:, None, :], C.shape)
+    return C, T, OJS
+
+
+def _loss_terms(om, C, T, OJS, lam):
+    om = om if om.ndim == 3 else om[:, None, :]
+    r = (om * C).sum(axis=2) - T
+    L = float(np.mean((r * r).mean(axis=1)) + lam * np.mean(((om - OJS) ** 2).sum(axis=2).mean(axis=1)))
+    return om, r, L
 
 
 def loss(theta, X, C, T, OJS, lam):
     """C: normalised candidates [n,3] or [n,V,3]; T: normalised targets [n] or
-    [n,V]; OJS: baseline (Jiang-Shu) weights [n,3].  The error term is the
-    mean over samples of the mean over variables of the squared error."""
-    C, T = _per_var(C, T)
+    [n,V]; OJS: baseline (Jiang-Shu) weights [n,3] or, per variable,
+    [n,V,3].  Error term: the mean over samples of the mean over variables of
+    the squared error; regulariser: lam times the mean over samples and
+    variables of |omega - omega_JS|^2."""
     om, _ = forward(theta, X, OJS)
-    r = (om[:, None, :] * C).sum(axis=2) - T
-    return float(np.mean((r * r).mean(axis=1)) + lam * np.mean(((om - OJS) ** 2).sum(axis=1)))
+    C, T, OJS = _per_var(C, T, OJS)
+    return _loss_terms(om, C, T, OJS, lam)[2]
 
 
 def loss_grad(theta, X, C, T, OJS, lam):
     """(loss, d loss / d theta) by reverse-mode differentiation."""
-    C, T = _per_var(C, T)
     p = unpack(theta)
-    n, nv = X.shape[0], C.shape[1]
     om, (X, A1, H1, A2, H2) = forward(theta, X, OJS)
-    r = (om[:, None, :] * C).sum(axis=2) - T
-    L = float(np.mean((r * r).mean(axis=1)) + lam * np.mean(((om - OJS) ** 2).sum(axis=1)))
-    dom = (2.0 / (n * nv)) * (r[:, :, None] * C).sum(axis=1) + (2.0 * lam / n) * (om - OJS)
-    # softmax backward
-    dZ = om * (dom - (dom * om).sum(axis=1, keepdims=True))
+    C, T, OJS = _per_var(C, T, OJS)
+    n, nv = X.shape[0], C.shape[1]
+    om, r, L = _loss_terms(om, C, T, OJS, lam)
+    dom = (2.0 / (n * nv)) * (r[:, :, None] * C) + (2.0 * lam / (n * nv)) * (om - OJS)
+    # softmax backward per variable; the variables share the logits
+    dZ = (om * (dom - (dom * om).sum(axis=2, keepdims=True))).sum(axis=1)
     g = {}
     g["W3"] = dZ.T @ H2
     g["b3"] = dZ.sum(axis=0)
@@ -175,13 +193,10 @@ def loss_grad(theta, X, C, T, OJS, lam):
 def edge_inputs(V, eps=1e-6):
     """Shared form: V [n, V, 5] holds every variable's stencil at one edge
     (right edge; pass the reversed stencils for a left edge).  Returns the
-    pooled features [n,5] (maximum over the variables) and the baseline
-    weights [n,3] (minimum over the variables of the Jiang-Shu weights,
-    renormalised)."""
+    pooled features [n,5] (maximum over the variables) and the variables'
+    own Jiang-Shu weights [n,V,3], the baselines the shared logits correct."""
     V = np.asarray(V, dtype=np.float64)
-    f = features(V, eps).max(axis=1)
-    w = js_weights_right(V, eps).min(axis=1)
-    return f, w / w.sum(axis=1, keepdims=True)
+    return features(V, eps).max(axis=1), js_weights_right(V, eps)
 
 
 def init_params(seed=0, out_scale=0.0):

@@ -645,9 +645,9 @@ void orc_cons_to_prim(const orc_grid* g, const double* q, double* w)
      per variable (mode 1): every variable and edge evaluates the network on
        its own stencil;
      shared per edge (mode 2): one evaluation per edge for all seven
-       variables, on the componentwise maximum of their features, and the
-       baseline the network corrects is the componentwise minimum of their
-       Jiang-Shu weights, renormalised.
+       variables, on the componentwise maximum of their features; its logits
+       correct each variable's own Jiang-Shu weights, so a zero output
+       layer is Jiang-Shu for every variable.
    Fallback per edge: if any weight of the edge is not finite, or its
    learned state (all seven primitives) is not admissible -- a negative
    partial density, alpha1 outside [0, 1], (Gamma + 1) p + Pi <= 0, or a
@@ -838,28 +838,28 @@ static void learned_cell(const orc_grid* g, const orc_learn* L, double st[NV][5]
             for (int k = 0; k < 5; ++k) X[1][v][k] = X[0][v][k];
     for (int side = 0; side < 2; ++side) {
         if (L->mode == 2) {
-            double f[5], base[3], z[3], om[3];
+            double f[5], z[3];
             for (int k = 0; k < 5; ++k) {
                 f[k] = X[side][0][k];
                 for (int v = 1; v < NV; ++v)
                     if (X[side][v][k] > f[k]) f[k] = X[side][v][k];
             }
-            double bs = 0.0;
-            for (int k = 0; k < 3; ++k) {
-                base[k] = O[side][0][k];
-                for (int v = 1; v < NV; ++v) {
-                    if (L->plant == 4)
-                        base[k] += O[side][v][k]; /* mistake: mean instead of minimum */
-                    else if (O[side][v][k] < base[k])
-                        base[k] = O[side][v][k];
-                }
-                bs += base[k];
-            }
-            for (int k = 0; k < 3; ++k) base[k] = base[k] / bs;
             mlp_logits(L->m, f, z);
-            fin[side] = corrected_weights(base, z, om);
-            for (int v = 0; v < NV; ++v)
+            double pooled[3], ps = 0.0;
+            if (L->plant == 4) { /* mistake: one baseline for all variables, their weights' minimum */
+                for (int k = 0; k < 3; ++k) {
+                    pooled[k] = O[side][0][k];
+                    for (int v = 1; v < NV; ++v)
+                        if (O[side][v][k] < pooled[k]) pooled[k] = O[side][v][k];
+                    ps += pooled[k];
+                }
+                for (int k = 0; k < 3; ++k) pooled[k] /= ps;
+            }
+            for (int v = 0; v < NV; ++v) {
+                double om[3];
+                fin[side] = corrected_weights(L->plant == 4 ? pooled : O[side][v], z, om) && fin[side];
                 val[side][v] = om[0] * C[side][v][0] + om[1] * C[side][v][1] + om[2] * C[side][v][2];
+            }
         } else {
             for (int v = 0; v < NV; ++v) {
                 double z[3], om[3];
@@ -1020,8 +1020,9 @@ void orc_rhs(const orc_grid* g, const double* q, double* rhs) { rhs_impl(g, q, r
    deliberate mistake to show what the comparisons catch: 1 the left edge
    takes the unreversed stencil's features, 2 the two edges exchanged, 3 the
    fallback per variable (only the variables that fail their own test take
-   the Jiang-Shu value) instead of per edge, 4 the shared baseline the mean
-   of the Jiang-Shu weights instead of their minimum. */
+   the Jiang-Shu value) instead of per edge, 4 the shared logits applied to
+   one baseline for all variables (the renormalised componentwise minimum
+   of their Jiang-Shu weights) instead of to each variable's own. */
 void orc_rhs_learned(const orc_grid* g, const double* q, const double* theta, int mode, int plant, double* rhs,
                      int64_t* counts)
 {

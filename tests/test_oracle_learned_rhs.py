@@ -15,10 +15,13 @@ What fixes each part without an implementation to compare with:
     backward pass is pinned by finite differences); a zero output layer
     returns the baseline; logits from the last bias alone give the closed
     softmax;
-  * a zero output layer reproduces the Jiang-Shu right-hand side (per
-    variable), and so does the shared form on a state whose seven
-    primitives are affine images of one profile (identical features and
-    weights in every variable);
+  * a zero output layer reproduces the Jiang-Shu right-hand side in both
+    forms; a network whose logits are its last bias alone (no dependence on
+    the features) gives the same right-hand side in both forms, since the
+    shared logits correct each variable's own Jiang-Shu weights; on a state
+    whose seven primitives are affine images of one profile (identical
+    features and weights in every variable) the two forms agree for any
+    network;
   * a network of NaNs makes every edge fall back: the Jiang-Shu right-hand
     side bit for bit, with the closed-form count of edges;
   * mirror symmetry (the left edge is the reversed stencil's right edge),
@@ -120,12 +123,30 @@ PROBLEMS = {
 }
 
 
+@pytest.mark.parametrize("mode", [PER_VAR, SHARED])
 @pytest.mark.parametrize("name", sorted(PROBLEMS))
-def test_zero_output_layer_is_jiang_shu(name):
+def test_zero_output_layer_is_jiang_shu(name, mode):
     P = PROBLEMS[name]()
     g, q0 = _q0(P)
-    r, fb, _ = oracle.rhs_learned(g, q0, omlp.init_params(5), PER_VAR)
+    r, fb, _ = oracle.rhs_learned(g, q0, omlp.init_params(5), mode)
     assert np.all(_rel(r, oracle.rhs(g, q0), P["spec"], q0) <= 1e-13)
+
+
+@pytest.mark.parametrize("name", sorted(PROBLEMS))
+def test_feature_free_logits_agree_in_both_forms(name):
+    """Logits from the last bias alone are the same on every edge and
+    variable, so the shared form (its logits applied to each variable's own
+    Jiang-Shu weights) equals the per-variable form."""
+    P = PROBLEMS[name]()
+    g, q0 = _q0(P)
+    p = omlp.unpack(omlp.init_params(13))
+    p["b3"] = np.array([0.6, -0.3, 0.2])
+    th = omlp.pack(p).astype(np.float32)
+    r1, fb1, _ = oracle.rhs_learned(g, q0, th, PER_VAR)
+    r2, fb2, _ = oracle.rhs_learned(g, q0, th, SHARED)
+    assert np.all(_rel(r2, r1, P["spec"], q0) <= 1e-13) and fb1 == fb2
+    if name != "tube":  # (the tube's edges are flat or at a bare jump, where the bias barely acts)
+        assert _rel(r1, oracle.rhs(g, q0), P["spec"], q0).max() > 1e-6  # the bias moves the result
 
 
 def _affine_state(n=96):
@@ -141,15 +162,16 @@ def _affine_state(n=96):
     return spec, w.reshape(7, 1, 1, n)
 
 
-def test_shared_form_on_an_affine_state_is_jiang_shu():
+def test_shared_form_on_an_affine_state_is_the_per_variable_form():
     spec, w = _affine_state()
     g = oracle.make_grid(spec)
     q0 = oracle.prim_to_cons(g, w)
-    r, _, _ = oracle.rhs_learned(g, q0, omlp.init_params(6), SHARED)
-    assert np.all(_rel(r, oracle.rhs(g, q0), spec, q0) <= 1e-12)
-    # and a non-zero network moves it (the form is live)
-    r1, _, _ = oracle.rhs_learned(g, q0, omlp.init_params(6, out_scale=0.5), SHARED)
-    assert _rel(r1, r, spec, q0).max() > 1e-6
+    th = omlp.init_params(6, out_scale=0.5)
+    r, _, _ = oracle.rhs_learned(g, q0, th, SHARED)
+    r1, _, _ = oracle.rhs_learned(g, q0, th, PER_VAR)
+    assert np.all(_rel(r, r1, spec, q0) <= 1e-12)
+    # and the network moves it (the form is live)
+    assert _rel(r, oracle.rhs(g, q0), spec, q0).max() > 1e-6
 
 
 def _edges(spec):
@@ -251,7 +273,7 @@ PLANTS = {
     1: (PER_VAR, "droplet", "random"),   # left edge with the unreversed stencil's features
     2: (PER_VAR, "smooth", "zero"),      # left and right edges exchanged
     3: (PER_VAR, "droplet", "steered"),  # fallback per variable, not per edge
-    4: (SHARED, "droplet", "random"),    # shared baseline: mean instead of minimum
+    4: (SHARED, "droplet", "random"),    # shared logits on one pooled baseline, not each variable's own
 }
 
 

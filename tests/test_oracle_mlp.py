@@ -130,12 +130,13 @@ def test_edge_inputs_of_identical_variables_are_the_single_variable_ones():
     V1 = rng.normal(size=(50, 5)) * 2.0
     f, B = mlp.edge_inputs(np.repeat(V1[:, None, :], 7, axis=1))
     np.testing.assert_array_equal(f, mlp.features(V1))
-    np.testing.assert_allclose(B, mlp.js_weights_right(V1), rtol=1e-15)
+    for v in range(7):
+        np.testing.assert_allclose(B[:, v], mlp.js_weights_right(V1), rtol=1e-15)
 
 
-def test_edge_inputs_pool_by_max_and_min():
-    """Features are the componentwise maxima; the baseline is the normalised
-    componentwise minimum of the weights; flat variables contribute zero
+def test_edge_inputs_pool_features_by_max_and_keep_each_baseline():
+    """Features are the componentwise maxima; each variable keeps its own
+    Jiang-Shu weights as the baseline; flat variables contribute zero
     features and the linear weights (1/10, 6/10, 3/10)."""
     rng = np.random.default_rng(5)
     V = rng.normal(size=(40, 3, 5))
@@ -146,11 +147,26 @@ def test_edge_inputs_pool_by_max_and_min():
     assert np.array_equal(X[:, 1], np.zeros((40, 5)))
     np.testing.assert_allclose(W[:, 1], np.broadcast_to([0.1, 0.6, 0.3], (40, 3)), rtol=1e-12)
     np.testing.assert_array_equal(f, np.maximum(np.maximum(X[:, 0], X[:, 1]), X[:, 2]))
-    m = np.minimum(np.minimum(W[:, 0], W[:, 1]), W[:, 2])
-    np.testing.assert_allclose(B, m / m.sum(axis=1, keepdims=True), rtol=1e-15)
+    np.testing.assert_array_equal(B, W)
     # mirrored edge: the reversed stencils swap beta0 and beta2
     fm, _ = mlp.edge_inputs(V[:, :, ::-1])
     np.testing.assert_allclose(fm, f[:, [2, 1, 0, 3, 4]], rtol=1e-15)
+
+
+def test_shared_logits_correct_each_variable():
+    """Shared form: a zero output layer gives every variable its own
+    Jiang-Shu weights; logits from the last bias b alone give each variable
+    softmax(log omega_JS,v + b)."""
+    rng = np.random.default_rng(6)
+    V = rng.normal(size=(30, 7, 5)) * rng.uniform(0.1, 10.0, size=(30, 7, 1))
+    f, B = mlp.edge_inputs(V)
+    om, _ = mlp.forward(mlp.init_params(2), f, B)
+    np.testing.assert_allclose(om, B, rtol=1e-14)
+    p = mlp.unpack(mlp.init_params(2))
+    p["b3"] = np.array([0.7, -0.2, 0.4])
+    om, _ = mlp.forward(mlp.pack(p), f, B)
+    e = B * np.exp(p["b3"])
+    np.testing.assert_allclose(om, e / e.sum(axis=2, keepdims=True), rtol=1e-14)
 
 
 def test_single_variable_loss_is_the_one_variable_case():
