@@ -91,9 +91,8 @@ enum { MFX_FP64 = 0, MFX_FP32_MIXED = 1 };
  * weights leave the convex set or the face state fails a positivity check;
  * one evaluation per variable and edge.  MFX_WENO5_LEARNED_EDGE: the same
  * network evaluated once per edge for all seven variables, on the
- * componentwise maximum of the variables' features and correcting the
- * componentwise minimum of their Jiang-Shu weights (renormalised); same
- * fallback.  Both learned modes run in the MFX_FP32_MIXED form.
+ * componentwise maximum of the variables' features; its logits correct each
+ * variable's own Jiang-Shu weights; same fallback.  Both learned modes run in the MFX_FP32_MIXED form.
  * MFX_WENO5_Z: WENO-Z weights (Borges, Carmona, Costa & Don 2008, exponent
  * 1), alpha_k = d_k (1 + |beta_0 - beta_2| / (beta_k + eps)), a comparison
  * form for the learned weights; any precision form. */
@@ -237,10 +236,14 @@ int mfx_stats(mfx_ctx* ctx, double* t, int64_t* step, int64_t* fallback_faces, u
  * WENO5 of Sec. II-B) and S = beta0 + beta1 + beta2 + eps:
  *   (beta0/S, beta1/S, beta2/S, |beta0 - beta2|/S, D^2/(S + D^2)),
  *   D = w0 - 4 w1 + 6 w2 - 4 w3 + w4
- * -- through 5 -> 32 (GELU, tanh form) -> 32 (GELU) -> 3 logits z, which
- * correct the Jiang-Shu weights of the third-order candidates:
+ * -- through 5 -> 32 (GELU) -> 32 (GELU) -> 3 logits z, which correct the
+ * Jiang-Shu weights of the third-order candidates:
  *   omega = softmax(ln omega_JS + z)
- * (a zero output layer reproduces Jiang-Shu exactly).  Parameters: 1347
+ * (a zero output layer reproduces Jiang-Shu exactly).  GELU is trained in
+ * its tanh form, a (1 + tanh(sqrt(2/pi) (a + 0.044715 a^3))) / 2, and
+ * evaluated at inference as max(a, 0) - t Q(t), t = min(|a|, 3.75), with Q
+ * a degree-6 minimax fit of the tanh form's remainder (within 1.2e-4 of the
+ * tanh form; the inference operands are bfloat16).  Parameters: 1347
  * float32, layout of mfx_set_mlp.  A left edge is the right edge of the
  * mirrored stencil.  These calls are not bound to a context; all pointers
  * are device pointers, work is enqueued on `stream` (hipStream_t as void*,
@@ -278,17 +281,20 @@ int mfx_mlp_features(const double* stencils, const double* targets, int64_t n, d
 /* Shared (per-edge) form: samples of a 1D sample set as
  * mfx_mlp_sample_stencils lays it out (stencils [14*ncell][5], targets
  * [14*ncell]).  Sample j = side*ncell + i (j < 2*ncell) gets feat[j][5] =
- * componentwise maximum over the seven variables of their features,
- * omega_base[j][3] = their componentwise minimum Jiang-Shu weights,
- * renormalised, and per variable cand[j][7][3], tnorm[j][7] normalised as
- * in mfx_mlp_features; a variable with a flat stencil or with
- * |tnorm| > tmax contributes zeros. */
+ * componentwise maximum over the seven variables of their features, and per
+ * variable omega_base[j][7][3] = its Jiang-Shu weights, cand[j][7][3],
+ * tnorm[j][7] normalised as in mfx_mlp_features; a variable with a flat
+ * stencil or with |tnorm| > tmax contributes zero candidates and target. */
 int mfx_mlp_features_edge(const double* stencils, const double* targets, int64_t ncell, double eps, double tmax,
                           float* feat, float* cand, float* tnorm, float* omega_base, void* stream);
 
 /* Bytes of the packed bfloat16 matrix-core operands (mfx_mlp_pack). */
 size_t mfx_mlp_packed_bytes(void);
-/* Pack float32 parameters into the per-lane bfloat16 operand layout. */
+/* Pack float32 parameters into the matrix-core operand words: for each of
+ * the 64 lanes of a wave, its bfloat16 A-operand fragments of the three
+ * layers and its float32 bias registers, stored word-major (word w of
+ * every lane contiguous) so that a wave reads each word as one contiguous
+ * kilobyte. */
 int mfx_mlp_pack(const float* params, void* packed, void* stream);
 
 /* Network weights omega[n][3] for features feat[n][5] and Jiang-Shu
@@ -300,10 +306,11 @@ int mfx_mlp_forward(const float* params, const void* packed, const float* feat, 
 
 /* Loss and gradient of one minibatch, float32, deterministic (per-block
  * sums in a fixed order, then a fixed-order sum over blocks), with nvar
- * (1, or 7 for the shared form) variables per sample sharing its weights:
- *   L = mean_i (1/nvar) sum_v (sum_k omega_ik cand_ivk - tnorm_iv)^2
- *     + lambda * mean_i sum_k (omega_ik - omega_js_ik)^2,
- * cand[n][nvar][3], tnorm[n][nvar].  grad_out[1347]; loss_out (device
+ * (1, or 7 for the shared form) variables per sample sharing its logits z,
+ * each correcting its own baseline: omega_iv = softmax(ln omega_js_iv + z_i),
+ *   L = mean_i (1/nvar) sum_v [ (sum_k omega_ivk cand_ivk - tnorm_iv)^2
+ *                               + lambda sum_k (omega_ivk - omega_js_ivk)^2 ],
+ * cand and omega_js [n][nvar][3], tnorm[n][nvar].  grad_out[1347]; loss_out (device
  * float, may be NULL); ws of at least mfx_mlp_grad_workspace(n) bytes. */
 size_t mfx_mlp_grad_workspace(int64_t n);
 int mfx_mlp_loss_grad(const float* params, const float* feat, const float* cand, const float* tnorm,

@@ -209,12 +209,8 @@ __device__ __forceinline__ void weno_features(float a, float b, float c, float d
     nlb[2] = -2.0f * log2f(eps + b2);
 }
 
-// Shared form, per variable: the features (as above) and the normalised
-// Jiang-Shu weights of the right edge (o) and of the mirrored left edge
-// (om, in the mirrored candidates' order), in the overflow-free ratio form
-// d_k (min_j s_j / s_k)^2, s_k = eps + beta_k.
-__device__ __forceinline__ void edge_stats(float a, float b, float c, float d, float e, float eps, float x[5],
-                                           float o[3], float om[3])
+// Features of the stencil a..e (as weno_features) and its indicators.
+__device__ __forceinline__ void edge_features(float a, float b, float c, float d, float e, float eps, float x[5])
 {
     float b0, b1, b2, D;
     weno_betas(a, b, c, d, e, b0, b1, b2, D);
@@ -225,6 +221,21 @@ __device__ __forceinline__ void edge_stats(float a, float b, float c, float d, f
     x[2] = b2 * iS;
     x[3] = fabsf(b0 - b2) * iS;
     x[4] = D * D * __builtin_amdgcn_rcpf(S + D * D);
+}
+
+// Shared form, per variable: the learned weights of the right edge (om)
+// and of the mirrored left edge (oml, in the mirrored candidates' order)
+// from the edge's exponentiated logits er, el (each exp(z - max z)):
+// omega_k proportional to omega_JS,k exp(z_k), with the Jiang-Shu weights
+// in the overflow-free ratio form d_k (min_j s_j / s_k)^2, s_k = eps +
+// beta_k (their normalisation cancels).  fin_r, fin_l: the weights are
+// finite.
+__device__ __forceinline__ void shared_weights(float a, float b, float c, float d, float e, float eps,
+                                               const float er[3], const float el[3], float om[3], float oml[3],
+                                               bool& fin_r, bool& fin_l)
+{
+    float b0, b1, b2, D;
+    weno_betas(a, b, c, d, e, b0, b1, b2, D);
     const float s0 = eps + b0, s1 = eps + b1, s2 = eps + b2;
     const float smin = fminf(s0, fminf(s1, s2));
     float q0 = smin * __builtin_amdgcn_rcpf(s0), q1 = smin * __builtin_amdgcn_rcpf(s1),
@@ -232,14 +243,18 @@ __device__ __forceinline__ void edge_stats(float a, float b, float c, float d, f
     q0 *= q0;
     q1 *= q1;
     q2 *= q2;
-    const float ir = __builtin_amdgcn_rcpf(0.1f * q0 + 0.6f * q1 + 0.3f * q2);
-    o[0] = 0.1f * q0 * ir;
-    o[1] = 0.6f * q1 * ir;
-    o[2] = 0.3f * q2 * ir;
-    const float im = __builtin_amdgcn_rcpf(0.1f * q2 + 0.6f * q1 + 0.3f * q0);
-    om[0] = 0.1f * q2 * im;
-    om[1] = 0.6f * q1 * im;
-    om[2] = 0.3f * q0 * im;
+    const float r0 = 0.1f * q0 * er[0], r1 = 0.6f * q1 * er[1], r2 = 0.3f * q2 * er[2];
+    const float ir = __builtin_amdgcn_rcpf(r0 + r1 + r2);
+    om[0] = r0 * ir;
+    om[1] = r1 * ir;
+    om[2] = r2 * ir;
+    const float m0 = 0.1f * q2 * el[0], m1 = 0.6f * q1 * el[1], m2 = 0.3f * q0 * el[2];
+    const float im = __builtin_amdgcn_rcpf(m0 + m1 + m2);
+    oml[0] = m0 * im;
+    oml[1] = m1 * im;
+    oml[2] = m2 * im;
+    fin_r = isfinite(ir);
+    fin_l = isfinite(im);
 }
 
 // Both edge values of the stencil a..e with the right edge's weights om
@@ -268,6 +283,17 @@ __device__ __forceinline__ void softmax3(const float z[3], const float lw[3], fl
     om[0] = e0 * inv;
     om[1] = e1 * inv;
     om[2] = e2 * inv;
+}
+
+// exp(z_k - max z) of three logits (finite logits give values in (0, 1],
+// the largest exactly 1; a non-finite logit makes them NaN).
+__device__ __forceinline__ void exp_logits(const float z[3], float ez[3])
+{
+    constexpr float LOG2E = 1.4426950408889634f;
+    const float zm = fmaxf(z[0], fmaxf(z[1], z[2]));
+    ez[0] = exp2f((z[0] - zm) * LOG2E);
+    ez[1] = exp2f((z[1] - zm) * LOG2E);
+    ez[2] = exp2f((z[2] - zm) * LOG2E);
 }
 
 // Learned weights of the lane's own sample (the whole wave calls this

@@ -134,10 +134,10 @@ __global__ void __launch_bounds__(256) features_kernel(const double* __restrict_
 // Shared form: one sample per (side, cell) of a 1D sample set laid out as
 // mfx_mlp_sample_stencils writes it (stencil (side*7 + v)*ncell + i).
 // Sample j = side*ncell + i gets the componentwise maximum of the seven
-// variables' features, the normalised componentwise minimum of their
-// Jiang-Shu weights, and per variable the stencil-normalised candidates and
-// target; a variable whose stencil is flat, or whose normalised target lies
-// more than `tmax` from the stencil value, contributes zeros.
+// variables' features and per variable its Jiang-Shu weights (base[j][v]),
+// stencil-normalised candidates and target; a variable whose stencil is
+// flat, or whose normalised target lies more than `tmax` from the stencil
+// value, contributes zero candidates and target.
 __global__ void __launch_bounds__(256) features_edge_kernel(const double* __restrict__ st,
                                                             const double* __restrict__ tg, long long ncell, double eps,
                                                             double tmax, float* __restrict__ feat,
@@ -147,7 +147,7 @@ __global__ void __launch_bounds__(256) features_edge_kernel(const double* __rest
     const long long j = (long long)blockIdx.x * 256 + threadIdx.x;
     if (j >= 2 * ncell) return;
     const long long side = j / ncell, i = j % ncell;
-    double f[5] = {0, 0, 0, 0, 0}, wmin[3] = {1, 1, 1};
+    double f[5] = {0, 0, 0, 0, 0};
     for (int v = 0; v < NV; ++v) {
         const long long s = (side * NV + v) * ncell + i;
         const double a = st[s * 5 + 0], b = st[s * 5 + 1], c = st[s * 5 + 2], d = st[s * 5 + 3], e = st[s * 5 + 4];
@@ -161,9 +161,10 @@ __global__ void __launch_bounds__(256) features_edge_kernel(const double* __rest
         const double al0 = 0.1 / ((eps + b0) * (eps + b0)), al1 = 0.6 / ((eps + b1) * (eps + b1)),
                      al2 = 0.3 / ((eps + b2) * (eps + b2));
         const double sa = al0 + al1 + al2;
-        wmin[0] = fmin(wmin[0], al0 / sa);
-        wmin[1] = fmin(wmin[1], al1 / sa);
-        wmin[2] = fmin(wmin[2], al2 / sa);
+        float* bv = base + (j * NV + v) * 3;
+        bv[0] = (float)(al0 / sa);
+        bv[1] = (float)(al1 / sa);
+        bv[2] = (float)(al2 / sa);
         const double mx = fmax(fmax(fmax(a, b), fmax(c, d)), e), mn = fmin(fmin(fmin(a, b), fmin(c, d)), e);
         const double sc = mx - mn;
         const double inv = sc > 0.0 ? 1.0 / sc : 0.0;
@@ -177,14 +178,12 @@ __global__ void __launch_bounds__(256) features_edge_kernel(const double* __rest
         tn[j * NV + v] = (float)t;
     }
     for (int k = 0; k < 5; ++k) feat[j * 5 + k] = (float)f[k];
-    const double sw = wmin[0] + wmin[1] + wmin[2];
-    for (int k = 0; k < 3; ++k) base[j * 3 + k] = (float)(wmin[k] / sw);
 }
 
-// Float32 forward of one sample (ojs: its Jiang-Shu weights); h1, h2 hidden
-// activations and a1, a2 pre-activations returned for the backward pass.
-__device__ __forceinline__ void mlp_forward_f32(const float* P, const float x[5], const float ojs[3], float a1[MLP_H],
-                                                float a2[MLP_H], float h1[MLP_H], float h2[MLP_H], float om[3])
+// Float32 logits of one sample; h1, h2 hidden activations and a1, a2
+// pre-activations returned for the backward pass.
+__device__ __forceinline__ void mlp_logits_f32(const float* P, const float x[5], float a1[MLP_H], float a2[MLP_H],
+                                               float h1[MLP_H], float h2[MLP_H], float zn[3])
 {
     for (int i = 0; i < MLP_H; ++i) {
         float s = P[MLP_OFF_B1 + i];
@@ -198,12 +197,17 @@ __device__ __forceinline__ void mlp_forward_f32(const float* P, const float x[5]
         a2[i] = s;
         h2[i] = gelu_ref(s);
     }
-    float z[3];
     for (int i = 0; i < 3; ++i) {
         float s = P[MLP_OFF_B3 + i];
         for (int j = 0; j < MLP_H; ++j) s += P[MLP_OFF_W3 + i * MLP_H + j] * h2[j];
-        z[i] = s + logf(ojs[i]);
+        zn[i] = s;
     }
+}
+
+// omega = softmax(zn + ln ojs).
+__device__ __forceinline__ void softmax_base(const float zn[3], const float ojs[3], float om[3])
+{
+    const float z[3] = {zn[0] + logf(ojs[0]), zn[1] + logf(ojs[1]), zn[2] + logf(ojs[2])};
     const float zm = fmaxf(z[0], fmaxf(z[1], z[2]));
     const float e0 = expf(z[0] - zm), e1 = expf(z[1] - zm), e2 = expf(z[2] - zm);
     const float se = e0 + e1 + e2;
@@ -221,10 +225,11 @@ __global__ void __launch_bounds__(256) forward_f32_kernel(const float* __restric
     __syncthreads();
     const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
-    float x[5], o[3], a1[MLP_H], a2[MLP_H], h1[MLP_H], h2[MLP_H], om[3];
+    float x[5], o[3], a1[MLP_H], a2[MLP_H], h1[MLP_H], h2[MLP_H], zn[3], om[3];
     for (int k = 0; k < 5; ++k) x[k] = feat[i * 5 + k];
     for (int k = 0; k < 3; ++k) o[k] = ojs[i * 3 + k];
-    mlp_forward_f32(sP, x, o, a1, a2, h1, h2, om);
+    mlp_logits_f32(sP, x, a1, a2, h1, h2, zn);
+    softmax_base(zn, o, om);
     for (int k = 0; k < 3; ++k) omega[i * 3 + k] = om[k];
 }
 
@@ -295,8 +300,9 @@ __global__ void __launch_bounds__(64) pack_kernel(const float* __restrict__ P, M
 // Stage 1 of the gradient: each block of TB samples runs forward and
 // backward per sample, parks the vectors the weight gradients need in LDS,
 // then sums each parameter's gradient over its samples in a fixed order.
-// NVAR variables share one sample's weights (cand[n][NVAR][3], tn[n][NVAR]);
-// the error term averages over them.
+// NVAR variables share one sample's logits, each correcting its own
+// Jiang-Shu weights (cand and ojs [n][NVAR][3], tn[n][NVAR]); the error
+// term and the regulariser average over them.
 template <int NVAR>
 __global__ void __launch_bounds__(TB) grad_partial_kernel(const float* __restrict__ P, const float* __restrict__ feat,
                                                           const float* __restrict__ cand, const float* __restrict__ tn,
@@ -312,25 +318,27 @@ __global__ void __launch_bounds__(TB) grad_partial_kernel(const float* __restric
     const long long i = (long long)blockIdx.x * TB + t;
     const bool valid = i < n;
     const long long ic = valid ? i : n - 1;
-    float x[5], o[3], a1[MLP_H], a2[MLP_H], h1[MLP_H], h2[MLP_H], om[3];
+    float x[5], a1[MLP_H], a2[MLP_H], h1[MLP_H], h2[MLP_H], zn[3];
     for (int k = 0; k < 5; ++k) x[k] = feat[ic * 5 + k];
-    for (int k = 0; k < 3; ++k) o[k] = ojs[ic * 3 + k];
-    mlp_forward_f32(sP, x, o, a1, a2, h1, h2, om);
-    float err = 0.f, dom[3] = {0.f, 0.f, 0.f};
+    mlp_logits_f32(sP, x, a1, a2, h1, h2, zn);
+    float err = 0.f, reg = 0.f, dz[3] = {0.f, 0.f, 0.f};
     for (int v = 0; v < NVAR; ++v) {
-        const float* c = cand + (ic * NVAR + v) * 3;
-        const float r = om[0] * c[0] + om[1] * c[1] + om[2] * c[2] - tn[ic * NVAR + v];
+        const long long iv = ic * NVAR + v;
+        float o[3], om[3], dom[3];
+        for (int k = 0; k < 3; ++k) o[k] = ojs[iv * 3 + k];
+        softmax_base(zn, o, om);
+        const float* c = cand + iv * 3;
+        const float r = om[0] * c[0] + om[1] * c[1] + om[2] * c[2] - tn[iv];
         err += r * r;
-        for (int k = 0; k < 3; ++k) dom[k] += r * c[k];
+        for (int k = 0; k < 3; ++k) {
+            reg += (om[k] - o[k]) * (om[k] - o[k]);
+            dom[k] = (2.f * inv_n / NVAR) * (r * c[k] + lam * (om[k] - o[k]));
+        }
+        // softmax backward of this variable; the variables share the logits
+        const float sdo = dom[0] * om[0] + dom[1] * om[1] + dom[2] * om[2];
+        for (int k = 0; k < 3; ++k) dz[k] += om[k] * (dom[k] - sdo);
     }
-    float reg = 0.f;
-    for (int k = 0; k < 3; ++k) {
-        reg += (om[k] - o[k]) * (om[k] - o[k]);
-        dom[k] = 2.f * inv_n * (dom[k] * (1.f / NVAR)) + 2.f * lam * inv_n * (om[k] - o[k]);
-    }
-    const float sdo = dom[0] * om[0] + dom[1] * om[1] + dom[2] * om[2];
-    float dz[3];
-    for (int k = 0; k < 3; ++k) dz[k] = valid ? om[k] * (dom[k] - sdo) : 0.f;
+    if (!valid) dz[0] = dz[1] = dz[2] = 0.f;
     // dA2 = (W3^T dz) * gelu'(a2); dA1 = (W2^T dA2) * gelu'(a1)
     float d2[MLP_H];
     for (int j = 0; j < MLP_H; ++j) {
@@ -348,7 +356,7 @@ __global__ void __launch_bounds__(TB) grad_partial_kernel(const float* __restric
     }
     for (int k = 0; k < 5; ++k) sx[t][k] = x[k];
     for (int k = 0; k < 3; ++k) sdz[t][k] = dz[k];
-    sl[t] = valid ? (err * (1.f / NVAR) + lam * reg) * inv_n : 0.f;
+    sl[t] = valid ? (err + lam * reg) * (1.f / NVAR) * inv_n : 0.f;
     __syncthreads();
     float* out = partial + (long long)blockIdx.x * GRAD_SLOTS;
     for (int p = t; p < GRAD_SLOTS; p += TB) {

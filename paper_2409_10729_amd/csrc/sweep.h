@@ -612,30 +612,23 @@ struct ReconLearned {
             cell_var(W, eps, lft, rgt);
     }
 
-    // Shared form: the features of all variables pooled by their maximum,
-    // the Jiang-Shu weights pooled by their minimum (renormalisation is left
-    // to the softmax, which ignores a common offset of the log-weights);
-    // one pair of network evaluations (right edge, mirrored left edge) for
-    // the cell, its weights applied to every variable.
+    // Shared form: one pair of network evaluations (right edge, mirrored
+    // left edge) per cell on the componentwise maximum of the seven
+    // variables' features; the logits correct each variable's own
+    // Jiang-Shu weights.
     template <class Win>
     __device__ __forceinline__ void cell_edge(const Win& W, float eps, float lft[NV], float rgt[NV])
     {
         float f[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
-        float wr[3] = {1.f, 1.f, 1.f}, wm[3] = {1.f, 1.f, 1.f};
         bool flat = true;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const float a = W(0, v), b = W(1, v), c = W(2, v), d = W(3, v), e = W(4, v);
             flat = flat && a == b && b == c && c == d && d == e;
-            float x[5], o[3], om[3];
-            edge_stats(a, b, c, d, e, eps, x, o, om);
+            float x[5];
+            edge_features(a, b, c, d, e, eps, x);
 #pragma unroll
             for (int k = 0; k < 5; ++k) f[k] = fmaxf(f[k], x[k]);
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                wr[k] = fminf(wr[k], o[k]);
-                wm[k] = fminf(wm[k], om[k]);
-            }
         }
         if (__all(flat)) {
             // constant stencils reconstruct to their value under any convex weights
@@ -644,20 +637,24 @@ struct ReconLearned {
             return;
         }
         const float fm[5] = {f[2], f[1], f[0], f[3], f[4]};
-        const float lw[3] = {log2f(wr[0]), log2f(wr[1]), log2f(wr[2])};
-        const float lwm[3] = {log2f(wm[0]), log2f(wm[1]), log2f(wm[2])};
-        float om[3], oml[3];
-        mlp_omega<PIPE>(m, f, lw, om);
-        mlp_omega<PIPE>(m, fm, lwm, oml);
+        float zr[3], zl[3], er[3], el[3];
+        mlp_logits<PIPE>(m, f, zr);
+        mlp_logits<PIPE>(m, fm, zl);
+        exp_logits(zr, er);
+        exp_logits(zl, el);
         // the stencils are read again from the window (LDS) below rather than
         // held in registers across the network evaluations
         asm volatile("" ::: "memory");
-        const bool finR = isfinite(om[0] + om[1] + om[2]);
-        const bool finL = isfinite(oml[0] + oml[1] + oml[2]);
+        bool finR = isfinite(er[0] + er[1] + er[2]), finL = isfinite(el[0] + el[1] + el[2]);
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             const float a = W(0, v), b = W(1, v), c = W(2, v), d = W(3, v), e = W(4, v);
+            float om[3], oml[3];
+            bool fr, fl;
+            shared_weights(a, b, c, d, e, eps, er, el, om, oml, fr, fl);
             weno5_apply(om, oml, a, b, c, d, e, lft[v], rgt[v]);
+            finR = finR && fr;
+            finL = finL && fl;
         }
         finish(W, eps, finR, finL, lft, rgt);
     }

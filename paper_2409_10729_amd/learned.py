@@ -152,8 +152,9 @@ def features(stencils, targets, eps: float = 1e-6):
 
 
 def features_edge(stencils, targets, tmax: float = 2.0, eps: float = 1e-6):
-    """Shared form: (feat [2n,5], cand [2n,7,3], tnorm [2n,7], base [2n,3])
-    of one 1D sample set of n cells (``mfx_mlp_features_edge``)."""
+    """Shared form: (feat [2n,5], cand [2n,7,3], tnorm [2n,7], base
+    [2n,7,3]: each variable's Jiang-Shu weights) of one 1D sample set of n
+    cells (``mfx_mlp_features_edge``)."""
     import torch
 
     ncell = stencils.shape[0] // 14
@@ -162,7 +163,7 @@ def features_edge(stencils, targets, tmax: float = 2.0, eps: float = 1e-6):
     feat = torch.empty((m, 5), **f32)
     cand = torch.empty((m, 7, 3), **f32)
     tn = torch.empty((m, 7), **f32)
-    base = torch.empty((m, 3), **f32)
+    base = torch.empty((m, 7, 3), **f32)
     _native.check_mlp(_native.lib().mfx_mlp_features_edge(_p(stencils), _p(targets), ncell, eps, tmax, _p(feat),
                                                           _p(cand), _p(tn), _p(base), _stream()))
     return feat, cand, tn, base
@@ -434,7 +435,7 @@ def js_validation_loss(data, lam):
     reference the network has to beat): error term only, regulariser 0."""
     feat, cand, tn, ojs = data
     if cand.dim() == 3:
-        r = (ojs[:, None, :] * cand).sum(dim=2) - tn
+        r = (ojs * cand).sum(dim=2) - tn
     else:
         r = (ojs * cand).sum(dim=1) - tn
     return float((r * r).mean().item())
