@@ -134,13 +134,16 @@ __device__ __forceinline__ float qsqrt<float>(float x)
 template <typename T>
 __device__ __forceinline__ void weno5_js(T a, T b, T c, T d, T e, T eps, T& left, T& right)
 {
-    const T k13 = T(13.0 / 12.0);
-    const T q0 = a - T(2) * b + c, h0 = a - T(4) * b + T(3) * c;
-    const T q1 = b - T(2) * c + d, h1 = b - d;
-    const T q2 = c - T(2) * d + e, h2 = T(3) * c - T(4) * d + e;
-    T s0 = eps + (k13 * q0 * q0 + T(0.25) * h0 * h0);
-    T s1 = eps + (k13 * q1 * q1 + T(0.25) * h1 * h1);
-    T s2 = eps + (k13 * q2 * q2 + T(0.25) * h2 * h2);
+    // beta_k = (13/12) q_k^2 + (1/4) h_k^2 with the factors taken into the
+    // differences (sqrt(13/12) q_k and h_k / 2), so each eps + beta_k is two
+    // fused multiply-adds
+    const T c13 = T(1.0408329997330663);  // sqrt(13/12)
+    const T q0 = c13 * (a - T(2) * b + c), h0 = T(0.5) * a - T(2) * b + T(1.5) * c;
+    const T q1 = c13 * (b - T(2) * c + d), h1 = T(0.5) * (b - d);
+    const T q2 = c13 * (c - T(2) * d + e), h2 = T(1.5) * c - T(2) * d + T(0.5) * e;
+    T s0 = fma(q0, q0, fma(h0, h0, eps));
+    T s1 = fma(q1, q1, fma(h1, h1, eps));
+    T s2 = fma(q2, q2, fma(h2, h2, eps));
     s0 *= s0;
     s1 *= s1;
     s2 *= s2;
@@ -154,14 +157,16 @@ __device__ __forceinline__ void weno5_js(T a, T b, T c, T d, T e, T eps, T& left
     const T l1 = T(2) * b + T(5) * c - d;
     const T l2 = T(11) * c - T(7) * d + T(2) * e;
 
-    const T wr0 = T(0.1) * t0, wr1 = T(0.6) * t1, wr2 = T(0.3) * t2;
-    const T wl0 = T(0.3) * t0, wl1 = T(0.6) * t1, wl2 = T(0.1) * t2;
+    // linear weights times ten (1, 6, 3 and 3, 6, 1: exact, and the common
+    // factor cancels in each quotient)
+    const T u0 = T(3) * t0, u1 = T(6) * t1, u2 = T(3) * t2;
     // one refined reciprocal of Dr Dl serves both quotients (the weights'
     // products stay far inside the float64 range: (eps + beta)^2 products up
-    // to ~1e90 for pressure jumps of 1e11, down to ~1e-24 on flat data)
-    const T Nr = wr0 * r0 + wr1 * r1 + wr2 * r2, Dr = T(6) * (wr0 + wr1 + wr2);
-    const T Nl = wl0 * l0 + wl1 * l1 + wl2 * l2, Dl = T(6) * (wl0 + wl1 + wl2);
-    const T inv = qdiv(T(1), Dr * Dl);
+    // to ~1e90 for pressure jumps of 1e11, down to ~1e-24 on flat data);
+    // the candidates' factor 6 is applied once, to the reciprocal
+    const T Nr = t0 * r0 + u1 * r1 + u2 * r2, Dr = t0 + u1 + u2;
+    const T Nl = u0 * l0 + u1 * l1 + t2 * l2, Dl = u0 + u1 + t2;
+    const T inv = qdiv(T(1.0 / 6.0), Dr * Dl);
     right = Nr * (Dl * inv);
     left = Nl * (Dr * inv);
 }
@@ -172,13 +177,14 @@ __device__ __forceinline__ void weno5_js(T a, T b, T c, T d, T e, T eps, T& left
 __device__ __forceinline__ void weno5_js_ratio(float a, float b, float c, float d, float e, float eps,
                                                float& left, float& right)
 {
-    const float k13 = 13.0f / 12.0f;
-    const float q0 = a - 2.f * b + c, h0 = a - 4.f * b + 3.f * c;
-    const float q1 = b - 2.f * c + d, h1 = b - d;
-    const float q2 = c - 2.f * d + e, h2 = 3.f * c - 4.f * d + e;
-    const float s0 = eps + (k13 * q0 * q0 + 0.25f * h0 * h0);
-    const float s1 = eps + (k13 * q1 * q1 + 0.25f * h1 * h1);
-    const float s2 = eps + (k13 * q2 * q2 + 0.25f * h2 * h2);
+    // indicators as in weno5_js (factors taken into the differences)
+    const float c13 = 1.04083300f;  // sqrt(13/12)
+    const float q0 = c13 * (a - 2.f * b + c), h0 = 0.5f * a - 2.f * b + 1.5f * c;
+    const float q1 = c13 * (b - 2.f * c + d), h1 = 0.5f * (b - d);
+    const float q2 = c13 * (c - 2.f * d + e), h2 = 1.5f * c - 2.f * d + 0.5f * e;
+    const float s0 = fmaf(q0, q0, fmaf(h0, h0, eps));
+    const float s1 = fmaf(q1, q1, fmaf(h1, h1, eps));
+    const float s2 = fmaf(q2, q2, fmaf(h2, h2, eps));
     const float smin = fminf(s0, fminf(s1, s2));
     float x0 = qdiv(smin, s0), x1 = qdiv(smin, s1), x2 = qdiv(smin, s2);
     x0 *= x0;
@@ -190,10 +196,10 @@ __device__ __forceinline__ void weno5_js_ratio(float a, float b, float c, float 
     const float l0 = -a + 5.f * b + 2.f * c;
     const float l1 = 2.f * b + 5.f * c - d;
     const float l2 = 11.f * c - 7.f * d + 2.f * e;
-    const float wr0 = 0.1f * x0, wr1 = 0.6f * x1, wr2 = 0.3f * x2;
-    const float wl0 = 0.3f * x0, wl1 = 0.6f * x1, wl2 = 0.1f * x2;
-    right = qdiv(wr0 * r0 + wr1 * r1 + wr2 * r2, 6.f * (wr0 + wr1 + wr2));
-    left = qdiv(wl0 * l0 + wl1 * l1 + wl2 * l2, 6.f * (wl0 + wl1 + wl2));
+    // linear weights times ten, as in weno5_js
+    const float u0 = 3.f * x0, u1 = 6.f * x1, u2 = 3.f * x2;
+    right = qdiv(x0 * r0 + u1 * r1 + u2 * r2, 6.f * (x0 + u1 + u2));
+    left = qdiv(u0 * l0 + u1 * l1 + x2 * l2, 6.f * (u0 + u1 + x2));
 }
 
 // WENO5 in the compute type: the product form in float64, the ratio form
