@@ -200,8 +200,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--compare-steps", type=int, default=200,
                     help="steps of the FP64 run whose time steps the FP32 and learned forms replay for their L1 "
-                         "error (negative: skip both forms)")
+                         "error (0: time the forms at the first CFL step without the comparison; negative: skip "
+                         "the forms)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-weights form")
+    ap.add_argument("--forms", default="all",
+                    help="comma-separated forms to compare after the FP64 run (fp32_mixed, fp64_weno3, fp64_wenoz, "
+                         "learned, learned_edge; default all), e.g. to profile one form's kernels")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain device-to-device copy of 7 * n^3 float64 (known bytes), five times, "
                          "to scale rocprofv3 FETCH_SIZE / WRITE_SIZE")
@@ -362,11 +366,16 @@ def main():
     if args.compare_steps >= 0:
         print(f"[bench] accuracy: fp64 reference over {args.compare_steps} steps", file=sys.stderr, flush=True)
         s64 = new_solver(MFX_FP64)
-        dts = [s64.rk3_step(sync=True) for _ in range(args.compare_steps)]
-        q64 = s64.get_state().cpu().numpy().reshape(7, -1)
+        if args.compare_steps > 0:
+            dts = [s64.rk3_step(sync=True) for _ in range(args.compare_steps)]
+            q64 = s64.get_state().cpu().numpy().reshape(7, -1)
+        else:
+            # timing only (e.g. under a profiler): the forms run at the first
+            # CFL step, with no accuracy comparison
+            dts, q64 = [s64.rk3_step(sync=True)], None
         s64.destroy()
         del s64
-        dt_fixed = dts[0] if dts else 1e-9
+        dt_fixed = dts[0]
         # (name, precision, weights, WENO order); fp64_weno3 (third order) and
         # fp64_wenoz (WENO-Z weights) are different schemes: their L1
         # distance to the fifth-order Jiang-Shu run is a scheme difference
@@ -376,11 +385,19 @@ def main():
             variants.append(("learned", MFX_FP32_MIXED, MFX_WENO5_LEARNED, 5))
         if MFX_WENO5_LEARNED_EDGE in nets:
             variants.append(("learned_edge", MFX_FP32_MIXED, MFX_WENO5_LEARNED_EDGE, 5))
+        if args.forms != "all":
+            keep = set(args.forms.split(","))
+            unknown = keep - {v[0] for v in variants}
+            if unknown:
+                raise SystemExit(f"bench.py: unknown or unavailable forms {sorted(unknown)}")
+            variants = [v for v in variants if v[0] in keep]
         for name, prec, weights, order in variants:
-            print(f"[bench] {name}: replaying {len(dts)} steps", file=sys.stderr, flush=True)
-            q, fb = replay(prec, dts, weights, order)
-            l1, rho_l1 = l1_vs(q, q64)
-            del q
+            l1 = rho_l1 = fb = None
+            if q64 is not None:
+                print(f"[bench] {name}: replaying {len(dts)} steps", file=sys.stderr, flush=True)
+                q, fb = replay(prec, dts, weights, order)
+                l1, rho_l1 = l1_vs(q, q64)
+                del q
             print(f"[bench] {name}: timing {args.steps} steps", file=sys.stderr, flush=True)
             ms_f, prof_f = time_form(prec, dt_fixed, weights, order)
             msf_step = ms_f / args.steps
@@ -394,13 +411,14 @@ def main():
                 "density_l1_rel_vs_fp64": rho_l1,
                 "kernels": kf,
             }
-            if weights in nets:
+            if weights in nets and fb is not None:
                 edges = 2 * N * sum(1 for k in P["spec"]["n"] if k > 1) * 3 * len(dts)
                 forms[name]["fallback_edges"] = fb
                 forms[name]["fallback_fraction"] = float(f"{fb / max(edges, 1):.3e}")
                 forms[name]["network"] = os.path.relpath(nets[weights][1], os.path.dirname(os.path.abspath(__file__)))
-            print(f"[bench] {name}: {msf_step:.3f} ms/step (x{ms_step / msf_step:.2f}), density L1 {rho_l1:.2e}",
-                  file=sys.stderr, flush=True)
+            acc = f", density L1 {rho_l1:.2e}" if rho_l1 is not None else ""
+            print(f"[bench] {name}: {msf_step:.3f} ms/step (x{ms_step / msf_step:.2f}){acc}", file=sys.stderr,
+                  flush=True)
         del q64
     del w_dev
 
