@@ -361,6 +361,9 @@ __device__ __forceinline__ void ghost_fix(const Grid& g, const MixOf<F>& mixd, i
     }
 }
 
+// Where the march converts the cell entering its window (see march).
+constexpr int ENTER_BEFORE = 0, ENTER_AFTER = 1;
+
 // Sink of the y and z sweeps: each lane writes its own cell (lanes are
 // consecutive x, so every access is a contiguous row).  KEEPQ: the march
 // hands over the cell's stage state, which it loaded four cells earlier,
@@ -377,6 +380,7 @@ template <typename T, bool FIRST, int MODE, bool KEEPQ = false, int CHK = CHK_NO
           class F = Fl2>
 struct GlobalSink {
     static constexpr bool keeps_q = KEEPQ;
+    static constexpr int enter_at = PREFETCH ? ENTER_BEFORE : ENTER_AFTER;  // see march
     static constexpr bool NEEDQN = MODE == OUT_STAGE2 || MODE == OUT_STAGE3;
     OutArgs<T> o;
     long long base, sd;
@@ -822,6 +826,42 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
         recon.at(c);
         recon.cell_win(W, eps, lft, rgt);
 
+        // The entering cell c+3 is converted before this step's stores are
+        // issued where the sink allows: vector-memory loads and stores share
+        // one completion counter, so a load used after a store would wait
+        // for the store as well.  ENTER_BEFORE (the y and z sweeps with
+        // Jiang-Shu weights): before the output, the stage state of the
+        // output cell c-1 taken out of the history before the entering
+        // cell's joins it.  ENTER_AFTER (the learned passes, the fused x-y
+        // pass and the LDS outputs of the marching x sweep): after the
+        // output, where converting costs no registers (converting earlier in
+        // the fused x-y pass took it from 247 to 256 registers with spills).
+        constexpr int AT = Sink::enter_at;
+        static_assert(!KQ || AT == ENTER_BEFORE, "a sink that keeps the stage state converts first");
+        T wn[AT == ENTER_BEFORE ? V : 1];
+        double qout[KQ ? V : 1];
+        if constexpr (AT == ENTER_BEFORE) {
+            if constexpr (KQ) {
+#pragma unroll
+                for (int v = 0; v < V; ++v) qout[v] = qh[0][v];
+            }
+            if (c < c1) {
+                prim_of<T, F>(mixd, qnext, wn);
+                src.finish_ahead(c + 3, wn);  // c + 3 >= c0 + 2 >= 2
+            }
+            if constexpr (KQ) {
+                if (c < c1) {
+#pragma unroll
+                    for (int v = 0; v < V; ++v) {
+                        qh[0][v] = qh[1][v];
+                        qh[1][v] = qh[2][v];
+                        qh[2][v] = qh[3][v];
+                        qh[3][v] = qnext[v];
+                    }
+                }
+            }
+        }
+
         if (c >= c0) {
             T Fl[V], uf;
             hllc_f<DIR, T, F>(mix, rprev, lft, Fl, uf);
@@ -835,7 +875,7 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
                 T src_a[F::NA];
 #pragma unroll
                 for (int a = 0; a < F::NA; ++a) src_a[a] = W(1, F::IA + a) * ((uf - ufprev) * ih);
-                sink.put(g, c - 1, fd, src_a, W, &qh[0][0]);
+                sink.put(g, c - 1, fd, src_a, W, qout);
             }
 #pragma unroll
             for (int v = 0; v < V; ++v) Fprev[v] = Fl[v];
@@ -844,21 +884,16 @@ __device__ __forceinline__ void march(const Grid& g, Src& src, Sink& sink, Recon
 #pragma unroll
         for (int v = 0; v < V; ++v) rprev[v] = rgt[v];
 
-        if (c < c1) {
-            // cell c+3 enters, cell c-2 (no longer needed) leaves
-            T w[V];
-            prim_of<T, F>(mixd, qnext, w);
-            src.finish_ahead(c + 3, w);  // c + 3 >= c0 + 2 >= 2
-            W.push(w);
-            if constexpr (KQ) {
-#pragma unroll
-                for (int v = 0; v < V; ++v) {
-                    qh[0][v] = qh[1][v];
-                    qh[1][v] = qh[2][v];
-                    qh[2][v] = qh[3][v];
-                    qh[3][v] = qnext[v];
-                }
+        // cell c+3 enters, cell c-2 (no longer needed) leaves
+        if constexpr (AT == ENTER_AFTER) {
+            if (c < c1) {
+                T w[V];
+                prim_of<T, F>(mixd, qnext, w);
+                src.finish_ahead(c + 3, w);  // c + 3 >= c0 + 2 >= 2
+                W.push(w);
             }
+        } else if (c < c1) {
+            W.push(wn);
         }
     }
 }
@@ -1035,6 +1070,7 @@ struct LdsSink {
     int nx, c0, c1;
 
     static constexpr bool keeps_q = false;
+    static constexpr int enter_at = ENTER_AFTER;
     __device__ __forceinline__ void prefetch(const Grid&, int) {}
     template <class Win>
     __device__ __forceinline__ void put(const Grid& g, int c, const T* fd, const T* src, const Win&, const double*)

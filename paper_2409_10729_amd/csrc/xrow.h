@@ -318,6 +318,7 @@ __global__ void __launch_bounds__(XROW_THREADS) __attribute__((amdgpu_waves_per_
 template <typename T, int MODE, int SCHEME = 5>
 struct XYSink {
     static constexpr bool keeps_q = false;
+    static constexpr int enter_at = ENTER_AFTER;  // see march
     __device__ __forceinline__ void prefetch(const Grid&, int) {}
     OutArgs<T> o;
     T* P;   // [NV][nx+4]
