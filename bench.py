@@ -19,6 +19,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -84,13 +85,22 @@ def sweep_flops_per_cell(d: int, mode: int, order: int = 5) -> int:
     return FLOPS_CONV + ndir * (7 * weno + FLOPS_HLLC + FLOPS_FLUXDIFF) + FLOPS_RK[mode]
 
 
+def code_of(text: str) -> str:
+    """C++ source without comments and blank lines."""
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", "", text)
+    return "\n".join(line.rstrip() for line in text.splitlines() if line.strip())
+
+
 def source_hash() -> str:
+    """Hash of the kernel sources' code (comments and blank lines left out:
+    a comment edit does not change what the counters measured)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2409_10729_amd", "csrc")
     for name in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, name), "rb") as f:
+        with open(os.path.join(csrc, name), encoding="utf-8") as f:
             h.update(name.encode())
-            h.update(f.read())
+            h.update(code_of(f.read()).encode())
     return h.hexdigest()[:16]
 
 
