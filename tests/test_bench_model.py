@@ -1,6 +1,9 @@
 """Host-side checks of the benchmark's measurement model (no GPU): the
 algorithmic byte and flop counts per cell that bench.py divides by the
-measured kernel times, checked against their definitions."""
+measured kernel times, checked against their definitions; the key that ties the committed
+traffic counters to the kernel sources."""
+import os
+
 import bench
 
 
@@ -35,3 +38,22 @@ def test_ridge_selects_the_roof():
     xy = bench.sweep_flops_per_cell(3, 0) / bench.sweep_bytes_per_cell(1, 0)
     z = bench.sweep_flops_per_cell(2, 3) / bench.sweep_bytes_per_cell(0, 3)
     assert xy > ridge > z  # the x-y pass is compute-bound, the z pass memory-bound
+
+
+def test_source_hash_ignores_comments_only(tmp_path, monkeypatch):
+    import shutil
+
+    import bench
+
+    src = os.path.join(bench.ROOT, "paper_2409_10729_amd", "csrc")
+    dst = tmp_path / "paper_2409_10729_amd" / "csrc"
+    shutil.copytree(src, dst)
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    h0 = bench.source_hash()
+    f = dst / "physics.h"
+    text = f.read_text()
+    f.write_text("// a new comment\n/* and a\n   block */\n" + text.replace("{", "{ // brace", 1) + "\n\n")
+    assert bench.source_hash() == h0
+    f.write_text(text.replace("{", "{ int unused_marker = 0;", 1))
+    assert bench.source_hash() != h0
+    assert bench.code_of("a = 1; // c\n/* x\ny */ b = 2;\n\n") == "a = 1;\n b = 2;"
