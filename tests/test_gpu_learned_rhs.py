@@ -3,7 +3,8 @@ learned right-hand side (oracle.rhs_learned), element by element.
 
 Each case runs the solver's right-hand side in a learned mode
 (MFX_WENO5_LEARNED: one network evaluation per variable and edge;
-MFX_WENO5_LEARNED_EDGE: one per edge on pooled features) through the C ABI
+MFX_WENO5_LEARNED_EDGE: one per edge on pooled features, its logits
+correcting each variable's own Jiang-Shu weights) through the C ABI
 and compares it with the oracle on the same state and network:
   * per field, max |gpu - oracle| over the flux scale <= the tolerance
     parity_util.learned_tolerance derives: the float32 bar (1e-5) plus four
