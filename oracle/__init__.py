@@ -93,6 +93,7 @@ def lib():
         L.orc_rhs.argtypes = [gp, dp, dp]
         L.orc_rhs_at.argtypes = [gp, dp, ctypes.c_int64, i64p, dp]
         L.orc_rhs_learned.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_int, dp, i64p]
+        L.orc_rhs_learned_at.argtypes = [gp, dp, dp, ctypes.c_int, ctypes.c_int64, i64p, dp]
         L.orc_mlp_omega.argtypes = [dp, ctypes.c_int64, dp, dp, dp]
         L.orc_gelu.argtypes = [ctypes.c_double]
         L.orc_gelu.restype = ctypes.c_double
@@ -241,6 +242,26 @@ def rhs_learned(g: OrcGrid, q: np.ndarray, theta, mode: int = LEARNED_PER_VARIAB
     lib().orc_rhs_learned(ctypes.byref(g), _dp(q), _dp(th), int(mode), int(plant), _dp(out),
                           counts.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)))
     return out, int(counts[0]), int(counts[1])
+
+
+def rhs_learned_at(g: OrcGrid, q: np.ndarray, theta, cells: np.ndarray, mode: int = LEARNED_PER_VARIABLE):
+    """The learned right-hand side of rhs_learned at linear cell indices
+    ``cells``, cell by cell (equal to rhs_learned there); returns
+    [ncell, 7]."""
+    if g.nf != 2:
+        raise ValueError("the learned weights are defined for two fluids")
+    if any(g.xf[d] for d in range(3)):
+        raise ValueError("the learned weights are defined on uniform cells")
+    q = _state(g, q, "q")
+    th = np.ascontiguousarray(np.asarray(theta, dtype=np.float32), dtype=np.float64)
+    assert th.size == 1347
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    if cells.size and (cells.min() < 0 or cells.max() >= g.n[0] * g.n[1] * g.n[2]):
+        raise ValueError("cell index outside the grid")
+    out = np.empty((cells.size, NV), dtype=np.float64)
+    lib().orc_rhs_learned_at(ctypes.byref(g), _dp(q), _dp(th), int(mode), cells.size,
+                             cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(out))
+    return out
 
 
 def mlp_omega(theta, X, base) -> np.ndarray:

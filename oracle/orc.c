@@ -1055,8 +1055,11 @@ double orc_gelu_tanh(double a) { return gelu_tanh(a); }
 /* ---------- right-hand side at selected cells, one by one ----------
    cells: linear indices (k*ny + j)*nx + i; out: [ncell][nvar].  Uses the same
    per-cell formulas with the BC map applied to each stencil index, and the
-   same accumulation order, so it equals orc_rhs at those cells. */
-void orc_rhs_at(const orc_grid* g, const double* q, int64_t ncell, const int64_t* cells, double* out)
+   same accumulation order, so it equals orc_rhs at those cells (and, with
+   learned weights L, orc_rhs_learned: the same learned_cell on the same
+   stencils). */
+static void rhs_at_impl(const orc_grid* g, const double* q, int64_t ncell, const int64_t* cells, double* out,
+                        const orc_learn* L)
 {
     const int64_t N = ncells(g);
     const int nv = nvar(g), ia0 = ialf(g);
@@ -1081,12 +1084,21 @@ void orc_rhs_at(const orc_grid* g, const double* q, int64_t ncell, const int64_t
                 cons_to_prim(g, qc, w7[o + 3]);
             }
             double lft[3][NVMAX], rgt[3][NVMAX];
-            for (int cc = 0; cc < 3; ++cc)
-                for (int v = 0; v < nv; ++v) {
-                    double st[5];
-                    for (int o = 0; o < 5; ++o) st[o] = w7[cc + o][v];
-                    reconstruct_at(g, d, pos[d] - 1 + cc, st, &lft[cc][v], &rgt[cc][v]);
+            for (int cc = 0; cc < 3; ++cc) {
+                if (L) { /* two fluids (nv == NV) */
+                    double st[NV][5];
+                    int fl[4];
+                    for (int v = 0; v < NV; ++v)
+                        for (int o = 0; o < 5; ++o) st[v][o] = w7[cc + o][v];
+                    learned_cell(g, L, st, lft[cc], rgt[cc], fl, fl + 2);
+                } else {
+                    for (int v = 0; v < nv; ++v) {
+                        double st[5];
+                        for (int o = 0; o < 5; ++o) st[o] = w7[cc + o][v];
+                        reconstruct_at(g, d, pos[d] - 1 + cc, st, &lft[cc][v], &rgt[cc][v]);
+                    }
                 }
+            }
             double Fm[NVMAX], Fp[NVMAX], um, up;
             hllc(g, rgt[0], lft[1], d, Fm, &um);
             hllc(g, rgt[1], lft[2], d, Fp, &up);
@@ -1096,6 +1108,26 @@ void orc_rhs_at(const orc_grid* g, const double* q, int64_t ncell, const int64_t
         }
         for (int v = 0; v < nv; ++v) out[c * nv + v] = r[v];
     }
+}
+
+void orc_rhs_at(const orc_grid* g, const double* q, int64_t ncell, const int64_t* cells, double* out)
+{
+    rhs_at_impl(g, q, ncell, cells, out, NULL);
+}
+
+/* The learned right-hand side (as orc_rhs_learned, mode 1 per variable, 2
+   shared per edge) at selected cells, one by one. */
+void orc_rhs_learned_at(const orc_grid* g, const double* q, const double* theta, int mode, int64_t ncell,
+                        const int64_t* cells, double* out)
+{
+    if (nvar(g) != NV) {
+        for (int64_t x = 0; x < ncell * nvar(g); ++x) out[x] = NAN;
+        return;
+    }
+    orc_mlp m;
+    mlp_load(theta, &m);
+    orc_learn L = {&m, mode == 2 ? 2 : 1, 0};
+    rhs_at_impl(g, q, ncell, cells, out, &L);
 }
 
 /* ---------- CFL time step ---------- */

@@ -30,7 +30,7 @@ import oracle
 from oracle import mlp as omlp
 from paper_2409_10729_amd import MFX_FP32_MIXED, MFX_WENO5_LEARNED, MFX_WENO5_LEARNED_EDGE
 from paper_2409_10729_amd import workloads as wl
-from parity_util import FP32_BAR, flux_scale, gpu_solver, learned_reference, learned_tolerance
+from parity_util import FP32_BAR, flux_scale, gpu_solver, learned_reference, learned_tolerance, sample_cells
 
 pytestmark = pytest.mark.gpu
 
@@ -125,3 +125,51 @@ def test_learned_rhs_matches_oracle(problem, mode, net, xpass, monkeypatch):
     assert np.all(err <= tol), (err, tol)
     assert above <= 0.01
     assert abs(st["fallback_faces"] - ref["fallbacks"]) <= fb_tol
+
+
+FULL = [
+    # the learned configuration (multi-bubble, 192^3) and the benchmark's problem (256^3)
+    ("bubble_cloud", 192, PER_VAR, "mlp_weno5"),
+    ("bubble_cloud", 192, SHARED, "mlp_weno5_edge"),
+    ("shock_droplet", 256, PER_VAR, "mlp_weno5"),
+    ("shock_droplet", 256, SHARED, "mlp_weno5_edge"),
+]
+
+
+@pytest.mark.parametrize("workload,n,mode,net", FULL)
+def test_full_size_learned_rhs_sampled(workload, n, mode, net):
+    """The learned right-hand side at full size, in the launch configuration
+    the benchmark times, against the oracle's cell-by-cell learned
+    right-hand side on sampled cells (random cells, every boundary-adjacent
+    cell class, the steepest interfaces and shocks).  Tolerance as above,
+    with the oracle's float32-rounding response measured on the same cells."""
+    P = getattr(wl, workload)(n=n, seed=0)
+    spec = P["spec"]
+    g = oracle.make_grid(spec)
+    q0 = oracle.prim_to_cons(g, P["w"])
+    theta = np.asarray(_network(net), dtype=np.float32)
+    print(f"full size {workload} {n}^3 mode {mode} net {net}", flush=True)
+    s = gpu_solver(spec, q0=q0, precision=MFX_FP32_MIXED, weights=WEIGHTS[mode])
+    s.set_mlp(torch.from_numpy(theta).cuda())
+    r = s.rhs().cpu().numpy().reshape(7, -1)
+    assert s.stats()["error"] == 0
+    s.destroy()
+    cells = sample_cells(spec, 300, seed=n, q0=q0)
+    ref = oracle.rhs_learned_at(g, q0, theta, cells, mode).T
+    w = oracle.cons_to_prim(g, q0)
+    q32 = oracle.prim_to_cons(g, w.astype(np.float32).astype(np.float64))
+    del w
+    ref32 = oracle.rhs_learned_at(g, q32, theta, cells, mode).T
+    del q32
+    sc = flux_scale(q0, spec)
+    sens = np.abs(ref - ref32).max(axis=1) / np.where(sc > 0, sc, 1.0)
+    tol = FP32_BAR + 4.0 * sens
+    den = np.maximum(np.abs(ref).max(axis=1), sc)
+    cell_err = np.abs(r[:, cells] - ref) / den[:, None]
+    err = cell_err.max(axis=1)
+    above = float(np.mean(cell_err.max(axis=0) > FP32_BAR))
+    print(f"  {cells.size} cells; error per field " + " ".join(f"{e:.1e}" for e in err), flush=True)
+    print("  tolerance " + " ".join(f"{t:.1e}" for t in tol) + f"; cells above the float32 bar {above:.4f}",
+          flush=True)
+    assert np.all(err <= tol), (err, tol)
+    assert above <= 0.01

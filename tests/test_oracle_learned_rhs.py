@@ -292,3 +292,25 @@ def test_planted_mistakes_exceed_the_gpu_tolerance(plant):
     tol = learned_tolerance(ref)
     print(f"plant {plant}: error/tolerance per field", np.round(err / tol, 1), flush=True)
     assert (err / tol).max() > 10.0
+
+
+@pytest.mark.parametrize("mode", [PER_VAR, SHARED])
+@pytest.mark.parametrize("name", ["smooth", "droplet", "walls"])
+def test_cell_by_cell_learned_rhs_equals_the_whole_grid(name, mode):
+    """rhs_learned_at (one cell at a time, the boundary rule applied to each
+    stencil index) equals rhs_learned (padded grid, pencils) bit for bit at
+    every cell, including those next to reflective and inflow sides."""
+    if name == "walls":
+        P = wl.shock_droplet_walls(n=(20, 12, 10), seed=5)
+        g1 = oracle.make_grid(dict(P["spec"], n=(1, 1, 1), bc=((0, 0),) * 3))
+        inflow = np.array([[oracle.prim_to_cons(g1, np.asarray(w7).reshape(7, 1, 1, 1)).reshape(7)
+                            for w7 in pair] for pair in P["inflow_prim"]])
+        P = dict(P, spec=dict(P["spec"], inflow=inflow))
+    else:
+        P = PROBLEMS[name]()
+    g, q0 = _q0(P)
+    th = omlp.init_params(14, out_scale=0.5)
+    r, _, _ = oracle.rhs_learned(g, q0, th, mode)
+    cells = np.arange(q0[0].size)
+    ra = oracle.rhs_learned_at(g, q0, th, cells, mode)
+    assert np.array_equal(ra.T, r.reshape(7, -1))
