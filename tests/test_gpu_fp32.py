@@ -13,7 +13,7 @@ import pytest
 import oracle
 from paper_2409_10729_amd import MFX_FP32_MIXED
 from paper_2409_10729_amd import workloads as wl
-from parity_util import gpu_solver, rhs_rel_linf
+from parity_util import gpu_solver, rhs_rel_linf, sample_cells
 
 pytestmark = pytest.mark.gpu
 
@@ -93,3 +93,21 @@ def test_fp32_x_sweep_variants_and_long_rows(monkeypatch, n, bc):
         assert np.all(err <= 1e-5), err
     d = rhs_rel_linf(rs["rows"], rs["march"], q0, P["spec"])
     assert np.all(d <= 1e-6), d
+
+
+@pytest.mark.parametrize("workload,n", [("shock_droplet", 256), ("bubble_cloud", 192)])
+def test_fp32_full_size_rhs_sampled(workload, n):
+    """The float form's right-hand side at full size, in the launch
+    configuration the benchmark times, against the oracle's FP64 right-hand
+    side on sampled cells (random, boundary layers, steepest interfaces and
+    shocks): within the float32 bar, 1e-5 of the flux scale."""
+    P = getattr(wl, workload)(n=n, seed=0)
+    g, q0 = _q0(P)
+    s = gpu_solver(P["spec"], q0=q0, precision=MFX_FP32_MIXED)
+    r = s.rhs().cpu().numpy().reshape(7, -1)
+    s.destroy()
+    cells = sample_cells(P["spec"], 2000, seed=n, q0=q0)
+    ref = oracle.rhs_at(g, q0, cells).T
+    err = rhs_rel_linf(r[:, cells], ref, q0, P["spec"])
+    print(f"fp32 rhs {workload} {n}^3 on {cells.size} cells: " + " ".join(f"{e:.2e}" for e in err), flush=True)
+    assert np.all(err <= 1e-5), err

@@ -406,3 +406,25 @@ def test_repeat_runs_bitwise_equal():
             s.rk3_step()
         res.append(s.get_state().cpu().numpy())
     assert np.array_equal(res[0], res[1])
+
+
+@pytest.mark.parametrize("scheme", ["weno3", "weno_z"])
+def test_full_size_other_schemes_rhs_sampled(scheme):
+    """The 256^3 workload with the third-order reconstruction and with WENO-Z
+    weights (the comparison forms the benchmark times): the right-hand side
+    on sampled cells against the oracle's, at the FP64 bar."""
+    from paper_2409_10729_amd import MFX_WENO5_JS, MFX_WENO5_Z
+
+    P = wl.shock_droplet(n=256, seed=0)
+    spec = dict(P["spec"], weno_order=3) if scheme == "weno3" else dict(P["spec"], weno_z=True)
+    g = oracle.make_grid(spec)
+    q0 = oracle.prim_to_cons(g, P["w"])
+    s = gpu_solver(spec, q0=q0, weights=MFX_WENO5_Z if scheme == "weno_z" else MFX_WENO5_JS)
+    r = s.rhs().cpu().numpy().reshape(7, -1)
+    s.destroy()
+    cells = sample_cells(spec, 2000, seed=7, q0=q0)
+    ref = oracle.rhs_at(g, q0, cells).T
+    err, errp = fp64_rhs_errors(r[:, cells], ref, q0, spec)
+    _report(f"{scheme} rhs 256^3 on {cells.size} cells", err)
+    _report(f"{scheme} rhs 256^3 on {cells.size} cells (physical-flux scale)", errp)
+    assert np.all(err <= TOL) and np.all(errp <= TOL), (err, errp)
