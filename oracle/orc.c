@@ -123,7 +123,8 @@ static void cons_to_prim(const orc_grid* g, const double* q, double* w)
 {
     const int m = imom(g), e = iene(g), a = ialf(g);
     double rho = mix_density(g, q);
-    double u = q[m] / rho, v = q[m + 1] / rho, ww = q[m + 2] / rho;
+    double ir = 1.0 / rho;
+    double u = q[m] * ir, v = q[m + 1] * ir, ww = q[m + 2] * ir;
     double ke = 0.5 * rho * (u * u + v * v + ww * ww);
     double G = mix_Gamma(g, q + a), P = mix_Pi(g, q + a);
     for (int i = 0; i < nvar(g); ++i) w[i] = q[i];
@@ -437,13 +438,16 @@ static void hllc(const orc_grid* g, const double* wl, const double* wr, int d, d
     Fk[m + d] = Fk[m + d] + p;
     Fk[e] = (E + p) * un;
 
-    double xi = (S - un) / (S - Ss);
+    /* xi = (S - u)/(S - S*); the star energy's pressure term
+       xi (S* - u) p/(S - u) is (S* - u) p/(S - S*), so one quotient serves both */
+    double inv = 1.0 / (S - Ss);
+    double xi = (S - un) * inv;
     for (int i = 0; i < nf; ++i) Us[i] = xi * w[i];
     Us[m] = xi * (rho * w[m]);
     Us[m + 1] = xi * (rho * w[m + 1]);
     Us[m + 2] = xi * (rho * w[m + 2]);
     Us[m + d] = xi * (rho * Ss);
-    Us[e] = xi * (E + (Ss - un) * (rho * Ss + p / (S - un)));
+    Us[e] = xi * (E + (Ss - un) * (rho * Ss)) + (Ss - un) * (p * inv);
     for (int i = a; i < nv; ++i) Us[i] = xi * w[i];
 
     for (int v = 0; v < nv; ++v) F[v] = Fk[v] + s * (Us[v] - U[v]);

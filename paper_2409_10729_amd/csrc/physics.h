@@ -64,7 +64,7 @@ using Fl2 = Fl<2>;
 
 // Conserved -> primitive for one cell, always in float64 and without
 // contraction, in the operation order of the plain definition
-//   u = (rho u)/rho, p = (rho E - rho |u|^2 / 2 - Pi) / Gamma.
+//   u = (rho u) (1/rho), p = (rho E - rho |u|^2 / 2 - Pi) / Gamma.
 // In water at 1e5 Pa the subtraction cancels about four digits
 // (Pi ~ 7.8e8), so the pressure carries ~1e-7 Pa of rounding noise that
 // every later stage inherits; fixing the order makes that noise the same
@@ -73,7 +73,8 @@ __device__ __forceinline__ void cons_to_prim(const Mix<double>& mix, const doubl
 {
 #pragma clang fp contract(off)
     const double rho = q[0] + q[1];
-    const double u = q[2] / rho, v = q[3] / rho, ww = q[4] / rho;
+    const double ir = 1.0 / rho;
+    const double u = q[2] * ir, v = q[3] * ir, ww = q[4] * ir;
     const double ke = 0.5 * rho * (u * u + v * v + ww * ww);
     const double a1 = q[6];
     const double G = a1 * mix.G1 + (1.0 - a1) * mix.G2;
@@ -440,14 +441,17 @@ __device__ __forceinline__ void hllc_fp64(const Mix<double>& mix, const double w
     Fk[2 + DIR] = Fk[2 + DIR] + p;
     Fk[5] = (E + p) * un;
 
-    const double xi = (S - un) / (S - Ss);
+    // one quotient for xi and the star energy's pressure term, whose
+    // xi (S* - u) p / (S - u) equals (S* - u) p / (S - S*)
+    const double inv = 1.0 / (S - Ss);
+    const double xi = (S - un) * inv;
     Us[0] = xi * w[0];
     Us[1] = xi * w[1];
     Us[2] = xi * (rho * w[2]);
     Us[3] = xi * (rho * w[3]);
     Us[4] = xi * (rho * w[4]);
     Us[2 + DIR] = xi * (rho * Ss);
-    Us[5] = xi * (E + (Ss - un) * (rho * Ss + p / (S - un)));
+    Us[5] = xi * (E + (Ss - un) * (rho * Ss)) + (Ss - un) * (p * inv);
     Us[6] = xi * w[6];
 #pragma unroll
     for (int v = 0; v < NV; ++v) F[v] = Fk[v] + s * (Us[v] - U[v]);
@@ -484,8 +488,8 @@ __device__ __forceinline__ void hllc_fast(const Mix<T>& mix, const T wl[NV], con
     const T S = left ? SL : SR;
     const T s = left ? fmin(T(0), SL) : fmax(T(0), SR);
 
-    const T xi = qdiv(S - un, S - Ss);
-    const T Eratio = qdiv(p, S - un);
+    const T inv = qdiv(T(1), S - Ss);  // as in the float64 flux: one quotient
+    const T xi = (S - un) * inv;
 
     T U[NV], Us[NV];
     U[0] = w[0];
@@ -498,7 +502,7 @@ __device__ __forceinline__ void hllc_fast(const Mix<T>& mix, const T wl[NV], con
 #pragma unroll
     for (int v = 0; v < NV; ++v) Us[v] = xi * U[v];
     Us[2 + DIR] = xi * (rho * Ss);
-    Us[5] = xi * (E + (Ss - un) * (rho * Ss + Eratio));
+    Us[5] = xi * (E + (Ss - un) * (rho * Ss)) + (Ss - un) * (p * inv);
 
     T Fk[NV];
 #pragma unroll
@@ -547,7 +551,8 @@ __device__ __forceinline__ void cons_to_prim_n(const MixN<double, NF>& mix, cons
 #pragma clang fp contract(off)
     using F = Fl<NF>;
     const double rho = density_n<NF>(q);
-    const double u = q[F::IM] / rho, v = q[F::IM + 1] / rho, ww = q[F::IM + 2] / rho;
+    const double ir = 1.0 / rho;
+    const double u = q[F::IM] * ir, v = q[F::IM + 1] * ir, ww = q[F::IM + 2] * ir;
     const double ke = 0.5 * rho * (u * u + v * v + ww * ww);
     double m = q[F::IA] * mix.G[0], s = q[F::IA];
     double mp = q[F::IA] * mix.P[0];
@@ -627,14 +632,17 @@ __device__ __forceinline__ void hllc_fp64_n(const MixN<double, NF>& mix, const d
     Fk[m + DIR] = Fk[m + DIR] + p;
     Fk[L::IE] = (E + p) * un;
 
-    const double xi = (S - un) / (S - Ss);
+    // one quotient for xi and the star energy's pressure term, whose
+    // xi (S* - u) p / (S - u) equals (S* - u) p / (S - S*)
+    const double inv = 1.0 / (S - Ss);
+    const double xi = (S - un) * inv;
 #pragma unroll
     for (int v = 0; v < L::NV; ++v) Us[v] = xi * w[v];
     Us[m] = xi * (rho * w[m]);
     Us[m + 1] = xi * (rho * w[m + 1]);
     Us[m + 2] = xi * (rho * w[m + 2]);
     Us[m + DIR] = xi * (rho * Ss);
-    Us[L::IE] = xi * (E + (Ss - un) * (rho * Ss + p / (S - un)));
+    Us[L::IE] = xi * (E + (Ss - un) * (rho * Ss)) + (Ss - un) * (p * inv);
 #pragma unroll
     for (int v = 0; v < L::NV; ++v) F[v] = Fk[v] + s * (Us[v] - U[v]);
     uf = un + s * (xi - 1.0);
@@ -677,8 +685,8 @@ __device__ __forceinline__ void hllc_fast_n(const MixN<T, NF>& mix, const T* wl,
     const T S = left ? SL : SR;
     const T s = left ? fmin(T(0), SL) : fmax(T(0), SR);
 
-    const T xi = qdiv(S - un, S - Ss);
-    const T Eratio = qdiv(p, S - un);
+    const T inv = qdiv(T(1), S - Ss);  // as in the float64 flux: one quotient
+    const T xi = (S - un) * inv;
 
     T U[L::NV], Us[L::NV];
 #pragma unroll
@@ -690,7 +698,7 @@ __device__ __forceinline__ void hllc_fast_n(const MixN<T, NF>& mix, const T* wl,
 #pragma unroll
     for (int v = 0; v < L::NV; ++v) Us[v] = xi * U[v];
     Us[m + DIR] = xi * (rho * Ss);
-    Us[L::IE] = xi * (E + (Ss - un) * (rho * Ss + Eratio));
+    Us[L::IE] = xi * (E + (Ss - un) * (rho * Ss)) + (Ss - un) * (p * inv);
 
     T Fk[L::NV];
 #pragma unroll

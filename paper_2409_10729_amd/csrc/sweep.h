@@ -174,7 +174,8 @@ __device__ __forceinline__ double cfl_speed(const Grid& g, const double* q, unsi
     double c2, u, v, w, rho;
     if constexpr (F::NF == 2) {
         rho = q[0] + q[1];
-        u = q[2] / rho, v = q[3] / rho, w = q[4] / rho;
+        const double ir = 1.0 / rho;
+        u = q[2] * ir, v = q[3] * ir, w = q[4] * ir;
         const double ke = 0.5 * rho * (u * u + v * v + w * w);
         const double a1 = q[6];
         const double G = a1 * g.G1 + (1.0 - a1) * g.G2;
