@@ -41,21 +41,27 @@ WORKLOADS = {
     "advected_bubble": ("air bubble advected through water at u=(1,0.5,0.25), periodic", 128),
     "shock_droplet_walls": ("Mach-2 air shock on a water droplet (R=0.15), 1% density noise, x inflow at the "
                             "post-shock state / transmissive, y,z reflective walls", 256),
+    "droplet_bubble": ("three fluids: Mach-2 air shock on a water droplet (R=0.15) and a helium bubble "
+                       "(R=0.08), 1% density noise, x transmissive / y,z periodic", 256),
+    "shock_droplet_stretched": ("Mach-2 air shock on a water droplet (R=0.15), 1% density noise, on cells refined "
+                                "around the droplet (tanh stretching, up to 2x finer), x transmissive / y,z "
+                                "periodic", 256),
 }
 
 
-def sweep_bytes_per_cell(first: int, mode: int, rhs_bytes: int = STATE_BYTES) -> int:
+def sweep_bytes_per_cell(first: int, mode: int, rhs_bytes: int = STATE_BYTES, state_bytes: int = STATE_BYTES) -> int:
     """Algorithmic HBM bytes per cell of one sweep launch: read the stage state
     (stencil and, for the stage update, the same cells again: counted once),
     read the partial RHS unless first, write the partial RHS / caller RHS /
     new state, and read the step's initial state in stages 2 and 3.
-    rhs_bytes is the partial-RHS size per cell (56 in FP64, 28 in FP32)."""
-    b = STATE_BYTES  # stage state
+    rhs_bytes is the partial-RHS size per cell (56 in FP64, 28 in FP32 for
+    two fluids); state_bytes the state's (8 per variable)."""
+    b = state_bytes  # stage state
     if not first:
         b += rhs_bytes  # partial RHS in
-    b += rhs_bytes if mode == 0 else STATE_BYTES  # output
+    b += rhs_bytes if mode == 0 else state_bytes  # output
     if mode in (3, 4):
-        b += STATE_BYTES  # q^n for the RK combination
+        b += state_bytes  # q^n for the RK combination
     return b
 
 
@@ -151,6 +157,8 @@ def cpu_baseline(P, q0_np, budget_s: float):
         spec = dict(P["spec"])
         spec["n"] = (nx, ny, k)
         spec["bc"] = (P["spec"]["bc"][0], P["spec"]["bc"][1], (0, 0))
+        if spec.get("faces") is not None and spec["faces"][2] is not None:  # unequal cells: the slab's z faces
+            spec["faces"] = (spec["faces"][0], spec["faces"][1], np.asarray(spec["faces"][2])[:k + 1])
         g = oracle.make_grid(spec)
         q = np.ascontiguousarray(q0_np[:, :k])
         return g, q
@@ -254,9 +262,16 @@ def main():
         P["spec"] = dict(P["spec"], inflow=inflow_states(P["spec"], P["inflow_prim"]))
     N = args.n ** 3
     w_dev = torch.from_numpy(P["w"]).cuda()
+    nv = P["w"].shape[0]  # variables: 7 for two fluids, 9 for three
+    stretched = any(f is not None for f in P["spec"].get("faces") or ())
+    # the byte count per cell follows the variable count; the flop count and
+    # the learned weights are defined for two fluids on equal cells
+    two_fluid_uniform = nv == 7 and not stretched
+    state_bytes = 8 * nv
+    nf = (nv - 3) // 2  # fluids: nf partial densities, 3 momenta, energy, nf - 1 fractions
 
     nets = {}
-    if not args.no_learned:
+    if not args.no_learned and two_fluid_uniform:
         for wmode, path in ((MFX_WENO5_LEARNED, learned.DEFAULT_PARAMS), (MFX_WENO5_LEARNED_EDGE, learned.EDGE_PARAMS)):
             if os.path.exists(path):
                 nets[wmode] = (torch.from_numpy(learned.load_params(path)).cuda(), path)
@@ -299,28 +314,28 @@ def main():
         s = new_solver(precision, weights, order)
         for dt in dts:
             s.rk3_step(dt)
-        q = s.get_state().cpu().numpy().reshape(7, -1)
+        q = s.get_state().cpu().numpy().reshape(nv, -1)
         fb = s.stats()["fallback_faces"]
         s.destroy()
         return q, fb
 
     def l1_vs(q, q64):
         den = np.abs(q64).sum(axis=1)
-        den[2:5] = den[2:5].max()
+        den[nf:nf + 3] = den[nf:nf + 3].max()  # the momenta share one scale
         l1 = (np.abs(q - q64).sum(axis=1) / den).tolist()
-        rho64 = q64[0] + q64[1]
-        rho_l1 = float(np.abs(q[0] + q[1] - rho64).sum() / np.abs(rho64).sum())
+        rho64 = q64[:nf].sum(axis=0)
+        rho_l1 = float(np.abs(q[:nf].sum(axis=0) - rho64).sum() / np.abs(rho64).sum())
         return [float(f"{x:.3e}") for x in l1], float(f"{rho_l1:.3e}")
 
     def kernel_table(prof, ms_total, rhs_bytes, order=5):
         per_dir = {}
         for (d, first, mode), (ms, cnt) in prof.items():
-            b = sweep_bytes_per_cell(first, mode, rhs_bytes) * N
+            b = sweep_bytes_per_cell(first, mode, rhs_bytes, state_bytes) * N
             e = per_dir.setdefault(d, {"ms": 0.0, "launches": 0, "bytes": 0, "flops": 0})
             e["ms"] += ms
             e["launches"] += cnt
             e["bytes"] += b * cnt
-            e["flops"] += sweep_flops_per_cell(d, mode, order) * N * cnt
+            e["flops"] += sweep_flops_per_cell(d, mode, order) * N * cnt if two_fluid_uniform else 0
         kernels = {}
         for d, e in sorted(per_dir.items()):
             mean_ms = e["ms"] / e["launches"]
@@ -332,10 +347,13 @@ def main():
                 "share": round(e["ms"] / ms_total, 4),
                 "alg_bytes_per_launch": bpl,
                 "achieved_GBs": round(bpl / (mean_ms * 1e-3) / 1e9, 1),
-                "alg_flops_per_launch": fpl,
-                "achieved_TFLOPs": round(fpl / (mean_ms * 1e-3) / 1e12, 2),
-                "flop_per_byte": round(fpl / bpl, 2),
             }
+            if two_fluid_uniform:
+                kernels[KERNEL_NAMES[d]].update({
+                    "alg_flops_per_launch": fpl,
+                    "achieved_TFLOPs": round(fpl / (mean_ms * 1e-3) / 1e12, 2),
+                    "flop_per_byte": round(fpl / bpl, 2),
+                })
         step_bytes = sum(e["bytes"] for e in per_dir.values()) / args.steps
         return kernels, step_bytes
 
@@ -344,29 +362,36 @@ def main():
     ms_total, prof = time_form(MFX_FP64, 0.0)
     ms_step = ms_total / args.steps
     grind = ms_step * 1e6 / (N * 3)
-    kernels, step_bytes = kernel_table(prof, ms_total, STATE_BYTES)
+    kernels, step_bytes = kernel_table(prof, ms_total, state_bytes)
     print(f"[bench] fp64: {ms_step:.3f} ms/step, {grind:.4f} ns/cell/stage", file=sys.stderr, flush=True)
     dom = max(kernels, key=lambda k: kernels[k]["mean_us"] * kernels[k]["launches"])
     kd = kernels[dom]
-    # the dominant kernel's bound by its arithmetic intensity against the
-    # ridge point of the float64 vector peak and HBM bandwidth
-    ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
-    if kd["flop_per_byte"] >= ridge:
-        roofline = {"bound": "alu", "achieved": kd["achieved_TFLOPs"], "peak": FP64_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(kd["achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4)}
+    if two_fluid_uniform:
+        # the dominant kernel's bound by its arithmetic intensity against the
+        # ridge point of the float64 vector peak and HBM bandwidth
+        ridge = FP64_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)
+        if kd["flop_per_byte"] >= ridge:
+            roofline = {"bound": "alu", "achieved": kd["achieved_TFLOPs"], "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": round(kd["achieved_TFLOPs"] / FP64_PEAK_TFLOPS, 4)}
+        else:
+            roofline = {"bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4)}
+        roofline.update({
+            "traffic": load_traffic(dom),
+            "kernel": dom,
+            "mean_us": kd["mean_us"],
+            "alg_bytes_per_launch": kd["alg_bytes_per_launch"],
+            "alg_flops_per_launch": kd["alg_flops_per_launch"],
+            "flop_per_byte": kd["flop_per_byte"],
+            "ridge_flop_per_byte": round(ridge, 2),
+            "hbm_frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4),
+        })
     else:
+        # (the flop count per cell is written for two fluids on equal cells)
         roofline = {"bound": "hbm", "achieved": kd["achieved_GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4)}
-    roofline.update({
-        "traffic": load_traffic(dom),
-        "kernel": dom,
-        "mean_us": kd["mean_us"],
-        "alg_bytes_per_launch": kd["alg_bytes_per_launch"],
-        "alg_flops_per_launch": kd["alg_flops_per_launch"],
-        "flop_per_byte": kd["flop_per_byte"],
-        "ridge_flop_per_byte": round(ridge, 2),
-        "hbm_frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4),
-    })
+                    "frac": round(kd["achieved_GBs"] / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                    "mean_us": kd["mean_us"], "alg_bytes_per_launch": kd["alg_bytes_per_launch"],
+                    "note": "algorithmic bytes only: the flop model covers two fluids on equal cells"}
 
     forms = {"fp64": {"ms_per_step": round(ms_step, 4), "grind": round(grind, 5), "kernels": kernels,
                       "step_alg_bytes_hbm_frac": round(step_bytes / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
@@ -378,7 +403,7 @@ def main():
         s64 = new_solver(MFX_FP64)
         if args.compare_steps > 0:
             dts = [s64.rk3_step(sync=True) for _ in range(args.compare_steps)]
-            q64 = s64.get_state().cpu().numpy().reshape(7, -1)
+            q64 = s64.get_state().cpu().numpy().reshape(nv, -1)
         else:
             # timing only (e.g. under a profiler): the forms run at the first
             # CFL step, with no accuracy comparison
@@ -389,8 +414,9 @@ def main():
         # (name, precision, weights, WENO order); fp64_weno3 (third order) and
         # fp64_wenoz (WENO-Z weights) are different schemes: their L1
         # distance to the fifth-order Jiang-Shu run is a scheme difference
-        variants = [("fp32_mixed", MFX_FP32_MIXED, MFX_WENO5_JS, 5), ("fp64_weno3", MFX_FP64, MFX_WENO5_JS, 3),
-                    ("fp64_wenoz", MFX_FP64, MFX_WENO5_Z, 5)]
+        variants = [("fp32_mixed", MFX_FP32_MIXED, MFX_WENO5_JS, 5)]
+        if not stretched:  # (unequal cells take WENO5 with Jiang-Shu weights)
+            variants += [("fp64_weno3", MFX_FP64, MFX_WENO5_JS, 3), ("fp64_wenoz", MFX_FP64, MFX_WENO5_Z, 5)]
         if MFX_WENO5_LEARNED in nets:
             variants.append(("learned", MFX_FP32_MIXED, MFX_WENO5_LEARNED, 5))
         if MFX_WENO5_LEARNED_EDGE in nets:
@@ -411,7 +437,7 @@ def main():
             print(f"[bench] {name}: timing {args.steps} steps", file=sys.stderr, flush=True)
             ms_f, prof_f = time_form(prec, dt_fixed, weights, order)
             msf_step = ms_f / args.steps
-            kf, _ = kernel_table(prof_f, ms_f, 56 if prec == MFX_FP64 else 28, order)
+            kf, _ = kernel_table(prof_f, ms_f, state_bytes if prec == MFX_FP64 else 4 * nv, order)
             forms[name] = {
                 "ms_per_step": round(msf_step, 4),
                 "grind": round(msf_step * 1e6 / (N * 3), 5),
@@ -452,7 +478,7 @@ def main():
             "seed": args.seed,
             "precision": "fp64",
         },
-        "grind_ns_per_cell_pde_rhs": round(grind / 7, 6),
+        "grind_ns_per_cell_pde_rhs": round(grind / nv, 6),
         "roofline": roofline,
         "forms": forms,
     }

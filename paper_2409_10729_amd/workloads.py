@@ -16,6 +16,8 @@ shock-bubble-cloud runs; these are single-GPU blocks of the same physics):
   shock_tube      1D water|air tube, 1000 cells, transmissive
   advected_bubble 3D periodic air bubble in water, uniform velocity
   shock_droplet   3D Mach-2 air shock on a water droplet with 1% density noise
+  shock_droplet_stretched
+                  the same on a grid refined around the droplet (tanh)
   bubble_cloud    3D Mach-1.5 water shock on several air bubbles
   droplet_cloud   3D Mach-2 air shock on many log-uniform droplets
   random_smooth   small random valid states for RHS parity
@@ -455,6 +457,39 @@ def tanh_faces(n, centre=0.5, depth=0.5, sharpness=8.0, lo=0.0, hi=1.0):
     out = lo + (hi - lo) * x
     out[0], out[-1] = lo, hi
     return out
+
+
+def shock_droplet_stretched(n=256, seed=0, mach=2.0, radius=0.15, noise=0.01, depth=0.5, sharpness=8.0):
+    """The shock_droplet problem on a grid refined around the droplet in all
+    three directions: faces from tanh_faces centred on the droplet centre
+    (cells there finer by up to 1 - depth), the fields evaluated at the
+    stretched cell centres, the shock 4 of the finest cells upstream of the
+    droplet; x transmissive, y/z periodic."""
+    n3 = (n, n, n) if np.isscalar(n) else tuple(n)
+    rng = np.random.default_rng(seed)
+    c = 0.5 + rng.uniform(-0.05, 0.05, size=3)
+    faces = [tanh_faces(n3[d], centre=c[d], depth=depth, sharpness=sharpness) for d in range(3)]
+    s = spec(n3, ((TRANSMISSIVE, TRANSMISSIVE), (PERIODIC, PERIODIC), (PERIODIC, PERIODIC)))
+    s["faces"] = tuple(faces)
+    xc, yc, zc = (0.5 * (f[1:] + f[:-1]) for f in faces)
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    h = float(min(np.diff(f).min() for f in faces))
+    r = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2)
+    water = _smooth_indicator(r, radius, 1.5 * h)
+    a1 = ALPHA_EPS + (1.0 - 2.0 * ALPHA_EPS) * water
+    rho_a1, p_a1 = 1.2, 1.0e5
+    rho_a2, p_a2, u_a2 = _ideal_gas_shock(mach, rho_a1, p_a1, AIR[0])
+    xs = c[0] - radius - 4.0 * h
+    post = X < xs
+    rho_air = np.where(post, rho_a2, rho_a1)
+    p = np.where(post, p_a2, p_a1)
+    u = np.where(post, u_a2, 0.0)
+    w = _pack(a1, 1000.0, rho_air, u, 0.0, 0.0, p)
+    f = _noise(rng, a1.shape, noise)
+    w[0] *= f
+    w[1] *= f
+    return {"name": "shock_droplet_stretched", "spec": s, "w": w,
+            "meta": {"centre": c.tolist(), "radius": radius, "shock_x": xs, "finest_width": h}}
 
 
 def stretched(P, faces):
