@@ -128,8 +128,8 @@ typedef struct {
                            holds nf partial densities, the momentum, the energy and the volume
                            fractions alpha_1 .. alpha_{nf-1} (alpha_nf = 1 - their sum), the mixture
                            rules stay linear in every fraction and every fraction carries its
-                           alpha_i div(u) source.  More than two fluids: Jiang-Shu or WENO-Z
-                           weights (the learned weights are for two), marching x sweep */
+                           alpha_i div(u) source.  More than two fluids: Jiang-Shu-family
+                           weights (the learned weights are for two) */
     const double* faces[3]; /* unequal cell widths along a direction (Sec. III-A: a structured mesh
                            refined locally, e.g. by hyperbolic-tangent stretching): a HOST pointer
                            to the n[d] + 1 face coordinates of direction d, finite and strictly
@@ -330,9 +330,10 @@ const char* mfx_mlp_last_error(void);
  * the summed event time in milliseconds and the launch count since the
  * last mfx_profile call; kind = (direction * 2 + first_pass) * 5 + output,
  * output 0 partial RHS, 1 caller RHS, 2/3/4 RK stage 1/2/3; direction 3
- * is the fused x-y pass (x and y in one kernel, used when both are active,
- * nx <= 512 and the weights are Jiang-Shu; MFX_FUSE_XY=0 in the environment
- * at mfx_init_grid turns it off).  Arrays hold MFX_PROF_KINDS entries;
+ * is the fused x-y pass (x and y in one kernel, used when both are active
+ * with equal cells, an x row fits the row kernel (nx <= 512), the weights
+ * are Jiang-Shu-family and the model is not three fluids in float64;
+ * MFX_FUSE_XY=0 in the environment at mfx_init_grid turns it off).  Arrays hold MFX_PROF_KINDS entries;
  * either may be NULL. */
 #define MFX_PROF_KINDS 40
 int mfx_profile(mfx_ctx* ctx, int enable);

@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 OUT = os.path.join(HERE, "libmfx.so")
 SOURCES = ["mfx.hip", "learned.hip", "k_fp64.hip", "k_fp32.hip", "k_nf3_fp64.hip", "k_nf3_fp32.hip",
-           "k_learned.hip", "k_xy_double.hip", "k_xy_float.hip"]
+           "k_learned.hip", "k_xy_double.hip", "k_xy_float.hip", "k_xy_nf3.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 ARCH = ["--offload-arch=gfx950"]

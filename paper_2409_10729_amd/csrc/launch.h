@@ -60,8 +60,8 @@ struct XYArgs {
 template <typename T, bool L, int SCHEME, class F>
 void launch_dispatch(int d, bool first, int mode, const LaunchArgs& a);
 
-// The fused x-y pass (two fluids, equal cells, Jiang-Shu or WENO-Z weights).
-template <typename T, int SCHEME>
+// The fused x-y pass (equal cells, Jiang-Shu-family weights); F: fluid model.
+template <typename T, int SCHEME, class F>
 void launch_xy(int mode, const XYArgs& a);
 
 }  // namespace mfx

@@ -10,23 +10,21 @@ namespace mfx {
 
 // The x row sweep reads the boundary faces that boundary_faces_x leaves in
 // `bface` (launched just before it on the same stream).
-// F: the fluid model (two fluids, or Fl<3> with the marching x sweep only).
+// F: the fluid model (Fl2 or Fl<3>).
 template <int DIR, typename T, bool FIRST, int MODE, bool L, int SCHEME, class F>
 void launch_one(const LaunchArgs& a)
 {
     const SweepGeom& sg = *a.sg;
     T* r = static_cast<T*>(a.r);
     if constexpr (DIR == 0) {
-        if constexpr (F::NF == 2 && SCHEME != SCHEME_WENO5NU) {
-            if (sg.xrows) {
-                T* bf = static_cast<T*>(a.bface);
-                const long long rows = (long long)a.g->n[1] * a.g->n[2];
-                boundary_faces_x<T, L, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf,
-                                                                                                 a.mlp, a.fb);
-                sweep_x_rows<T, FIRST, MODE, L, SCHEME><<<sg.grid, sg.block, sg.lds, a.st>>>(
-                    *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.mlp, a.fb);
-                return;
-            }
+        if (sg.xrows) {
+            T* bf = static_cast<T*>(a.bface);
+            const long long rows = (long long)a.g->n[1] * a.g->n[2];
+            boundary_faces_x<T, L, SCHEME, F><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(*a.g, a.qs, bf,
+                                                                                                a.mlp, a.fb);
+            sweep_x_rows<T, FIRST, MODE, L, SCHEME, F><<<sg.grid, sg.block, sg.lds, a.st>>>(
+                *a.g, a.qs, a.qn, r, a.out, sg.seg, bf, a.dt_dev, a.dt_arg, a.mlp, a.fb);
+            return;
         }
         sweep_x_march<T, FIRST, MODE, L, SCHEME, F><<<sg.grid, XROWS, 0, a.st>>>(
             *a.g, a.qs, a.qn, r, a.out, sg.seg, a.dt_dev, a.dt_arg, a.mlp, a.fb);
@@ -67,7 +65,7 @@ void launch_dispatch(int d, bool first, int mode, const LaunchArgs& a)
         first ? launch_mode<2, T, true, L, SCHEME, F>(mode, a) : launch_mode<2, T, false, L, SCHEME, F>(mode, a);
 }
 
-template <typename T, int MODE, int SCHEME>
+template <typename T, int MODE, int SCHEME, class F>
 void launch_xy_mode(const XYArgs& a)
 {
     const Grid& g = *a.g;
@@ -80,21 +78,21 @@ void launch_xy_mode(const XYArgs& a)
     const dim3 grid(1, (unsigned)g.n[2], (unsigned)((g.n[1] + seg - 1) / seg));
     const int block = 64 * ((g.n[0] + 63) / 64);
     T* bf = static_cast<T*>(a.bface);
-    boundary_faces_x<T, false, SCHEME><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(g, a.qs, bf, a.mlp, a.fb);
-    const size_t lds = xrow_lds_bytes(g.n[0], sizeof(T));
-    sweep_xy<T, MODE, SCHEME><<<grid, block, lds, a.st>>>(g, a.qs, a.qn, static_cast<T*>(a.r), a.out, seg, bf,
+    boundary_faces_x<T, false, SCHEME, F><<<(unsigned)((rows + 255) / 256), 256, 0, a.st>>>(g, a.qs, bf, a.mlp, a.fb);
+    const size_t lds = xrow_lds_bytes(g.n[0], sizeof(T), F::NV);
+    sweep_xy<T, MODE, SCHEME, F><<<grid, block, lds, a.st>>>(g, a.qs, a.qn, static_cast<T*>(a.r), a.out, seg, bf,
                                                           a.dt_dev, a.dt_arg);
 }
 
-template <typename T, int SCHEME>
+template <typename T, int SCHEME, class F>
 void launch_xy(int mode, const XYArgs& a)
 {
     switch (mode) {
-    case OUT_ACCUM: launch_xy_mode<T, OUT_ACCUM, SCHEME>(a); break;
-    case OUT_RHS: launch_xy_mode<T, OUT_RHS, SCHEME>(a); break;
-    case OUT_STAGE1: launch_xy_mode<T, OUT_STAGE1, SCHEME>(a); break;
-    case OUT_STAGE2: launch_xy_mode<T, OUT_STAGE2, SCHEME>(a); break;
-    default: launch_xy_mode<T, OUT_STAGE3, SCHEME>(a); break;
+    case OUT_ACCUM: launch_xy_mode<T, OUT_ACCUM, SCHEME, F>(a); break;
+    case OUT_RHS: launch_xy_mode<T, OUT_RHS, SCHEME, F>(a); break;
+    case OUT_STAGE1: launch_xy_mode<T, OUT_STAGE1, SCHEME, F>(a); break;
+    case OUT_STAGE2: launch_xy_mode<T, OUT_STAGE2, SCHEME, F>(a); break;
+    default: launch_xy_mode<T, OUT_STAGE3, SCHEME, F>(a); break;
     }
 }
 

@@ -67,42 +67,40 @@ struct Layout {
 };
 
 // The x sweep takes whole rows when a row fits the row kernel (nx <=
-// XROW_MAX and its LDS fits a workgroup), else it marches along x.
-// (x_mode() below sends an inflow x side with aliased row buffers to the
-// march: the row kernels write inflow ghost slots once per block.)
-bool use_xrows(const int n[3], int mode_override, size_t elem)
+// XROW_MAX and its LDS, for nv variables, fits a workgroup), else it
+// marches along x.  (x_mode() below sends an inflow x side with aliased
+// row buffers to the march: the row kernels write inflow ghost slots once
+// per block.)
+bool use_xrows(const int n[3], int mode_override, size_t elem, int nv)
 {
     if (mode_override == 1) return false;
-    return n[0] <= XROW_MAX && xrow_lds_bytes(n[0], elem) <= 64 * 1024;
+    return n[0] <= XROW_MAX && xrow_lds_bytes(n[0], elem, nv) <= 64 * 1024;
 }
 
 // x sweep mode for a descriptor: the override, or the march (1) when an x
-// side is inflow and the row buffers would be aliased, for more than two
-// fluids, or for unequal cells along x.
+// side is inflow and the row buffers would be aliased.
 int x_mode(const mfx_grid_desc* d, int xmode_override)
 {
-    if (fluids_of(d) != 2) return 1;  // the row kernels are written for two fluids
-    if (d->faces[0]) return 1;        // unequal cells along x: the marching pass reads per-position tables
     const size_t elem = d->precision == MFX_FP32_MIXED ? sizeof(float) : sizeof(double);
     const bool inflow_x = d->bc[0][0] == MFX_BC_INFLOW || d->bc[0][1] == MFX_BC_INFLOW;
-    if (inflow_x && d->n[0] <= XROW_MAX && xrow_layout(d->n[0], elem).alias) return 1;
+    if (inflow_x && d->n[0] <= XROW_MAX && xrow_layout(d->n[0], elem, vars_of(d)).alias) return 1;
     return xmode_override;
 }
 
-SweepGeom sweep_geom(const int n[3], int d, int seg_override, int xmode_override, size_t elem, bool learned)
+SweepGeom sweep_geom(const int n[3], int d, int seg_override, int xmode_override, size_t elem, bool learned, int nv)
 {
     int seg = seg_override > 0 ? seg_override : 64;
     SweepGeom g;
     g.lds = 0;
     g.xrows = false;
-    if (d == 0 && use_xrows(n, xmode_override, elem)) {
+    if (d == 0 && use_xrows(n, xmode_override, elem, nv)) {
         const long long rows = (long long)n[1] * n[2];
         // about 2048 blocks, at least one row each
         const long long rpb = std::max<long long>(1, rows / 2048);
         g.grid = dim3((unsigned)((rows + rpb - 1) / rpb), 1, 1);
         g.block = 64 * ((n[0] + 63) / 64);
         g.seg = (int)rpb;
-        g.lds = xrow_lds_bytes(n[0], elem);
+        g.lds = xrow_lds_bytes(n[0], elem, nv);
         g.xrows = true;
     } else if (d == 0) {
         // blocks of XROWS rows (y,z flattened), segments along x
@@ -137,7 +135,7 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     // blocks of a y/z sweep that reduces the new state of a step
     long long np = CFL_BLOCKS;
     for (int dd = 1; dd < 3; ++dd) {
-        const SweepGeom sg = sweep_geom(d->n, dd, seg_override, xmode_override, elem, false);
+        const SweepGeom sg = sweep_geom(d->n, dd, seg_override, xmode_override, elem, false, (int)nv);
         np = std::max<long long>(np, (long long)sg.grid.x * sg.grid.y * sg.grid.z);
     }
     const long long nrows = (long long)d->n[1] * d->n[2];
@@ -157,7 +155,7 @@ Layout make_layout(const mfx_grid_desc* d, int seg_override, int xmode_override)
     L.partial = off;
     off += align_up(sizeof(double) * (size_t)np);
     L.bface = off;
-    off += align_up(elem * BFACE * 2 * (size_t)nrows);
+    off += align_up(elem * (nv + 1) * 2 * (size_t)nrows);  // flux components and face velocity per face
     L.mlp = off;
     off += align_up(sizeof(MlpNet));
     L.mlp_params = off;
@@ -642,7 +640,7 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
                  const double* dt_dev, double dt_arg, bool cfl = false)
 {
     SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem,
-                              learned_weights(c->desc));
+                              learned_weights(c->desc), vars_of(&c->desc));
     mfx_ctx::Pending pend{(d * 2 + (first ? 1 : 0)) * 5 + mode, nullptr, nullptr};
     if (c->profiling) {
         pend.a = take_event(c);
@@ -675,12 +673,15 @@ int launch_sweep(mfx_ctx* c, int d, const double* qs, const double* qn, double* 
 }
 
 // The fused x-y pass applies when x and y are the first two active
-// directions, x rows fit the row kernel, the weights are Jiang-Shu and the
-// cells are equal along x and y.
+// directions, x rows fit the row kernel, the weights are Jiang-Shu-family and
+// the cells are equal along x and y.  Three fluids in float64 keep the
+// separate x row and y passes: the fused pass holds its five-cell window in
+// registers (90 for nine float64 variables) and would spill.
 bool fused_xy(const mfx_ctx* c)
 {
-    return c->fuse_xy && !learned_weights(c->desc) && c->g.nf == 2 && c->ndirs >= 2 && c->dirs[0] == 0 && c->dirs[1] == 1 &&
-           !c->g.nu[0] && !c->g.nu[1] && use_xrows(c->g.n, c->xmode_override, c->elem);
+    if (c->g.nf == 3 && c->elem == sizeof(double)) return false;
+    return c->fuse_xy && !learned_weights(c->desc) && c->ndirs >= 2 && c->dirs[0] == 0 && c->dirs[1] == 1 &&
+           !c->g.nu[0] && !c->g.nu[1] && use_xrows(c->g.n, c->xmode_override, c->elem, vars_of(&c->desc));
 }
 
 // The fused pass, profiled as direction 3 (first pass).
@@ -695,10 +696,13 @@ int launch_sweep_xy(mfx_ctx* c, const double* qs, const double* qn, double* out,
         HIP_TRY(c, hipEventRecord(pend.a, c->stream));
     }
     const XYArgs xa{&c->g, c->stream, qs, qn, c->r, out, dt_dev, dt_arg, c->bface, c->mlp, c->fallback, c->seg_override};
-    if (c->desc.precision == MFX_FP32_MIXED)
-        by_scheme<false>(scheme_of(c->desc), [&](auto s) { launch_xy<float, decltype(s)::value>(mode, xa); });
+    const bool f32 = c->desc.precision == MFX_FP32_MIXED;
+    if (c->g.nf == 3)  // (float only: see fused_xy)
+        by_scheme<false>(scheme_of(c->desc), [&](auto s) { launch_xy<float, decltype(s)::value, Fl<3>>(mode, xa); });
+    else if (f32)
+        by_scheme<false>(scheme_of(c->desc), [&](auto s) { launch_xy<float, decltype(s)::value, Fl2>(mode, xa); });
     else
-        by_scheme<false>(scheme_of(c->desc), [&](auto s) { launch_xy<double, decltype(s)::value>(mode, xa); });
+        by_scheme<false>(scheme_of(c->desc), [&](auto s) { launch_xy<double, decltype(s)::value, Fl2>(mode, xa); });
     int rc = launch_check(c, "fused x-y sweep");
     if (rc) return rc;
     if (c->profiling) {
@@ -718,7 +722,7 @@ long long cfl_blocks_in_last_pass(const mfx_ctx* c)
     const int d = c->dirs[c->ndirs - 1];
     if (d == 0 || !c->g.active[d]) return 0;
     if (fused_xy(c) && c->ndirs == 2) return 0;  // the fused x-y pass is the last
-    const SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem, false);
+    const SweepGeom sg = sweep_geom(c->g.n, d, c->seg_override, c->xmode_override, c->elem, false, vars_of(&c->desc));
     return (long long)sg.grid.x * sg.grid.y * sg.grid.z;
 }
 
@@ -1166,7 +1170,7 @@ void* g_scratch_ptr[MAX_DEVICES] = {};
 
 size_t static_bface_bytes(const mfx_grid_desc* d, size_t elem)
 {
-    return align_up(elem * BFACE * 2 * (size_t)d->n[1] * (size_t)d->n[2]);
+    return align_up(elem * (vars_of(d) + 1) * 2 * (size_t)d->n[1] * (size_t)d->n[2]);
 }
 
 size_t static_need(const mfx_grid_desc* d)

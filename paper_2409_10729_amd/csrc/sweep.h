@@ -504,7 +504,7 @@ enum : int {
     SCHEME_WENO3 = 3,   // WENO3, Jiang-Shu weights, on the middle three cells
     SCHEME_WENO5 = 5,   // WENO5, Jiang-Shu weights
     SCHEME_WENO5Z = 6,  // WENO5, WENO-Z weights (comparison form)
-    SCHEME_WENO5NU = 7, // WENO5, Jiang-Shu weights, on unequal cells (marching sweeps only)
+    SCHEME_WENO5NU = 7, // WENO5, Jiang-Shu weights, on unequal cells (not the fused x-y pass)
 };
 
 // Reconstruction of one cell's two edge states (all seven primitives) from
@@ -547,7 +547,8 @@ struct ReconJS {
 
 // Unequal cells along the sweep: at(c) loads the coefficients of stencil
 // position c from the direction's table (the same position on every lane of
-// a marching sweep, so the loads are uniform), the flux difference of cell c
+// a marching sweep, so the loads are uniform; in the x row kernel each lane
+// loads its own position once per block), the flux difference of cell c
 // divides by its own width.
 template <typename T>
 struct ReconJS<T, SCHEME_WENO5NU> {

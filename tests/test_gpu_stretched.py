@@ -2,14 +2,17 @@
 hyperbolic-tangent stretching) on the HIP path against the oracle, through
 the C ABI.
 
-A direction with unequal cells runs the marching sweep with per-position
-coefficient tables (x: the marching x sweep; y, z: the y/z sweeps), its flux
-differences divide by each cell's width, and the CFL reduction reads each
-cell's widths.  Covered: stretching along x, y or z alone (next to the fused
-x-y pass and the row kernels of equal directions) and along all three; every
-boundary type (ghost cells take the widths the boundary rule maps them to);
-short segments (tables read at segment starts); the float form; three
-fluids; a multi-step shock tube refined at its interface.  Bar: FP64 relative
+A direction with unequal cells reads per-position coefficient tables (x:
+the x row kernel, each lane with its own position's coefficients, or the
+marching x sweep; y, z: the y/z sweeps), its flux differences divide by
+each cell's width, and the CFL reduction reads each cell's widths.
+Covered: stretching along x, y or z alone (next to the fused x-y pass and
+the row kernels of equal directions) and along all three; every boundary
+type (ghost cells take the widths the boundary rule maps them to); short
+segments (tables read at segment starts); the marching x sweep forced, for
+rows longer than the row kernel takes and for an inflow side with shared
+row buffers; the float form; three fluids; a multi-step shock tube refined
+at its interface.  Bar: FP64 relative
 1e-12 (both right-hand-side scales, and the state after a step); the time
 step equal to the oracle's; the float form 1e-5 of the flux scale.
 """
@@ -54,7 +57,7 @@ def _inflow_states(seed, nf=2):
 
 # (n, bc, stretched directions, seed)
 CASES = [
-    ((40, 24, 20), ((T_, T_), (P_, P_), (P_, P_)), (0,), 80),        # x march with tables; y, z equal
+    ((40, 24, 20), ((T_, T_), (P_, P_), (P_, P_)), (0,), 80),        # x rows with tables; y, z equal
     ((48, 36, 16), ((P_, P_), (T_, R_), (P_, P_)), (1,), 81),        # x rows (equal) + y with tables
     ((33, 20, 40), ((R_, T_), (P_, P_), (T_, T_)), (2,), 82),        # fused x-y pass + z with tables
     ((26, 22, 30), ((I_, T_), (P_, P_), (R_, I_)), (0, 1, 2), 83),   # all three, every boundary type
@@ -62,6 +65,8 @@ CASES = [
     ((200, 1, 1), ((T_, T_), (P_, P_), (P_, P_)), (0,), 85),         # 1D
     ((64, 48, 1), ((R_, R_), (R_, R_), (P_, P_)), (1,), 86),         # x-y plane, walls
     ((5, 40, 7), ((R_, I_), (I_, R_), (T_, R_)), (0, 2), 87),        # short rows between walls
+    ((600, 3, 2), ((T_, T_), (P_, P_), (P_, P_)), (0,), 88),         # rows too long: x march with tables
+    ((400, 2, 3), ((I_, T_), (P_, P_), (P_, P_)), (0, 1), 89),       # float64: inflow, shared row buffers: march
 ]
 
 
@@ -76,13 +81,15 @@ def _setup(n, bc, which, seed):
     return spec, g, oracle.prim_to_cons(g, P["w"])
 
 
-@pytest.mark.parametrize("seg", [None, 8])
+@pytest.mark.parametrize("seg,xsweep", [(None, None), (8, None), (None, "march")])
 @pytest.mark.parametrize("n,bc,which,seed", CASES)
-def test_stretched_rhs_and_step_match_oracle(monkeypatch, n, bc, which, seed, seg):
+def test_stretched_rhs_and_step_match_oracle(monkeypatch, n, bc, which, seed, seg, xsweep):
     if seg is not None:
         monkeypatch.setenv("MFX_SWEEP_SEG", str(seg))
+    if xsweep is not None:
+        monkeypatch.setenv("MFX_XSWEEP", xsweep)
     spec, g, q0 = _setup(n, bc, which, seed)
-    print(f"case n={n} bc={bc} stretched={which} seed={seed} seg={seg}", flush=True)
+    print(f"case n={n} bc={bc} stretched={which} seed={seed} seg={seg} x sweep={xsweep}", flush=True)
     s = gpu_solver(spec, q0=q0)
     r_ref = oracle.rhs(g, q0)
     err, errp = fp64_rhs_errors(s.rhs().cpu().numpy(), r_ref, q0, spec)
@@ -98,13 +105,39 @@ def test_stretched_rhs_and_step_match_oracle(monkeypatch, n, bc, which, seed, se
     assert np.all(err <= TOL), err
 
 
-@pytest.mark.parametrize("n,bc,which,seed", CASES[:4])
+@pytest.mark.parametrize("n,bc,which,seed", CASES[:4] + CASES[-1:])
 def test_stretched_float_form_matches_oracle(n, bc, which, seed):
     spec, g, q0 = _setup(n, bc, which, seed)
     s32 = gpu_solver(spec, q0=q0, precision=MFX_FP32_MIXED)
     err32 = rhs_rel_linf(s32.rhs().cpu().numpy(), oracle.rhs(g, q0), q0, spec)
     _report("stretched rhs float form", err32)
     assert np.all(err32 <= 1e-5), err32
+
+
+def test_full_size_stretched_rhs_sampled():
+    """256^3 shock droplet on cells stretched in all three directions
+    (finest cells at the droplet), in the benchmark's launch configuration:
+    the right-hand side and one CFL step on sampled cells."""
+    P = wl.shock_droplet_stretched(n=256, seed=0)
+    spec = P["spec"]
+    g = oracle.make_grid(spec)
+    q0 = oracle.prim_to_cons(g, P["w"])
+    del P
+    s = gpu_solver(spec, q0=q0)
+    r = s.rhs().cpu().numpy().reshape(7, -1)
+    cells = sample_cells(spec, 3000, seed=5, q0=q0)
+    err, errp = fp64_rhs_errors(r[:, cells], oracle.rhs_at(g, q0, cells).T, q0, spec)
+    _report(f"stretched rhs 256^3 on {cells.size} cells", err)
+    _report(f"stretched rhs 256^3 on {cells.size} cells (physical-flux scale)", errp)
+    assert np.all(err <= TOL) and np.all(errp <= TOL), (err, errp)
+    dt = s.rk3_step(sync=True)
+    assert dt == pytest.approx(oracle.cfl_dt(g, q0), rel=1e-15)
+    q = s.get_state().cpu().numpy().reshape(7, -1)
+    s.destroy()
+    cells = sample_cells(spec, 200, seed=6, q0=q0)
+    err = rel_linf(q[:, cells], oracle_step_at(spec, q0, cells, dt))
+    _report(f"stretched step 256^3 on {cells.size} cells", err)
+    assert np.all(err <= TOL), err
 
 
 @pytest.mark.parametrize("which", [(0,), (1, 2), (0, 1, 2)])
