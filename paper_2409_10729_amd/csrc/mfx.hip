@@ -514,9 +514,7 @@ __global__ void __launch_bounds__(UTIL_BLOCK) cfl_partial_kernel(Grid g, const d
         double hw[3];
         const double* hp = nullptr;
         if (g.nonuniform) {  // the cell's own widths where a direction has unequal cells
-            const long long pos[3] = {c % g.n[0], (c / g.n[0]) % g.n[1], c / g.stride[2]};
-#pragma unroll
-            for (int d = 0; d < 3; ++d) hw[d] = g.nu[d] ? g.nu[d][(pos[d] + 1) * NU_K + NU_H] : g.dx[d];
+            cell_widths(g, c, hw);
             hp = hw;
         }
         smax = fmax(smax, cfl_speed<F>(g, qc, bad, hp));
@@ -714,11 +712,11 @@ int launch_sweep_xy(mfx_ctx* c, const double* qs, const double* qn, double* out,
 
 // Blocks of the last pass when that pass (a y or z sweep with Jiang-Shu
 // weights writing a step's new state) also reduces the CFL speed of its
-// output; 0 when the standalone reduction is needed.
+// output (on unequal cells with each cell's widths, as the standalone
+// reduction); 0 when the standalone reduction is needed.
 long long cfl_blocks_in_last_pass(const mfx_ctx* c)
 {
-    // (unequal cells: the standalone reduction reads each cell's widths)
-    if (!c->fuse_cfl || learned_weights(c->desc) || c->g.nonuniform) return 0;
+    if (!c->fuse_cfl || learned_weights(c->desc)) return 0;
     const int d = c->dirs[c->ndirs - 1];
     if (d == 0 || !c->g.active[d]) return 0;
     if (fused_xy(c) && c->ndirs == 2) return 0;  // the fused x-y pass is the last

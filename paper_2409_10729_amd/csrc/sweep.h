@@ -230,18 +230,34 @@ enum : int {
     CHK_CFL = 2,    // the CFL maximum and every status bit (stage 3)
 };
 
+// Widths of cell `cell` per direction (the table's width where the
+// direction has unequal cells, else g.dx).
+__device__ __forceinline__ void cell_widths(const Grid& g, long long cell, double hw[3])
+{
+    const long long pos[3] = {cell % g.n[0], (cell / g.n[0]) % g.n[1], cell / g.stride[2]};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) hw[d] = g.nu[d] ? g.nu[d][(pos[d] + 1) * NU_K + NU_H] : g.dx[d];
+}
+
 // Running CFL maximum and validity flags of the cells a lane writes.
 template <class F = Fl2>
 struct CflAcc {
     double smax;
     unsigned bad;
     bool cfl;  // false: only the status bits, no CFL speed
-    __device__ __forceinline__ void add(const Grid& g, const double* q)
+    __device__ __forceinline__ void add(const Grid& g, const double* q, long long cell)
     {
-        if (cfl)
-            smax = fmax(smax, cfl_speed<F>(g, q, bad));
-        else
+        if (cfl) {
+            if (g.nonuniform) {  // the cell's own widths
+                double hw[3];
+                cell_widths(g, cell, hw);
+                smax = fmax(smax, cfl_speed<F>(g, q, bad, hw));
+            } else {
+                smax = fmax(smax, cfl_speed<F>(g, q, bad));
+            }
+        } else {
             bad |= state_bits<F>(q);
+        }
     }
 };
 
@@ -316,7 +332,7 @@ __device__ __forceinline__ void store_cell(const Grid& g, const OutArgs<T>& o, l
         }
 #pragma unroll
         for (int v = 0; v < F::NV; ++v) o.out[v * N + cell] = qo[v];
-        if (acc) acc->add(g, qo);
+        if (acc) acc->add(g, qo, cell);
     }
 }
 
@@ -984,7 +1000,12 @@ __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 3 : 1) sweep_yz
     const int c1 = min(c0 + seg, n);
     GlobalSrc<DIR, F> src{qs, g.inflow_dev + DIR * 2 * NVMAX, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
     constexpr int CHK = (MODE == OUT_STAGE1 || MODE == OUT_STAGE2) ? CHK_STATE : (CFL ? CHK_CFL : CHK_NONE);
-    GlobalSink<T, FIRST, MODE, (MODE >= OUT_STAGE1 && !LEARNED), CHK, !LEARNED, F> sink{
+    // The stage updates keep the stage state from the window loads, except
+    // on unequal cells: there the marching position's 33 coefficients
+    // already take the registers the history would need, and keeping it
+    // drops the sweep to one wave per SIMD (re-reading the state is faster).
+    constexpr bool KEEPQ = MODE >= OUT_STAGE1 && !LEARNED && SCHEME != SCHEME_WENO5NU;
+    GlobalSink<T, FIRST, MODE, KEEPQ, CHK, !LEARNED, F> sink{
         OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid,
         CflAcc<F>{0.0, 0u, CHK == CHK_CFL}};
     auto recon = make_recon<T, LEARNED, SCHEME>(g, mlp, valid);

@@ -5,7 +5,8 @@ the C ABI.
 A direction with unequal cells reads per-position coefficient tables (x:
 the x row kernel, each lane with its own position's coefficients, or the
 marching x sweep; y, z: the y/z sweeps), its flux differences divide by
-each cell's width, and the CFL reduction reads each cell's widths.
+each cell's width, and the CFL reduction reads each cell's widths (in
+the last sweep of a step, or the standalone pass).
 Covered: stretching along x, y or z alone (next to the fused x-y pass and
 the row kernels of equal directions) and along all three; every boundary
 type (ghost cells take the widths the boundary rule maps them to); short
@@ -112,6 +113,29 @@ def test_stretched_float_form_matches_oracle(n, bc, which, seed):
     err32 = rhs_rel_linf(s32.rhs().cpu().numpy(), oracle.rhs(g, q0), q0, spec)
     _report("stretched rhs float form", err32)
     assert np.all(err32 <= 1e-5), err32
+
+
+@pytest.mark.parametrize("n,bc,which,seed", [
+    ((24, 20, 28), ((T_, T_), (P_, P_), (P_, P_)), (0,), 95),  # z reduces with the x widths
+    ((20, 22, 24), ((R_, T_), (P_, P_), (T_, R_)), (0, 1, 2), 96),  # z reduces, every width unequal
+    ((40, 36, 1), ((T_, T_), (P_, P_), (P_, P_)), (1,), 97),  # x rows, then the y sweep reduces
+])
+def test_cfl_in_last_sweep_matches_standalone(monkeypatch, n, bc, which, seed):
+    """On unequal cells the CFL reduction inside the last sweep of a step
+    reads each cell's widths as the standalone reduction does: the same
+    time steps and states bit for bit, and the oracle's CFL time step."""
+    spec, g, q0 = _setup(n, bc, which, seed)
+    res = []
+    for fuse in ("0", "1"):
+        monkeypatch.setenv("MFX_FUSE_CFL", fuse)
+        s = gpu_solver(spec, q0=q0)
+        dts = [s.rk3_step(sync=True) for _ in range(4)]
+        q = s.get_state().cpu().numpy()
+        dts.append(s.rk3_step(sync=True))  # CFL time step of q, from the fourth step's reduction
+        res.append((dts, q))
+    assert res[0][0] == res[1][0]
+    assert np.array_equal(res[0][1], res[1][1])
+    assert res[1][0][-1] == pytest.approx(oracle.cfl_dt(g, res[1][1]), rel=1e-15)
 
 
 def test_full_size_stretched_rhs_sampled():
