@@ -1001,10 +1001,12 @@ __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 3 : 1) sweep_yz
     GlobalSrc<DIR, F> src{qs, g.inflow_dev + DIR * 2 * NVMAX, base, g.stride[DIR], g.N, n, g.bc[DIR][0], g.bc[DIR][1]};
     constexpr int CHK = (MODE == OUT_STAGE1 || MODE == OUT_STAGE2) ? CHK_STATE : (CFL ? CHK_CFL : CHK_NONE);
     // The stage updates keep the stage state from the window loads, except
-    // on unequal cells: there the marching position's 33 coefficients
-    // already take the registers the history would need, and keeping it
-    // drops the sweep to one wave per SIMD (re-reading the state is faster).
-    constexpr bool KEEPQ = MODE >= OUT_STAGE1 && !LEARNED && SCHEME != SCHEME_WENO5NU;
+    // in float64 on unequal cells: there the marching position's 33
+    // coefficients already take the registers the history would need, and
+    // keeping it drops the sweep to one wave per SIMD (re-reading the state
+    // is faster).
+    constexpr bool KEEPQ =
+        MODE >= OUT_STAGE1 && !LEARNED && (SCHEME != SCHEME_WENO5NU || sizeof(T) == sizeof(float));
     GlobalSink<T, FIRST, MODE, KEEPQ, CHK, !LEARNED, F> sink{
         OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid,
         CflAcc<F>{0.0, 0u, CHK == CHK_CFL}};
