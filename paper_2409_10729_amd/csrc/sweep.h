@@ -1130,8 +1130,8 @@ struct LdsSink {
 // (No occupancy target: a one-wave block stages XCHUNK rows of input and
 // output and the 5-cell window in LDS, about 48 KB in float64, so LDS
 // rather than registers bounds the blocks per CU.  This pass serves rows
-// longer than the row kernels take, x inflow sides with aliased row
-// buffers, more than two fluids and unequal cells along x.)
+// longer than the row kernels take and x inflow sides with aliased row
+// buffers.)
 template <typename T, bool FIRST, int MODE, bool LEARNED, int SCHEME = 5, class F = Fl2>
 __global__ void __launch_bounds__(XROWS) sweep_x_march(Grid g, const double* __restrict__ qs, const double* qn,
                                                           T* __restrict__ racc, double* out, int seg,
