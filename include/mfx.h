@@ -346,8 +346,8 @@ int mfx_profile_read(mfx_ctx* ctx, double* ms, int64_t* counts);
  * partial right-hand side, the x rows' boundary faces, the inflow states)
  * lives in a static device array of MFX_STATIC_SCRATCH_BYTES that every GPU
  * the library runs on holds until the process ends; the call allocates
- * nothing.  Scratch a grid needs: 768 + a(e * 16 * ny * nz) + a(e * nv * nx *
- * ny * nz) bytes, a() rounding up to a multiple of 256, e = 8 for MFX_FP64
+ * nothing.  Scratch a grid needs: 768 + a(e * 2 (nv + 1) * ny * nz) + a(e * nv *
+ * nx * ny * nz) bytes, a() rounding up to a multiple of 256, e = 8 for MFX_FP64
  * and 4 for MFX_FP32_MIXED, nv = 2 num_fluids + 3 (two fluids: up to about
  * 2.3 million cells in float64, e.g. 128^3, and 4.6 million in float32); a
  * larger grid is rejected with MFX_ENOMEM before anything is enqueued.  Jiang-Shu or WENO-Z weights,
