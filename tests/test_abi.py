@@ -193,23 +193,26 @@ def test_size_limits():
         assert L.mfx_workspace_bytes(ctypes.byref(d)) == 0
 
 
-def _static_need(n, elem):
+def _static_need(n, elem, nv=7):
     """Scratch bytes of mfx_rhs_static as its declaration states them."""
     def a(x):
         return (x + 255) // 256 * 256
-    return 768 + a(elem * 16 * n[1] * n[2]) + a(elem * 7 * n[0] * n[1] * n[2])
+    return 768 + a(elem * 2 * (nv + 1) * n[1] * n[2]) + a(elem * nv * n[0] * n[1] * n[2])
 
 
-@pytest.mark.parametrize("n,precision", [((134, 134, 134), _native.MFX_FP64), ((168, 168, 168), _native.MFX_FP32_MIXED),
-                                         ((2000, 2000, 1), _native.MFX_FP64)])
-def test_static_rhs_rejects_grids_beyond_its_scratch(n, precision):
+@pytest.mark.parametrize("n,precision,nf", [((134, 134, 134), _native.MFX_FP64, 2),
+                                            ((168, 168, 168), _native.MFX_FP32_MIXED, 2),
+                                            ((2000, 2000, 1), _native.MFX_FP64, 2),
+                                            ((124, 124, 124), _native.MFX_FP64, 3)])
+def test_static_rhs_rejects_grids_beyond_its_scratch(n, precision, nf):
     """Grids whose scratch exceeds the static array are refused before any
     device call (MFX_ENOMEM); the limit follows the header's formula."""
     L = _native.lib()
     elem = 8 if precision == _native.MFX_FP64 else 4
-    assert _static_need(n, elem) > _native.STATIC_SCRATCH_BYTES
-    d = _native.make_desc(wl.spec(n, ((1, 1), (0, 0), (0, 0))), precision)
-    nb = 7 * 8 * n[0] * n[1] * n[2]
+    nv = 2 * nf + 3
+    assert _static_need(n, elem, nv) > _native.STATIC_SCRATCH_BYTES
+    d = _native.make_desc(wl.spec_fluids(n, ((1, 1), (0, 0), (0, 0)), nf), precision)
+    nb = nv * 8 * n[0] * n[1] * n[2]
     rc = L.mfx_rhs_static(ctypes.byref(d), ctypes.c_void_p(1 << 40), ctypes.c_void_p((1 << 40) + nb), None)
     assert rc == _native.MFX_ENOMEM
     assert b"scratch" in L.mfx_last_error(None)
@@ -218,6 +221,7 @@ def test_static_rhs_rejects_grids_beyond_its_scratch(n, precision):
 def test_static_rhs_limits_admit_the_stated_sizes():
     assert _static_need((128, 128, 128), 8) <= _native.STATIC_SCRATCH_BYTES
     assert _static_need((160, 160, 160), 4) <= _native.STATIC_SCRATCH_BYTES
+    assert _static_need((120, 120, 120), 8, 9) <= _native.STATIC_SCRATCH_BYTES
 
 
 @pytest.mark.parametrize("case", ["learned", "null", "overlap", "bad_desc"])
