@@ -476,6 +476,47 @@ struct LdsWindow {
     }
 };
 
+// The ring with its newest cell in registers: four LDS slots hold cells
+// c-2..c+1 (s0: the slot of c-2) and cell c+2 sits in registers, so a lane
+// takes 4/5 of the LDS of LdsWindow for NVV more registers (for sweeps
+// whose blocks per CU the LDS bounds).
+template <typename T, int LANES, int NVV>
+struct LdsRegWindow {
+    static constexpr bool in_registers = false;
+    static constexpr int nv = NVV;
+    T* col;
+    int s0;
+    T r4[NVV];
+    __device__ __forceinline__ int slot(int k) const
+    {
+        const int s = s0 + k;
+        return s >= 4 ? s - 4 : s;
+    }
+    __device__ __forceinline__ T operator()(int k, int v) const
+    {
+        return k == 4 ? r4[v] : col[(slot(k) * NVV + v) * LANES];
+    }
+    __device__ __forceinline__ void store(int k, const T* w)
+    {
+        if (k == 4) {
+#pragma unroll
+            for (int v = 0; v < NVV; ++v) r4[v] = w[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NVV; ++v) col[(slot(k) * NVV + v) * LANES] = w[v];
+        }
+    }
+    // cell c+2 takes the slot of c-2 (which leaves), the new cell c+3 the registers
+    __device__ __forceinline__ void push(const T* w)
+    {
+#pragma unroll
+        for (int v = 0; v < NVV; ++v) col[(s0 * NVV + v) * LANES] = r4[v];
+        s0 = s0 == 3 ? 0 : s0 + 1;
+#pragma unroll
+        for (int v = 0; v < NVV; ++v) r4[v] = w[v];
+    }
+};
+
 // The same ring in registers (rotated by moves), for kernels whose LDS
 // holds other data.
 template <typename T, int NVV = NV>
@@ -1011,8 +1052,13 @@ __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 3 : 1) sweep_yz
         OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid,
         CflAcc<F>{0.0, 0u, CHK == CHK_CFL}};
     auto recon = make_recon<T, LEARNED, SCHEME>(g, mlp, valid);
-    __shared__ T win[5][F::NV][BLOCK];
-    LdsWindow<T, BLOCK, F::NV> W{&win[0][0][threadIdx.x], 0};
+    // Three fluids in the accumulating passes: the window's LDS (5 x 9
+    // values per lane) rather than the registers bounds the blocks per CU,
+    // so its newest cell moves to registers.
+    constexpr bool REG_HEAD = F::NF == 3 && !LEARNED && (MODE == OUT_ACCUM || MODE == OUT_RHS);
+    using Win = typename std::conditional<REG_HEAD, LdsRegWindow<T, BLOCK, F::NV>, LdsWindow<T, BLOCK, F::NV>>::type;
+    __shared__ T win[REG_HEAD ? 4 : 5][F::NV][BLOCK];
+    Win W{&win[0][0][threadIdx.x], 0};
     march<DIR, T, F>(g, src, sink, recon, c0, c1, W);
     recon.flush(fb);
     if constexpr (CHK != CHK_NONE) {
