@@ -46,6 +46,19 @@ def test_workspace_bytes_scales_with_grid():
     assert L.mfx_workspace_bytes(ctypes.byref(d2)) > b
 
 
+def test_workspace_bytes_three_fluids():
+    """Nine variables: the state buffers and the RHS hold nine fields, and
+    the x rows' boundary faces ten values per face (flux components and the
+    face velocity), two faces per row."""
+    L = _native.lib()
+    n = (32, 16, 8)
+    N = n[0] * n[1] * n[2]
+    d3 = _native.make_desc(wl.spec_fluids(n, ((1, 1), (0, 0), (0, 0)), 3))
+    b3 = L.mfx_workspace_bytes(ctypes.byref(d3))
+    assert b3 >= 4 * 9 * 8 * N + 10 * 2 * 8 * n[1] * n[2]
+    assert b3 > L.mfx_workspace_bytes(ctypes.byref(_desc()))
+
+
 @pytest.mark.parametrize("field,value", [
     ("cfl", 0.0), ("cfl", 1.5), ("weno_eps", 0.0), ("precision", 7), ("weights", 9), ("weno_order", 4),
     ("weno_order", 1),
