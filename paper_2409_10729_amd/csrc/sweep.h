@@ -239,25 +239,29 @@ __device__ __forceinline__ void cell_widths(const Grid& g, long long cell, doubl
     for (int d = 0; d < 3; ++d) hw[d] = g.nu[d] ? g.nu[d][(pos[d] + 1) * NU_K + NU_H] : g.dx[d];
 }
 
-// Running CFL maximum and validity flags of the cells a lane writes.
+// Running CFL maximum and validity flags of the cells a lane writes.  On
+// unequal cells hw holds the widths of the cell being written: the lane's
+// and the block's transverse positions are fixed for a marching sweep, so
+// only the width along the sweep changes (at(c), from the direction's table
+// nud; null where that direction has equal cells).
 template <class F = Fl2>
 struct CflAcc {
     double smax;
     unsigned bad;
     bool cfl;  // false: only the status bits, no CFL speed
-    __device__ __forceinline__ void add(const Grid& g, const double* q, long long cell)
+    double hw[3];
+    const double* nud;
+    int dir;
+    __device__ __forceinline__ void at(int c)
     {
-        if (cfl) {
-            if (g.nonuniform) {  // the cell's own widths
-                double hw[3];
-                cell_widths(g, cell, hw);
-                smax = fmax(smax, cfl_speed<F>(g, q, bad, hw));
-            } else {
-                smax = fmax(smax, cfl_speed<F>(g, q, bad));
-            }
-        } else {
+        if (nud) hw[dir] = nud[(long long)(c + 1) * NU_K + NU_H];
+    }
+    __device__ __forceinline__ void add(const Grid& g, const double* q)
+    {
+        if (cfl)
+            smax = fmax(smax, cfl_speed<F>(g, q, bad, g.nonuniform ? hw : nullptr));
+        else
             bad |= state_bits<F>(q);
-        }
     }
 };
 
@@ -332,7 +336,7 @@ __device__ __forceinline__ void store_cell(const Grid& g, const OutArgs<T>& o, l
         }
 #pragma unroll
         for (int v = 0; v < F::NV; ++v) o.out[v * N + cell] = qo[v];
-        if (acc) acc->add(g, qo, cell);
+        if (acc) acc->add(g, qo);
     }
 }
 
@@ -431,6 +435,7 @@ struct GlobalSink {
             for (int v = 0; v < F::NV; ++v) r[v] = FIRST ? fd[v] : rin[v] + fd[v];
 #pragma unroll
             for (int a = 0; a < F::NA; ++a) r[F::IA + a] += src[a];
+            if constexpr (CHK == CHK_CFL) acc.at(c);
             store_cell<T, MODE, F>(g, o, base + (long long)c * sd, r, KEEPQ ? qc : nullptr, CHK ? &acc : nullptr,
                                    NEEDQN ? qnin : nullptr);
         }
@@ -1048,9 +1053,16 @@ __global__ void __launch_bounds__(yz_block<LEARNED>(), LEARNED ? 3 : 1) sweep_yz
     // is faster).
     constexpr bool KEEPQ =
         MODE >= OUT_STAGE1 && !LEARNED && (SCHEME != SCHEME_WENO5NU || sizeof(T) == sizeof(float));
+    CflAcc<F> acc{0.0, 0u, CHK == CHK_CFL, {g.dx[0], g.dx[1], g.dx[2]}, nullptr, DIR};
+    if constexpr (CHK == CHK_CFL) {
+        if (g.nonuniform) {  // widths of the lane's x position and the block's transverse position
+            if (g.nu[0]) acc.hw[0] = g.nu[0][(long long)(i + 1) * NU_K + NU_H];
+            if (g.nu[SA]) acc.hw[SA] = g.nu[SA][(long long)(blockIdx.y + 1) * NU_K + NU_H];
+            acc.nud = g.nu[DIR];
+        }
+    }
     GlobalSink<T, FIRST, MODE, KEEPQ, CHK, !LEARNED, F> sink{
-        OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid,
-        CflAcc<F>{0.0, 0u, CHK == CHK_CFL}};
+        OutArgs<T>{qs, qn, racc, out, dt_dev ? *dt_dev : dt_arg}, base, g.stride[DIR], valid, acc};
     auto recon = make_recon<T, LEARNED, SCHEME>(g, mlp, valid);
     // Three fluids in the accumulating passes: the window's LDS (5 x 9
     // values per lane) rather than the registers bounds the blocks per CU,
