@@ -2,7 +2,7 @@
 scratch in a static device array) against mfx_rhs on a context, through the
 C ABI: two calls in a row on one GPU, the second on a smaller grid (the
 array keeps the first call's contents), in float64 and in the float form,
-with every boundary type.  Same kernels and launch shapes, so the results
+with every boundary type, for two and for three fluids.  Same kernels and launch shapes, so the results
 are bit for bit the same."""
 import numpy as np
 import pytest
@@ -48,4 +48,39 @@ def test_static_rhs_equals_context_rhs(precision, weights):
         out = torch.full_like(qd, float("nan"))
         rhs_static(spec, qd, out, precision=precision, weights=weights)
         got = out.cpu().numpy()
+        assert np.array_equal(got, ref), np.abs(got - ref).max()
+
+
+def _inflow3(seed):
+    """Conserved three-fluid inflow states [3][2][9] of random valid primitives."""
+    rng = np.random.default_rng(seed)
+    g1 = oracle.make_grid(wl.spec_fluids((1, 1, 1), ((P_, P_),) * 3, 3))
+    out = np.zeros((3, 2, 9))
+    for d in range(3):
+        for s in range(2):
+            a = rng.dirichlet((1.0, 3.0, 1.0))
+            w = np.array([a[0] * 1000.0, a[1] * 1.5, a[2] * 0.17, 20.0, -10.0, 5.0, 1.5e5, a[0], a[1]])
+            out[d, s] = oracle.prim_to_cons(g1, w.reshape(9, 1, 1, 1)).reshape(9)
+    return out
+
+
+@pytest.mark.parametrize("precision", [MFX_FP64, MFX_FP32_MIXED])
+def test_static_rhs_equals_context_rhs_three_fluids(precision):
+    """Nine variables: the static scratch holds ten values per boundary face
+    and nine partial right-hand-side fields."""
+    cases = [((64, 48, 40), ((T_, T_), (P_, P_), (P_, P_)), 3),      # larger first
+             ((37, 29, 23), ((I_, R_), (T_, I_), (R_, T_)), 4)]      # then smaller, every boundary type
+    for n, bc, seed in cases:
+        print(f"static rhs, three fluids: n={n} bc={bc} precision={precision}", flush=True)
+        P = wl.random_smooth_nf(n=n, seed=seed, bc=bc, nf=3)
+        spec = dict(P["spec"], inflow=_inflow3(seed))
+        g = oracle.make_grid(spec)
+        q0 = oracle.prim_to_cons(g, P["w"])
+        s = gpu_solver(spec, q0=q0, precision=precision)
+        ref = s.rhs().cpu().numpy()
+        qd = torch.from_numpy(q0).cuda()
+        out = torch.full_like(qd, float("nan"))
+        rhs_static(spec, qd, out, precision=precision)
+        got = out.cpu().numpy()
+        assert got.shape[0] == 9
         assert np.array_equal(got, ref), np.abs(got - ref).max()
